@@ -1,0 +1,451 @@
+"""Pins of the FP64 oracle against facts fixed by the paper or by mathematics.
+
+Each test checks an oracle function against something other than itself: a
+library routine, a brute-force definition, a closed form, an invariant the
+paper proves, or a matrix the paper prints.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.linalg
+import scipy.sparse.linalg
+
+from oracle import krylov, metrics, tikhonov, tube
+from oracle.cprod import (Operator, combine, cprod, cprod_adjoint, cprod_definition,
+                          diamond, fro, inner)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- transforms
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 8, 31, 64])
+def test_dct_matrix_is_scipy_orthonormal_dct2(n):
+    """C_n (eq. dft1) is the orthonormal DCT-II, and C_n C_n^T = I."""
+    ref = scipy.fft.dct(np.eye(n), type=2, norm="ortho", axis=0)
+    C = tube.dct_matrix(n)
+    assert np.allclose(C, ref, atol=1e-14)
+    assert np.allclose(C @ C.T, np.eye(n), atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+def test_dct_diagonalises_th_with_eigenvalues_Mv(n):
+    """eq. (dft5): C_n th(v) C_n^{-1} is diagonal; its diagonal is M v (Remark 2.1)."""
+    rng = np.random.default_rng(n)
+    v = rng.standard_normal(n)
+    C = tube.dct_matrix(n)
+    D = C @ tube.th(v) @ C.T
+    assert np.abs(D - np.diag(np.diag(D))).max() < 1e-13
+    assert np.allclose(np.diag(D), tube.m_matrix(n) @ v, atol=1e-13)
+    # eigenvalues by LAPACK agree as a set
+    ev = np.sort(np.linalg.eigvalsh(tube.th(v)))
+    assert np.allclose(ev, np.sort(tube.m_matrix(n) @ v), atol=1e-12)
+
+
+def test_th_reproduces_printed_colour_matrix():
+    """th(0.8, 0, 0.1) equals the A_color printed in Sec. 4 (golden fixture)."""
+    rows = []
+    tube_vals = None
+    with open(os.path.join(GOLDEN, "colour_mixing.txt")) as f:
+        for line in f:
+            if line.startswith("# tube:"):
+                tube_vals = [float(x) for x in line.split(":")[1].split()]
+            elif line.strip() and not line.startswith("#"):
+                rows.append([float(x) for x in line.split()])
+    A_color = np.array(rows)
+    assert np.allclose(tube.th(tube_vals), A_color, atol=1e-15)
+    # rows sum to one, as the paper states for A_color
+    assert np.allclose(A_color.sum(axis=1), 1.0)
+
+
+def test_mat_of_mixed_blur_is_kronecker():
+    """With A(:,:,k) = t_k T (eq. tensor_form), mat(A) = th(t) (x) T."""
+    rng = np.random.default_rng(1)
+    t = np.array([0.8, 0.0, 0.1])
+    T = rng.standard_normal((4, 4))
+    A = np.stack([c * T for c in t])
+    assert np.allclose(tube.mat(A), np.kron(tube.th(t), T), atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [2, 3, 6])
+def test_M_inverse_closed_form(n):
+    """M^{-1} = (I+Z)^{-1} C_n^T W with (I+Z)^{-1}_{ij} = (-1)^{j-i} (j >= i)."""
+    IZinv = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i, n):
+            IZinv[i, j] = (-1.0) ** (j - i)
+    C = tube.dct_matrix(n)
+    W = np.diag(C[:, 0])
+    assert np.allclose(tube.inverse_transform_matrix(n, "th"), IZinv @ C.T @ W, atol=1e-12)
+
+
+def test_M_maps_first_unit_tube_to_ones():
+    """Under M every transform-domain slice of e_1 (x) I is I (identity tensor, Sec. 2.2)."""
+    for n in [1, 2, 3, 8, 31]:
+        e1 = np.zeros(n)
+        e1[0] = 1.0
+        assert np.allclose(tube.m_matrix(n) @ e1, np.ones(n), atol=1e-13)
+
+
+@pytest.mark.parametrize("p,n1,n2", [(2, 2, 3), (3, 3, 2), (5, 2, 2)])
+def test_block_diagonalisation_eq_dft8(p, n1, n2):
+    """eq. (dft8): (C (x) I) mat(A) (C^T (x) I) is block diagonal with blocks (A x_3 M)_k."""
+    rng = np.random.default_rng(p * 100 + n1)
+    A = rng.standard_normal((p, n1, n2))
+    C = tube.dct_matrix(p)
+    BD = np.kron(C, np.eye(n1)) @ tube.mat(A) @ np.kron(C.T, np.eye(n2))
+    Ah = tube.mode3(A, tube.m_matrix(p))
+    for r in range(p):
+        for c in range(p):
+            blk = BD[r * n1:(r + 1) * n1, c * n2:(c + 1) * n2]
+            if r == c:
+                assert np.allclose(blk, Ah[r], atol=1e-12)
+            else:
+                assert np.abs(blk).max() < 1e-12
+
+
+def test_ten_inverts_mat():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((4, 3, 5))
+    assert np.allclose(tube.ten(tube.mat(A), 3, 5, 4), A, atol=1e-15)
+
+
+# ------------------------------------------------------------------ c-product
+
+SHAPES = [(1, 2, 3, 2), (2, 3, 2, 4), (3, 4, 5, 3), (4, 2, 2, 2), (6, 3, 4, 5), (5, 5, 5, 1)]
+
+
+@pytest.mark.parametrize("p,n1,n2,s", SHAPES)
+def test_cprod_transform_equals_definition(p, n1, n2, s):
+    """Algorithm 1 with L = M equals the Definition ten(mat(A) mat(B)) (brute force)."""
+    rng = np.random.default_rng(p + 10 * n1 + 100 * n2 + 1000 * s)
+    A = rng.standard_normal((p, n1, n2))
+    X = rng.standard_normal((p, n2, s))
+    ref = cprod_definition(A, X)
+    out = cprod(A, X, "th")
+    assert np.abs(out - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_plain_dct_product_differs_from_definition():
+    """The plain DCT of Algorithm 1 does not realise the Definition for n3 >= 2."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((3, 4, 4))
+    X = rng.standard_normal((3, 4, 4))
+    assert np.abs(cprod(A, X, "dct2") - cprod_definition(A, X)).max() > 1e-2
+
+
+@pytest.mark.parametrize("p,n1,n2,s", SHAPES[:4])
+def test_closure_mat_of_product(p, n1, n2, s):
+    """mat(A) mat(X) = mat(A *c X): the product stays in the T+H algebra."""
+    rng = np.random.default_rng(7 + p)
+    A = rng.standard_normal((p, n1, n2))
+    X = rng.standard_normal((p, n2, s))
+    assert np.allclose(tube.mat(A) @ tube.mat(X), tube.mat(cprod(A, X)), atol=1e-12)
+
+
+def test_identity_tensor():
+    """(e_1 (x) I) *c X = X under M (identity tensor of Sec. 2.2)."""
+    rng = np.random.default_rng(11)
+    for p in [1, 2, 3, 8]:
+        I = np.zeros((p, 4, 4))
+        I[0] = np.eye(4)
+        X = rng.standard_normal((p, 4, 3))
+        assert np.allclose(cprod(I, X), X, atol=1e-13)
+        assert np.allclose(cprod_definition(I, X), X, atol=1e-13)
+
+
+@pytest.mark.parametrize("tb", ["th", "dct2"])
+def test_associativity(tb):
+    rng = np.random.default_rng(13)
+    A = rng.standard_normal((4, 3, 3))
+    B = rng.standard_normal((4, 3, 3))
+    X = rng.standard_normal((4, 3, 2))
+    assert np.allclose(cprod(cprod(A, B, tb), X, tb), cprod(A, cprod(B, X, tb), tb), atol=1e-12)
+
+
+@pytest.mark.parametrize("tb", ["th", "dct2"])
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_adjoint_is_dense_transpose(tb, two_sided):
+    """M* is the exact adjoint: <M X, Y> = <X, M* Y>, and Mat(M*) = Mat(M)^T."""
+    rng = np.random.default_rng(17)
+    p, n1, n2, s = 3, 3, 2, 2
+    A = rng.standard_normal((p, n1, n2))
+    B = rng.standard_normal((p, s, s)) if two_sided else None
+    op = Operator(A, B, tb)
+    X = rng.standard_normal((p, n2, s))
+    Y = rng.standard_normal((p, n1, s))
+    assert abs(inner(op.apply(X), Y) - inner(X, op.adjoint(Y))) < 1e-12
+    Dm = op.dense(s)
+    cols = []
+    for e in range(p * n1 * s):
+        y = np.zeros(p * n1 * s)
+        y[e] = 1.0
+        cols.append(op.adjoint(y.reshape(p, n1, s)).ravel())
+    Dadj = np.stack(cols, axis=1)
+    assert np.allclose(Dadj, Dm.T, atol=1e-12)
+    # Dense M equals the literal Definition applied column by column
+    if not two_sided and tb == "th":
+        for e in range(p * n2 * s):
+            x = np.zeros(p * n2 * s)
+            x[e] = 1.0
+            assert np.allclose(Dm[:, e], cprod_definition(A, x.reshape(p, n2, s)).ravel(), atol=1e-12)
+
+
+def test_adjoint_for_orthogonal_dct_is_slice_transpose():
+    """For L = C_n (orthogonal), M* transposes every transform-domain slice."""
+    rng = np.random.default_rng(19)
+    A = rng.standard_normal((3, 4, 5))
+    Y = rng.standard_normal((3, 4, 2))
+    C = tube.dct_matrix(3)
+    Ah = tube.mode3(A, C)
+    ref = tube.mode3(np.matmul(np.transpose(Ah, (0, 2, 1)), tube.mode3(Y, C)), C.T)
+    assert np.allclose(cprod_adjoint(A, Y, "dct2"), ref, atol=1e-13)
+    # ... and for M the slice-transpose is NOT the adjoint
+    Ah = tube.mode3(A, tube.m_matrix(3))
+    Minv = np.linalg.inv(tube.m_matrix(3))
+    wrong = tube.mode3(np.matmul(np.transpose(Ah, (0, 2, 1)), tube.mode3(Y, tube.m_matrix(3))), Minv)
+    assert np.abs(wrong - cprod_adjoint(A, Y, "th")).max() > 1e-3
+
+
+def test_inner_product_remark_does_not_hold():
+    """Remark 2.2 (<A,B> = <A~,B~>/n3) is false for both transforms; the oracle
+    therefore computes inner products in the spatial domain."""
+    rng = np.random.default_rng(23)
+    X = rng.standard_normal((3, 4, 4))
+    for tb in ["th", "dct2"]:
+        Xh = tube.mode3(X, tube.transform_matrix(3, tb))
+        assert abs(inner(X, X) - inner(Xh, Xh) / 3.0) > 1e-3 * inner(X, X)
+    # Parseval with factor 1 for the orthonormal DCT
+    Xh = tube.mode3(X, tube.dct_matrix(3))
+    assert abs(inner(X, X) - inner(Xh, Xh)) < 1e-10
+
+
+# ----------------------------------------------------------- Krylov processes
+
+def _problem(seed=29, p=3, n=4, s=2, two_sided=False, tb="th"):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((p, n, n)) + 3.0 * np.stack([np.eye(n)] + [np.zeros((n, n))] * (p - 1))
+    B = (rng.standard_normal((p, s, s)) + 2.0 * np.stack([np.eye(s)] + [np.zeros((s, s))] * (p - 1))) if two_sided else None
+    op = Operator(A, B, tb)
+    C = rng.standard_normal((p, n, s))
+    return op, C
+
+
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_gkb_relations_prop_3_2(two_sided):
+    """Proposition 3.2 relations and orthonormality under the c-diamond product."""
+    op, C = _problem(two_sided=two_sided)
+    m = 5
+    g = krylov.gkb(op, C, m, reorth="full")
+    assert g.steps == m and not g.breakdown
+    Ct = g.bidiagonal(m)
+    # A *c V_m = U_{m+1} (*) C~_m
+    for j in range(m):
+        lhs = op.apply(g.V[j])
+        rhs = combine(g.U[: m + 1], Ct[:, j])
+        assert fro(lhs - rhs) < 1e-12
+    # A^T *c U_m = V_m (*) C_m^T  (C_m = first m rows of C~_m)
+    Cm = Ct[:m, :]
+    for j in range(m):
+        lhs = op.adjoint(g.U[j])
+        rhs = combine(g.V[:m], Cm.T[:, j])
+        assert fro(lhs - rhs) < 1e-12
+    # U_{m+1} (*) (beta_1 e_1) = C
+    e = np.zeros(m + 1)
+    e[0] = g.beta[0]
+    assert fro(combine(g.U[: m + 1], e) - C) < 1e-12
+    # orthonormality and norm preservation
+    assert np.allclose(diamond(g.U[: m + 1], g.U[: m + 1]), np.eye(m + 1), atol=1e-13)
+    assert np.allclose(diamond(g.V[:m], g.V[:m]), np.eye(m), atol=1e-13)
+    z = np.random.default_rng(1).standard_normal(m + 1)
+    assert abs(fro(combine(g.U[: m + 1], z)) - np.linalg.norm(z)) < 1e-12
+
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgs2"])
+def test_arnoldi_relations_prop_3_1(ortho):
+    """Proposition 3.1 relations for Algorithm 2."""
+    op, C = _problem(seed=31)
+    m = 6
+    ar = krylov.Arnoldi(op, C, m, ortho)
+    for _ in range(m):
+        assert ar.step()
+    H = ar.hessenberg()
+    for j in range(m):
+        assert fro(op.apply(ar.V[j]) - combine(ar.V[: m + 1], H[:, j])) < 1e-12
+    assert np.allclose(diamond(ar.V[: m + 1], ar.V[: m + 1]), np.eye(m + 1), atol=1e-12)
+    # V_m^T <> (A *c V_m) = H_m
+    AV = [op.apply(v) for v in ar.V[:m]]
+    assert np.allclose(diamond(ar.V[:m], AV), H[:m, :], atol=1e-12)
+    # H is upper Hessenberg
+    assert np.abs(np.tril(H, -2)).max() == 0.0
+
+
+def test_lsqr_equals_scipy_lsqr_on_dense_operator():
+    """DC-LSQR iterates equal textbook LSQR (scipy) on the dense matrix of M."""
+    op, C = _problem(seed=37, p=3, n=4, s=2)
+    D = op.dense(2)
+    b = C.ravel()
+    for k in range(1, 7):
+        ours = krylov.dc_lsqr(op, C, k)["X"].ravel()
+        ref = scipy.sparse.linalg.lsqr(D, b, damp=0.0, atol=0.0, btol=0.0, conlim=0.0, iter_lim=k)[0]
+        assert np.linalg.norm(ours - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_lsqr_equals_gk_at_lambda_zero_and_residual():
+    """Algorithm 6 iterate = Algorithm 5 at lambda = 0; |phibar_{k+1}| = ||C - M(X_k)||."""
+    op, C = _problem(seed=41, two_sided=True)
+    for k in [1, 3, 6]:
+        ls = krylov.dc_lsqr(op, C, k)
+        gk = krylov.dc_gk(op, C, k, lam=0.0)
+        assert fro(ls["X"] - gk["X"]) <= 1e-10 * fro(gk["X"])
+        assert abs(ls["resnorm"] - fro(C - op.apply(ls["X"]))) <= 1e-10 * fro(C)
+
+
+def test_gmres_lambda0_is_krylov_least_squares():
+    """One DC-GMRES(m) cycle at lambda = 0 minimises ||C - M(X_0 + Z)|| over
+    Z in TK_m(A, R_0) (eq. tr3), checked by brute force with the power basis."""
+    op, C = _problem(seed=43, p=2, n=3, s=2)
+    rng = np.random.default_rng(2)
+    X0 = rng.standard_normal(C.shape)
+    R0 = C - op.apply(X0)
+    for m in [1, 2, 3]:
+        K = [R0]
+        for _ in range(m - 1):
+            K.append(op.apply(K[-1]))
+        Kmat = np.stack([op.apply(k).ravel() for k in K], axis=1)
+        coef, *_ = np.linalg.lstsq(Kmat, R0.ravel(), rcond=None)
+        ref = X0 + combine(K, coef)
+        out = krylov.dc_gmres(op, C, X0, m, 1, lam=0.0)["X"]
+        assert fro(out - ref) <= 1e-9 * fro(ref)
+
+
+def test_gk_tikhonov_full_dimension_is_dense_tikhonov():
+    """At k = dim, the projected Tikhonov iterate equals (M*M + l^2 I)^{-1} M* C."""
+    op, C = _problem(seed=47, p=2, n=3, s=2)
+    D = op.dense(2)
+    dim = D.shape[1]
+    lam = 0.3
+    ref = np.linalg.solve(D.T @ D + lam ** 2 * np.eye(dim), D.T @ C.ravel())
+    out = krylov.dc_gk(op, C, dim, lam=lam, reorth="full")
+    assert np.linalg.norm(out["X"].ravel() - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_gk_tikhonov_krylov_restriction():
+    """For k < dim, the iterate minimises the Tikhonov functional over
+    K_k(M*M, M*C) (dense check with an orthonormalised power basis)."""
+    op, C = _problem(seed=53, p=2, n=3, s=2)
+    D = op.dense(2)
+    lam = 0.2
+    b = C.ravel()
+    for k in [2, 4]:
+        K = [D.T @ b]
+        for _ in range(k - 1):
+            K.append(D.T @ (D @ K[-1]))
+        Q, _ = np.linalg.qr(np.stack(K, axis=1))
+        A_stack = np.vstack([D @ Q, lam * np.eye(k)])
+        z, *_ = np.linalg.lstsq(A_stack, np.concatenate([b, np.zeros(k)]), rcond=None)
+        ref = Q @ z
+        out = krylov.dc_gk(op, C, k, lam=lam, reorth="full")["X"].ravel()
+        assert np.linalg.norm(out - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_breakdown_identity_operator():
+    """A = e_1 (x) I: alpha_1 = 1, beta_2 = 0, h_21 = 0, exact recovery in one step."""
+    p, n, s = 3, 4, 2
+    A = np.zeros((p, n, n))
+    A[0] = np.eye(n)
+    rng = np.random.default_rng(59)
+    C = rng.standard_normal((p, n, s))
+    op = Operator(A)
+    g = krylov.gkb(op, C, 5)
+    assert g.breakdown and g.steps == 1
+    assert abs(g.alpha[0] - 1.0) < 1e-14 and g.beta[1] < 1e-14
+    ls = krylov.dc_lsqr(op, C, 5)
+    assert ls["status"] == "breakdown" and fro(ls["X"] - C) < 1e-13
+    gm = krylov.dc_gmres(op, C, np.zeros_like(C), 4, 1, lam=0.0)
+    assert gm["status"] == "breakdown" and fro(gm["X"] - C) < 1e-13
+
+
+# ------------------------------------------------------- projected problems
+
+def _rand_projected(seed, m, bidiag):
+    rng = np.random.default_rng(seed)
+    if bidiag:
+        a = np.exp(-0.5 * np.arange(m + 1)) * rng.uniform(0.5, 1.5, m + 1)
+        b = np.exp(-0.5 * np.arange(m + 1)) * rng.uniform(0.5, 1.5, m + 1)
+        H = tikhonov.lower_bidiagonal(a, b, m)
+    else:
+        H = np.triu(rng.standard_normal((m + 1, m)), -1) * np.exp(-0.4 * np.arange(m))[None, :]
+    return H, float(rng.uniform(0.5, 2.0))
+
+
+@pytest.mark.parametrize("bidiag", [True, False])
+def test_projected_solve_three_ways(bidiag):
+    """SVD solve = normal equations (eq. tikho2/normeq2) = stacked LS (eq. min)."""
+    H, beta = _rand_projected(61, 8, bidiag)
+    m = H.shape[1]
+    rhs = np.zeros(m + 1)
+    rhs[0] = beta
+    for lam in [1e-3, 0.05, 1.0]:
+        y, _ = tikhonov.solve_projected(H, beta, lam)
+        y_ne = np.linalg.solve(H.T @ H + lam ** 2 * np.eye(m), H.T @ rhs)
+        y_ls, *_ = np.linalg.lstsq(np.vstack([H, lam * np.eye(m)]), np.concatenate([rhs, np.zeros(m)]), rcond=None)
+        assert np.allclose(y, y_ne, rtol=1e-8, atol=1e-10)
+        assert np.allclose(y, y_ls, rtol=1e-8, atol=1e-10)
+
+
+def _dense_gcv(H, beta, lam, square=False):
+    """GCV from its definition: ||(I - Infl) b||^2 / trace(I - Infl)^2, no SVD."""
+    r, m = H.shape
+    b = np.zeros(r)
+    b[0] = beta
+    Infl = H @ np.linalg.solve(H.T @ H + lam ** 2 * np.eye(m), H.T)
+    res = b - Infl @ b
+    return float(res @ res) / float(np.trace(np.eye(r) - Infl)) ** 2
+
+
+@pytest.mark.parametrize("bidiag", [True, False])
+def test_gcv_rect_matches_definition(bidiag):
+    H, beta = _rand_projected(67, 7, bidiag)
+    sig, Vt, g = tikhonov.projected_svd(H, beta)
+    for lam in [1e-4, 1e-2, 0.3, 3.0]:
+        assert abs(tikhonov.gcv_rect(sig, g, lam) - _dense_gcv(H, beta, lam)) <= 1e-9 * _dense_gcv(H, beta, lam)
+
+
+def test_gcv_paper_is_square_problem_gcv():
+    """The printed eq. (gcv2) is the GCV function of a square projected problem."""
+    rng = np.random.default_rng(71)
+    H = rng.standard_normal((6, 6)) * np.exp(-0.5 * np.arange(6))[None, :]
+    sig, Vt, g = tikhonov.projected_svd(H, 1.3)
+    for lam in [1e-3, 0.1, 1.0]:
+        ref = _dense_gcv(H, 1.3, lam)
+        assert abs(tikhonov.gcv_paper(sig, g, lam) - ref) <= 1e-8 * ref
+
+
+@pytest.mark.parametrize("mode", ["rect", "paper"])
+@pytest.mark.parametrize("seed", [73, 79, 83])
+def test_gcv_minimiser_against_brute_force(mode, seed):
+    """The minimiser finds the minimum of a 1e5-point log grid to grid resolution."""
+    H, beta = _rand_projected(seed, 12, True)
+    sig, Vt, g = tikhonov.projected_svd(H, beta)
+    f = tikhonov.gcv_rect if mode == "rect" else tikhonov.gcv_paper
+    lam, val = tikhonov.gcv_minimize(sig, g, mode)
+    grid = sig[0] * 10.0 ** np.linspace(-8, 0, 100000)
+    brute = min(f(sig, g, l) for l in grid)
+    assert val <= brute * (1.0 + 1e-6)
+    assert abs(val - f(sig, g, lam)) <= 1e-12 * val
+
+
+# ------------------------------------------------------------------ metrics
+
+def test_snr_relerr_consistency():
+    """SNR = 20 log10(||X^ - E|| / ||X^||) - 20 log10(relerr) (both use ||X^ - X||)."""
+    rng = np.random.default_rng(89)
+    Xt = rng.uniform(0, 1, (3, 8, 8))
+    X = Xt + 0.05 * rng.standard_normal(Xt.shape)
+    e = metrics.relative_error(Xt, X)
+    lhs = metrics.snr(Xt, X)
+    rhs = 20 * np.log10(np.linalg.norm(Xt - Xt.mean()) / np.linalg.norm(Xt)) - 20 * np.log10(e)
+    assert abs(lhs - rhs) < 1e-10

@@ -1,0 +1,33 @@
+"""The seeded input generators: shapes, ranges, determinism, and the blur of Sec. 4."""
+import math
+
+import numpy as np
+
+import workloads as W
+
+
+def test_gaussian_toeplitz_entries():
+    """a_kl = exp(-(k-l)^2/(2 sigma^2)) / (sigma sqrt(2 pi)) inside the band, 0 outside."""
+    T = W.gaussian_toeplitz(20, 4.0, 6)
+    for k in range(20):
+        for l in range(20):
+            d = k - l
+            ref = math.exp(-d * d / 32.0) / (4.0 * math.sqrt(2 * math.pi)) if abs(d) <= 6 else 0.0
+            assert abs(T[k, l] - ref) < 1e-15
+    assert np.allclose(T, T.T)
+
+
+def test_generators_deterministic_and_in_range():
+    a = W.colour_small()
+    b = W.colour_small()
+    assert np.array_equal(a["X_true"], b["X_true"]) and np.array_equal(a["N0"], b["N0"])
+    assert a["X_true"].shape == (3, 32, 32) and a["A"].shape == (3, 32, 32)
+    assert a["X_true"].min() == 0.0 and a["X_true"].max() == 1.0
+    c = W.colour_256()
+    assert c["X_true"].shape == (3, 256, 256) and c["nu"] == 1e-2
+
+
+def test_batch_instances_span_sizes():
+    sizes = {W.batch_instance(i)["A"].shape for i in range(6)}
+    for p, n, n2 in sizes:
+        assert n == n2 and p in (3, 8, 31) and n in (64, 128, 192, 256, 384, 512)

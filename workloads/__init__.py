@@ -1,0 +1,173 @@
+"""Seeded synthetic inputs shared by the HIP library's tests/benchmark and the oracle.
+
+This module holds none of the method's arithmetic: it draws images, blur
+matrices and raw noise only.  Each side forms the observation
+C = M(X_true) + nu * ||M(X_true)||_F / ||N0||_F * N0 with its own operator.
+
+Everything is FP64 numpy, laid out (n3, rows, cols) = (p, n, s).
+
+The paper's test images are not available, so every image here is a
+synthetic stand-in with the paper's shapes, value range [0, 1] and kind of
+structure (smooth regions plus edges), blurred by the banded Gaussian
+Toeplitz matrix of Sec. 4 and contaminated by Gaussian noise at a relative
+level nu (Sec. 4).
+
+Seeds: workload c (1-based), instance i uses numpy.random.default_rng(1000 c + i).
+"""
+import math
+
+import numpy as np
+
+# Mixing tubes (A(:,:,k) = a_k T, the recipe of eq. tensor_form in Sec. 4).
+COLOUR_TUBE = (0.7, 0.15, 0.15)
+PAPER_COLOUR_TUBE = (0.8, 0.0, 0.1)     # th(0.8, 0, 0.1) is the printed A_color
+
+
+def gaussian_toeplitz(n, sigma, r):
+    """Banded Gaussian blur of Sec. 4: a_kl = exp(-(k-l)^2/(2 sigma^2))/(sigma sqrt(2 pi)), |k-l| <= r."""
+    T = np.zeros((n, n))
+    c = 1.0 / (sigma * math.sqrt(2.0 * math.pi))
+    for d in range(-r, r + 1):
+        val = c * math.exp(-(d * d) / (2.0 * sigma * sigma))
+        idx = np.arange(max(0, -d), min(n, n - d))
+        T[idx, idx + d] = val
+    return T
+
+
+def _minmax(X):
+    lo, hi = X.min(), X.max()
+    return (X - lo) / (hi - lo) if hi > lo else np.zeros_like(X)
+
+
+def smooth_field(rng, p, n, s, count=8):
+    """Sum of ``count`` random 2-D Gaussians per channel, globally scaled to [0, 1]."""
+    X = np.zeros((p, n, s))
+    ii = np.arange(n)[:, None]
+    jj = np.arange(s)[None, :]
+    for k in range(p):
+        for _ in range(count):
+            ci = rng.uniform(0, n)
+            cj = rng.uniform(0, s)
+            w = rng.uniform(n / 16.0, n / 4.0)
+            amp = rng.uniform(0.2, 1.0)
+            X[k] += amp * np.exp(-((ii - ci) ** 2 + (jj - cj) ** 2) / (2.0 * w * w))
+    return _minmax(X)
+
+
+def edges_field(rng, p, n, s, count=20):
+    """Smooth field plus ``count`` axis-aligned rectangles per channel, scaled to [0, 1]."""
+    X = smooth_field(rng, p, n, s)
+    for k in range(p):
+        for _ in range(count):
+            h = int(rng.uniform(n / 32.0, n / 4.0))
+            w = int(rng.uniform(s / 32.0, s / 4.0))
+            i0 = int(rng.integers(0, max(1, n - h)))
+            j0 = int(rng.integers(0, max(1, s - w)))
+            X[k, i0:i0 + h, j0:j0 + w] += rng.uniform(0.1, 0.6)
+    return _minmax(X)
+
+
+def moving_blobs(rng, p, n, s, count=8, speed=2.0):
+    """Video: ``count`` Gaussian blobs (width U[8, 32] px) drifting ``speed`` px/frame,
+    reflected at the borders; frame k is slice k."""
+    X = np.zeros((p, n, s))
+    ii = np.arange(n)[:, None]
+    jj = np.arange(s)[None, :]
+    blobs = []
+    for _ in range(count):
+        ang = rng.uniform(0.0, 2.0 * math.pi)
+        blobs.append([rng.uniform(0, n), rng.uniform(0, s), speed * math.cos(ang),
+                      speed * math.sin(ang), rng.uniform(8.0, 32.0), rng.uniform(0.3, 1.0)])
+    for k in range(p):
+        for b in blobs:
+            X[k] += b[5] * np.exp(-((ii - b[0]) ** 2 + (jj - b[1]) ** 2) / (2.0 * b[4] ** 2))
+            b[0] += b[2]
+            b[1] += b[3]
+            if b[0] < 0 or b[0] >= n:
+                b[2] = -b[2]
+                b[0] = min(max(b[0], 0.0), n - 1.0)
+            if b[1] < 0 or b[1] >= s:
+                b[3] = -b[3]
+                b[1] = min(max(b[1], 0.0), s - 1.0)
+    return _minmax(X)
+
+
+def mixed_blur(tube, T):
+    """A with frontal slices A(:,:,k) = tube_k * T."""
+    return np.stack([c * T for c in tube], axis=0)
+
+
+def tube_for(p):
+    """Mixing tube used for a given n3: the colour tube for p = 3, the
+    half-kernel (0.5, 0.25, 0, ...) of [0.25, 0.5, 0.25] otherwise."""
+    if p == 3:
+        return COLOUR_TUBE
+    t = np.zeros(p)
+    t[0] = 0.5
+    if p > 1:
+        t[1] = 0.25
+    return tuple(t)
+
+
+def colour_small():
+    """n1 = n2 = s = 32, n3 = 3, sigma = 2, r = 4, smooth field, nu = 1e-3, 20 iterations, FP64."""
+    rng = np.random.default_rng(1000 * 1 + 0)
+    n, p = 32, 3
+    A = mixed_blur(COLOUR_TUBE, gaussian_toeplitz(n, 2.0, 4))
+    X = smooth_field(rng, p, n, n)
+    N0 = rng.standard_normal((p, n, n))
+    return {"name": "colour_32x32x3", "A": A, "B": None, "X_true": X, "N0": N0,
+            "nu": 1e-3, "iters": 20}
+
+
+def colour_256(instance=0):
+    """n1 = n2 = s = 256, n3 = 3, sigma = 3, r = 8, smooth + edges field, nu = 1e-2, 40 iterations."""
+    rng = np.random.default_rng(1000 * 2 + instance)
+    n, p = 256, 3
+    A = mixed_blur(COLOUR_TUBE, gaussian_toeplitz(n, 3.0, 8))
+    X = edges_field(rng, p, n, n)
+    N0 = rng.standard_normal((p, n, n))
+    return {"name": "colour_256x256x3", "A": A, "B": None, "X_true": X, "N0": N0,
+            "nu": 1e-2, "iters": 40}
+
+
+def video_256(instance=0, frames=32):
+    """Two-sided A *c X *c B, n = s = 256, n3 = 32 frames: A = e_1 (x) T_{2.5,7}
+    (per-frame blur), B(:,:,k) = t_k T_{1.5,4}^T with t = (0.5, 0.25, 0, ...),
+    moving blobs, nu = 5e-3, 40 Arnoldi steps."""
+    rng = np.random.default_rng(1000 * 3 + instance)
+    n, p = 256, frames
+    A = np.zeros((p, n, n))
+    A[0] = gaussian_toeplitz(n, 2.5, 7)
+    Tb = gaussian_toeplitz(n, 1.5, 4).T
+    B = mixed_blur(tube_for(p), Tb)
+    X = moving_blobs(rng, p, n, n)
+    N0 = rng.standard_normal((p, n, n))
+    return {"name": "video_256x256x32", "A": A, "B": B, "X_true": X, "N0": N0,
+            "nu": 5e-3, "iters": 40}
+
+
+def batch_instance(i):
+    """Instance i (0..63) of the uneven batched set: n = s in {64, ..., 512},
+    n3 in {3, 8, 31}, sigma ~ U[1, 4], r = ceil(2.5 sigma), nu ~ logU[1e-3, 1e-2]."""
+    rng = np.random.default_rng(1000 * 4 + i)
+    n = int(rng.choice([64, 128, 192, 256, 384, 512]))
+    p = int(rng.choice([3, 8, 31]))
+    sigma = float(rng.uniform(1.0, 4.0))
+    r = int(math.ceil(2.5 * sigma))
+    nu = float(10.0 ** rng.uniform(-3.0, -2.0))
+    A = mixed_blur(tube_for(p), gaussian_toeplitz(n, sigma, r))
+    X = edges_field(rng, p, n, n)
+    N0 = rng.standard_normal((p, n, n))
+    return {"name": "batch_%02d" % i, "A": A, "B": None, "X_true": X, "N0": N0,
+            "nu": nu, "iters": 40}
+
+
+def tiny_random(seed, p, n1, n2, s, two_sided=False):
+    """Dense random operator and tensors for the small parity cases."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((p, n1, n2))
+    B = rng.standard_normal((p, s, s)) if two_sided else None
+    X = rng.standard_normal((p, n2, s))
+    Y = rng.standard_normal((p, n1, s))
+    return {"A": A, "B": B, "X": X, "Y": Y}
