@@ -1,0 +1,237 @@
+/*
+ * libdctkrylov -- discrete cosine tensor Krylov solvers on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the c-product of El Ichi, El Guide and Jbilou, "Discrete cosine
+ * transform LSQR and GMRES methods for multidimensional ill-posed problems"
+ * (arXiv:2103.11847), its exact adjoint, and the global Golub-Kahan / LSQR and
+ * global Arnoldi / GMRES solvers with projected Tikhonov regularisation and GCV.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Tensors.  A third-order tensor T in R^{n1 x n2 x n3} is a dense buffer of
+ *   n3*n1*n2 elements holding frontal slice k (0-based) at offset k*n1*n2,
+ *   each slice row-major: element (i, j, k) at [k*n1*n2 + i*n2 + j].  The
+ *   paper's p is n3.  "Vectors" of the Krylov methods are tensors
+ *   X in R^{n2 x s x p} (buffer length p*n2*s) or R^{n1 x s x p}.
+ * Pointers.  Unless a parameter says "host", every tensor pointer is a device
+ *   pointer on the context's device, owned by the caller; the library never
+ *   frees or reallocates it.  Buffers may not overlap unless stated.
+ * Streams.  All GPU work of a call is enqueued on the context's stream.
+ *   Kernel-level calls (tube transforms, products, single Krylov steps) are
+ *   asynchronous; calls that fill a host struct or host array synchronise
+ *   the stream once before returning.
+ * Errors.  Every call returns an int status.  Arguments are validated
+ *   before anything is enqueued.  DCTK_BREAKDOWN is a positive status: the
+ *   partial result is valid.  A failing HIP call maps to DCTK_EHIP and its
+ *   hipError_t is available from dctk_last_hip_error.  No C++ exception
+ *   crosses this interface.
+ * Threads.  A context and the objects made from it are used by one host
+ *   thread at a time.
+ */
+#ifndef DCTKRYLOV_H
+#define DCTKRYLOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define DCTK_OK 0
+#define DCTK_BREAKDOWN 1      /* Krylov breakdown (Algorithm 2 step 3(d)); result valid */
+#define DCTK_EINVAL (-1)      /* NULL pointer, bad enum, non-finite scalar, k out of range */
+#define DCTK_ESHAPE (-2)      /* inconsistent or non-positive dimensions */
+#define DCTK_EDTYPE (-3)      /* unsupported dtype combination */
+#define DCTK_ENOMEM (-4)      /* device or host allocation failed */
+#define DCTK_EHIP (-5)        /* a HIP runtime call failed */
+#define DCTK_ENONFINITE (-6)  /* the input or a Krylov scalar is NaN/Inf */
+#define DCTK_ESTATE (-7)      /* call out of order (e.g. step before init) */
+
+/* ---- element types --------------------------------------------------- */
+#define DCTK_F64 0
+#define DCTK_F32 1
+#define DCTK_BF16 2
+#define DCTK_F16 3
+
+/* ---- tube transforms (Sec. 2.2) --------------------------------------- */
+/* DCTK_TUBE_TH:   L = M = W^{-1} C_n (I + Z) of Remark 2.1 (W = diag of the
+ *                 first column of C_n, Z = ones on the superdiagonal).  With
+ *                 this L, Algorithm 1 computes exactly the Definition
+ *                 A *c B = ten(mat(A) mat(B)) of Sec. 2.2.  Default.
+ * DCTK_TUBE_DCT2: L = C_n, the orthonormal DCT-II of eq. (dft1), i.e. the
+ *                 Matlab dct of Algorithm 1 step 1 read literally.          */
+#define DCTK_TUBE_TH 0
+#define DCTK_TUBE_DCT2 1
+
+/* which matrix of the transform family (dctk_tube_matrix) */
+#define DCTK_MAT_L 0          /* L          forward transform                    */
+#define DCTK_MAT_LINV 1       /* L^{-1}     inverse transform                    */
+#define DCTK_MAT_LINVT 2      /* L^{-T}     forward transform of the adjoint     */
+#define DCTK_MAT_LT 3         /* L^{T}      inverse transform of the adjoint     */
+
+typedef struct dctk_ctx_s* dctk_ctx;
+typedef struct dctk_op_s* dctk_op;
+typedef struct dctk_krylov_s* dctk_krylov;
+
+/* ---- context ---------------------------------------------------------- */
+/* Creates a context bound to HIP device `device` and the HIP stream
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  The context owns
+ * small device scratch for reductions.  Error: DCTK_EINVAL (out NULL),
+ * DCTK_EHIP (device cannot be set). */
+int dctk_create(dctk_ctx* out, int device, void* hip_stream);
+int dctk_destroy(dctk_ctx ctx);
+/* Replaces the stream used by later calls (same device). */
+int dctk_set_stream(dctk_ctx ctx, void* hip_stream);
+/* Waits for all work enqueued by this context. */
+int dctk_synchronize(dctk_ctx ctx);
+/* Static English text for a status code; never NULL. */
+const char* dctk_status_string(int status);
+/* The hipError_t of the last failing HIP call made for ctx (0 if none). */
+int dctk_last_hip_error(dctk_ctx ctx);
+/* Interface version (major*100 + minor). */
+int dctk_version(void);
+
+/* Kernel timing.  Between dctk_profile_begin and dctk_profile_end the
+ * library brackets every tube-transform and slice-GEMM launch it enqueues
+ * for this context with HIP events on the context's stream.
+ * dctk_profile_end synchronises and writes, for kind 0 (forward tube
+ * transform), 1 (slice GEMMs of one product) and 2 (inverse tube transform
+ * with epilogue), the summed device time in ms to ms[3] and the launch count
+ * to count[3] (either may be NULL).  Error: DCTK_ESTATE if not profiling. */
+int dctk_profile_begin(dctk_ctx ctx);
+int dctk_profile_end(dctk_ctx ctx, double* ms, int* count);
+
+/* ---- tube transforms (Algorithm 1 steps 1 and 3; Remark 2.1) ----------- */
+/* Host helper: writes the p x p matrix `which` (DCTK_MAT_*) of transform
+ * `tube`, row-major FP64, into the host array out[p*p].  Built in FP64 from
+ * the closed forms of eq. (dft1) and Remark 2.1.  No GPU is touched. */
+int dctk_tube_matrix(int tube, int which, int64_t p, double* out);
+
+/* out = in x_3 G along the tubes: out[k][e] = sum_t G[k][t] in[t][e] for
+ * e < count, where in/out hold p slices of `count` elements (count = n1*n2
+ * of a tensor) and G = L (adjoint_pair = 0) or L^{-T} (adjoint_pair = 1).
+ * dtype: DCTK_F64 or DCTK_F32 (both buffers).  in and out must not overlap. */
+int dctk_tube_fwd(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p, int64_t count,
+                  const void* in, void* out);
+/* Same with G = L^{-1} (adjoint_pair = 0) or L^{T} (adjoint_pair = 1). */
+int dctk_tube_inv(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p, int64_t count,
+                  const void* in, void* out);
+
+/* ---- operators M(X) = A *c X  or  A *c X *c B  (eq. 2) ------------------ */
+/* Creates the operator of eq. (2) from A in R^{n1 x n2 x p} (device, FP64,
+ * the layout above) and, if B != NULL, B in R^{s x s x p} (device, FP64).
+ * The transform-domain slices A~ = A x_3 L (and B~) are computed once in FP64
+ * and stored in `gemm_dtype` (DCTK_F64, DCTK_F32, DCTK_BF16 or DCTK_F16),
+ * owned by the operator.  The operator acts on vectors X in R^{n2 x s x p}.
+ * Vector element type: DCTK_F64 when gemm_dtype is DCTK_F64, else DCTK_F32
+ * (BF16/F16 operators cast the transformed vector to the GEMM type and
+ * accumulate in FP32).  A and B are only read during this call.
+ * Errors: DCTK_ESHAPE (a dimension <= 0, or p > 64), DCTK_EDTYPE, DCTK_ENOMEM. */
+int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1, int64_t n2,
+                   const void* A, int64_t s, const void* B, dctk_op* out);
+int dctk_op_destroy(dctk_op op);
+/* dims[0..7] = p, n1, n2, s, two_sided, gemm_dtype, vec_dtype, tube. */
+int dctk_op_info(dctk_op op, int64_t* dims);
+
+/* Y = a * M(X) + b * Y   (Algorithm 1 applied to eq. 2).  X: p x n2 x s,
+ * Y: p x n1 x s, both in the operator's vector type.  b == 0 never reads Y.
+ * X and Y must not overlap.  Asynchronous. */
+int dctk_cprod(dctk_ctx ctx, dctk_op op, double a, const void* X, double b, void* Y);
+/* X = a * M*(Y) + b * X, with M* the exact adjoint of M under the inner
+ * product <A, B> = sum a_ijk b_ijk of Sec. 2.2 (the paper's A^T *c, which it
+ * uses in Algorithms 4 and 6 without defining it).  For DCTK_TUBE_DCT2 this
+ * is the slice-transpose product; for DCTK_TUBE_TH it uses L^{-T} and L^T. */
+int dctk_cprod_T(dctk_ctx ctx, dctk_op op, double a, const void* Y, double b, void* X);
+
+/* ---- Krylov workspaces and single steps (Algorithms 2 and 4) ------------ */
+#define DCTK_KRYLOV_GKB 0       /* Golub-Kahan (Algorithm 4) + LSQR (Algorithm 6) */
+#define DCTK_KRYLOV_ARNOLDI 1   /* global Arnoldi (Algorithm 2)                    */
+
+#define DCTK_REORTH_NONE 0      /* paper-literal                                */
+#define DCTK_REORTH_V 1         /* GKB: reorthogonalise V_{j+1} against V_1..V_j  */
+#define DCTK_REORTH_FULL 2      /* GKB: both U and V (classical Gram-Schmidt x2)  */
+
+#define DCTK_ORTHO_MGS 0        /* Arnoldi: modified Gram-Schmidt (Algorithm 2)   */
+#define DCTK_ORTHO_CGS2 1       /* Arnoldi: classical Gram-Schmidt applied twice  */
+
+/* Allocates a device workspace for `kind` on operator op: the bases
+ * (k_max + 1 vectors each), the FP64 projected matrix and scalars, and the
+ * iterate buffers.  The workspace belongs to op's context and must be
+ * destroyed before op.  k_max in [1, 64]. */
+int dctk_krylov_create(dctk_ctx ctx, dctk_op op, int kind, int k_max, int ortho, dctk_krylov* out);
+int dctk_krylov_destroy(dctk_krylov ws);
+
+/* Algorithm 4 step 2 on C (p x n1 x s): beta_1 = ||C||, U_1 = C/beta_1,
+ * alpha_1 = ||M*(U_1)||, V_1 = M*(U_1)/alpha_1, and the LSQR start of
+ * Algorithm 6 step 2 (W_1 = V_1, X_0 = 0, rhobar_1 = alpha_1, phibar_1 = beta_1).
+ * `reorth` is DCTK_REORTH_*.  Asynchronous. */
+int dctk_gkb_init(dctk_ctx ctx, dctk_krylov ws, const void* C, int reorth, double tol);
+/* One pass of Algorithm 4 step 3 (a)-(f) together with the LSQR update of
+ * Algorithm 6 steps 3(c)-(g).  All scalars stay on the device; after a
+ * breakdown or once |phibar_{j+1}| < tol the step is a no-op.  Asynchronous.
+ * Error: DCTK_ESTATE if not initialised or k_max steps were taken. */
+int dctk_gkb_step(dctk_ctx ctx, dctk_krylov ws);
+/* Algorithm 2 step 2 on V (p x n1 x s, n1 == n2): beta = ||V||, V_1 = V/beta. */
+int dctk_arnoldi_init(dctk_ctx ctx, dctk_krylov ws, const void* V);
+/* One pass of Algorithm 2 step 3 (a)-(e): column j of H~ on the device. */
+int dctk_arnoldi_step(dctk_ctx ctx, dctk_krylov ws);
+
+/* Synchronises and copies the workspace scalars to host arrays (any may be
+ * NULL):  GKB: alpha[0..k_max] = alpha_1.., beta[0..k_max] = beta_1..;
+ * Arnoldi: H[(k_max+1) * k_max] row-major h_{i+1,j+1}, beta[0] = ||V||.
+ * info4[0..3] = steps taken, status (DCTK_OK / DCTK_BREAKDOWN), converged
+ * flag, and the capacity k_max. */
+int dctk_krylov_read(dctk_ctx ctx, dctk_krylov ws, double* alpha, double* beta_or_H, int* info4);
+/* Device pointer to basis vector j (0-based) of basis `which`
+ * (0 = U for GKB / V for Arnoldi, 1 = V for GKB), or to the LSQR iterate X
+ * (which = 2) and search direction W (which = 3).  Owned by the workspace. */
+int dctk_krylov_basis(dctk_krylov ws, int which, int j, void** ptr);
+
+/* Enqueues a copy of the vector named by (which, j) as in dctk_krylov_basis
+ * into the caller's device buffer dst (p*n1*s or p*n2*s elements of the
+ * vector type).  Asynchronous. */
+int dctk_krylov_copy(dctk_ctx ctx, dctk_krylov ws, int which, int j, void* dst);
+
+/* ---- solvers ------------------------------------------------------------ */
+typedef struct {
+  int k_max;        /* GKB steps (LSQR) or Arnoldi steps per cycle (GMRES), <= workspace k_max */
+  int reorth;       /* DCTK_REORTH_* (GKB only) */
+  int gcv_mode;     /* 0: GCV of the rectangular projected problem; 1: eq. (gcv2) as printed */
+  int reserved;
+  double lambda;    /* < 0: lambda by GCV; 0: no Tikhonov (LSQR iterate / GMRES LS); > 0: fixed */
+  double tol;       /* stop when the residual norm < tol; 0 runs k_max steps / all cycles */
+} dctk_solve_opts;
+
+typedef struct {
+  int iters;        /* GKB steps taken (LSQR) or total Arnoldi steps (GMRES) */
+  int status;       /* DCTK_OK or DCTK_BREAKDOWN */
+  int converged;    /* 1 when stopped by tol */
+  int cycles;       /* GMRES cycles run */
+  double lambda;    /* regularisation parameter used (last cycle for GMRES) */
+  double resnorm;   /* LSQR: |phibar_{k+1}| = ||C - M(X_LSQR)||;  GMRES: ||C - M(X)|| */
+  double gcv;       /* GCV value at lambda (NaN when lambda was not chosen by GCV) */
+} dctk_solve_info;
+
+/* DC-LSQR / DC-GK (Algorithms 4, 5, 6) for min ||M(X) - C||: runs k_max
+ * Golub-Kahan steps with the LSQR recurrence (X_0 = 0).  lambda == 0 returns
+ * the LSQR iterate of Algorithm 6; otherwise X = V_k (*) y_lambda with y the
+ * projected Tikhonov solution of eq. (normeq2) (lambda > 0 fixed, < 0 chosen
+ * by GCV), computed in FP64 on the device.  ws must be a DCTK_KRYLOV_GKB
+ * workspace of op.  C: p x n1 x s, X (output): p x n2 x s.  Synchronises
+ * once to fill info (may be NULL). */
+int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X,
+                        const dctk_solve_opts* opts, dctk_solve_info* info);
+/* DC-GMRES(m) with Tikhonov on every cycle (Algorithm 3), m = opts->k_max,
+ * `cycles` restart cycles (the paper's itermax), X (p x n2 x s, n1 == n2)
+ * holds X_0 on entry and the result on exit.  ws must be a
+ * DCTK_KRYLOV_ARNOLDI workspace of op.  Synchronises once to fill info. */
+int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, int cycles,
+                         const dctk_solve_opts* opts, dctk_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCTKRYLOV_H */

@@ -1,0 +1,319 @@
+"""libdctkrylov: discrete cosine tensor Krylov solvers on AMD Instinct MI355X.
+
+Thin Python binding of the C-ABI declared in include/dctkrylov.h.  Every
+function here has the name of the C entry point it calls and only marshals
+arguments (torch tensors -> device pointers, structs -> ctypes); all
+arithmetic runs in the HIP library.  Importing the package does not load
+the library; the first call does, and raises if it is missing or cannot be
+loaded (there is no fallback).
+
+Tensors are torch tensors on the GPU, contiguous, shaped (p, rows, cols):
+frontal slice k is t[k].
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdctkrylov.so")
+
+DCTK_OK, DCTK_BREAKDOWN = 0, 1
+DCTK_EINVAL, DCTK_ESHAPE, DCTK_EDTYPE, DCTK_ENOMEM, DCTK_EHIP, DCTK_ENONFINITE, DCTK_ESTATE = -1, -2, -3, -4, -5, -6, -7
+DCTK_F64, DCTK_F32, DCTK_BF16, DCTK_F16 = 0, 1, 2, 3
+DCTK_TUBE_TH, DCTK_TUBE_DCT2 = 0, 1
+DCTK_MAT_L, DCTK_MAT_LINV, DCTK_MAT_LINVT, DCTK_MAT_LT = 0, 1, 2, 3
+DCTK_KRYLOV_GKB, DCTK_KRYLOV_ARNOLDI = 0, 1
+DCTK_REORTH_NONE, DCTK_REORTH_V, DCTK_REORTH_FULL = 0, 1, 2
+DCTK_ORTHO_MGS, DCTK_ORTHO_CGS2 = 0, 1
+
+TUBES = {"th": DCTK_TUBE_TH, "dct2": DCTK_TUBE_DCT2}
+DTYPES = {"f64": DCTK_F64, "f32": DCTK_F32, "bf16": DCTK_BF16, "f16": DCTK_F16}
+
+
+class DctkError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s failed: %s (status %d)" % (where, _status_string(status), status))
+
+
+class dctk_solve_opts(ctypes.Structure):
+    _fields_ = [("k_max", ctypes.c_int), ("reorth", ctypes.c_int), ("gcv_mode", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("lam", ctypes.c_double), ("tol", ctypes.c_double)]
+
+
+class dctk_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("converged", ctypes.c_int),
+                ("cycles", ctypes.c_int), ("lam", ctypes.c_double), ("resnorm", ctypes.c_double),
+                ("gcv", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "status": self.status, "converged": self.converged,
+                "cycles": self.cycles, "lambda": self.lam, "resnorm": self.resnorm, "gcv": self.gcv}
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_L = ctypes.c_int64
+_D = ctypes.c_double
+_SIGS = {
+    "dctk_create": (_I, [ctypes.POINTER(_P), _I, _P]),
+    "dctk_destroy": (_I, [_P]),
+    "dctk_set_stream": (_I, [_P, _P]),
+    "dctk_synchronize": (_I, [_P]),
+    "dctk_status_string": (ctypes.c_char_p, [_I]),
+    "dctk_last_hip_error": (_I, [_P]),
+    "dctk_version": (_I, []),
+    "dctk_profile_begin": (_I, [_P]),
+    "dctk_profile_end": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I)]),
+    "dctk_tube_matrix": (_I, [_I, _I, _L, ctypes.POINTER(_D)]),
+    "dctk_tube_fwd": (_I, [_P, _I, _I, _I, _L, _L, _P, _P]),
+    "dctk_tube_inv": (_I, [_P, _I, _I, _I, _L, _L, _P, _P]),
+    "dctk_op_create": (_I, [_P, _I, _I, _L, _L, _L, _P, _L, _P, ctypes.POINTER(_P)]),
+    "dctk_op_destroy": (_I, [_P]),
+    "dctk_op_info": (_I, [_P, ctypes.POINTER(_L)]),
+    "dctk_cprod": (_I, [_P, _P, _D, _P, _D, _P]),
+    "dctk_cprod_T": (_I, [_P, _P, _D, _P, _D, _P]),
+    "dctk_krylov_create": (_I, [_P, _P, _I, _I, _I, ctypes.POINTER(_P)]),
+    "dctk_krylov_destroy": (_I, [_P]),
+    "dctk_gkb_init": (_I, [_P, _P, _P, _I, _D]),
+    "dctk_gkb_step": (_I, [_P, _P]),
+    "dctk_arnoldi_init": (_I, [_P, _P, _P]),
+    "dctk_arnoldi_step": (_I, [_P, _P]),
+    "dctk_krylov_read": (_I, [_P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I)]),
+    "dctk_krylov_basis": (_I, [_P, _I, _I, ctypes.POINTER(_P)]),
+    "dctk_krylov_copy": (_I, [_P, _P, _I, _I, _P]),
+    "dctk_lsqr_tik_solve": (_I, [_P, _P, _P, _P, ctypes.POINTER(dctk_solve_opts), ctypes.POINTER(dctk_solve_info)]),
+    "dctk_gmres_tik_solve": (_I, [_P, _P, _P, _P, _I, ctypes.POINTER(dctk_solve_opts),
+                                  ctypes.POINTER(dctk_solve_info)]),
+}
+EXPORTED = tuple(sorted(_SIGS))
+
+
+def lib():
+    """Load libdctkrylov.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdctkrylov.so is not built (%s); run python -m paper_2103_11847_amd.build"
+                               % LIB_PATH)
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _status_string(status):
+    try:
+        return lib().dctk_status_string(status).decode()
+    except Exception:  # noqa: BLE001 - message formatting only
+        return "status %d" % status
+
+
+def _check(status, where, allow_breakdown=True):
+    if status == DCTK_OK or (allow_breakdown and status == DCTK_BREAKDOWN):
+        return status
+    raise DctkError(status, where)
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("expected %s, got %s" % (dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _vec_torch_dtype(code):
+    torch = _torch()
+    return torch.float64 if code == DCTK_F64 else torch.float32
+
+
+# ---- context -------------------------------------------------------------------
+def dctk_version():
+    return lib().dctk_version()
+
+
+def dctk_create(device=0, stream=None):
+    """Context on `device` and a HIP stream (a torch stream or raw pointer; default: torch's current)."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    h = ctypes.c_void_p()
+    _check(lib().dctk_create(ctypes.byref(h), int(device), ctypes.c_void_p(sp)), "dctk_create")
+    return h
+
+
+def dctk_destroy(ctx):
+    return _check(lib().dctk_destroy(ctx), "dctk_destroy")
+
+
+def dctk_set_stream(ctx, stream):
+    sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    return _check(lib().dctk_set_stream(ctx, ctypes.c_void_p(sp)), "dctk_set_stream")
+
+
+def dctk_synchronize(ctx):
+    return _check(lib().dctk_synchronize(ctx), "dctk_synchronize")
+
+
+def dctk_status_string(status):
+    return lib().dctk_status_string(int(status)).decode()
+
+
+def dctk_last_hip_error(ctx):
+    return lib().dctk_last_hip_error(ctx)
+
+
+def dctk_profile_begin(ctx):
+    return _check(lib().dctk_profile_begin(ctx), "dctk_profile_begin")
+
+
+def dctk_profile_end(ctx):
+    """Returns {kind: (ms_total, launches)} for kinds 'tube_fwd', 'gemm', 'tube_inv'."""
+    ms = (ctypes.c_double * 3)()
+    cnt = (ctypes.c_int * 3)()
+    _check(lib().dctk_profile_end(ctx, ms, cnt), "dctk_profile_end")
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(("tube_fwd", "gemm", "tube_inv"))}
+
+
+# ---- tube transforms ----------------------------------------------------------------
+def dctk_tube_matrix(tube, which, p):
+    """The p x p transform matrix (host, FP64) as a nested list."""
+    buf = (ctypes.c_double * (p * p))()
+    _check(lib().dctk_tube_matrix(int(tube), int(which), int(p), buf), "dctk_tube_matrix")
+    return [[buf[i * p + j] for j in range(p)] for i in range(p)]
+
+
+def _tube_call(fn, name, ctx, tube, adjoint_pair, x, out):
+    torch = _torch()
+    code = DCTK_F64 if x.dtype == torch.float64 else DCTK_F32
+    if x.dtype not in (torch.float64, torch.float32) or out.dtype != x.dtype or out.shape != x.shape:
+        raise ValueError("tube transform needs matching float32/float64 tensors")
+    p = x.shape[0]
+    count = x.numel() // p if p else 0
+    return _check(fn(ctx, int(tube), int(adjoint_pair), code, p, count, _ptr(x), _ptr(out)), name)
+
+
+def dctk_tube_fwd(ctx, tube, adjoint_pair, x, out):
+    return _tube_call(lib().dctk_tube_fwd, "dctk_tube_fwd", ctx, tube, adjoint_pair, x, out)
+
+
+def dctk_tube_inv(ctx, tube, adjoint_pair, x, out):
+    return _tube_call(lib().dctk_tube_inv, "dctk_tube_inv", ctx, tube, adjoint_pair, x, out)
+
+
+# ---- operators ----------------------------------------------------------------------
+def dctk_op_create(ctx, tube, gemm_dtype, A, s, B=None):
+    """A: (p, n1, n2) float64 GPU tensor; B: optional (p, s, s) float64."""
+    torch = _torch()
+    p, n1, n2 = A.shape
+    h = ctypes.c_void_p()
+    _check(lib().dctk_op_create(ctx, int(tube), int(gemm_dtype), p, n1, n2, _ptr(A, torch.float64), int(s),
+                                _ptr(B, torch.float64), ctypes.byref(h)), "dctk_op_create")
+    return h
+
+
+def dctk_op_destroy(op):
+    return _check(lib().dctk_op_destroy(op), "dctk_op_destroy")
+
+
+def dctk_op_info(op):
+    d = (ctypes.c_int64 * 8)()
+    _check(lib().dctk_op_info(op, d), "dctk_op_info")
+    keys = ("p", "n1", "n2", "s", "two_sided", "gemm_dtype", "vec_dtype", "tube")
+    return dict(zip(keys, list(d)))
+
+
+def dctk_cprod(ctx, op, a, X, b, Y):
+    return _check(lib().dctk_cprod(ctx, op, float(a), _ptr(X), float(b), _ptr(Y)), "dctk_cprod")
+
+
+def dctk_cprod_T(ctx, op, a, Y, b, X):
+    return _check(lib().dctk_cprod_T(ctx, op, float(a), _ptr(Y), float(b), _ptr(X)), "dctk_cprod_T")
+
+
+# ---- Krylov workspaces ---------------------------------------------------------------
+def dctk_krylov_create(ctx, op, kind, k_max, ortho=DCTK_ORTHO_MGS):
+    h = ctypes.c_void_p()
+    _check(lib().dctk_krylov_create(ctx, op, int(kind), int(k_max), int(ortho), ctypes.byref(h)),
+           "dctk_krylov_create")
+    return h
+
+
+def dctk_krylov_destroy(ws):
+    return _check(lib().dctk_krylov_destroy(ws), "dctk_krylov_destroy")
+
+
+def dctk_gkb_init(ctx, ws, C, reorth=DCTK_REORTH_NONE, tol=0.0):
+    return _check(lib().dctk_gkb_init(ctx, ws, _ptr(C), int(reorth), float(tol)), "dctk_gkb_init")
+
+
+def dctk_gkb_step(ctx, ws):
+    return _check(lib().dctk_gkb_step(ctx, ws), "dctk_gkb_step")
+
+
+def dctk_arnoldi_init(ctx, ws, V):
+    return _check(lib().dctk_arnoldi_init(ctx, ws, _ptr(V)), "dctk_arnoldi_init")
+
+
+def dctk_arnoldi_step(ctx, ws):
+    return _check(lib().dctk_arnoldi_step(ctx, ws), "dctk_arnoldi_step")
+
+
+def dctk_krylov_read(ctx, ws, k_max, kind):
+    """Returns dict(alpha, beta | H, beta0, steps, status, converged)."""
+    info = (ctypes.c_int * 4)()
+    if kind == DCTK_KRYLOV_GKB:
+        a = (ctypes.c_double * (k_max + 1))()
+        b = (ctypes.c_double * (k_max + 1))()
+        _check(lib().dctk_krylov_read(ctx, ws, a, b, info), "dctk_krylov_read")
+        return {"alpha": list(a), "beta": list(b), "steps": info[0], "status": info[1], "converged": info[2]}
+    a = (ctypes.c_double * 1)()
+    H = (ctypes.c_double * ((k_max + 1) * k_max))()
+    _check(lib().dctk_krylov_read(ctx, ws, a, H, info), "dctk_krylov_read")
+    Hm = [[H[i * k_max + j] for j in range(k_max)] for i in range(k_max + 1)]
+    return {"H": Hm, "beta0": a[0], "steps": info[0], "status": info[1], "converged": info[2]}
+
+
+def dctk_krylov_basis(ws, which, j):
+    p = ctypes.c_void_p()
+    _check(lib().dctk_krylov_basis(ws, int(which), int(j), ctypes.byref(p)), "dctk_krylov_basis")
+    return p.value
+
+
+# ---- solvers ----------------------------------------------------------------------------
+def make_opts(k_max, reorth=DCTK_REORTH_NONE, gcv_mode=0, lam=-1.0, tol=0.0):
+    return dctk_solve_opts(int(k_max), int(reorth), int(gcv_mode), 0, float(lam), float(tol))
+
+
+def dctk_lsqr_tik_solve(ctx, ws, C, X, opts):
+    info = dctk_solve_info()
+    _check(lib().dctk_lsqr_tik_solve(ctx, ws, _ptr(C), _ptr(X), ctypes.byref(opts), ctypes.byref(info)),
+           "dctk_lsqr_tik_solve")
+    return info
+
+
+def dctk_gmres_tik_solve(ctx, ws, C, X, cycles, opts):
+    info = dctk_solve_info()
+    _check(lib().dctk_gmres_tik_solve(ctx, ws, _ptr(C), _ptr(X), int(cycles), ctypes.byref(opts),
+                                      ctypes.byref(info)), "dctk_gmres_tik_solve")
+    return info
+
+
+def dctk_krylov_copy(ctx, ws, which, j, dst):
+    """Copy basis vector j of basis `which` (or X / W) into the GPU tensor dst."""
+    return _check(lib().dctk_krylov_copy(ctx, ws, int(which), int(j), _ptr(dst)), "dctk_krylov_copy")

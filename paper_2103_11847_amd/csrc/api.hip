@@ -1,0 +1,739 @@
+// The C-ABI of libdctkrylov: contexts, operators, tube transforms, c-products,
+// Krylov workspaces and the DC-LSQR / DC-GK / DC-GMRES solvers.
+//
+// Everything after argument validation is enqueued on the context's stream;
+// Krylov scalars (alpha, beta, h, the LSQR rotations, lambda, y) live in a
+// device-resident state so a solve synchronises once, at the end.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace dctk;
+
+namespace dctk {
+
+int hip_fail(dctk_ctx ctx, hipError_t e) {
+  if (ctx) ctx->last_hip_error = (int)e;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return DCTK_ENOMEM;
+  return DCTK_EHIP;
+}
+
+static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct Profiler {
+  struct Rec { hipEvent_t a, b; int kind; };
+  std::vector<Rec> recs;
+  hipEvent_t open = nullptr;
+};
+
+void prof_begin(dctk_ctx ctx, int kind) {
+  (void)kind;
+  if (!ctx || !ctx->prof) return;
+  Profiler* P = (Profiler*)ctx->prof;
+  hipEvent_t ev;
+  if (hipEventCreate(&ev) != hipSuccess) return;
+  (void)hipEventRecord(ev, ctx->stream);
+  P->open = ev;
+}
+
+void prof_end(dctk_ctx ctx, int kind) {
+  if (!ctx || !ctx->prof) return;
+  Profiler* P = (Profiler*)ctx->prof;
+  if (!P->open) return;
+  hipEvent_t ev;
+  if (hipEventCreate(&ev) != hipSuccess) return;
+  (void)hipEventRecord(ev, ctx->stream);
+  P->recs.push_back({P->open, ev, kind});
+  P->open = nullptr;
+}
+
+}  // namespace dctk
+
+extern "C" {
+
+const char* dctk_status_string(int status) {
+  switch (status) {
+    case DCTK_OK: return "ok";
+    case DCTK_BREAKDOWN: return "Krylov breakdown (result valid)";
+    case DCTK_EINVAL: return "invalid argument";
+    case DCTK_ESHAPE: return "inconsistent or non-positive dimensions";
+    case DCTK_EDTYPE: return "unsupported element type";
+    case DCTK_ENOMEM: return "out of memory";
+    case DCTK_EHIP: return "HIP runtime error";
+    case DCTK_ENONFINITE: return "non-finite value";
+    case DCTK_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+int dctk_version(void) { return 100; }
+
+int dctk_tube_matrix(int tube, int which, int64_t p, double* out) { return build_tube_matrix(tube, which, p, out); }
+
+// ---- context -----------------------------------------------------------------
+int dctk_create(dctk_ctx* out, int device, void* hip_stream) {
+  if (out == nullptr) return DCTK_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DCTK_EINVAL;
+  dctk_ctx c = new (std::nothrow) dctk_ctx_s();
+  if (!c) return DCTK_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->last_hip_error = 0;
+  c->prof = nullptr;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->red_partials, sizeof(double) * kRedBlocks * kRedVals);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->red_tickets, sizeof(unsigned) * kTickets);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->red_out, sizeof(double) * kRedVals);
+  if (e == hipSuccess) e = hipMemset(c->red_tickets, 0, sizeof(unsigned) * kTickets);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    int st = hip_fail(c, e);
+    if (c->red_partials) (void)hipFree(c->red_partials);
+    if (c->red_tickets) (void)hipFree(c->red_tickets);
+    if (c->red_out) (void)hipFree(c->red_out);
+    delete c;
+    return st;
+  }
+  set_num_cus(c->num_cus);
+  *out = c;
+  return DCTK_OK;
+}
+
+int dctk_destroy(dctk_ctx ctx) {
+  if (!ctx) return DCTK_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(ctx->red_partials);
+  (void)hipFree(ctx->red_tickets);
+  (void)hipFree(ctx->red_out);
+  delete ctx;
+  return DCTK_OK;
+}
+
+int dctk_set_stream(dctk_ctx ctx, void* hip_stream) {
+  if (!ctx) return DCTK_EINVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return DCTK_OK;
+}
+
+int dctk_synchronize(dctk_ctx ctx) {
+  if (!ctx) return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DCTK_OK;
+}
+
+int dctk_last_hip_error(dctk_ctx ctx) { return ctx ? ctx->last_hip_error : 0; }
+
+int dctk_profile_begin(dctk_ctx ctx) {
+  if (!ctx) return DCTK_EINVAL;
+  if (ctx->prof) return DCTK_ESTATE;
+  Profiler* P = new (std::nothrow) Profiler();
+  if (!P) return DCTK_ENOMEM;
+  ctx->prof = P;
+  return DCTK_OK;
+}
+
+int dctk_profile_end(dctk_ctx ctx, double* ms, int* count) {
+  if (!ctx) return DCTK_EINVAL;
+  if (!ctx->prof) return DCTK_ESTATE;
+  Profiler* P = (Profiler*)ctx->prof;
+  ctx->prof = nullptr;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  double acc[PROF_KINDS] = {0.0, 0.0, 0.0};
+  int cnt[PROF_KINDS] = {0, 0, 0};
+  for (auto& r : P->recs) {
+    float t = 0.0f;
+    if (e == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      acc[r.kind] += t;
+      cnt[r.kind] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  if (P->open) (void)hipEventDestroy(P->open);
+  delete P;
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  for (int k = 0; k < PROF_KINDS; ++k) {
+    if (ms) ms[k] = acc[k];
+    if (count) count[k] = cnt[k];
+  }
+  return DCTK_OK;
+}
+
+// ---- tube transforms -----------------------------------------------------------
+static int tube_common(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, int64_t count, const void* in,
+                       void* out) {
+  if (!ctx || !in || !out) return DCTK_EINVAL;
+  if (tube != DCTK_TUBE_TH && tube != DCTK_TUBE_DCT2) return DCTK_EINVAL;
+  if (dtype != DCTK_F64 && dtype != DCTK_F32) return DCTK_EDTYPE;
+  if (p <= 0 || count <= 0 || p > kMaxTube) return DCTK_ESHAPE;
+  const size_t bytes = (size_t)(p * count) * (dtype == DCTK_F64 ? 8 : 4);
+  if (ranges_overlap(in, bytes, out, bytes)) return DCTK_EINVAL;
+  std::vector<double> G((size_t)(p * p));
+  build_tube_matrix(tube, which, p, G.data());
+  std::vector<float> Gf((size_t)(p * p));
+  for (size_t i = 0; i < G.size(); ++i) Gf[i] = (float)G[i];
+  // the matrix travels in a small device buffer owned by this call
+  void* dG = nullptr;
+  const size_t gbytes = G.size() * (dtype == DCTK_F64 ? 8 : 4);
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  DCTK_HIP(ctx, hipMalloc(&dG, gbytes));
+  hipError_t e = hipMemcpyAsync(dG, dtype == DCTK_F64 ? (const void*)G.data() : (const void*)Gf.data(), gbytes,
+                                hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_tube(ctx->stream, dtype, dtype, p, count, in, out, (const double*)dG, (const float*)dG, 1.0, 0.0,
+                    nullptr, Gate{nullptr, 0, 0});
+  // the host copies of G must outlive the async copy; the device copy is freed after the work
+  hipError_t e3 = hipStreamSynchronize(ctx->stream);
+  hipError_t e2 = hipFree(dG);
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  if (e2 != hipSuccess) return hip_fail(ctx, e2);
+  if (e3 != hipSuccess) return hip_fail(ctx, e3);
+  return DCTK_OK;
+}
+
+int dctk_tube_fwd(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p, int64_t count, const void* in,
+                  void* out) {
+  return tube_common(ctx, tube, adjoint_pair ? DCTK_MAT_LINVT : DCTK_MAT_L, dtype, p, count, in, out);
+}
+int dctk_tube_inv(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p, int64_t count, const void* in,
+                  void* out) {
+  return tube_common(ctx, tube, adjoint_pair ? DCTK_MAT_LT : DCTK_MAT_LINV, dtype, p, count, in, out);
+}
+
+// ---- operators -------------------------------------------------------------------
+static void op_free(dctk_op op) {
+  if (!op) return;
+  void* ptrs[] = {op->Ah, op->Bh, op->Gd, op->Gf, op->xh, op->th, op->ch};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete op;
+}
+
+int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1, int64_t n2, const void* A,
+                   int64_t s, const void* B, dctk_op* out) {
+  if (!ctx || !A || !out) return DCTK_EINVAL;
+  *out = nullptr;
+  if (tube != DCTK_TUBE_TH && tube != DCTK_TUBE_DCT2) return DCTK_EINVAL;
+  if (gemm_dtype < DCTK_F64 || gemm_dtype > DCTK_F16) return DCTK_EDTYPE;
+  if (p <= 0 || n1 <= 0 || n2 <= 0 || s <= 0) return DCTK_ESHAPE;
+  if (n1 > (1 << 30) || n2 > (1 << 30) || s > (1 << 30) || p > kMaxTube) return DCTK_ESHAPE;
+  dctk_op op = new (std::nothrow) dctk_op_s();
+  if (!op) return DCTK_ENOMEM;
+  op->ctx = ctx;
+  op->tube = tube;
+  op->gemm_dtype = gemm_dtype;
+  op->vec_dtype = gemm_dtype == DCTK_F64 ? DCTK_F64 : DCTK_F32;
+  op->p = p; op->n1 = n1; op->n2 = n2; op->s = s;
+  op->two_sided = B != nullptr;
+  const size_t ge = elem_size(gemm_dtype);
+  const size_t ae = gemm_dtype == DCTK_F64 ? 8 : 4;
+  const int64_t nmax = n1 > n2 ? n1 : n2;
+  const int64_t pp = p * p;
+  std::vector<double> Gd((size_t)(4 * pp));
+  for (int w = 0; w < 4; ++w) build_tube_matrix(tube, w, p, Gd.data() + w * pp);
+  std::vector<float> Gf(Gd.size());
+  for (size_t i = 0; i < Gd.size(); ++i) Gf[i] = (float)Gd[i];
+  double* tmp = nullptr;
+  hipError_t e = hipSetDevice(ctx->device);
+#define DCTK_TRY(call) do { if (e == hipSuccess) e = (call); } while (0)
+  DCTK_TRY(hipMalloc((void**)&op->Gd, sizeof(double) * 4 * pp));
+  DCTK_TRY(hipMalloc((void**)&op->Gf, sizeof(float) * 4 * pp));
+  DCTK_TRY(hipMemcpy(op->Gd, Gd.data(), sizeof(double) * 4 * pp, hipMemcpyHostToDevice));
+  DCTK_TRY(hipMemcpy(op->Gf, Gf.data(), sizeof(float) * 4 * pp, hipMemcpyHostToDevice));
+  DCTK_TRY(hipMalloc(&op->Ah, ge * (size_t)(p * n1 * n2)));
+  if (op->two_sided) DCTK_TRY(hipMalloc(&op->Bh, ge * (size_t)(p * s * s)));
+  DCTK_TRY(hipMalloc(&op->xh, ge * (size_t)(p * nmax * s)));
+  if (op->two_sided) DCTK_TRY(hipMalloc(&op->th, ge * (size_t)(p * nmax * s)));
+  DCTK_TRY(hipMalloc(&op->ch, ae * (size_t)(p * nmax * s)));
+  // A~ = A x_3 L and B~ = B x_3 L in FP64, then cast to the GEMM type
+  const int64_t tmpn = (n1 * n2 > s * s || !op->two_sided) ? n1 * n2 : s * s;
+  if (gemm_dtype != DCTK_F64) DCTK_TRY(hipMalloc((void**)&tmp, sizeof(double) * (size_t)(p * tmpn)));
+  Gate none{nullptr, 0, 0};
+  if (gemm_dtype == DCTK_F64) {
+    DCTK_TRY(launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, n1 * n2, A, op->Ah, op->Gd, op->Gf, 1.0, 0.0, nullptr, none));
+    if (op->two_sided)
+      DCTK_TRY(launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, s * s, B, op->Bh, op->Gd, op->Gf, 1.0, 0.0, nullptr, none));
+  } else {
+    DCTK_TRY(launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, n1 * n2, A, tmp, op->Gd, op->Gf, 1.0, 0.0, nullptr, none));
+    DCTK_TRY(launch_cast(ctx, p * n1 * n2, tmp, gemm_dtype, op->Ah));
+    if (op->two_sided) {
+      DCTK_TRY(launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, s * s, B, tmp, op->Gd, op->Gf, 1.0, 0.0, nullptr, none));
+      DCTK_TRY(launch_cast(ctx, p * s * s, tmp, gemm_dtype, op->Bh));
+    }
+  }
+  DCTK_TRY(hipStreamSynchronize(ctx->stream));
+#undef DCTK_TRY
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    int st = hip_fail(ctx, e);
+    op_free(op);
+    return st;
+  }
+  *out = op;
+  return DCTK_OK;
+}
+
+int dctk_op_destroy(dctk_op op) {
+  if (!op) return DCTK_EINVAL;
+  (void)hipSetDevice(op->ctx->device);
+  (void)hipStreamSynchronize(op->ctx->stream);
+  op_free(op);
+  return DCTK_OK;
+}
+
+int dctk_op_info(dctk_op op, int64_t* dims) {
+  if (!op || !dims) return DCTK_EINVAL;
+  dims[0] = op->p; dims[1] = op->n1; dims[2] = op->n2; dims[3] = op->s;
+  dims[4] = op->two_sided; dims[5] = op->gemm_dtype; dims[6] = op->vec_dtype; dims[7] = op->tube;
+  return DCTK_OK;
+}
+
+static int cprod_common(dctk_ctx ctx, dctk_op op, int adjoint, double a, const void* in, double b, void* out) {
+  if (!ctx || !op || !in || !out) return DCTK_EINVAL;
+  if (op->ctx != ctx && op->ctx->device != ctx->device) return DCTK_EINVAL;
+  if (!std::isfinite(a) || !std::isfinite(b)) return DCTK_EINVAL;
+  const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
+  const size_t nin = (size_t)(op->p * (adjoint ? op->n1 : op->n2) * op->s) * ve;
+  const size_t nout = (size_t)(op->p * (adjoint ? op->n2 : op->n1) * op->s) * ve;
+  if (ranges_overlap(in, nin, out, nout)) return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  DCTK_HIP(ctx, apply_op(op, ctx->stream, adjoint, a, in, b, out, out, Gate{nullptr, 0, 0}));
+  return DCTK_OK;
+}
+
+int dctk_cprod(dctk_ctx ctx, dctk_op op, double a, const void* X, double b, void* Y) {
+  return cprod_common(ctx, op, 0, a, X, b, Y);
+}
+int dctk_cprod_T(dctk_ctx ctx, dctk_op op, double a, const void* Y, double b, void* X) {
+  return cprod_common(ctx, op, 1, a, Y, b, X);
+}
+
+// ---- Krylov workspaces -----------------------------------------------------------
+int dctk_krylov_create(dctk_ctx ctx, dctk_op op, int kind, int k_max, int ortho, dctk_krylov* out) {
+  if (!ctx || !op || !out) return DCTK_EINVAL;
+  *out = nullptr;
+  if (kind != DCTK_KRYLOV_GKB && kind != DCTK_KRYLOV_ARNOLDI) return DCTK_EINVAL;
+  if (k_max < 1 || k_max > kMaxK) return DCTK_EINVAL;
+  if (ortho != DCTK_ORTHO_MGS && ortho != DCTK_ORTHO_CGS2) return DCTK_EINVAL;
+  if (kind == DCTK_KRYLOV_ARNOLDI && (op->n1 != op->n2)) return DCTK_ESHAPE;
+  dctk_krylov ws = new (std::nothrow) dctk_krylov_s();
+  if (!ws) return DCTK_ENOMEM;
+  ws->op = op;
+  ws->kind = kind;
+  ws->k_max = k_max;
+  ws->ortho = ortho;
+  const int64_t nmax = op->n1 > op->n2 ? op->n1 : op->n2;
+  ws->nvec = round_up(op->p * nmax * op->s, 64);  // slot stride in elements (256-byte aligned slots)
+  const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
+  ws->vbytes = (size_t)ws->nvec * ve;
+  hipError_t e = hipSetDevice(ctx->device);
+  const size_t nslots = (size_t)(k_max + 1);
+  if (e == hipSuccess) e = hipMalloc(&ws->U, ws->vbytes * nslots);
+  if (e == hipSuccess && kind == DCTK_KRYLOV_GKB) e = hipMalloc(&ws->V, ws->vbytes * nslots);
+  if (e == hipSuccess) e = hipMalloc(&ws->X, ws->vbytes);
+  if (e == hipSuccess) e = hipMalloc(&ws->W, ws->vbytes);
+  if (e == hipSuccess) e = hipMalloc(&ws->T, ws->vbytes);
+  if (e == hipSuccess) e = hipMalloc(&ws->R, ws->vbytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->st, sizeof(KState));
+  if (e == hipSuccess) e = hipMemset(ws->st, 0, sizeof(KState));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    int st = hip_fail(ctx, e);
+    void* ptrs[] = {ws->U, ws->V, ws->X, ws->W, ws->T, ws->R, ws->st};
+    for (void* q : ptrs)
+      if (q) (void)hipFree(q);
+    delete ws;
+    return st;
+  }
+  *out = ws;
+  return DCTK_OK;
+}
+
+int dctk_krylov_destroy(dctk_krylov ws) {
+  if (!ws) return DCTK_EINVAL;
+  (void)hipSetDevice(ws->op->ctx->device);
+  (void)hipStreamSynchronize(ws->op->ctx->stream);
+  void* ptrs[] = {ws->U, ws->V, ws->X, ws->W, ws->T, ws->R, ws->st};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete ws;
+  return DCTK_OK;
+}
+
+}  // extern "C"
+
+namespace dctk {
+
+static inline char* slot(void* base, const dctk_krylov ws, int i) { return (char*)base + (size_t)i * ws->vbytes; }
+
+// Algorithm 4 step 2 + Algorithm 6 step 2, writing the LSQR iterate into X.
+static hipError_t gkb_init_impl(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, double tol) {
+  dctk_op op = ws->op;
+  KState* st = ws->st;
+  const int vdt = op->vec_dtype;
+  const int64_t nU = op->p * op->n1 * op->s, nV = op->p * op->n2 * op->s;
+  hipError_t e;
+  if ((e = launch_state_reset(ctx, st, 1, tol)) != hipSuccess) return e;
+  // beta_1 = ||C||
+  if ((e = launch_axpy_red(ctx, vdt, nU, nullptr, C, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_GKB_BETA1, nullptr, st,
+                           0, Gate{nullptr, 0, 0})) != hipSuccess)
+    return e;
+  const Gate g0{st, 0, PH_AFTER_U};
+  // U_1 = C / beta_1
+  if ((e = launch_scale(ctx, vdt, nU, slot(ws->U, ws, 0), C, &st->beta[0], g0)) != hipSuccess) return e;
+  // V~ = M*(U_1) into V slot 0; alpha_1 = ||V~||
+  if ((e = apply_op(op, ctx->stream, 1, 1.0, slot(ws->U, ws, 0), 0.0, nullptr, slot(ws->V, ws, 0), g0)) != hipSuccess)
+    return e;
+  if ((e = launch_axpy_red(ctx, vdt, nV, nullptr, slot(ws->V, ws, 0), nullptr, nullptr, 0.0, 0.0, nullptr,
+                           ACT_GKB_ALPHA1, nullptr, st, 0, g0)) != hipSuccess)
+    return e;
+  // V_1 = V~/alpha_1, W_1 = V_1, X_0 = 0
+  return launch_lsqr_start(ctx, vdt, nV, X, ws->W, slot(ws->V, ws, 0), st);
+}
+
+// Classical Gram-Schmidt applied twice of w against nb basis slots.
+static hipError_t cgs2(dctk_ctx ctx, dctk_krylov ws, void* basis, int nb, void* w, int64_t n, Gate g) {
+  hipError_t e;
+  KState* st = ws->st;
+  for (int pass = 0; pass < 2; ++pass) {
+    if ((e = launch_multidot(ctx, ws->op->vec_dtype, n, basis, ws->nvec, nb, w, st->coef, 1, 0, nullptr, g)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_subtract(ctx, ws->op->vec_dtype, n, w, basis, ws->nvec, nb, st->coef, 1, g)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+// Algorithm 4 step 3 (a)-(f) and Algorithm 6 steps 3(c)-(g), step j (1-based).
+static hipError_t gkb_step_impl(dctk_ctx ctx, dctk_krylov ws, int j, void* X) {
+  dctk_op op = ws->op;
+  KState* st = ws->st;
+  const int vdt = op->vec_dtype;
+  const int64_t nU = op->p * op->n1 * op->s, nV = op->p * op->n2 * op->s;
+  void* Uj = slot(ws->U, ws, j - 1);
+  void* Un = slot(ws->U, ws, j);
+  void* Vj = slot(ws->V, ws, j - 1);
+  void* Vn = slot(ws->V, ws, j);
+  const Gate ga{st, j, PH_ALWAYS};
+  const Gate gu{st, j, PH_AFTER_U};
+  hipError_t e;
+  // (a) U~ = M(V_j) - alpha_j U_j   (b) beta_{j+1} = ||U~||
+  if ((e = apply_op(op, ctx->stream, 0, 1.0, Vj, 0.0, nullptr, Un, ga)) != hipSuccess) return e;
+  if (ws->reorth == DCTK_REORTH_FULL) {
+    if ((e = launch_axpy_red(ctx, vdt, nU, Un, Un, Uj, &st->alpha[j - 1], -1.0, 0.0, nullptr, -1, nullptr, st, j,
+                             ga)) != hipSuccess)
+      return e;
+    if ((e = cgs2(ctx, ws, ws->U, j, Un, nU, ga)) != hipSuccess) return e;
+    if ((e = launch_axpy_red(ctx, vdt, nU, nullptr, Un, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_GKB_BETA, nullptr, st,
+                             j, ga)) != hipSuccess)
+      return e;
+  } else {
+    if ((e = launch_axpy_red(ctx, vdt, nU, Un, Un, Uj, &st->alpha[j - 1], -1.0, 0.0, nullptr, ACT_GKB_BETA, nullptr,
+                             st, j, ga)) != hipSuccess)
+      return e;
+  }
+  // (c) U_{j+1} = U~ / beta_{j+1}
+  if ((e = launch_scale(ctx, vdt, nU, Un, Un, &st->beta[j], gu)) != hipSuccess) return e;
+  // (d) V~ = M*(U_{j+1}) - beta_{j+1} V_j   (e) alpha_{j+1} = ||V~||
+  if ((e = apply_op(op, ctx->stream, 1, 1.0, Un, 0.0, nullptr, Vn, gu)) != hipSuccess) return e;
+  if (ws->reorth != DCTK_REORTH_NONE) {
+    if ((e = launch_axpy_red(ctx, vdt, nV, Vn, Vn, Vj, &st->beta[j], -1.0, 0.0, nullptr, -1, nullptr, st, j, gu)) !=
+        hipSuccess)
+      return e;
+    if ((e = cgs2(ctx, ws, ws->V, j, Vn, nV, gu)) != hipSuccess) return e;
+    if ((e = launch_axpy_red(ctx, vdt, nV, nullptr, Vn, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_GKB_ALPHA, nullptr,
+                             st, j, gu)) != hipSuccess)
+      return e;
+  } else {
+    if ((e = launch_axpy_red(ctx, vdt, nV, Vn, Vn, Vj, &st->beta[j], -1.0, 0.0, nullptr, ACT_GKB_ALPHA, nullptr, st, j,
+                             gu)) != hipSuccess)
+      return e;
+  }
+  // LSQR rotation, then (f) V_{j+1} = V~/alpha_{j+1} with the X and W updates
+  if ((e = launch_lsqr_scalars(ctx, st, j)) != hipSuccess) return e;
+  return launch_lsqr_update(ctx, vdt, nV, X, ws->W, Vn, st, j);
+}
+
+// Algorithm 2 step 2 on R: beta = ||R||, V_1 = R / beta.
+static hipError_t arnoldi_start_impl(dctk_ctx ctx, dctk_krylov ws, const void* R) {
+  dctk_op op = ws->op;
+  KState* st = ws->st;
+  const int64_t n = op->p * op->n1 * op->s;
+  hipError_t e;
+  const Gate g0{st, 0, PH_ALWAYS};
+  if ((e = launch_axpy_red(ctx, op->vec_dtype, n, nullptr, R, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_ARN_BETA,
+                           nullptr, st, 0, g0)) != hipSuccess)
+    return e;
+  return launch_scale(ctx, op->vec_dtype, n, slot(ws->U, ws, 0), R, &st->beta0, g0);
+}
+
+// Algorithm 2 step 3 (a)-(e), step j (1-based): W = M(V_j) into slot j.
+static hipError_t arnoldi_step_impl(dctk_ctx ctx, dctk_krylov ws, int j) {
+  dctk_op op = ws->op;
+  KState* st = ws->st;
+  const int vdt = op->vec_dtype;
+  const int64_t n = op->p * op->n1 * op->s;
+  void* W = slot(ws->U, ws, j);
+  const Gate ga{st, j, PH_ALWAYS};
+  const Gate gu{st, j, PH_AFTER_U};
+  hipError_t e;
+  if ((e = apply_op(op, ctx->stream, 0, 1.0, slot(ws->U, ws, j - 1), 0.0, nullptr, W, ga)) != hipSuccess) return e;
+  double* Hcol = &st->H[j - 1];  // H[i][j-1] at Hcol[i * kMaxK]
+  if (ws->ortho == DCTK_ORTHO_MGS) {
+    // h_{i,j} = <V_i, W>; W = W - h_{i,j} V_i, fused as: subtract the previous term, then dot with V_i
+    for (int i = 0; i < j; ++i) {
+      const void* prev = i > 0 ? slot(ws->U, ws, i - 1) : nullptr;
+      if ((e = launch_axpy_red(ctx, vdt, n, prev ? W : nullptr, W, prev, prev ? &Hcol[(i - 1) * kMaxK] : nullptr,
+                               -1.0, 0.0, slot(ws->U, ws, i), ACT_DOT_STORE, &Hcol[i * kMaxK], st, j, ga)) !=
+          hipSuccess)
+        return e;
+    }
+    if ((e = launch_axpy_red(ctx, vdt, n, W, W, slot(ws->U, ws, j - 1), &Hcol[(j - 1) * kMaxK], -1.0, 0.0, nullptr,
+                             ACT_ARN_H, nullptr, st, j, ga)) != hipSuccess)
+      return e;
+  } else {
+    for (int pass = 0; pass < 2; ++pass) {
+      if ((e = launch_multidot(ctx, vdt, n, ws->U, ws->nvec, j, W, Hcol, kMaxK, 1, st->coef, ga)) != hipSuccess)
+        return e;
+      if ((e = launch_subtract(ctx, vdt, n, W, ws->U, ws->nvec, j, st->coef, 1, ga)) != hipSuccess) return e;
+    }
+    if ((e = launch_axpy_red(ctx, vdt, n, nullptr, W, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_ARN_H, nullptr, st, j,
+                             ga)) != hipSuccess)
+      return e;
+  }
+  // V_{j+1} = W / h_{j+1,j}
+  return launch_scale(ctx, vdt, n, W, W, &st->H[j * kMaxK + (j - 1)], gu);
+}
+
+struct HostState {
+  int steps, stop_step, stop_kind, status, converged, cycles, halt, total_steps;
+  double scale, rhobar, phibar, cx, cw, tol, beta0, lambda, gcv, resnorm;
+};
+
+static int read_state(dctk_ctx ctx, dctk_krylov ws, HostState* hs) {
+  static_assert(sizeof(HostState) <= sizeof(KState), "state prefix");
+  DCTK_HIP(ctx, hipMemcpyAsync(hs, ws->st, sizeof(HostState), hipMemcpyDeviceToHost, ctx->stream));
+  DCTK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DCTK_OK;
+}
+
+}  // namespace dctk
+
+extern "C" {
+
+static int ws_check(dctk_ctx ctx, dctk_krylov ws, int kind) {
+  if (!ctx || !ws) return DCTK_EINVAL;
+  if (ws->kind != kind) return DCTK_EINVAL;
+  if (ws->op->ctx->device != ctx->device) return DCTK_EINVAL;
+  return DCTK_OK;
+}
+
+int dctk_gkb_init(dctk_ctx ctx, dctk_krylov ws, const void* C, int reorth, double tol) {
+  int r = ws_check(ctx, ws, DCTK_KRYLOV_GKB);
+  if (r) return r;
+  if (!C) return DCTK_EINVAL;
+  if (reorth < DCTK_REORTH_NONE || reorth > DCTK_REORTH_FULL) return DCTK_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return DCTK_EINVAL;
+  ws->reorth = reorth;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  DCTK_HIP(ctx, gkb_init_impl(ctx, ws, C, ws->X, tol));
+  ws->host_steps = 0;
+  ws->initialised = 1;
+  return DCTK_OK;
+}
+
+int dctk_gkb_step(dctk_ctx ctx, dctk_krylov ws) {
+  int r = ws_check(ctx, ws, DCTK_KRYLOV_GKB);
+  if (r) return r;
+  if (!ws->initialised || ws->host_steps >= ws->k_max) return DCTK_ESTATE;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  const int j = ws->host_steps + 1;
+  DCTK_HIP(ctx, gkb_step_impl(ctx, ws, j, ws->X));
+  ws->host_steps = j;
+  return DCTK_OK;
+}
+
+int dctk_arnoldi_init(dctk_ctx ctx, dctk_krylov ws, const void* V) {
+  int r = ws_check(ctx, ws, DCTK_KRYLOV_ARNOLDI);
+  if (r) return r;
+  if (!V) return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  DCTK_HIP(ctx, launch_state_reset(ctx, ws->st, 1, 0.0));
+  DCTK_HIP(ctx, arnoldi_start_impl(ctx, ws, V));
+  ws->host_steps = 0;
+  ws->initialised = 1;
+  return DCTK_OK;
+}
+
+int dctk_arnoldi_step(dctk_ctx ctx, dctk_krylov ws) {
+  int r = ws_check(ctx, ws, DCTK_KRYLOV_ARNOLDI);
+  if (r) return r;
+  if (!ws->initialised || ws->host_steps >= ws->k_max) return DCTK_ESTATE;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  const int j = ws->host_steps + 1;
+  DCTK_HIP(ctx, arnoldi_step_impl(ctx, ws, j));
+  ws->host_steps = j;
+  return DCTK_OK;
+}
+
+int dctk_krylov_read(dctk_ctx ctx, dctk_krylov ws, double* alpha, double* beta_or_H, int* info4) {
+  if (!ctx || !ws) return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  KState* h = new (std::nothrow) KState();
+  if (!h) return DCTK_ENOMEM;
+  hipError_t e = hipMemcpyAsync(h, ws->st, sizeof(KState), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(ctx, e);
+  }
+  const int K = ws->k_max;
+  if (ws->kind == DCTK_KRYLOV_GKB) {
+    if (alpha) for (int i = 0; i <= K; ++i) alpha[i] = h->alpha[i];
+    if (beta_or_H) for (int i = 0; i <= K; ++i) beta_or_H[i] = h->beta[i];
+  } else {
+    if (beta_or_H)
+      for (int i = 0; i <= K; ++i)
+        for (int j = 0; j < K; ++j) beta_or_H[i * K + j] = h->H[i * kMaxK + j];
+    if (alpha) alpha[0] = h->beta0;
+  }
+  if (info4) {
+    info4[0] = h->steps;
+    info4[1] = h->status;
+    info4[2] = h->converged;
+    info4[3] = K;
+  }
+  delete h;
+  return DCTK_OK;
+}
+
+int dctk_krylov_basis(dctk_krylov ws, int which, int j, void** ptr) {
+  if (!ws || !ptr) return DCTK_EINVAL;
+  if (which == 2) { *ptr = ws->X; return DCTK_OK; }
+  if (which == 3) { *ptr = ws->W; return DCTK_OK; }
+  if (j < 0 || j > ws->k_max) return DCTK_EINVAL;
+  if (which == 0) { *ptr = slot(ws->U, ws, j); return DCTK_OK; }
+  if (which == 1 && ws->V) { *ptr = slot(ws->V, ws, j); return DCTK_OK; }
+  return DCTK_EINVAL;
+}
+
+int dctk_krylov_copy(dctk_ctx ctx, dctk_krylov ws, int which, int j, void* dst) {
+  if (!ctx || !ws || !dst) return DCTK_EINVAL;
+  void* src = nullptr;
+  int r = dctk_krylov_basis(ws, which, j, &src);
+  if (r) return r;
+  dctk_op op = ws->op;
+  const bool u_side = (ws->kind == DCTK_KRYLOV_GKB && which == 0);
+  const int64_t n = op->p * (u_side ? op->n1 : op->n2) * op->s;
+  const size_t bytes = (size_t)n * (op->vec_dtype == DCTK_F64 ? 8 : 4);
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  DCTK_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  return DCTK_OK;
+}
+
+static int check_opts(const dctk_solve_opts* o, const dctk_krylov ws) {
+  if (!o) return DCTK_EINVAL;
+  if (o->k_max < 1 || o->k_max > ws->k_max) return DCTK_EINVAL;
+  if (o->reorth < DCTK_REORTH_NONE || o->reorth > DCTK_REORTH_FULL) return DCTK_EINVAL;
+  if (o->gcv_mode != 0 && o->gcv_mode != 1) return DCTK_EINVAL;
+  if (std::isnan(o->lambda) || std::isinf(o->lambda)) return DCTK_EINVAL;
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return DCTK_EINVAL;
+  return DCTK_OK;
+}
+
+int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, const dctk_solve_opts* opts,
+                        dctk_solve_info* info) {
+  int r = ws_check(ctx, ws, DCTK_KRYLOV_GKB);
+  if (r) return r;
+  if (!C || !X) return DCTK_EINVAL;
+  if ((r = check_opts(opts, ws))) return r;
+  dctk_op op = ws->op;
+  const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
+  if (ranges_overlap(C, (size_t)(op->p * op->n1 * op->s) * ve, X, (size_t)(op->p * op->n2 * op->s) * ve))
+    return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  ws->reorth = opts->reorth;
+  const bool tik = opts->lambda != 0.0;
+  void* Xl = tik ? ws->X : X;  // LSQR iterate (Algorithm 6)
+  DCTK_HIP(ctx, gkb_init_impl(ctx, ws, C, Xl, opts->tol));
+  for (int j = 1; j <= opts->k_max; ++j) DCTK_HIP(ctx, gkb_step_impl(ctx, ws, j, Xl));
+  ws->host_steps = opts->k_max;
+  ws->initialised = 1;
+  if (tik) {
+    // Algorithm 5: lambda (GCV or fixed), y, X = V_k (*) y
+    DCTK_HIP(ctx, launch_projected(ctx, ws->st, 1, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda));
+    DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec,
+                                 opts->k_max, &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
+  }
+  HostState hs;
+  if ((r = read_state(ctx, ws, &hs))) return r;
+  if (info) {
+    info->iters = hs.steps;
+    info->status = hs.status;
+    info->converged = hs.converged;
+    info->cycles = 0;
+    info->lambda = tik ? hs.lambda : 0.0;
+    info->resnorm = std::fabs(hs.phibar);
+    info->gcv = (tik && opts->lambda < 0.0) ? hs.gcv : NAN;
+  }
+  return hs.status;
+}
+
+int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, int cycles,
+                         const dctk_solve_opts* opts, dctk_solve_info* info) {
+  int r = ws_check(ctx, ws, DCTK_KRYLOV_ARNOLDI);
+  if (r) return r;
+  if (!C || !X) return DCTK_EINVAL;
+  if (cycles < 1) return DCTK_EINVAL;
+  if ((r = check_opts(opts, ws))) return r;
+  dctk_op op = ws->op;
+  const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
+  const int64_t n = op->p * op->n1 * op->s;
+  if (ranges_overlap(C, (size_t)n * ve, X, (size_t)n * ve)) return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  KState* st = ws->st;
+  const Gate g0{st, 0, PH_ALWAYS};
+  const int m = opts->k_max;
+  DCTK_HIP(ctx, launch_state_reset(ctx, st, 1, opts->tol));
+  // R_0 = C - M(X_0)
+  DCTK_HIP(ctx, apply_op(op, ctx->stream, 0, -1.0, X, 1.0, C, ws->R, g0));
+  for (int c = 0; c < cycles; ++c) {
+    DCTK_HIP(ctx, launch_state_reset(ctx, st, 0, 0.0));
+    DCTK_HIP(ctx, arnoldi_start_impl(ctx, ws, ws->R));
+    for (int j = 1; j <= m; ++j) DCTK_HIP(ctx, arnoldi_step_impl(ctx, ws, j));
+    DCTK_HIP(ctx, launch_projected(ctx, st, 0, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda));
+    DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, n, X, X, ws->U, ws->nvec, m, &st->steps, st->y, g0));
+    DCTK_HIP(ctx, apply_op(op, ctx->stream, 0, -1.0, X, 1.0, C, ws->R, g0));
+    DCTK_HIP(ctx, launch_axpy_red(ctx, op->vec_dtype, n, nullptr, ws->R, nullptr, nullptr, 0.0, 0.0, nullptr,
+                                  ACT_GMRES_RES, nullptr, st, 0, g0));
+  }
+  ws->host_steps = 0;
+  ws->initialised = 0;
+  HostState hs;
+  if ((r = read_state(ctx, ws, &hs))) return r;
+  if (info) {
+    info->iters = hs.total_steps;
+    info->status = hs.status;
+    info->converged = hs.converged;
+    info->cycles = hs.cycles;
+    info->lambda = hs.lambda;
+    info->resnorm = hs.resnorm;
+    info->gcv = opts->lambda < 0.0 ? hs.gcv : NAN;
+  }
+  return hs.status;
+}
+
+}  // extern "C"

@@ -1,0 +1,306 @@
+// Transform-domain frontal-slice products (Algorithm 1 step 2): the one
+// dense contraction of the c-product, C~_k = op(A~_k) op(B~_k) for k < p,
+// as batched GEMMs on the gfx950 matrix cores.
+//
+// Tile: BM x BN outputs per workgroup of 4 waves arranged 2 x 2, each wave
+// owning (BM/2) x (BN/2) as 16 x 16 MFMA blocks.  Operands are staged through
+// LDS as [rows][BK + pad] (contraction index contiguous) so each lane's MFMA
+// operand is one LDS read: 1 element for the K = 4 FP32/FP64 instructions,
+// 8 packed 16-bit elements for the K = 32 BF16/FP16 instructions of gfx950.
+// Global loads are ordered along each operand's contiguous dimension; the
+// next K-chunk is prefetched into registers while the current one is
+// multiplied.  Ragged edges are zero-filled on load and masked on store.
+#include "internal.h"
+
+namespace dctk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// MFMA per input type: KSTEP = contraction length of one instruction,
+// EPL = elements of A (and of B) each lane supplies.
+template <typename TI> struct Mfma;
+// ROWS_STRIDED: output register r of lane l holds row (l/16) + 4 r (FP64)
+// instead of 4 (l/16) + r (FP32 / BF16 / FP16), column l % 16 in both.
+template <> struct Mfma<double> {
+  static constexpr int KSTEP = 4, EPL = 1;
+  static constexpr bool ROWS_STRIDED = true;
+  typedef double acc_t;
+  typedef f64x4 frag_t;
+  __device__ static frag_t mac(const double* a, const double* b, frag_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  static constexpr bool ROWS_STRIDED = false;
+  static constexpr int KSTEP = 4, EPL = 1;
+  typedef float acc_t;
+  typedef f32x4 frag_t;
+  __device__ static frag_t mac(const float* a, const float* b, frag_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<bf16_t> {
+  static constexpr bool ROWS_STRIDED = false;
+  static constexpr int KSTEP = 32, EPL = 8;
+  typedef float acc_t;
+  typedef f32x4 frag_t;
+  __device__ static frag_t mac(const bf16_t* a, const bf16_t* b, frag_t c) {
+    bf16x8 av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(a));
+    bf16x8 bv = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(b));
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<f16_t> {
+  static constexpr bool ROWS_STRIDED = false;
+  static constexpr int KSTEP = 32, EPL = 8;
+  typedef float acc_t;
+  typedef f32x4 frag_t;
+  __device__ static frag_t mac(const f16_t* a, const f16_t* b, frag_t c) {
+    f16x8 av = __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(a));
+    f16x8 bv = __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(b));
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, c, 0, 0, 0);
+  }
+};
+
+template <typename TO, typename TA> __device__ inline TO out_cvt(TA v) { return (TO)v; }
+template <> __device__ inline bf16_t out_cvt<bf16_t, float>(float v) { return float_to_bf16(v); }
+
+template <typename TI, typename TO, int BM, int BN, bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
+                                                   const TI* __restrict__ A, int64_t lda, int64_t sA,
+                                                   const TI* __restrict__ B, int64_t ldb, int64_t sB,
+                                                   TO* __restrict__ C, int64_t ldc, int64_t sC, Gate g) {
+  typedef Mfma<TI> MF;
+  typedef typename MF::acc_t acc_t;
+  typedef typename MF::frag_t frag_t;
+  constexpr int KSTEP = MF::KSTEP;
+  constexpr int BK = (KSTEP == 4) ? 16 : 64;
+  constexpr int PAD = (sizeof(TI) == 2) ? 8 : (sizeof(TI) == 4 ? 4 : 2);  // 16 bytes
+  constexpr int LDS_LD = BK + PAD;
+  constexpr int A_PER = BM * BK / 256;  // elements of the A tile per thread
+  constexpr int B_PER = BN * BK / 256;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  static_assert(A_PER >= 1 && B_PER >= 1, "tile too small");
+
+  if (!gate_open(g)) return;
+
+  __shared__ __attribute__((aligned(16))) TI As[BM * LDS_LD];
+  __shared__ __attribute__((aligned(16))) TI Bs[BN * LDS_LD];
+
+  const int bz = blockIdx.z;
+  const int m0 = blockIdx.y * BM;
+  const int n0 = blockIdx.x * BN;
+  A += (int64_t)bz * sA;
+  B += (int64_t)bz * sB;
+  C += (int64_t)bz * sC;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // element (r, kk) of the A tile (r < BM, kk < BK) handled by this thread, slot u
+  auto a_coord = [&](int u, int& r, int& kk) {
+    int idx = tid + u * 256;
+    if (!TA) { r = idx / BK; kk = idx % BK; }   // contiguous along k
+    else     { kk = idx / BM; r = idx % BM; }   // contiguous along m
+  };
+  auto b_coord = [&](int u, int& c, int& kk) {
+    int idx = tid + u * 256;
+    if (!TB) { kk = idx / BN; c = idx % BN; }   // contiguous along n
+    else     { c = idx / BK; kk = idx % BK; }   // contiguous along k
+  };
+
+  TI ra[A_PER], rb[B_PER];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u) {
+      int r, kk;
+      a_coord(u, r, kk);
+      int gm = m0 + r, gk = k0 + kk;
+      TI v = (TI)0;
+      if (gm < M && gk < K) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < B_PER; ++u) {
+      int c, kk;
+      b_coord(u, c, kk);
+      int gn = n0 + c, gk = k0 + kk;
+      TI v = (TI)0;
+      if (gn < N && gk < K) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      rb[u] = v;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u) {
+      int r, kk;
+      a_coord(u, r, kk);
+      As[r * LDS_LD + kk] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < B_PER; ++u) {
+      int c, kk;
+      b_coord(u, c, kk);
+      Bs[c * LDS_LD + kk] = rb[u];
+    }
+  };
+
+  frag_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = (acc_t)0;
+
+  const int lr = lane & 15;          // row (A) / column (B) within a 16-block
+  const int lk = (lane >> 4) * MF::EPL;  // first contraction index of this lane
+
+  load_tiles(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    store_tiles();
+    __syncthreads();
+    if (k0 + BK < K) load_tiles(k0 + BK);  // prefetch the next chunk into registers
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += KSTEP) {
+      const TI* ap[FM];
+      const TI* bp[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) ap[i] = &As[(wm * WM + i * 16 + lr) * LDS_LD + ks + lk];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bp[j] = &Bs[(wn * WN + j * 16 + lr) * LDS_LD + ks + lk];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = MF::mac(ap[i], bp[j], acc[i][j]);
+    }
+  }
+
+  // D layout of the 16x16 instructions: column lane % 16; rows 4 (lane/16) + r, or
+  // lane/16 + 4 r for FP64.
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * WN + j * 16 + (lane & 15);
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + (MF::ROWS_STRIDED ? (lane >> 4) + 4 * r : (lane >> 4) * 4 + r);
+        if (row < M) C[(int64_t)row * ldc + col] = out_cvt<TO, acc_t>(acc[i][j][r]);
+      }
+    }
+}
+
+template <typename TI, typename TO, int BM, int BN>
+static hipError_t launch_gemm_tile(hipStream_t s, int M, int N, int K, const void* A, int64_t lda,
+                                   int64_t sA, int ta, const void* B, int64_t ldb, int64_t sB, int tb,
+                                   void* C, int64_t ldc, int64_t sC, int batch, Gate g) {
+  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)batch);
+  const TI* a = (const TI*)A;
+  const TI* b = (const TI*)B;
+  TO* c = (TO*)C;
+#define DCTK_GEMM_LAUNCH(TA_, TB_) \
+  hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, TA_, TB_>), grid, dim3(256), 0, s, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, g)
+  if (!ta && !tb) DCTK_GEMM_LAUNCH(false, false);
+  else if (ta && !tb) DCTK_GEMM_LAUNCH(true, false);
+  else if (!ta && tb) DCTK_GEMM_LAUNCH(false, true);
+  else DCTK_GEMM_LAUNCH(true, true);
+#undef DCTK_GEMM_LAUNCH
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+static hipError_t launch_gemm_t(hipStream_t s, int M, int N, int K, const void* A, int64_t lda, int64_t sA,
+                                int ta, const void* B, int64_t ldb, int64_t sB, int tb, void* C, int64_t ldc,
+                                int64_t sC, int batch, Gate g, int num_cus) {
+  // 64 x 64 tiles when they fill the chip, 32 x 32 otherwise.
+  int64_t tiles64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64) * batch;
+  if (tiles64 >= 2 * (int64_t)num_cus)
+    return launch_gemm_tile<TI, TO, 64, 64>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
+  return launch_gemm_tile<TI, TO, 32, 32>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
+}
+
+static int g_num_cus = 256;
+
+hipError_t launch_gemm(hipStream_t s, int in_dtype, int out_acc, int M, int N, int K,
+                       const void* A, int64_t lda, int64_t sA, int ta,
+                       const void* B, int64_t ldb, int64_t sB, int tb,
+                       void* C, int64_t ldc, int64_t sC, int batch, Gate g) {
+  // out_acc = 1: output in the accumulator type; 0: output in the input type
+  switch (in_dtype) {
+    case DCTK_F64:
+      return launch_gemm_t<double, double>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+    case DCTK_F32:
+      return launch_gemm_t<float, float>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+    case DCTK_BF16:
+      if (out_acc)
+        return launch_gemm_t<bf16_t, float>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+      return launch_gemm_t<bf16_t, bf16_t>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+    case DCTK_F16:
+      if (out_acc)
+        return launch_gemm_t<f16_t, float>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+      return launch_gemm_t<f16_t, f16_t>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// ---- the c-product and its adjoint on an operator's workspaces ---------------
+static size_t dtype_size(int dt) { return dt == DCTK_F64 ? 8 : (dt == DCTK_F32 ? 4 : 2); }
+
+hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, double a, const void* X, double b,
+                    const void* src, void* Y, Gate g) {
+  const int64_t p = op->p, n1 = op->n1, n2 = op->n2, sc = op->s;
+  const int gdt = op->gemm_dtype, vdt = op->vec_dtype;
+  const double* Gd = op->Gd;
+  const float* Gf = op->Gf;
+  const int64_t pp = p * p;
+  hipError_t e;
+  // rows of the input / output vectors
+  const int64_t rin = adjoint ? n1 : n2;
+  const int64_t rout = adjoint ? n2 : n1;
+  // step 1: transform the input tubes (L, or L^{-T} for the adjoint) into the GEMM type
+  const int gi = adjoint ? 2 : 0;
+  dctk_ctx ctx = op->ctx;
+  prof_begin(ctx, PROF_TUBE_FWD);
+  e = launch_tube(s, vdt, gdt, p, rin * sc, X, op->xh, Gd + gi * pp, Gf + gi * pp, 1.0, 0.0, nullptr, g);
+  prof_end(ctx, PROF_TUBE_FWD);
+  if (e != hipSuccess) return e;
+  // step 2: slice products
+  const int64_t sAh = n1 * n2;
+  prof_begin(ctx, PROF_GEMM);
+  if (!op->two_sided) {
+    // forward: (n1 x n2)(n2 x s);  adjoint: (n2 x n1 := A~^T)(n1 x s)
+    e = launch_gemm(s, gdt, 1, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
+                    op->xh, sc, rin * sc, 0, op->ch, sc, rout * sc, (int)p, g);
+  } else {
+    e = launch_gemm(s, gdt, 0, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
+                    op->xh, sc, rin * sc, 0, op->th, sc, rout * sc, (int)p, g);
+    if (e != hipSuccess) return e;
+    // right factor: forward (rout x s)(s x s) with B~; adjoint with B~^T
+    e = launch_gemm(s, gdt, 1, (int)rout, (int)sc, (int)sc, op->th, sc, rout * sc, 0,
+                    op->Bh, sc, sc * sc, adjoint ? 1 : 0, op->ch, sc, rout * sc, (int)p, g);
+  }
+  prof_end(ctx, PROF_GEMM);
+  if (e != hipSuccess) return e;
+  // step 3: inverse transform (L^{-1}, or L^T for the adjoint) with the a/b epilogue
+  const int go = adjoint ? 3 : 1;
+  prof_begin(ctx, PROF_TUBE_INV);
+  e = launch_tube(s, vdt, vdt, p, rout * sc, op->ch, Y, Gd + go * pp, Gf + go * pp, a, b,
+                  (b != 0.0) ? src : nullptr, g);
+  prof_end(ctx, PROF_TUBE_INV);
+  return e;
+}
+
+void set_num_cus(int n) { if (n > 0) g_num_cus = n; }
+size_t elem_size(int dt) { return dtype_size(dt); }
+
+}  // namespace dctk

@@ -1,0 +1,203 @@
+// Tube transforms along mode 3 (Algorithm 1 steps 1 and 3; Remark 2.1).
+//
+// A tube transform is out = in x_3 G with G a small p x p matrix: for every
+// position e of a frontal slice, out[k][e] = sum_t G[k][t] in[t][e].  With the
+// slice-major layout the p inputs of a tube are p slices apart, so a thread
+// streams VEC consecutive positions of every slice (coalesced 16-byte loads
+// along the slice) and keeps KB outputs in registers per pass; G sits in LDS.
+// The work is HBM-bound for the p of colour images and video (2p flops per
+// 2 elements moved).
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace dctk {
+
+// ---- host: the transform matrices, FP64 closed forms -----------------------
+// C_n of eq. (dft1), 0-based: C[i][j] = sqrt((2 - [i == 0]) / n) cos(i (2j + 1) pi / (2n)).
+static void dct_matrix(int64_t n, std::vector<double>& C) {
+  C.assign((size_t)(n * n), 0.0);
+  const double pi = 3.14159265358979323846264338327950288;
+  for (int64_t i = 0; i < n; ++i) {
+    double sc = std::sqrt((i == 0 ? 1.0 : 2.0) / (double)n);
+    for (int64_t j = 0; j < n; ++j)
+      C[(size_t)(i * n + j)] = sc * std::cos((double)i * (double)(2 * j + 1) * pi / (2.0 * (double)n));
+  }
+}
+
+int build_tube_matrix(int tube, int which, int64_t p, double* out) {
+  if (p <= 0) return DCTK_ESHAPE;
+  if (out == nullptr) return DCTK_EINVAL;
+  if (which < DCTK_MAT_L || which > DCTK_MAT_LT) return DCTK_EINVAL;
+  std::vector<double> C, L((size_t)(p * p)), Li((size_t)(p * p));
+  dct_matrix(p, C);
+  if (tube == DCTK_TUBE_DCT2) {
+    for (int64_t i = 0; i < p; ++i)
+      for (int64_t j = 0; j < p; ++j) {
+        L[(size_t)(i * p + j)] = C[(size_t)(i * p + j)];
+        Li[(size_t)(i * p + j)] = C[(size_t)(j * p + i)];  // C^{-1} = C^T
+      }
+  } else if (tube == DCTK_TUBE_TH) {
+    // M = W^{-1} C (I + Z): row i of C (I + Z) is C[i][j] + C[i][j-1], scaled by 1 / C[i][0].
+    for (int64_t i = 0; i < p; ++i)
+      for (int64_t j = 0; j < p; ++j) {
+        double v = C[(size_t)(i * p + j)] + (j > 0 ? C[(size_t)(i * p + j - 1)] : 0.0);
+        L[(size_t)(i * p + j)] = v / C[(size_t)(i * p)];
+      }
+    // M^{-1} = (I + Z)^{-1} C^T W with (I + Z)^{-1}[i][l] = (-1)^{l - i} for l >= i:
+    // M^{-1}[i][j] = C[j][0] * sum_{l >= i} (-1)^{l - i} C[j][l].
+    for (int64_t i = 0; i < p; ++i)
+      for (int64_t j = 0; j < p; ++j) {
+        double acc = 0.0, sg = 1.0;
+        for (int64_t l = i; l < p; ++l, sg = -sg) acc += sg * C[(size_t)(j * p + l)];
+        Li[(size_t)(i * p + j)] = acc * C[(size_t)(j * p)];
+      }
+  } else {
+    return DCTK_EINVAL;
+  }
+  for (int64_t i = 0; i < p; ++i)
+    for (int64_t j = 0; j < p; ++j) {
+      double v;
+      switch (which) {
+        case DCTK_MAT_L: v = L[(size_t)(i * p + j)]; break;
+        case DCTK_MAT_LINV: v = Li[(size_t)(i * p + j)]; break;
+        case DCTK_MAT_LINVT: v = Li[(size_t)(j * p + i)]; break;
+        default: v = L[(size_t)(j * p + i)]; break;
+      }
+      out[i * p + j] = v;
+    }
+  return DCTK_OK;
+}
+
+// ---- device: the streaming transform ----------------------------------------
+template <typename T> struct Vec4Load;
+template <> struct Vec4Load<float> {
+  __device__ static void load(const float* p, float* v) {
+    float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+};
+template <> struct Vec4Load<double> {
+  __device__ static void load(const double* p, double* v) {
+    double2 a = *reinterpret_cast<const double2*>(p);
+    double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+};
+
+template <typename T> struct Vec4Store {
+  __device__ static void store(T* p, const T* v) {
+    for (int i = 0; i < 4; ++i) p[i] = v[i];
+  }
+};
+template <> struct Vec4Store<float> {
+  __device__ static void store(float* p, const float* v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+};
+template <> struct Vec4Store<double> {
+  __device__ static void store(double* p, const double* v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+  }
+};
+
+// TIN/TSRC: float or double; TOUT: float, double, bf16_t or f16_t; TC: compute type.
+template <typename TIN, typename TOUT, typename TC, int KB, bool VEC>
+__global__ __launch_bounds__(kThreads) void tube_kernel(int p, int64_t count, const TIN* __restrict__ in,
+                                                        TOUT* out, const TC* __restrict__ G,
+                                                        TC a, TC b, const TOUT* src, Gate g) {
+  if (!gate_open(g)) return;
+  extern __shared__ char smem_raw[];
+  TC* sG = reinterpret_cast<TC*>(smem_raw);
+  for (int i = threadIdx.x; i < p * p; i += blockDim.x) sG[i] = G[i];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+  for (int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e0 < count; e0 += stride) {
+    const int nv = (count - e0) < 4 ? (int)(count - e0) : 4;
+    for (int k0 = 0; k0 < p; k0 += KB) {
+      TC acc[KB][4];
+#pragma unroll
+      for (int kk = 0; kk < KB; ++kk)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[kk][v] = (TC)0;
+      for (int t = 0; t < p; ++t) {
+        TIN xv[4];
+        const TIN* ip = in + (int64_t)t * count + e0;
+        if (VEC && nv == 4) {
+          Vec4Load<TIN>::load(ip, xv);
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xv[v] = v < nv ? ip[v] : (TIN)0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+          const TC gk = (k0 + kk < p) ? sG[(k0 + kk) * p + t] : (TC)0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[kk][v] += gk * (TC)xv[v];
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < KB; ++kk) {
+        const int k = k0 + kk;
+        if (k >= p) break;
+        TOUT* op = out + (int64_t)k * count + e0;
+        TOUT ov[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          TC r = a * acc[kk][v];
+          if (b != (TC)0 && v < nv) r += b * (TC)src[(int64_t)k * count + e0 + v];
+          ov[v] = cvt<TOUT, TC>(r);
+        }
+        if (VEC && nv == 4) {
+          Vec4Store<TOUT>::store(op, ov);
+        } else {
+          for (int v = 0; v < nv; ++v) op[v] = ov[v];
+        }
+      }
+    }
+  }
+}
+
+template <typename TIN, typename TOUT, typename TC>
+static hipError_t launch_tube_t(hipStream_t s, int64_t p, int64_t count, const void* in, void* out,
+                                const TC* G, double a, double b, const void* src, Gate g) {
+  int64_t nthreads = (count + 3) / 4;
+  int64_t blocks = (nthreads + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  size_t shmem = (size_t)(p * p) * sizeof(TC);
+  bool vec = (count % 4 == 0) && (((uintptr_t)in) % 32 == 0) && (((uintptr_t)out) % 32 == 0) &&
+             (src == nullptr || ((uintptr_t)src) % 32 == 0);
+  const TIN* i = (const TIN*)in;
+  TOUT* o = (TOUT*)out;
+  const TOUT* sr = (const TOUT*)src;
+  TC ta = (TC)a, tb = (TC)b;
+#define DCTK_TUBE_LAUNCH(KB, V) \
+  hipLaunchKernelGGL((tube_kernel<TIN, TOUT, TC, KB, V>), dim3((unsigned)blocks), dim3(kThreads), shmem, s, (int)p, count, i, o, G, ta, tb, sr, g)
+  if (p <= 4) {
+    if (vec) DCTK_TUBE_LAUNCH(4, true); else DCTK_TUBE_LAUNCH(4, false);
+  } else {
+    if (vec) DCTK_TUBE_LAUNCH(8, true); else DCTK_TUBE_LAUNCH(8, false);
+  }
+#undef DCTK_TUBE_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_tube(hipStream_t s, int vec_dtype, int out_dtype, int64_t p, int64_t count,
+                       const void* in, void* out, const double* Gd, const float* Gf,
+                       double a, double b, const void* src, Gate g) {
+  if (vec_dtype == DCTK_F64) {
+    // FP64 input: output FP64 (the only FP64 GEMM type)
+    return launch_tube_t<double, double, double>(s, p, count, in, out, Gd, a, b, src, g);
+  }
+  switch (out_dtype) {
+    case DCTK_F32: return launch_tube_t<float, float, float>(s, p, count, in, out, Gf, a, b, src, g);
+    case DCTK_BF16: return launch_tube_t<float, bf16_t, float>(s, p, count, in, out, Gf, a, b, src, g);
+    case DCTK_F16: return launch_tube_t<float, f16_t, float>(s, p, count, in, out, Gf, a, b, src, g);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dctk

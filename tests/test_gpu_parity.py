@@ -1,0 +1,415 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances (relative Frobenius unless stated):
+  * c-product / adjoint / tube transform: 1e-10 in FP64, 1e-5 in FP32; the
+    BF16/FP16 GEMM modes are checked against a bound derived from their unit
+    roundoff (8 u sqrt(p) with u = 2^-8 / 2^-11 for one rounding of each
+    operand, FP32 accumulation);
+  * Golub-Kahan / Arnoldi scalars and solver iterates in FP64 with full
+    reorthogonalisation on both sides: 1e-9 (the Krylov recurrences amplify
+    the 1e-16 product error by the conditioning of the projected problem);
+  * GCV: the GCV value at the library's lambda is within 1e-9 of the
+    oracle's minimum, and X equals the oracle's X at the library's lambda.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import krylov, metrics, tikhonov
+from oracle import tube as otube
+from oracle.cprod import Operator, fro
+from tests.gpu_util import rel, say, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2103_11847_amd as dk  # noqa: E402
+
+F64, F32 = torch.float64, torch.float32
+VT = {dk.DCTK_F64: F64, dk.DCTK_F32: F32, dk.DCTK_BF16: F32, dk.DCTK_F16: F32}
+TOL_PROD = {dk.DCTK_F64: 1e-10, dk.DCTK_F32: 1e-5}
+
+
+_OPS = []   # operator handles created by the tests, destroyed with the context
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = dk.dctk_create(0)
+    yield c
+    dk.dctk_synchronize(c)
+    while _OPS:
+        dk.dctk_op_destroy(_OPS.pop())
+    dk.dctk_destroy(c)
+
+
+@pytest.fixture(autouse=True)
+def _release_ops():
+    """Destroy each test's operators when it ends (also when it fails)."""
+    n = len(_OPS)
+    yield
+    torch.cuda.synchronize()
+    while len(_OPS) > n:
+        dk.dctk_op_destroy(_OPS.pop())
+
+
+class Op:
+    """Operator handle; destroyed by the fixtures above, never by __del__."""
+
+    def __init__(self, ctx, A, B, s, gemm_dtype, tube="th"):
+        self.ctx = ctx
+        self.h = dk.dctk_op_create(ctx, dk.TUBES[tube], gemm_dtype, to_gpu(A, F64), s,
+                                   None if B is None else to_gpu(B, F64))
+        _OPS.append(self.h)
+        self.vt = VT[gemm_dtype]
+        self.oracle = Operator(A, B, tube)
+
+
+# ------------------------------------------------------------------ transforms
+
+@pytest.mark.parametrize("dtype", [dk.DCTK_F64, dk.DCTK_F32])
+@pytest.mark.parametrize("tb", ["th", "dct2"])
+@pytest.mark.parametrize("p,count", [(1, 37), (3, 4 * 1000 + 3), (8, 257), (31, 129), (64, 1024)])
+def test_tube_transforms(ctx, dtype, tb, p, count):
+    say("tube", dtype, tb, p, count)
+    rng = np.random.default_rng(p * 7 + count)
+    x = rng.standard_normal((p, count))
+    xt = to_gpu(x, VT[dtype])
+    L = otube.transform_matrix(p, tb)
+    Li = np.linalg.inv(L)
+    cases = [(dk.dctk_tube_fwd, 0, L), (dk.dctk_tube_fwd, 1, Li.T), (dk.dctk_tube_inv, 0, Li),
+             (dk.dctk_tube_inv, 1, L.T)]
+    for fn, adj, G in cases:
+        out = torch.empty_like(xt)
+        fn(ctx, dk.TUBES[tb], adj, xt, out)
+        ref = G @ x
+        assert rel(to_np(out), ref) <= TOL_PROD[dtype] * max(1.0, np.sqrt(p) / 4), (fn.__name__, adj)
+
+
+# ------------------------------------------------------------------ c-product
+
+PROD_SHAPES = [
+    (3, 32, 32, 32),      # colour, one tile
+    (3, 70, 45, 33),      # several tiles, ragged in every dimension
+    (8, 64, 64, 64),
+    (31, 17, 23, 5),
+    (1, 100, 80, 7),
+    (2, 129, 3, 65),
+]
+
+
+@pytest.mark.parametrize("gdt", [dk.DCTK_F64, dk.DCTK_F32])
+@pytest.mark.parametrize("two_sided", [False, True])
+@pytest.mark.parametrize("shape", PROD_SHAPES)
+def test_cprod_and_adjoint(ctx, gdt, two_sided, shape):
+    p, n1, n2, s = shape
+    say("cprod", gdt, two_sided, shape)
+    w = W.tiny_random(sum(shape), p, n1, n2, s, two_sided)
+    op = Op(ctx, w["A"], w["B"], s, gdt)
+    X = to_gpu(w["X"], op.vt)
+    Y = torch.empty((p, n1, s), dtype=op.vt, device="cuda:0")
+    dk.dctk_cprod(ctx, op.h, 1.0, X, 0.0, Y)
+    assert rel(to_np(Y), op.oracle.apply(w["X"])) <= TOL_PROD[gdt]
+    Yin = to_gpu(w["Y"], op.vt)
+    Z = torch.empty((p, n2, s), dtype=op.vt, device="cuda:0")
+    dk.dctk_cprod_T(ctx, op.h, 1.0, Yin, 0.0, Z)
+    assert rel(to_np(Z), op.oracle.adjoint(w["Y"])) <= TOL_PROD[gdt]
+
+
+@pytest.mark.parametrize("tb", ["th", "dct2"])
+def test_cprod_epilogue_and_tubes(ctx, tb):
+    say("epilogue", tb)
+    p, n1, n2, s = 5, 40, 36, 24
+    w = W.tiny_random(99, p, n1, n2, s, False)
+    op = Op(ctx, w["A"], None, s, dk.DCTK_F64, tb)
+    X = to_gpu(w["X"], F64)
+    Y0 = w["Y"]
+    Y = to_gpu(Y0, F64)
+    dk.dctk_cprod(ctx, op.h, -0.75, X, 1.5, Y)
+    assert rel(to_np(Y), -0.75 * op.oracle.apply(w["X"]) + 1.5 * Y0) <= 1e-10
+    # b = 0 never reads Y (NaN in Y must not leak)
+    Y.fill_(float("nan"))
+    dk.dctk_cprod(ctx, op.h, 2.0, X, 0.0, Y)
+    assert rel(to_np(Y), 2.0 * op.oracle.apply(w["X"])) <= 1e-10
+
+
+def test_cprod_matches_definition_on_gpu(ctx):
+    """The GPU product equals the literal Toeplitz-plus-Hankel Definition (brute force)."""
+    from oracle.cprod import cprod_definition
+    w = W.tiny_random(5, 4, 6, 5, 3, False)
+    op = Op(ctx, w["A"], None, 3, dk.DCTK_F64)
+    Y = torch.empty((4, 6, 3), dtype=F64, device="cuda:0")
+    dk.dctk_cprod(ctx, op.h, 1.0, to_gpu(w["X"], F64), 0.0, Y)
+    assert rel(to_np(Y), cprod_definition(w["A"], w["X"])) <= 1e-10
+
+
+@pytest.mark.parametrize("gdt,u", [(dk.DCTK_BF16, 2.0 ** -8), (dk.DCTK_F16, 2.0 ** -11)])
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_low_precision_gemm_modes(ctx, gdt, u, two_sided):
+    p, n1, n2, s = 3, 96, 80, 48
+    say("lowp", gdt, two_sided)
+    w = W.tiny_random(11, p, n1, n2, s, two_sided)
+    op = Op(ctx, w["A"], w["B"], s, gdt)
+    Y = torch.empty((p, n1, s), dtype=F32, device="cuda:0")
+    dk.dctk_cprod(ctx, op.h, 1.0, to_gpu(w["X"], F32), 0.0, Y)
+    bound = 8.0 * u * np.sqrt(p) * (2.0 if two_sided else 1.0)
+    err = rel(to_np(Y), op.oracle.apply(w["X"]))
+    say("  rel err", err, "bound", bound)
+    assert err <= bound
+
+
+def test_ragged_and_degenerate_shapes(ctx):
+    """n = 1 slices and s = 1 (a single column) run and agree."""
+    for (p, n1, n2, s) in [(1, 1, 1, 1), (3, 1, 5, 1), (4, 5, 1, 2), (2, 3, 3, 1)]:
+        w = W.tiny_random(3, p, n1, n2, s, True)
+        op = Op(ctx, w["A"], w["B"], s, dk.DCTK_F64)
+        Y = torch.empty((p, n1, s), dtype=F64, device="cuda:0")
+        dk.dctk_cprod(ctx, op.h, 1.0, to_gpu(w["X"], F64), 0.0, Y)
+        assert rel(to_np(Y), op.oracle.apply(w["X"])) <= 1e-10
+
+
+def test_validation_errors(ctx):
+    w = W.tiny_random(1, 3, 8, 8, 4, False)
+    with pytest.raises(dk.DctkError) as e:
+        dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, 9, to_gpu(w["A"], F64), 4)
+    assert e.value.status == dk.DCTK_EDTYPE
+    op = Op(ctx, w["A"], None, 4, dk.DCTK_F64)
+    X = to_gpu(w["X"], F64)
+    with pytest.raises(dk.DctkError) as e:
+        dk.dctk_cprod(ctx, op.h, 1.0, X, 0.0, X)   # overlapping in/out
+    assert e.value.status == dk.DCTK_EINVAL
+    with pytest.raises(dk.DctkError) as e:
+        dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, 65)
+    assert e.value.status == dk.DCTK_EINVAL
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, 4)
+    with pytest.raises(dk.DctkError) as e:
+        dk.dctk_gkb_step(ctx, ws)                   # step before init
+    assert e.value.status == dk.DCTK_ESTATE
+    dk.dctk_krylov_destroy(ws)
+
+
+# ---------------------------------------------------------- Krylov processes
+
+def _krylov_problem(seed, p=3, n=24, s=10, two_sided=False):
+    rng = np.random.default_rng(seed)
+    A = 0.3 * rng.standard_normal((p, n, n)) / np.sqrt(n)
+    A[0] += np.eye(n)
+    B = None
+    if two_sided:
+        B = 0.3 * rng.standard_normal((p, s, s)) / np.sqrt(s)
+        B[0] += np.eye(s)
+    C = rng.standard_normal((p, n, s))
+    return A, B, C
+
+
+@pytest.mark.parametrize("two_sided", [False, True])
+@pytest.mark.parametrize("reorth", [dk.DCTK_REORTH_FULL, dk.DCTK_REORTH_V])
+def test_gkb_steps_match_oracle(ctx, two_sided, reorth):
+    say("gkb", two_sided, reorth)
+    A, B, C = _krylov_problem(3, two_sided=two_sided)
+    k = 12
+    op = Op(ctx, A, B, C.shape[2], dk.DCTK_F64)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    dk.dctk_gkb_init(ctx, ws, to_gpu(C, F64), reorth, 0.0)
+    for _ in range(k):
+        dk.dctk_gkb_step(ctx, ws)
+    r = dk.dctk_krylov_read(ctx, ws, k, dk.DCTK_KRYLOV_GKB)
+    g = krylov.gkb(op.oracle, C, k, "full" if reorth == dk.DCTK_REORTH_FULL else "v")
+    assert r["steps"] == k and r["status"] == 0
+    assert rel(r["alpha"][: k + 1], g.alpha[: k + 1]) <= 1e-9
+    assert rel(r["beta"][: k + 1], g.beta[: k + 1]) <= 1e-9
+    # bases: V_k and U_{k+1}
+    v = torch.empty(C.shape, dtype=F64, device="cuda:0")
+    dk.dctk_krylov_copy(ctx, ws, 1, k - 1, v)
+    assert rel(to_np(v), g.V[k - 1]) <= 1e-8
+    dk.dctk_krylov_copy(ctx, ws, 0, k, v)
+    assert rel(to_np(v), g.U[k]) <= 1e-8
+    dk.dctk_krylov_destroy(ws)
+
+
+@pytest.mark.parametrize("ortho", [dk.DCTK_ORTHO_MGS, dk.DCTK_ORTHO_CGS2])
+def test_arnoldi_steps_match_oracle(ctx, ortho):
+    say("arnoldi", ortho)
+    A, _, C = _krylov_problem(5)
+    m = 10
+    op = Op(ctx, A, None, C.shape[2], dk.DCTK_F64)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_ARNOLDI, m, ortho)
+    dk.dctk_arnoldi_init(ctx, ws, to_gpu(C, F64))
+    for _ in range(m):
+        dk.dctk_arnoldi_step(ctx, ws)
+    r = dk.dctk_krylov_read(ctx, ws, m, dk.DCTK_KRYLOV_ARNOLDI)
+    ar = krylov.Arnoldi(op.oracle, C, m, "mgs" if ortho == dk.DCTK_ORTHO_MGS else "cgs2")
+    for _ in range(m):
+        ar.step()
+    assert r["steps"] == m
+    assert abs(r["beta0"] - ar.beta) <= 1e-12 * ar.beta
+    assert rel(np.array(r["H"]), ar.H) <= 1e-9
+    dk.dctk_krylov_destroy(ws)
+
+
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_lsqr_iterate_matches_oracle(ctx, two_sided):
+    """lambda = 0: the Algorithm 6 iterate, with full reorthogonalisation on both sides."""
+    say("lsqr", two_sided)
+    A, B, C = _krylov_problem(7, two_sided=two_sided)
+    k = 15
+    op = Op(ctx, A, B, C.shape[2], dk.DCTK_F64)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    X = torch.empty(C.shape, dtype=F64, device="cuda:0")
+    info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(k, dk.DCTK_REORTH_FULL, 0, 0.0))
+    ref = krylov.dc_lsqr(op.oracle, C, k, reorth="full")
+    assert info.iters == k
+    assert rel(to_np(X), ref["X"]) <= 1e-9
+    assert abs(info.resnorm - ref["resnorm"]) <= 1e-9 * fro(C)
+    dk.dctk_krylov_destroy(ws)
+
+
+@pytest.mark.parametrize("lam", [0.05, 0.5])
+def test_gk_fixed_lambda_matches_oracle(ctx, lam):
+    A, _, C = _krylov_problem(9)
+    k = 12
+    op = Op(ctx, A, None, C.shape[2], dk.DCTK_F64)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    X = torch.empty(C.shape, dtype=F64, device="cuda:0")
+    dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(k, dk.DCTK_REORTH_FULL, 0, lam))
+    ref = krylov.dc_gk(op.oracle, C, k, lam=lam, reorth="full")
+    assert rel(to_np(X), ref["X"]) <= 1e-9
+    dk.dctk_krylov_destroy(ws)
+
+
+def _colour_small_problem():
+    w = W.colour_small()
+    orc = Operator(w["A"])
+    Ch = orc.apply(w["X_true"])
+    return w, w["N0"], Ch + w["nu"] * fro(Ch) / fro(w["N0"]) * w["N0"]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gk_gcv_matches_oracle(ctx, mode):
+    """GCV at k = 12 on the 32 x 32 x 3 colour problem (where the FP64 process is
+    stable: a 1e-16 perturbation of C moves alpha_j by < 1e-13): the GCV value at
+    the library's lambda equals the oracle's minimum; X equals the oracle's X at
+    the library's lambda."""
+    say("gcv", mode)
+    w, _, C = _colour_small_problem()
+    op = Op(ctx, w["A"], None, 32, dk.DCTK_F64)
+    k = 12
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    X = torch.empty(C.shape, dtype=F64, device="cuda:0")
+    info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(k, dk.DCTK_REORTH_FULL, mode, -1.0))
+    gmode = "rect" if mode == 0 else "paper"
+    ref = krylov.dc_gk(op.oracle, C, k, lam=None, gcv_mode=gmode, reorth="full")
+    g = ref["gkb"]
+    sig, Vt, gg = tikhonov.projected_svd(g.bidiagonal(k), g.beta[0])
+    f = tikhonov.gcv_rect if mode == 0 else tikhonov.gcv_paper
+    gmin = f(sig, gg, ref["lambda"])
+    assert f(sig, gg, info.lam) <= gmin * (1.0 + 1e-9)
+    assert abs(info.gcv - f(sig, gg, info.lam)) <= 1e-9 * abs(info.gcv)
+    at_lam = krylov.dc_gk(op.oracle, C, k, lam=info.lam, reorth="full")
+    assert rel(to_np(X), at_lam["X"]) <= 1e-9
+    dk.dctk_krylov_destroy(ws)
+
+
+def test_gk_gcv_20_steps_restoration_level(ctx):
+    """k = 20 on the same problem: past step ~15 rounding is amplified by the
+    process itself (oracle vs oracle with C perturbed by 1e-16: alpha moves 3%,
+    X moves 5e-6), so X is compared at 1e-4 and the restoration error at 1.001x."""
+    w, _, C = _colour_small_problem()
+    op = Op(ctx, w["A"], None, 32, dk.DCTK_F64)
+    k = 20
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    X = torch.empty(C.shape, dtype=F64, device="cuda:0")
+    dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(k, dk.DCTK_REORTH_FULL, 0, -1.0))
+    ref = krylov.dc_gk(op.oracle, C, k, lam=None, reorth="full")
+    Xg = to_np(X)
+    assert rel(Xg, ref["X"]) <= 1e-4
+    assert metrics.relative_error(w["X_true"], Xg) <= 1.001 * metrics.relative_error(w["X_true"], ref["X"])
+    dk.dctk_krylov_destroy(ws)
+
+
+@pytest.mark.parametrize("ortho", [dk.DCTK_ORTHO_MGS, dk.DCTK_ORTHO_CGS2])
+@pytest.mark.parametrize("lam", [0.0, 0.2, -1.0])
+def test_gmres_matches_oracle(ctx, ortho, lam):
+    say("gmres", ortho, lam)
+    A, _, C = _krylov_problem(11)
+    m, cycles = 8, 3
+    op = Op(ctx, A, None, C.shape[2], dk.DCTK_F64)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_ARNOLDI, m, ortho)
+    X0 = 0.1 * np.random.default_rng(1).standard_normal(C.shape)
+    X = to_gpu(X0, F64)
+    info = dk.dctk_gmres_tik_solve(ctx, ws, to_gpu(C, F64), X, cycles, dk.make_opts(m, 0, 0, lam))
+    ref = krylov.dc_gmres(op.oracle, C, X0, m, cycles, lam=None if lam < 0 else lam,
+                          ortho="mgs" if ortho == dk.DCTK_ORTHO_MGS else "cgs2")
+    assert info.cycles == cycles
+    tol = 1e-9 if lam >= 0 else 1e-6   # GCV: lambda agrees to the minimiser's accuracy
+    assert rel(to_np(X), ref["X"]) <= tol
+    assert abs(info.resnorm - ref["resnorm"]) <= 1e-6 * ref["resnorm"]
+    dk.dctk_krylov_destroy(ws)
+
+
+def test_breakdown_identity_operator(ctx):
+    """A = e_1 (x) I: breakdown after one step, exact recovery (X = C)."""
+    p, n, s = 3, 16, 8
+    A = np.zeros((p, n, n))
+    A[0] = np.eye(n)
+    C = np.random.default_rng(2).standard_normal((p, n, s))
+    op = Op(ctx, A, None, s, dk.DCTK_F64)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, 5)
+    X = torch.empty(C.shape, dtype=F64, device="cuda:0")
+    info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(5, 0, 0, 0.0))
+    assert info.status == dk.DCTK_BREAKDOWN and info.iters == 1
+    assert rel(to_np(X), C) <= 1e-13
+    # GK with GCV on the breakdown also recovers C
+    info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(5, 0, 0, 1e-12))
+    assert rel(to_np(X), C) <= 1e-10
+    dk.dctk_krylov_destroy(ws)
+    wa = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_ARNOLDI, 4)
+    X.zero_()
+    info = dk.dctk_gmres_tik_solve(ctx, wa, to_gpu(C, F64), X, 2, dk.make_opts(4, 0, 0, 0.0))
+    assert info.status == dk.DCTK_BREAKDOWN
+    assert rel(to_np(X), C) <= 1e-13
+    dk.dctk_krylov_destroy(wa)
+
+
+def test_zero_rhs(ctx):
+    A, _, C = _krylov_problem(13)
+    op = Op(ctx, A, None, C.shape[2], dk.DCTK_F32)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, 4)
+    X = torch.full(C.shape, 7.0, dtype=F32, device="cuda:0")
+    info = dk.dctk_lsqr_tik_solve(ctx, ws, torch.zeros(C.shape, dtype=F32, device="cuda:0"), X,
+                                  dk.make_opts(4, 0, 0, -1.0))
+    assert info.status == dk.DCTK_BREAKDOWN and info.iters == 0
+    assert float(X.abs().max()) == 0.0
+    dk.dctk_krylov_destroy(ws)
+
+
+# ---------------------------------------------------------- workload sizes
+
+@pytest.mark.parametrize("gdt", [dk.DCTK_F32, dk.DCTK_BF16])
+def test_colour_256_restoration(ctx, gdt):
+    """The benchmarked solve (256 x 256 x 3, 40 GKB steps, GCV): restoration error
+    within 1.05x of the FP64 oracle's on the same input; c-product parity at size."""
+    say("colour256", gdt)
+    w = W.colour_256()
+    orc = Operator(w["A"])
+    Ch = orc.apply(w["X_true"])
+    C = Ch + w["nu"] * fro(Ch) / fro(w["N0"]) * w["N0"]
+    k = w["iters"]
+    ref = krylov.dc_gk(orc, C, k, lam=None, gcv_mode="rect", reorth="none")
+    e_ref = metrics.relative_error(w["X_true"], ref["X"])
+    op = Op(ctx, w["A"], None, 256, gdt)
+    # product parity at full size
+    Y = torch.empty(C.shape, dtype=F32, device="cuda:0")
+    dk.dctk_cprod(ctx, op.h, 1.0, to_gpu(w["X_true"], F32), 0.0, Y)
+    tol = 1e-5 if gdt == dk.DCTK_F32 else 8.0 * 2.0 ** -8 * np.sqrt(3)
+    assert rel(to_np(Y), Ch) <= tol
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    X = torch.empty(C.shape, dtype=F32, device="cuda:0")
+    info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F32), X, dk.make_opts(k, 0, 0, -1.0))
+    e = metrics.relative_error(w["X_true"], to_np(X))
+    say("  relerr gpu", e, "oracle", e_ref, "lambda", info.lam, ref["lambda"])
+    assert info.iters == k
+    assert e <= 1.05 * e_ref
+    dk.dctk_krylov_destroy(ws)
