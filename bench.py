@@ -111,6 +111,7 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
     # restoration error of the benchmarked solve
+    kr = dk.dctk_krylov_read(ctx, ws, k, dk.DCTK_KRYLOV_GKB)
     Xn = X.double().cpu().numpy()
     err_gpu = float(np.linalg.norm((Xn - w["X_true"]).ravel()) / np.linalg.norm(w["X_true"].ravel()))
 
@@ -179,7 +180,8 @@ def main():
         "cpu_baseline": cpu,
         "restoration": {"relerr_gpu": err_gpu, "relerr_oracle_fp64": err_oracle,
                         "ratio": (err_gpu / err_oracle) if err_oracle else None, "gate_1_05": gate_ok,
-                        "lambda_gpu": info.lam, "lambda_oracle": lam_oracle, "iters": info.iters},
+                        "lambda_gpu": info.lam, "lambda_oracle": lam_oracle, "iters": info.iters,
+                        "jacobi_sweeps": kr["sweeps"]},
         "cprod": {"us": cprod_us, "GB_per_s": gb / (cprod_us * 1e-6),
                   "hbm_frac": gb / (cprod_us * 1e-6) / HBM_PEAK_GBS,
                   "mfma_frac": flops / (cprod_us * 1e-6) / 1e12 / peak},

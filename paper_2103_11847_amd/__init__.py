@@ -276,17 +276,19 @@ def dctk_arnoldi_step(ctx, ws):
 
 def dctk_krylov_read(ctx, ws, k_max, kind):
     """Returns dict(alpha, beta | H, beta0, steps, status, converged)."""
-    info = (ctypes.c_int * 4)()
+    info = (ctypes.c_int * 6)()
     if kind == DCTK_KRYLOV_GKB:
         a = (ctypes.c_double * (k_max + 1))()
         b = (ctypes.c_double * (k_max + 1))()
         _check(lib().dctk_krylov_read(ctx, ws, a, b, info), "dctk_krylov_read")
-        return {"alpha": list(a), "beta": list(b), "steps": info[0], "status": info[1], "converged": info[2]}
+        return {"alpha": list(a), "beta": list(b), "steps": info[0], "status": info[1], "converged": info[2],
+                "sweeps": info[4]}
     a = (ctypes.c_double * 1)()
     H = (ctypes.c_double * ((k_max + 1) * k_max))()
     _check(lib().dctk_krylov_read(ctx, ws, a, H, info), "dctk_krylov_read")
     Hm = [[H[i * k_max + j] for j in range(k_max)] for i in range(k_max + 1)]
-    return {"H": Hm, "beta0": a[0], "steps": info[0], "status": info[1], "converged": info[2]}
+    return {"H": Hm, "beta0": a[0], "steps": info[0], "status": info[1], "converged": info[2],
+            "sweeps": info[4], "cycles": info[5]}
 
 
 def dctk_krylov_basis(ws, which, j):

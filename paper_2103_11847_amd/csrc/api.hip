@@ -93,15 +93,10 @@ int dctk_create(dctk_ctx* out, int device, void* hip_stream) {
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->red_partials, sizeof(double) * kRedBlocks * kRedVals);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->red_tickets, sizeof(unsigned) * kTickets);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->red_out, sizeof(double) * kRedVals);
-  if (e == hipSuccess) e = hipMemset(c->red_tickets, 0, sizeof(unsigned) * kTickets);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     int st = hip_fail(c, e);
     if (c->red_partials) (void)hipFree(c->red_partials);
-    if (c->red_tickets) (void)hipFree(c->red_tickets);
-    if (c->red_out) (void)hipFree(c->red_out);
     delete c;
     return st;
   }
@@ -115,8 +110,6 @@ int dctk_destroy(dctk_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(ctx->red_partials);
-  (void)hipFree(ctx->red_tickets);
-  (void)hipFree(ctx->red_out);
   delete ctx;
   return DCTK_OK;
 }
@@ -191,9 +184,13 @@ static int tube_common(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, 
   DCTK_HIP(ctx, hipMalloc(&dG, gbytes));
   hipError_t e = hipMemcpyAsync(dG, dtype == DCTK_F64 ? (const void*)G.data() : (const void*)Gf.data(), gbytes,
                                 hipMemcpyHostToDevice, ctx->stream);
+  Ctl plain{};
+  plain.kind = CTL_PLAIN;
+  plain.a = 1.0;
+  plain.s = 1.0;
   if (e == hipSuccess)
-    e = launch_tube(ctx->stream, dtype, dtype, p, count, in, out, (const double*)dG, (const float*)dG, 1.0, 0.0,
-                    nullptr, Gate{nullptr, 0, 0});
+    e = launch_tube(ctx->stream, dtype, dtype, p, count, in, out, (const double*)dG, (const float*)dG, nullptr,
+                    nullptr, plain, false, true, nullptr);
   // the host copies of G must outlive the async copy; the device copy is freed after the work
   hipError_t e3 = hipStreamSynchronize(ctx->stream);
   hipError_t e2 = hipFree(dG);
@@ -260,19 +257,24 @@ int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1
   // A~ = A x_3 L and B~ = B x_3 L in FP64, then cast to the GEMM type
   const int64_t tmpn = (n1 * n2 > s * s || !op->two_sided) ? n1 * n2 : s * s;
   if (gemm_dtype != DCTK_F64) DCTK_TRY(hipMalloc((void**)&tmp, sizeof(double) * (size_t)(p * tmpn)));
-  Gate none{nullptr, 0, 0};
+  Ctl none{};
+  none.kind = CTL_PLAIN;
+  none.a = 1.0;
+  none.s = 1.0;
+#define DCTK_TUBE_F64(SRC, DST, CNT) \
+  launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, (CNT), (SRC), (DST), op->Gd, op->Gf, nullptr, nullptr, none, false, true, nullptr)
   if (gemm_dtype == DCTK_F64) {
-    DCTK_TRY(launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, n1 * n2, A, op->Ah, op->Gd, op->Gf, 1.0, 0.0, nullptr, none));
-    if (op->two_sided)
-      DCTK_TRY(launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, s * s, B, op->Bh, op->Gd, op->Gf, 1.0, 0.0, nullptr, none));
+    DCTK_TRY(DCTK_TUBE_F64(A, op->Ah, n1 * n2));
+    if (op->two_sided) DCTK_TRY(DCTK_TUBE_F64(B, op->Bh, s * s));
   } else {
-    DCTK_TRY(launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, n1 * n2, A, tmp, op->Gd, op->Gf, 1.0, 0.0, nullptr, none));
+    DCTK_TRY(DCTK_TUBE_F64(A, tmp, n1 * n2));
     DCTK_TRY(launch_cast(ctx, p * n1 * n2, tmp, gemm_dtype, op->Ah));
     if (op->two_sided) {
-      DCTK_TRY(launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, s * s, B, tmp, op->Gd, op->Gf, 1.0, 0.0, nullptr, none));
+      DCTK_TRY(DCTK_TUBE_F64(B, tmp, s * s));
       DCTK_TRY(launch_cast(ctx, p * s * s, tmp, gemm_dtype, op->Bh));
     }
   }
+#undef DCTK_TUBE_F64
   DCTK_TRY(hipStreamSynchronize(ctx->stream));
 #undef DCTK_TRY
   if (tmp) (void)hipFree(tmp);
@@ -309,7 +311,12 @@ static int cprod_common(dctk_ctx ctx, dctk_op op, int adjoint, double a, const v
   const size_t nout = (size_t)(op->p * (adjoint ? op->n2 : op->n1) * op->s) * ve;
   if (ranges_overlap(in, nin, out, nout)) return DCTK_EINVAL;
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
-  DCTK_HIP(ctx, apply_op(op, ctx->stream, adjoint, a, in, b, out, out, Gate{nullptr, 0, 0}));
+  Ctl c{};
+  c.kind = CTL_PLAIN;
+  c.a = a;
+  c.b = b;
+  c.s = 1.0;
+  DCTK_HIP(ctx, apply_op(op, ctx->stream, adjoint, in, out, b != 0.0 ? out : nullptr, nullptr, c, nullptr));
   return DCTK_OK;
 }
 
@@ -344,14 +351,17 @@ int dctk_krylov_create(dctk_ctx ctx, dctk_op op, int kind, int k_max, int ortho,
   if (e == hipSuccess && kind == DCTK_KRYLOV_GKB) e = hipMalloc(&ws->V, ws->vbytes * nslots);
   if (e == hipSuccess) e = hipMalloc(&ws->X, ws->vbytes);
   if (e == hipSuccess) e = hipMalloc(&ws->W, ws->vbytes);
-  if (e == hipSuccess) e = hipMalloc(&ws->T, ws->vbytes);
+  if (e == hipSuccess) e = hipMalloc(&ws->T, 2 * ws->vbytes);
   if (e == hipSuccess) e = hipMalloc(&ws->R, ws->vbytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->partA, sizeof(double) * kRedBlocks);
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->partB, sizeof(double) * kRedBlocks);
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->partM, sizeof(double) * kRedBlocks * kRedVals);
   if (e == hipSuccess) e = hipMalloc((void**)&ws->st, sizeof(KState));
   if (e == hipSuccess) e = hipMemset(ws->st, 0, sizeof(KState));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     int st = hip_fail(ctx, e);
-    void* ptrs[] = {ws->U, ws->V, ws->X, ws->W, ws->T, ws->R, ws->st};
+    void* ptrs[] = {ws->U, ws->V, ws->X, ws->W, ws->T, ws->R, ws->partA, ws->partB, ws->partM, ws->st};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
     delete ws;
@@ -365,7 +375,7 @@ int dctk_krylov_destroy(dctk_krylov ws) {
   if (!ws) return DCTK_EINVAL;
   (void)hipSetDevice(ws->op->ctx->device);
   (void)hipStreamSynchronize(ws->op->ctx->stream);
-  void* ptrs[] = {ws->U, ws->V, ws->X, ws->W, ws->T, ws->R, ws->st};
+  void* ptrs[] = {ws->U, ws->V, ws->X, ws->W, ws->T, ws->R, ws->partA, ws->partB, ws->partM, ws->st};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete ws;
@@ -378,7 +388,39 @@ namespace dctk {
 
 static inline char* slot(void* base, const dctk_krylov ws, int i) { return (char*)base + (size_t)i * ws->vbytes; }
 
-// Algorithm 4 step 2 + Algorithm 6 step 2, writing the LSQR iterate into X.
+static Ctl make_ctl(int kind, int j, KState* st, const double* part_in, int npart_in, double* part_out) {
+  Ctl c{};
+  c.kind = kind;
+  c.j = j;
+  c.st = st;
+  c.part_in = part_in;
+  c.npart_in = npart_in;
+  c.part_out = part_out;
+  c.a = 1.0;
+  c.s = 1.0;
+  return c;
+}
+
+// Classical Gram-Schmidt applied twice: w -= B (B^T w), with B the first nb slots of `basis`.
+// When hcol is given the coefficients are also added to it (Arnoldi column).
+static hipError_t cgs2(dctk_ctx ctx, dctk_krylov ws, void* basis, int nb, void* w, int64_t n, Gate g,
+                       double* hcol) {
+  hipError_t e;
+  KState* st = ws->st;
+  for (int pass = 0; pass < 2; ++pass) {
+    int nbk = 0;
+    if ((e = launch_multidot(ctx, ws->op->vec_dtype, n, basis, ws->nvec, nb, w, ws->partM, &nbk, g)) != hipSuccess)
+      return e;
+    if ((e = launch_coef_finalize(ctx, ws->partM, nbk, nb, st->coef, hcol, kMaxK, g)) != hipSuccess) return e;
+    if ((e = launch_subtract(ctx, ws->op->vec_dtype, n, w, basis, ws->nvec, nb, st->coef, g)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+// Algorithm 4 step 2 and Algorithm 6 step 2, writing the LSQR iterate into X:
+//   partials of ||C||^2;  [beta_1, U_1 = C/beta_1, V~ = M*(U_1), partials of ||V~||^2];
+//   [alpha_1, V_1 = V~/alpha_1, W_1 = V_1, X_0 = 0]
 static hipError_t gkb_init_impl(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, double tol) {
   dctk_op op = ws->op;
   KState* st = ws->st;
@@ -386,38 +428,20 @@ static hipError_t gkb_init_impl(dctk_ctx ctx, dctk_krylov ws, const void* C, voi
   const int64_t nU = op->p * op->n1 * op->s, nV = op->p * op->n2 * op->s;
   hipError_t e;
   if ((e = launch_state_reset(ctx, st, 1, tol)) != hipSuccess) return e;
-  // beta_1 = ||C||
-  if ((e = launch_axpy_red(ctx, vdt, nU, nullptr, C, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_GKB_BETA1, nullptr, st,
-                           0, Gate{nullptr, 0, 0})) != hipSuccess)
+  int npA = 0, npB = 0;
+  if ((e = launch_sumsq(ctx, vdt, nU, C, nullptr, ws->partA, &npA, Gate{nullptr, 0, 0})) != hipSuccess) return e;
+  const Ctl c = make_ctl(CTL_GKB_INIT, 0, st, ws->partA, npA, ws->partB);
+  if ((e = apply_op(op, ctx->stream, 1, C, slot(ws->V, ws, 0), nullptr, slot(ws->U, ws, 0), c, &npB)) != hipSuccess)
     return e;
-  const Gate g0{st, 0, PH_AFTER_U};
-  // U_1 = C / beta_1
-  if ((e = launch_scale(ctx, vdt, nU, slot(ws->U, ws, 0), C, &st->beta[0], g0)) != hipSuccess) return e;
-  // V~ = M*(U_1) into V slot 0; alpha_1 = ||V~||
-  if ((e = apply_op(op, ctx->stream, 1, 1.0, slot(ws->U, ws, 0), 0.0, nullptr, slot(ws->V, ws, 0), g0)) != hipSuccess)
-    return e;
-  if ((e = launch_axpy_red(ctx, vdt, nV, nullptr, slot(ws->V, ws, 0), nullptr, nullptr, 0.0, 0.0, nullptr,
-                           ACT_GKB_ALPHA1, nullptr, st, 0, g0)) != hipSuccess)
-    return e;
-  // V_1 = V~/alpha_1, W_1 = V_1, X_0 = 0
-  return launch_lsqr_start(ctx, vdt, nV, X, ws->W, slot(ws->V, ws, 0), st);
+  return launch_gkb_start(ctx, vdt, nV, X, ws->W, slot(ws->V, ws, 0), ws->partB, npB, st);
 }
 
-// Classical Gram-Schmidt applied twice of w against nb basis slots.
-static hipError_t cgs2(dctk_ctx ctx, dctk_krylov ws, void* basis, int nb, void* w, int64_t n, Gate g) {
-  hipError_t e;
-  KState* st = ws->st;
-  for (int pass = 0; pass < 2; ++pass) {
-    if ((e = launch_multidot(ctx, ws->op->vec_dtype, n, basis, ws->nvec, nb, w, st->coef, 1, 0, nullptr, g)) !=
-        hipSuccess)
-      return e;
-    if ((e = launch_subtract(ctx, ws->op->vec_dtype, n, w, basis, ws->nvec, nb, st->coef, 1, g)) != hipSuccess)
-      return e;
-  }
-  return hipSuccess;
-}
-
-// Algorithm 4 step 3 (a)-(f) and Algorithm 6 steps 3(c)-(g), step j (1-based).
+// Algorithm 4 step 3 (a)-(f) with the LSQR update of Algorithm 6 (c)-(g), step j:
+//   K1: T = M(V_j) - alpha_j U_j, partials of ||T||^2             (one product)
+//   K2: beta_{j+1}; U_{j+1} = T/beta_{j+1}; V~ = M*(U_{j+1}) - beta_{j+1} V_j,
+//       partials of ||V~||^2                                         (one product)
+//   K3: alpha_{j+1}; rotation; V_{j+1} = V~/alpha_{j+1}; X and W updates
+// With reorthogonalisation, CGS2 passes run on T (before K2) and on V~ (before K3).
 static hipError_t gkb_step_impl(dctk_ctx ctx, dctk_krylov ws, int j, void* X) {
   dctk_op op = ws->op;
   KState* st = ws->st;
@@ -427,100 +451,77 @@ static hipError_t gkb_step_impl(dctk_ctx ctx, dctk_krylov ws, int j, void* X) {
   void* Un = slot(ws->U, ws, j);
   void* Vj = slot(ws->V, ws, j - 1);
   void* Vn = slot(ws->V, ws, j);
-  const Gate ga{st, j, PH_ALWAYS};
-  const Gate gu{st, j, PH_AFTER_U};
+  void* T = ws->T;
   hipError_t e;
-  // (a) U~ = M(V_j) - alpha_j U_j   (b) beta_{j+1} = ||U~||
-  if ((e = apply_op(op, ctx->stream, 0, 1.0, Vj, 0.0, nullptr, Un, ga)) != hipSuccess) return e;
-  if (ws->reorth == DCTK_REORTH_FULL) {
-    if ((e = launch_axpy_red(ctx, vdt, nU, Un, Un, Uj, &st->alpha[j - 1], -1.0, 0.0, nullptr, -1, nullptr, st, j,
-                             ga)) != hipSuccess)
-      return e;
-    if ((e = cgs2(ctx, ws, ws->U, j, Un, nU, ga)) != hipSuccess) return e;
-    if ((e = launch_axpy_red(ctx, vdt, nU, nullptr, Un, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_GKB_BETA, nullptr, st,
-                             j, ga)) != hipSuccess)
-      return e;
-  } else {
-    if ((e = launch_axpy_red(ctx, vdt, nU, Un, Un, Uj, &st->alpha[j - 1], -1.0, 0.0, nullptr, ACT_GKB_BETA, nullptr,
-                             st, j, ga)) != hipSuccess)
-      return e;
+  int npA = 0, npB = 0;
+  const bool ru = ws->reorth == DCTK_REORTH_FULL;
+  const bool rv = ws->reorth != DCTK_REORTH_NONE;
+  const Ctl c1 = make_ctl(CTL_GKB_FWD, j, st, nullptr, 0, ru ? nullptr : ws->partA);
+  if ((e = apply_op(op, ctx->stream, 0, Vj, T, Uj, nullptr, c1, &npA)) != hipSuccess) return e;
+  if (ru) {
+    const Gate g{st, j, 0};
+    if ((e = cgs2(ctx, ws, ws->U, j, T, nU, g, nullptr)) != hipSuccess) return e;
+    if ((e = launch_sumsq(ctx, vdt, nU, T, nullptr, ws->partA, &npA, g)) != hipSuccess) return e;
   }
-  // (c) U_{j+1} = U~ / beta_{j+1}
-  if ((e = launch_scale(ctx, vdt, nU, Un, Un, &st->beta[j], gu)) != hipSuccess) return e;
-  // (d) V~ = M*(U_{j+1}) - beta_{j+1} V_j   (e) alpha_{j+1} = ||V~||
-  if ((e = apply_op(op, ctx->stream, 1, 1.0, Un, 0.0, nullptr, Vn, gu)) != hipSuccess) return e;
-  if (ws->reorth != DCTK_REORTH_NONE) {
-    if ((e = launch_axpy_red(ctx, vdt, nV, Vn, Vn, Vj, &st->beta[j], -1.0, 0.0, nullptr, -1, nullptr, st, j, gu)) !=
-        hipSuccess)
-      return e;
-    if ((e = cgs2(ctx, ws, ws->V, j, Vn, nV, gu)) != hipSuccess) return e;
-    if ((e = launch_axpy_red(ctx, vdt, nV, nullptr, Vn, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_GKB_ALPHA, nullptr,
-                             st, j, gu)) != hipSuccess)
-      return e;
-  } else {
-    if ((e = launch_axpy_red(ctx, vdt, nV, Vn, Vn, Vj, &st->beta[j], -1.0, 0.0, nullptr, ACT_GKB_ALPHA, nullptr, st, j,
-                             gu)) != hipSuccess)
-      return e;
+  const Ctl c2 = make_ctl(CTL_GKB_ADJ, j, st, ws->partA, npA, rv ? nullptr : ws->partB);
+  if ((e = apply_op(op, ctx->stream, 1, T, Vn, Vj, Un, c2, &npB)) != hipSuccess) return e;
+  if (rv) {
+    const Gate g{st, j, 1};
+    if ((e = cgs2(ctx, ws, ws->V, j, Vn, nV, g, nullptr)) != hipSuccess) return e;
+    if ((e = launch_sumsq(ctx, vdt, nV, Vn, nullptr, ws->partB, &npB, g)) != hipSuccess) return e;
   }
-  // LSQR rotation, then (f) V_{j+1} = V~/alpha_{j+1} with the X and W updates
-  if ((e = launch_lsqr_scalars(ctx, st, j)) != hipSuccess) return e;
-  return launch_lsqr_update(ctx, vdt, nV, X, ws->W, Vn, st, j);
+  return launch_gkb_update(ctx, vdt, nV, X, ws->W, Vn, ws->partB, npB, st, j);
 }
 
-// Algorithm 2 step 2 on R: beta = ||R||, V_1 = R / beta.
-static hipError_t arnoldi_start_impl(dctk_ctx ctx, dctk_krylov ws, const void* R) {
+// Algorithm 2 step 2 on R with the partials of ||R||^2 already in `part`: V_1 = R / ||R||.
+static hipError_t arnoldi_start_impl(dctk_ctx ctx, dctk_krylov ws, const void* R, const double* part, int npart) {
   dctk_op op = ws->op;
-  KState* st = ws->st;
   const int64_t n = op->p * op->n1 * op->s;
-  hipError_t e;
-  const Gate g0{st, 0, PH_ALWAYS};
-  if ((e = launch_axpy_red(ctx, op->vec_dtype, n, nullptr, R, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_ARN_BETA,
-                           nullptr, st, 0, g0)) != hipSuccess)
-    return e;
-  return launch_scale(ctx, op->vec_dtype, n, slot(ws->U, ws, 0), R, &st->beta0, g0);
+  return launch_arn_start(ctx, op->vec_dtype, n, slot(ws->U, ws, 0), R, part, npart, ws->st);
 }
 
-// Algorithm 2 step 3 (a)-(e), step j (1-based): W = M(V_j) into slot j.
+// Algorithm 2 step 3 (a)-(e), step j: W = M(V_j) (with V_j = W_{j-1}/h_{j,j-1}
+// formed and recorded by the same kernel), the Gram-Schmidt passes, and the
+// partials of ||W||^2 in partA (h_{j+1,j} is recorded by the next product or
+// by launch_arn_finish).
 static hipError_t arnoldi_step_impl(dctk_ctx ctx, dctk_krylov ws, int j) {
   dctk_op op = ws->op;
   KState* st = ws->st;
   const int vdt = op->vec_dtype;
   const int64_t n = op->p * op->n1 * op->s;
-  void* W = slot(ws->U, ws, j);
-  const Gate ga{st, j, PH_ALWAYS};
-  const Gate gu{st, j, PH_AFTER_U};
+  void* Win = (j == 1) ? slot(ws->U, ws, 0) : slot(ws->T, ws, (j - 1) & 1);
+  void* xnorm = (j == 1) ? nullptr : slot(ws->U, ws, j - 1);
+  void* W = slot(ws->T, ws, j & 1);
   hipError_t e;
-  if ((e = apply_op(op, ctx->stream, 0, 1.0, slot(ws->U, ws, j - 1), 0.0, nullptr, W, ga)) != hipSuccess) return e;
+  const Ctl c = make_ctl(CTL_ARN_FWD, j, st, ws->partA, ws->last_npart, nullptr);
+  if ((e = apply_op(op, ctx->stream, 0, Win, W, nullptr, xnorm, c, nullptr)) != hipSuccess) return e;
   double* Hcol = &st->H[j - 1];  // H[i][j-1] at Hcol[i * kMaxK]
+  int np = 0;
   if (ws->ortho == DCTK_ORTHO_MGS) {
-    // h_{i,j} = <V_i, W>; W = W - h_{i,j} V_i, fused as: subtract the previous term, then dot with V_i
-    for (int i = 0; i < j; ++i) {
-      const void* prev = i > 0 ? slot(ws->U, ws, i - 1) : nullptr;
-      if ((e = launch_axpy_red(ctx, vdt, n, prev ? W : nullptr, W, prev, prev ? &Hcol[(i - 1) * kMaxK] : nullptr,
-                               -1.0, 0.0, slot(ws->U, ws, i), ACT_DOT_STORE, &Hcol[i * kMaxK], st, j, ga)) !=
-          hipSuccess)
-        return e;
+    // h_{i,j} = <V_i, W>; W -= h_{i,j} V_i, as: record and subtract the previous term, then dot with V_i
+    const double* pin = nullptr;
+    int npin = 0;
+    for (int i = 0; i <= j; ++i) {
+      double* pout = (i == j) ? ws->partA : ((i & 1) ? ws->partM : ws->partB);
+      const void* vprev = i > 0 ? slot(ws->U, ws, i - 1) : nullptr;
+      const void* vi = i < j ? slot(ws->U, ws, i) : nullptr;
+      double* hdst = i > 0 ? &Hcol[(i - 1) * kMaxK] : nullptr;
+      if ((e = launch_mgs(ctx, vdt, n, W, vprev, vi, pin, npin, hdst, pout, &np, st, j)) != hipSuccess) return e;
+      pin = pout;
+      npin = np;
     }
-    if ((e = launch_axpy_red(ctx, vdt, n, W, W, slot(ws->U, ws, j - 1), &Hcol[(j - 1) * kMaxK], -1.0, 0.0, nullptr,
-                             ACT_ARN_H, nullptr, st, j, ga)) != hipSuccess)
-      return e;
   } else {
-    for (int pass = 0; pass < 2; ++pass) {
-      if ((e = launch_multidot(ctx, vdt, n, ws->U, ws->nvec, j, W, Hcol, kMaxK, 1, st->coef, ga)) != hipSuccess)
-        return e;
-      if ((e = launch_subtract(ctx, vdt, n, W, ws->U, ws->nvec, j, st->coef, 1, ga)) != hipSuccess) return e;
-    }
-    if ((e = launch_axpy_red(ctx, vdt, n, nullptr, W, nullptr, nullptr, 0.0, 0.0, nullptr, ACT_ARN_H, nullptr, st, j,
-                             ga)) != hipSuccess)
-      return e;
+    const Gate g{st, j - 1, 1};
+    if ((e = cgs2(ctx, ws, ws->U, j, W, n, g, Hcol)) != hipSuccess) return e;
+    if ((e = launch_sumsq(ctx, vdt, n, W, nullptr, ws->partA, &np, g)) != hipSuccess) return e;
   }
-  // V_{j+1} = W / h_{j+1,j}
-  return launch_scale(ctx, vdt, n, W, W, &st->H[j * kMaxK + (j - 1)], gu);
+  ws->last_npart = np;
+  return hipSuccess;
 }
 
 struct HostState {
   int steps, stop_step, stop_kind, status, converged, cycles, halt, total_steps;
-  double scale, rhobar, phibar, cx, cw, tol, beta0, lambda, gcv, resnorm;
+  double tol, beta0, lambda, gcv, resnorm;
 };
 
 static int read_state(dctk_ctx ctx, dctk_krylov ws, HostState* hs) {
@@ -528,6 +529,14 @@ static int read_state(dctk_ctx ctx, dctk_krylov ws, HostState* hs) {
   DCTK_HIP(ctx, hipMemcpyAsync(hs, ws->st, sizeof(HostState), hipMemcpyDeviceToHost, ctx->stream));
   DCTK_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return DCTK_OK;
+}
+
+static double lsqr_resnorm(dctk_ctx ctx, dctk_krylov ws, int steps) {
+  double v = 0.0;
+  if (hipMemcpyAsync(&v, &ws->st->phibar[steps], sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+    return NAN;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return NAN;
+  return std::fabs(v);
 }
 
 }  // namespace dctk
@@ -572,7 +581,10 @@ int dctk_arnoldi_init(dctk_ctx ctx, dctk_krylov ws, const void* V) {
   if (!V) return DCTK_EINVAL;
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
   DCTK_HIP(ctx, launch_state_reset(ctx, ws->st, 1, 0.0));
-  DCTK_HIP(ctx, arnoldi_start_impl(ctx, ws, V));
+  int np = 0;
+  DCTK_HIP(ctx, launch_sumsq(ctx, ws->op->vec_dtype, ws->op->p * ws->op->n1 * ws->op->s, V, nullptr, ws->partB, &np,
+                             Gate{nullptr, 0, 0}));
+  DCTK_HIP(ctx, arnoldi_start_impl(ctx, ws, V, ws->partB, np));
   ws->host_steps = 0;
   ws->initialised = 1;
   return DCTK_OK;
@@ -585,6 +597,8 @@ int dctk_arnoldi_step(dctk_ctx ctx, dctk_krylov ws) {
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
   const int j = ws->host_steps + 1;
   DCTK_HIP(ctx, arnoldi_step_impl(ctx, ws, j));
+  // record h_{j+1,j} now (the next step's product records the same value again)
+  DCTK_HIP(ctx, launch_arn_finish(ctx, ws->partA, ws->last_npart, ws->st, j + 1));
   ws->host_steps = j;
   return DCTK_OK;
 }
@@ -615,6 +629,8 @@ int dctk_krylov_read(dctk_ctx ctx, dctk_krylov ws, double* alpha, double* beta_o
     info4[1] = h->status;
     info4[2] = h->converged;
     info4[3] = K;
+    info4[4] = (int)h->sweeps;
+    info4[5] = h->cycles;
   }
   delete h;
   return DCTK_OK;
@@ -686,7 +702,7 @@ int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, co
     info->converged = hs.converged;
     info->cycles = 0;
     info->lambda = tik ? hs.lambda : 0.0;
-    info->resnorm = std::fabs(hs.phibar);
+    info->resnorm = lsqr_resnorm(ctx, ws, hs.steps);
     info->gcv = (tik && opts->lambda < 0.0) ? hs.gcv : NAN;
   }
   return hs.status;
@@ -705,20 +721,30 @@ int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, i
   if (ranges_overlap(C, (size_t)n * ve, X, (size_t)n * ve)) return DCTK_EINVAL;
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
   KState* st = ws->st;
-  const Gate g0{st, 0, PH_ALWAYS};
+  const Gate g0{st, 0, 0};  // open unless the solve halted
   const int m = opts->k_max;
   DCTK_HIP(ctx, launch_state_reset(ctx, st, 1, opts->tol));
-  // R_0 = C - M(X_0)
-  DCTK_HIP(ctx, apply_op(op, ctx->stream, 0, -1.0, X, 1.0, C, ws->R, g0));
+  // R_0 = C - M(X_0) with the partials of ||R_0||^2
+  Ctl cr{};
+  cr.kind = CTL_PLAIN;
+  cr.a = -1.0;
+  cr.b = 1.0;
+  cr.s = 1.0;
+  cr.st = st;
+  cr.part_out = ws->partB;
+  double* partR = ws->partB;
+  int npR = 0;
+  // the residual partials live in partB only until the cycle start consumes them
+  DCTK_HIP(ctx, apply_op(op, ctx->stream, 0, X, ws->R, C, nullptr, cr, &npR));
   for (int c = 0; c < cycles; ++c) {
     DCTK_HIP(ctx, launch_state_reset(ctx, st, 0, 0.0));
-    DCTK_HIP(ctx, arnoldi_start_impl(ctx, ws, ws->R));
-    for (int j = 1; j <= m; ++j) DCTK_HIP(ctx, arnoldi_step_impl(ctx, ws, j));
+    DCTK_HIP(ctx, arnoldi_start_impl(ctx, ws, ws->R, partR, npR));
+    for (int j2 = 1; j2 <= m; ++j2) DCTK_HIP(ctx, arnoldi_step_impl(ctx, ws, j2));
+    DCTK_HIP(ctx, launch_arn_finish(ctx, ws->partA, ws->last_npart, st, m + 1));
     DCTK_HIP(ctx, launch_projected(ctx, st, 0, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda));
     DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, n, X, X, ws->U, ws->nvec, m, &st->steps, st->y, g0));
-    DCTK_HIP(ctx, apply_op(op, ctx->stream, 0, -1.0, X, 1.0, C, ws->R, g0));
-    DCTK_HIP(ctx, launch_axpy_red(ctx, op->vec_dtype, n, nullptr, ws->R, nullptr, nullptr, 0.0, 0.0, nullptr,
-                                  ACT_GMRES_RES, nullptr, st, 0, g0));
+    DCTK_HIP(ctx, apply_op(op, ctx->stream, 0, X, ws->R, C, nullptr, cr, &npR));
+    DCTK_HIP(ctx, launch_gmres_res(ctx, partR, npR, st));
   }
   ws->host_steps = 0;
   ws->initialised = 0;

@@ -1,0 +1,690 @@
+// The whole c-product of Algorithm 1 in one kernel, for one-sided operators
+// with n3 = p <= 8 (colour images, short tubes):
+//
+//   step 1  X~_k = sum_t Lin[k][t] (s X_t)      computed while the X tile is
+//           staged into LDS (each thread holds the p entries of its tubes);
+//   step 2  C~_k = op(A~_k) X~_k                 16x16 MFMA blocks, all p slices
+//           of an output tile in one workgroup, accumulated in registers;
+//   step 3  Y_t  = a sum_k Lout[t][k] C~_k + b src_t    applied to the
+//           accumulators (each lane holds the same (row, col) of every slice),
+//           with per-workgroup partial sums of Y^2 for the next Krylov norm.
+//
+// The forward transform of the input and the inverse transform of the output
+// never touch HBM, so one product reads A~, X (and src) once and writes Y once.
+// Small problems (fewer 32x32 tiles than CUs) use 16x16 tiles with the 4 waves
+// splitting the contraction (reduced through LDS) so every CU has work;
+// larger ones use 32x32 or 64x64 tiles with 2x2 waves.
+#include "mfma.h"
+
+namespace dctk {
+
+struct FusedArgs {
+  int p, M, N, K;          // output rows, columns, contraction length
+  int64_t lda, sA;         // A~ slice: row stride and slice stride
+  const void* A;
+  const void* X;           // p x K x N vector type
+  void* Y;                 // p x M x N vector type
+  const void* src;         // p x M x N or null
+  void* xnorm;             // p x K x N or null: receives s X
+  const void* Gin;         // p x p, vector type
+  const void* Gout;        // p x p, vector type
+  Ctl ctl;
+};
+
+// EXACT: p == PMAX (no slice guards); otherwise p <= PMAX at run time.
+template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA>
+__global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa) {
+  typedef Mfma<TI> MF;
+  typedef typename MF::acc_t acc_t;
+  typedef typename MF::frag_t frag_t;
+  constexpr int KSTEP = MF::KSTEP;
+  static_assert(BK % KSTEP == 0, "BK");
+  constexpr int BKT = BK * WK;                // contraction chunk staged per iteration
+  constexpr int PAD = 16 / (int)sizeof(TI);   // 16-byte row padding
+  constexpr int LD = BKT + PAD;
+  constexpr int WGM = (WK == 1) ? 2 : 1;      // waves along M / N
+  constexpr int WGN = (WK == 1) ? 2 : 1;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  static_assert(WK == 1 || WK == 4, "WK");
+  static_assert(FM >= 1 && FN >= 1, "tile");
+
+  __shared__ __attribute__((aligned(16))) TI As[PMAX * BM * LD];
+  __shared__ __attribute__((aligned(16))) TI Bs[PMAX * BN * LD];
+  __shared__ TV sGin[PMAX * PMAX], sGout[PMAX * PMAX];
+  __shared__ double sh[8];
+
+  double a_d, b_d, s_d;
+  if (!ctl_begin(fa.ctl, a_d, b_d, s_d, sh)) return;
+  const TV sc = (TV)s_d;
+
+  const int p = EXACT ? PMAX : fa.p;
+  const int M = fa.M, N = fa.N, K = fa.K;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < p * p; i += 256) {
+    sGin[i] = ((const TV*)fa.Gin)[i];
+    sGout[i] = ((const TV*)fa.Gout)[i];
+  }
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const TI* A = (const TI*)fa.A;
+  const TV* X = (const TV*)fa.X;
+  TV* xnorm = (blockIdx.y == 0) ? (TV*)fa.xnorm : nullptr;
+
+  const int wk = (WK == 1) ? 0 : wave;
+  const int wmn = (WK == 1) ? wave : 0;
+  const int wm = wmn >> 1, wn = wmn & 1;
+  const int lr = lane & 15;
+  const int lk = (lane >> 4) * MF::EPL;
+
+  frag_t acc[PMAX][FM][FN];
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[k][i][j][r] = (acc_t)0;
+
+  // Staging: every thread owns A_PER elements of the A~ tiles and X_PER tube
+  // positions of the X tile per chunk; all global loads of the next chunk are
+  // issued into registers before the current chunk is multiplied.
+  constexpr int A_TOT = PMAX * BM * BKT, X_TOT = BKT * BN;
+  constexpr int A_PER = (A_TOT + 255) / 256, X_PER = (X_TOT + 255) / 256;
+  TI ra[A_PER];
+  TV rx[X_PER][PMAX];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u) {
+      const int idx = tid + u * 256;
+      const int k = idx / (BM * BKT);
+      const int rem = idx - k * (BM * BKT);
+      int r, kk;
+      if (!TA) { r = rem / BKT; kk = rem - r * BKT; }
+      else { kk = rem / BM; r = rem - kk * BM; }
+      const int gm = m0 + r, gk = k0 + kk;
+      // clamped address + select: every load is issued, none is out of bounds
+      const bool ok = (A_TOT % 256 == 0 || idx < A_TOT) && k < p && gm < M && gk < K;
+      const int64_t off = ok ? (int64_t)k * fa.sA + (TA ? (int64_t)gk * fa.lda + gm : (int64_t)gm * fa.lda + gk) : 0;
+      const TI v = A[off];
+      ra[u] = ok ? v : (TI)0;
+    }
+#pragma unroll
+    for (int u = 0; u < X_PER; ++u) {
+      const int idx = tid + u * 256;
+      const int kk = idx / BN, n = idx - kk * BN;
+      const int gk = k0 + kk, gn = n0 + n;
+      const bool in = (X_TOT % 256 == 0 || idx < X_TOT) && gk < K && gn < N;
+#pragma unroll
+      for (int t = 0; t < PMAX; ++t) {
+        const bool ok = in && t < p;
+        const TV v = X[ok ? ((int64_t)t * K + gk) * N + gn : 0];
+        rx[u][t] = ok ? v : (TV)0;
+      }
+    }
+  };
+  auto store_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u) {
+      const int idx = tid + u * 256;
+      if (A_TOT % 256 == 0 || idx < A_TOT) {
+        const int k = idx / (BM * BKT);
+        const int rem = idx - k * (BM * BKT);
+        int r, kk;
+        if (!TA) { r = rem / BKT; kk = rem - r * BKT; }
+        else { kk = rem / BM; r = rem - kk * BM; }
+        As[(k * BM + r) * LD + kk] = ra[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < X_PER; ++u) {
+      const int idx = tid + u * 256;
+      if (X_TOT % 256 == 0 || idx < X_TOT) {
+        const int kk = idx / BN, n = idx - kk * BN;
+        const int gk = k0 + kk, gn = n0 + n;
+        TV xv[PMAX];
+#pragma unroll
+        for (int t = 0; t < PMAX; ++t) xv[t] = sc * rx[u][t];
+        if (xnorm != nullptr && gk < K && gn < N) {
+#pragma unroll
+          for (int t = 0; t < PMAX; ++t)
+            if (t < p) xnorm[((int64_t)t * K + gk) * N + gn] = xv[t];
+        }
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k) {
+          if (k < p) {
+            TV h = (TV)0;
+#pragma unroll
+            for (int t = 0; t < PMAX; ++t)
+              if (t < p) h += sGin[k * p + t] * xv[t];
+            Bs[(k * BN + n) * LD + kk] = cvt<TI, TV>(h);
+          }
+        }
+      }
+    }
+  };
+
+  load_chunk(0);
+  for (int k0 = 0; k0 < K; k0 += BKT) {
+    __syncthreads();
+    store_chunk(k0);
+    __syncthreads();
+    if (k0 + BKT < K) load_chunk(k0 + BKT);
+    const int kb = wk * BK, ke = (WK == 1) ? BKT : kb + BK;
+    for (int ks = kb; ks < ke; ks += KSTEP) {
+#pragma unroll
+      for (int k = 0; k < PMAX; ++k) {
+        if (k < p) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+              const TI* ap = &As[(k * BM + wm * WM + i * 16 + lr) * LD + ks + lk];
+              const TI* bp = &Bs[(k * BN + wn * WN + j * 16 + lr) * LD + ks + lk];
+              acc[k][i][j] = MF::mac(ap, bp, acc[k][i][j]);
+            }
+        }
+      }
+    }
+  }
+
+  // split contraction: sum the four waves' accumulators (wave 0 keeps the result)
+  if constexpr (WK == 4) {
+    constexpr int SLOT = 64 * 4;  // accumulators of one slice of one wave
+    acc_t* red = reinterpret_cast<acc_t*>(As);
+    constexpr int CAP = (int)((sizeof(TI) * PMAX * BM * LD) / (sizeof(acc_t) * 3 * SLOT));
+    constexpr int PER = CAP < 1 ? 1 : (CAP > PMAX ? PMAX : CAP);
+    static_assert(CAP >= 1, "LDS too small for the cross-wave reduction");
+#pragma unroll
+    for (int k0 = 0; k0 < PMAX; k0 += PER) {
+      __syncthreads();
+      if (wave > 0) {
+#pragma unroll
+        for (int kk = 0; kk < PER; ++kk) {
+          if (k0 + kk < PMAX) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[((wave - 1) * PER + kk) * SLOT + lane * 4 + r] = acc[k0 + kk][0][0][r];
+          }
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int kk = 0; kk < PER; ++kk) {
+          if (k0 + kk < PMAX) {
+#pragma unroll
+            for (int w = 0; w < 3; ++w)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[k0 + kk][0][0][r] += red[(w * PER + kk) * SLOT + lane * 4 + r];
+          }
+        }
+      }
+    }
+  }
+
+  // epilogue: inverse transform across slices, a/b/src, partial sums of squares
+  const TV a = (TV)a_d, b = (TV)b_d;
+  const TV* src = (const TV*)fa.src;
+  TV* Y = (TV*)fa.Y;
+  double sq = 0.0;
+  if (WK == 1 || wave == 0) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int col = n0 + wn * WN + j * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WM + i * 16 + (MF::ROWS_STRIDED ? (lane >> 4) + 4 * r : (lane >> 4) * 4 + r);
+          if (row < M && col < N) {
+#pragma unroll
+            for (int t = 0; t < PMAX; ++t) {
+              if (t >= p) break;
+              TV y = (TV)0;
+#pragma unroll
+              for (int k = 0; k < PMAX; ++k)
+                if (k < p) y += sGout[t * p + k] * (TV)acc[k][i][j][r];
+              const int64_t o = ((int64_t)t * M + row) * N + col;
+              TV v = a * y;
+              if (b != (TV)0) v += b * src[o];
+              Y[o] = v;
+              sq += (double)v * (double)v;
+            }
+          }
+        }
+      }
+  }
+  if (fa.ctl.part_out != nullptr) {
+    const double tot = block_sum_all(sq, sh);
+    if (tid == 0) fa.ctl.part_out[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+// ---- FP32 / FP64: row-index-contiguous staging with 16-byte vectors ---------
+// The A~ and X~ tiles are staged as [slice][k][m] and [slice][k][n], so the
+// MFMA operand reads (16 consecutive rows per lane group) are conflict free and
+// X, whose rows are contiguous in n, moves as VW-element vectors from HBM to
+// LDS with the tube transform applied in between.  Offsets are 32-bit from the
+// base pointers (the host checks that every tensor has < 2^31 elements).
+template <typename T, int VW> struct VecIO;
+template <typename T> struct VecIO<T, 1> {
+  __device__ static void ld(const T* p, T* v) { v[0] = p[0]; }
+  __device__ static void st(T* p, const T* v) { p[0] = v[0]; }
+};
+template <> struct VecIO<float, 4> {
+  __device__ static void ld(const float* p, float* v) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  __device__ static void st(float* p, const float* v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+};
+template <> struct VecIO<double, 2> {
+  __device__ static void ld(const double* p, double* v) {
+    const double2 q = *reinterpret_cast<const double2*>(p);
+    v[0] = q.x; v[1] = q.y;
+  }
+  __device__ static void st(double* p, const double* v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  }
+};
+
+template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA, int VW>
+__global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
+  typedef Mfma<T> MF;
+  typedef typename MF::acc_t acc_t;
+  typedef typename MF::frag_t frag_t;
+  constexpr int KSTEP = MF::KSTEP;
+  static_assert(KSTEP == 4 && MF::EPL == 1, "32/64-bit MFMA only");
+  static_assert(BK % KSTEP == 0, "BK");
+  constexpr int BKT = BK * WK;
+  constexpr int PADM = (BM == 16 || sizeof(T) == 8) ? 0 : 16;  // bank offset between k rows
+  constexpr int PADN = (BN == 16 || sizeof(T) == 8) ? 0 : 16;
+  constexpr int LDM = BM + PADM, LDN = BN + PADN;
+  constexpr int WGM = (WK == 1) ? 2 : 1, WGN = (WK == 1) ? 2 : 1;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  static_assert(WK == 1 || WK == 4, "WK");
+  static_assert(FM >= 1 && FN >= 1, "tile");
+  static_assert(BM % VW == 0 && BN % VW == 0 && BKT % VW == 0, "vector width");
+
+  // one LDS buffer: the A~ and X~ tiles, reused by the cross-wave reduction
+  __shared__ __attribute__((aligned(16))) T smem[PMAX * BKT * LDM + PMAX * BKT * LDN];
+  T* const As = smem;
+  T* const Bs = smem + PMAX * BKT * LDM;
+  __shared__ T sGin[PMAX * PMAX], sGout[PMAX * PMAX];
+  __shared__ double sh[8];
+
+  const int p = EXACT ? PMAX : fa.p;
+  const int M = fa.M, N = fa.N, K = fa.K;
+  const int lda = (int)fa.lda, sA = (int)fa.sA;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < p * p; i += 256) {
+    sGin[i] = ((const T*)fa.Gin)[i];
+    sGout[i] = ((const T*)fa.Gout)[i];
+  }
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const T* A = (const T*)fa.A;
+  const T* X = (const T*)fa.X;
+  T* xnorm = (blockIdx.y == 0) ? (T*)fa.xnorm : nullptr;
+
+  const int wk = (WK == 1) ? 0 : wave;
+  const int wmn = (WK == 1) ? wave : 0;
+  const int wm = wmn >> 1, wn = wmn & 1;
+  const int lr = lane & 15;
+  const int lk = lane >> 4;
+
+  frag_t acc[PMAX][FM][FN];
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[k][i][j][r] = (acc_t)0;
+
+  // A~ vectors: TA -> along m ([k][m] rows of the transposed slice); else along k
+  constexpr int AV_ROW = TA ? BM / VW : BKT / VW;            // vectors per contiguous row
+  constexpr int A_V = PMAX * (TA ? BKT : BM) * AV_ROW;       // vectors per chunk
+  constexpr int A_PER = (A_V + 255) / 256;
+  constexpr int X_V = BKT * (BN / VW);                       // tube-vector positions per chunk
+  constexpr int X_PER = (X_V + 255) / 256;
+  T ra[A_PER][VW];
+  T rx[X_PER][PMAX][VW];
+
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u) {
+      const int idx = tid + u * 256;
+      const int k = idx / ((TA ? BKT : BM) * AV_ROW);
+      const int rem = idx - k * ((TA ? BKT : BM) * AV_ROW);
+      const int row = rem / AV_ROW, cv = (rem - row * AV_ROW) * VW;
+      // TA: row = kk, cv = m offset; else row = m, cv = kk offset
+      const int gm = m0 + (TA ? cv : row), gk = k0 + (TA ? row : cv);
+      const bool ok = (A_V % 256 == 0 || idx < A_V) && k < p && gm < M && gk < K;
+      const int off = ok ? k * sA + (TA ? gk * lda + gm : gm * lda + gk) : 0;
+      VecIO<T, VW>::ld(A + off, ra[u]);
+      if (!ok) {
+#pragma unroll
+        for (int v = 0; v < VW; ++v) ra[u][v] = (T)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < X_PER; ++u) {
+      const int idx = tid + u * 256;
+      const int kk = idx / (BN / VW), nv = (idx - kk * (BN / VW)) * VW;
+      const int gk = k0 + kk, gn = n0 + nv;
+      const bool in = (X_V % 256 == 0 || idx < X_V) && gk < K && gn < N;
+#pragma unroll
+      for (int t = 0; t < PMAX; ++t) {
+        const bool ok = in && t < p;
+        VecIO<T, VW>::ld(X + (ok ? (t * K + gk) * N + gn : 0), rx[u][t]);
+        if (!ok) {
+#pragma unroll
+          for (int v = 0; v < VW; ++v) rx[u][t][v] = (T)0;
+        }
+      }
+    }
+  };
+  T sc = (T)1;  // input scale, set by the control block before the first store
+  auto store_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u) {
+      const int idx = tid + u * 256;
+      if (A_V % 256 == 0 || idx < A_V) {
+        const int k = idx / ((TA ? BKT : BM) * AV_ROW);
+        const int rem = idx - k * ((TA ? BKT : BM) * AV_ROW);
+        const int row = rem / AV_ROW, cv = (rem - row * AV_ROW) * VW;
+        if (TA) {
+          VecIO<T, VW>::st(&As[(k * BKT + row) * LDM + cv], ra[u]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VW; ++v) As[(k * BKT + cv + v) * LDM + row] = ra[u][v];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < X_PER; ++u) {
+      const int idx = tid + u * 256;
+      if (X_V % 256 == 0 || idx < X_V) {
+        const int kk = idx / (BN / VW), nv = (idx - kk * (BN / VW)) * VW;
+        const int gk = k0 + kk, gn = n0 + nv;
+        T xv[PMAX][VW];
+#pragma unroll
+        for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+          for (int v = 0; v < VW; ++v) xv[t][v] = sc * rx[u][t][v];
+        if (xnorm != nullptr && gk < K && gn < N) {
+#pragma unroll
+          for (int t = 0; t < PMAX; ++t)
+            if (t < p) VecIO<T, VW>::st(xnorm + (t * K + gk) * N + gn, xv[t]);
+        }
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k) {
+          if (k < p) {
+            T h[VW];
+#pragma unroll
+            for (int v = 0; v < VW; ++v) h[v] = (T)0;
+#pragma unroll
+            for (int t = 0; t < PMAX; ++t) {
+              if (t < p) {
+                const T g = sGin[k * p + t];
+#pragma unroll
+                for (int v = 0; v < VW; ++v) h[v] += g * xv[t][v];
+              }
+            }
+            VecIO<T, VW>::st(&Bs[(k * BKT + kk) * LDN + nv], h);
+          }
+        }
+      }
+    }
+  };
+
+  // the first chunk's loads do not depend on the control block: issue them
+  // before its (memory-latency bound) evaluation
+  load_chunk(0);
+  double a_d, b_d, s_d;
+  if (!ctl_begin(fa.ctl, a_d, b_d, s_d, sh)) return;
+  sc = (T)s_d;
+  for (int k0 = 0; k0 < K; k0 += BKT) {
+    __syncthreads();
+    store_chunk(k0);
+    __syncthreads();
+    if (k0 + BKT < K) load_chunk(k0 + BKT);
+    const int kb = wk * BK, ke = (WK == 1) ? BKT : kb + BK;
+    for (int ks = kb; ks < ke; ks += KSTEP) {
+#pragma unroll
+      for (int k = 0; k < PMAX; ++k) {
+        if (k < p) {
+          const T* arow = &As[(k * BKT + ks + lk) * LDM + wm * WM + lr];
+          const T* brow = &Bs[(k * BKT + ks + lk) * LDN + wn * WN + lr];
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[k][i][j] = MF::mac(arow + i * 16, brow + j * 16, acc[k][i][j]);
+        }
+      }
+    }
+  }
+
+  // Epilogue.  Output element (i, j, r) of this lane: row m0 + wm WM + 16 i + rr(r),
+  // column n0 + wn WN + 16 j + lane % 16.  With a split contraction (WK = 4) the
+  // four waves' partial accumulators are summed through LDS and wave w finishes
+  // register r = w, so all four waves share the epilogue.
+  constexpr int RN = (WK == 4) ? 1 : 4;  // accumulator registers finished by this wave
+  auto out_row = [&](int i, int r) {
+    return m0 + wm * WM + i * 16 + (MF::ROWS_STRIDED ? (lane >> 4) + 4 * r : (lane >> 4) * 4 + r);
+  };
+  const int rbase = (WK == 4) ? wave : 0;
+  const T a = (T)a_d, b = (T)b_d;
+  const T* src = (const T*)fa.src;
+  T* Y = (T*)fa.Y;
+  // prefetch the epilogue's src values (independent of the accumulators).  src
+  // is null whenever b = 0, so the loads are issued only when both are set;
+  // inside, out-of-range positions load element 0 of the (non-null) src.
+  T sv[FM][FN][RN][PMAX];
+  const bool use_src = src != nullptr && b != (T)0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int rr = 0; rr < RN; ++rr)
+#pragma unroll
+        for (int t = 0; t < PMAX; ++t) sv[i][j][rr][t] = (T)0;
+  if (use_src) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int col = n0 + wn * WN + j * 16 + (lane & 15);
+#pragma unroll
+        for (int rr = 0; rr < RN; ++rr) {
+          const int row = out_row(i, rbase + rr);
+#pragma unroll
+          for (int t = 0; t < PMAX; ++t) {
+            const bool ok = t < p && row < M && col < N;
+            const T v = src[ok ? (t * M + row) * N + col : 0];
+            sv[i][j][rr][t] = ok ? v : (T)0;
+          }
+        }
+      }
+  }
+
+  T accf[PMAX][FM][FN][RN];
+  if constexpr (WK == 4) {
+    constexpr int SLOT = 64 * 4;  // one slice of one wave: 64 lanes x 4 registers
+    static_assert(sizeof(smem) >= sizeof(acc_t) * 4 * PMAX * SLOT, "LDS too small for the cross-wave reduction");
+    acc_t* red = reinterpret_cast<acc_t*>(smem);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(wave * PMAX + k) * SLOT + r * 64 + lane] = acc[k][0][0][r];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      acc_t v = (acc_t)0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) v += red[(w * PMAX + k) * SLOT + wave * 64 + lane];
+      accf[k][0][0][0] = (T)v;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accf[k][i][j][r] = (T)acc[k][i][j][r];
+  }
+
+  double sq = 0.0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * WN + j * 16 + (lane & 15);
+#pragma unroll
+      for (int rr = 0; rr < RN; ++rr) {
+        const int row = out_row(i, rbase + rr);
+        if (row < M && col < N) {
+#pragma unroll
+          for (int t = 0; t < PMAX; ++t) {
+            if (t >= p) break;
+            T y = (T)0;
+#pragma unroll
+            for (int k = 0; k < PMAX; ++k)
+              if (k < p) y += sGout[t * p + k] * accf[k][i][j][rr];
+            const T v = a * y + b * sv[i][j][rr][t];
+            Y[(t * M + row) * N + col] = v;
+            sq += (double)v * (double)v;
+          }
+        }
+      }
+    }
+  if (fa.ctl.part_out != nullptr) {
+    const double tot = block_sum_all(sq, sh);
+    if (tid == 0) fa.ctl.part_out[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK>
+static hipError_t launch_fused_mn_cfg(hipStream_t s, const FusedArgs& fa, int ta, bool vec, int* nblocks_out) {
+  dim3 grid((unsigned)((fa.N + BN - 1) / BN), (unsigned)((fa.M + BM - 1) / BM));
+  if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
+  if ((int64_t)grid.x * grid.y > kRedBlocks && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
+  constexpr int VW = 16 / (int)sizeof(T);
+#define DCTK_MN_LAUNCH(TA_, VW_) \
+  hipLaunchKernelGGL((cprod_fused_mn_kernel<T, PMAX, EXACT, BM, BN, WK, BK, TA_, VW_>), grid, dim3(256), 0, s, fa)
+  if (ta) {
+    if (vec) DCTK_MN_LAUNCH(true, VW); else DCTK_MN_LAUNCH(true, 1);
+  } else {
+    if (vec) DCTK_MN_LAUNCH(false, VW); else DCTK_MN_LAUNCH(false, 1);
+  }
+#undef DCTK_MN_LAUNCH
+  return hipGetLastError();
+}
+
+template <typename T, int PMAX, bool EXACT>
+static hipError_t launch_fused_mn_p(hipStream_t s, const FusedArgs& fa, int ta, bool vec, int* nblocks_out) {
+  constexpr int BK = (sizeof(T) == 8) ? 8 : 16;
+  // 16x16 tiles (small problems, latency bound): the whole contraction of a
+  // 256-long K in one staged chunk when it fits in ~130 KB of LDS
+  constexpr int BK16 = PMAX > 4 ? BK : (sizeof(T) == 8 ? 32 : 64);
+  const int64_t t32 = (int64_t)((fa.M + 31) / 32) * ((fa.N + 31) / 32);
+  const int64_t t64 = (int64_t)((fa.M + 63) / 64) * ((fa.N + 63) / 64);
+  const int ncu = num_cus();
+  if (t32 < ncu) return launch_fused_mn_cfg<T, PMAX, EXACT, 16, 16, 4, BK16>(s, fa, ta, vec, nblocks_out);
+  if (t64 < ncu || sizeof(T) == 8 || PMAX > 4 || t64 > kRedBlocks)
+    return launch_fused_mn_cfg<T, PMAX, EXACT, 32, 32, 1, BK>(s, fa, ta, vec, nblocks_out);
+  return launch_fused_mn_cfg<T, PMAX, EXACT, 64, 64, 1, BK>(s, fa, ta, vec, nblocks_out);
+}
+
+template <typename T>
+static hipError_t launch_fused_mn(hipStream_t s, const FusedArgs& fa, int ta, int* nblocks_out) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  const bool vec = fa.M % VW == 0 && fa.N % VW == 0 && fa.K % VW == 0 && fa.lda % VW == 0 &&
+                   ((uintptr_t)fa.A % 16) == 0 && ((uintptr_t)fa.X % 16) == 0 &&
+                   (fa.xnorm == nullptr || ((uintptr_t)fa.xnorm % 16) == 0);
+  if (fa.p == 3) return launch_fused_mn_p<T, 3, true>(s, fa, ta, vec, nblocks_out);
+  if (fa.p <= 4) return launch_fused_mn_p<T, 4, false>(s, fa, ta, vec, nblocks_out);
+  return launch_fused_mn_p<T, 8, false>(s, fa, ta, vec, nblocks_out);
+}
+
+template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK>
+static hipError_t launch_fused_cfg(hipStream_t s, const FusedArgs& fa, int ta, int* nblocks_out) {
+  dim3 grid((unsigned)((fa.N + BN - 1) / BN), (unsigned)((fa.M + BM - 1) / BM));
+  if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
+  if ((int64_t)grid.x * grid.y > kRedBlocks && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
+  if (ta)
+    hipLaunchKernelGGL((cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true>), grid, dim3(256), 0, s, fa);
+  else
+    hipLaunchKernelGGL((cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false>), grid, dim3(256), 0, s, fa);
+  return hipGetLastError();
+}
+
+// Tile choice: 16x16 with a split contraction while 32x32 tiles would not
+// cover the CUs, then 32x32, then 64x64 (FP64 and p > 4 stay at 32x32 to
+// bound the accumulator registers).
+template <typename TI, typename TV, int PMAX, bool EXACT>
+static hipError_t launch_fused_p(hipStream_t s, const FusedArgs& fa, int ta, int* nblocks_out) {
+  constexpr int KS = Mfma<TI>::KSTEP;
+  // contraction chunk per wave: keep each LDS operand buffer near 16-20 KB
+  constexpr int BK16 = (KS == 32) ? 32 : (sizeof(TI) == 8 ? (PMAX > 4 ? 4 : 8) : (PMAX > 4 ? 8 : 16));
+  constexpr int BK32 = (KS == 32) ? 32 : (sizeof(TI) == 8 ? (PMAX > 4 ? 4 : 8) : 16);
+  constexpr int BK64 = (KS == 32) ? 32 : (PMAX > 4 ? 8 : 16);
+  const int64_t t32 = (int64_t)((fa.M + 31) / 32) * ((fa.N + 31) / 32);
+  const int64_t t64 = (int64_t)((fa.M + 63) / 64) * ((fa.N + 63) / 64);
+  const int ncu = num_cus();
+  if (t32 < ncu) return launch_fused_cfg<TI, TV, PMAX, EXACT, 16, 16, 4, BK16>(s, fa, ta, nblocks_out);
+  if (t64 < ncu || sizeof(TI) == 8 || PMAX > 4 || t64 > kRedBlocks)
+    return launch_fused_cfg<TI, TV, PMAX, EXACT, 32, 32, 1, BK32>(s, fa, ta, nblocks_out);
+  return launch_fused_cfg<TI, TV, PMAX, EXACT, 64, 64, 1, BK64>(s, fa, ta, nblocks_out);
+}
+
+template <typename TI, typename TV>
+static hipError_t launch_fused_t(hipStream_t s, const FusedArgs& fa, int ta, int* nblocks_out) {
+  if (fa.p == 3) return launch_fused_p<TI, TV, 3, true>(s, fa, ta, nblocks_out);  // colour images
+  if (fa.p <= 4) return launch_fused_p<TI, TV, 4, false>(s, fa, ta, nblocks_out);
+  return launch_fused_p<TI, TV, 8, false>(s, fa, ta, nblocks_out);
+}
+
+hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,
+                        void* xnorm, const Ctl& ctl, int* nblocks_out) {
+  FusedArgs fa;
+  fa.p = (int)op->p;
+  fa.M = (int)(adjoint ? op->n2 : op->n1);
+  fa.K = (int)(adjoint ? op->n1 : op->n2);
+  fa.N = (int)op->s;
+  fa.lda = op->n2;
+  fa.sA = op->n1 * op->n2;
+  fa.A = op->Ah;
+  fa.X = X;
+  fa.Y = Y;
+  fa.src = src;
+  fa.xnorm = xnorm;
+  const int64_t pp = op->p * op->p;
+  const int gi = adjoint ? 2 : 0, go = adjoint ? 3 : 1;
+  if (op->vec_dtype == DCTK_F64) {
+    fa.Gin = op->Gd + gi * pp;
+    fa.Gout = op->Gd + go * pp;
+  } else {
+    fa.Gin = op->Gf + gi * pp;
+    fa.Gout = op->Gf + go * pp;
+  }
+  fa.ctl = ctl;
+  // split-contraction tiles need the whole p x 16 x 16 accumulator set per wave
+  switch (op->gemm_dtype) {
+    case DCTK_F64: return launch_fused_mn<double>(s, fa, adjoint, nblocks_out);
+    case DCTK_F32: return launch_fused_mn<float>(s, fa, adjoint, nblocks_out);
+    case DCTK_BF16: return launch_fused_t<bf16_t, float>(s, fa, adjoint, nblocks_out);
+    case DCTK_F16: return launch_fused_t<f16_t, float>(s, fa, adjoint, nblocks_out);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dctk

@@ -10,63 +10,10 @@
 // Global loads are ordered along each operand's contiguous dimension; the
 // next K-chunk is prefetched into registers while the current one is
 // multiplied.  Ragged edges are zero-filled on load and masked on store.
-#include "internal.h"
+#include "mfma.h"
 
 namespace dctk {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-
-// MFMA per input type: KSTEP = contraction length of one instruction,
-// EPL = elements of A (and of B) each lane supplies.
-template <typename TI> struct Mfma;
-// ROWS_STRIDED: output register r of lane l holds row (l/16) + 4 r (FP64)
-// instead of 4 (l/16) + r (FP32 / BF16 / FP16), column l % 16 in both.
-template <> struct Mfma<double> {
-  static constexpr int KSTEP = 4, EPL = 1;
-  static constexpr bool ROWS_STRIDED = true;
-  typedef double acc_t;
-  typedef f64x4 frag_t;
-  __device__ static frag_t mac(const double* a, const double* b, frag_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
-  }
-};
-template <> struct Mfma<float> {
-  static constexpr bool ROWS_STRIDED = false;
-  static constexpr int KSTEP = 4, EPL = 1;
-  typedef float acc_t;
-  typedef f32x4 frag_t;
-  __device__ static frag_t mac(const float* a, const float* b, frag_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
-  }
-};
-template <> struct Mfma<bf16_t> {
-  static constexpr bool ROWS_STRIDED = false;
-  static constexpr int KSTEP = 32, EPL = 8;
-  typedef float acc_t;
-  typedef f32x4 frag_t;
-  __device__ static frag_t mac(const bf16_t* a, const bf16_t* b, frag_t c) {
-    bf16x8 av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(a));
-    bf16x8 bv = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(b));
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
-  }
-};
-template <> struct Mfma<f16_t> {
-  static constexpr bool ROWS_STRIDED = false;
-  static constexpr int KSTEP = 32, EPL = 8;
-  typedef float acc_t;
-  typedef f32x4 frag_t;
-  __device__ static frag_t mac(const f16_t* a, const f16_t* b, frag_t c) {
-    f16x8 av = __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(a));
-    f16x8 bv = __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(b));
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, c, 0, 0, 0);
-  }
-};
-
-template <typename TO, typename TA> __device__ inline TO out_cvt(TA v) { return (TO)v; }
-template <> __device__ inline bf16_t out_cvt<bf16_t, float>(float v) { return float_to_bf16(v); }
 
 template <typename TI, typename TO, int BM, int BN, bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
@@ -256,8 +203,17 @@ hipError_t launch_gemm(hipStream_t s, int in_dtype, int out_acc, int M, int N, i
 // ---- the c-product and its adjoint on an operator's workspaces ---------------
 static size_t dtype_size(int dt) { return dt == DCTK_F64 ? 8 : (dt == DCTK_F32 ? 4 : 2); }
 
-hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, double a, const void* X, double b,
-                    const void* src, void* Y, Gate g) {
+hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,
+                    void* xnorm, const Ctl& ctl, int* nblocks_out) {
+  dctk_ctx ctx = op->ctx;
+  const int64_t nmax = op->n1 > op->n2 ? op->n1 : op->n2;
+  const bool small_offsets = op->p * op->n1 * op->n2 < (int64_t(1) << 31) && op->p * nmax * op->s < (int64_t(1) << 31);
+  if (!op->two_sided && op->p <= kFusedMaxP && small_offsets) {
+    prof_begin(ctx, PROF_GEMM);
+    hipError_t e = launch_fused(op, s, adjoint, X, Y, src, xnorm, ctl, nblocks_out);
+    prof_end(ctx, PROF_GEMM);
+    return e;
+  }
   const int64_t p = op->p, n1 = op->n1, n2 = op->n2, sc = op->s;
   const int gdt = op->gemm_dtype, vdt = op->vec_dtype;
   const double* Gd = op->Gd;
@@ -267,13 +223,24 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, double a, const void
   // rows of the input / output vectors
   const int64_t rin = adjoint ? n1 : n2;
   const int64_t rout = adjoint ? n2 : n1;
-  // step 1: transform the input tubes (L, or L^{-T} for the adjoint) into the GEMM type
+  // step 1: transform the input tubes (L, or L^{-T} for the adjoint) into the GEMM type;
+  // this kernel evaluates the control block (input scale, recorded scalars)
   const int gi = adjoint ? 2 : 0;
-  dctk_ctx ctx = op->ctx;
   prof_begin(ctx, PROF_TUBE_FWD);
-  e = launch_tube(s, vdt, gdt, p, rin * sc, X, op->xh, Gd + gi * pp, Gf + gi * pp, 1.0, 0.0, nullptr, g);
+  e = launch_tube(s, vdt, gdt, p, rin * sc, X, op->xh, Gd + gi * pp, Gf + gi * pp, nullptr, xnorm, ctl, true,
+                  false, nullptr);
   prof_end(ctx, PROF_TUBE_FWD);
   if (e != hipSuccess) return e;
+  // later kernels read the recorded scalars from the state
+  Ctl later = ctl;
+  later.from_state = 1;
+  Gate g{nullptr, 0, 0};
+  if (ctl.kind != CTL_PLAIN) {
+    g.st = ctl.st;
+    g.j = ctl.kind == CTL_ARN_FWD ? ctl.j - 1 : ctl.j;
+    g.mode = (ctl.kind == CTL_GKB_FWD) ? 0 : 1;
+    if (ctl.kind == CTL_GKB_FWD) g.j = ctl.j;
+  }
   // step 2: slice products
   const int64_t sAh = n1 * n2;
   prof_begin(ctx, PROF_GEMM);
@@ -291,16 +258,17 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, double a, const void
   }
   prof_end(ctx, PROF_GEMM);
   if (e != hipSuccess) return e;
-  // step 3: inverse transform (L^{-1}, or L^T for the adjoint) with the a/b epilogue
+  // step 3: inverse transform (L^{-1}, or L^T for the adjoint) with the epilogue
   const int go = adjoint ? 3 : 1;
   prof_begin(ctx, PROF_TUBE_INV);
-  e = launch_tube(s, vdt, vdt, p, rout * sc, op->ch, Y, Gd + go * pp, Gf + go * pp, a, b,
-                  (b != 0.0) ? src : nullptr, g);
+  e = launch_tube(s, vdt, vdt, p, rout * sc, op->ch, Y, Gd + go * pp, Gf + go * pp, src, nullptr, later, false,
+                  true, nblocks_out);
   prof_end(ctx, PROF_TUBE_INV);
   return e;
 }
 
 void set_num_cus(int n) { if (n > 0) g_num_cus = n; }
+int num_cus() { return g_num_cus; }
 size_t elem_size(int dt) { return dtype_size(dt); }
 
 }  // namespace dctk

@@ -2,8 +2,6 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
-#include <hip/hip_bf16.h>
-#include <hip/hip_fp16.h>
 #include <stdint.h>
 
 #include "../../include/dctkrylov.h"
@@ -11,75 +9,72 @@
 namespace dctk {
 
 constexpr int kMaxK = 64;              // largest Krylov dimension (projected problem <= 65 x 64)
-constexpr int kRedBlocks = 1024;       // max blocks of a reducing kernel
-constexpr int kRedVals = kMaxK + 2;    // max values reduced by one kernel
-constexpr int kTickets = 8;            // reduction ticket counters per context
+constexpr int kRedBlocks = 4096;       // max blocks of a reducing kernel (partials per reduction)
+constexpr int kRedVals = kMaxK + 2;    // max values reduced by one multi-dot kernel
 constexpr int kThreads = 256;          // threads per block of streaming kernels
 constexpr int kMaxTube = 64;           // largest n3 (the p x p transform matrix sits in LDS)
+constexpr int kFusedMaxP = 8;          // n3 up to which a c-product is one fused kernel
+constexpr double kBreakFactor = 64.0;  // breakdown: new norm <= 64 eps * running max
 
 typedef unsigned short bf16_t;         // storage of bfloat16 (bit pattern)
 typedef _Float16 f16_t;
 
 // ---- device-resident state of one Krylov workspace ------------------------
-// Gate phases: which part of a Golub-Kahan / Arnoldi step a kernel belongs to.
-enum Phase : int {
-  PH_ALWAYS = 0,   // runs unless the process stopped at an earlier step
-  PH_AFTER_U = 1,  // GKB: needs U_{j+1} (skipped after a beta breakdown in this step)
-  PH_VNORM = 2,    // GKB: needs V_{j+1} (skipped after any breakdown in this step)
-  PH_WUPD = 3,     // LSQR: search-direction update (skipped after any breakdown)
-};
+// Every scalar a step produces is stored at its step index, so a kernel only
+// reads entries written by earlier kernels: no intra-kernel races between the
+// block that records a scalar and the blocks that use it.
 enum StopKind : int { STOP_NONE = 0, STOP_BETA = 1, STOP_ALPHA = 2, STOP_CONV = 3 };
 
 struct KState {
   int steps;        // steps completed in the current process
   int stop_step;    // -1 while running; else the 1-based step at which it stopped
-  int stop_kind;    // StopKind
-  int status;       // DCTK_OK / DCTK_BREAKDOWN
+  int stop_kind;    // StopKind (GKB: which norm broke down; Arnoldi: STOP_BETA)
+  int status;       // DCTK_OK / DCTK_BREAKDOWN / DCTK_ENONFINITE
   int converged;
   int cycles;       // GMRES cycles finished
   int halt;         // GMRES: set on convergence / zero residual; every gated kernel skips
   int total_steps;  // GMRES: Arnoldi steps over all cycles
-  double scale;     // running max of alpha, beta (or |h|) for the breakdown test
-  double rhobar, phibar;
-  double cx, cw;    // LSQR step (f): X += cx W;  W = V_{j+1} - cw W
   double tol;
-  double beta0;     // ||R_0|| (Arnoldi) or beta_1 (GKB)
+  double beta0;     // ||R_0|| (Arnoldi)
   double lambda;    // projected solve: lambda used
   double gcv;       // GCV value at lambda
   double resnorm;   // GMRES: ||C - M(X)||
-  double alpha[kMaxK + 2];
-  double beta[kMaxK + 2];
-  double H[(kMaxK + 1) * kMaxK];   // Arnoldi Hessenberg, row-major, ld = kMaxK
-  double coef[kRedVals];           // Gram coefficients of the current reorthogonalisation pass
-  double y[kMaxK + 1];             // projected solution
+  double sweeps;    // one-sided Jacobi sweeps of the last projected solve
+  double pad[2];
+  double alpha[kMaxK + 2];          // GKB alpha_1.. at [0..]
+  double beta[kMaxK + 2];           // GKB beta_1.. at [0..]
+  double rhobar[kMaxK + 2];         // LSQR rhobar_{j+1} at [j]
+  double phibar[kMaxK + 2];         // LSQR phibar_{j+1} at [j]
+  double H[(kMaxK + 1) * kMaxK];    // Arnoldi Hessenberg, row-major, ld = kMaxK
+  double coef[kRedVals];            // Gram coefficients of the current reorthogonalisation pass
+  double y[kMaxK + 1];              // projected solution
 };
 
-struct Gate {
-  const KState* st;  // nullptr: always open
-  int j;             // 1-based step the kernel belongs to
-  int phase;
+// ---- control of a product kernel inside a Krylov step -----------------------
+// A c-product inside a Krylov step reads its scalars from the device: either
+// by summing the per-block partials of the previous kernel (fixed order, in
+// every block, so all blocks agree bit for bit) or from the state arrays.
+enum CtlKind : int {
+  CTL_PLAIN = 0,     // out = a*y + b*src with constant a, b; input scale s
+  CTL_GKB_INIT = 1,  // Alg. 4 step 2: beta_1 = sqrt(sum part_in); input x 1/beta_1 (-> U_1); out = M*(U_1)
+  CTL_GKB_FWD = 2,   // Alg. 4 (a): out = M(V_j) - alpha_j U_j
+  CTL_GKB_ADJ = 3,   // Alg. 4 (b)-(d): beta_{j+1} = sqrt(sum part_in); input x 1/beta (-> U_{j+1});
+                     //   out = M*(U_{j+1}) - beta_{j+1} V_j
+  CTL_ARN_FWD = 4,   // Alg. 2 (a): h_{j,j-1} = sqrt(sum part_in) (j > 1); input x 1/h (-> V_j); out = M(V_j)
 };
 
-__device__ inline bool gate_open(const Gate& g) {
-  if (g.st == nullptr) return true;
-  const volatile KState* st = g.st;
-  if (st->halt) return false;
-  int ss = st->stop_step;
-  if (ss < 0 || ss > g.j) return true;
-  if (ss < g.j) return false;
-  int kind = st->stop_kind;
-  switch (g.phase) {
-    case PH_AFTER_U: return kind != STOP_BETA;
-    case PH_VNORM: return kind == STOP_CONV;
-    case PH_WUPD: return kind == STOP_CONV;
-    default: return true;
-  }
-}
+struct Ctl {
+  int kind;
+  int j;                  // 1-based step (0: initialisation)
+  int from_state;         // 1: scalars already recorded in st (later kernels of an unfused product)
+  int npart_in;
+  KState* st;
+  const double* part_in;  // partials consumed (sums of squares)
+  double* part_out;       // per-block sum of squares of the output (nullptr: none)
+  double a, b, s;         // CTL_PLAIN constants
+};
 
 // ---- type helpers ----------------------------------------------------------
-template <typename T> struct AccOf { typedef float type; };
-template <> struct AccOf<double> { typedef double type; };
-
 __device__ __host__ inline float bf16_to_float(bf16_t v) {
   union { uint32_t u; float f; } c;
   c.u = ((uint32_t)v) << 16;
@@ -98,7 +93,6 @@ __device__ __host__ inline bf16_t float_to_bf16(float f) {  // round to nearest 
 template <typename TO, typename TI> __device__ inline TO cvt(TI v) { return (TO)v; }
 template <> __device__ inline bf16_t cvt<bf16_t, float>(float v) { return float_to_bf16(v); }
 template <> __device__ inline bf16_t cvt<bf16_t, double>(double v) { return float_to_bf16((float)v); }
-template <> __device__ inline float cvt<float, bf16_t>(bf16_t v) { return bf16_to_float(v); }
 template <> __device__ inline f16_t cvt<f16_t, double>(double v) { return (f16_t)(float)v; }
 
 // ---- wave / block reductions (64-wide waves) -----------------------------
@@ -107,19 +101,172 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Sum over a block of kThreads threads; result valid in thread 0.  `sh` holds
-// kThreads/64 doubles.  Fixed order: deterministic.
-__device__ inline double block_sum(double v, double* sh) {
+// Sum over the block; the result is returned to every thread.  `sh` holds
+// blockDim/64 + 1 doubles.  Fixed order: deterministic.
+__device__ inline double block_sum_all(double v, double* sh) {
   v = wave_sum(v);
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
   if (lane == 0) sh[wid] = v;
   __syncthreads();
-  double r = 0.0;
   if (threadIdx.x == 0) {
+    double r = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+    sh[blockDim.x >> 6] = r;
   }
   __syncthreads();
-  return r;
+  return sh[blockDim.x >> 6];
+}
+
+__device__ inline double block_max_all(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sh[w]);
+    sh[blockDim.x >> 6] = r;
+  }
+  __syncthreads();
+  return sh[blockDim.x >> 6];
+}
+
+// Sum of part[0..n) in a fixed order, returned to every thread of the block.
+__device__ inline double block_sum_partials(const double* part, int n, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+  return block_sum_all(v, sh);
+}
+
+// Running max of |alpha_1..alpha_na|, |beta_1..beta_nb| (breakdown scale).
+__device__ inline double gkb_scale(const KState* st, int na, int nb, double* sh) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < na; i += blockDim.x) m = fmax(m, fabs(st->alpha[i]));
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) m = fmax(m, fabs(st->beta[i]));
+  return block_max_all(m, sh);
+}
+
+// Evaluates the control block at kernel start (all threads of every block
+// call it).  Returns false when the kernel must do nothing.  Block 0 records
+// the scalar it produced in the state.  `sh` holds >= 20 doubles.
+__device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin, double* sh) {
+  a = 1.0; b = 0.0; sin = 1.0;
+  if (c.kind == CTL_PLAIN) {
+    // a plain product inside a GMRES solve is skipped once the solve halted
+    if (c.st != nullptr && ((volatile KState*)c.st)->halt) return false;
+    a = c.a; b = c.b; sin = c.s;
+    return true;
+  }
+  KState* st = c.st;
+  const int ss = ((volatile KState*)st)->stop_step;
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0;
+  const double eps = 2.220446049250313e-16;
+  switch (c.kind) {
+    case CTL_GKB_INIT: {
+      if (c.from_state) {
+        if (ss == 0) return false;
+        sin = 1.0 / st->beta[0];
+        return true;
+      }
+      const double bt = sqrt(block_sum_partials(c.part_in, c.npart_in, sh));
+      const bool bad = !(bt > 0.0) || !isfinite(bt);
+      if (first) {
+        st->beta[0] = bt;
+        st->steps = 0;
+        if (bad) {
+          st->stop_step = 0;
+          st->stop_kind = STOP_BETA;
+          st->status = isfinite(bt) ? DCTK_BREAKDOWN : DCTK_ENONFINITE;
+        }
+      }
+      if (bad) return false;
+      sin = 1.0 / bt;
+      return true;
+    }
+    case CTL_GKB_FWD: {
+      if (ss >= 0) return false;  // stopped at an earlier step
+      b = -st->alpha[c.j - 1];
+      return true;
+    }
+    case CTL_GKB_ADJ: {
+      if (ss >= 0 && ss < c.j) return false;
+      if (c.from_state) {
+        if (ss == c.j) return false;
+        const double bt = st->beta[c.j];
+        sin = 1.0 / bt;
+        b = -bt;
+        return true;
+      }
+      const double bt = sqrt(block_sum_partials(c.part_in, c.npart_in, sh));
+      const double scale = fmax(gkb_scale(st, c.j, c.j, sh), bt);
+      const bool fin = isfinite(bt);
+      const bool brk = !fin || bt <= kBreakFactor * eps * scale;
+      if (first) {
+        st->beta[c.j] = bt;
+        st->steps = c.j;
+        if (brk) {
+          st->stop_step = c.j;
+          st->stop_kind = STOP_BETA;
+          st->status = fin ? DCTK_BREAKDOWN : DCTK_ENONFINITE;
+        }
+      }
+      if (brk) return false;
+      sin = 1.0 / bt;
+      b = -bt;
+      return true;
+    }
+    case CTL_ARN_FWD: {
+      if (((volatile KState*)st)->halt) return false;
+      if (ss >= 0 && ss < c.j) return false;
+      if (c.j == 1) return true;  // V_1 was normalised by the cycle start
+      const int r = c.j - 1, col = c.j - 2;   // h_{j, j-1} (1-based) at H[j-1][j-2]
+      if (c.from_state) {
+        if (ss == c.j - 1) return false;
+        sin = 1.0 / st->H[r * kMaxK + col];
+        return true;
+      }
+      const double h = sqrt(block_sum_partials(c.part_in, c.npart_in, sh));
+      double m = 0.0;
+      for (int i = threadIdx.x; i < r; i += blockDim.x) m = fmax(m, fabs(st->H[i * kMaxK + col]));
+      const double scale = fmax(block_max_all(m, sh), h);
+      const bool fin = isfinite(h);
+      const bool brk = !fin || h <= kBreakFactor * eps * scale;
+      if (first) {
+        st->H[r * kMaxK + col] = h;
+        st->steps = c.j - 1;
+        if (brk) {
+          st->stop_step = c.j - 1;
+          st->stop_kind = STOP_BETA;
+          st->status = fin ? DCTK_BREAKDOWN : DCTK_ENONFINITE;
+        }
+      }
+      if (brk) return false;
+      sin = 1.0 / h;
+      return true;
+    }
+    default:
+      return false;
+  }
+}
+
+// Gate of the plain kernels (GEMMs, reorthogonalisation passes) of a step:
+// mode 0 runs while the process has not stopped before step j; mode 1 also
+// requires that it did not stop at step j (its input exists).
+struct Gate {
+  const KState* st;  // nullptr: always open
+  int j;
+  int mode;
+};
+
+__device__ inline bool gate_open(const Gate& g) {
+  if (g.st == nullptr) return true;
+  const volatile KState* st = g.st;
+  if (st->halt) return false;
+  const int ss = st->stop_step;
+  if (ss < 0) return true;
+  return g.mode == 0 ? ss >= g.j : ss > g.j;
 }
 
 }  // namespace dctk
@@ -130,9 +277,7 @@ struct dctk_ctx_s {
   hipStream_t stream;
   int last_hip_error;
   int num_cus;
-  double* red_partials;   // kRedBlocks * kRedVals doubles
-  unsigned* red_tickets;  // kTickets counters, zero between uses
-  double* red_out;        // kRedVals doubles: results of standalone reductions
+  double* red_partials;   // kRedBlocks * kRedVals doubles: partials of standalone reductions
   void* prof;             // dctk::Profiler while profiling, else null
 };
 
@@ -156,14 +301,18 @@ struct dctk_krylov_s {
   int reorth;
   int initialised;
   int host_steps;          // steps enqueued since init
-  int64_t nvec;            // elements of one basis vector: p*max(n1,n2)*s
-  size_t vbytes;           // bytes of one basis vector (vector dtype)
-  void* U;                 // (k_max+1) vectors (GKB U / Arnoldi V)
-  void* V;                 // (k_max+1) vectors (GKB V)
+  int last_npart;          // partials produced by the last enqueued norm (feeds the next step)
+  int64_t nvec;            // slot stride in elements (>= p*max(n1,n2)*s, 64-aligned)
+  size_t vbytes;           // bytes of one slot
+  void* U;                 // (k_max+1) slots (GKB U / Arnoldi V)
+  void* V;                 // (k_max+1) slots (GKB V)
   void* X;                 // LSQR iterate
   void* W;                 // LSQR search direction
-  void* T;                 // scratch vector (product result)
+  void* T;                 // scratch vectors (2 slots)
   void* R;                 // GMRES residual
+  double* partA;           // kRedBlocks partials (norms feeding the next product)
+  double* partB;           // kRedBlocks partials
+  double* partM;           // kRedBlocks * kRedVals partials of multi-dots
   dctk::KState* st;        // device state
 };
 
@@ -184,67 +333,71 @@ int hip_fail(dctk_ctx ctx, hipError_t e);
 
 // transform matrices (host, FP64): which = DCTK_MAT_*
 int build_tube_matrix(int tube, int which, int64_t p, double* out);
+size_t elem_size(int dt);
+void set_num_cus(int n);
+int num_cus();
 
-// ---- launchers (all enqueue on `stream`) -----------------------------------
-// out[k][e] = a * sum_t G[k][t] in[t][e] + b * src[k][e]   (src may be null when b == 0)
-hipError_t launch_tube(hipStream_t s, int vec_dtype, int out_dtype, int64_t p, int64_t count,
+// ---- product kernels ---------------------------------------------------------
+// Streaming tube transform: out[k][e] = a * sum_t G[k][t] (s * in[t][e]) + b * src[k][e].
+// `xnorm` (may be null) receives s * in.  Scalars come from the control block;
+// ctl.part_out gets per-block sums of out^2.
+hipError_t launch_tube(hipStream_t st, int in_dtype, int out_dtype, int64_t p, int64_t count,
                        const void* in, void* out, const double* Gd, const float* Gf,
-                       double a, double b, const void* src, Gate g);
+                       const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi, int* nblocks_out);
 
-// C_k = op(A_k) op(B_k), batched over `batch`; A: M x K (or K x M if ta), B: K x N (or N x K if tb)
+// C_k = op(A_k) op(B_k), batched over `batch`
 hipError_t launch_gemm(hipStream_t s, int in_dtype, int out_acc, int M, int N, int K,
                        const void* A, int64_t lda, int64_t sA, int ta,
                        const void* B, int64_t ldb, int64_t sB, int tb,
                        void* C, int64_t ldc, int64_t sC, int batch, Gate g);
 
-// Full c-product / adjoint on the op's workspaces:  Y = a*M(X) + b*src
-hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, double a, const void* X, double b,
-                    const void* src, void* Y, Gate g);
+// Fused c-product for one-sided operators with p <= kFusedMaxP.
+hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,
+                        void* xnorm, const Ctl& ctl, int* nblocks_out);
+
+// The c-product / adjoint under a control block: Y = a*M(s X) + b*src; xnorm gets s X.
+// Writes the number of partials produced to *nblocks_out (when ctl.part_out).
+hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,
+                    void* xnorm, const Ctl& ctl, int* nblocks_out);
 
 // ---- streaming vector kernels (vec.hip) ------------------------------------
-enum Act : int {
-  ACT_STORE = 0,       // out_slot[0] = sqrt(sum)
-  ACT_GKB_BETA1 = 1,   // GKB init: beta_1
-  ACT_GKB_ALPHA1 = 2,  // GKB init: alpha_1 (+ LSQR start)
-  ACT_GKB_BETA = 3,    // beta_{j+1} + breakdown test
-  ACT_GKB_ALPHA = 4,   // alpha_{j+1} + breakdown test
-  ACT_ARN_BETA = 5,    // Arnoldi init: beta = ||R_0||
-  ACT_ARN_H = 6,       // h_{j+1,j} + breakdown test
-  ACT_GMRES_RES = 7,   // GMRES: ||C - M(X)|| + convergence test
-  ACT_DOT_STORE = 8,   // dst[0] = sum (no square root)
-};
-
-// out = x + c*y (c = csign * (*cptr) if cptr else cconst); when act >= 0 also
-// reduce sum(out . z) (z null: out . out) into the action.  y may be null
-// (out = x); out may be null (reduce only).
-hipError_t launch_axpy_red(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x,
-                           const void* y, const double* cptr, double csign, double cconst,
-                           const void* z, int act, double* dst, KState* st, int j, Gate g);
-// out = in / (*den)
-hipError_t launch_scale(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* in,
-                        const double* den, Gate g);
-// coef[i] (+)= <basis_i, w> for i < nb (basis vectors `stride` elements apart); accumulate
-// into dst (dst[i*dst_stride]) when accumulate, else overwrite.
-hipError_t launch_multidot(dctk_ctx ctx, int dtype, int64_t n, const void* basis, int64_t stride,
-                           int nb, const void* w, double* dst, int dst_stride, int accumulate,
-                           double* coef_copy, Gate g);
-// w -= sum_i coef[i*cstride] basis_i
-hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* basis,
-                           int64_t stride, int nb, const double* coef, int cstride, Gate g);
-// out = (x0 ? x0 : 0) + sum_{i < *nptr (or nb)} y[i] basis_i
-hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x0,
-                          const void* basis, int64_t stride, int nb, const int* nptr,
-                          const double* y, Gate g);
-// LSQR step (f) with V normalisation
-hipError_t launch_lsqr_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* Vnext,
-                              KState* st, int j);
-hipError_t launch_lsqr_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* V1, KState* st);
-hipError_t launch_lsqr_scalars(dctk_ctx ctx, KState* st, int j);
-hipError_t launch_fill_zero(dctk_ctx ctx, int dtype, int64_t n, void* x);
+// partials of sum(x . z) (z null: x . x)
+hipError_t launch_sumsq(dctk_ctx ctx, int dtype, int64_t n, const void* x, const void* z, double* part,
+                        int* nblocks, Gate g);
+// out = x + c*y with c = csign * cptr[0]; partials of out^2 (part may be null)
+hipError_t launch_axpy_sumsq(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x, const void* y,
+                             const double* cptr, double csign, double* part, int* nblocks, Gate g);
+// partials of <basis_i, w>, i < nb, laid out part[i * nblocks + block]
+hipError_t launch_multidot(dctk_ctx ctx, int dtype, int64_t n, const void* basis, int64_t stride, int nb,
+                           const void* w, double* part, int* nblocks, Gate g);
+// one block: coef[i] = sum_b part[i*nblocks + b]; dst[i*dst_stride] += coef[i] when dst
+hipError_t launch_coef_finalize(dctk_ctx ctx, const double* part, int nblocks, int nb, double* coef,
+                                double* dst, int dst_stride, Gate g);
+// w -= sum_i coef[i] basis_i
+hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* basis, int64_t stride,
+                           int nb, const double* coef, Gate g);
+// out = (x0 ? x0 : 0) + sum_{i < min(nb, *nptr)} y[i] basis_i
+hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x0, const void* basis,
+                          int64_t stride, int nb, const int* nptr, const double* y, Gate g);
+// GMRES cycle start: beta = sqrt(sum part) -> st->beta0 (halt on 0); out = in / beta
+hipError_t launch_arn_start(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* in, const double* part,
+                            int npart, KState* st);
+// Arnoldi MGS pass i of step j: when part_in, h = sum part_in is recorded at hdst and
+// w -= h * vprev; then partials of <vi, w> (vi null: |w|^2) into part_out
+hipError_t launch_mgs(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* vprev, const void* vi,
+                      const double* part_in, int npart_in, double* hdst, double* part_out, int* nblocks,
+                      KState* st, int j);
+// Arnoldi: record h_{j+1,j} = sqrt(sum part) with the breakdown test (one block)
+hipError_t launch_arn_finish(dctk_ctx ctx, const double* part, int npart, KState* st, int j);
+// GMRES: ||C - M(X)|| = sqrt(sum part) with the convergence test (one block)
+hipError_t launch_gmres_res(dctk_ctx ctx, const double* part, int npart, KState* st);
+// GKB start (Algorithm 6 step 2) and the per-step update (Algorithm 6 (c)-(g))
+hipError_t launch_gkb_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* V1, const double* part,
+                            int npart, KState* st);
+hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* Vn, const double* part,
+                             int npart, KState* st, int j);
 hipError_t launch_state_reset(dctk_ctx ctx, KState* st, int full, double tol);
 hipError_t launch_cast(dctk_ctx ctx, int64_t n, const double* in, int out_dtype, void* out);
-void set_num_cus(int n);
-size_t elem_size(int dt);
 
 // projected FP64 problem (projected.hip): bidiag = 1 reads alpha/beta, else H.
 // Writes st->y[0..k), st->lambda, st->gcv.

@@ -103,16 +103,24 @@ template <> struct Vec4Store<double> {
   }
 };
 
-// TIN/TSRC: float or double; TOUT: float, double, bf16_t or f16_t; TC: compute type.
-template <typename TIN, typename TOUT, typename TC, int KB, bool VEC>
+// TIN: float or double; TOUT: float, double, bf16_t or f16_t; TC: compute type.
+// SCALE: apply the control block's input scale (and write xnorm); EPI: apply
+// its a/b/src epilogue and write per-block partials of out^2.
+template <typename TIN, typename TOUT, typename TC, int KB, bool VEC, bool SCALE, bool EPI>
 __global__ __launch_bounds__(kThreads) void tube_kernel(int p, int64_t count, const TIN* __restrict__ in,
-                                                        TOUT* out, const TC* __restrict__ G,
-                                                        TC a, TC b, const TOUT* src, Gate g) {
-  if (!gate_open(g)) return;
+                                                        TOUT* out, const TC* __restrict__ G, const TOUT* src,
+                                                        TIN* xnorm, Ctl ctl) {
+  __shared__ double sh[kThreads / 64 + 2];
+  double a_d, b_d, s_d;
+  if (!ctl_begin(ctl, a_d, b_d, s_d, sh)) return;
+  if (!SCALE) s_d = 1.0;
+  if (!EPI) { a_d = 1.0; b_d = 0.0; }
+  const TC a = (TC)a_d, b = (TC)b_d, sc = (TC)s_d;
   extern __shared__ char smem_raw[];
   TC* sG = reinterpret_cast<TC*>(smem_raw);
   for (int i = threadIdx.x; i < p * p; i += blockDim.x) sG[i] = G[i];
   __syncthreads();
+  double sq = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
   for (int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e0 < count; e0 += stride) {
     const int nv = (count - e0) < 4 ? (int)(count - e0) : 4;
@@ -131,6 +139,15 @@ __global__ __launch_bounds__(kThreads) void tube_kernel(int p, int64_t count, co
 #pragma unroll
           for (int v = 0; v < 4; ++v) xv[v] = v < nv ? ip[v] : (TIN)0;
         }
+        if (SCALE) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xv[v] = (TIN)(sc * (TC)xv[v]);
+          if (xnorm != nullptr && k0 == 0) {
+            TIN* xp = xnorm + (int64_t)t * count + e0;
+            if (VEC && nv == 4) Vec4Store<TIN>::store(xp, xv);
+            else for (int v = 0; v < nv; ++v) xp[v] = xv[v];
+          }
+        }
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk) {
           const TC gk = (k0 + kk < p) ? sG[(k0 + kk) * p + t] : (TC)0;
@@ -147,8 +164,12 @@ __global__ __launch_bounds__(kThreads) void tube_kernel(int p, int64_t count, co
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           TC r = a * acc[kk][v];
-          if (b != (TC)0 && v < nv) r += b * (TC)src[(int64_t)k * count + e0 + v];
+          if (EPI && b != (TC)0 && v < nv) r += b * (TC)src[(int64_t)k * count + e0 + v];
           ov[v] = cvt<TOUT, TC>(r);
+          if (EPI && v < nv) {
+            const double rv = (double)r;
+            sq += rv * rv;
+          }
         }
         if (VEC && nv == 4) {
           Vec4Store<TOUT>::store(op, ov);
@@ -158,45 +179,71 @@ __global__ __launch_bounds__(kThreads) void tube_kernel(int p, int64_t count, co
       }
     }
   }
+  if (EPI && ctl.part_out != nullptr) {
+    const double tot = block_sum_all(sq, sh);
+    if (threadIdx.x == 0) ctl.part_out[blockIdx.x] = tot;
+  }
 }
 
 template <typename TIN, typename TOUT, typename TC>
 static hipError_t launch_tube_t(hipStream_t s, int64_t p, int64_t count, const void* in, void* out,
-                                const TC* G, double a, double b, const void* src, Gate g) {
+                                const TC* G, const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi,
+                                int* nblocks_out) {
   int64_t nthreads = (count + 3) / 4;
   int64_t blocks = (nthreads + kThreads - 1) / kThreads;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > kRedBlocks) blocks = kRedBlocks;
   if (blocks < 1) blocks = 1;
+  if (nblocks_out) *nblocks_out = (int)blocks;
   size_t shmem = (size_t)(p * p) * sizeof(TC);
   bool vec = (count % 4 == 0) && (((uintptr_t)in) % 32 == 0) && (((uintptr_t)out) % 32 == 0) &&
-             (src == nullptr || ((uintptr_t)src) % 32 == 0);
+             (src == nullptr || ((uintptr_t)src) % 32 == 0) && (xnorm == nullptr || ((uintptr_t)xnorm) % 32 == 0);
   const TIN* i = (const TIN*)in;
   TOUT* o = (TOUT*)out;
   const TOUT* sr = (const TOUT*)src;
-  TC ta = (TC)a, tb = (TC)b;
-#define DCTK_TUBE_LAUNCH(KB, V) \
-  hipLaunchKernelGGL((tube_kernel<TIN, TOUT, TC, KB, V>), dim3((unsigned)blocks), dim3(kThreads), shmem, s, (int)p, count, i, o, G, ta, tb, sr, g)
+  TIN* xn = (TIN*)xnorm;
+#define DCTK_TUBE_LAUNCH(KB, V, S, E) \
+  hipLaunchKernelGGL((tube_kernel<TIN, TOUT, TC, KB, V, S, E>), dim3((unsigned)blocks), dim3(kThreads), shmem, s, (int)p, count, i, o, G, sr, xn, ctl)
+#define DCTK_TUBE_SE(KB, V)                                  \
+  do {                                                       \
+    if (scale && epi) DCTK_TUBE_LAUNCH(KB, V, true, true);    \
+    else if (scale) DCTK_TUBE_LAUNCH(KB, V, true, false);     \
+    else if (epi) DCTK_TUBE_LAUNCH(KB, V, false, true);       \
+    else DCTK_TUBE_LAUNCH(KB, V, false, false);               \
+  } while (0)
   if (p <= 4) {
-    if (vec) DCTK_TUBE_LAUNCH(4, true); else DCTK_TUBE_LAUNCH(4, false);
+    if (vec) DCTK_TUBE_SE(4, true); else DCTK_TUBE_SE(4, false);
   } else {
-    if (vec) DCTK_TUBE_LAUNCH(8, true); else DCTK_TUBE_LAUNCH(8, false);
+    if (vec) DCTK_TUBE_SE(8, true); else DCTK_TUBE_SE(8, false);
   }
+#undef DCTK_TUBE_SE
 #undef DCTK_TUBE_LAUNCH
   return hipGetLastError();
 }
 
-hipError_t launch_tube(hipStream_t s, int vec_dtype, int out_dtype, int64_t p, int64_t count,
+// in_dtype: element type of `in` (F64/F32); out_dtype: of `out` (F64, F32, BF16, F16).
+// A transform whose output is a GEMM operand applies the input side of the
+// control block (scale); one whose input is a GEMM result applies the epilogue
+// side (epi).
+hipError_t launch_tube(hipStream_t s, int in_dtype, int out_dtype, int64_t p, int64_t count,
                        const void* in, void* out, const double* Gd, const float* Gf,
-                       double a, double b, const void* src, Gate g) {
-  if (vec_dtype == DCTK_F64) {
-    // FP64 input: output FP64 (the only FP64 GEMM type)
-    return launch_tube_t<double, double, double>(s, p, count, in, out, Gd, a, b, src, g);
+                       const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi, int* nblocks_out) {
+  if (in_dtype == DCTK_F64) {
+    if (out_dtype != DCTK_F64) return hipErrorInvalidValue;
+    return launch_tube_t<double, double, double>(s, p, count, in, out, Gd, src, xnorm, ctl, scale, epi, nblocks_out);
   }
   switch (out_dtype) {
-    case DCTK_F32: return launch_tube_t<float, float, float>(s, p, count, in, out, Gf, a, b, src, g);
-    case DCTK_BF16: return launch_tube_t<float, bf16_t, float>(s, p, count, in, out, Gf, a, b, src, g);
-    case DCTK_F16: return launch_tube_t<float, f16_t, float>(s, p, count, in, out, Gf, a, b, src, g);
-    default: return hipErrorInvalidValue;
+    case DCTK_F32:
+      return launch_tube_t<float, float, float>(s, p, count, in, out, Gf, src, xnorm, ctl, scale, epi, nblocks_out);
+    case DCTK_BF16:
+      if (src) return hipErrorInvalidValue;
+      return launch_tube_t<float, bf16_t, float>(s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false,
+                                                 nblocks_out);
+    case DCTK_F16:
+      if (src) return hipErrorInvalidValue;
+      return launch_tube_t<float, f16_t, float>(s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false,
+                                                nblocks_out);
+    default:
+      return hipErrorInvalidValue;
   }
 }
 

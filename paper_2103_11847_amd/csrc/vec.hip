@@ -2,21 +2,17 @@
 // Krylov methods (Sec. 2.2 inner product; Algorithms 2, 4 and 6; the
 // combination V (*) y of eq. ev1), as streaming kernels.
 //
-// Reductions are deterministic: every block reduces its share in FP64 with
-// wavefront shuffles and writes one partial per value; the last block to
-// arrive (ticket counter) sums the partials in block order and applies the
-// Krylov "action" (store beta_{j+1}, test for breakdown, advance the LSQR
-// scalars, ...) so the scalars never leave the device.  The ticket is
-// returned to zero by that block, so no memset is needed between uses.
+// Reductions are deterministic and need no fences: a reducing kernel writes
+// one FP64 partial per block; the kernel that needs the value (the next one
+// in stream order, after the kernel boundary has made the partials visible)
+// sums them in block order in every block, so all blocks hold the same bits.
+// Block 0 records the scalar in the device state (indexed by step).
 #include <cfloat>
 #include <cmath>
 
 #include "internal.h"
 
 namespace dctk {
-
-static constexpr double kEps = DBL_EPSILON;
-static constexpr double kBreak = 64.0;
 
 template <typename T> struct V4;
 template <> struct V4<float> {
@@ -59,170 +55,65 @@ __device__ inline void st4(T* base, int64_t e, int64_t n, bool vec, const double
   }
 }
 
-// ---- Krylov actions applied by the last block --------------------------------
-__device__ void apply_action(int act, double sum, double* dst, KState* st, int j) {
-  const double ss = sqrt(sum);
-  const bool finite = isfinite(sum);
-  switch (act) {
-    case ACT_STORE:
-      if (dst) dst[0] = ss;
-      break;
-    case ACT_GKB_BETA1:
-      st->beta[0] = ss;
-      st->beta0 = ss;
-      st->scale = ss;
-      st->phibar = ss;
-      st->steps = 0;
-      if (!finite) { st->status = DCTK_ENONFINITE; st->stop_step = 0; st->stop_kind = STOP_BETA; }
-      else if (ss == 0.0) { st->status = DCTK_BREAKDOWN; st->stop_step = 0; st->stop_kind = STOP_BETA; }
-      break;
-    case ACT_GKB_ALPHA1:
-      st->alpha[0] = ss;
-      st->rhobar = ss;
-      st->scale = fmax(st->scale, ss);
-      if (!finite) { st->status = DCTK_ENONFINITE; st->stop_step = 0; st->stop_kind = STOP_ALPHA; }
-      else if (ss <= kBreak * kEps * st->scale) { st->status = DCTK_BREAKDOWN; st->stop_step = 0; st->stop_kind = STOP_ALPHA; }
-      break;
-    case ACT_GKB_BETA:
-      st->beta[j] = ss;
-      st->scale = fmax(st->scale, ss);
-      st->steps = j;
-      if (!finite) { st->status = DCTK_ENONFINITE; st->stop_step = j; st->stop_kind = STOP_BETA; }
-      else if (ss <= kBreak * kEps * st->scale) { st->status = DCTK_BREAKDOWN; st->stop_step = j; st->stop_kind = STOP_BETA; }
-      break;
-    case ACT_GKB_ALPHA:
-      st->alpha[j] = ss;
-      st->scale = fmax(st->scale, ss);
-      st->steps = j;
-      if (!finite) { st->status = DCTK_ENONFINITE; st->stop_step = j; st->stop_kind = STOP_ALPHA; }
-      else if (ss <= kBreak * kEps * st->scale) { st->status = DCTK_BREAKDOWN; st->stop_step = j; st->stop_kind = STOP_ALPHA; }
-      break;
-    case ACT_ARN_BETA:
-      st->beta0 = ss;
-      st->steps = 0;
-      if (!finite) { st->status = DCTK_ENONFINITE; st->halt = 1; }
-      else if (ss == 0.0) { st->halt = 1; }
-      break;
-    case ACT_ARN_H: {
-      st->H[j * kMaxK + (j - 1)] = ss;
-      double sc = st->scale;
-      for (int i = 0; i <= j; ++i) sc = fmax(sc, fabs(st->H[i * kMaxK + (j - 1)]));
-      st->scale = sc;
-      st->steps = j;
-      if (!finite) { st->status = DCTK_ENONFINITE; st->stop_step = j; st->stop_kind = STOP_BETA; st->halt = 1; }
-      else if (ss <= kBreak * kEps * sc) { st->status = DCTK_BREAKDOWN; st->stop_step = j; st->stop_kind = STOP_BETA; }
-      break;
-    }
-    case ACT_GMRES_RES:
-      st->resnorm = ss;
-      st->cycles += 1;
-      st->total_steps += st->steps;
-      if (!finite) { st->status = DCTK_ENONFINITE; st->halt = 1; }
-      else if (ss < st->tol) { st->converged = 1; st->halt = 1; }
-      break;
-    case ACT_DOT_STORE:
-      if (dst) dst[0] = sum;
-      break;
-    default:
-      break;
-  }
-}
+__device__ inline bool first_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
-// Last-block protocol: returns true in the block that must finish the reduction.
-__device__ inline bool arrive_last(unsigned* ticket) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(ticket, 1u);
-    last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
-}
+#define DCTK_GRID_LOOP(e, n) \
+  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < (n); e += (int64_t)gridDim.x * blockDim.x * 4)
 
-__device__ inline void reset_ticket(unsigned* ticket) {
-  if (threadIdx.x == 0) atomicExch(ticket, 0u);
-}
-
-// out = x + c*y, optional reduction of out . z (z == nullptr: out . out).
-// `out` may be nullptr (reduce only).  act < 0: no reduction.
+// ---- reductions ----------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_axpy_red(int64_t n, T* out, const T* x,
-                                                       const T* y, const double* cptr, double csign,
-                                                       double cconst, const T* z, int act, double* dst,
-                                                       KState* st, int j, double* partials, unsigned* ticket,
-                                                       bool vec, Gate g) {
+__global__ __launch_bounds__(kThreads) void k_sumsq(int64_t n, const T* x, const T* z, double* part, bool vec,
+                                                    Gate g) {
   if (!gate_open(g)) return;
-  __shared__ double sh[kThreads / 64];
-  const double c = cptr ? csign * cptr[0] : cconst;
+  __shared__ double sh[kThreads / 64 + 2];
   double acc = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < n; e += stride) {
-    double xv[4], yv[4], o[4];
+  DCTK_GRID_LOOP(e, n) {
+    double xv[4];
     ld4(x, e, n, vec, xv);
-    if (y) {
-      ld4(y, e, n, vec, yv);
-      for (int i = 0; i < 4; ++i) o[i] = xv[i] + c * yv[i];
+    if (z) {
+      double zv[4];
+      ld4(z, e, n, vec, zv);
+      for (int i = 0; i < 4; ++i) acc += xv[i] * zv[i];
     } else {
-      for (int i = 0; i < 4; ++i) o[i] = xv[i];
-    }
-    if (out) {
-      st4(out, e, n, vec, o);
-      // use the stored (rounded) values so the norm describes the vector in memory
-      for (int i = 0; i < 4; ++i) o[i] = (double)(T)o[i];
-    }
-    if (act >= 0) {
-      if (z) {
-        double zv[4];
-        ld4(z, e, n, vec, zv);
-        for (int i = 0; i < 4; ++i) acc += o[i] * zv[i];
-      } else {
-        for (int i = 0; i < 4; ++i) acc += o[i] * o[i];
-      }
+      for (int i = 0; i < 4; ++i) acc += xv[i] * xv[i];
     }
   }
-  if (act < 0) return;
-  double bs = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-  if (!arrive_last(ticket)) return;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) v += ((volatile double*)partials)[b];
-  double total = block_sum(v, sh);
-  if (threadIdx.x == 0) apply_action(act, total, dst, st, j);
-  reset_ticket(ticket);
+  const double t = block_sum_all(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// out = in / den[0]
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scale(int64_t n, T* out, const T* in, const double* den,
-                                                    bool vec, Gate g) {
+__global__ __launch_bounds__(kThreads) void k_axpy_sumsq(int64_t n, T* out, const T* x, const T* y,
+                                                         const double* cptr, double csign, double* part, bool vec,
+                                                         Gate g) {
   if (!gate_open(g)) return;
-  const double s = 1.0 / den[0];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < n; e += stride) {
-    double v[4];
-    ld4(in, e, n, vec, v);
-    for (int i = 0; i < 4; ++i) v[i] *= s;
-    st4(out, e, n, vec, v);
+  __shared__ double sh[kThreads / 64 + 2];
+  const double c = csign * cptr[0];
+  double acc = 0.0;
+  DCTK_GRID_LOOP(e, n) {
+    double xv[4], yv[4];
+    ld4(x, e, n, vec, xv);
+    ld4(y, e, n, vec, yv);
+    for (int i = 0; i < 4; ++i) xv[i] = (double)(T)(xv[i] + c * yv[i]);
+    st4(out, e, n, vec, xv);
+    for (int i = 0; i < 4; ++i) acc += xv[i] * xv[i];
+  }
+  if (part) {
+    const double t = block_sum_all(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
   }
 }
 
-// coef_i = <basis_i, w>, i < nb.  Partials laid out [value][block].
+// partials of <basis_i, w> for i < nb: part[i * gridDim.x + block]
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_multidot(int64_t n, const T* basis, int64_t bstride, int nb,
-                                                       const T* w, double* dst, int dst_stride,
-                                                       int accumulate, double* coef_copy, double* partials,
-                                                       unsigned* ticket, bool vec, Gate g) {
+                                                       const T* w, double* part, bool vec, Gate g) {
   if (!gate_open(g)) return;
-  __shared__ double sh[kThreads / 64];
-  __shared__ double blk[kRedVals];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+  __shared__ double sh[kThreads / 64 + 2];
   for (int i0 = 0; i0 < nb; i0 += 8) {
     double acc[8];
     for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-    for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < n; e += stride) {
+    DCTK_GRID_LOOP(e, n) {
       double wv[4];
       ld4(w, e, n, vec, wv);
       for (int u = 0; u < 8 && i0 + u < nb; ++u) {
@@ -232,38 +123,37 @@ __global__ __launch_bounds__(kThreads) void k_multidot(int64_t n, const T* basis
       }
     }
     for (int u = 0; u < 8 && i0 + u < nb; ++u) {
-      double bs = block_sum(acc[u], sh);
-      if (threadIdx.x == 0) blk[i0 + u] = bs;
+      const double t = block_sum_all(acc[u], sh);
+      if (threadIdx.x == 0) part[(int64_t)(i0 + u) * gridDim.x + blockIdx.x] = t;
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) partials[(int64_t)i * gridDim.x + blockIdx.x] = blk[i];
-  if (!arrive_last(ticket)) return;
-  // one wave per value: fixed order over blocks
+}
+
+// one block: coef[i] = sum_b part[i * nblocks + b]; dst[i * dst_stride] += coef[i]
+__global__ __launch_bounds__(kThreads) void k_coef_finalize(const double* part, int nblocks, int nb, double* coef,
+                                                            double* dst, int dst_stride, Gate g) {
+  if (!gate_open(g)) return;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int i = wid; i < nb; i += (int)(blockDim.x >> 6)) {
     double v = 0.0;
-    for (int b = lane; b < (int)gridDim.x; b += 64) v += ((volatile double*)partials)[(int64_t)i * gridDim.x + b];
+    for (int b = lane; b < nblocks; b += 64) v += part[(int64_t)i * nblocks + b];
     v = wave_sum(v);
     if (lane == 0) {
-      if (accumulate) dst[i * dst_stride] += v;
-      else dst[i * dst_stride] = v;
-      if (coef_copy) coef_copy[i] = v;
+      coef[i] = v;
+      if (dst) dst[i * dst_stride] += v;
     }
   }
-  reset_ticket(ticket);
 }
 
-// w -= sum_i coef[i*cstride] basis_i
+// w -= sum_i coef[i] basis_i
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_subtract(int64_t n, T* w, const T* basis, int64_t bstride,
-                                                       int nb, const double* coef, int cstride, bool vec, Gate g) {
+__global__ __launch_bounds__(kThreads) void k_subtract(int64_t n, T* w, const T* basis, int64_t bstride, int nb,
+                                                       const double* coef, bool vec, Gate g) {
   if (!gate_open(g)) return;
   __shared__ double sc[kRedVals];
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) sc[i] = coef[i * cstride];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) sc[i] = coef[i];
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < n; e += stride) {
+  DCTK_GRID_LOOP(e, n) {
     double wv[4];
     ld4(w, e, n, vec, wv);
     for (int i = 0; i < nb; ++i) {
@@ -275,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_subtract(int64_t n, T* w, const T*
   }
 }
 
-// out = x0 + sum_{i < nb} y[i] basis_i   (nb from *nptr when given)
+// out = x0 + sum_{i < cnt} y[i] basis_i
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_combine(int64_t n, T* out, const T* x0, const T* basis,
                                                       int64_t bstride, int nb, const int* nptr, const double* y,
@@ -287,8 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(int64_t n, T* out, const T
   if (cnt < 0) cnt = 0;
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) sy[i] = y[i];
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < n; e += stride) {
+  DCTK_GRID_LOOP(e, n) {
     double o[4] = {0.0, 0.0, 0.0, 0.0};
     if (x0) ld4(x0, e, n, vec, o);
     for (int i = 0; i < cnt; ++i) {
@@ -300,70 +189,37 @@ __global__ __launch_bounds__(kThreads) void k_combine(int64_t n, T* out, const T
   }
 }
 
-// Algorithm 6 steps (c)-(e) and (g) for step j: one thread.
-__global__ void k_lsqr_scalars(KState* st, int j) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int ss = st->stop_step;
-  if (ss >= 0 && ss < j) return;
-  const bool beta_break = (ss == j && st->stop_kind == STOP_BETA);
-  const double bnext = st->beta[j];
-  const double anext = beta_break ? 0.0 : st->alpha[j];
-  const double rhobar = st->rhobar, phibar = st->phibar;
-  const double rho = sqrt(rhobar * rhobar + bnext * bnext);
-  const double c = rhobar / rho, s = bnext / rho;
-  const double theta = s * anext;
-  st->rhobar = c * anext;
-  const double phi = c * phibar;
-  st->phibar = -s * phibar;
-  st->cx = phi / rho;
-  st->cw = theta / rho;
-  if (ss < 0 && fabs(st->phibar) < st->tol) {
-    st->stop_step = j;
-    st->stop_kind = STOP_CONV;
-    st->converged = 1;
-  }
-}
-
-// Algorithm 6 step (f) for step j, with V_{j+1} = V~ / alpha_{j+1} done in place.
+// ---- Golub-Kahan / LSQR ----------------------------------------------------------
+// Algorithm 6 step 2 after M*(U_1): alpha_1 from the partials; V_1 = V~/alpha_1
+// in place; W_1 = V_1; X_0 = 0.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_lsqr_update(int64_t n, T* X, T* W, T* Vn, KState* st, int j, bool vec) {
-  const int ss = st->stop_step;
-  if (ss >= 0 && ss < j) return;
-  const int kind = (ss == j) ? st->stop_kind : STOP_NONE;
-  const bool have_v = (kind == STOP_NONE || kind == STOP_CONV);
-  const double cx = st->cx, cw = st->cw;
-  const double ia = have_v ? 1.0 / st->alpha[j] : 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < n; e += stride) {
-    double xv[4], wv[4];
-    ld4(X, e, n, vec, xv);
-    ld4(W, e, n, vec, wv);
-    for (int u = 0; u < 4; ++u) xv[u] += cx * wv[u];
-    st4(X, e, n, vec, xv);
-    if (have_v) {
-      double vv[4];
-      ld4(Vn, e, n, vec, vv);
-      for (int u = 0; u < 4; ++u) {
-        vv[u] *= ia;
-        vv[u] = (double)(T)vv[u];
-        wv[u] = vv[u] - cw * wv[u];
+__global__ __launch_bounds__(kThreads) void k_gkb_start(int64_t n, T* X, T* W, T* V1, const double* part, int npart,
+                                                        KState* st, bool vec) {
+  __shared__ double sh[kThreads / 64 + 2];
+  const bool ok = ((volatile KState*)st)->stop_step < 0;
+  bool brk = true;
+  double alpha = 0.0;
+  if (ok) {
+    alpha = sqrt(block_sum_partials(part, npart, sh));
+    const double scale = fmax(st->beta[0], alpha);
+    const bool fin = isfinite(alpha);
+    brk = !fin || alpha <= kBreakFactor * DBL_EPSILON * scale;
+    if (first_thread()) {
+      st->alpha[0] = alpha;
+      st->rhobar[0] = alpha;
+      st->phibar[0] = st->beta[0];
+      if (brk) {
+        st->stop_step = 0;
+        st->stop_kind = STOP_ALPHA;
+        st->status = fin ? DCTK_BREAKDOWN : DCTK_ENONFINITE;
       }
-      st4(Vn, e, n, vec, vv);
-      st4(W, e, n, vec, wv);
     }
   }
-}
-
-// LSQR start (Algorithm 6 step 2): V_1 = V~/alpha_1 in place, W_1 = V_1, X_0 = 0.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_lsqr_start(int64_t n, T* X, T* W, T* V1, KState* st, bool vec) {
-  const bool ok = st->stop_step < 0;
-  const double ia = ok ? 1.0 / st->alpha[0] : 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < n; e += stride) {
+  const double ia = brk ? 0.0 : 1.0 / alpha;
+  DCTK_GRID_LOOP(e, n) {
     double z[4] = {0.0, 0.0, 0.0, 0.0};
     st4(X, e, n, vec, z);
-    if (ok) {
+    if (!brk) {
       double v[4];
       ld4(V1, e, n, vec, v);
       for (int u = 0; u < 4; ++u) v[u] = (double)(T)(v[u] * ia);
@@ -375,18 +231,186 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_start(int64_t n, T* X, T* W, 
   }
 }
 
+// Algorithm 4 (e)-(f) and Algorithm 6 (c)-(g) for step j: alpha_{j+1} from the
+// partials of V~ (unless beta_{j+1} broke down), the plane rotation, then
+// V_{j+1} = V~/alpha_{j+1} in place, X_j = X_{j-1} + (phi_j/rho_j) W_j,
+// W_{j+1} = V_{j+1} - (theta_{j+1}/rho_j) W_j.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fill_zero(int64_t n, T* x) {
+__global__ __launch_bounds__(kThreads) void k_gkb_update(int64_t n, T* X, T* W, T* Vn, const double* part,
+                                                         int npart, KState* st, int j, bool vec) {
+  __shared__ double sh[kThreads / 64 + 2];
+  // the first elements' loads do not depend on the scalars: issue them before
+  // the (memory-latency bound) prologue
+  const int64_t e_first = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  double xv0[4], wv0[4], vv0[4];
+  ld4(X, e_first, n, vec, xv0);
+  ld4(W, e_first, n, vec, wv0);
+  ld4(Vn, e_first, n, vec, vv0);
+  const volatile KState* vst = st;
+  const int ss = vst->stop_step;
+  if (ss >= 0 && ss < j) return;
+  const bool bbreak = (ss == j && vst->stop_kind == STOP_BETA);
+  double alpha = 0.0;
+  bool abreak = false, fin = true;
+  if (!bbreak) {
+    alpha = sqrt(block_sum_partials(part, npart, sh));
+    const double scale = fmax(gkb_scale(st, j, j + 1, sh), alpha);
+    fin = isfinite(alpha);
+    abreak = !fin || alpha <= kBreakFactor * DBL_EPSILON * scale;
+  }
+  const double bnext = st->beta[j];
+  const double anext = bbreak ? 0.0 : alpha;
+  const double rhob = st->rhobar[j - 1], phib = st->phibar[j - 1];
+  const double rho = sqrt(rhob * rhob + bnext * bnext);
+  const double c = rhob / rho, s = bnext / rho;
+  const double theta = s * anext;
+  const double phi = c * phib;
+  const double phibar_new = -s * phib;
+  const double cx = phi / rho, cw = theta / rho;
+  const bool conv = !bbreak && !abreak && fabs(phibar_new) < st->tol;
+  if (first_thread()) {
+    if (!bbreak) {
+      st->alpha[j] = alpha;
+      st->steps = j;
+    }
+    st->rhobar[j] = c * anext;
+    st->phibar[j] = phibar_new;
+    if (abreak) {
+      st->stop_step = j;
+      st->stop_kind = STOP_ALPHA;
+      st->status = fin ? DCTK_BREAKDOWN : DCTK_ENONFINITE;
+    } else if (conv) {
+      st->stop_step = j;
+      st->stop_kind = STOP_CONV;
+      st->converged = 1;
+    }
+  }
+  const bool have_v = !bbreak && !abreak;
+  const double ia = have_v ? 1.0 / alpha : 0.0;
+  DCTK_GRID_LOOP(e, n) {
+    double xv[4], wv[4], vv[4];
+    if (e == e_first) {
+      for (int u = 0; u < 4; ++u) { xv[u] = xv0[u]; wv[u] = wv0[u]; vv[u] = vv0[u]; }
+    } else {
+      ld4(X, e, n, vec, xv);
+      ld4(W, e, n, vec, wv);
+      ld4(Vn, e, n, vec, vv);
+    }
+    for (int u = 0; u < 4; ++u) xv[u] += cx * wv[u];
+    st4(X, e, n, vec, xv);
+    if (have_v) {
+      for (int u = 0; u < 4; ++u) {
+        vv[u] = (double)(T)(vv[u] * ia);
+        wv[u] = vv[u] - cw * wv[u];
+      }
+      st4(Vn, e, n, vec, vv);
+      st4(W, e, n, vec, wv);
+    }
+  }
+}
+
+// ---- Arnoldi / GMRES -----------------------------------------------------------
+// cycle start: beta = ||R|| from the partials; V_1 = R / beta
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_arn_start(int64_t n, T* out, const T* in, const double* part, int npart,
+                                                        KState* st, bool vec) {
+  if (((volatile KState*)st)->halt) return;
+  __shared__ double sh[kThreads / 64 + 2];
+  const double beta = sqrt(block_sum_partials(part, npart, sh));
+  const bool fin = isfinite(beta);
+  const bool ok = fin && beta > 0.0;
+  if (first_thread()) {
+    st->beta0 = beta;
+    st->steps = 0;
+    if (!ok) {
+      st->halt = 1;
+      if (!fin) st->status = DCTK_ENONFINITE;
+    }
+  }
+  if (!ok) return;
+  const double ib = 1.0 / beta;
+  DCTK_GRID_LOOP(e, n) {
+    double v[4];
+    ld4(in, e, n, vec, v);
+    for (int u = 0; u < 4; ++u) v[u] *= ib;
+    st4(out, e, n, vec, v);
+  }
+}
+
+// One modified Gram-Schmidt pass of Algorithm 2 step 3(b) for step j: when
+// part_in is given, h = sum(part_in) is recorded at hdst and w -= h vprev;
+// then the partials of <vi, w> (vi null: of <w, w>) go to part_out.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_mgs(int64_t n, T* w, const T* vprev, const T* vi, const double* part_in,
+                                                  int npart_in, double* hdst, double* part_out, bool vec, Gate g) {
+  if (!gate_open(g)) return;
+  __shared__ double sh[kThreads / 64 + 2];
+  double h = 0.0;
+  if (part_in) {
+    h = block_sum_partials(part_in, npart_in, sh);
+    if (first_thread()) hdst[0] = h;
+  }
+  double acc = 0.0;
+  DCTK_GRID_LOOP(e, n) {
+    double wv[4];
+    ld4(w, e, n, vec, wv);
+    if (part_in) {
+      double pv[4];
+      ld4(vprev, e, n, vec, pv);
+      for (int u = 0; u < 4; ++u) wv[u] = (double)(T)(wv[u] - h * pv[u]);
+      st4(w, e, n, vec, wv);
+    }
+    if (vi) {
+      double v[4];
+      ld4(vi, e, n, vec, v);
+      for (int u = 0; u < 4; ++u) acc += v[u] * wv[u];
+    } else {
+      for (int u = 0; u < 4; ++u) acc += wv[u] * wv[u];
+    }
+  }
+  const double t = block_sum_all(acc, sh);
+  if (threadIdx.x == 0) part_out[blockIdx.x] = t;
+}
+
+// one block: h_{j,j-1} from the partials (breakdown test) -- the prologue of the
+// next Arnoldi product, for the last step of a cycle
+__global__ __launch_bounds__(kThreads) void k_arn_finish(Ctl c) {
+  __shared__ double sh[kThreads / 64 + 2];
+  double a, b, s;
+  (void)ctl_begin(c, a, b, s, sh);
+}
+
+// one block: ||C - M(X)|| from the partials; cycle bookkeeping; convergence
+__global__ __launch_bounds__(kThreads) void k_gmres_res(const double* part, int npart, KState* st) {
+  if (((volatile KState*)st)->halt) return;
+  __shared__ double sh[kThreads / 64 + 2];
+  const double r = sqrt(block_sum_partials(part, npart, sh));
+  if (threadIdx.x == 0) {
+    st->resnorm = r;
+    st->cycles += 1;
+    st->total_steps += st->steps;
+    if (!isfinite(r)) {
+      st->status = DCTK_ENONFINITE;
+      st->halt = 1;
+    } else if (r < st->tol) {
+      st->converged = 1;
+      st->halt = 1;
+    }
+  }
+}
+
+template <typename TO>
+__global__ __launch_bounds__(kThreads) void k_cast(int64_t n, const double* in, TO* out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) x[e] = (T)0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) out[e] = cvt<TO, double>(in[e]);
 }
 
 // full = 1: clear everything (new solve); full = 0: start a new GMRES cycle (unless halted)
 __global__ void k_state_reset(KState* st, int full, double tol) {
-  if (full == 0 && st->halt) return;
-  double* d = reinterpret_cast<double*>(st);
-  const int nd = (int)(sizeof(KState) / sizeof(double));
+  if (full == 0 && ((volatile KState*)st)->halt) return;
   if (full) {
+    double* d = reinterpret_cast<double*>(st);
+    const int nd = (int)(sizeof(KState) / sizeof(double));
     for (int i = threadIdx.x; i < nd; i += blockDim.x) d[i] = 0.0;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -402,15 +426,8 @@ __global__ void k_state_reset(KState* st, int full, double tol) {
       st->steps = 0;
       st->stop_step = -1;
       st->stop_kind = STOP_NONE;
-      st->scale = 0.0;
     }
   }
-}
-
-template <typename TO>
-__global__ __launch_bounds__(kThreads) void k_cast(int64_t n, const double* in, TO* out) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) out[e] = cvt<TO, double>(in[e]);
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -420,70 +437,77 @@ static inline unsigned grid_for(int64_t n) {
   if (b < 1) b = 1;
   return (unsigned)b;
 }
-static inline bool aligned32(const void* p) { return p == nullptr || ((uintptr_t)p % 32) == 0; }
+static inline bool al(const void* p) { return p == nullptr || ((uintptr_t)p % 32) == 0; }
 
-hipError_t launch_axpy_red(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x, const void* y,
-                           const double* cptr, double csign, double cconst, const void* z, int act,
-                           double* dst, KState* st, int j, Gate g) {
-  unsigned grid = grid_for(n);
-  bool vec = (n % 4 == 0) && aligned32(out) && aligned32(x) && aligned32(y) && aligned32(z);
+hipError_t launch_sumsq(dctk_ctx ctx, int dtype, int64_t n, const void* x, const void* z, double* part, int* nblocks,
+                        Gate g) {
+  const unsigned grid = grid_for(n);
+  if (nblocks) *nblocks = (int)grid;
+  const bool vec = (n % 4 == 0) && al(x) && al(z);
   if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_axpy_red<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)out,
-                       (const double*)x, (const double*)y, cptr, csign, cconst, (const double*)z, act, dst, st, j,
-                       ctx->red_partials, ctx->red_tickets, vec, g);
+    hipLaunchKernelGGL(k_sumsq<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (const double*)x,
+                       (const double*)z, part, vec, g);
   else
-    hipLaunchKernelGGL(k_axpy_red<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)out,
-                       (const float*)x, (const float*)y, cptr, csign, cconst, (const float*)z, act, dst, st, j,
-                       ctx->red_partials, ctx->red_tickets, vec, g);
+    hipLaunchKernelGGL(k_sumsq<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (const float*)x,
+                       (const float*)z, part, vec, g);
   return hipGetLastError();
 }
 
-hipError_t launch_scale(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* in, const double* den, Gate g) {
-  unsigned grid = grid_for(n);
-  bool vec = (n % 4 == 0) && aligned32(out) && aligned32(in);
+hipError_t launch_axpy_sumsq(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x, const void* y,
+                             const double* cptr, double csign, double* part, int* nblocks, Gate g) {
+  const unsigned grid = grid_for(n);
+  if (nblocks) *nblocks = (int)grid;
+  const bool vec = (n % 4 == 0) && al(out) && al(x) && al(y);
   if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_scale<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)out,
-                       (const double*)in, den, vec, g);
+    hipLaunchKernelGGL(k_axpy_sumsq<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)out,
+                       (const double*)x, (const double*)y, cptr, csign, part, vec, g);
   else
-    hipLaunchKernelGGL(k_scale<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)out,
-                       (const float*)in, den, vec, g);
+    hipLaunchKernelGGL(k_axpy_sumsq<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)out,
+                       (const float*)x, (const float*)y, cptr, csign, part, vec, g);
   return hipGetLastError();
 }
 
 hipError_t launch_multidot(dctk_ctx ctx, int dtype, int64_t n, const void* basis, int64_t stride, int nb,
-                           const void* w, double* dst, int dst_stride, int accumulate, double* coef_copy, Gate g) {
+                           const void* w, double* part, int* nblocks, Gate g) {
+  const unsigned grid = grid_for(n);
+  if (nblocks) *nblocks = (int)grid;
   if (nb <= 0) return hipSuccess;
-  unsigned grid = grid_for(n);
-  bool vec = (n % 4 == 0) && (stride % 4 == 0) && aligned32(basis) && aligned32(w);
+  const bool vec = (n % 4 == 0) && (stride % 4 == 0) && al(basis) && al(w);
   if (dtype == DCTK_F64)
     hipLaunchKernelGGL(k_multidot<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (const double*)basis,
-                       stride, nb, (const double*)w, dst, dst_stride, accumulate, coef_copy, ctx->red_partials,
-                       ctx->red_tickets, vec, g);
+                       stride, nb, (const double*)w, part, vec, g);
   else
     hipLaunchKernelGGL(k_multidot<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (const float*)basis,
-                       stride, nb, (const float*)w, dst, dst_stride, accumulate, coef_copy, ctx->red_partials,
-                       ctx->red_tickets, vec, g);
+                       stride, nb, (const float*)w, part, vec, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_finalize(dctk_ctx ctx, const double* part, int nblocks, int nb, double* coef, double* dst,
+                                int dst_stride, Gate g) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coef_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, part, nblocks, nb, coef, dst,
+                     dst_stride, g);
   return hipGetLastError();
 }
 
 hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* basis, int64_t stride, int nb,
-                           const double* coef, int cstride, Gate g) {
+                           const double* coef, Gate g) {
   if (nb <= 0) return hipSuccess;
-  unsigned grid = grid_for(n);
-  bool vec = (n % 4 == 0) && (stride % 4 == 0) && aligned32(basis) && aligned32(w);
+  const unsigned grid = grid_for(n);
+  const bool vec = (n % 4 == 0) && (stride % 4 == 0) && al(basis) && al(w);
   if (dtype == DCTK_F64)
     hipLaunchKernelGGL(k_subtract<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)w,
-                       (const double*)basis, stride, nb, coef, cstride, vec, g);
+                       (const double*)basis, stride, nb, coef, vec, g);
   else
     hipLaunchKernelGGL(k_subtract<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)w,
-                       (const float*)basis, stride, nb, coef, cstride, vec, g);
+                       (const float*)basis, stride, nb, coef, vec, g);
   return hipGetLastError();
 }
 
 hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x0, const void* basis,
                           int64_t stride, int nb, const int* nptr, const double* y, Gate g) {
-  unsigned grid = grid_for(n);
-  bool vec = (n % 4 == 0) && (stride % 4 == 0) && aligned32(out) && aligned32(x0) && aligned32(basis);
+  const unsigned grid = grid_for(n);
+  const bool vec = (n % 4 == 0) && (stride % 4 == 0) && al(out) && al(x0) && al(basis);
   if (dtype == DCTK_F64)
     hipLaunchKernelGGL(k_combine<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)out,
                        (const double*)x0, (const double*)basis, stride, nb, nptr, y, vec, g);
@@ -493,41 +517,74 @@ hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const v
   return hipGetLastError();
 }
 
-hipError_t launch_lsqr_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* Vn, KState* st, int j) {
-  unsigned grid = grid_for(n);
-  bool vec = (n % 4 == 0) && aligned32(X) && aligned32(W) && aligned32(Vn);
+hipError_t launch_arn_start(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* in, const double* part,
+                            int npart, KState* st) {
+  const unsigned grid = grid_for(n);
+  const bool vec = (n % 4 == 0) && al(out) && al(in);
   if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_lsqr_update<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)X, (double*)W,
-                       (double*)Vn, st, j, vec);
+    hipLaunchKernelGGL(k_arn_start<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)out,
+                       (const double*)in, part, npart, st, vec);
   else
-    hipLaunchKernelGGL(k_lsqr_update<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)X, (float*)W,
-                       (float*)Vn, st, j, vec);
+    hipLaunchKernelGGL(k_arn_start<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)out,
+                       (const float*)in, part, npart, st, vec);
   return hipGetLastError();
 }
 
-hipError_t launch_lsqr_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* V1, KState* st) {
-  unsigned grid = grid_for(n);
-  bool vec = (n % 4 == 0) && aligned32(X) && aligned32(W) && aligned32(V1);
+hipError_t launch_mgs(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* vprev, const void* vi,
+                      const double* part_in, int npart_in, double* hdst, double* part_out, int* nblocks, KState* st,
+                      int j) {
+  const unsigned grid = grid_for(n);
+  if (nblocks) *nblocks = (int)grid;
+  const bool vec = (n % 4 == 0) && al(w) && al(vprev) && al(vi);
+  const Gate g{st, j - 1, 1};  // runs when the product of step j ran
   if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_lsqr_start<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)X, (double*)W,
-                       (double*)V1, st, vec);
+    hipLaunchKernelGGL(k_mgs<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)w,
+                       (const double*)vprev, (const double*)vi, part_in, npart_in, hdst, part_out, vec, g);
   else
-    hipLaunchKernelGGL(k_lsqr_start<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)X, (float*)W,
-                       (float*)V1, st, vec);
+    hipLaunchKernelGGL(k_mgs<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)w,
+                       (const float*)vprev, (const float*)vi, part_in, npart_in, hdst, part_out, vec, g);
   return hipGetLastError();
 }
 
-hipError_t launch_lsqr_scalars(dctk_ctx ctx, KState* st, int j) {
-  hipLaunchKernelGGL(k_lsqr_scalars, dim3(1), dim3(64), 0, ctx->stream, st, j);
+hipError_t launch_arn_finish(dctk_ctx ctx, const double* part, int npart, KState* st, int j) {
+  Ctl c{};
+  c.kind = CTL_ARN_FWD;
+  c.j = j;
+  c.st = st;
+  c.part_in = part;
+  c.npart_in = npart;
+  hipLaunchKernelGGL(k_arn_finish, dim3(1), dim3(kThreads), 0, ctx->stream, c);
   return hipGetLastError();
 }
 
-hipError_t launch_fill_zero(dctk_ctx ctx, int dtype, int64_t n, void* x) {
-  unsigned grid = grid_for(n * 4 > n ? n : n);
+hipError_t launch_gmres_res(dctk_ctx ctx, const double* part, int npart, KState* st) {
+  hipLaunchKernelGGL(k_gmres_res, dim3(1), dim3(kThreads), 0, ctx->stream, part, npart, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_gkb_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* V1, const double* part,
+                            int npart, KState* st) {
+  const unsigned grid = grid_for(n);
+  const bool vec = (n % 4 == 0) && al(X) && al(W) && al(V1);
   if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_fill_zero<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)x);
+    hipLaunchKernelGGL(k_gkb_start<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)X, (double*)W,
+                       (double*)V1, part, npart, st, vec);
   else
-    hipLaunchKernelGGL(k_fill_zero<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)x);
+    hipLaunchKernelGGL(k_gkb_start<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)X, (float*)W,
+                       (float*)V1, part, npart, st, vec);
+  return hipGetLastError();
+}
+
+hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* Vn, const double* part,
+                             int npart, KState* st, int j) {
+  const unsigned grid = grid_for(n);
+  const bool vec = (n % 4 == 0) && al(X) && al(W) && al(Vn);
+  if (dtype == DCTK_F64)
+    hipLaunchKernelGGL(k_gkb_update<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)X, (double*)W,
+                       (double*)Vn, part, npart, st, j, vec);
+  else
+    hipLaunchKernelGGL(k_gkb_update<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)X, (float*)W,
+                       (float*)Vn, part, npart, st, j, vec);
   return hipGetLastError();
 }
 
