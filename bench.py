@@ -9,13 +9,14 @@ X = V_k (*) y -- every stage of the hot path, inputs resident in HBM.
 Printed JSON line (rank 0):
   value        solves/s, counted only if the restoration error of the solve
                is within 1.05x of the FP64 oracle's on the same input
-  roofline     the dominant kernel (slice GEMMs of the c-product) timed live
-               with HIP events around each launch, against the FP32 MFMA peak
+  roofline     the dominant kernel (the fused c-product with the largest total
+               time) timed live with HIP events around each launch; bound by
+               MFMA or HBM according to its arithmetic intensity
   cpu_baseline the FP64 oracle timed on the host cores on a bounded sample
   cprod        one c-product: time, algorithmic GB/s and MFMA fraction
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--gemm f32|bf16|f16]
-                       [--no-cpu-baseline]
+                       [--no-cpu-baseline] [--cprod-reps R] [--copy-calib-mib M]
 """
 import argparse
 import json
@@ -31,6 +32,25 @@ if ROOT not in sys.path:
 
 METRIC = "LSQR solves/s at ≤1.05× FP64-oracle error; c-product GB/s & MFMA util"
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the fused products at this workload (FP32 GEMMs), from
+# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy read
+# in the same runs.  They describe the kernel sources with this digest only.
+TRAFFIC_SOURCES = ("paper_2103_11847_amd/csrc/fused.hip", "paper_2103_11847_amd/csrc/mfma.h",
+                   "paper_2103_11847_amd/csrc/internal.h")
+TRAFFIC = {"digest": "55480a57c0a79568", "gemm": "f32",
+           "bytes": {"fused_fwd": 6526694, "fused_adj": 7333451}}
+
+
+def measured_traffic(kind, gemm):
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != TRAFFIC["digest"] or gemm != TRAFFIC["gemm"]:
+        return None
+    return TRAFFIC["bytes"].get(kind)
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "f64": 78.6}
 
 
@@ -42,7 +62,22 @@ def parse():
     ap.add_argument("--gemm", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cprod-reps", type=int, default=200,
+                    help="standalone c-product launches timed after the solves (0: none)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run 3 plain device copies of this many MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def blas_threads():
+    try:
+        import threadpoolctl
+        n = [d.get("num_threads", 0) for d in threadpoolctl.threadpool_info() if d.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
 
 
 def oracle_leg(w, C_ref_builder, budget_s):
@@ -115,41 +150,72 @@ def main():
     Xn = X.double().cpu().numpy()
     err_gpu = float(np.linalg.norm((Xn - w["X_true"]).ravel()) / np.linalg.norm(w["X_true"].ravel()))
 
-    # dominant kernel, timed live with HIP events around every launch inside solves
+    # dominant kernel, timed live with HIP events (on the library's stream) around every
+    # c-product launch inside the solves
     prof_steps = max(3, min(10, args.steps))
     dk.dctk_profile_begin(ctx)
     for _ in range(prof_steps):
         dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
     prof = dk.dctk_profile_end(ctx)
-    gemm_ms, gemm_n = prof["gemm"]
-    gemm_us = gemm_ms * 1e3 / max(1, gemm_n)
-    flops = 2.0 * n * n * s * p  # one batch of p slice GEMMs
-    peak = MFMA_PEAK_TFLOPS[args.gemm]
-    achieved = flops / (gemm_us * 1e-6) / 1e12
-    tube_ms = prof["tube_fwd"][0] + prof["tube_inv"][0]
-    tube_n = prof["tube_fwd"][1] + prof["tube_inv"][1]
+    kind = max(("fused_fwd", "fused_adj", "gemm"), key=lambda k_: prof[k_][0])
+    k_ms, k_n = prof[kind]
+    k_us = k_ms * 1e3 / max(1, k_n)
+    flops = 2.0 * n * n * s * p  # the p slice GEMMs of one product (dense-equivalent)
+    bg = 4 if args.gemm == "f32" else 2
+    N = p * n * s
+    # algorithmic bytes of one launch inside a GKB step: A~ once, the input, the epilogue's
+    # src (alpha U_j or beta V_j) and the output; the adjoint also writes U_{j+1} = U~/beta
+    nvec_io = {"fused_fwd": 3, "fused_adj": 4, "gemm": 2}[kind]
+    kbytes = p * n * n * bg + nvec_io * N * 4
+    peak_f = MFMA_PEAK_TFLOPS[args.gemm]
+    ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
+    ai = flops / kbytes
+    if ai >= ridge:
+        roof = {"bound": "mfma", "achieved": flops / (k_us * 1e-6) / 1e12, "peak": peak_f, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": kbytes / (k_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(kind, args.gemm)
+    roof.update({"kernel": {"fused_fwd": "fused c-product M(X) (transform + p slice MFMA GEMMs + inverse)",
+                            "fused_adj": "fused adjoint c-product M*(Y)",
+                            "gemm": "slice GEMM batch"}[kind],
+                 "avg_us": k_us, "launches": k_n, "flops_per_launch": flops, "bytes_per_launch": kbytes,
+                 "arith_intensity": ai,
+                 "per_kind_avg_us": {k_: (v[0] * 1e3 / v[1] if v[1] else None) for k_, v in prof.items()}})
 
-    # one c-product, standalone (transform + GEMM + transform)
-    Y = torch.empty_like(C)
-    for _ in range(5):
-        dk.dctk_cprod(ctx, op, 1.0, C, 0.0, Y)
-    torch.cuda.synchronize()
-    reps = 200
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(reps):
-        dk.dctk_cprod(ctx, op, 1.0, C, 0.0, Y)
-    ev1.record()
-    torch.cuda.synchronize()
-    cprod_us = ev0.elapsed_time(ev1) * 1e3 / reps
-    gb = (p * n * n * (2 if args.gemm != "f32" else 4) + 2 * p * n * s * 4) / 1e9
+    # one c-product, standalone, on the library's stream (the context uses the null stream)
+    cprod = None
+    if args.cprod_reps > 0:
+        Y = torch.empty_like(C)
+        for _ in range(5):
+            dk.dctk_cprod(ctx, op, 1.0, C, 0.0, Y)
+        torch.cuda.synchronize()
+        reps = args.cprod_reps
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            dk.dctk_cprod(ctx, op, 1.0, C, 0.0, Y)
+        ev1.record()
+        torch.cuda.synchronize()
+        cprod_us = ev0.elapsed_time(ev1) * 1e3 / reps
+        gb = (p * n * n * bg + 2 * N * 4) / 1e9
+        cprod = {"us": cprod_us, "GB_per_s": gb / (cprod_us * 1e-6), "hbm_frac": gb / (cprod_us * 1e-6) / HBM_PEAK_GBS,
+                 "mfma_frac": flops / (cprod_us * 1e-6) / 1e12 / peak_f, "cprods_per_s": 1e6 / cprod_us}
+    if args.copy_calib_mib > 0:
+        nel = args.copy_calib_mib * (1 << 20) // 4
+        src_b = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst_b = torch.empty_like(src_b)
+        for _ in range(3):
+            dst_b.copy_(src_b)
+        torch.cuda.synchronize()
+        del src_b, dst_b
 
     cpu = None
     err_oracle = None
     lam_oracle = None
     if not args.no_cpu_baseline:
         err_oracle, lam_oracle, cps, nsolve, dt = oracle_leg(w, None, args.cpu_seconds)
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        threads = blas_threads()
         cpu = {"value": cps, "unit": "solves/s", "cores": threads, "kind": "oracle",
                "sample": "%d full FP64 DC-GK solves (40 GKB steps + GCV) of the same 256x256x3 workload "
                          "in %.1f s (numpy, BLAS matmul)" % (nsolve, dt)}
@@ -173,19 +239,13 @@ def main():
         "config": {"workload": "colour deblur 256x256x3, DC-LSQR/DC-GK 40 GKB steps + FP64 GCV, one solve per step",
                    "n1": n, "n2": n, "s": s, "n3": p, "gkb_steps": k, "gemm_dtype": args.gemm,
                    "vector_dtype": "f32", "reorth": "none", "tube": "th"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "slice GEMM batch (p=3 of 256x256x256)", "avg_us": gemm_us,
-                     "launches": gemm_n},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "restoration": {"relerr_gpu": err_gpu, "relerr_oracle_fp64": err_oracle,
                         "ratio": (err_gpu / err_oracle) if err_oracle else None, "gate_1_05": gate_ok,
                         "lambda_gpu": info.lam, "lambda_oracle": lam_oracle, "iters": info.iters,
                         "jacobi_sweeps": kr["sweeps"]},
-        "cprod": {"us": cprod_us, "GB_per_s": gb / (cprod_us * 1e-6),
-                  "hbm_frac": gb / (cprod_us * 1e-6) / HBM_PEAK_GBS,
-                  "mfma_frac": flops / (cprod_us * 1e-6) / 1e12 / peak},
-        "tube_avg_us": tube_ms * 1e3 / max(1, tube_n),
+        "cprod": cprod,
     }
     dk.dctk_krylov_destroy(ws)
     dk.dctk_op_destroy(op)

@@ -94,12 +94,17 @@ int dctk_last_hip_error(dctk_ctx ctx);
 int dctk_version(void);
 
 /* Kernel timing.  Between dctk_profile_begin and dctk_profile_end the
- * library brackets every tube-transform and slice-GEMM launch it enqueues
- * for this context with HIP events on the context's stream.
- * dctk_profile_end synchronises and writes, for kind 0 (forward tube
- * transform), 1 (slice GEMMs of one product) and 2 (inverse tube transform
- * with epilogue), the summed device time in ms to ms[3] and the launch count
- * to count[3] (either may be NULL).  Error: DCTK_ESTATE if not profiling. */
+ * library times every c-product launch it enqueues for this context with
+ * HIP events on the context's stream (a fused product's events are recorded
+ * by its own dispatch, so they time the kernel alone; the unfused kinds are
+ * bracketed by separate event records).  dctk_profile_end synchronises and
+ * writes, per kind, the summed device time in ms to ms[DCTK_PROF_KINDS] and
+ * the launch count to count[DCTK_PROF_KINDS] (either may be NULL).  Kinds:
+ * 0 forward tube transform, 1 slice GEMMs of one product, 2 inverse tube
+ * transform with epilogue (these three make up an unfused product), 3 one
+ * fused forward product M(X), 4 one fused adjoint product M*(Y).
+ * Error: DCTK_ESTATE if not profiling. */
+#define DCTK_PROF_KINDS 5
 int dctk_profile_begin(dctk_ctx ctx);
 int dctk_profile_end(dctk_ctx ctx, double* ms, int* count);
 

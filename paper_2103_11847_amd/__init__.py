@@ -178,16 +178,19 @@ def dctk_last_hip_error(ctx):
     return lib().dctk_last_hip_error(ctx)
 
 
+PROF_KINDS = ("tube_fwd", "gemm", "tube_inv", "fused_fwd", "fused_adj")
+
+
 def dctk_profile_begin(ctx):
     return _check(lib().dctk_profile_begin(ctx), "dctk_profile_begin")
 
 
 def dctk_profile_end(ctx):
-    """Returns {kind: (ms_total, launches)} for kinds 'tube_fwd', 'gemm', 'tube_inv'."""
-    ms = (ctypes.c_double * 3)()
-    cnt = (ctypes.c_int * 3)()
+    """Returns {kind: (ms_total, launches)} for the kinds in PROF_KINDS."""
+    ms = (ctypes.c_double * len(PROF_KINDS))()
+    cnt = (ctypes.c_int * len(PROF_KINDS))()
     _check(lib().dctk_profile_end(ctx, ms, cnt), "dctk_profile_end")
-    return {k: (ms[i], cnt[i]) for i, k in enumerate(("tube_fwd", "gemm", "tube_inv"))}
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(PROF_KINDS)}
 
 
 # ---- tube transforms ----------------------------------------------------------------

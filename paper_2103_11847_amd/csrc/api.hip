@@ -11,6 +11,8 @@
 
 #include "internal.h"
 
+static_assert(dctk::PROF_KINDS == DCTK_PROF_KINDS, "profiler kinds");
+
 using namespace dctk;
 
 namespace dctk {
@@ -42,6 +44,21 @@ void prof_begin(dctk_ctx ctx, int kind) {
   if (hipEventCreate(&ev) != hipSuccess) return;
   (void)hipEventRecord(ev, ctx->stream);
   P->open = ev;
+}
+
+void prof_kernel(dctk_ctx ctx, int kind, hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
+  if (!ctx || !ctx->prof) return;
+  Profiler* P = (Profiler*)ctx->prof;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return;
+  }
+  P->recs.push_back({a, b, kind});
+  *start = a;
+  *stop = b;
 }
 
 void prof_end(dctk_ctx ctx, int kind) {
@@ -143,8 +160,8 @@ int dctk_profile_end(dctk_ctx ctx, double* ms, int* count) {
   Profiler* P = (Profiler*)ctx->prof;
   ctx->prof = nullptr;
   hipError_t e = hipStreamSynchronize(ctx->stream);
-  double acc[PROF_KINDS] = {0.0, 0.0, 0.0};
-  int cnt[PROF_KINDS] = {0, 0, 0};
+  double acc[PROF_KINDS] = {};
+  int cnt[PROF_KINDS] = {};
   for (auto& r : P->recs) {
     float t = 0.0f;
     if (e == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {

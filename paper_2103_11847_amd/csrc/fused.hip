@@ -14,6 +14,8 @@
 // Small problems (fewer 32x32 tiles than CUs) use 16x16 tiles with the 4 waves
 // splitting the contraction (reduced through LDS) so every CU has work;
 // larger ones use 32x32 or 64x64 tiles with 2x2 waves.
+#include <hip/hip_ext.h>
+
 #include "mfma.h"
 
 namespace dctk {
@@ -30,6 +32,23 @@ struct FusedArgs {
   const void* Gout;        // p x p, vector type
   Ctl ctl;
 };
+
+// XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round robin in
+// dispatch order (x fastest), and each XCD has its own L2.  When the grid
+// splits into 2 x 4 equal regions, XCD r is given region r, so an XCD reads
+// half of the A~ rows and a quarter of the X columns instead of all A~ rows;
+// otherwise the hardware order is kept.
+__device__ inline void xcd_tile(int& tx, int& ty) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  tx = blockIdx.x;
+  ty = blockIdx.y;
+  if (gx % 4 != 0 || gy % 2 != 0) return;
+  const int lin = blockIdx.y * gx + blockIdx.x;
+  const int xcd = lin & 7, slot = lin >> 3;
+  const int rw = gx / 4, rh = gy / 2;  // region size in tiles; rw * rh = slots per XCD
+  tx = (xcd & 3) * rw + slot % rw;
+  ty = (xcd >> 2) * rh + slot / rw;
+}
 
 // EXACT: p == PMAX (no slice guards); otherwise p <= PMAX at run time.
 template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA>
@@ -309,10 +328,17 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
   static_assert(FM >= 1 && FN >= 1, "tile");
   static_assert(BM % VW == 0 && BN % VW == 0 && BKT % VW == 0, "vector width");
 
-  // one LDS buffer: the A~ and X~ tiles, reused by the cross-wave reduction
-  __shared__ __attribute__((aligned(16))) T smem[PMAX * BKT * LDM + PMAX * BKT * LDN];
+  // one LDS buffer: the A~ and X~ tiles, reused by the cross-wave reduction.
+  // A~ layout: TA -> [slice][k][m] (rows of A~_k read along m); else
+  // [slice][m][k] with a pad of 16 bytes per row, so that both the 16-byte
+  // row stores and the MFMA operand reads (16 rows x 4 k per instruction)
+  // fall in distinct banks.
+  constexpr int LDK = BKT + 16 / (int)sizeof(T);
+  constexpr int A_LDS = TA ? PMAX * BKT * LDM : PMAX * BM * LDK;
+  constexpr int ASTEP = TA ? 16 : 16 * LDK;  // next 16 output rows
+  __shared__ __attribute__((aligned(16))) T smem[A_LDS + PMAX * BKT * LDN];
   T* const As = smem;
-  T* const Bs = smem + PMAX * BKT * LDM;
+  T* const Bs = smem + A_LDS;
   __shared__ T sGin[PMAX * PMAX], sGout[PMAX * PMAX];
   __shared__ double sh[8];
 
@@ -324,10 +350,12 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
     sGin[i] = ((const T*)fa.Gin)[i];
     sGout[i] = ((const T*)fa.Gout)[i];
   }
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  int tx, ty;
+  xcd_tile(tx, ty);
+  const int m0 = ty * BM, n0 = tx * BN;
   const T* A = (const T*)fa.A;
   const T* X = (const T*)fa.X;
-  T* xnorm = (blockIdx.y == 0) ? (T*)fa.xnorm : nullptr;
+  T* xnorm = (ty == 0) ? (T*)fa.xnorm : nullptr;
 
   const int wk = (WK == 1) ? 0 : wave;
   const int wmn = (WK == 1) ? wave : 0;
@@ -397,12 +425,10 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
         const int k = idx / ((TA ? BKT : BM) * AV_ROW);
         const int rem = idx - k * ((TA ? BKT : BM) * AV_ROW);
         const int row = rem / AV_ROW, cv = (rem - row * AV_ROW) * VW;
-        if (TA) {
+        if (TA)
           VecIO<T, VW>::st(&As[(k * BKT + row) * LDM + cv], ra[u]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < VW; ++v) As[(k * BKT + cv + v) * LDM + row] = ra[u][v];
-        }
+        else
+          VecIO<T, VW>::st(&As[(k * BM + row) * LDK + cv], ra[u]);
       }
     }
 #pragma unroll
@@ -458,12 +484,13 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
 #pragma unroll
       for (int k = 0; k < PMAX; ++k) {
         if (k < p) {
-          const T* arow = &As[(k * BKT + ks + lk) * LDM + wm * WM + lr];
+          const T* arow = TA ? &As[(k * BKT + ks + lk) * LDM + wm * WM + lr]
+                             : &As[(k * BM + wm * WM + lr) * LDK + ks + lk];
           const T* brow = &Bs[(k * BKT + ks + lk) * LDN + wn * WN + lr];
 #pragma unroll
           for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc[k][i][j] = MF::mac(arow + i * 16, brow + j * 16, acc[k][i][j]);
+            for (int j = 0; j < FN; ++j) acc[k][i][j] = MF::mac(arow + i * ASTEP, brow + j * 16, acc[k][i][j]);
         }
       }
     }
@@ -572,14 +599,20 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
   }
 }
 
+// Start/stop events of the launch being enqueued (null unless the context is
+// profiling): the dispatch itself records them, so the measured interval is
+// the kernel's execution, not the queue's.
+static thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
+
 template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK>
 static hipError_t launch_fused_mn_cfg(hipStream_t s, const FusedArgs& fa, int ta, bool vec, int* nblocks_out) {
   dim3 grid((unsigned)((fa.N + BN - 1) / BN), (unsigned)((fa.M + BM - 1) / BM));
   if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
   if ((int64_t)grid.x * grid.y > kRedBlocks && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
   constexpr int VW = 16 / (int)sizeof(T);
-#define DCTK_MN_LAUNCH(TA_, VW_) \
-  hipLaunchKernelGGL((cprod_fused_mn_kernel<T, PMAX, EXACT, BM, BN, WK, BK, TA_, VW_>), grid, dim3(256), 0, s, fa)
+#define DCTK_MN_LAUNCH(TA_, VW_)                                                                         \
+  hipExtLaunchKernelGGL((cprod_fused_mn_kernel<T, PMAX, EXACT, BM, BN, WK, BK, TA_, VW_>), grid, dim3(256), 0, s, \
+                        t_ev0, t_ev1, 0, fa)
   if (ta) {
     if (vec) DCTK_MN_LAUNCH(true, VW); else DCTK_MN_LAUNCH(true, 1);
   } else {
@@ -621,9 +654,11 @@ static hipError_t launch_fused_cfg(hipStream_t s, const FusedArgs& fa, int ta, i
   if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
   if ((int64_t)grid.x * grid.y > kRedBlocks && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
   if (ta)
-    hipLaunchKernelGGL((cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true>), grid, dim3(256), 0, s, fa);
+    hipExtLaunchKernelGGL((cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true>), grid, dim3(256), 0, s,
+                          t_ev0, t_ev1, 0, fa);
   else
-    hipLaunchKernelGGL((cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false>), grid, dim3(256), 0, s, fa);
+    hipExtLaunchKernelGGL((cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false>), grid, dim3(256), 0, s,
+                          t_ev0, t_ev1, 0, fa);
   return hipGetLastError();
 }
 
@@ -677,14 +712,17 @@ hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, v
     fa.Gout = op->Gf + go * pp;
   }
   fa.ctl = ctl;
-  // split-contraction tiles need the whole p x 16 x 16 accumulator set per wave
+  prof_kernel(op->ctx, adjoint ? PROF_FUSED_ADJ : PROF_FUSED_FWD, &t_ev0, &t_ev1);
+  hipError_t e;
   switch (op->gemm_dtype) {
-    case DCTK_F64: return launch_fused_mn<double>(s, fa, adjoint, nblocks_out);
-    case DCTK_F32: return launch_fused_mn<float>(s, fa, adjoint, nblocks_out);
-    case DCTK_BF16: return launch_fused_t<bf16_t, float>(s, fa, adjoint, nblocks_out);
-    case DCTK_F16: return launch_fused_t<f16_t, float>(s, fa, adjoint, nblocks_out);
-    default: return hipErrorInvalidValue;
+    case DCTK_F64: e = launch_fused_mn<double>(s, fa, adjoint, nblocks_out); break;
+    case DCTK_F32: e = launch_fused_mn<float>(s, fa, adjoint, nblocks_out); break;
+    case DCTK_BF16: e = launch_fused_t<bf16_t, float>(s, fa, adjoint, nblocks_out); break;
+    case DCTK_F16: e = launch_fused_t<f16_t, float>(s, fa, adjoint, nblocks_out); break;
+    default: e = hipErrorInvalidValue;
   }
+  t_ev0 = t_ev1 = nullptr;
+  return e;
 }
 
 }  // namespace dctk

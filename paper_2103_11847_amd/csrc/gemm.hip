@@ -209,10 +209,7 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   const int64_t nmax = op->n1 > op->n2 ? op->n1 : op->n2;
   const bool small_offsets = op->p * op->n1 * op->n2 < (int64_t(1) << 31) && op->p * nmax * op->s < (int64_t(1) << 31);
   if (!op->two_sided && op->p <= kFusedMaxP && small_offsets) {
-    prof_begin(ctx, PROF_GEMM);
-    hipError_t e = launch_fused(op, s, adjoint, X, Y, src, xnorm, ctl, nblocks_out);
-    prof_end(ctx, PROF_GEMM);
-    return e;
+    return launch_fused(op, s, adjoint, X, Y, src, xnorm, ctl, nblocks_out);
   }
   const int64_t p = op->p, n1 = op->n1, n2 = op->n2, sc = op->s;
   const int gdt = op->gemm_dtype, vdt = op->vec_dtype;

@@ -319,9 +319,20 @@ struct dctk_krylov_s {
 namespace dctk {
 
 // ---- profiling: HIP events around transform / GEMM launches -----------------
-enum ProfKind : int { PROF_TUBE_FWD = 0, PROF_GEMM = 1, PROF_TUBE_INV = 2, PROF_KINDS = 3 };
+enum ProfKind : int {
+  PROF_TUBE_FWD = 0,
+  PROF_GEMM = 1,
+  PROF_TUBE_INV = 2,
+  PROF_FUSED_FWD = 3,
+  PROF_FUSED_ADJ = 4,
+  PROF_KINDS = 5
+};
 void prof_begin(dctk_ctx ctx, int kind);  // no-ops unless profiling
 void prof_end(dctk_ctx ctx, int kind);
+// While profiling: creates a start/stop event pair for one kernel launch that
+// records them itself (hipExtLaunchKernel) and registers it under kind; else
+// sets both to null.
+void prof_kernel(dctk_ctx ctx, int kind, hipEvent_t* start, hipEvent_t* stop);
 
 // error plumbing
 int hip_fail(dctk_ctx ctx, hipError_t e);
