@@ -66,6 +66,9 @@ def parse():
                     help="standalone c-product launches timed after the solves (0: none)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run 3 plain device copies of this many MiB (HBM counter calibration)")
+    ap.add_argument("--workload", default="colour256", choices=["colour256", "batch64"],
+                    help="colour256: one 256x256x3 solve per step (default); batch64: the uneven "
+                         "64-instance batch per step (merged launches, HIP graph)")
     return ap.parse_args()
 
 
@@ -113,6 +116,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "batch64":
+        return bench_batch(args)
     dev = torch.device("cuda:0")
     w = W.colour_256()
     p, n, s, k = 3, 256, 256, w["iters"]
@@ -251,6 +256,130 @@ def main():
     dk.dctk_op_destroy(op)
     dk.dctk_destroy(ctx)
     print(json.dumps(line))
+
+
+def oracle_batch_leg(insts, k, budget_s):
+    """FP64 oracle on the smallest instances of the batch: restoration errors and solves/s."""
+    from oracle import krylov, metrics
+    from oracle.cprod import Operator, fro
+    order = sorted(range(len(insts)), key=lambda i: insts[i]["w"]["A"].size * insts[i]["w"]["X_true"].shape[2])
+    errs, n, t0 = {}, 0, time.perf_counter()
+    for i in order:
+        w = insts[i]["w"]
+        op = Operator(w["A"])
+        Ch = op.apply(w["X_true"])
+        C = Ch + w["nu"] * fro(Ch) / fro(w["N0"]) * w["N0"]
+        r = krylov.dc_gk(op, C, k, lam=None, gcv_mode="rect", reorth="none")
+        errs[i] = metrics.relative_error(w["X_true"], r["X"])
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    return errs, n, time.perf_counter() - t0
+
+
+def bench_batch(args):
+    """The uneven 64-instance batch: one step = all 64 DC-GK solves (40 GKB steps + GCV each)."""
+    import torch
+    import paper_2103_11847_amd as dk
+    import workloads as W
+    dev = torch.device("cuda:0")
+    gdt = dk.DTYPES[args.gemm]
+    k = 40
+    ctx = dk.dctk_create(0)
+    insts = []
+    flops = 0.0
+    for i in range(64):
+        w = W.batch_instance(i)
+        p, n = w["A"].shape[0], w["A"].shape[1]
+        A64 = torch.from_numpy(w["A"]).to(dev)
+        op64 = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F64, A64, n)
+        Xt = torch.from_numpy(w["X_true"]).to(dev)
+        Ch = torch.empty_like(Xt)
+        dk.dctk_cprod(ctx, op64, 1.0, Xt, 0.0, Ch)
+        dk.dctk_op_destroy(op64)
+        N0 = torch.from_numpy(w["N0"]).to(dev)
+        C = (Ch + w["nu"] * torch.linalg.norm(Ch) / torch.linalg.norm(N0) * N0).to(torch.float32).contiguous()
+        op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, A64, n)
+        ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k)
+        insts.append({"w": w, "op": op, "ws": ws, "C": C, "X": torch.empty_like(C)})
+        flops += (2 * k + 1) * 2.0 * n * n * n * p
+        del Xt, Ch, N0
+    opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0, 0.0)
+    # a loop of plain single solves
+    for it in insts:
+        dk.dctk_lsqr_tik_solve(ctx, it["ws"], it["C"], it["X"], opts)
+    ref = [it["X"].clone() for it in insts]
+    loop_steps = max(1, min(3, args.steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(loop_steps):
+        for it in insts:
+            dk.dctk_lsqr_tik_solve(ctx, it["ws"], it["C"], it["X"], opts)
+    torch.cuda.synchronize()
+    loop_s = (time.perf_counter() - t0) / loop_steps
+    # the batch: merged launches captured in a graph
+    b = dk.dctk_batch_create(ctx, [it["ws"] for it in insts], [it["C"] for it in insts],
+                             [it["X"] for it in insts], opts, True)
+    merged, single = dk.dctk_batch_stats(b)
+    for _ in range(args.warmup):
+        dk.dctk_batch_run(ctx, b)
+    dk.dctk_synchronize(ctx)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dk.dctk_batch_run(ctx, b)
+    dk.dctk_synchronize(ctx)
+    batch_s = (time.perf_counter() - t0) / args.steps
+    infos = dk.dctk_batch_info(ctx, b, len(insts))
+    same = all(torch.equal(it["X"], r) for it, r in zip(insts, ref))
+    errs = []
+    for it in insts:
+        Xn = it["X"].double().cpu().numpy()
+        Xt = it["w"]["X_true"]
+        errs.append(float(np.linalg.norm((Xn - Xt).ravel()) / np.linalg.norm(Xt.ravel())))
+    cpu, gate_ok, worst = None, same, None
+    if not args.no_cpu_baseline:
+        oerr, nsolve, dt = oracle_batch_leg(insts, k, args.cpu_seconds)
+        ratios = [errs[i] / e for i, e in oerr.items()]
+        worst = max(ratios)
+        gate_ok = gate_ok and worst <= 1.05
+        elems = sum(insts[i]["w"]["X_true"].size for i in oerr)
+        cpu = {"value": nsolve / dt, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": "%d FP64 DC-GK solves (40 GKB steps + GCV) of the smallest batch instances "
+                         "(%d tensor elements in all) in %.1f s; the batch's instances average %.0f elements"
+                         % (nsolve, elems, dt, sum(it["w"]["X_true"].size for it in insts) / len(insts))}
+    dk.dctk_batch_destroy(b)
+    for it in insts:
+        dk.dctk_krylov_destroy(it["ws"])
+        dk.dctk_op_destroy(it["op"])
+    dk.dctk_destroy(ctx)
+    value = (64.0 / batch_s) if gate_ok else 0.0
+    peak = MFMA_PEAK_TFLOPS[args.gemm]
+    sizes = collections_count([(it["w"]["A"].shape[1], it["w"]["A"].shape[0]) for it in insts])
+    line = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": batch_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.gemm, "data": "synthetic",
+        "config": {"workload": "uneven batch of 64 DC-GK solves (n=s in {64..512}, n3 in {3,8,31}, 40 GKB steps "
+                               "+ FP64 GCV each), one batch per step, merged launches in a HIP graph",
+                   "instances": 64, "gkb_steps": k, "gemm_dtype": args.gemm, "sizes_n_n3": sizes},
+        "roofline": {"bound": "mfma", "achieved": flops / batch_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+                     "frac": flops / batch_s / 1e12 / peak, "traffic": None,
+                     "kernel": "whole batch step (slice-GEMM flops of all 81 products per instance)"},
+        "cpu_baseline": cpu,
+        "batch": {"loop_of_single_solves_per_s": 64.0 / loop_s, "speedup_vs_loop": loop_s / batch_s,
+                  "launches_merged": merged, "launches_single": single, "bitwise_equal_to_single": same,
+                  "worst_relerr_ratio_vs_oracle": worst, "median_relerr": float(np.median(errs)),
+                  "lambda_range": [min(x.lam for x in infos), max(x.lam for x in infos)]},
+    }
+    print(json.dumps(line))
+
+
+def collections_count(items):
+    out = {}
+    for n, p in items:
+        key = "%dx%d" % (n, p)
+        out[key] = out.get(key, 0) + 1
+    return out
 
 
 if __name__ == "__main__":

@@ -236,6 +236,40 @@ int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X,
 int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, int cycles,
                          const dctk_solve_opts* opts, dctk_solve_info* info);
 
+/* ---- batches of independent solves ------------------------------------- */
+/* Many DC-LSQR / DC-GK solves (Algorithms 4, 5, 6) of independent problems
+ * of uneven n1, n2, s and n3, run together.  The plan records, for every
+ * instance, the kernel launches dctk_lsqr_tik_solve would enqueue with opts;
+ * the launches of one kernel at the same point of the schedule are merged,
+ * across instances, into one launch whose workgroups each look up their
+ * instance; the resulting schedule (one launch per kernel variant per
+ * schedule point) is captured once into a HIP graph.  Every instance computes
+ * exactly what its own dctk_lsqr_tik_solve would.
+ *
+ * dctk_batch_create: count in [1, DCTK_BATCH_MAX]; ws[i] distinct
+ *   DCTK_KRYLOV_GKB workspaces on ctx's device; C[i] (p x n1 x s) and X[i]
+ *   (p x n2 x s) device buffers of instance i in its vector type, captured by
+ *   the plan (every run reads C[i] and writes X[i]; they must outlive the
+ *   batch).  opts applies to all (reorth must be DCTK_REORTH_NONE; k_max <=
+ *   each workspace's).  use_graph = 0 replays the merged launches from the host
+ *   instead of a graph.  The batch owns device copies of the launch arguments
+ *   (allocated here, freed by dctk_batch_destroy).  Errors: DCTK_EINVAL on a
+ *   bad argument, DCTK_ENOMEM, DCTK_EHIP.
+ * dctk_batch_run: enqueues one run of all solves on ctx's stream (async).
+ * dctk_batch_info: synchronises and fills infos[0..count) as
+ *   dctk_lsqr_tik_solve would; returns DCTK_OK or the first non-OK status.
+ * dctk_batch_stats: launches per run of the merged schedule, and of the
+ *   same solves run one by one (either may be NULL).
+ * dctk_batch_destroy: synchronises ctx's stream and frees the plan. */
+#define DCTK_BATCH_MAX 256
+typedef struct dctk_batch_s* dctk_batch;
+int dctk_batch_create(dctk_ctx ctx, int count, const dctk_krylov* ws, const void* const* C, void* const* X,
+                      const dctk_solve_opts* opts, int use_graph, dctk_batch* out);
+int dctk_batch_run(dctk_ctx ctx, dctk_batch b);
+int dctk_batch_info(dctk_ctx ctx, dctk_batch b, dctk_solve_info* infos);
+int dctk_batch_stats(dctk_batch b, int* merged_launches, int* single_launches);
+int dctk_batch_destroy(dctk_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,7 @@ DCTK_MAT_L, DCTK_MAT_LINV, DCTK_MAT_LINVT, DCTK_MAT_LT = 0, 1, 2, 3
 DCTK_KRYLOV_GKB, DCTK_KRYLOV_ARNOLDI = 0, 1
 DCTK_REORTH_NONE, DCTK_REORTH_V, DCTK_REORTH_FULL = 0, 1, 2
 DCTK_ORTHO_MGS, DCTK_ORTHO_CGS2 = 0, 1
+DCTK_BATCH_MAX = 256
 
 TUBES = {"th": DCTK_TUBE_TH, "dct2": DCTK_TUBE_DCT2}
 DTYPES = {"f64": DCTK_F64, "f32": DCTK_F32, "bf16": DCTK_BF16, "f16": DCTK_F16}
@@ -86,6 +87,12 @@ _SIGS = {
     "dctk_lsqr_tik_solve": (_I, [_P, _P, _P, _P, ctypes.POINTER(dctk_solve_opts), ctypes.POINTER(dctk_solve_info)]),
     "dctk_gmres_tik_solve": (_I, [_P, _P, _P, _P, _I, ctypes.POINTER(dctk_solve_opts),
                                   ctypes.POINTER(dctk_solve_info)]),
+    "dctk_batch_create": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                               ctypes.POINTER(dctk_solve_opts), _I, ctypes.POINTER(_P)]),
+    "dctk_batch_run": (_I, [_P, _P]),
+    "dctk_batch_info": (_I, [_P, _P, ctypes.POINTER(dctk_solve_info)]),
+    "dctk_batch_stats": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "dctk_batch_destroy": (_I, [_P]),
 }
 EXPORTED = tuple(sorted(_SIGS))
 
@@ -317,6 +324,41 @@ def dctk_gmres_tik_solve(ctx, ws, C, X, cycles, opts):
     _check(lib().dctk_gmres_tik_solve(ctx, ws, _ptr(C), _ptr(X), int(cycles), ctypes.byref(opts),
                                       ctypes.byref(info)), "dctk_gmres_tik_solve")
     return info
+
+
+def dctk_batch_create(ctx, ws_list, C_list, X_list, opts, use_graph=True):
+    """Plan a batch of DC-LSQR / DC-GK solves: ws_list[i] solves C_list[i] into X_list[i]."""
+    n = len(ws_list)
+    if len(C_list) != n or len(X_list) != n:
+        raise ValueError("dctk_batch_create: ws, C and X lists differ in length")
+    arr = ctypes.c_void_p * n
+    ws_a = arr(*[w for w in ws_list])
+    c_a = arr(*[_ptr(c) for c in C_list])
+    x_a = arr(*[_ptr(x) for x in X_list])
+    h = ctypes.c_void_p()
+    _check(lib().dctk_batch_create(ctx, n, ws_a, c_a, x_a, ctypes.byref(opts), 1 if use_graph else 0,
+                                   ctypes.byref(h)), "dctk_batch_create")
+    return h.value
+
+
+def dctk_batch_run(ctx, batch):
+    return _check(lib().dctk_batch_run(ctx, batch), "dctk_batch_run")
+
+
+def dctk_batch_info(ctx, batch, count):
+    infos = (dctk_solve_info * count)()
+    _check(lib().dctk_batch_info(ctx, batch, infos), "dctk_batch_info")
+    return list(infos)
+
+
+def dctk_batch_stats(batch):
+    m, s = ctypes.c_int(), ctypes.c_int()
+    _check(lib().dctk_batch_stats(batch, ctypes.byref(m), ctypes.byref(s)), "dctk_batch_stats")
+    return m.value, s.value
+
+
+def dctk_batch_destroy(batch):
+    return _check(lib().dctk_batch_destroy(batch), "dctk_batch_destroy")
 
 
 def dctk_krylov_copy(ctx, ws, which, j, dst):

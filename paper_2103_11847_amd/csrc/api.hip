@@ -38,7 +38,7 @@ struct Profiler {
 
 void prof_begin(dctk_ctx ctx, int kind) {
   (void)kind;
-  if (!ctx || !ctx->prof) return;
+  if (!ctx || !ctx->prof || ctx->rec) return;
   Profiler* P = (Profiler*)ctx->prof;
   hipEvent_t ev;
   if (hipEventCreate(&ev) != hipSuccess) return;
@@ -62,7 +62,7 @@ void prof_kernel(dctk_ctx ctx, int kind, hipEvent_t* start, hipEvent_t* stop) {
 }
 
 void prof_end(dctk_ctx ctx, int kind) {
-  if (!ctx || !ctx->prof) return;
+  if (!ctx || !ctx->prof || ctx->rec) return;
   Profiler* P = (Profiler*)ctx->prof;
   if (!P->open) return;
   hipEvent_t ev;
@@ -107,6 +107,7 @@ int dctk_create(dctk_ctx* out, int device, void* hip_stream) {
   c->stream = (hipStream_t)hip_stream;
   c->last_hip_error = 0;
   c->prof = nullptr;
+  c->rec = nullptr;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->red_partials, sizeof(double) * kRedBlocks * kRedVals);
@@ -206,7 +207,7 @@ static int tube_common(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, 
   plain.a = 1.0;
   plain.s = 1.0;
   if (e == hipSuccess)
-    e = launch_tube(ctx->stream, dtype, dtype, p, count, in, out, (const double*)dG, (const float*)dG, nullptr,
+    e = launch_tube(ctx, ctx->stream, dtype, dtype, p, count, in, out, (const double*)dG, (const float*)dG, nullptr,
                     nullptr, plain, false, true, nullptr);
   // the host copies of G must outlive the async copy; the device copy is freed after the work
   hipError_t e3 = hipStreamSynchronize(ctx->stream);
@@ -279,7 +280,7 @@ int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1
   none.a = 1.0;
   none.s = 1.0;
 #define DCTK_TUBE_F64(SRC, DST, CNT) \
-  launch_tube(ctx->stream, DCTK_F64, DCTK_F64, p, (CNT), (SRC), (DST), op->Gd, op->Gf, nullptr, nullptr, none, false, true, nullptr)
+  launch_tube(ctx, ctx->stream, DCTK_F64, DCTK_F64, p, (CNT), (SRC), (DST), op->Gd, op->Gf, nullptr, nullptr, none, false, true, nullptr)
   if (gemm_dtype == DCTK_F64) {
     DCTK_TRY(DCTK_TUBE_F64(A, op->Ah, n1 * n2));
     if (op->two_sided) DCTK_TRY(DCTK_TUBE_F64(B, op->Bh, s * s));
@@ -444,12 +445,16 @@ static hipError_t gkb_init_impl(dctk_ctx ctx, dctk_krylov ws, const void* C, voi
   const int vdt = op->vec_dtype;
   const int64_t nU = op->p * op->n1 * op->s, nV = op->p * op->n2 * op->s;
   hipError_t e;
+  rec_phase(ctx);
   if ((e = launch_state_reset(ctx, st, 1, tol)) != hipSuccess) return e;
   int npA = 0, npB = 0;
+  rec_phase(ctx);
   if ((e = launch_sumsq(ctx, vdt, nU, C, nullptr, ws->partA, &npA, Gate{nullptr, 0, 0})) != hipSuccess) return e;
   const Ctl c = make_ctl(CTL_GKB_INIT, 0, st, ws->partA, npA, ws->partB);
+  rec_phase(ctx);
   if ((e = apply_op(op, ctx->stream, 1, C, slot(ws->V, ws, 0), nullptr, slot(ws->U, ws, 0), c, &npB)) != hipSuccess)
     return e;
+  rec_phase(ctx);
   return launch_gkb_start(ctx, vdt, nV, X, ws->W, slot(ws->V, ws, 0), ws->partB, npB, st);
 }
 
@@ -474,6 +479,7 @@ static hipError_t gkb_step_impl(dctk_ctx ctx, dctk_krylov ws, int j, void* X) {
   const bool ru = ws->reorth == DCTK_REORTH_FULL;
   const bool rv = ws->reorth != DCTK_REORTH_NONE;
   const Ctl c1 = make_ctl(CTL_GKB_FWD, j, st, nullptr, 0, ru ? nullptr : ws->partA);
+  rec_phase(ctx);
   if ((e = apply_op(op, ctx->stream, 0, Vj, T, Uj, nullptr, c1, &npA)) != hipSuccess) return e;
   if (ru) {
     const Gate g{st, j, 0};
@@ -481,13 +487,42 @@ static hipError_t gkb_step_impl(dctk_ctx ctx, dctk_krylov ws, int j, void* X) {
     if ((e = launch_sumsq(ctx, vdt, nU, T, nullptr, ws->partA, &npA, g)) != hipSuccess) return e;
   }
   const Ctl c2 = make_ctl(CTL_GKB_ADJ, j, st, ws->partA, npA, rv ? nullptr : ws->partB);
+  rec_phase(ctx);
   if ((e = apply_op(op, ctx->stream, 1, T, Vn, Vj, Un, c2, &npB)) != hipSuccess) return e;
   if (rv) {
     const Gate g{st, j, 1};
     if ((e = cgs2(ctx, ws, ws->V, j, Vn, nV, g, nullptr)) != hipSuccess) return e;
     if ((e = launch_sumsq(ctx, vdt, nV, Vn, nullptr, ws->partB, &npB, g)) != hipSuccess) return e;
   }
+  rec_phase(ctx);
   return launch_gkb_update(ctx, vdt, nV, X, ws->W, Vn, ws->partB, npB, st, j);
+}
+
+// Everything dctk_lsqr_tik_solve enqueues (Algorithms 4-6, then Algorithm 5's
+// projected solve and X = V_k (*) y when lambda != 0).  Also used, with the
+// context recording, to plan batches.
+hipError_t lsqr_enqueue(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, const dctk_solve_opts* opts) {
+  dctk_op op = ws->op;
+  hipError_t e;
+  ws->reorth = opts->reorth;
+  const bool tik = opts->lambda != 0.0;
+  void* Xl = tik ? ws->X : X;  // LSQR iterate (Algorithm 6)
+  if ((e = gkb_init_impl(ctx, ws, C, Xl, opts->tol)) != hipSuccess) return e;
+  for (int j = 1; j <= opts->k_max; ++j)
+    if ((e = gkb_step_impl(ctx, ws, j, Xl)) != hipSuccess) return e;
+  ws->host_steps = opts->k_max;
+  ws->initialised = 1;
+  if (tik) {
+    // Algorithm 5: lambda (GCV or fixed), y, X = V_k (*) y
+    rec_phase(ctx);
+    if ((e = launch_projected(ctx, ws->st, 1, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda)) != hipSuccess)
+      return e;
+    rec_phase(ctx);
+    if ((e = launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, opts->k_max,
+                            &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0})) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
 }
 
 // Algorithm 2 step 2 on R with the partials of ||R||^2 already in `part`: V_1 = R / ||R||.
@@ -554,6 +589,23 @@ static double lsqr_resnorm(dctk_ctx ctx, dctk_krylov ws, int steps) {
     return NAN;
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return NAN;
   return std::fabs(v);
+}
+
+int lsqr_info(dctk_ctx ctx, dctk_krylov ws, const dctk_solve_opts* opts, dctk_solve_info* info) {
+  HostState hs;
+  int r;
+  if ((r = read_state(ctx, ws, &hs))) return r;
+  const bool tik = opts->lambda != 0.0;
+  if (info) {
+    info->iters = hs.steps;
+    info->status = hs.status;
+    info->converged = hs.converged;
+    info->cycles = 0;
+    info->lambda = tik ? hs.lambda : 0.0;
+    info->resnorm = lsqr_resnorm(ctx, ws, hs.steps);
+    info->gcv = (tik && opts->lambda < 0.0) ? hs.gcv : NAN;
+  }
+  return hs.status;
 }
 
 }  // namespace dctk
@@ -677,7 +729,9 @@ int dctk_krylov_copy(dctk_ctx ctx, dctk_krylov ws, int which, int j, void* dst) 
   return DCTK_OK;
 }
 
-static int check_opts(const dctk_solve_opts* o, const dctk_krylov ws) {
+}  // extern "C"
+
+int dctk::check_solve_opts(const dctk_solve_opts* o, const dctk_krylov ws) {
   if (!o) return DCTK_EINVAL;
   if (o->k_max < 1 || o->k_max > ws->k_max) return DCTK_EINVAL;
   if (o->reorth < DCTK_REORTH_NONE || o->reorth > DCTK_REORTH_FULL) return DCTK_EINVAL;
@@ -687,42 +741,21 @@ static int check_opts(const dctk_solve_opts* o, const dctk_krylov ws) {
   return DCTK_OK;
 }
 
+extern "C" {
+
 int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, const dctk_solve_opts* opts,
                         dctk_solve_info* info) {
   int r = ws_check(ctx, ws, DCTK_KRYLOV_GKB);
   if (r) return r;
   if (!C || !X) return DCTK_EINVAL;
-  if ((r = check_opts(opts, ws))) return r;
+  if ((r = check_solve_opts(opts, ws))) return r;
   dctk_op op = ws->op;
   const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
   if (ranges_overlap(C, (size_t)(op->p * op->n1 * op->s) * ve, X, (size_t)(op->p * op->n2 * op->s) * ve))
     return DCTK_EINVAL;
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
-  ws->reorth = opts->reorth;
-  const bool tik = opts->lambda != 0.0;
-  void* Xl = tik ? ws->X : X;  // LSQR iterate (Algorithm 6)
-  DCTK_HIP(ctx, gkb_init_impl(ctx, ws, C, Xl, opts->tol));
-  for (int j = 1; j <= opts->k_max; ++j) DCTK_HIP(ctx, gkb_step_impl(ctx, ws, j, Xl));
-  ws->host_steps = opts->k_max;
-  ws->initialised = 1;
-  if (tik) {
-    // Algorithm 5: lambda (GCV or fixed), y, X = V_k (*) y
-    DCTK_HIP(ctx, launch_projected(ctx, ws->st, 1, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda));
-    DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec,
-                                 opts->k_max, &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
-  }
-  HostState hs;
-  if ((r = read_state(ctx, ws, &hs))) return r;
-  if (info) {
-    info->iters = hs.steps;
-    info->status = hs.status;
-    info->converged = hs.converged;
-    info->cycles = 0;
-    info->lambda = tik ? hs.lambda : 0.0;
-    info->resnorm = lsqr_resnorm(ctx, ws, hs.steps);
-    info->gcv = (tik && opts->lambda < 0.0) ? hs.gcv : NAN;
-  }
-  return hs.status;
+  DCTK_HIP(ctx, lsqr_enqueue(ctx, ws, C, X, opts));
+  return lsqr_info(ctx, ws, opts, info);
 }
 
 int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, int cycles,
@@ -731,7 +764,7 @@ int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, i
   if (r) return r;
   if (!C || !X) return DCTK_EINVAL;
   if (cycles < 1) return DCTK_EINVAL;
-  if ((r = check_opts(opts, ws))) return r;
+  if ((r = check_solve_opts(opts, ws))) return r;
   dctk_op op = ws->op;
   const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
   const int64_t n = op->p * op->n1 * op->s;

@@ -14,13 +14,12 @@
 // Small problems (fewer 32x32 tiles than CUs) use 16x16 tiles with the 4 waves
 // splitting the contraction (reduced through LDS) so every CU has work;
 // larger ones use 32x32 or 64x64 tiles with 2x2 waves.
-#include <hip/hip_ext.h>
-
 #include "mfma.h"
 
 namespace dctk {
 
 struct FusedArgs {
+  int gx, gy, gz;          // this instance's grid (tiles along N, M)
   int p, M, N, K;          // output rows, columns, contraction length
   int64_t lda, sA;         // A~ slice: row stride and slice stride
   const void* A;
@@ -37,13 +36,13 @@ struct FusedArgs {
 // dispatch order (x fastest), and each XCD has its own L2.  When the grid
 // splits into 2 x 4 equal regions, XCD r is given region r, so an XCD reads
 // half of the A~ rows and a quarter of the X columns instead of all A~ rows;
-// otherwise the hardware order is kept.
-__device__ inline void xcd_tile(int& tx, int& ty) {
-  const int gx = gridDim.x, gy = gridDim.y;
-  tx = blockIdx.x;
-  ty = blockIdx.y;
-  if (gx % 4 != 0 || gy % 2 != 0) return;
-  const int lin = blockIdx.y * gx + blockIdx.x;
+// otherwise (and in grouped launches, whose workgroups are not aligned to the
+// XCD rotation) the plain order is kept.
+__device__ inline void xcd_tile(const VBlock& vb, bool grouped, int gx, int gy, int& tx, int& ty) {
+  tx = vb.x;
+  ty = vb.y;
+  if (grouped || gx % 4 != 0 || gy % 2 != 0) return;
+  const int lin = vb.y * gx + vb.x;
   const int xcd = lin & 7, slot = lin >> 3;
   const int rw = gx / 4, rh = gy / 2;  // region size in tiles; rw * rh = slots per XCD
   tx = (xcd & 3) * rw + slot % rw;
@@ -52,7 +51,7 @@ __device__ inline void xcd_tile(int& tx, int& ty) {
 
 // EXACT: p == PMAX (no slice guards); otherwise p <= PMAX at run time.
 template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA>
-__global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa) {
+__global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const FusedArgs* grp, const int4* bmap) {
   typedef Mfma<TI> MF;
   typedef typename MF::acc_t acc_t;
   typedef typename MF::frag_t frag_t;
@@ -73,8 +72,10 @@ __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa) {
   __shared__ TV sGin[PMAX * PMAX], sGout[PMAX * PMAX];
   __shared__ double sh[8];
 
+  VBlock vb;
+  const FusedArgs fa = pick_args(fa_, grp, bmap, vb);
   double a_d, b_d, s_d;
-  if (!ctl_begin(fa.ctl, a_d, b_d, s_d, sh)) return;
+  if (!ctl_begin(fa.ctl, a_d, b_d, s_d, sh, vb)) return;
   const TV sc = (TV)s_d;
 
   const int p = EXACT ? PMAX : fa.p;
@@ -84,10 +85,10 @@ __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa) {
     sGin[i] = ((const TV*)fa.Gin)[i];
     sGout[i] = ((const TV*)fa.Gout)[i];
   }
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = vb.y * BM, n0 = vb.x * BN;
   const TI* A = (const TI*)fa.A;
   const TV* X = (const TV*)fa.X;
-  TV* xnorm = (blockIdx.y == 0) ? (TV*)fa.xnorm : nullptr;
+  TV* xnorm = (vb.y == 0) ? (TV*)fa.xnorm : nullptr;
 
   const int wk = (WK == 1) ? 0 : wave;
   const int wmn = (WK == 1) ? wave : 0;
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa) {
   }
   if (fa.ctl.part_out != nullptr) {
     const double tot = block_sum_all(sq, sh);
-    if (tid == 0) fa.ctl.part_out[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    if (tid == 0) fa.ctl.part_out[vb.y * fa.gx + vb.x] = tot;
   }
 }
 
@@ -310,7 +311,7 @@ template <> struct VecIO<double, 2> {
 };
 
 template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA, int VW>
-__global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
+__global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa_, const FusedArgs* grp, const int4* bmap) {
   typedef Mfma<T> MF;
   typedef typename MF::acc_t acc_t;
   typedef typename MF::frag_t frag_t;
@@ -342,6 +343,8 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
   __shared__ T sGin[PMAX * PMAX], sGout[PMAX * PMAX];
   __shared__ double sh[8];
 
+  VBlock vb;
+  const FusedArgs fa = pick_args(fa_, grp, bmap, vb);
   const int p = EXACT ? PMAX : fa.p;
   const int M = fa.M, N = fa.N, K = fa.K;
   const int lda = (int)fa.lda, sA = (int)fa.sA;
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
     sGout[i] = ((const T*)fa.Gout)[i];
   }
   int tx, ty;
-  xcd_tile(tx, ty);
+  xcd_tile(vb, grp != nullptr, fa.gx, fa.gy, tx, ty);
   const int m0 = ty * BM, n0 = tx * BN;
   const T* A = (const T*)fa.A;
   const T* X = (const T*)fa.X;
@@ -472,7 +475,7 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
   // before its (memory-latency bound) evaluation
   load_chunk(0);
   double a_d, b_d, s_d;
-  if (!ctl_begin(fa.ctl, a_d, b_d, s_d, sh)) return;
+  if (!ctl_begin(fa.ctl, a_d, b_d, s_d, sh, vb)) return;
   sc = (T)s_d;
   for (int k0 = 0; k0 < K; k0 += BKT) {
     __syncthreads();
@@ -595,35 +598,34 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa) {
     }
   if (fa.ctl.part_out != nullptr) {
     const double tot = block_sum_all(sq, sh);
-    if (tid == 0) fa.ctl.part_out[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    if (tid == 0) fa.ctl.part_out[ty * fa.gx + tx] = tot;  // by tile: the same order under any tile mapping
   }
 }
 
-// Start/stop events of the launch being enqueued (null unless the context is
-// profiling): the dispatch itself records them, so the measured interval is
-// the kernel's execution, not the queue's.
-static thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
+// Where a fused product goes: the context (recording or not), its stream, and
+// start/stop events (null unless the context is profiling) that the dispatch
+// itself records, so the measured interval is the kernel's execution alone.
+struct FusedLaunch {
+  dctk_ctx ctx;
+  hipStream_t s;
+  hipEvent_t e0, e1;
+};
 
 template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK>
-static hipError_t launch_fused_mn_cfg(hipStream_t s, const FusedArgs& fa, int ta, bool vec, int* nblocks_out) {
+static hipError_t launch_fused_mn_cfg(const FusedLaunch& L, const FusedArgs& fa, int ta, bool vec, int* nblocks_out) {
   dim3 grid((unsigned)((fa.N + BN - 1) / BN), (unsigned)((fa.M + BM - 1) / BM));
   if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
   if ((int64_t)grid.x * grid.y > kRedBlocks && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
   constexpr int VW = 16 / (int)sizeof(T);
-#define DCTK_MN_LAUNCH(TA_, VW_)                                                                         \
-  hipExtLaunchKernelGGL((cprod_fused_mn_kernel<T, PMAX, EXACT, BM, BN, WK, BK, TA_, VW_>), grid, dim3(256), 0, s, \
-                        t_ev0, t_ev1, 0, fa)
-  if (ta) {
-    if (vec) DCTK_MN_LAUNCH(true, VW); else DCTK_MN_LAUNCH(true, 1);
-  } else {
-    if (vec) DCTK_MN_LAUNCH(false, VW); else DCTK_MN_LAUNCH(false, 1);
-  }
+#define DCTK_MN_LAUNCH(TA_, VW_) \
+  launch_kernel(L.ctx, L.s, cprod_fused_mn_kernel<T, PMAX, EXACT, BM, BN, WK, BK, TA_, VW_>, grid, 256, 0, fa, L.e0, L.e1)
+  if (ta) return vec ? DCTK_MN_LAUNCH(true, VW) : DCTK_MN_LAUNCH(true, 1);
+  return vec ? DCTK_MN_LAUNCH(false, VW) : DCTK_MN_LAUNCH(false, 1);
 #undef DCTK_MN_LAUNCH
-  return hipGetLastError();
 }
 
 template <typename T, int PMAX, bool EXACT>
-static hipError_t launch_fused_mn_p(hipStream_t s, const FusedArgs& fa, int ta, bool vec, int* nblocks_out) {
+static hipError_t launch_fused_mn_p(const FusedLaunch& L, const FusedArgs& fa, int ta, bool vec, int* nblocks_out) {
   constexpr int BK = (sizeof(T) == 8) ? 8 : 16;
   // 16x16 tiles (small problems, latency bound): the whole contraction of a
   // 256-long K in one staged chunk when it fits in ~130 KB of LDS
@@ -631,42 +633,37 @@ static hipError_t launch_fused_mn_p(hipStream_t s, const FusedArgs& fa, int ta, 
   const int64_t t32 = (int64_t)((fa.M + 31) / 32) * ((fa.N + 31) / 32);
   const int64_t t64 = (int64_t)((fa.M + 63) / 64) * ((fa.N + 63) / 64);
   const int ncu = num_cus();
-  if (t32 < ncu) return launch_fused_mn_cfg<T, PMAX, EXACT, 16, 16, 4, BK16>(s, fa, ta, vec, nblocks_out);
+  if (t32 < ncu) return launch_fused_mn_cfg<T, PMAX, EXACT, 16, 16, 4, BK16>(L, fa, ta, vec, nblocks_out);
   if (t64 < ncu || sizeof(T) == 8 || PMAX > 4 || t64 > kRedBlocks)
-    return launch_fused_mn_cfg<T, PMAX, EXACT, 32, 32, 1, BK>(s, fa, ta, vec, nblocks_out);
-  return launch_fused_mn_cfg<T, PMAX, EXACT, 64, 64, 1, BK>(s, fa, ta, vec, nblocks_out);
+    return launch_fused_mn_cfg<T, PMAX, EXACT, 32, 32, 1, BK>(L, fa, ta, vec, nblocks_out);
+  return launch_fused_mn_cfg<T, PMAX, EXACT, 64, 64, 1, BK>(L, fa, ta, vec, nblocks_out);
 }
 
 template <typename T>
-static hipError_t launch_fused_mn(hipStream_t s, const FusedArgs& fa, int ta, int* nblocks_out) {
+static hipError_t launch_fused_mn(const FusedLaunch& L, const FusedArgs& fa, int ta, int* nblocks_out) {
   constexpr int VW = 16 / (int)sizeof(T);
   const bool vec = fa.M % VW == 0 && fa.N % VW == 0 && fa.K % VW == 0 && fa.lda % VW == 0 &&
                    ((uintptr_t)fa.A % 16) == 0 && ((uintptr_t)fa.X % 16) == 0 &&
                    (fa.xnorm == nullptr || ((uintptr_t)fa.xnorm % 16) == 0);
-  if (fa.p == 3) return launch_fused_mn_p<T, 3, true>(s, fa, ta, vec, nblocks_out);
-  if (fa.p <= 4) return launch_fused_mn_p<T, 4, false>(s, fa, ta, vec, nblocks_out);
-  return launch_fused_mn_p<T, 8, false>(s, fa, ta, vec, nblocks_out);
+  if (fa.p == 3) return launch_fused_mn_p<T, 3, true>(L, fa, ta, vec, nblocks_out);
+  if (fa.p <= 4) return launch_fused_mn_p<T, 4, false>(L, fa, ta, vec, nblocks_out);
+  return launch_fused_mn_p<T, 8, false>(L, fa, ta, vec, nblocks_out);
 }
 
 template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK>
-static hipError_t launch_fused_cfg(hipStream_t s, const FusedArgs& fa, int ta, int* nblocks_out) {
+static hipError_t launch_fused_cfg(const FusedLaunch& L, const FusedArgs& fa, int ta, int* nblocks_out) {
   dim3 grid((unsigned)((fa.N + BN - 1) / BN), (unsigned)((fa.M + BM - 1) / BM));
   if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
   if ((int64_t)grid.x * grid.y > kRedBlocks && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
-  if (ta)
-    hipExtLaunchKernelGGL((cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true>), grid, dim3(256), 0, s,
-                          t_ev0, t_ev1, 0, fa);
-  else
-    hipExtLaunchKernelGGL((cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false>), grid, dim3(256), 0, s,
-                          t_ev0, t_ev1, 0, fa);
-  return hipGetLastError();
+  if (ta) return launch_kernel(L.ctx, L.s, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true>, grid, 256, 0, fa, L.e0, L.e1);
+  return launch_kernel(L.ctx, L.s, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false>, grid, 256, 0, fa, L.e0, L.e1);
 }
 
 // Tile choice: 16x16 with a split contraction while 32x32 tiles would not
 // cover the CUs, then 32x32, then 64x64 (FP64 and p > 4 stay at 32x32 to
 // bound the accumulator registers).
 template <typename TI, typename TV, int PMAX, bool EXACT>
-static hipError_t launch_fused_p(hipStream_t s, const FusedArgs& fa, int ta, int* nblocks_out) {
+static hipError_t launch_fused_p(const FusedLaunch& L, const FusedArgs& fa, int ta, int* nblocks_out) {
   constexpr int KS = Mfma<TI>::KSTEP;
   // contraction chunk per wave: keep each LDS operand buffer near 16-20 KB
   constexpr int BK16 = (KS == 32) ? 32 : (sizeof(TI) == 8 ? (PMAX > 4 ? 4 : 8) : (PMAX > 4 ? 8 : 16));
@@ -675,17 +672,17 @@ static hipError_t launch_fused_p(hipStream_t s, const FusedArgs& fa, int ta, int
   const int64_t t32 = (int64_t)((fa.M + 31) / 32) * ((fa.N + 31) / 32);
   const int64_t t64 = (int64_t)((fa.M + 63) / 64) * ((fa.N + 63) / 64);
   const int ncu = num_cus();
-  if (t32 < ncu) return launch_fused_cfg<TI, TV, PMAX, EXACT, 16, 16, 4, BK16>(s, fa, ta, nblocks_out);
+  if (t32 < ncu) return launch_fused_cfg<TI, TV, PMAX, EXACT, 16, 16, 4, BK16>(L, fa, ta, nblocks_out);
   if (t64 < ncu || sizeof(TI) == 8 || PMAX > 4 || t64 > kRedBlocks)
-    return launch_fused_cfg<TI, TV, PMAX, EXACT, 32, 32, 1, BK32>(s, fa, ta, nblocks_out);
-  return launch_fused_cfg<TI, TV, PMAX, EXACT, 64, 64, 1, BK64>(s, fa, ta, nblocks_out);
+    return launch_fused_cfg<TI, TV, PMAX, EXACT, 32, 32, 1, BK32>(L, fa, ta, nblocks_out);
+  return launch_fused_cfg<TI, TV, PMAX, EXACT, 64, 64, 1, BK64>(L, fa, ta, nblocks_out);
 }
 
 template <typename TI, typename TV>
-static hipError_t launch_fused_t(hipStream_t s, const FusedArgs& fa, int ta, int* nblocks_out) {
-  if (fa.p == 3) return launch_fused_p<TI, TV, 3, true>(s, fa, ta, nblocks_out);  // colour images
-  if (fa.p <= 4) return launch_fused_p<TI, TV, 4, false>(s, fa, ta, nblocks_out);
-  return launch_fused_p<TI, TV, 8, false>(s, fa, ta, nblocks_out);
+static hipError_t launch_fused_t(const FusedLaunch& L, const FusedArgs& fa, int ta, int* nblocks_out) {
+  if (fa.p == 3) return launch_fused_p<TI, TV, 3, true>(L, fa, ta, nblocks_out);  // colour images
+  if (fa.p <= 4) return launch_fused_p<TI, TV, 4, false>(L, fa, ta, nblocks_out);
+  return launch_fused_p<TI, TV, 8, false>(L, fa, ta, nblocks_out);
 }
 
 hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,
@@ -712,17 +709,15 @@ hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, v
     fa.Gout = op->Gf + go * pp;
   }
   fa.ctl = ctl;
-  prof_kernel(op->ctx, adjoint ? PROF_FUSED_ADJ : PROF_FUSED_FWD, &t_ev0, &t_ev1);
-  hipError_t e;
+  FusedLaunch L{op->ctx, s, nullptr, nullptr};
+  if (!recording(op->ctx)) prof_kernel(op->ctx, adjoint ? PROF_FUSED_ADJ : PROF_FUSED_FWD, &L.e0, &L.e1);
   switch (op->gemm_dtype) {
-    case DCTK_F64: e = launch_fused_mn<double>(s, fa, adjoint, nblocks_out); break;
-    case DCTK_F32: e = launch_fused_mn<float>(s, fa, adjoint, nblocks_out); break;
-    case DCTK_BF16: e = launch_fused_t<bf16_t, float>(s, fa, adjoint, nblocks_out); break;
-    case DCTK_F16: e = launch_fused_t<f16_t, float>(s, fa, adjoint, nblocks_out); break;
-    default: e = hipErrorInvalidValue;
+    case DCTK_F64: return launch_fused_mn<double>(L, fa, adjoint, nblocks_out);
+    case DCTK_F32: return launch_fused_mn<float>(L, fa, adjoint, nblocks_out);
+    case DCTK_BF16: return launch_fused_t<bf16_t, float>(L, fa, adjoint, nblocks_out);
+    case DCTK_F16: return launch_fused_t<f16_t, float>(L, fa, adjoint, nblocks_out);
+    default: return hipErrorInvalidValue;
   }
-  t_ev0 = t_ev1 = nullptr;
-  return e;
 }
 
 }  // namespace dctk

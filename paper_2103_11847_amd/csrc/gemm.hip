@@ -15,11 +15,28 @@
 namespace dctk {
 
 
+struct GemmArgs {
+  int gx, gy, gz;
+  int M, N, K;
+  const void* A;
+  int64_t lda, sA;
+  const void* B;
+  int64_t ldb, sB;
+  void* C;
+  int64_t ldc, sC;
+  Gate g;
+};
+
 template <typename TI, typename TO, int BM, int BN, bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
-                                                   const TI* __restrict__ A, int64_t lda, int64_t sA,
-                                                   const TI* __restrict__ B, int64_t ldb, int64_t sB,
-                                                   TO* __restrict__ C, int64_t ldc, int64_t sC, Gate g) {
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const GemmArgs ga = pick_args(ga_, grp, bmap, vb);
+  const int M = ga.M, N = ga.N, K = ga.K;
+  const TI* __restrict__ A = (const TI*)ga.A;
+  const TI* __restrict__ B = (const TI*)ga.B;
+  TO* __restrict__ C = (TO*)ga.C;
+  const int64_t lda = ga.lda, sA = ga.sA, ldb = ga.ldb, sB = ga.sB, ldc = ga.ldc, sC = ga.sC;
+  const Gate g = ga.g;
   typedef Mfma<TI> MF;
   typedef typename MF::acc_t acc_t;
   typedef typename MF::frag_t frag_t;
@@ -38,9 +55,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
   __shared__ __attribute__((aligned(16))) TI As[BM * LDS_LD];
   __shared__ __attribute__((aligned(16))) TI Bs[BN * LDS_LD];
 
-  const int bz = blockIdx.z;
-  const int m0 = blockIdx.y * BM;
-  const int n0 = blockIdx.x * BN;
+  const int bz = vb.z;
+  const int m0 = vb.y * BM;
+  const int n0 = vb.x * BN;
   A += (int64_t)bz * sA;
   B += (int64_t)bz * sB;
   C += (int64_t)bz * sC;
@@ -147,54 +164,63 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
 }
 
 template <typename TI, typename TO, int BM, int BN>
-static hipError_t launch_gemm_tile(hipStream_t s, int M, int N, int K, const void* A, int64_t lda,
+static hipError_t launch_gemm_tile(dctk_ctx ctx, hipStream_t s, int M, int N, int K, const void* A, int64_t lda,
                                    int64_t sA, int ta, const void* B, int64_t ldb, int64_t sB, int tb,
                                    void* C, int64_t ldc, int64_t sC, int batch, Gate g) {
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)batch);
-  const TI* a = (const TI*)A;
-  const TI* b = (const TI*)B;
-  TO* c = (TO*)C;
-#define DCTK_GEMM_LAUNCH(TA_, TB_) \
-  hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, TA_, TB_>), grid, dim3(256), 0, s, M, N, K, a, lda, sA, b, ldb, sB, c, ldc, sC, g)
+  GemmArgs ga{};
+  ga.M = M;
+  ga.N = N;
+  ga.K = K;
+  ga.A = A;
+  ga.lda = lda;
+  ga.sA = sA;
+  ga.B = B;
+  ga.ldb = ldb;
+  ga.sB = sB;
+  ga.C = C;
+  ga.ldc = ldc;
+  ga.sC = sC;
+  ga.g = g;
+#define DCTK_GEMM_LAUNCH(TA_, TB_) return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_>, grid, 256, 0, ga)
   if (!ta && !tb) DCTK_GEMM_LAUNCH(false, false);
-  else if (ta && !tb) DCTK_GEMM_LAUNCH(true, false);
-  else if (!ta && tb) DCTK_GEMM_LAUNCH(false, true);
-  else DCTK_GEMM_LAUNCH(true, true);
+  if (ta && !tb) DCTK_GEMM_LAUNCH(true, false);
+  if (!ta && tb) DCTK_GEMM_LAUNCH(false, true);
+  DCTK_GEMM_LAUNCH(true, true);
 #undef DCTK_GEMM_LAUNCH
-  return hipGetLastError();
 }
 
 template <typename TI, typename TO>
-static hipError_t launch_gemm_t(hipStream_t s, int M, int N, int K, const void* A, int64_t lda, int64_t sA,
+static hipError_t launch_gemm_t(dctk_ctx ctx, hipStream_t s, int M, int N, int K, const void* A, int64_t lda, int64_t sA,
                                 int ta, const void* B, int64_t ldb, int64_t sB, int tb, void* C, int64_t ldc,
                                 int64_t sC, int batch, Gate g, int num_cus) {
   // 64 x 64 tiles when they fill the chip, 32 x 32 otherwise.
   int64_t tiles64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64) * batch;
   if (tiles64 >= 2 * (int64_t)num_cus)
-    return launch_gemm_tile<TI, TO, 64, 64>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
-  return launch_gemm_tile<TI, TO, 32, 32>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
+    return launch_gemm_tile<TI, TO, 64, 64>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
+  return launch_gemm_tile<TI, TO, 32, 32>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
 }
 
 static int g_num_cus = 256;
 
-hipError_t launch_gemm(hipStream_t s, int in_dtype, int out_acc, int M, int N, int K,
+hipError_t launch_gemm(dctk_ctx ctx, hipStream_t s, int in_dtype, int out_acc, int M, int N, int K,
                        const void* A, int64_t lda, int64_t sA, int ta,
                        const void* B, int64_t ldb, int64_t sB, int tb,
                        void* C, int64_t ldc, int64_t sC, int batch, Gate g) {
   // out_acc = 1: output in the accumulator type; 0: output in the input type
   switch (in_dtype) {
     case DCTK_F64:
-      return launch_gemm_t<double, double>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+      return launch_gemm_t<double, double>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
     case DCTK_F32:
-      return launch_gemm_t<float, float>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+      return launch_gemm_t<float, float>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
     case DCTK_BF16:
       if (out_acc)
-        return launch_gemm_t<bf16_t, float>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
-      return launch_gemm_t<bf16_t, bf16_t>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+        return launch_gemm_t<bf16_t, float>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+      return launch_gemm_t<bf16_t, bf16_t>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
     case DCTK_F16:
       if (out_acc)
-        return launch_gemm_t<f16_t, float>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
-      return launch_gemm_t<f16_t, f16_t>(s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+        return launch_gemm_t<f16_t, float>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+      return launch_gemm_t<f16_t, f16_t>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
     default:
       return hipErrorInvalidValue;
   }
@@ -224,7 +250,7 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   // this kernel evaluates the control block (input scale, recorded scalars)
   const int gi = adjoint ? 2 : 0;
   prof_begin(ctx, PROF_TUBE_FWD);
-  e = launch_tube(s, vdt, gdt, p, rin * sc, X, op->xh, Gd + gi * pp, Gf + gi * pp, nullptr, xnorm, ctl, true,
+  e = launch_tube(ctx, s, vdt, gdt, p, rin * sc, X, op->xh, Gd + gi * pp, Gf + gi * pp, nullptr, xnorm, ctl, true,
                   false, nullptr);
   prof_end(ctx, PROF_TUBE_FWD);
   if (e != hipSuccess) return e;
@@ -243,14 +269,14 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   prof_begin(ctx, PROF_GEMM);
   if (!op->two_sided) {
     // forward: (n1 x n2)(n2 x s);  adjoint: (n2 x n1 := A~^T)(n1 x s)
-    e = launch_gemm(s, gdt, 1, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
+    e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
                     op->xh, sc, rin * sc, 0, op->ch, sc, rout * sc, (int)p, g);
   } else {
-    e = launch_gemm(s, gdt, 0, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
+    e = launch_gemm(ctx, s, gdt, 0, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
                     op->xh, sc, rin * sc, 0, op->th, sc, rout * sc, (int)p, g);
     if (e != hipSuccess) return e;
     // right factor: forward (rout x s)(s x s) with B~; adjoint with B~^T
-    e = launch_gemm(s, gdt, 1, (int)rout, (int)sc, (int)sc, op->th, sc, rout * sc, 0,
+    e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)sc, op->th, sc, rout * sc, 0,
                     op->Bh, sc, sc * sc, adjoint ? 1 : 0, op->ch, sc, rout * sc, (int)p, g);
   }
   prof_end(ctx, PROF_GEMM);
@@ -258,7 +284,7 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   // step 3: inverse transform (L^{-1}, or L^T for the adjoint) with the epilogue
   const int go = adjoint ? 3 : 1;
   prof_begin(ctx, PROF_TUBE_INV);
-  e = launch_tube(s, vdt, vdt, p, rout * sc, op->ch, Y, Gd + go * pp, Gf + go * pp, src, nullptr, later, false,
+  e = launch_tube(ctx, s, vdt, vdt, p, rout * sc, op->ch, Y, Gd + go * pp, Gf + go * pp, src, nullptr, later, false,
                   true, nblocks_out);
   prof_end(ctx, PROF_TUBE_INV);
   return e;

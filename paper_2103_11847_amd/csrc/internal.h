@@ -1,8 +1,12 @@
 // Internal declarations of libdctkrylov (not installed).  gfx950 only.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <vector>
 
 #include "../../include/dctkrylov.h"
 
@@ -148,10 +152,35 @@ __device__ inline double gkb_scale(const KState* st, int na, int nb, double* sh)
   return block_max_all(m, sh);
 }
 
+// ---- plain and grouped launches -------------------------------------------------
+// A kernel that can run for several problem instances in one launch takes its
+// arguments as one struct `a` (which records the instance's own grid in gx, gy,
+// gz) plus two pointers: for a grouped launch, `grp` holds the argument
+// structs of the instances and `bmap` gives, for every workgroup of the 1-D
+// launch grid, {instance, x, y, z} within that instance's grid.  A plain launch
+// passes null for both and the hardware indices are used.
+struct VBlock {
+  int x, y, z;
+};
+
+__device__ inline VBlock hw_block() { return VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z}; }
+
+template <typename A>
+__device__ inline A pick_args(const A& a, const A* grp, const int4* bmap, VBlock& vb) {
+  if (grp == nullptr) {
+    vb = hw_block();
+    return a;
+  }
+  const int4 m = bmap[blockIdx.x];
+  vb = VBlock{m.y, m.z, m.w};
+  return grp[m.x];
+}
+
 // Evaluates the control block at kernel start (all threads of every block
-// call it).  Returns false when the kernel must do nothing.  Block 0 records
-// the scalar it produced in the state.  `sh` holds >= 20 doubles.
-__device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin, double* sh) {
+// call it).  Returns false when the kernel must do nothing.  Block (0, 0, 0)
+// of the instance records the scalar it produced in the state.  `sh` holds
+// >= 20 doubles.
+__device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin, double* sh, const VBlock& vb) {
   a = 1.0; b = 0.0; sin = 1.0;
   if (c.kind == CTL_PLAIN) {
     // a plain product inside a GMRES solve is skipped once the solve halted
@@ -161,7 +190,7 @@ __device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin
   }
   KState* st = c.st;
   const int ss = ((volatile KState*)st)->stop_step;
-  const bool first = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0;
+  const bool first = vb.x == 0 && vb.y == 0 && vb.z == 0 && threadIdx.x == 0;
   const double eps = 2.220446049250313e-16;
   switch (c.kind) {
     case CTL_GKB_INIT: {
@@ -279,6 +308,7 @@ struct dctk_ctx_s {
   int num_cus;
   double* red_partials;   // kRedBlocks * kRedVals doubles: partials of standalone reductions
   void* prof;             // dctk::Profiler while profiling, else null
+  void* rec;              // dctk::Recorder while a batch schedule is being planned, else null
 };
 
 struct dctk_op_s {
@@ -342,6 +372,64 @@ int hip_fail(dctk_ctx ctx, hipError_t e);
     if (e_ != hipSuccess) return ::dctk::hip_fail((ctx), e_); \
   } while (0)
 
+// ---- launch recording (batch planning) ----------------------------------------
+// While ctx->rec is set, the launchers of the batchable kernels append a record
+// instead of launching: the kernel, the instance's grid and block, and the
+// bytes of its argument struct.  `phase` is advanced by the planner between the
+// steps of the schedule; `sub` numbers the records within a phase.
+struct LaunchRec {
+  const void* fn;
+  dim3 grid;
+  unsigned threads;
+  unsigned shmem;
+  int phase, sub;
+  std::vector<unsigned char> args;
+};
+struct Recorder {
+  int phase = 0;
+  int sub = 0;
+  std::vector<LaunchRec> recs;
+};
+inline void rec_phase(dctk_ctx ctx) {
+  if (ctx && ctx->rec) {
+    Recorder* r = (Recorder*)ctx->rec;
+    r->phase += 1;
+    r->sub = 0;
+  }
+}
+
+// Launch (or record) kernel fn(A a, const A* grp, const int4* bmap) as a plain
+// launch with grid `grid`.  The grid is stored in a.gx/gy/gz first.  Start and
+// stop events (may be null) are recorded by the dispatch itself.
+template <typename A>
+hipError_t launch_kernel(dctk_ctx ctx, hipStream_t s, void (*fn)(A, const A*, const int4*), dim3 grid,
+                         unsigned threads, unsigned shmem, A a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  a.gx = (int)grid.x;
+  a.gy = (int)grid.y;
+  a.gz = (int)grid.z;
+  if (ctx && ctx->rec) {
+    Recorder* r = (Recorder*)ctx->rec;
+    LaunchRec lr;
+    lr.fn = (const void*)fn;
+    lr.grid = grid;
+    lr.threads = threads;
+    lr.shmem = shmem;
+    lr.phase = r->phase;
+    lr.sub = r->sub++;
+    lr.args.resize(sizeof(A));
+    memcpy(lr.args.data(), &a, sizeof(A));
+    r->recs.push_back(std::move(lr));
+    return hipSuccess;
+  }
+  const A* grp = nullptr;
+  const int4* bmap = nullptr;
+  void* kargs[3] = {&a, &grp, &bmap};
+  hipError_t e = hipExtLaunchKernel((const void*)fn, grid, dim3(threads), kargs, shmem, s, e0, e1, 0);
+  return e != hipSuccess ? e : hipGetLastError();
+}
+// Launchers of kernels that cannot be recorded refuse while planning.
+inline bool recording(dctk_ctx ctx) { return ctx && ctx->rec; }
+
 // transform matrices (host, FP64): which = DCTK_MAT_*
 int build_tube_matrix(int tube, int which, int64_t p, double* out);
 size_t elem_size(int dt);
@@ -352,12 +440,12 @@ int num_cus();
 // Streaming tube transform: out[k][e] = a * sum_t G[k][t] (s * in[t][e]) + b * src[k][e].
 // `xnorm` (may be null) receives s * in.  Scalars come from the control block;
 // ctl.part_out gets per-block sums of out^2.
-hipError_t launch_tube(hipStream_t st, int in_dtype, int out_dtype, int64_t p, int64_t count,
+hipError_t launch_tube(dctk_ctx ctx, hipStream_t st, int in_dtype, int out_dtype, int64_t p, int64_t count,
                        const void* in, void* out, const double* Gd, const float* Gf,
                        const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi, int* nblocks_out);
 
 // C_k = op(A_k) op(B_k), batched over `batch`
-hipError_t launch_gemm(hipStream_t s, int in_dtype, int out_acc, int M, int N, int K,
+hipError_t launch_gemm(dctk_ctx ctx, hipStream_t s, int in_dtype, int out_acc, int M, int N, int K,
                        const void* A, int64_t lda, int64_t sA, int ta,
                        const void* B, int64_t ldb, int64_t sB, int tb,
                        void* C, int64_t ldc, int64_t sC, int batch, Gate g);
@@ -409,6 +497,12 @@ hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* 
                              int npart, KState* st, int j);
 hipError_t launch_state_reset(dctk_ctx ctx, KState* st, int full, double tol);
 hipError_t launch_cast(dctk_ctx ctx, int64_t n, const double* in, int out_dtype, void* out);
+
+// ---- solves (api.hip) ------------------------------------------------------------
+int check_solve_opts(const dctk_solve_opts* o, const dctk_krylov ws);
+// everything dctk_lsqr_tik_solve enqueues, and its info once finished (synchronises)
+hipError_t lsqr_enqueue(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, const dctk_solve_opts* opts);
+int lsqr_info(dctk_ctx ctx, dctk_krylov ws, const dctk_solve_opts* opts, dctk_solve_info* info);
 
 // projected FP64 problem (projected.hip): bidiag = 1 reads alpha/beta, else H.
 // Writes st->y[0..k), st->lambda, st->gcv.

@@ -109,7 +109,20 @@ __device__ inline double gcv_wave(int mode, double lam, int k, const double* sig
   return t1 / (t2 * t2);
 }
 
-__global__ __launch_bounds__(kPT) void k_projected(KState* st, int bidiag, int gcv_mode, double lam_fixed) {
+struct ProjArgs {
+  int gx, gy, gz;
+  int bidiag;
+  int gcv_mode;
+  KState* st;
+  double lam_fixed;
+};
+
+__global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* group, const int4* bmap) {
+  VBlock vb;
+  const ProjArgs a = pick_args(a_, group, bmap, vb);
+  KState* st = a.st;
+  const int bidiag = a.bidiag, gcv_mode = a.gcv_mode;
+  const double lam_fixed = a.lam_fixed;
   if (((volatile KState*)st)->halt) return;
   __shared__ double G[kMaxK * kLdG];      // G[c * kLdG + r]: column c of the matrix
   __shared__ double Vm[kMaxK * kMaxK];    // Vm[c * kMaxK + r]: right singular vectors
@@ -349,8 +362,12 @@ __global__ __launch_bounds__(kPT) void k_projected(KState* st, int bidiag, int g
 }
 
 hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, double lambda) {
-  hipLaunchKernelGGL(k_projected, dim3(1), dim3(kPT), 0, ctx->stream, st, bidiag, gcv_mode, lambda);
-  return hipGetLastError();
+  ProjArgs a{};
+  a.bidiag = bidiag;
+  a.gcv_mode = gcv_mode;
+  a.st = st;
+  a.lam_fixed = lambda;
+  return launch_kernel(ctx, ctx->stream, k_projected, dim3(1), kPT, 0, a);
 }
 
 }  // namespace dctk

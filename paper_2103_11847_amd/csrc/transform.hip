@@ -106,13 +106,33 @@ template <> struct Vec4Store<double> {
 // TIN: float or double; TOUT: float, double, bf16_t or f16_t; TC: compute type.
 // SCALE: apply the control block's input scale (and write xnorm); EPI: apply
 // its a/b/src epilogue and write per-block partials of out^2.
+struct TubeArgs {
+  int gx, gy, gz;
+  int p;
+  int64_t count;       // tube positions (elements per slice)
+  const void* in;      // p x count, TIN
+  void* out;           // p x count, TOUT
+  const void* G;       // p x p, TC
+  const void* src;     // p x count, TOUT, or null
+  void* xnorm;         // p x count, TIN, or null
+  Ctl ctl;
+};
+
 template <typename TIN, typename TOUT, typename TC, int KB, bool VEC, bool SCALE, bool EPI>
-__global__ __launch_bounds__(kThreads) void tube_kernel(int p, int64_t count, const TIN* __restrict__ in,
-                                                        TOUT* out, const TC* __restrict__ G, const TOUT* src,
-                                                        TIN* xnorm, Ctl ctl) {
+__global__ __launch_bounds__(kThreads) void tube_kernel(TubeArgs ta_, const TubeArgs* grp, const int4* bmap) {
   __shared__ double sh[kThreads / 64 + 2];
+  VBlock vb;
+  const TubeArgs ta = pick_args(ta_, grp, bmap, vb);
+  const int p = ta.p;
+  const int64_t count = ta.count;
+  const TIN* __restrict__ in = (const TIN*)ta.in;
+  TOUT* out = (TOUT*)ta.out;
+  const TC* __restrict__ G = (const TC*)ta.G;
+  const TOUT* src = (const TOUT*)ta.src;
+  TIN* xnorm = (TIN*)ta.xnorm;
+  const Ctl& ctl = ta.ctl;
   double a_d, b_d, s_d;
-  if (!ctl_begin(ctl, a_d, b_d, s_d, sh)) return;
+  if (!ctl_begin(ctl, a_d, b_d, s_d, sh, vb)) return;
   if (!SCALE) s_d = 1.0;
   if (!EPI) { a_d = 1.0; b_d = 0.0; }
   const TC a = (TC)a_d, b = (TC)b_d, sc = (TC)s_d;
@@ -121,8 +141,8 @@ __global__ __launch_bounds__(kThreads) void tube_kernel(int p, int64_t count, co
   for (int i = threadIdx.x; i < p * p; i += blockDim.x) sG[i] = G[i];
   __syncthreads();
   double sq = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-  for (int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e0 < count; e0 += stride) {
+  const int64_t stride = (int64_t)ta.gx * blockDim.x * 4;
+  for (int64_t e0 = ((int64_t)vb.x * blockDim.x + threadIdx.x) * 4; e0 < count; e0 += stride) {
     const int nv = (count - e0) < 4 ? (int)(count - e0) : 4;
     for (int k0 = 0; k0 < p; k0 += KB) {
       TC acc[KB][4];
@@ -181,12 +201,12 @@ __global__ __launch_bounds__(kThreads) void tube_kernel(int p, int64_t count, co
   }
   if (EPI && ctl.part_out != nullptr) {
     const double tot = block_sum_all(sq, sh);
-    if (threadIdx.x == 0) ctl.part_out[blockIdx.x] = tot;
+    if (threadIdx.x == 0) ctl.part_out[vb.x] = tot;
   }
 }
 
 template <typename TIN, typename TOUT, typename TC>
-static hipError_t launch_tube_t(hipStream_t s, int64_t p, int64_t count, const void* in, void* out,
+static hipError_t launch_tube_t(dctk_ctx ctx, hipStream_t s, int64_t p, int64_t count, const void* in, void* out,
                                 const TC* G, const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi,
                                 int* nblocks_out) {
   int64_t nthreads = (count + 3) / 4;
@@ -197,12 +217,18 @@ static hipError_t launch_tube_t(hipStream_t s, int64_t p, int64_t count, const v
   size_t shmem = (size_t)(p * p) * sizeof(TC);
   bool vec = (count % 4 == 0) && (((uintptr_t)in) % 32 == 0) && (((uintptr_t)out) % 32 == 0) &&
              (src == nullptr || ((uintptr_t)src) % 32 == 0) && (xnorm == nullptr || ((uintptr_t)xnorm) % 32 == 0);
-  const TIN* i = (const TIN*)in;
-  TOUT* o = (TOUT*)out;
-  const TOUT* sr = (const TOUT*)src;
-  TIN* xn = (TIN*)xnorm;
+  TubeArgs ta{};
+  ta.p = (int)p;
+  ta.count = count;
+  ta.in = in;
+  ta.out = out;
+  ta.G = G;
+  ta.src = src;
+  ta.xnorm = xnorm;
+  ta.ctl = ctl;
+  const dim3 grid((unsigned)blocks);
 #define DCTK_TUBE_LAUNCH(KB, V, S, E) \
-  hipLaunchKernelGGL((tube_kernel<TIN, TOUT, TC, KB, V, S, E>), dim3((unsigned)blocks), dim3(kThreads), shmem, s, (int)p, count, i, o, G, sr, xn, ctl)
+  return launch_kernel(ctx, s, tube_kernel<TIN, TOUT, TC, KB, V, S, E>, grid, kThreads, (unsigned)shmem, ta)
 #define DCTK_TUBE_SE(KB, V)                                  \
   do {                                                       \
     if (scale && epi) DCTK_TUBE_LAUNCH(KB, V, true, true);    \
@@ -217,30 +243,29 @@ static hipError_t launch_tube_t(hipStream_t s, int64_t p, int64_t count, const v
   }
 #undef DCTK_TUBE_SE
 #undef DCTK_TUBE_LAUNCH
-  return hipGetLastError();
 }
 
 // in_dtype: element type of `in` (F64/F32); out_dtype: of `out` (F64, F32, BF16, F16).
 // A transform whose output is a GEMM operand applies the input side of the
 // control block (scale); one whose input is a GEMM result applies the epilogue
 // side (epi).
-hipError_t launch_tube(hipStream_t s, int in_dtype, int out_dtype, int64_t p, int64_t count,
+hipError_t launch_tube(dctk_ctx ctx, hipStream_t s, int in_dtype, int out_dtype, int64_t p, int64_t count,
                        const void* in, void* out, const double* Gd, const float* Gf,
                        const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi, int* nblocks_out) {
   if (in_dtype == DCTK_F64) {
     if (out_dtype != DCTK_F64) return hipErrorInvalidValue;
-    return launch_tube_t<double, double, double>(s, p, count, in, out, Gd, src, xnorm, ctl, scale, epi, nblocks_out);
+    return launch_tube_t<double, double, double>(ctx, s, p, count, in, out, Gd, src, xnorm, ctl, scale, epi, nblocks_out);
   }
   switch (out_dtype) {
     case DCTK_F32:
-      return launch_tube_t<float, float, float>(s, p, count, in, out, Gf, src, xnorm, ctl, scale, epi, nblocks_out);
+      return launch_tube_t<float, float, float>(ctx, s, p, count, in, out, Gf, src, xnorm, ctl, scale, epi, nblocks_out);
     case DCTK_BF16:
       if (src) return hipErrorInvalidValue;
-      return launch_tube_t<float, bf16_t, float>(s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false,
+      return launch_tube_t<float, bf16_t, float>(ctx, s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false,
                                                  nblocks_out);
     case DCTK_F16:
       if (src) return hipErrorInvalidValue;
-      return launch_tube_t<float, f16_t, float>(s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false,
+      return launch_tube_t<float, f16_t, float>(ctx, s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false,
                                                 nblocks_out);
     default:
       return hipErrorInvalidValue;

@@ -56,18 +56,69 @@ __device__ inline void st4(T* base, int64_t e, int64_t n, bool vec, const double
 }
 
 __device__ inline bool first_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
+__device__ inline bool first_thread(const VBlock& vb) { return vb.x == 0 && threadIdx.x == 0; }
 
 #define DCTK_GRID_LOOP(e, n) \
   for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < (n); e += (int64_t)gridDim.x * blockDim.x * 4)
+// the same over an instance's own 1-D grid (plain or grouped launch)
+#define DCTK_VGRID_LOOP(e, n, vb, gx) \
+  for (int64_t e = ((int64_t)(vb).x * blockDim.x + threadIdx.x) * 4; e < (n); e += (int64_t)(gx) * blockDim.x * 4)
+
+// argument structs of the kernels that run in grouped launches
+struct SumsqArgs {
+  int gx, gy, gz;
+  int vec;
+  int64_t n;
+  const void* x;
+  const void* z;
+  double* part;
+  Gate g;
+};
+struct GkbArgs {  // start and per-step update of Algorithm 6
+  int gx, gy, gz;
+  int vec;
+  int64_t n;
+  void* X;
+  void* W;
+  void* V;
+  const double* part;
+  int npart;
+  int j;
+  KState* st;
+};
+struct CombineArgs {
+  int gx, gy, gz;
+  int vec;
+  int64_t n;
+  void* out;
+  const void* x0;
+  const void* basis;
+  int64_t bstride;
+  int nb;
+  const int* nptr;
+  const double* y;
+  Gate g;
+};
+struct ResetArgs {
+  int gx, gy, gz;
+  int full;
+  KState* st;
+  double tol;
+};
 
 // ---- reductions ----------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sumsq(int64_t n, const T* x, const T* z, double* part, bool vec,
-                                                    Gate g) {
-  if (!gate_open(g)) return;
+__global__ __launch_bounds__(kThreads) void k_sumsq(SumsqArgs a_, const SumsqArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const SumsqArgs a = pick_args(a_, grp, bmap, vb);
+  if (!gate_open(a.g)) return;
+  const int64_t n = a.n;
+  const T* x = (const T*)a.x;
+  const T* z = (const T*)a.z;
+  const bool vec = a.vec;
   __shared__ double sh[kThreads / 64 + 2];
   double acc = 0.0;
-  DCTK_GRID_LOOP(e, n) {
+  DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double xv[4];
     ld4(x, e, n, vec, xv);
     if (z) {
@@ -79,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_sumsq(int64_t n, const T* x, const
     }
   }
   const double t = block_sum_all(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) a.part[vb.x] = t;
 }
 
 template <typename T>
@@ -167,17 +218,24 @@ __global__ __launch_bounds__(kThreads) void k_subtract(int64_t n, T* w, const T*
 
 // out = x0 + sum_{i < cnt} y[i] basis_i
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_combine(int64_t n, T* out, const T* x0, const T* basis,
-                                                      int64_t bstride, int nb, const int* nptr, const double* y,
-                                                      bool vec, Gate g) {
-  if (!gate_open(g)) return;
+__global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a_, const CombineArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const CombineArgs a = pick_args(a_, grp, bmap, vb);
+  if (!gate_open(a.g)) return;
+  const int64_t n = a.n, bstride = a.bstride;
+  T* out = (T*)a.out;
+  const T* x0 = (const T*)a.x0;
+  const T* basis = (const T*)a.basis;
+  const int nb = a.nb;
+  const double* y = a.y;
+  const bool vec = a.vec;
   __shared__ double sy[kRedVals];
-  int cnt = nptr ? nptr[0] : nb;
+  int cnt = a.nptr ? a.nptr[0] : nb;
   if (cnt > nb) cnt = nb;
   if (cnt < 0) cnt = 0;
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) sy[i] = y[i];
   __syncthreads();
-  DCTK_GRID_LOOP(e, n) {
+  DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double o[4] = {0.0, 0.0, 0.0, 0.0};
     if (x0) ld4(x0, e, n, vec, o);
     for (int i = 0; i < cnt; ++i) {
@@ -193,8 +251,17 @@ __global__ __launch_bounds__(kThreads) void k_combine(int64_t n, T* out, const T
 // Algorithm 6 step 2 after M*(U_1): alpha_1 from the partials; V_1 = V~/alpha_1
 // in place; W_1 = V_1; X_0 = 0.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gkb_start(int64_t n, T* X, T* W, T* V1, const double* part, int npart,
-                                                        KState* st, bool vec) {
+__global__ __launch_bounds__(kThreads) void k_gkb_start(GkbArgs a_, const GkbArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const GkbArgs a = pick_args(a_, grp, bmap, vb);
+  const int64_t n = a.n;
+  T* X = (T*)a.X;
+  T* W = (T*)a.W;
+  T* V1 = (T*)a.V;
+  const double* part = a.part;
+  const int npart = a.npart;
+  KState* st = a.st;
+  const bool vec = a.vec;
   __shared__ double sh[kThreads / 64 + 2];
   const bool ok = ((volatile KState*)st)->stop_step < 0;
   bool brk = true;
@@ -204,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_gkb_start(int64_t n, T* X, T* W, T
     const double scale = fmax(st->beta[0], alpha);
     const bool fin = isfinite(alpha);
     brk = !fin || alpha <= kBreakFactor * DBL_EPSILON * scale;
-    if (first_thread()) {
+    if (first_thread(vb)) {
       st->alpha[0] = alpha;
       st->rhobar[0] = alpha;
       st->phibar[0] = st->beta[0];
@@ -216,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_gkb_start(int64_t n, T* X, T* W, T
     }
   }
   const double ia = brk ? 0.0 : 1.0 / alpha;
-  DCTK_GRID_LOOP(e, n) {
+  DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double z[4] = {0.0, 0.0, 0.0, 0.0};
     st4(X, e, n, vec, z);
     if (!brk) {
@@ -236,12 +303,21 @@ __global__ __launch_bounds__(kThreads) void k_gkb_start(int64_t n, T* X, T* W, T
 // V_{j+1} = V~/alpha_{j+1} in place, X_j = X_{j-1} + (phi_j/rho_j) W_j,
 // W_{j+1} = V_{j+1} - (theta_{j+1}/rho_j) W_j.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gkb_update(int64_t n, T* X, T* W, T* Vn, const double* part,
-                                                         int npart, KState* st, int j, bool vec) {
+__global__ __launch_bounds__(kThreads) void k_gkb_update(GkbArgs a_, const GkbArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const GkbArgs a = pick_args(a_, grp, bmap, vb);
+  const int64_t n = a.n;
+  T* X = (T*)a.X;
+  T* W = (T*)a.W;
+  T* Vn = (T*)a.V;
+  const double* part = a.part;
+  const int npart = a.npart, j = a.j;
+  KState* st = a.st;
+  const bool vec = a.vec;
   __shared__ double sh[kThreads / 64 + 2];
   // the first elements' loads do not depend on the scalars: issue them before
   // the (memory-latency bound) prologue
-  const int64_t e_first = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  const int64_t e_first = ((int64_t)vb.x * blockDim.x + threadIdx.x) * 4;
   double xv0[4], wv0[4], vv0[4];
   ld4(X, e_first, n, vec, xv0);
   ld4(W, e_first, n, vec, wv0);
@@ -268,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_gkb_update(int64_t n, T* X, T* W, 
   const double phibar_new = -s * phib;
   const double cx = phi / rho, cw = theta / rho;
   const bool conv = !bbreak && !abreak && fabs(phibar_new) < st->tol;
-  if (first_thread()) {
+  if (first_thread(vb)) {
     if (!bbreak) {
       st->alpha[j] = alpha;
       st->steps = j;
@@ -287,7 +363,7 @@ __global__ __launch_bounds__(kThreads) void k_gkb_update(int64_t n, T* X, T* W, 
   }
   const bool have_v = !bbreak && !abreak;
   const double ia = have_v ? 1.0 / alpha : 0.0;
-  DCTK_GRID_LOOP(e, n) {
+  DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double xv[4], wv[4], vv[4];
     if (e == e_first) {
       for (int u = 0; u < 4; ++u) { xv[u] = xv0[u]; wv[u] = wv0[u]; vv[u] = vv0[u]; }
@@ -377,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void k_mgs(int64_t n, T* w, const T* vpre
 __global__ __launch_bounds__(kThreads) void k_arn_finish(Ctl c) {
   __shared__ double sh[kThreads / 64 + 2];
   double a, b, s;
-  (void)ctl_begin(c, a, b, s, sh);
+  (void)ctl_begin(c, a, b, s, sh, hw_block());
 }
 
 // one block: ||C - M(X)|| from the partials; cycle bookkeeping; convergence
@@ -406,7 +482,12 @@ __global__ __launch_bounds__(kThreads) void k_cast(int64_t n, const double* in, 
 }
 
 // full = 1: clear everything (new solve); full = 0: start a new GMRES cycle (unless halted)
-__global__ void k_state_reset(KState* st, int full, double tol) {
+__global__ void k_state_reset(ResetArgs a_, const ResetArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const ResetArgs a = pick_args(a_, grp, bmap, vb);
+  KState* st = a.st;
+  const int full = a.full;
+  const double tol = a.tol;
   if (full == 0 && ((volatile KState*)st)->halt) return;
   if (full) {
     double* d = reinterpret_cast<double*>(st);
@@ -443,18 +524,20 @@ hipError_t launch_sumsq(dctk_ctx ctx, int dtype, int64_t n, const void* x, const
                         Gate g) {
   const unsigned grid = grid_for(n);
   if (nblocks) *nblocks = (int)grid;
-  const bool vec = (n % 4 == 0) && al(x) && al(z);
-  if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_sumsq<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (const double*)x,
-                       (const double*)z, part, vec, g);
-  else
-    hipLaunchKernelGGL(k_sumsq<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (const float*)x,
-                       (const float*)z, part, vec, g);
-  return hipGetLastError();
+  SumsqArgs a{};
+  a.vec = (n % 4 == 0) && al(x) && al(z);
+  a.n = n;
+  a.x = x;
+  a.z = z;
+  a.part = part;
+  a.g = g;
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_sumsq<double>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_sumsq<float>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_axpy_sumsq(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x, const void* y,
                              const double* cptr, double csign, double* part, int* nblocks, Gate g) {
+  if (recording(ctx)) return hipErrorNotSupported;
   const unsigned grid = grid_for(n);
   if (nblocks) *nblocks = (int)grid;
   const bool vec = (n % 4 == 0) && al(out) && al(x) && al(y);
@@ -469,6 +552,7 @@ hipError_t launch_axpy_sumsq(dctk_ctx ctx, int dtype, int64_t n, void* out, cons
 
 hipError_t launch_multidot(dctk_ctx ctx, int dtype, int64_t n, const void* basis, int64_t stride, int nb,
                            const void* w, double* part, int* nblocks, Gate g) {
+  if (recording(ctx)) return hipErrorNotSupported;
   const unsigned grid = grid_for(n);
   if (nblocks) *nblocks = (int)grid;
   if (nb <= 0) return hipSuccess;
@@ -484,6 +568,7 @@ hipError_t launch_multidot(dctk_ctx ctx, int dtype, int64_t n, const void* basis
 
 hipError_t launch_coef_finalize(dctk_ctx ctx, const double* part, int nblocks, int nb, double* coef, double* dst,
                                 int dst_stride, Gate g) {
+  if (recording(ctx)) return hipErrorNotSupported;
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_coef_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, part, nblocks, nb, coef, dst,
                      dst_stride, g);
@@ -492,6 +577,7 @@ hipError_t launch_coef_finalize(dctk_ctx ctx, const double* part, int nblocks, i
 
 hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* basis, int64_t stride, int nb,
                            const double* coef, Gate g) {
+  if (recording(ctx)) return hipErrorNotSupported;
   if (nb <= 0) return hipSuccess;
   const unsigned grid = grid_for(n);
   const bool vec = (n % 4 == 0) && (stride % 4 == 0) && al(basis) && al(w);
@@ -507,18 +593,24 @@ hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const vo
 hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x0, const void* basis,
                           int64_t stride, int nb, const int* nptr, const double* y, Gate g) {
   const unsigned grid = grid_for(n);
-  const bool vec = (n % 4 == 0) && (stride % 4 == 0) && al(out) && al(x0) && al(basis);
-  if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_combine<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)out,
-                       (const double*)x0, (const double*)basis, stride, nb, nptr, y, vec, g);
-  else
-    hipLaunchKernelGGL(k_combine<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)out,
-                       (const float*)x0, (const float*)basis, stride, nb, nptr, y, vec, g);
-  return hipGetLastError();
+  CombineArgs a{};
+  a.vec = (n % 4 == 0) && (stride % 4 == 0) && al(out) && al(x0) && al(basis);
+  a.n = n;
+  a.out = out;
+  a.x0 = x0;
+  a.basis = basis;
+  a.bstride = stride;
+  a.nb = nb;
+  a.nptr = nptr;
+  a.y = y;
+  a.g = g;
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_combine<double>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_combine<float>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_arn_start(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* in, const double* part,
                             int npart, KState* st) {
+  if (recording(ctx)) return hipErrorNotSupported;
   const unsigned grid = grid_for(n);
   const bool vec = (n % 4 == 0) && al(out) && al(in);
   if (dtype == DCTK_F64)
@@ -533,6 +625,7 @@ hipError_t launch_arn_start(dctk_ctx ctx, int dtype, int64_t n, void* out, const
 hipError_t launch_mgs(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* vprev, const void* vi,
                       const double* part_in, int npart_in, double* hdst, double* part_out, int* nblocks, KState* st,
                       int j) {
+  if (recording(ctx)) return hipErrorNotSupported;
   const unsigned grid = grid_for(n);
   if (nblocks) *nblocks = (int)grid;
   const bool vec = (n % 4 == 0) && al(w) && al(vprev) && al(vi);
@@ -547,6 +640,7 @@ hipError_t launch_mgs(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* v
 }
 
 hipError_t launch_arn_finish(dctk_ctx ctx, const double* part, int npart, KState* st, int j) {
+  if (recording(ctx)) return hipErrorNotSupported;
   Ctl c{};
   c.kind = CTL_ARN_FWD;
   c.j = j;
@@ -558,6 +652,7 @@ hipError_t launch_arn_finish(dctk_ctx ctx, const double* part, int npart, KState
 }
 
 hipError_t launch_gmres_res(dctk_ctx ctx, const double* part, int npart, KState* st) {
+  if (recording(ctx)) return hipErrorNotSupported;
   hipLaunchKernelGGL(k_gmres_res, dim3(1), dim3(kThreads), 0, ctx->stream, part, npart, st);
   return hipGetLastError();
 }
@@ -565,30 +660,39 @@ hipError_t launch_gmres_res(dctk_ctx ctx, const double* part, int npart, KState*
 hipError_t launch_gkb_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* V1, const double* part,
                             int npart, KState* st) {
   const unsigned grid = grid_for(n);
-  const bool vec = (n % 4 == 0) && al(X) && al(W) && al(V1);
-  if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_gkb_start<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)X, (double*)W,
-                       (double*)V1, part, npart, st, vec);
-  else
-    hipLaunchKernelGGL(k_gkb_start<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)X, (float*)W,
-                       (float*)V1, part, npart, st, vec);
-  return hipGetLastError();
+  GkbArgs a{};
+  a.vec = (n % 4 == 0) && al(X) && al(W) && al(V1);
+  a.n = n;
+  a.X = X;
+  a.W = W;
+  a.V = V1;
+  a.part = part;
+  a.npart = npart;
+  a.j = 0;
+  a.st = st;
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_gkb_start<double>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_gkb_start<float>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* Vn, const double* part,
                              int npart, KState* st, int j) {
   const unsigned grid = grid_for(n);
-  const bool vec = (n % 4 == 0) && al(X) && al(W) && al(Vn);
-  if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_gkb_update<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)X, (double*)W,
-                       (double*)Vn, part, npart, st, j, vec);
-  else
-    hipLaunchKernelGGL(k_gkb_update<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)X, (float*)W,
-                       (float*)Vn, part, npart, st, j, vec);
-  return hipGetLastError();
+  GkbArgs a{};
+  a.vec = (n % 4 == 0) && al(X) && al(W) && al(Vn);
+  a.n = n;
+  a.X = X;
+  a.W = W;
+  a.V = Vn;
+  a.part = part;
+  a.npart = npart;
+  a.j = j;
+  a.st = st;
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_gkb_update<double>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_gkb_update<float>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_cast(dctk_ctx ctx, int64_t n, const double* in, int out_dtype, void* out) {
+  if (recording(ctx)) return hipErrorNotSupported;
   unsigned grid = grid_for(n * 4);
   switch (out_dtype) {
     case DCTK_F64: hipLaunchKernelGGL(k_cast<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, in, (double*)out); break;
@@ -601,8 +705,11 @@ hipError_t launch_cast(dctk_ctx ctx, int64_t n, const double* in, int out_dtype,
 }
 
 hipError_t launch_state_reset(dctk_ctx ctx, KState* st, int full, double tol) {
-  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(256), 0, ctx->stream, st, full, tol);
-  return hipGetLastError();
+  ResetArgs a{};
+  a.full = full;
+  a.st = st;
+  a.tol = tol;
+  return launch_kernel(ctx, ctx->stream, k_state_reset, dim3(1), 256, 0, a);
 }
 
 }  // namespace dctk
