@@ -66,6 +66,8 @@ def parse():
                     help="standalone c-product launches timed after the solves (0: none)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run 3 plain device copies of this many MiB (HBM counter calibration)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch64: keep the size-based product paths instead of timing them per shape")
     ap.add_argument("--workload", default="colour256", choices=["colour256", "batch64"],
                     help="colour256: one 256x256x3 solve per step (default); batch64: the uneven "
                          "64-instance batch per step (merged launches, HIP graph)")
@@ -287,6 +289,7 @@ def bench_batch(args):
     k = 40
     ctx = dk.dctk_create(0)
     insts = []
+    tuned = {}
     flops = 0.0
     for i in range(64):
         w = W.batch_instance(i)
@@ -300,6 +303,13 @@ def bench_batch(args):
         N0 = torch.from_numpy(w["N0"]).to(dev)
         C = (Ch + w["nu"] * torch.linalg.norm(Ch) / torch.linalg.norm(N0) * N0).to(torch.float32).contiguous()
         op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, A64, n)
+        if not args.no_autotune:
+            key = (p, n)
+            if key not in tuned:
+                tuned[key] = dk.dctk_op_autotune(ctx, op, 5)
+            t = tuned[key]
+            dk.dctk_op_set_path(op, 0, t["fwd_path"], t["fwd_tile"])
+            dk.dctk_op_set_path(op, 1, t["adj_path"], t["adj_tile"])
         ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k)
         insts.append({"w": w, "op": op, "ws": ws, "C": C, "X": torch.empty_like(C)})
         flops += (2 * k + 1) * 2.0 * n * n * n * p
@@ -361,7 +371,8 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": args.gemm, "data": "synthetic",
         "config": {"workload": "uneven batch of 64 DC-GK solves (n=s in {64..512}, n3 in {3,8,31}, 40 GKB steps "
                                "+ FP64 GCV each), one batch per step, merged launches in a HIP graph",
-                   "instances": 64, "gkb_steps": k, "gemm_dtype": args.gemm, "sizes_n_n3": sizes},
+                   "instances": 64, "gkb_steps": k, "gemm_dtype": args.gemm, "sizes_n_n3": sizes,
+                   "autotuned_paths": {"%dx%d" % (kk[1], kk[0]): v for kk, v in tuned.items()}},
         "roofline": {"bound": "mfma", "achieved": flops / batch_s / 1e12, "peak": peak, "unit": "TFLOP/s",
                      "frac": flops / batch_s / 1e12 / peak, "traffic": None,
                      "kernel": "whole batch step (slice-GEMM flops of all 81 products per instance)"},

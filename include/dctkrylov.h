@@ -137,6 +137,26 @@ int dctk_tube_inv(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p
 int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1, int64_t n2,
                    const void* A, int64_t s, const void* B, dctk_op* out);
 int dctk_op_destroy(dctk_op op);
+
+/* Product paths.  A product (and its adjoint) runs either fused -- one
+ * kernel doing the tube transform while staging tiles, the p slice GEMMs on
+ * the matrix cores and the inverse transform in the epilogue (one-sided
+ * operators with p <= 8) -- or as three kernels: tube transform, batched slice
+ * GEMMs, inverse transform with epilogue (Algorithm 1 steps 1-3).  The
+ * output tile edge of the GEMM part is 16, 32 or 64 (fused) or 32, 64 or 128
+ * (three kernels; 128 for FP32 only).  All paths compute the same product;
+ * results differ only by the rounding of the contraction order.
+ * dctk_op_autotune: times every path and tile the operator can take, `reps`
+ * launches each (1..1000) of the forward and of the adjoint product on ctx's
+ * stream, and keeps the fastest per direction for all later products of op.
+ * choice (host int[4], may be NULL) receives {forward path, forward tile,
+ * adjoint path, adjoint tile} with path 1 = fused, 0 = three kernels.
+ * Synchronises; allocates and frees two temporary vectors.
+ * dctk_op_set_path: sets a direction's path (-1 = chosen by problem size, the
+ * default) and tile (0 = by problem size).  Errors: DCTK_EINVAL for a path
+ * or tile the operator cannot take. */
+int dctk_op_autotune(dctk_ctx ctx, dctk_op op, int reps, int* choice);
+int dctk_op_set_path(dctk_op op, int adjoint, int path, int tile);
 /* dims[0..7] = p, n1, n2, s, two_sided, gemm_dtype, vec_dtype, tube. */
 int dctk_op_info(dctk_op op, int64_t* dims);
 
@@ -250,8 +270,7 @@ int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, i
  *   DCTK_KRYLOV_GKB workspaces on ctx's device; C[i] (p x n1 x s) and X[i]
  *   (p x n2 x s) device buffers of instance i in its vector type, captured by
  *   the plan (every run reads C[i] and writes X[i]; they must outlive the
- *   batch).  opts applies to all (reorth must be DCTK_REORTH_NONE; k_max <=
- *   each workspace's).  use_graph = 0 replays the merged launches from the host
+ *   batch).  opts applies to all (k_max <= each workspace's).  use_graph = 0 replays the merged launches from the host
  *   instead of a graph.  The batch owns device copies of the launch arguments
  *   (allocated here, freed by dctk_batch_destroy).  Errors: DCTK_EINVAL on a
  *   bad argument, DCTK_ENOMEM, DCTK_EHIP.

@@ -73,6 +73,8 @@ _SIGS = {
     "dctk_op_create": (_I, [_P, _I, _I, _L, _L, _L, _P, _L, _P, ctypes.POINTER(_P)]),
     "dctk_op_destroy": (_I, [_P]),
     "dctk_op_info": (_I, [_P, ctypes.POINTER(_L)]),
+    "dctk_op_autotune": (_I, [_P, _P, _I, ctypes.POINTER(_I)]),
+    "dctk_op_set_path": (_I, [_P, _I, _I, _I]),
     "dctk_cprod": (_I, [_P, _P, _D, _P, _D, _P]),
     "dctk_cprod_T": (_I, [_P, _P, _D, _P, _D, _P]),
     "dctk_krylov_create": (_I, [_P, _P, _I, _I, _I, ctypes.POINTER(_P)]),
@@ -246,6 +248,17 @@ def dctk_op_info(op):
     _check(lib().dctk_op_info(op, d), "dctk_op_info")
     keys = ("p", "n1", "n2", "s", "two_sided", "gemm_dtype", "vec_dtype", "tube")
     return dict(zip(keys, list(d)))
+
+
+def dctk_op_autotune(ctx, op, reps=10):
+    """Time the product paths and tiles of op; returns {fwd_path, fwd_tile, adj_path, adj_tile}."""
+    ch = (ctypes.c_int * 4)()
+    _check(lib().dctk_op_autotune(ctx, op, int(reps), ch), "dctk_op_autotune")
+    return {"fwd_path": ch[0], "fwd_tile": ch[1], "adj_path": ch[2], "adj_tile": ch[3]}
+
+
+def dctk_op_set_path(op, adjoint, path, tile=0):
+    return _check(lib().dctk_op_set_path(op, int(adjoint), int(path), int(tile)), "dctk_op_set_path")
 
 
 def dctk_cprod(ctx, op, a, X, b, Y):

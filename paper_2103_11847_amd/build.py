@@ -35,11 +35,30 @@ def _compile(src):
     return r.returncode, obj, out
 
 
-def build(verbose=True):
+def _stale(src, headers_mtime):
+    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return os.path.getmtime(src) > t or headers_mtime > t
+
+
+def build(verbose=True, incremental=False):
+    """Compile every source (incremental=True: only those older than their object
+    or than any header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(_compile, srcs))
+    todo = srcs
+    if incremental:
+        hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+        hdrs.append(os.path.join(HERE, "..", "include", "dctkrylov.h"))
+        hm = max(os.path.getmtime(h) for h in hdrs)
+        todo = [s_ for s_ in srcs if _stale(s_, hm)]
+    with ThreadPoolExecutor(max_workers=max(1, min(8, len(todo)))) as ex:
+        results = list(ex.map(_compile, todo))
+    results_by_src = dict(zip(todo, results))
+    results = [results_by_src.get(s_, (0, os.path.join(BUILD, os.path.basename(s_)[:-4] + ".o"), ""))
+               for s_ in srcs]
     objs = []
     failed = False
     for (rc, obj, out), src in zip(results, srcs):
@@ -62,4 +81,4 @@ def build(verbose=True):
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(incremental="--incremental" in sys.argv))

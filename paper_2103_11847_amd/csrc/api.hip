@@ -252,6 +252,10 @@ int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1
   op->vec_dtype = gemm_dtype == DCTK_F64 ? DCTK_F64 : DCTK_F32;
   op->p = p; op->n1 = n1; op->n2 = n2; op->s = s;
   op->two_sided = B != nullptr;
+  for (int d = 0; d < 2; ++d) {
+    op->tune[d][0] = -1;
+    op->tune[d][1] = 0;
+  }
   const size_t ge = elem_size(gemm_dtype);
   const size_t ae = gemm_dtype == DCTK_F64 ? 8 : 4;
   const int64_t nmax = n1 > n2 ? n1 : n2;
@@ -310,6 +314,87 @@ int dctk_op_destroy(dctk_op op) {
   (void)hipSetDevice(op->ctx->device);
   (void)hipStreamSynchronize(op->ctx->stream);
   op_free(op);
+  return DCTK_OK;
+}
+
+int dctk_op_autotune(dctk_ctx ctx, dctk_op op, int reps, int* choice) {
+  if (!ctx || !op || reps < 1 || reps > 1000) return DCTK_EINVAL;
+  if (op->ctx->device != ctx->device || ctx->rec) return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
+  const int64_t nmax = op->n1 > op->n2 ? op->n1 : op->n2;
+  const size_t bytes = (size_t)(op->p * nmax * op->s) * ve;
+  void* X = nullptr;
+  void* Y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&X, bytes);
+  if (e == hipSuccess) e = hipMalloc(&Y, bytes);
+  if (e == hipSuccess) e = hipMemsetAsync(X, 0, bytes, ctx->stream);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  Ctl c{};
+  c.kind = CTL_PLAIN;
+  c.a = 1.0;
+  c.s = 1.0;
+  for (int adj = 0; adj < 2 && e == hipSuccess; ++adj) {
+    int cand[6][2];
+    int nc = 0;
+    if (fused_eligible(op)) {
+      cand[nc][0] = 1; cand[nc++][1] = 16;
+      cand[nc][0] = 1; cand[nc++][1] = 32;
+      if (op->p <= 4 && op->gemm_dtype != DCTK_F64) { cand[nc][0] = 1; cand[nc++][1] = 64; }
+    }
+    cand[nc][0] = 0; cand[nc++][1] = 32;
+    cand[nc][0] = 0; cand[nc++][1] = 64;
+    if (op->gemm_dtype == DCTK_F32) { cand[nc][0] = 0; cand[nc++][1] = 128; }
+    float best = 1e30f;
+    int bi = -1;
+    for (int i = 0; i < nc && e == hipSuccess; ++i) {
+      op->tune[adj][0] = cand[i][0];
+      op->tune[adj][1] = cand[i][1];
+      hipError_t el = hipSuccess;
+      for (int r = 0; r < 2 && el == hipSuccess; ++r) el = apply_op(op, ctx->stream, adj, X, Y, nullptr, nullptr, c, nullptr);
+      if (el != hipSuccess) continue;  // a variant the shape cannot take: skip it
+      e = hipEventRecord(e0, ctx->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = apply_op(op, ctx->stream, adj, X, Y, nullptr, nullptr, c, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        bi = i;
+      }
+    }
+    op->tune[adj][0] = bi >= 0 ? cand[bi][0] : -1;
+    op->tune[adj][1] = bi >= 0 ? cand[bi][1] : 0;
+    if (choice) {
+      choice[2 * adj] = op->tune[adj][0];
+      choice[2 * adj + 1] = op->tune[adj][1];
+    }
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (X) (void)hipFree(X);
+  if (Y) (void)hipFree(Y);
+  if (e != hipSuccess) {
+    for (int d = 0; d < 2; ++d) {
+      op->tune[d][0] = -1;
+      op->tune[d][1] = 0;
+    }
+    return hip_fail(ctx, e);
+  }
+  return DCTK_OK;
+}
+
+int dctk_op_set_path(dctk_op op, int adjoint, int path, int tile) {
+  if (!op || (adjoint != 0 && adjoint != 1) || path < -1 || path > 1) return DCTK_EINVAL;
+  if (tile != 0 && tile != 16 && tile != 32 && tile != 64 && tile != 128) return DCTK_EINVAL;
+  if (path == 1 && (!fused_eligible(op) || tile == 128)) return DCTK_EINVAL;
+  if (path == 0 && tile == 16) return DCTK_EINVAL;
+  op->tune[adjoint][0] = path;
+  op->tune[adjoint][1] = tile;
   return DCTK_OK;
 }
 

@@ -85,7 +85,6 @@ int dctk_batch_create(dctk_ctx ctx, int count, const dctk_krylov* ws, const void
     for (int k = 0; k < i; ++k)
       if (ws[k] == ws[i]) return DCTK_EINVAL;
   }
-  if (opts->reorth != DCTK_REORTH_NONE) return DCTK_EINVAL;
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
 
   // 1. record every instance's schedule

@@ -286,29 +286,6 @@ __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const F
 // X, whose rows are contiguous in n, moves as VW-element vectors from HBM to
 // LDS with the tube transform applied in between.  Offsets are 32-bit from the
 // base pointers (the host checks that every tensor has < 2^31 elements).
-template <typename T, int VW> struct VecIO;
-template <typename T> struct VecIO<T, 1> {
-  __device__ static void ld(const T* p, T* v) { v[0] = p[0]; }
-  __device__ static void st(T* p, const T* v) { p[0] = v[0]; }
-};
-template <> struct VecIO<float, 4> {
-  __device__ static void ld(const float* p, float* v) {
-    const float4 q = *reinterpret_cast<const float4*>(p);
-    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-  }
-  __device__ static void st(float* p, const float* v) {
-    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-  }
-};
-template <> struct VecIO<double, 2> {
-  __device__ static void ld(const double* p, double* v) {
-    const double2 q = *reinterpret_cast<const double2*>(p);
-    v[0] = q.x; v[1] = q.y;
-  }
-  __device__ static void st(double* p, const double* v) {
-    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
-  }
-};
 
 template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA, int VW>
 __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa_, const FusedArgs* grp, const int4* bmap) {
@@ -609,6 +586,7 @@ struct FusedLaunch {
   dctk_ctx ctx;
   hipStream_t s;
   hipEvent_t e0, e1;
+  int tile;  // output tile edge chosen by the autotuner (16, 32, 64), 0: by problem size
 };
 
 template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK>
@@ -633,8 +611,9 @@ static hipError_t launch_fused_mn_p(const FusedLaunch& L, const FusedArgs& fa, i
   const int64_t t32 = (int64_t)((fa.M + 31) / 32) * ((fa.N + 31) / 32);
   const int64_t t64 = (int64_t)((fa.M + 63) / 64) * ((fa.N + 63) / 64);
   const int ncu = num_cus();
-  if (t32 < ncu) return launch_fused_mn_cfg<T, PMAX, EXACT, 16, 16, 4, BK16>(L, fa, ta, vec, nblocks_out);
-  if (t64 < ncu || sizeof(T) == 8 || PMAX > 4 || t64 > kRedBlocks)
+  if (L.tile == 16 || (L.tile == 0 && t32 < ncu))
+    return launch_fused_mn_cfg<T, PMAX, EXACT, 16, 16, 4, BK16>(L, fa, ta, vec, nblocks_out);
+  if (L.tile == 32 || (L.tile == 0 && (t64 < ncu || sizeof(T) == 8 || PMAX > 4)) || t64 > kRedBlocks)
     return launch_fused_mn_cfg<T, PMAX, EXACT, 32, 32, 1, BK>(L, fa, ta, vec, nblocks_out);
   return launch_fused_mn_cfg<T, PMAX, EXACT, 64, 64, 1, BK>(L, fa, ta, vec, nblocks_out);
 }
@@ -672,8 +651,9 @@ static hipError_t launch_fused_p(const FusedLaunch& L, const FusedArgs& fa, int 
   const int64_t t32 = (int64_t)((fa.M + 31) / 32) * ((fa.N + 31) / 32);
   const int64_t t64 = (int64_t)((fa.M + 63) / 64) * ((fa.N + 63) / 64);
   const int ncu = num_cus();
-  if (t32 < ncu) return launch_fused_cfg<TI, TV, PMAX, EXACT, 16, 16, 4, BK16>(L, fa, ta, nblocks_out);
-  if (t64 < ncu || sizeof(TI) == 8 || PMAX > 4 || t64 > kRedBlocks)
+  if (L.tile == 16 || (L.tile == 0 && t32 < ncu))
+    return launch_fused_cfg<TI, TV, PMAX, EXACT, 16, 16, 4, BK16>(L, fa, ta, nblocks_out);
+  if (L.tile == 32 || (L.tile == 0 && (t64 < ncu || sizeof(TI) == 8 || PMAX > 4)) || t64 > kRedBlocks)
     return launch_fused_cfg<TI, TV, PMAX, EXACT, 32, 32, 1, BK32>(L, fa, ta, nblocks_out);
   return launch_fused_cfg<TI, TV, PMAX, EXACT, 64, 64, 1, BK64>(L, fa, ta, nblocks_out);
 }
@@ -709,7 +689,7 @@ hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, v
     fa.Gout = op->Gf + go * pp;
   }
   fa.ctl = ctl;
-  FusedLaunch L{op->ctx, s, nullptr, nullptr};
+  FusedLaunch L{op->ctx, s, nullptr, nullptr, op->tune[adjoint ? 1 : 0][1]};
   if (!recording(op->ctx)) prof_kernel(op->ctx, adjoint ? PROF_FUSED_ADJ : PROF_FUSED_FWD, &L.e0, &L.e1);
   switch (op->gemm_dtype) {
     case DCTK_F64: return launch_fused_mn<double>(L, fa, adjoint, nblocks_out);

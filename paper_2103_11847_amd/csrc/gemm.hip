@@ -163,6 +163,202 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs ga_, const GemmArgs*
     }
 }
 
+// FP32 / FP64 slice GEMM with 16-byte global loads (VW elements) along each
+// operand's contiguous dimension and LDS tiles kept in that same orientation:
+// A~ as [m][k] (or [k][m] when transposed), the right operand as [k][n] (or
+// [n][k]).  Rows of the [.][k] tiles carry a 16-byte pad and those of the
+// [k][.] tiles a 64-byte pad, so the 16-byte stores and the MFMA operand reads
+// (16 rows x 4 k per instruction) hit distinct banks.  4 waves in 2 x 2, each
+// owning (BM/2) x (BN/2) as 16 x 16 blocks; the next chunk is prefetched into
+// registers while the current one is multiplied.  Out-of-range elements are
+// loaded from a clamped address and replaced by zero (no branches per load).
+template <typename T, int BM, int BN, int BK, bool TA, bool TB, int VW>
+__global__ __launch_bounds__(256) void gemm_mn_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
+  typedef Mfma<T> MF;
+  typedef typename MF::frag_t frag_t;
+  constexpr int KSTEP = MF::KSTEP;
+  static_assert(KSTEP == 4 && MF::EPL == 1, "32/64-bit MFMA only");
+  constexpr int PADK = 16 / (int)sizeof(T), PADR = 64 / (int)sizeof(T);
+  constexpr int LDAK = BK + PADK, LDAM = BM + PADR;   // A as [m][k] / [k][m]
+  constexpr int LDBK = BK + PADK, LDBN = BN + PADR;   // B as [n][k] / [k][n]
+  constexpr int A_LDS = TA ? BK * LDAM : BM * LDAK;
+  constexpr int B_LDS = TB ? BN * LDBK : BK * LDBN;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  // vectors per chunk and per thread
+  constexpr int A_V = BM * BK / VW, B_V = BN * BK / VW;
+  constexpr int A_PER = (A_V + 255) / 256, B_PER = (B_V + 255) / 256;
+  static_assert(FM >= 1 && FN >= 1, "tile");
+  static_assert(BK % KSTEP == 0 && BK % VW == 0 && BM % VW == 0 && BN % VW == 0, "chunk");
+
+  VBlock vb;
+  const GemmArgs ga = pick_args(ga_, grp, bmap, vb);
+  if (!gate_open(ga.g)) return;
+  __shared__ __attribute__((aligned(16))) T As[A_LDS];
+  __shared__ __attribute__((aligned(16))) T Bs[B_LDS];
+
+  const int M = ga.M, N = ga.N, K = ga.K;
+  const T* __restrict__ A = (const T*)ga.A + (int64_t)vb.z * ga.sA;
+  const T* __restrict__ B = (const T*)ga.B + (int64_t)vb.z * ga.sB;
+  T* __restrict__ C = (T*)ga.C + (int64_t)vb.z * ga.sC;
+  const int64_t lda = ga.lda, ldb = ga.ldb, ldc = ga.ldc;
+  const int m0 = vb.y * BM, n0 = vb.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // chunk coordinates of vector u of this thread: (row r, contiguous offset c)
+  // A: TA -> rows are k (BK of them), vectors along m; else rows m, vectors along k
+  constexpr int A_ROWV = TA ? BM / VW : BK / VW;
+  constexpr int B_ROWV = TB ? BK / VW : BN / VW;
+  T ra[A_PER][VW], rb[B_PER][VW];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u) {
+      const int idx = tid + u * 256;
+      const int r = idx / A_ROWV, c = (idx - r * A_ROWV) * VW;
+      const int gm = m0 + (TA ? c : r), gk = k0 + (TA ? r : c);
+      const bool ok = (A_V % 256 == 0 || idx < A_V) && gm < M && gk < K;
+      const int64_t off = ok ? (TA ? (int64_t)gk * lda + gm : (int64_t)gm * lda + gk) : 0;
+      VecIO<T, VW>::ld(A + off, ra[u]);
+      if (!ok) {
+#pragma unroll
+        for (int v = 0; v < VW; ++v) ra[u][v] = (T)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < B_PER; ++u) {
+      const int idx = tid + u * 256;
+      const int r = idx / B_ROWV, c = (idx - r * B_ROWV) * VW;
+      const int gn = n0 + (TB ? r : c), gk = k0 + (TB ? c : r);
+      const bool ok = (B_V % 256 == 0 || idx < B_V) && gn < N && gk < K;
+      const int64_t off = ok ? (TB ? (int64_t)gn * ldb + gk : (int64_t)gk * ldb + gn) : 0;
+      VecIO<T, VW>::ld(B + off, rb[u]);
+      if (!ok) {
+#pragma unroll
+        for (int v = 0; v < VW; ++v) rb[u][v] = (T)0;
+      }
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int u = 0; u < A_PER; ++u) {
+      const int idx = tid + u * 256;
+      if (A_V % 256 == 0 || idx < A_V) {
+        const int r = idx / A_ROWV, c = (idx - r * A_ROWV) * VW;
+        VecIO<T, VW>::st(&As[r * (TA ? LDAM : LDAK) + c], ra[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < B_PER; ++u) {
+      const int idx = tid + u * 256;
+      if (B_V % 256 == 0 || idx < B_V) {
+        const int r = idx / B_ROWV, c = (idx - r * B_ROWV) * VW;
+        VecIO<T, VW>::st(&Bs[r * (TB ? LDBK : LDBN) + c], rb[u]);
+      }
+    }
+  };
+
+  frag_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = (T)0;
+
+  load_chunk(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    store_chunk();
+    __syncthreads();
+    if (k0 + BK < K) load_chunk(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += KSTEP) {
+      const T* ap[FM];
+      const T* bp[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int m = wm * WM + i * 16 + lr;
+        ap[i] = TA ? &As[(ks + lk) * LDAM + m] : &As[m * LDAK + ks + lk];
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = wn * WN + j * 16 + lr;
+        bp[j] = TB ? &Bs[n * LDBK + ks + lk] : &Bs[(ks + lk) * LDBN + n];
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = MF::mac(ap[i], bp[j], acc[i][j]);
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * WN + j * 16 + lr;
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + (MF::ROWS_STRIDED ? lk + 4 * r : lk * 4 + r);
+        if (row < M) C[(int64_t)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+template <typename T, int BM, int BN, int BK>
+static hipError_t launch_gemm_mn(dctk_ctx ctx, hipStream_t s, const GemmArgs& ga, int ta, int tb, bool vec,
+                                 int batch) {
+  const dim3 grid((unsigned)((ga.N + BN - 1) / BN), (unsigned)((ga.M + BM - 1) / BM), (unsigned)batch);
+  constexpr int VW = 16 / (int)sizeof(T);
+#define DCTK_GMN(TA_, TB_, VW_) return launch_kernel(ctx, s, gemm_mn_kernel<T, BM, BN, BK, TA_, TB_, VW_>, grid, 256, 0, ga)
+#define DCTK_GMN_V(TA_, TB_)    \
+  do {                          \
+    if (vec) DCTK_GMN(TA_, TB_, VW); \
+    DCTK_GMN(TA_, TB_, 1);      \
+  } while (0)
+  if (!ta && !tb) DCTK_GMN_V(false, false);
+  if (ta && !tb) DCTK_GMN_V(true, false);
+  if (!ta && tb) DCTK_GMN_V(false, true);
+  DCTK_GMN_V(true, true);
+#undef DCTK_GMN_V
+#undef DCTK_GMN
+}
+
+// FP32 / FP64 GEMMs with the output in the input type: 128 x 128 tiles while
+// they give every CU two tiles, then 64 x 64 while they cover the CUs, else 32 x 32.
+template <typename T>
+static hipError_t launch_gemm_vec(dctk_ctx ctx, hipStream_t s, int M, int N, int K, const void* A, int64_t lda,
+                                  int64_t sA, int ta, const void* B, int64_t ldb, int64_t sB, int tb, void* C,
+                                  int64_t ldc, int64_t sC, int batch, Gate g, int num_cus, int tile) {
+  GemmArgs ga{};
+  ga.M = M;
+  ga.N = N;
+  ga.K = K;
+  ga.A = A;
+  ga.lda = lda;
+  ga.sA = sA;
+  ga.B = B;
+  ga.ldb = ldb;
+  ga.sB = sB;
+  ga.C = C;
+  ga.ldc = ldc;
+  ga.sC = sC;
+  ga.g = g;
+  constexpr int VW = 16 / (int)sizeof(T);
+  const bool vec = M % VW == 0 && N % VW == 0 && K % VW == 0 && lda % VW == 0 && ldb % VW == 0 &&
+                   sA % VW == 0 && sB % VW == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0;
+  const int64_t t128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128) * batch;
+  const int64_t t64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64) * batch;
+  constexpr int BK = sizeof(T) == 8 ? 16 : 32;
+  if (sizeof(T) == 4 && (tile == 128 || (tile == 0 && t128 >= 2 * (int64_t)num_cus)))
+    return launch_gemm_mn<T, 128, 128, 16>(ctx, s, ga, ta, tb, vec, batch);
+  if (tile == 64 || tile == 128 || (tile == 0 && t64 >= (int64_t)num_cus))
+    return launch_gemm_mn<T, 64, 64, BK>(ctx, s, ga, ta, tb, vec, batch);
+  return launch_gemm_mn<T, 32, 32, BK>(ctx, s, ga, ta, tb, vec, batch);
+}
+
 template <typename TI, typename TO, int BM, int BN>
 static hipError_t launch_gemm_tile(dctk_ctx ctx, hipStream_t s, int M, int N, int K, const void* A, int64_t lda,
                                    int64_t sA, int ta, const void* B, int64_t ldb, int64_t sB, int tb,
@@ -193,10 +389,10 @@ static hipError_t launch_gemm_tile(dctk_ctx ctx, hipStream_t s, int M, int N, in
 template <typename TI, typename TO>
 static hipError_t launch_gemm_t(dctk_ctx ctx, hipStream_t s, int M, int N, int K, const void* A, int64_t lda, int64_t sA,
                                 int ta, const void* B, int64_t ldb, int64_t sB, int tb, void* C, int64_t ldc,
-                                int64_t sC, int batch, Gate g, int num_cus) {
+                                int64_t sC, int batch, Gate g, int num_cus, int tile) {
   // 64 x 64 tiles when they fill the chip, 32 x 32 otherwise.
   int64_t tiles64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64) * batch;
-  if (tiles64 >= 2 * (int64_t)num_cus)
+  if (tile == 64 || tile == 128 || (tile == 0 && tiles64 >= 2 * (int64_t)num_cus))
     return launch_gemm_tile<TI, TO, 64, 64>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
   return launch_gemm_tile<TI, TO, 32, 32>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
 }
@@ -206,21 +402,21 @@ static int g_num_cus = 256;
 hipError_t launch_gemm(dctk_ctx ctx, hipStream_t s, int in_dtype, int out_acc, int M, int N, int K,
                        const void* A, int64_t lda, int64_t sA, int ta,
                        const void* B, int64_t ldb, int64_t sB, int tb,
-                       void* C, int64_t ldc, int64_t sC, int batch, Gate g) {
+                       void* C, int64_t ldc, int64_t sC, int batch, Gate g, int tile) {
   // out_acc = 1: output in the accumulator type; 0: output in the input type
   switch (in_dtype) {
     case DCTK_F64:
-      return launch_gemm_t<double, double>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+      return launch_gemm_vec<double>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus, tile);
     case DCTK_F32:
-      return launch_gemm_t<float, float>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+      return launch_gemm_vec<float>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus, tile);
     case DCTK_BF16:
       if (out_acc)
-        return launch_gemm_t<bf16_t, float>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
-      return launch_gemm_t<bf16_t, bf16_t>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+        return launch_gemm_t<bf16_t, float>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus, tile);
+      return launch_gemm_t<bf16_t, bf16_t>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus, tile);
     case DCTK_F16:
       if (out_acc)
-        return launch_gemm_t<f16_t, float>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
-      return launch_gemm_t<f16_t, f16_t>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus);
+        return launch_gemm_t<f16_t, float>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus, tile);
+      return launch_gemm_t<f16_t, f16_t>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g, g_num_cus, tile);
     default:
       return hipErrorInvalidValue;
   }
@@ -229,14 +425,29 @@ hipError_t launch_gemm(dctk_ctx ctx, hipStream_t s, int in_dtype, int out_acc, i
 // ---- the c-product and its adjoint on an operator's workspaces ---------------
 static size_t dtype_size(int dt) { return dt == DCTK_F64 ? 8 : (dt == DCTK_F32 ? 4 : 2); }
 
+bool fused_eligible(dctk_op op) {
+  const int64_t nmax = op->n1 > op->n2 ? op->n1 : op->n2;
+  const bool small_offsets = op->p * op->n1 * op->n2 < (int64_t(1) << 31) && op->p * nmax * op->s < (int64_t(1) << 31);
+  return !op->two_sided && op->p <= kFusedMaxP && small_offsets;
+}
+
+// Without a tuned choice: the fused product while the problem is small enough to
+// be latency-bound (fewer 32 x 32 output tiles than CUs) and its transforms stay
+// cheap next to the slice GEMMs (p <= 4, or small slices); else transform, GEMM,
+// transform.
+bool use_fused(dctk_op op, int adjoint) {
+  const int path = op->tune[adjoint ? 1 : 0][0];
+  if (path >= 0) return path == 1;
+  const int64_t M = adjoint ? op->n2 : op->n1, K = adjoint ? op->n1 : op->n2, N = op->s;
+  const int64_t t32 = ((M + 31) / 32) * ((N + 31) / 32);
+  return t32 < g_num_cus && (op->p <= 4 || M * N * K <= (int64_t)192 * 192 * 192);
+}
+
 hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,
                     void* xnorm, const Ctl& ctl, int* nblocks_out) {
   dctk_ctx ctx = op->ctx;
-  const int64_t nmax = op->n1 > op->n2 ? op->n1 : op->n2;
-  const bool small_offsets = op->p * op->n1 * op->n2 < (int64_t(1) << 31) && op->p * nmax * op->s < (int64_t(1) << 31);
-  if (!op->two_sided && op->p <= kFusedMaxP && small_offsets) {
-    return launch_fused(op, s, adjoint, X, Y, src, xnorm, ctl, nblocks_out);
-  }
+  if (fused_eligible(op) && use_fused(op, adjoint)) return launch_fused(op, s, adjoint, X, Y, src, xnorm, ctl, nblocks_out);
+  const int tile = op->tune[adjoint ? 1 : 0][1];
   const int64_t p = op->p, n1 = op->n1, n2 = op->n2, sc = op->s;
   const int gdt = op->gemm_dtype, vdt = op->vec_dtype;
   const double* Gd = op->Gd;
@@ -270,14 +481,14 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   if (!op->two_sided) {
     // forward: (n1 x n2)(n2 x s);  adjoint: (n2 x n1 := A~^T)(n1 x s)
     e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
-                    op->xh, sc, rin * sc, 0, op->ch, sc, rout * sc, (int)p, g);
+                    op->xh, sc, rin * sc, 0, op->ch, sc, rout * sc, (int)p, g, tile);
   } else {
     e = launch_gemm(ctx, s, gdt, 0, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
-                    op->xh, sc, rin * sc, 0, op->th, sc, rout * sc, (int)p, g);
+                    op->xh, sc, rin * sc, 0, op->th, sc, rout * sc, (int)p, g, tile);
     if (e != hipSuccess) return e;
     // right factor: forward (rout x s)(s x s) with B~; adjoint with B~^T
     e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)sc, op->th, sc, rout * sc, 0,
-                    op->Bh, sc, sc * sc, adjoint ? 1 : 0, op->ch, sc, rout * sc, (int)p, g);
+                    op->Bh, sc, sc * sc, adjoint ? 1 : 0, op->ch, sc, rout * sc, (int)p, g, tile);
   }
   prof_end(ctx, PROF_GEMM);
   if (e != hipSuccess) return e;

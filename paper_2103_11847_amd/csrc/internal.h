@@ -316,6 +316,10 @@ struct dctk_op_s {
   int tube, gemm_dtype, vec_dtype;
   int64_t p, n1, n2, s;
   int two_sided;
+  // product path per direction [0 forward, 1 adjoint]: {path, tile} with path
+  // -1 by problem size, 0 unfused (transform, GEMM, transform), 1 fused; tile
+  // 0 by problem size, else the output tile edge (set by dctk_op_autotune)
+  int tune[2][2];
   void* Ah;       // p*n1*n2, gemm dtype
   void* Bh;       // p*s*s, gemm dtype (two-sided)
   double* Gd;     // 4 matrices p*p (L, L^-1, L^-T, L^T), FP64
@@ -444,11 +448,15 @@ hipError_t launch_tube(dctk_ctx ctx, hipStream_t st, int in_dtype, int out_dtype
                        const void* in, void* out, const double* Gd, const float* Gf,
                        const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi, int* nblocks_out);
 
-// C_k = op(A_k) op(B_k), batched over `batch`
+// C_k = op(A_k) op(B_k), batched over `batch`; tile 0: by problem size, else 32/64/128
 hipError_t launch_gemm(dctk_ctx ctx, hipStream_t s, int in_dtype, int out_acc, int M, int N, int K,
                        const void* A, int64_t lda, int64_t sA, int ta,
                        const void* B, int64_t ldb, int64_t sB, int tb,
-                       void* C, int64_t ldc, int64_t sC, int batch, Gate g);
+                       void* C, int64_t ldc, int64_t sC, int batch, Gate g, int tile = 0);
+
+// Whether an operator can take the fused product, and whether it does in a direction.
+bool fused_eligible(dctk_op op);
+bool use_fused(dctk_op op, int adjoint);
 
 // Fused c-product for one-sided operators with p <= kFusedMaxP.
 hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,

@@ -56,6 +56,31 @@ template <> struct Mfma<f16_t> {
   }
 };
 
+// 16-byte (or scalar) global/LDS accesses of VW consecutive elements
+template <typename T, int VW> struct VecIO;
+template <typename T> struct VecIO<T, 1> {
+  __device__ static void ld(const T* p, T* v) { v[0] = p[0]; }
+  __device__ static void st(T* p, const T* v) { p[0] = v[0]; }
+};
+template <> struct VecIO<float, 4> {
+  __device__ static void ld(const float* p, float* v) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  __device__ static void st(float* p, const float* v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+};
+template <> struct VecIO<double, 2> {
+  __device__ static void ld(const double* p, double* v) {
+    const double2 q = *reinterpret_cast<const double2*>(p);
+    v[0] = q.x; v[1] = q.y;
+  }
+  __device__ static void st(double* p, const double* v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  }
+};
+
 template <typename TO, typename TA> __device__ inline TO out_cvt(TA v) { return (TO)v; }
 template <> __device__ inline bf16_t out_cvt<bf16_t, float>(float v) { return float_to_bf16(v); }
 

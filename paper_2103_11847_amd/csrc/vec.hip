@@ -99,6 +99,21 @@ struct CombineArgs {
   const double* y;
   Gate g;
 };
+struct GramArgs {  // reorthogonalisation passes: multi-dot, coefficient sums, subtraction
+  int gx, gy, gz;
+  int vec;
+  int64_t n;
+  const void* basis;
+  int64_t bstride;
+  int nb;
+  int nblocks;       // coefficient sums: partials per coefficient
+  void* w;
+  double* part;
+  double* coef;
+  double* dst;       // coefficient sums: optional accumulation target (Arnoldi column)
+  int dst_stride;
+  Gate g;
+};
 struct ResetArgs {
   int gx, gy, gz;
   int full;
@@ -157,14 +172,20 @@ __global__ __launch_bounds__(kThreads) void k_axpy_sumsq(int64_t n, T* out, cons
 
 // partials of <basis_i, w> for i < nb: part[i * gridDim.x + block]
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_multidot(int64_t n, const T* basis, int64_t bstride, int nb,
-                                                       const T* w, double* part, bool vec, Gate g) {
-  if (!gate_open(g)) return;
+__global__ __launch_bounds__(kThreads) void k_multidot(GramArgs a_, const GramArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const GramArgs a = pick_args(a_, grp, bmap, vb);
+  if (!gate_open(a.g)) return;
+  const int64_t n = a.n, bstride = a.bstride;
+  const T* basis = (const T*)a.basis;
+  const T* w = (const T*)a.w;
+  const int nb = a.nb;
+  const bool vec = a.vec;
   __shared__ double sh[kThreads / 64 + 2];
   for (int i0 = 0; i0 < nb; i0 += 8) {
     double acc[8];
     for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-    DCTK_GRID_LOOP(e, n) {
+    DCTK_VGRID_LOOP(e, n, vb, a.gx) {
       double wv[4];
       ld4(w, e, n, vec, wv);
       for (int u = 0; u < 8 && i0 + u < nb; ++u) {
@@ -175,15 +196,20 @@ __global__ __launch_bounds__(kThreads) void k_multidot(int64_t n, const T* basis
     }
     for (int u = 0; u < 8 && i0 + u < nb; ++u) {
       const double t = block_sum_all(acc[u], sh);
-      if (threadIdx.x == 0) part[(int64_t)(i0 + u) * gridDim.x + blockIdx.x] = t;
+      if (threadIdx.x == 0) a.part[(int64_t)(i0 + u) * a.gx + vb.x] = t;
     }
   }
 }
 
 // one block: coef[i] = sum_b part[i * nblocks + b]; dst[i * dst_stride] += coef[i]
-__global__ __launch_bounds__(kThreads) void k_coef_finalize(const double* part, int nblocks, int nb, double* coef,
-                                                            double* dst, int dst_stride, Gate g) {
-  if (!gate_open(g)) return;
+__global__ __launch_bounds__(kThreads) void k_coef_finalize(GramArgs a_, const GramArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const GramArgs a = pick_args(a_, grp, bmap, vb);
+  if (!gate_open(a.g)) return;
+  const double* part = a.part;
+  const int nblocks = a.nblocks, nb = a.nb, dst_stride = a.dst_stride;
+  double* coef = a.coef;
+  double* dst = a.dst;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int i = wid; i < nb; i += (int)(blockDim.x >> 6)) {
     double v = 0.0;
@@ -198,13 +224,19 @@ __global__ __launch_bounds__(kThreads) void k_coef_finalize(const double* part, 
 
 // w -= sum_i coef[i] basis_i
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_subtract(int64_t n, T* w, const T* basis, int64_t bstride, int nb,
-                                                       const double* coef, bool vec, Gate g) {
-  if (!gate_open(g)) return;
+__global__ __launch_bounds__(kThreads) void k_subtract(GramArgs a_, const GramArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const GramArgs a = pick_args(a_, grp, bmap, vb);
+  if (!gate_open(a.g)) return;
+  const int64_t n = a.n, bstride = a.bstride;
+  T* w = (T*)a.w;
+  const T* basis = (const T*)a.basis;
+  const int nb = a.nb;
+  const bool vec = a.vec;
   __shared__ double sc[kRedVals];
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) sc[i] = coef[i];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) sc[i] = a.coef[i];
   __syncthreads();
-  DCTK_GRID_LOOP(e, n) {
+  DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double wv[4];
     ld4(w, e, n, vec, wv);
     for (int i = 0; i < nb; ++i) {
@@ -552,42 +584,51 @@ hipError_t launch_axpy_sumsq(dctk_ctx ctx, int dtype, int64_t n, void* out, cons
 
 hipError_t launch_multidot(dctk_ctx ctx, int dtype, int64_t n, const void* basis, int64_t stride, int nb,
                            const void* w, double* part, int* nblocks, Gate g) {
-  if (recording(ctx)) return hipErrorNotSupported;
   const unsigned grid = grid_for(n);
   if (nblocks) *nblocks = (int)grid;
   if (nb <= 0) return hipSuccess;
-  const bool vec = (n % 4 == 0) && (stride % 4 == 0) && al(basis) && al(w);
-  if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_multidot<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (const double*)basis,
-                       stride, nb, (const double*)w, part, vec, g);
-  else
-    hipLaunchKernelGGL(k_multidot<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (const float*)basis,
-                       stride, nb, (const float*)w, part, vec, g);
-  return hipGetLastError();
+  GramArgs a{};
+  a.vec = (n % 4 == 0) && (stride % 4 == 0) && al(basis) && al(w);
+  a.n = n;
+  a.basis = basis;
+  a.bstride = stride;
+  a.nb = nb;
+  a.w = const_cast<void*>(w);
+  a.part = part;
+  a.g = g;
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_multidot<double>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_multidot<float>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_coef_finalize(dctk_ctx ctx, const double* part, int nblocks, int nb, double* coef, double* dst,
                                 int dst_stride, Gate g) {
-  if (recording(ctx)) return hipErrorNotSupported;
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coef_finalize, dim3(1), dim3(kThreads), 0, ctx->stream, part, nblocks, nb, coef, dst,
-                     dst_stride, g);
-  return hipGetLastError();
+  GramArgs a{};
+  a.part = const_cast<double*>(part);
+  a.nblocks = nblocks;
+  a.nb = nb;
+  a.coef = coef;
+  a.dst = dst;
+  a.dst_stride = dst_stride;
+  a.g = g;
+  return launch_kernel(ctx, ctx->stream, k_coef_finalize, dim3(1), kThreads, 0, a);
 }
 
 hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* basis, int64_t stride, int nb,
                            const double* coef, Gate g) {
-  if (recording(ctx)) return hipErrorNotSupported;
   if (nb <= 0) return hipSuccess;
   const unsigned grid = grid_for(n);
-  const bool vec = (n % 4 == 0) && (stride % 4 == 0) && al(basis) && al(w);
-  if (dtype == DCTK_F64)
-    hipLaunchKernelGGL(k_subtract<double>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (double*)w,
-                       (const double*)basis, stride, nb, coef, vec, g);
-  else
-    hipLaunchKernelGGL(k_subtract<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, (float*)w,
-                       (const float*)basis, stride, nb, coef, vec, g);
-  return hipGetLastError();
+  GramArgs a{};
+  a.vec = (n % 4 == 0) && (stride % 4 == 0) && al(basis) && al(w);
+  a.n = n;
+  a.w = w;
+  a.basis = basis;
+  a.bstride = stride;
+  a.nb = nb;
+  a.coef = const_cast<double*>(coef);
+  a.g = g;
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_subtract<double>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_subtract<float>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x0, const void* basis,

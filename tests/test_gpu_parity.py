@@ -160,6 +160,63 @@ def test_low_precision_gemm_modes(ctx, gdt, u, two_sided):
     assert err <= bound
 
 
+PATHS = [(1, 16), (1, 32), (1, 64), (0, 32), (0, 64), (0, 128)]
+
+
+@pytest.mark.parametrize("gdt", [dk.DCTK_F64, dk.DCTK_F32])
+@pytest.mark.parametrize("shape,two_sided", [((3, 96, 80, 72), False), ((8, 64, 64, 64), False),
+                                             ((5, 40, 56, 44), False), ((3, 33, 37, 29), False),
+                                             ((4, 48, 48, 48), True), ((12, 70, 70, 36), False)])
+def test_every_product_path_and_tile(ctx, gdt, shape, two_sided):
+    """Each product path / tile the operator can take (fused 16/32/64, three kernels with
+    32/64/128 GEMM tiles) gives the oracle's product and adjoint."""
+    p, n1, n2, s = shape
+    w = W.tiny_random(sum(shape) + 5, p, n1, n2, s, two_sided)
+    op = Op(ctx, w["A"], w["B"], s, gdt)
+    X, Yin = to_gpu(w["X"], op.vt), to_gpu(w["Y"], op.vt)
+    ref, ref_t = op.oracle.apply(w["X"]), op.oracle.adjoint(w["Y"])
+    ran = 0
+    for path, tile in PATHS:
+        ok = True
+        for adj in (0, 1):
+            try:
+                dk.dctk_op_set_path(op.h, adj, path, tile)
+            except dk.DctkError:
+                ok = False
+        if not ok:
+            continue
+        say("path", shape, two_sided, gdt, path, tile)
+        Y = torch.empty((p, n1, s), dtype=op.vt, device="cuda:0")
+        dk.dctk_cprod(ctx, op.h, 1.0, X, 0.0, Y)
+        assert rel(to_np(Y), ref) <= TOL_PROD[gdt], (path, tile)
+        Z = torch.empty((p, n2, s), dtype=op.vt, device="cuda:0")
+        dk.dctk_cprod_T(ctx, op.h, 1.0, Yin, 0.0, Z)
+        assert rel(to_np(Z), ref_t) <= TOL_PROD[gdt], (path, tile)
+        ran += 1
+    fusable = not two_sided and p <= 8
+    assert ran >= (5 if fusable else 3) - (1 if fusable and gdt == dk.DCTK_F64 else 0)
+
+
+def test_autotune_keeps_products_exact(ctx):
+    p, n1, n2, s = 3, 128, 128, 128
+    w = W.tiny_random(77, p, n1, n2, s, False)
+    op = Op(ctx, w["A"], None, s, dk.DCTK_F32)
+    ch = dk.dctk_op_autotune(ctx, op.h, 5)
+    say("autotune", ch)
+    assert ch["fwd_path"] in (0, 1) and ch["adj_path"] in (0, 1)
+    assert ch["fwd_tile"] in (16, 32, 64, 128) and ch["adj_tile"] in (16, 32, 64, 128)
+    Y = torch.empty((p, n1, s), dtype=F32, device="cuda:0")
+    dk.dctk_cprod(ctx, op.h, 1.0, to_gpu(w["X"], F32), 0.0, Y)
+    assert rel(to_np(Y), op.oracle.apply(w["X"])) <= 1e-5
+    Z = torch.empty((p, n2, s), dtype=F32, device="cuda:0")
+    dk.dctk_cprod_T(ctx, op.h, 1.0, to_gpu(w["Y"], F32), 0.0, Z)
+    assert rel(to_np(Z), op.oracle.adjoint(w["Y"])) <= 1e-5
+    with pytest.raises(dk.DctkError):
+        dk.dctk_op_set_path(op.h, 0, 1, 128)
+    with pytest.raises(dk.DctkError):
+        dk.dctk_op_set_path(op.h, 2, 0, 32)
+
+
 def test_ragged_and_degenerate_shapes(ctx):
     """n = 1 slices and s = 1 (a single column) run and agree."""
     for (p, n1, n2, s) in [(1, 1, 1, 1), (3, 1, 5, 1), (4, 5, 1, 2), (2, 3, 3, 1)]:

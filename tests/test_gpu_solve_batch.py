@@ -81,10 +81,11 @@ SHAPES = [
 ]
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_equals_single_solves(ctx, use_graph):
+@pytest.mark.parametrize("use_graph,reorth", [(True, dk.DCTK_REORTH_NONE), (False, dk.DCTK_REORTH_NONE),
+                                              (True, dk.DCTK_REORTH_FULL)])
+def test_batch_equals_single_solves(ctx, use_graph, reorth):
     k = 12
-    opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0)
+    opts = dk.make_opts(k, reorth, 0, -1.0)
     insts = [Inst(ctx, *sh[:6], k, two_sided=sh[6]) for sh in SHAPES]
     try:
         # single solves first: the reference iterates and infos
@@ -156,8 +157,6 @@ def test_batch_validation(ctx):
         opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0)
         with pytest.raises(dk.DctkError):   # the same workspace twice
             dk.dctk_batch_create(ctx, [a.ws, a.ws], [a.C, a.C], [a.X, a.X], opts)
-        with pytest.raises(dk.DctkError):   # reorthogonalisation is not batched
-            dk.dctk_batch_create(ctx, [a.ws], [a.C], [a.X], dk.make_opts(k, dk.DCTK_REORTH_FULL, 0, -1.0))
         with pytest.raises(dk.DctkError):   # more steps than the workspace holds
             dk.dctk_batch_create(ctx, [a.ws], [a.C], [a.X], dk.make_opts(k + 1, dk.DCTK_REORTH_NONE, 0, -1.0))
         with pytest.raises(dk.DctkError):
