@@ -19,4 +19,7 @@ Modules
                global Arnoldi (Algorithm 2), DC-GMRES(m) (Algorithm 3)
   tikhonov  -- projected Tikhonov by SVD and GCV (eqs. leastsq, normeq2, gcv2)
   metrics   -- relative error and SNR (Sec. 4)
+  mlp       -- the learned stopping index / regularisation parameter: features
+               from the first GKB steps, the 16-64-64-2 GELU network with
+               bfloat16-rounded weights, its gradients, loss and Adam step
 """

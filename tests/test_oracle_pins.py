@@ -449,3 +449,76 @@ def test_snr_relerr_consistency():
     lhs = metrics.snr(Xt, X)
     rhs = 20 * np.log10(np.linalg.norm(Xt - Xt.mean()) / np.linalg.norm(Xt)) - 20 * np.log10(e)
     assert abs(lhs - rhs) < 1e-10
+
+
+# ---------------------------------------------------------------- learned stop MLP
+from oracle import mlp as omlp  # noqa: E402
+
+
+def test_mlp_gelu_closed_forms():
+    # GELU(0) = 0, GELU(x) -> x for large x, -> 0 for very negative x, and
+    # GELU(1) = Phi(1) with Phi(1) = 0.841344746068543 (standard normal table)
+    assert omlp.gelu(0.0) == 0.0
+    assert abs(float(omlp.gelu(1.0)) - 0.841344746068543) < 1e-15
+    assert abs(float(omlp.gelu(10.0)) - 10.0) < 1e-12
+    assert abs(float(omlp.gelu(-10.0))) < 1e-20
+    # derivative: Phi(0) = 1/2 at 0; against central differences elsewhere
+    assert abs(float(omlp.gelu_grad(0.0)) - 0.5) < 1e-15
+    for x in (-2.3, -0.4, 0.7, 1.9):
+        h = 1e-6
+        fd = (float(omlp.gelu(x + h)) - float(omlp.gelu(x - h))) / (2 * h)
+        assert abs(float(omlp.gelu_grad(x)) - fd) < 1e-8
+
+
+def test_mlp_zero_weights_output_is_bias():
+    P = np.zeros(omlp.N_PARAMS)
+    P[-2:] = [0.25, -1.5]
+    out, _ = omlp.forward(P, np.random.default_rng(0).standard_normal((5, 16)))
+    assert np.all(out == np.array([0.25, -1.5]))
+
+
+def test_mlp_gradients_central_differences():
+    rng = np.random.default_rng(3)
+    P = 0.3 * rng.standard_normal(omlp.N_PARAMS)
+    X = rng.standard_normal((7, 16))
+    T = rng.standard_normal((7, 2))
+    w = np.array([1.0, 0.5])
+
+    def loss(Pv):
+        out, _ = omlp.forward(Pv, X)
+        return omlp.loss_and_dout(out, T, w)[0]
+
+    out, cache = omlp.forward(P, X)
+    _, dout = omlp.loss_and_dout(out, T, w)
+    g = omlp.backward(P, cache, dout)
+    idx = rng.choice(omlp.N_PARAMS, 40, replace=False)
+    idx = np.concatenate([idx, [0, 1023, 1024, 1087, 1088, 5183, 5184, 5247, 5248, 5375, 5376, 5377]])
+    for i in idx:
+        e = np.zeros_like(P)
+        e[i] = 1e-6
+        fd = (loss(P + e) - loss(P - e)) / 2e-6
+        assert abs(g[i] - fd) <= 1e-7 * max(1.0, abs(fd)), i
+
+
+def test_mlp_bf16_rounding():
+    # exactly representable values stay; halfway cases go to even; 1 + 2^-9 rounds down to 1
+    vals = np.array([1.0, 0.5, -3.0, 1.0 + 2.0 ** -8, 1.0 + 2.0 ** -9, 1.0 + 3 * 2.0 ** -9], dtype=np.float32)
+    r = omlp.bf16_round(vals)
+    assert list(r) == [1.0, 0.5, -3.0, 1.0, 1.0, 1.0 + 2.0 ** -7]
+
+
+def test_mlp_features_definition():
+    alpha = np.array([2.0, 1.0, 0.5, 0.25, 0.2, 0.1, 0.05, 0.02, 0.01])
+    beta = np.array([4.0, 1.0, 1.0, 0.5, 0.5, 0.2, 0.1, 0.1, 0.05])
+    phibar = np.array([4.0, 2.0, 1.0, 0.5, 0.4, 0.3, 0.2, 0.1, 0.05])
+    f = omlp.features(alpha, beta, phibar)
+    assert f[0] == np.log(0.5) and f[8] == np.log(0.5)
+    assert f[7] == np.log(0.02 / 0.1) and f[15] == np.log(0.05 / 4.0)
+
+
+def test_mlp_adam_first_step_is_signed_lr():
+    # the first bias-corrected Adam step moves each parameter by lr * g / (|g| + eps)
+    P = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 0.0])
+    Pn, m, v = omlp.adam(P, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    assert np.allclose(Pn, P - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
