@@ -74,6 +74,7 @@ extern "C" {
 typedef struct dctk_ctx_s* dctk_ctx;
 typedef struct dctk_op_s* dctk_op;
 typedef struct dctk_krylov_s* dctk_krylov;
+typedef struct dctk_mlp_s* dctk_mlp;
 
 /* ---- context ---------------------------------------------------------- */
 /* Creates a context bound to HIP device `device` and the HIP stream
@@ -255,6 +256,62 @@ int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X,
  * DCTK_KRYLOV_ARNOLDI workspace of op.  Synchronises once to fill info. */
 int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, int cycles,
                          const dctk_solve_opts* opts, dctk_solve_info* info);
+
+/* Algorithm 5 at step count k from the bases a finished (or stepped) GKB
+ * workspace holds: the projected Tikhonov solution of the first k steps (k in
+ * [1, steps enqueued]; lambda fixed (> 0) or by GCV (< 0); opts->k_max, reorth
+ * and tol are ignored) and X = V_k (*) y.  The workspace is left as it was,
+ * apart from its recorded lambda / GCV.  Synchronises to fill info. */
+int dctk_krylov_project(dctk_ctx ctx, dctk_krylov ws, int k, const dctk_solve_opts* opts, void* X,
+                        dctk_solve_info* info);
+
+/* ---- learned stopping index and regularisation parameter ---------------- */
+/* A 16-64-64-2 network with GELU activations predicts, from the first 8 GKB
+ * steps, log lambda and the stopping index of DC-LSQR / DC-GK (the paper
+ * leaves both to the user or to GCV, Sec. 3.1 and Sec. 4).  Inputs: for j =
+ * 1..8, log(alpha_j / beta_j) and log(|phibar_{j+1}| / beta_1) (Algorithms 4
+ * and 6).  Outputs (t_lambda, t_k) are normalised: lambda = exp(t_lambda sigma
+ * + mu), k = round(t_k k_scale + k_offset) (dctk_mlp_set_scaling; defaults 0,
+ * 1, 40, 0; k_offset is a calibrated safety margin: stopping late costs steps,
+ * stopping early costs restoration error).
+ * Parameters: DCTK_MLP_PARAMS FP32 values [W1 (64x16), b1 (64), W2 (64x64),
+ * b2 (64), W3 (2x64), b3 (2)], weights row-major (output, input); every pass
+ * uses them rounded to bfloat16 and accumulates in FP32.  Training minimises
+ * (1/2B) sum_b [w_lambda (out_b0 - T_b0)^2 + w_k (out_b1 - T_b1)^2] with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  Device arrays: X is B x 16, outputs
+ * and targets B x 2, row-major FP32; B in [1, DCTK_MLP_MAX_BATCH].
+ * dctk_mlp_create: Xavier-uniform weights from a splitmix64 stream of `seed`,
+ *   zero biases.  Owns its parameters, Adam moments and scratch.
+ * dctk_mlp_set_params / get_params: host FP32 master values (set also resets
+ *   Adam); get may also return the bfloat16 bits (host_bf16, may be NULL).
+ * dctk_mlp_forward: out = network(X), async.
+ * dctk_mlp_gradient: grad (device, DCTK_MLP_PARAMS) of sum_b <dout_b, out_b>.
+ * dctk_mlp_train_step: one Adam step on the loss above; *loss (host, may be
+ *   NULL; synchronises when given) receives the loss before the step.
+ * dctk_mlp_features: the 16 inputs of a GKB workspace after >= 8 steps into
+ *   out16 (device); NaN when unavailable (fewer steps, breakdown).
+ * dctk_lsqr_learned_solve: DC-GK with the learned stop: 8 GKB steps, the
+ *   network's (lambda, k) (k clamped to [8, opts->k_max]), GKB steps up to k,
+ *   then Algorithm 5 at k with lambda = the prediction if GCV(prediction) <=
+ *   gate * min GCV (gate >= 1), else the GCV minimiser.  opts->lambda must be
+ *   < 0.  *pred_k gets k (-1: no valid prediction; then k_max steps and GCV),
+ *   *accepted 1 when the predicted lambda passed the gate.  Synchronises
+ *   twice (after the prediction and at the end). */
+#define DCTK_MLP_PARAMS 5378
+#define DCTK_MLP_MAX_BATCH (1 << 20)
+int dctk_mlp_create(dctk_ctx ctx, uint64_t seed, dctk_mlp* out);
+int dctk_mlp_destroy(dctk_mlp m);
+int dctk_mlp_set_params(dctk_ctx ctx, dctk_mlp m, const float* host);
+int dctk_mlp_get_params(dctk_ctx ctx, dctk_mlp m, float* host, uint16_t* host_bf16);
+int dctk_mlp_set_scaling(dctk_mlp m, double mu, double sigma, double k_scale, double k_offset);
+int dctk_mlp_forward(dctk_ctx ctx, dctk_mlp m, int B, const float* X, float* out);
+int dctk_mlp_gradient(dctk_ctx ctx, dctk_mlp m, int B, const float* X, const float* dout, float* grad);
+int dctk_mlp_train_step(dctk_ctx ctx, dctk_mlp m, int B, const float* X, const float* T, double w_lambda,
+                        double w_k, double lr, double* loss);
+int dctk_mlp_features(dctk_ctx ctx, dctk_krylov ws, float* out16);
+int dctk_lsqr_learned_solve(dctk_ctx ctx, dctk_krylov ws, dctk_mlp mlp, const void* C, void* X,
+                            const dctk_solve_opts* opts, double gate, dctk_solve_info* info, int* pred_k,
+                            int* accepted);
 
 /* ---- batches of independent solves ------------------------------------- */
 /* Many DC-LSQR / DC-GK solves (Algorithms 4, 5, 6) of independent problems

@@ -25,6 +25,8 @@ DCTK_KRYLOV_GKB, DCTK_KRYLOV_ARNOLDI = 0, 1
 DCTK_REORTH_NONE, DCTK_REORTH_V, DCTK_REORTH_FULL = 0, 1, 2
 DCTK_ORTHO_MGS, DCTK_ORTHO_CGS2 = 0, 1
 DCTK_BATCH_MAX = 256
+DCTK_MLP_PARAMS = 5378
+DCTK_MLP_MAX_BATCH = 1 << 20
 
 TUBES = {"th": DCTK_TUBE_TH, "dct2": DCTK_TUBE_DCT2}
 DTYPES = {"f64": DCTK_F64, "f32": DCTK_F32, "bf16": DCTK_BF16, "f16": DCTK_F16}
@@ -89,6 +91,18 @@ _SIGS = {
     "dctk_lsqr_tik_solve": (_I, [_P, _P, _P, _P, ctypes.POINTER(dctk_solve_opts), ctypes.POINTER(dctk_solve_info)]),
     "dctk_gmres_tik_solve": (_I, [_P, _P, _P, _P, _I, ctypes.POINTER(dctk_solve_opts),
                                   ctypes.POINTER(dctk_solve_info)]),
+    "dctk_krylov_project": (_I, [_P, _P, _I, ctypes.POINTER(dctk_solve_opts), _P, ctypes.POINTER(dctk_solve_info)]),
+    "dctk_mlp_create": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "dctk_mlp_destroy": (_I, [_P]),
+    "dctk_mlp_set_params": (_I, [_P, _P, ctypes.POINTER(ctypes.c_float)]),
+    "dctk_mlp_get_params": (_I, [_P, _P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint16)]),
+    "dctk_mlp_set_scaling": (_I, [_P, _D, _D, _D, _D]),
+    "dctk_mlp_forward": (_I, [_P, _P, _I, _P, _P]),
+    "dctk_mlp_gradient": (_I, [_P, _P, _I, _P, _P, _P]),
+    "dctk_mlp_train_step": (_I, [_P, _P, _I, _P, _P, _D, _D, _D, ctypes.POINTER(_D)]),
+    "dctk_mlp_features": (_I, [_P, _P, _P]),
+    "dctk_lsqr_learned_solve": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(dctk_solve_opts), _D,
+                                     ctypes.POINTER(dctk_solve_info), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "dctk_batch_create": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                ctypes.POINTER(dctk_solve_opts), _I, ctypes.POINTER(_P)]),
     "dctk_batch_run": (_I, [_P, _P]),
@@ -337,6 +351,74 @@ def dctk_gmres_tik_solve(ctx, ws, C, X, cycles, opts):
     _check(lib().dctk_gmres_tik_solve(ctx, ws, _ptr(C), _ptr(X), int(cycles), ctypes.byref(opts),
                                       ctypes.byref(info)), "dctk_gmres_tik_solve")
     return info
+
+
+def dctk_krylov_project(ctx, ws, k, opts, X):
+    """Algorithm 5 at step count k from a stepped GKB workspace into X."""
+    info = dctk_solve_info()
+    _check(lib().dctk_krylov_project(ctx, ws, int(k), ctypes.byref(opts), _ptr(X), ctypes.byref(info)),
+           "dctk_krylov_project")
+    return info
+
+
+def dctk_mlp_create(ctx, seed=0):
+    h = ctypes.c_void_p()
+    _check(lib().dctk_mlp_create(ctx, ctypes.c_uint64(seed), ctypes.byref(h)), "dctk_mlp_create")
+    return h.value
+
+
+def dctk_mlp_destroy(m):
+    return _check(lib().dctk_mlp_destroy(m), "dctk_mlp_destroy")
+
+
+def dctk_mlp_set_params(ctx, m, params):
+    """params: sequence of DCTK_MLP_PARAMS floats (host)."""
+    arr = (ctypes.c_float * DCTK_MLP_PARAMS)(*[float(x) for x in params])
+    return _check(lib().dctk_mlp_set_params(ctx, m, arr), "dctk_mlp_set_params")
+
+
+def dctk_mlp_get_params(ctx, m):
+    """Returns (FP32 master params, bfloat16 bit patterns) as Python lists."""
+    arr = (ctypes.c_float * DCTK_MLP_PARAMS)()
+    bits = (ctypes.c_uint16 * DCTK_MLP_PARAMS)()
+    _check(lib().dctk_mlp_get_params(ctx, m, arr, bits), "dctk_mlp_get_params")
+    return list(arr), list(bits)
+
+
+def dctk_mlp_set_scaling(m, mu, sigma, k_scale, k_offset=0.0):
+    return _check(lib().dctk_mlp_set_scaling(m, float(mu), float(sigma), float(k_scale), float(k_offset)),
+                  "dctk_mlp_set_scaling")
+
+
+def dctk_mlp_forward(ctx, m, X, out):
+    return _check(lib().dctk_mlp_forward(ctx, m, int(X.shape[0]), _ptr(X), _ptr(out)), "dctk_mlp_forward")
+
+
+def dctk_mlp_gradient(ctx, m, X, dout, grad):
+    return _check(lib().dctk_mlp_gradient(ctx, m, int(X.shape[0]), _ptr(X), _ptr(dout), _ptr(grad)),
+                  "dctk_mlp_gradient")
+
+
+def dctk_mlp_train_step(ctx, m, X, T, w_lambda, w_k, lr, want_loss=False):
+    loss = ctypes.c_double()
+    _check(lib().dctk_mlp_train_step(ctx, m, int(X.shape[0]), _ptr(X), _ptr(T), float(w_lambda), float(w_k),
+                                     float(lr), ctypes.byref(loss) if want_loss else None),
+           "dctk_mlp_train_step")
+    return loss.value if want_loss else None
+
+
+def dctk_mlp_features(ctx, ws, out16):
+    return _check(lib().dctk_mlp_features(ctx, ws, _ptr(out16)), "dctk_mlp_features")
+
+
+def dctk_lsqr_learned_solve(ctx, ws, m, C, X, opts, gate=1.05):
+    """Returns (info, predicted k or -1, 1 if the predicted lambda passed the gate)."""
+    info = dctk_solve_info()
+    k, acc = ctypes.c_int(), ctypes.c_int()
+    _check(lib().dctk_lsqr_learned_solve(ctx, ws, m, _ptr(C), _ptr(X), ctypes.byref(opts), float(gate),
+                                         ctypes.byref(info), ctypes.byref(k), ctypes.byref(acc)),
+           "dctk_lsqr_learned_solve")
+    return info, k.value, acc.value
 
 
 def dctk_batch_create(ctx, ws_list, C_list, X_list, opts, use_graph=True):

@@ -843,6 +843,69 @@ int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, co
   return lsqr_info(ctx, ws, opts, info);
 }
 
+int dctk_krylov_project(dctk_ctx ctx, dctk_krylov ws, int k, const dctk_solve_opts* opts, void* X,
+                        dctk_solve_info* info) {
+  int r = ws_check(ctx, ws, DCTK_KRYLOV_GKB);
+  if (r) return r;
+  if (!X || !opts) return DCTK_EINVAL;
+  if (!ws->initialised || k < 1 || k > ws->host_steps) return DCTK_EINVAL;
+  if (opts->gcv_mode != 0 && opts->gcv_mode != 1) return DCTK_EINVAL;
+  if (std::isnan(opts->lambda) || std::isinf(opts->lambda) || opts->lambda == 0.0) return DCTK_EINVAL;
+  dctk_op op = ws->op;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  DCTK_HIP(ctx, launch_projected(ctx, ws->st, 1, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda, k));
+  // the basis vectors beyond a breakdown are never formed: combine min(k, steps) of them
+  DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, k,
+                               &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
+  HostState hs;
+  if ((r = read_state(ctx, ws, &hs))) return r;
+  if (info) {
+    info->iters = hs.steps < k ? hs.steps : k;
+    info->status = hs.status;
+    info->converged = hs.converged;
+    info->cycles = 0;
+    info->lambda = hs.lambda;
+    info->resnorm = lsqr_resnorm(ctx, ws, info->iters);
+    info->gcv = opts->lambda < 0.0 ? hs.gcv : NAN;
+  }
+  return hs.status;
+}
+
+int dctk_lsqr_learned_solve(dctk_ctx ctx, dctk_krylov ws, dctk_mlp mlp, const void* C, void* X,
+                            const dctk_solve_opts* opts, double gate, dctk_solve_info* info, int* pred_k,
+                            int* accepted) {
+  int r = ws_check(ctx, ws, DCTK_KRYLOV_GKB);
+  if (r) return r;
+  if (!C || !X || !mlp) return DCTK_EINVAL;
+  if ((r = check_solve_opts(opts, ws))) return r;
+  if (opts->lambda >= 0.0 || !(gate >= 1.0) || !std::isfinite(gate)) return DCTK_EINVAL;
+  const int kf = 8;  // steps whose scalars feed the network
+  if (opts->k_max < kf) return DCTK_EINVAL;
+  dctk_op op = ws->op;
+  const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
+  if (ranges_overlap(C, (size_t)(op->p * op->n1 * op->s) * ve, X, (size_t)(op->p * op->n2 * op->s) * ve))
+    return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  ws->reorth = opts->reorth;
+  DCTK_HIP(ctx, gkb_init_impl(ctx, ws, C, ws->X, opts->tol));
+  for (int j = 1; j <= kf; ++j) DCTK_HIP(ctx, gkb_step_impl(ctx, ws, j, ws->X));
+  float pred[5];
+  DCTK_HIP(ctx, mlp_predict(ctx, mlp, ws->st, kf, opts->k_max, pred));
+  const bool valid = pred[4] > 0.5f;
+  const int kstop = valid ? (int)pred[3] : opts->k_max;
+  for (int j = kf + 1; j <= kstop; ++j) DCTK_HIP(ctx, gkb_step_impl(ctx, ws, j, ws->X));
+  ws->host_steps = kstop;
+  ws->initialised = 1;
+  DCTK_HIP(ctx, launch_projected(ctx, ws->st, 1, opts->gcv_mode, -1.0, 0, valid ? (double)pred[2] : -1.0, gate));
+  DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, kstop,
+                               &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
+  double gate_ok = 0.0;
+  DCTK_HIP(ctx, hipMemcpyAsync(&gate_ok, &ws->st->gate_ok, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  if (pred_k) *pred_k = valid ? kstop : -1;
+  if (accepted) *accepted = gate_ok > 0.5 ? 1 : 0;
+  return lsqr_info(ctx, ws, opts, info);
+}
+
 int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, int cycles,
                          const dctk_solve_opts* opts, dctk_solve_info* info) {
   int r = ws_check(ctx, ws, DCTK_KRYLOV_ARNOLDI);

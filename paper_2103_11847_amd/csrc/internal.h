@@ -44,7 +44,8 @@ struct KState {
   double gcv;       // GCV value at lambda
   double resnorm;   // GMRES: ||C - M(X)||
   double sweeps;    // one-sided Jacobi sweeps of the last projected solve
-  double pad[2];
+  double gate_ok;   // 1 when a proposed lambda passed the GCV gate of the last projected solve
+  double pad;
   double alpha[kMaxK + 2];          // GKB alpha_1.. at [0..]
   double beta[kMaxK + 2];           // GKB beta_1.. at [0..]
   double rhobar[kMaxK + 2];         // LSQR rhobar_{j+1} at [j]
@@ -514,6 +515,13 @@ int lsqr_info(dctk_ctx ctx, dctk_krylov ws, const dctk_solve_opts* opts, dctk_so
 
 // projected FP64 problem (projected.hip): bidiag = 1 reads alpha/beta, else H.
 // Writes st->y[0..k), st->lambda, st->gcv.
-hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, double lambda);
+// k_use > 0 projects at min(k_use, steps); lam_cand > 0 (with GCV) is kept when its GCV
+// value is <= gate * the minimum (st->gate_ok records the decision).
+hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, double lambda, int k_use = 0,
+                            double lam_cand = -1.0, double gate = 1.0);
+
+// learned stop (mlp.hip): features of st -> network -> host pred[5] =
+// {t_lambda, t_k, lambda, k, valid}; synchronises
+hipError_t mlp_predict(dctk_ctx ctx, dctk_mlp m, const KState* st, int kmin, int kmax, float* host_pred);
 
 }  // namespace dctk

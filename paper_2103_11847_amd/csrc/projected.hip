@@ -113,8 +113,11 @@ struct ProjArgs {
   int gx, gy, gz;
   int bidiag;
   int gcv_mode;
+  int k_use;         // > 0: project at min(k_use, steps) instead of all steps taken
   KState* st;
-  double lam_fixed;
+  double lam_fixed;  // >= 0: this lambda; < 0: GCV
+  double lam_cand;   // > 0 (with GCV): a proposed lambda, kept when GCV(lam_cand) <= gate * min GCV
+  double gate;
 };
 
 __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* group, const int4* bmap) {
@@ -122,7 +125,8 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
   const ProjArgs a = pick_args(a_, group, bmap, vb);
   KState* st = a.st;
   const int bidiag = a.bidiag, gcv_mode = a.gcv_mode;
-  const double lam_fixed = a.lam_fixed;
+  const double lam_fixed = a.lam_fixed, lam_cand = a.lam_cand, gate = a.gate;
+  const int k_use = a.k_use;
   if (((volatile KState*)st)->halt) return;
   __shared__ double G[kMaxK * kLdG];      // G[c * kLdG + r]: column c of the matrix
   __shared__ double Vm[kMaxK * kMaxK];    // Vm[c * kMaxK + r]: right singular vectors
@@ -136,7 +140,9 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int k = st->steps;
+  if (k_use > 0 && k_use < k) k = k_use;
   if (k > kMaxK) k = kMaxK;
+  if (tid == 0) st->gate_ok = 0.0;
   const int rows = k + 1;
   const double beta = bidiag ? st->beta[0] : st->beta0;
   if (k <= 0) {
@@ -340,6 +346,15 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
         if (fm <= gridv[ib]) { s_lam = pow(10.0, tm); s_gcv = fm; }
         else { s_lam = pow(10.0, t0 + (double)ib * dt); s_gcv = gridv[ib]; }
       }
+      // a proposed lambda is kept when its GCV value is within the gate of the minimum
+      if (lam_cand > 0.0) {
+        const double fcand = gcv_wave(gcv_mode, lam_cand, k, ssort, gs, s_gperp2, lane);
+        if (lane == 0) {
+          const bool keep = fcand <= gate * s_gcv;
+          st->gate_ok = keep ? 1.0 : 0.0;
+          if (keep) { s_lam = lam_cand; s_gcv = fcand; }
+        }
+      }
     }
   }
   __syncthreads();
@@ -361,12 +376,16 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
   }
 }
 
-hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, double lambda) {
+hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, double lambda, int k_use,
+                            double lam_cand, double gate) {
   ProjArgs a{};
   a.bidiag = bidiag;
   a.gcv_mode = gcv_mode;
+  a.k_use = k_use;
   a.st = st;
   a.lam_fixed = lambda;
+  a.lam_cand = lam_cand;
+  a.gate = gate;
   return launch_kernel(ctx, ctx->stream, k_projected, dim3(1), kPT, 0, a);
 }
 

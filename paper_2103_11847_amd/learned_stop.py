@@ -1,0 +1,177 @@
+"""Training data, training and evaluation of the learned stopping rule.
+
+The network of dctk_mlp_* is trained on solves the library itself runs: for
+each training problem, one DC-GK solve of k_max Golub-Kahan steps fills a
+workspace; the 16 features come from its first 8 steps (dctk_mlp_features);
+Algorithm 5 is then evaluated at every step count k (dctk_krylov_project, GCV
+lambda) and the restoration error ||X_k - X_true|| / ||X_true|| picks the
+label: the earliest k >= 8 whose error is within `near` of the smallest one,
+with the GCV lambda at that k.  The labels need X_true, so they exist only for
+synthetic problems; at run time the network sees the features alone.
+
+Every step runs in the HIP library; this module only moves data.
+"""
+import numpy as np
+
+import paper_2103_11847_amd as dk
+
+K_FEAT = 8
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def observation(ctx, inst, dev):
+    """C = M(X_true) + noise at relative level nu (FP64 product of the library), FP32."""
+    torch = _torch()
+    A64 = torch.from_numpy(inst["A"]).to(dev)
+    n2s = inst["X_true"].shape
+    op64 = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F64, A64, n2s[2])
+    try:
+        Xt = torch.from_numpy(inst["X_true"]).to(dev)
+        Ch = torch.empty((inst["A"].shape[0], inst["A"].shape[1], n2s[2]), dtype=torch.float64, device=dev)
+        dk.dctk_cprod(ctx, op64, 1.0, Xt, 0.0, Ch)
+    finally:
+        dk.dctk_op_destroy(op64)
+    N0 = torch.from_numpy(inst["N0"]).to(dev)
+    C = Ch + inst["nu"] * torch.linalg.norm(Ch) / torch.linalg.norm(N0) * N0
+    return A64, C.to(torch.float32).contiguous(), Xt.to(torch.float32)
+
+
+def label_instance(ctx, inst, k_max=40, near=1.02, gemm=dk.DCTK_F32, dev="cuda:0"):
+    """Features, per-k restoration errors and GCV lambdas, and the label (k*, lambda*)."""
+    torch = _torch()
+    A64, C, Xt = observation(ctx, inst, dev)
+    p, n1, n2 = inst["A"].shape
+    s = inst["X_true"].shape[2]
+    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gemm, A64, s)
+    ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k_max)
+    try:
+        X = torch.empty((p, n2, s), dtype=torch.float32, device=dev)
+        info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, dk.make_opts(k_max, dk.DCTK_REORTH_NONE, 0, -1.0))
+        feat = torch.empty(16, dtype=torch.float32, device=dev)
+        dk.dctk_mlp_features(ctx, ws, feat)
+        nx = torch.linalg.norm(Xt)
+        errs, lams = [], []
+        for k in range(1, info.iters + 1):
+            ik = dk.dctk_krylov_project(ctx, ws, k, dk.make_opts(k_max, dk.DCTK_REORTH_NONE, 0, -1.0), X)
+            errs.append(float(torch.linalg.norm(X - Xt) / nx))
+            lams.append(ik.lam)
+    finally:
+        dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
+    errs = np.array(errs)
+    best = float(errs.min())
+    ks = [k for k in range(K_FEAT, len(errs) + 1) if errs[k - 1] <= near * best]
+    kstar = ks[0] if ks else int(np.argmin(errs)) + 1
+    return {"features": feat.cpu().numpy(), "errors": errs, "lambdas": np.array(lams), "k": kstar,
+            "lambda": lams[kstar - 1], "err_kmax": float(errs[-1]), "err_best": best}
+
+
+def make_dataset(ctx, instances, k_max=40, near=1.02, gemm=dk.DCTK_F32):
+    rows = [label_instance(ctx, inst, k_max, near, gemm) for inst in instances]
+    F = np.stack([r["features"] for r in rows]).astype(np.float32)
+    K = np.array([r["k"] for r in rows], dtype=np.float64)
+    L = np.array([r["lambda"] for r in rows], dtype=np.float64)
+    ok = np.all(np.isfinite(F), axis=1) & np.isfinite(L) & (L > 0)
+    return {"F": F[ok], "k": K[ok], "lambda": L[ok], "rows": [r for r, o in zip(rows, ok) if o]}
+
+
+def targets(data, k_scale=40.0):
+    """Normalised targets (t_lambda, t_k) and the scaling (mu, sigma, k_scale)."""
+    ll = np.log(data["lambda"])
+    mu, sigma = float(ll.mean()), float(max(ll.std(), 1e-3))
+    T = np.stack([(ll - mu) / sigma, data["k"] / k_scale], axis=1).astype(np.float32)
+    return T, (mu, sigma, k_scale)
+
+
+def train(ctx, mlp, F, T, steps=1500, batch=256, lr=2e-3, w_lambda=1.0, w_k=4.0, seed=0, dev="cuda:0"):
+    """Adam on mini-batches drawn without replacement per epoch; returns the loss curve."""
+    torch = _torch()
+    Fd = torch.from_numpy(np.ascontiguousarray(F)).to(dev)
+    Td = torch.from_numpy(np.ascontiguousarray(T)).to(dev)
+    rng = np.random.default_rng(seed)
+    n = F.shape[0]
+    b = min(batch, n)
+    order = rng.permutation(n)
+    pos = 0
+    curve = []
+    for step in range(steps):
+        if pos + b > n:
+            order = rng.permutation(n)
+            pos = 0
+        idx = torch.from_numpy(order[pos:pos + b]).to(dev)
+        pos += b
+        Xb = Fd.index_select(0, idx).contiguous()
+        Tb = Td.index_select(0, idx).contiguous()
+        want = step % 100 == 0 or step == steps - 1
+        loss = dk.dctk_mlp_train_step(ctx, mlp, Xb, Tb, w_lambda, w_k, lr, want_loss=want)
+        if want:
+            curve.append((step, loss))
+    return curve
+
+
+def calibrate_offset(ctx, mlp, F, k_true, scaling, quantile=0.9, dev="cuda:0"):
+    """Safety margin on the predicted stop: the `quantile` of (k* - raw prediction)
+    over the given (training) problems, so that most predictions do not stop early."""
+    torch = _torch()
+    mu, sigma, ks = scaling
+    Fd = torch.from_numpy(np.ascontiguousarray(F)).to(dev)
+    out = torch.empty((F.shape[0], 2), dtype=torch.float32, device=dev)
+    dk.dctk_mlp_forward(ctx, mlp, Fd, out)
+    raw = out[:, 1].double().cpu().numpy() * ks
+    off = float(max(0.0, np.quantile(np.asarray(k_true, dtype=np.float64) - raw, quantile)))
+    dk.dctk_mlp_set_scaling(mlp, mu, sigma, ks, off)
+    return off
+
+
+def evaluate(ctx, mlp, instances, k_max=40, gate=1.05, gemm=dk.DCTK_F32, dev="cuda:0"):
+    """Learned-stop solve against the plain GCV solve at k_max on each instance:
+    restoration errors, steps and wall time of both."""
+    import time
+    torch = _torch()
+    out = []
+    for inst in instances:
+        A64, C, Xt = observation(ctx, inst, dev)
+        p, n1, n2 = inst["A"].shape
+        s = inst["X_true"].shape[2]
+        op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gemm, A64, s)
+        ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k_max)
+        try:
+            X = torch.empty((p, n2, s), dtype=torch.float32, device=dev)
+            opts = dk.make_opts(k_max, dk.DCTK_REORTH_NONE, 0, -1.0)
+            nx = float(torch.linalg.norm(Xt))
+            dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+            t_plain = time.perf_counter() - t0
+            e_plain = float(torch.linalg.norm(X - Xt)) / nx
+            dk.dctk_lsqr_learned_solve(ctx, ws, mlp, C, X, opts, gate)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            linfo, kpred, acc = dk.dctk_lsqr_learned_solve(ctx, ws, mlp, C, X, opts, gate)
+            t_learned = time.perf_counter() - t0
+            e_learned = float(torch.linalg.norm(X - Xt)) / nx
+        finally:
+            dk.dctk_krylov_destroy(ws)
+            dk.dctk_op_destroy(op)
+        out.append({"err_plain": e_plain, "err_learned": e_learned, "k_plain": info.iters,
+                    "k_learned": linfo.iters, "k_pred": kpred, "accepted": acc,
+                    "t_plain": t_plain, "t_learned": t_learned,
+                    "lambda_plain": info.lam, "lambda_learned": linfo.lam})
+    return out
+
+
+def summary(results):
+    r = np.array([x["err_learned"] / x["err_plain"] for x in results])
+    return {"instances": len(results),
+            "median_err_ratio": float(np.median(r)), "max_err_ratio": float(r.max()),
+            "frac_within_1_05": float(np.mean(r <= 1.05)),
+            "mean_k_plain": float(np.mean([x["k_plain"] for x in results])),
+            "mean_k_learned": float(np.mean([x["k_learned"] for x in results])),
+            "frac_lambda_accepted": float(np.mean([x["accepted"] for x in results])),
+            "time_plain_s": float(sum(x["t_plain"] for x in results)),
+            "time_learned_s": float(sum(x["t_learned"] for x in results))}

@@ -1,0 +1,208 @@
+"""The learned stopping rule: network kernels against the FP64 oracle, the
+features of a GKB workspace, projection at a step count, the learned solve,
+and what a network trained on the library's own solves gains over plain GCV.
+
+Tolerances: forward outputs 1e-5 relative (FP32 accumulation of bfloat16
+weights and FP32 inputs against FP64 with the same rounded weights);
+gradients 1e-4 relative per parameter block (FP32 sums of B products);
+features 1e-5 absolute (FP32 logs of FP64 scalars)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import krylov
+from oracle import mlp as omlp
+from oracle.cprod import Operator, fro
+from tests.gpu_util import rel, say, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2103_11847_amd as dk  # noqa: E402
+from paper_2103_11847_amd import learned_stop as ls  # noqa: E402
+
+F64, F32 = torch.float64, torch.float32
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = dk.dctk_create(0)
+    yield c
+    dk.dctk_synchronize(c)
+    dk.dctk_destroy(c)
+
+
+@pytest.fixture
+def net(ctx):
+    m = dk.dctk_mlp_create(ctx, 7)
+    yield m
+    torch.cuda.synchronize()
+    dk.dctk_mlp_destroy(m)
+
+
+def _rounded_params(ctx, m):
+    P, bits = dk.dctk_mlp_get_params(ctx, m)
+    Pb = np.array(bits, dtype=np.uint32) << 16
+    return np.array(P, dtype=np.float64), Pb.view(np.float32).astype(np.float64)
+
+
+def test_stored_weights_are_bf16_of_master(ctx, net):
+    P, Pb = _rounded_params(ctx, net)
+    assert np.array_equal(Pb, omlp.bf16_round(P.astype(np.float32)))
+    assert np.all(P[omlp.N_PARAMS - 2:] == 0.0)
+
+
+def test_forward_and_gradient_match_oracle(ctx, net):
+    rng = np.random.default_rng(1)
+    B = 300
+    Xh = rng.standard_normal((B, 16)).astype(np.float32)
+    P, Pb = _rounded_params(ctx, net)
+    X = to_gpu(Xh, F32)
+    out = torch.empty((B, 2), dtype=F32, device="cuda:0")
+    dk.dctk_mlp_forward(ctx, net, X, out)
+    ref, cache = omlp.forward(Pb, Xh.astype(np.float64))
+    say("forward rel", rel(to_np(out), ref))
+    assert rel(to_np(out), ref) <= 1e-5
+    dout_h = rng.standard_normal((B, 2)).astype(np.float32)
+    grad = torch.empty(omlp.N_PARAMS, dtype=F32, device="cuda:0")
+    dk.dctk_mlp_gradient(ctx, net, X, to_gpu(dout_h, F32), grad)
+    gref = omlp.backward(Pb, cache, dout_h.astype(np.float64))
+    g = to_np(grad)
+    o = 0
+    for name, shape in omlp.SIZES:
+        n = int(np.prod(shape))
+        say("grad", name, rel(g[o:o + n], gref[o:o + n]))
+        assert rel(g[o:o + n], gref[o:o + n]) <= 1e-4, name
+        o += n
+
+
+def test_train_step_loss_and_adam(ctx, net):
+    rng = np.random.default_rng(2)
+    B = 128
+    Xh = rng.standard_normal((B, 16)).astype(np.float32)
+    Th = rng.standard_normal((B, 2)).astype(np.float32)
+    P0, Pb0 = _rounded_params(ctx, net)
+    X, T = to_gpu(Xh, F32), to_gpu(Th, F32)
+    loss = dk.dctk_mlp_train_step(ctx, net, X, T, 1.0, 0.5, 1e-3, want_loss=True)
+    out, cache = omlp.forward(Pb0, Xh.astype(np.float64))
+    lref, dref = omlp.loss_and_dout(out, Th.astype(np.float64), np.array([1.0, 0.5]))
+    say("loss", loss, lref)
+    assert abs(loss - lref) <= 1e-5 * abs(lref)
+    g = omlp.backward(Pb0, cache, dref)
+    Pref, _, _ = omlp.adam(P0, g, np.zeros_like(P0), np.zeros_like(P0), 1, 1e-3)
+    P1, _ = _rounded_params(ctx, net)
+    # the first Adam step moves every parameter with a non-negligible gradient by lr sign(g)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert np.max(np.abs((P1 - Pref)[big])) <= 1e-6
+    # and training reduces the loss
+    for _ in range(200):
+        dk.dctk_mlp_train_step(ctx, net, X, T, 1.0, 0.5, 1e-3)
+    l2 = dk.dctk_mlp_train_step(ctx, net, X, T, 1.0, 0.5, 1e-3, want_loss=True)
+    say("loss after 200 steps", l2)
+    assert l2 < 0.5 * loss
+
+
+def test_features_match_oracle(ctx):
+    w = W.learned_stop_instance(1, n=24, p_choices=(4,))
+    orc = Operator(w["A"])
+    Ch = orc.apply(w["X_true"])
+    C = Ch + w["nu"] * fro(Ch) / fro(w["N0"]) * w["N0"]
+    r = krylov.dc_lsqr(orc, C, 8, history=True)
+    phibar = [r["beta"][0]] + [fro(C - orc.apply(Xj)) for Xj in r["history"]]
+    fref = omlp.features(r["alpha"], r["beta"], phibar)
+    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F64, to_gpu(w["A"], F64), 24)
+    ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, 10)
+    try:
+        X = torch.empty((4, 24, 24), dtype=F64, device="cuda:0")
+        dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(8, 0, 0, 0.0))
+        f = torch.empty(16, dtype=F32, device="cuda:0")
+        dk.dctk_mlp_features(ctx, ws, f)
+        say("features", to_np(f), fref)
+        assert np.max(np.abs(to_np(f) - fref)) <= 1e-5
+    finally:
+        torch.cuda.synchronize()
+        dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
+
+
+def _setup(ctx, inst, k):
+    A64, C, Xt = ls.observation(ctx, inst, "cuda:0")
+    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F32, A64, inst["X_true"].shape[2])
+    ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k)
+    return op, ws, C, Xt
+
+
+def test_project_equals_shorter_solve(ctx):
+    inst = W.learned_stop_instance(5, n=40)
+    op, ws, C, Xt = _setup(ctx, inst, 30)
+    try:
+        X = torch.empty_like(Xt)
+        dk.dctk_lsqr_tik_solve(ctx, ws, C, X, dk.make_opts(30, 0, 0, -1.0))
+        for k in (9, 17, 30):
+            Xp = torch.empty_like(Xt)
+            ip = dk.dctk_krylov_project(ctx, ws, k, dk.make_opts(30, 0, 0, -1.0), Xp)
+            Xs = torch.empty_like(Xt)
+            ws2 = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k)
+            try:
+                i2 = dk.dctk_lsqr_tik_solve(ctx, ws2, C, Xs, dk.make_opts(k, 0, 0, -1.0))
+            finally:
+                torch.cuda.synchronize()
+                dk.dctk_krylov_destroy(ws2)
+            assert torch.equal(Xp, Xs), k
+            assert ip.lam == i2.lam and ip.iters == k
+        with pytest.raises(dk.DctkError):
+            dk.dctk_krylov_project(ctx, ws, 31, dk.make_opts(30, 0, 0, -1.0), X)
+    finally:
+        torch.cuda.synchronize()
+        dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
+
+
+def test_learned_solve_follows_its_prediction(ctx, net):
+    """The learned solve takes the predicted number of steps and either the predicted
+    lambda (gate passed) or the GCV one: X equals the projection at that k with that lambda."""
+    inst = W.learned_stop_instance(9, n=40)
+    op, ws, C, Xt = _setup(ctx, inst, 40)
+    try:
+        dk.dctk_mlp_set_scaling(net, -3.0, 1.0, 40.0, 0.0)
+        X = torch.empty_like(Xt)
+        info, k, acc = dk.dctk_lsqr_learned_solve(ctx, ws, net, C, X, dk.make_opts(40, 0, 0, -1.0), 1.05)
+        say("learned", k, acc, info.iters, info.lam)
+        assert 8 <= k <= 40 and info.iters == k
+        Xp = torch.empty_like(Xt)
+        lam = info.lam if acc else -1.0
+        ip = dk.dctk_krylov_project(ctx, ws, k, dk.make_opts(40, 0, 0, lam), Xp)
+        assert torch.equal(Xp, X)
+        assert ip.lam == info.lam
+        # a gate of 1e30 accepts any positive prediction
+        info2, k2, acc2 = dk.dctk_lsqr_learned_solve(ctx, ws, net, C, X, dk.make_opts(40, 0, 0, -1.0), 1e30)
+        assert acc2 == 1 and k2 == k
+    finally:
+        torch.cuda.synchronize()
+        dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
+
+
+def test_trained_network_gain(ctx, net):
+    """Train on the library's own solves of 512 problems, evaluate on 48 others: the
+    learned-stop solve keeps the restoration error of GCV at 40 steps (within 1.05x on
+    most problems) with fewer Golub-Kahan steps and less time."""
+    train_set = [W.learned_stop_instance(i, n=64) for i in range(512)]
+    data = ls.make_dataset(ctx, train_set)
+    T, scaling = ls.targets(data)
+    say("labels: k mean %.1f min %d max %d; log lambda mean %.2f sd %.2f"
+        % (data["k"].mean(), data["k"].min(), data["k"].max(), scaling[0], scaling[1]))
+    dk.dctk_mlp_set_scaling(net, *scaling)
+    curve = ls.train(ctx, net, data["F"], T, steps=2000)
+    say("loss curve", curve[0], curve[-1])
+    assert curve[-1][1] < curve[0][1]
+    off = ls.calibrate_offset(ctx, net, data["F"], data["k"], scaling)
+    say("stop offset", off)
+    res = ls.evaluate(ctx, net, [W.learned_stop_instance(1000 + i, n=64) for i in range(48)])
+    summ = ls.summary(res)
+    say("gain", summ)
+    assert summ["median_err_ratio"] <= 1.05
+    assert summ["frac_within_1_05"] >= 0.75
+    assert summ["mean_k_learned"] < summ["mean_k_plain"]

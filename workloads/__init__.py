@@ -171,3 +171,55 @@ def tiny_random(seed, p, n1, n2, s, two_sided=False):
     X = rng.standard_normal((p, n2, s))
     Y = rng.standard_normal((p, n1, s))
     return {"A": A, "B": B, "X": X, "Y": Y}
+
+
+def band_blur(p, n, sig_lo=1.5, sig_hi=4.0):
+    """Hyperspectral-like operator: frontal slice k is 2^-(k+1) T_{sigma_k, ceil(2.5 sigma_k)}
+    with sigma_k spanning [sig_lo, sig_hi] linearly over the p bands."""
+    A = np.zeros((p, n, n))
+    for k in range(p):
+        sk = sig_lo + (sig_hi - sig_lo) * (k / max(1, p - 1))
+        A[k] = 2.0 ** -(k + 1) * gaussian_toeplitz(n, sk, int(math.ceil(2.5 * sk)))
+    return A
+
+
+def spectral_field(rng, p, n, s, count=8):
+    """8 spatial Gaussians, each with a smooth spectral profile across the p bands, in [0, 1]."""
+    ii = np.arange(n)[:, None]
+    jj = np.arange(s)[None, :]
+    t = np.arange(p) / max(1, p - 1)
+    X = np.zeros((p, n, s))
+    for _ in range(count):
+        ci, cj = rng.uniform(0, n), rng.uniform(0, s)
+        w = rng.uniform(n / 16.0, n / 4.0)
+        spat = np.exp(-((ii - ci) ** 2 + (jj - cj) ** 2) / (2.0 * w * w))
+        mu, sd, amp = rng.uniform(0.0, 1.0), rng.uniform(0.15, 0.6), rng.uniform(0.2, 1.0)
+        prof = amp * np.exp(-((t - mu) ** 2) / (2.0 * sd * sd))
+        X += prof[:, None, None] * spat[None, :, :]
+    return _minmax(X)
+
+
+def hyperspectral(instance=0, n=512, p=64, seed_base=5000):
+    """The hyperspectral-like workload: n1 = n2 = s = n, n3 = p, band-dependent blur
+    sigma from 1.5 to 4, spectral Gaussian field, noise nu ~ logU[1e-3, 2e-2]."""
+    rng = np.random.default_rng(seed_base + instance)
+    A = band_blur(p, n)
+    X = spectral_field(rng, p, n, n)
+    N0 = rng.standard_normal((p, n, n))
+    nu = float(10.0 ** rng.uniform(-3.0, math.log10(2e-2)))
+    return {"name": "hyperspectral_%dx%dx%d" % (n, n, p), "A": A, "B": None, "X_true": X, "N0": N0,
+            "nu": nu, "iters": 40}
+
+
+def learned_stop_instance(i, n=64, p_choices=(8, 16)):
+    """Training / evaluation instance for the learned stopping rule: a hyperspectral-like
+    problem with random blur range, band count and noise level (seed 6000 + i)."""
+    rng = np.random.default_rng(6000 + i)
+    p = int(rng.choice(p_choices))
+    lo = float(rng.uniform(1.0, 2.5))
+    hi = float(rng.uniform(lo + 0.5, 5.0))
+    A = band_blur(p, n, lo, hi)
+    X = spectral_field(rng, p, n, n)
+    N0 = rng.standard_normal((p, n, n))
+    nu = float(10.0 ** rng.uniform(-3.0, math.log10(3e-2)))
+    return {"name": "learned_%d" % i, "A": A, "B": None, "X_true": X, "N0": N0, "nu": nu, "iters": 40}
