@@ -327,7 +327,13 @@ int dctk_lsqr_learned_solve(dctk_ctx ctx, dctk_krylov ws, dctk_mlp mlp, const vo
  *   DCTK_KRYLOV_GKB workspaces on ctx's device; C[i] (p x n1 x s) and X[i]
  *   (p x n2 x s) device buffers of instance i in its vector type, captured by
  *   the plan (every run reads C[i] and writes X[i]; they must outlive the
- *   batch).  opts applies to all (k_max <= each workspace's).  use_graph = 0 replays the merged launches from the host
+ *   batch).  opts applies to all (k_max <= each workspace's).  With mlp !=
+ *   NULL every instance uses the learned stop without a host round trip:
+ *   after step 8 the network sets, on the device, the instance's step limit
+ *   (later steps' kernels exit at once) and its proposed lambda, which the
+ *   projected solve keeps when GCV(proposal) <= gate * min GCV (opts->lambda
+ *   < 0, k_max >= 8, gate >= 1).  The plan holds mlp's parameters by
+ *   reference: later training changes later runs.  use_graph = 0 replays the merged launches from the host
  *   instead of a graph.  The batch owns device copies of the launch arguments
  *   (allocated here, freed by dctk_batch_destroy).  Errors: DCTK_EINVAL on a
  *   bad argument, DCTK_ENOMEM, DCTK_EHIP.
@@ -336,11 +342,15 @@ int dctk_lsqr_learned_solve(dctk_ctx ctx, dctk_krylov ws, dctk_mlp mlp, const vo
  *   dctk_lsqr_tik_solve would; returns DCTK_OK or the first non-OK status.
  * dctk_batch_stats: launches per run of the merged schedule, and of the
  *   same solves run one by one (either may be NULL).
+ * dctk_batch_learned: synchronises; per instance the learned step limit (0:
+ *   none) and whether the proposed lambda passed the gate (host arrays of
+ *   count, either may be NULL).
  * dctk_batch_destroy: synchronises ctx's stream and frees the plan. */
 #define DCTK_BATCH_MAX 256
 typedef struct dctk_batch_s* dctk_batch;
 int dctk_batch_create(dctk_ctx ctx, int count, const dctk_krylov* ws, const void* const* C, void* const* X,
-                      const dctk_solve_opts* opts, int use_graph, dctk_batch* out);
+                      const dctk_solve_opts* opts, dctk_mlp mlp, double gate, int use_graph, dctk_batch* out);
+int dctk_batch_learned(dctk_ctx ctx, dctk_batch b, int* k_limit, int* accepted);
 int dctk_batch_run(dctk_ctx ctx, dctk_batch b);
 int dctk_batch_info(dctk_ctx ctx, dctk_batch b, dctk_solve_info* infos);
 int dctk_batch_stats(dctk_batch b, int* merged_launches, int* single_launches);

@@ -104,7 +104,8 @@ _SIGS = {
     "dctk_lsqr_learned_solve": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(dctk_solve_opts), _D,
                                      ctypes.POINTER(dctk_solve_info), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "dctk_batch_create": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
-                               ctypes.POINTER(dctk_solve_opts), _I, ctypes.POINTER(_P)]),
+                               ctypes.POINTER(dctk_solve_opts), _P, _D, _I, ctypes.POINTER(_P)]),
+    "dctk_batch_learned": (_I, [_P, _P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "dctk_batch_run": (_I, [_P, _P]),
     "dctk_batch_info": (_I, [_P, _P, ctypes.POINTER(dctk_solve_info)]),
     "dctk_batch_stats": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -421,8 +422,9 @@ def dctk_lsqr_learned_solve(ctx, ws, m, C, X, opts, gate=1.05):
     return info, k.value, acc.value
 
 
-def dctk_batch_create(ctx, ws_list, C_list, X_list, opts, use_graph=True):
-    """Plan a batch of DC-LSQR / DC-GK solves: ws_list[i] solves C_list[i] into X_list[i]."""
+def dctk_batch_create(ctx, ws_list, C_list, X_list, opts, use_graph=True, mlp=None, gate=1.05):
+    """Plan a batch of DC-LSQR / DC-GK solves: ws_list[i] solves C_list[i] into X_list[i]
+    (with the device-side learned stop when mlp is given)."""
     n = len(ws_list)
     if len(C_list) != n or len(X_list) != n:
         raise ValueError("dctk_batch_create: ws, C and X lists differ in length")
@@ -431,8 +433,8 @@ def dctk_batch_create(ctx, ws_list, C_list, X_list, opts, use_graph=True):
     c_a = arr(*[_ptr(c) for c in C_list])
     x_a = arr(*[_ptr(x) for x in X_list])
     h = ctypes.c_void_p()
-    _check(lib().dctk_batch_create(ctx, n, ws_a, c_a, x_a, ctypes.byref(opts), 1 if use_graph else 0,
-                                   ctypes.byref(h)), "dctk_batch_create")
+    _check(lib().dctk_batch_create(ctx, n, ws_a, c_a, x_a, ctypes.byref(opts), mlp, float(gate),
+                                   1 if use_graph else 0, ctypes.byref(h)), "dctk_batch_create")
     return h.value
 
 
@@ -444,6 +446,14 @@ def dctk_batch_info(ctx, batch, count):
     infos = (dctk_solve_info * count)()
     _check(lib().dctk_batch_info(ctx, batch, infos), "dctk_batch_info")
     return list(infos)
+
+
+def dctk_batch_learned(ctx, batch, count):
+    """Per instance: (learned step limit, 1 if the proposed lambda passed the gate)."""
+    kl = (ctypes.c_int * count)()
+    acc = (ctypes.c_int * count)()
+    _check(lib().dctk_batch_learned(ctx, batch, kl, acc), "dctk_batch_learned")
+    return list(kl), list(acc)
 
 
 def dctk_batch_stats(batch):

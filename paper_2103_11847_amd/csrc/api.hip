@@ -676,6 +676,29 @@ static double lsqr_resnorm(dctk_ctx ctx, dctk_krylov ws, int steps) {
   return std::fabs(v);
 }
 
+hipError_t learned_enqueue(dctk_ctx ctx, dctk_krylov ws, dctk_mlp m, const void* C, void* X,
+                           const dctk_solve_opts* opts, double gate) {
+  const int kf = 8;
+  dctk_op op = ws->op;
+  hipError_t e;
+  ws->reorth = opts->reorth;
+  if ((e = gkb_init_impl(ctx, ws, C, ws->X, opts->tol)) != hipSuccess) return e;
+  for (int j = 1; j <= kf; ++j)
+    if ((e = gkb_step_impl(ctx, ws, j, ws->X)) != hipSuccess) return e;
+  rec_phase(ctx);
+  if ((e = launch_mlp_stop(ctx, m, ws->st, kf, opts->k_max)) != hipSuccess) return e;
+  // steps beyond the predicted stop exit at once (their gate reads st->k_limit)
+  for (int j = kf + 1; j <= opts->k_max; ++j)
+    if ((e = gkb_step_impl(ctx, ws, j, ws->X)) != hipSuccess) return e;
+  ws->host_steps = opts->k_max;
+  ws->initialised = 1;
+  rec_phase(ctx);
+  if ((e = launch_projected(ctx, ws->st, 1, opts->gcv_mode, -1.0, 0, -1.0, gate, 1)) != hipSuccess) return e;
+  rec_phase(ctx);
+  return launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, opts->k_max,
+                        &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0});
+}
+
 int lsqr_info(dctk_ctx ctx, dctk_krylov ws, const dctk_solve_opts* opts, dctk_solve_info* info) {
   HostState hs;
   int r;

@@ -71,12 +71,13 @@ using namespace dctk;
 extern "C" {
 
 int dctk_batch_create(dctk_ctx ctx, int count, const dctk_krylov* ws, const void* const* C, void* const* X,
-                      const dctk_solve_opts* opts, int use_graph, dctk_batch* out) {
+                      const dctk_solve_opts* opts, dctk_mlp mlp, double gate, int use_graph, dctk_batch* out) {
   if (!out) return DCTK_EINVAL;
   *out = nullptr;
   if (!ctx || !ws || !C || !X || !opts) return DCTK_EINVAL;
   if (count < 1 || count > DCTK_BATCH_MAX) return DCTK_EINVAL;
   if (ctx->rec) return DCTK_ESTATE;
+  if (mlp && (opts->lambda >= 0.0 || opts->k_max < 8 || !(gate >= 1.0) || !std::isfinite(gate))) return DCTK_EINVAL;
   for (int i = 0; i < count; ++i) {
     if (!ws[i] || !C[i] || !X[i]) return DCTK_EINVAL;
     if (ws[i]->kind != DCTK_KRYLOV_GKB || ws[i]->op->ctx->device != ctx->device) return DCTK_EINVAL;
@@ -92,7 +93,8 @@ int dctk_batch_create(dctk_ctx ctx, int count, const dctk_krylov* ws, const void
   int single = 0;
   for (int i = 0; i < count; ++i) {
     ctx->rec = &recs[i];
-    hipError_t e = lsqr_enqueue(ctx, ws[i], C[i], X[i], opts);
+    hipError_t e = mlp ? learned_enqueue(ctx, ws[i], mlp, C[i], X[i], opts, gate)
+                       : lsqr_enqueue(ctx, ws[i], C[i], X[i], opts);
     ctx->rec = nullptr;
     if (e != hipSuccess) return hip_fail(ctx, e);
     single += (int)recs[i].recs.size();
@@ -225,6 +227,22 @@ int dctk_batch_info(dctk_ctx ctx, dctk_batch b, dctk_solve_info* infos) {
     if (first == DCTK_OK) first = r;
   }
   return first;
+}
+
+int dctk_batch_learned(dctk_ctx ctx, dctk_batch b, int* k_limit, int* accepted) {
+  if (!ctx || !b || b->ctx != ctx) return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  for (int i = 0; i < b->count; ++i) {
+    KState* st = b->ws[i]->st;
+    int kl = 0;
+    double ok = 0.0;
+    DCTK_HIP(ctx, hipMemcpyAsync(&kl, &st->k_limit, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    DCTK_HIP(ctx, hipMemcpyAsync(&ok, &st->gate_ok, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    DCTK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (k_limit) k_limit[i] = kl;
+    if (accepted) accepted[i] = ok > 0.5 ? 1 : 0;
+  }
+  return DCTK_OK;
 }
 
 int dctk_batch_stats(dctk_batch b, int* merged_launches, int* single_launches) {

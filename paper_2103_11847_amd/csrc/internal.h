@@ -53,7 +53,16 @@ struct KState {
   double H[(kMaxK + 1) * kMaxK];    // Arnoldi Hessenberg, row-major, ld = kMaxK
   double coef[kRedVals];            // Gram coefficients of the current reorthogonalisation pass
   double y[kMaxK + 1];              // projected solution
+  int k_limit;                      // > 0: GKB steps beyond it are skipped (learned stop)
+  int pad_i;
+  double pred_lambda;               // learned stop: predicted lambda (0: none)
 };
+
+// GKB step j runs only up to a learned step limit (0: no limit)
+__device__ inline bool beyond_limit(const KState* st, int j) {
+  const int kl = ((const volatile KState*)st)->k_limit;
+  return kl > 0 && j > kl;
+}
 
 // ---- control of a product kernel inside a Krylov step -----------------------
 // A c-product inside a Krylov step reads its scalars from the device: either
@@ -216,12 +225,12 @@ __device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin
       return true;
     }
     case CTL_GKB_FWD: {
-      if (ss >= 0) return false;  // stopped at an earlier step
+      if (ss >= 0 || beyond_limit(st, c.j)) return false;  // stopped at an earlier step
       b = -st->alpha[c.j - 1];
       return true;
     }
     case CTL_GKB_ADJ: {
-      if (ss >= 0 && ss < c.j) return false;
+      if ((ss >= 0 && ss < c.j) || beyond_limit(st, c.j)) return false;
       if (c.from_state) {
         if (ss == c.j) return false;
         const double bt = st->beta[c.j];
@@ -294,6 +303,7 @@ __device__ inline bool gate_open(const Gate& g) {
   if (g.st == nullptr) return true;
   const volatile KState* st = g.st;
   if (st->halt) return false;
+  if (st->k_limit > 0 && g.j > st->k_limit) return false;
   const int ss = st->stop_step;
   if (ss < 0) return true;
   return g.mode == 0 ? ss >= g.j : ss > g.j;
@@ -518,7 +528,12 @@ int lsqr_info(dctk_ctx ctx, dctk_krylov ws, const dctk_solve_opts* opts, dctk_so
 // k_use > 0 projects at min(k_use, steps); lam_cand > 0 (with GCV) is kept when its GCV
 // value is <= gate * the minimum (st->gate_ok records the decision).
 hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, double lambda, int k_use = 0,
-                            double lam_cand = -1.0, double gate = 1.0);
+                            double lam_cand = -1.0, double gate = 1.0, int cand_from_state = 0);
+// device-side learned stop: st->k_limit and st->pred_lambda from the network (after step 8)
+hipError_t launch_mlp_stop(dctk_ctx ctx, dctk_mlp m, KState* st, int kmin, int kmax);
+// DC-GK with the device-side learned stop, fully asynchronous (recordable)
+hipError_t learned_enqueue(dctk_ctx ctx, dctk_krylov ws, dctk_mlp m, const void* C, void* X,
+                           const dctk_solve_opts* opts, double gate);
 
 // learned stop (mlp.hip): features of st -> network -> host pred[5] =
 // {t_lambda, t_k, lambda, k, valid}; synchronises

@@ -240,6 +240,43 @@ __global__ __launch_bounds__(64) void k_mlp_predict(const KState* st, const bf16
   pred[4] = (ok && isfinite(lam) && lam > 0.0f && isfinite(y[1])) ? 1.0f : 0.0f;
 }
 
+// Device-side learned stop for a workspace (plain or grouped launch, one
+// 64-thread workgroup per instance): after step 8, sets the step limit and
+// the proposed lambda in the state; no limit when the features are unusable.
+struct StopArgs {
+  int gx, gy, gz;
+  int kmin, kmax;
+  KState* st;
+  const bf16_t* Pb;
+  float mu, sigma, kscale, koffset;
+};
+
+__global__ __launch_bounds__(64) void k_mlp_stop(StopArgs a_, const StopArgs* grp, const int4* bmap) {
+  VBlock vb;
+  const StopArgs a = pick_args(a_, grp, bmap, vb);
+  __shared__ float sW[kNParams];
+  __shared__ float f[kNIn];
+  __shared__ int ok;
+  stage_params(a.Pb, sW);
+  KState* st = a.st;
+  if (threadIdx.x == 0) ok = (((volatile KState*)st)->stop_step < 0 && state_features(st, f)) ? 1 : 0;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (!ok) {
+    st->k_limit = 0;
+    st->pred_lambda = 0.0;
+    return;
+  }
+  float y[2];
+  mlp_sample(sW, f, nullptr, nullptr, y);
+  const float lam = expf(y[0] * a.sigma + a.mu);
+  float kf = rintf(y[1] * a.kscale + a.koffset);
+  kf = fminf(fmaxf(kf, (float)a.kmin), (float)a.kmax);
+  const bool valid = isfinite(lam) && lam > 0.0f && isfinite(kf);
+  st->k_limit = valid ? (int)kf : 0;
+  st->pred_lambda = valid ? (double)lam : 0.0;
+}
+
 }  // namespace dctk
 
 using namespace dctk;
@@ -314,6 +351,19 @@ static hipError_t mlp_grad(dctk_ctx ctx, dctk_mlp m, int B, const float* X, cons
 }
 
 namespace dctk {
+hipError_t launch_mlp_stop(dctk_ctx ctx, dctk_mlp m, KState* st, int kmin, int kmax) {
+  StopArgs a{};
+  a.kmin = kmin;
+  a.kmax = kmax;
+  a.st = st;
+  a.Pb = m->Pb;
+  a.mu = (float)m->mu;
+  a.sigma = (float)m->sigma;
+  a.kscale = (float)m->kscale;
+  a.koffset = (float)m->koffset;
+  return launch_kernel(ctx, ctx->stream, k_mlp_stop, dim3(1), 64, 0, a);
+}
+
 hipError_t mlp_predict(dctk_ctx ctx, dctk_mlp m, const KState* st, int kmin, int kmax, float* host_pred) {
   hipLaunchKernelGGL(k_mlp_predict, dim3(1), dim3(64), 0, ctx->stream, st, m->Pb, (float)m->mu, (float)m->sigma,
                      (float)m->kscale, (float)m->koffset, kmin, kmax, m->pred);

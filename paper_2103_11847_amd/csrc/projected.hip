@@ -118,6 +118,7 @@ struct ProjArgs {
   double lam_fixed;  // >= 0: this lambda; < 0: GCV
   double lam_cand;   // > 0 (with GCV): a proposed lambda, kept when GCV(lam_cand) <= gate * min GCV
   double gate;
+  int cand_from_state;  // 1: the proposed lambda is st->pred_lambda (learned stop)
 };
 
 __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* group, const int4* bmap) {
@@ -125,7 +126,8 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
   const ProjArgs a = pick_args(a_, group, bmap, vb);
   KState* st = a.st;
   const int bidiag = a.bidiag, gcv_mode = a.gcv_mode;
-  const double lam_fixed = a.lam_fixed, lam_cand = a.lam_cand, gate = a.gate;
+  const double lam_fixed = a.lam_fixed, gate = a.gate;
+  const double lam_cand = a.cand_from_state ? ((volatile KState*)st)->pred_lambda : a.lam_cand;
   const int k_use = a.k_use;
   if (((volatile KState*)st)->halt) return;
   __shared__ double G[kMaxK * kLdG];      // G[c * kLdG + r]: column c of the matrix
@@ -377,8 +379,9 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
 }
 
 hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, double lambda, int k_use,
-                            double lam_cand, double gate) {
+                            double lam_cand, double gate, int cand_from_state) {
   ProjArgs a{};
+  a.cand_from_state = cand_from_state;
   a.bidiag = bidiag;
   a.gcv_mode = gcv_mode;
   a.k_use = k_use;

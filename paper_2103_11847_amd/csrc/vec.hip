@@ -356,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void k_gkb_update(GkbArgs a_, const GkbAr
   ld4(Vn, e_first, n, vec, vv0);
   const volatile KState* vst = st;
   const int ss = vst->stop_step;
-  if (ss >= 0 && ss < j) return;
+  if ((ss >= 0 && ss < j) || beyond_limit(st, j)) return;
   const bool bbreak = (ss == j && vst->stop_kind == STOP_BETA);
   double alpha = 0.0;
   bool abreak = false, fin = true;
