@@ -68,6 +68,10 @@ def parse():
                     help="also run 3 plain device copies of this many MiB (HBM counter calibration)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch64: keep the size-based product paths instead of timing them per shape")
+    ap.add_argument("--learned", action="store_true",
+                    help="batch64: train the stopping network on the library's own solves of 256 smaller "
+                         "problems of the same family, run the batch with the learned stop, and compare "
+                         "with plain FP32 single solves")
     ap.add_argument("--workload", default="colour256", choices=["colour256", "batch64"],
                     help="colour256: one 256x256x3 solve per step (default); batch64: the uneven "
                          "64-instance batch per step (merged launches, HIP graph)")
@@ -315,21 +319,31 @@ def bench_batch(args):
         flops += (2 * k + 1) * 2.0 * n * n * n * p
         del Xt, Ch, N0
     opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0, 0.0)
-    # a loop of plain single solves
+    mlp, learned_info = None, None
+    plain = None
+    if args.learned:
+        mlp, learned_info = train_stop_network(ctx, args)
+        plain = plain_fp32_loop(ctx, insts, k, opts, args)
+    # a loop of single solves of the same form (learned or not)
+    def single(it):
+        if mlp is not None:
+            dk.dctk_lsqr_learned_solve(ctx, it["ws"], mlp, it["C"], it["X"], opts, 1.05)
+        else:
+            dk.dctk_lsqr_tik_solve(ctx, it["ws"], it["C"], it["X"], opts)
     for it in insts:
-        dk.dctk_lsqr_tik_solve(ctx, it["ws"], it["C"], it["X"], opts)
+        single(it)
     ref = [it["X"].clone() for it in insts]
     loop_steps = max(1, min(3, args.steps))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(loop_steps):
         for it in insts:
-            dk.dctk_lsqr_tik_solve(ctx, it["ws"], it["C"], it["X"], opts)
+            single(it)
     torch.cuda.synchronize()
     loop_s = (time.perf_counter() - t0) / loop_steps
     # the batch: merged launches captured in a graph
     b = dk.dctk_batch_create(ctx, [it["ws"] for it in insts], [it["C"] for it in insts],
-                             [it["X"] for it in insts], opts, True)
+                             [it["X"] for it in insts], opts, True, mlp=mlp, gate=1.05)
     merged, single = dk.dctk_batch_stats(b)
     for _ in range(args.warmup):
         dk.dctk_batch_run(ctx, b)
@@ -340,6 +354,7 @@ def bench_batch(args):
     dk.dctk_synchronize(ctx)
     batch_s = (time.perf_counter() - t0) / args.steps
     infos = dk.dctk_batch_info(ctx, b, len(insts))
+    k_used = [x.iters for x in infos]
     same = all(torch.equal(it["X"], r) for it, r in zip(insts, ref))
     errs = []
     for it in insts:
@@ -361,6 +376,19 @@ def bench_batch(args):
     for it in insts:
         dk.dctk_krylov_destroy(it["ws"])
         dk.dctk_op_destroy(it["op"])
+    target = None
+    if plain is not None:
+        ratios = np.array(errs) / np.array(plain["errs"])
+        target = {"plain_fp32_single_solves_per_s": 64.0 / plain["loop_s"],
+                  "speedup_vs_plain_fp32_single": plain["loop_s"] / batch_s,
+                  "relerr_ratio_vs_plain_fp32": {"median": float(np.median(ratios)),
+                                                 "p90": float(np.quantile(ratios, 0.9)),
+                                                 "max": float(ratios.max()),
+                                                 "frac_within_1_05": float(np.mean(ratios <= 1.05))},
+                  "mean_steps": float(np.mean(k_used)), "network": learned_info}
+        gate_ok = gate_ok and float(np.median(ratios)) <= 1.05
+    if mlp is not None:
+        dk.dctk_mlp_destroy(mlp)
     dk.dctk_destroy(ctx)
     value = (64.0 / batch_s) if gate_ok else 0.0
     peak = MFMA_PEAK_TFLOPS[args.gemm]
@@ -369,8 +397,9 @@ def bench_batch(args):
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": batch_s * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.gemm, "data": "synthetic",
-        "config": {"workload": "uneven batch of 64 DC-GK solves (n=s in {64..512}, n3 in {3,8,31}, 40 GKB steps "
-                               "+ FP64 GCV each), one batch per step, merged launches in a HIP graph",
+        "config": {"workload": "uneven batch of 64 DC-GK solves (n=s in {64..512}, n3 in {3,8,31}, %s "
+                               "+ FP64 GCV each), one batch per step, merged launches in a HIP graph"
+                               % ("learned stop after 8 of up to 40 GKB steps" if args.learned else "40 GKB steps"),
                    "instances": 64, "gkb_steps": k, "gemm_dtype": args.gemm, "sizes_n_n3": sizes,
                    "autotuned_paths": {"%dx%d" % (kk[1], kk[0]): v for kk, v in tuned.items()}},
         "roofline": {"bound": "mfma", "achieved": flops / batch_s / 1e12, "peak": peak, "unit": "TFLOP/s",
@@ -381,8 +410,59 @@ def bench_batch(args):
                   "launches_merged": merged, "launches_single": single, "bitwise_equal_to_single": same,
                   "worst_relerr_ratio_vs_oracle": worst, "median_relerr": float(np.median(errs)),
                   "lambda_range": [min(x.lam for x in infos), max(x.lam for x in infos)]},
+        "target_form": target,
     }
     print(json.dumps(line))
+
+
+def train_stop_network(ctx, args):
+    """The stopping network, trained on the library's own FP32 solves of 256 smaller
+    problems of the batch's family (labels from their restoration errors)."""
+    import paper_2103_11847_amd as dk
+    from paper_2103_11847_amd import learned_stop as ls
+    import workloads as W
+    t0 = time.perf_counter()
+    data = ls.make_dataset(ctx, [W.batch_train_instance(i) for i in range(256)])
+    t_data = time.perf_counter() - t0
+    T, scaling = ls.targets(data)
+    m = dk.dctk_mlp_create(ctx, 5)
+    dk.dctk_mlp_set_scaling(m, *scaling)
+    t0 = time.perf_counter()
+    curve = ls.train(ctx, m, data["F"], T, steps=2000)
+    t_train = time.perf_counter() - t0
+    off = ls.calibrate_offset(ctx, m, data["F"], data["k"], scaling)
+    return m, {"train_problems": int(data["F"].shape[0]), "label_seconds": t_data, "train_seconds": t_train,
+               "loss_first_last": [curve[0][1], curve[-1][1]], "stop_offset": off,
+               "label_k_mean": float(data["k"].mean())}
+
+
+def plain_fp32_loop(ctx, insts, k, opts, args):
+    """Plain FP32 GPU LSQR (DC-GK, 40 steps, GCV), one solve after another: time and errors."""
+    import torch
+    import paper_2103_11847_amd as dk
+    made = []
+    for it in insts:
+        w = it["w"]
+        op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F32, torch.from_numpy(w["A"]).to("cuda:0"),
+                               w["A"].shape[1])
+        made.append((op, dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k)))
+    X = [torch.empty_like(it["C"]) for it in insts]
+    for (op, ws), it, x in zip(made, insts, X):
+        dk.dctk_lsqr_tik_solve(ctx, ws, it["C"], x, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (op, ws), it, x in zip(made, insts, X):
+        dk.dctk_lsqr_tik_solve(ctx, ws, it["C"], x, opts)
+    torch.cuda.synchronize()
+    loop_s = time.perf_counter() - t0
+    errs = []
+    for it, x in zip(insts, X):
+        Xt = it["w"]["X_true"]
+        errs.append(float(np.linalg.norm((x.double().cpu().numpy() - Xt).ravel()) / np.linalg.norm(Xt.ravel())))
+    for op, ws in made:
+        dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
+    return {"loop_s": loop_s, "errs": errs}
 
 
 def collections_count(items):

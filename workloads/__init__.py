@@ -223,3 +223,18 @@ def learned_stop_instance(i, n=64, p_choices=(8, 16)):
     N0 = rng.standard_normal((p, n, n))
     nu = float(10.0 ** rng.uniform(-3.0, math.log10(3e-2)))
     return {"name": "learned_%d" % i, "A": A, "B": None, "X_true": X, "N0": N0, "nu": nu, "iters": 40}
+
+
+def batch_train_instance(i):
+    """Training problem for the learned stop on the uneven batch: the batch's
+    distributions with smaller slices, n = s in {64, 96, 128} (seed 7000 + i)."""
+    rng = np.random.default_rng(7000 + i)
+    n = int(rng.choice([64, 96, 128]))
+    p = int(rng.choice([3, 8, 31]))
+    sigma = float(rng.uniform(1.0, 4.0))
+    r = int(math.ceil(2.5 * sigma))
+    nu = float(10.0 ** rng.uniform(-3.0, -2.0))
+    A = mixed_blur(tube_for(p), gaussian_toeplitz(n, sigma, r))
+    X = edges_field(rng, p, n, n)
+    N0 = rng.standard_normal((p, n, n))
+    return {"name": "batch_train_%d" % i, "A": A, "B": None, "X_true": X, "N0": N0, "nu": nu, "iters": 40}
