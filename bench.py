@@ -72,7 +72,7 @@ def parse():
                     help="batch64: train the stopping network on the library's own solves of 256 smaller "
                          "problems of the same family, run the batch with the learned stop, and compare "
                          "with plain FP32 single solves")
-    ap.add_argument("--workload", default="colour256", choices=["colour256", "batch64"],
+    ap.add_argument("--workload", default="colour256", choices=["colour256", "batch64", "video256", "hyper512"],
                     help="colour256: one 256x256x3 solve per step (default); batch64: the uneven "
                          "64-instance batch per step (merged launches, HIP graph)")
     return ap.parse_args()
@@ -124,6 +124,8 @@ def main():
         sys.exit(1)
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload in ("video256", "hyper512"):
+        return bench_large(args)
     dev = torch.device("cuda:0")
     w = W.colour_256()
     p, n, s, k = 3, 256, 256, w["iters"]
@@ -463,6 +465,111 @@ def plain_fp32_loop(ctx, insts, k, opts, args):
         dk.dctk_krylov_destroy(ws)
         dk.dctk_op_destroy(op)
     return {"loop_s": loop_s, "errs": errs}
+
+
+def bench_large(args):
+    """video256: two-sided 256x256x32 DC-GMRES (40 Arnoldi steps, GCV); hyper512: 512x512x64
+    DC-GK (40 GKB steps, GCV).  One step = one solve; the dominant kernel is timed live."""
+    import torch
+    import paper_2103_11847_amd as dk
+    import workloads as W
+    dev = torch.device("cuda:0")
+    gdt = dk.DTYPES[args.gemm]
+    video = args.workload == "video256"
+    w = W.video_256() if video else W.hyperspectral(0)
+    p, n, s = w["X_true"].shape
+    k = 40
+    ctx = dk.dctk_create(0)
+    A64 = torch.from_numpy(w["A"]).to(dev)
+    B64 = torch.from_numpy(w["B"]).to(dev) if video else None
+    op64 = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F64, A64, s, B64)
+    Xt = torch.from_numpy(w["X_true"]).to(dev)
+    Ch = torch.empty_like(Xt)
+    dk.dctk_cprod(ctx, op64, 1.0, Xt, 0.0, Ch)
+    dk.dctk_op_destroy(op64)
+    N0 = torch.from_numpy(w["N0"]).to(dev)
+    C = (Ch + w["nu"] * torch.linalg.norm(Ch) / torch.linalg.norm(N0) * N0).to(torch.float32).contiguous()
+    del Ch, N0
+    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, A64, s, B64)
+    tuned = None if args.no_autotune else dk.dctk_op_autotune(ctx, op, 3)
+    ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_ARNOLDI if video else dk.DCTK_KRYLOV_GKB, k)
+    X = torch.zeros_like(C)
+    opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0, 0.0)
+
+    def solve():
+        if video:
+            X.zero_()
+            return dk.dctk_gmres_tik_solve(ctx, ws, C, X, 1, opts)
+        return dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+    for _ in range(args.warmup):
+        info = solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = solve()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    err = float(torch.linalg.norm(X.double() - Xt) / torch.linalg.norm(Xt))
+    dk.dctk_profile_begin(ctx)
+    solve()
+    prof = dk.dctk_profile_end(ctx)
+    kind = max(prof, key=lambda k_: prof[k_][0])
+    k_ms, k_n = prof[kind]
+    k_us = k_ms * 1e3 / max(1, k_n)
+    bg = {"f32": 4, "bf16": 2, "f16": 2}[args.gemm]
+    N = p * n * s
+    if kind in ("gemm", "fused_fwd", "fused_adj"):
+        flops = 2.0 * n * n * s * p * (2 if video else 1)
+        byts = p * n * n * bg + (p * s * s * bg if video else 0) + N * (bg + 4 if kind == "gemm" else 8)
+    else:  # tube transform: read and write p x n x s, 2p flops per element
+        flops = 2.0 * p * N
+        byts = N * (4 + (bg if kind == "tube_fwd" else 4))
+    peak_f = MFMA_PEAK_TFLOPS[args.gemm]
+    if kind.startswith("tube"):
+        peak_f = MFMA_PEAK_TFLOPS["f32"]   # vector FP32 arithmetic
+    ai = flops / byts
+    if ai >= peak_f * 1e12 / (HBM_PEAK_GBS * 1e9):
+        roof = {"bound": "mfma" if not kind.startswith("tube") else "alu", "achieved": flops / (k_us * 1e-6) / 1e12,
+                "peak": peak_f, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": byts / (k_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof.update({"traffic": None, "kernel": kind, "avg_us": k_us, "launches": k_n, "flops_per_launch": flops,
+                 "bytes_per_launch": byts, "arith_intensity": ai,
+                 "per_kind_avg_us": {k_: (v[0] * 1e3 / v[1] if v[1] else None) for k_, v in prof.items()}})
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import krylov
+        from oracle.cprod import Operator
+        orc = Operator(w["A"], w["B"])
+        Cn = C.double().cpu().numpy()
+        ksample = 4
+        t0 = time.perf_counter()
+        if video:
+            krylov.dc_gmres(orc, Cn, np.zeros_like(Cn), ksample, 1, lam=None)
+        else:
+            krylov.dc_gk(orc, Cn, ksample, lam=None)
+        dt = time.perf_counter() - t0
+        per_solve = dt * k / ksample
+        cpu = {"value": 1.0 / per_solve, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": "one FP64 oracle solve with %d of the %d Krylov steps (%.1f s), scaled by %d/%d"
+                         % (ksample, k, dt, k, ksample)}
+    dk.dctk_krylov_destroy(ws)
+    dk.dctk_op_destroy(op)
+    dk.dctk_destroy(ctx)
+    line = {
+        "metric": METRIC, "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.gemm, "data": "synthetic",
+        "config": {"workload": ("video deblur 256x256x32 two-sided A*X*B, DC-GMRES 40 Arnoldi steps + FP64 GCV"
+                                if video else
+                                "hyperspectral-like 512x512x64 band-dependent blur, DC-GK 40 GKB steps + FP64 GCV"),
+                   "n1": n, "n2": n, "s": s, "n3": p, "krylov_steps": k, "gemm_dtype": args.gemm,
+                   "product_paths": tuned},
+        "roofline": roof, "cpu_baseline": cpu,
+        "restoration": {"relerr_gpu": err, "lambda": info.lam, "iters": info.iters},
+    }
+    print(json.dumps(line))
 
 
 def collections_count(items):

@@ -10,7 +10,7 @@
 #include <cmath>
 #include <vector>
 
-#include "internal.h"
+#include "mfma.h"
 
 namespace dctk {
 
@@ -205,6 +205,136 @@ __global__ __launch_bounds__(kThreads) void tube_kernel(TubeArgs ta_, const Tube
   }
 }
 
+// Long tubes (p >= 16): the transform out = G x in is a (p x p)(p x count)
+// contraction, so it runs on the matrix cores.  A workgroup takes 64 positions
+// and all p outputs: G (p x p, FP32, rows padded to 16) and the 64-position
+// input tile (p x 64, 16-byte loads, scaled by the control block's s and
+// written to xnorm on the way) are staged in LDS; wave w computes the 16
+// positions of column block w for every 16-row band of outputs with
+// 16x16x4 FP32 MFMAs; the epilogue applies a, b, src and writes per-block
+// partial sums of out^2.
+template <typename TOUT, int PM, bool SCALE, bool EPI>
+__global__ __launch_bounds__(256) void tube_mfma_kernel(TubeArgs ta_, const TubeArgs* grp, const int4* bmap) {
+  typedef Mfma<float> MF;
+  constexpr int NB = 64;            // positions per workgroup
+  constexpr int LDG = PM + 4;       // G as [k][t], t contiguous (+16 bytes)
+  constexpr int LDX = NB + 16;      // input as [t][e], e contiguous (+64 bytes)
+  constexpr int FR = PM / 16;       // row bands
+  __shared__ __attribute__((aligned(16))) float sG[PM * LDG];
+  __shared__ __attribute__((aligned(16))) float sX[PM * LDX];
+  __shared__ double sh[256 / 64 + 2];
+  VBlock vb;
+  const TubeArgs ta = pick_args(ta_, grp, bmap, vb);
+  double a_d, b_d, s_d;
+  if (!ctl_begin(ta.ctl, a_d, b_d, s_d, sh, vb)) return;
+  if (!SCALE) s_d = 1.0;
+  if (!EPI) { a_d = 1.0; b_d = 0.0; }
+  const float a = (float)a_d, b = (float)b_d, sc = (float)s_d;
+  const int p = ta.p;
+  const int64_t count = ta.count;
+  const float* in = (const float*)ta.in;
+  TOUT* out = (TOUT*)ta.out;
+  const float* G = (const float*)ta.G;
+  const TOUT* src = (const TOUT*)ta.src;
+  float* xnorm = (float*)ta.xnorm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t e0 = (int64_t)vb.x * NB;
+  for (int i = tid; i < PM * PM; i += 256) {
+    const int k = i / PM, t = i % PM;
+    sG[k * LDG + t] = (k < p && t < p) ? G[k * p + t] : 0.0f;
+  }
+  // input tile: p rows of 64 positions, 16 float4 per row
+  const bool vec = (count % 4 == 0) && (((uintptr_t)in) % 16 == 0) &&
+                   (xnorm == nullptr || ((uintptr_t)xnorm) % 16 == 0);
+  for (int i = tid; i < PM * (NB / 4); i += 256) {
+    const int t = i / (NB / 4), c = (i % (NB / 4)) * 4;
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t e = e0 + c;
+    if (t < p) {
+      const float* ip = in + (int64_t)t * count + e;
+      if (vec && e + 4 <= count) {
+        const float4 q = *reinterpret_cast<const float4*>(ip);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+      } else {
+        for (int u = 0; u < 4; ++u) v[u] = (e + u < count) ? ip[u] : 0.0f;
+      }
+      if (SCALE) {
+        for (int u = 0; u < 4; ++u) v[u] *= sc;
+        if (xnorm != nullptr) {
+          float* xp = xnorm + (int64_t)t * count + e;
+          if (vec && e + 4 <= count) *reinterpret_cast<float4*>(xp) = make_float4(v[0], v[1], v[2], v[3]);
+          else for (int u = 0; u < 4; ++u) if (e + u < count) xp[u] = v[u];
+        }
+      }
+    }
+    *reinterpret_cast<float4*>(&sX[t * LDX + c]) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  typename MF::frag_t acc[FR];
+#pragma unroll
+  for (int f = 0; f < FR; ++f)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[f][r] = 0.0f;
+#pragma unroll 4
+  for (int t0 = 0; t0 < PM; t0 += 4) {
+    const float* bp = &sX[(t0 + lk) * LDX + wave * 16 + lr];
+#pragma unroll
+    for (int f = 0; f < FR; ++f) acc[f] = MF::mac(&sG[(f * 16 + lr) * LDG + t0 + lk], bp, acc[f]);
+  }
+  double sq = 0.0;
+  const int64_t e = e0 + wave * 16 + lr;
+  if (e < count) {
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = f * 16 + lk * 4 + r;
+        if (k < p) {
+          float y = a * acc[f][r];
+          if (EPI && b != 0.0f) y += b * (float)src[(int64_t)k * count + e];
+          out[(int64_t)k * count + e] = cvt<TOUT, float>(y);
+          if (EPI) sq += (double)y * (double)y;
+        }
+      }
+  }
+  if (EPI && ta.ctl.part_out != nullptr) {
+    const double tot = block_sum_all(sq, sh);
+    if (tid == 0) ta.ctl.part_out[vb.x] = tot;
+  }
+}
+
+template <typename TOUT>
+static hipError_t launch_tube_mfma(dctk_ctx ctx, hipStream_t s, int64_t p, int64_t count, const void* in, void* out,
+                                   const float* G, const void* src, void* xnorm, const Ctl& ctl, bool scale,
+                                   bool epi, int* nblocks_out) {
+  const int64_t blocks = (count + 63) / 64;
+  if (nblocks_out) *nblocks_out = (int)blocks;
+  if (epi && ctl.part_out != nullptr && blocks > kRedBlocks) return hipErrorInvalidConfiguration;
+  TubeArgs ta{};
+  ta.p = (int)p;
+  ta.count = count;
+  ta.in = in;
+  ta.out = out;
+  ta.G = G;
+  ta.src = src;
+  ta.xnorm = xnorm;
+  ta.ctl = ctl;
+  const dim3 grid((unsigned)blocks);
+#define DCTK_TM(PM_) \
+  do { \
+    if (scale && epi) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, true, true>, grid, 256, 0, ta); \
+    if (scale) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, true, false>, grid, 256, 0, ta); \
+    if (epi) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, false, true>, grid, 256, 0, ta); \
+    return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, false, false>, grid, 256, 0, ta); \
+  } while (0)
+  if (p <= 16) DCTK_TM(16);
+  if (p <= 32) DCTK_TM(32);
+  if (p <= 48) DCTK_TM(48);
+  DCTK_TM(64);
+#undef DCTK_TM
+}
+
 template <typename TIN, typename TOUT, typename TC>
 static hipError_t launch_tube_t(dctk_ctx ctx, hipStream_t s, int64_t p, int64_t count, const void* in, void* out,
                                 const TC* G, const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi,
@@ -256,15 +386,22 @@ hipError_t launch_tube(dctk_ctx ctx, hipStream_t s, int in_dtype, int out_dtype,
     if (out_dtype != DCTK_F64) return hipErrorInvalidValue;
     return launch_tube_t<double, double, double>(ctx, s, p, count, in, out, Gd, src, xnorm, ctl, scale, epi, nblocks_out);
   }
+  // long tubes on the matrix cores (unless the 64-position blocks would exceed the partial-sum slots)
+  const bool mfma = p >= 16 && p <= kMaxTube && !(epi && ctl.part_out != nullptr && (count + 63) / 64 > kRedBlocks);
   switch (out_dtype) {
     case DCTK_F32:
+      if (mfma) return launch_tube_mfma<float>(ctx, s, p, count, in, out, Gf, src, xnorm, ctl, scale, epi, nblocks_out);
       return launch_tube_t<float, float, float>(ctx, s, p, count, in, out, Gf, src, xnorm, ctl, scale, epi, nblocks_out);
     case DCTK_BF16:
       if (src) return hipErrorInvalidValue;
+      if (mfma)
+        return launch_tube_mfma<bf16_t>(ctx, s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false, nblocks_out);
       return launch_tube_t<float, bf16_t, float>(ctx, s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false,
                                                  nblocks_out);
     case DCTK_F16:
       if (src) return hipErrorInvalidValue;
+      if (mfma)
+        return launch_tube_mfma<f16_t>(ctx, s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false, nblocks_out);
       return launch_tube_t<float, f16_t, float>(ctx, s, p, count, in, out, Gf, nullptr, xnorm, ctl, scale, false,
                                                 nblocks_out);
     default:

@@ -94,7 +94,7 @@ def moving_blobs(rng, p, n, s, count=8, speed=2.0):
 
 def mixed_blur(tube, T):
     """A with frontal slices A(:,:,k) = tube_k * T."""
-    return np.stack([c * T for c in tube], axis=0)
+    return np.ascontiguousarray(np.stack([c * T for c in tube], axis=0))
 
 
 def tube_for(p):
