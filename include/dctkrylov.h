@@ -145,7 +145,7 @@ int dctk_op_destroy(dctk_op op);
  * operators with p <= 8) -- or as three kernels: tube transform, batched slice
  * GEMMs, inverse transform with epilogue (Algorithm 1 steps 1-3).  The
  * output tile edge of the GEMM part is 16, 32 or 64 (fused) or 32, 64 or 128
- * (three kernels; 128 for FP32 only).  All paths compute the same product;
+ * (three kernels; 128 not for FP64).  All paths compute the same product;
  * results differ only by the rounding of the contraction order.
  * dctk_op_autotune: times every path and tile the operator can take, `reps`
  * launches each (1..1000) of the forward and of the adjoint product on ctx's

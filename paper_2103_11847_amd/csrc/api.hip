@@ -346,7 +346,7 @@ int dctk_op_autotune(dctk_ctx ctx, dctk_op op, int reps, int* choice) {
     }
     cand[nc][0] = 0; cand[nc++][1] = 32;
     cand[nc][0] = 0; cand[nc++][1] = 64;
-    if (op->gemm_dtype == DCTK_F32) { cand[nc][0] = 0; cand[nc++][1] = 128; }
+    if (op->gemm_dtype != DCTK_F64) { cand[nc][0] = 0; cand[nc++][1] = 128; }
     float best = 1e30f;
     int bi = -1;
     for (int i = 0; i < nc && e == hipSuccess; ++i) {

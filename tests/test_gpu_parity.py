@@ -163,7 +163,7 @@ def test_low_precision_gemm_modes(ctx, gdt, u, two_sided):
 PATHS = [(1, 16), (1, 32), (1, 64), (0, 32), (0, 64), (0, 128)]
 
 
-@pytest.mark.parametrize("gdt", [dk.DCTK_F64, dk.DCTK_F32])
+@pytest.mark.parametrize("gdt", [dk.DCTK_F64, dk.DCTK_F32, dk.DCTK_BF16, dk.DCTK_F16])
 @pytest.mark.parametrize("shape,two_sided", [((3, 96, 80, 72), False), ((8, 64, 64, 64), False),
                                              ((5, 40, 56, 44), False), ((3, 33, 37, 29), False),
                                              ((4, 48, 48, 48), True), ((12, 70, 70, 36), False)])
@@ -175,6 +175,8 @@ def test_every_product_path_and_tile(ctx, gdt, shape, two_sided):
     op = Op(ctx, w["A"], w["B"], s, gdt)
     X, Yin = to_gpu(w["X"], op.vt), to_gpu(w["Y"], op.vt)
     ref, ref_t = op.oracle.apply(w["X"]), op.oracle.adjoint(w["Y"])
+    u = {dk.DCTK_BF16: 2.0 ** -8, dk.DCTK_F16: 2.0 ** -11}.get(gdt)
+    tol = TOL_PROD[gdt] if u is None else 8.0 * u * np.sqrt(p) * (2.0 if two_sided else 1.0)
     ran = 0
     for path, tile in PATHS:
         ok = True
@@ -188,10 +190,10 @@ def test_every_product_path_and_tile(ctx, gdt, shape, two_sided):
         say("path", shape, two_sided, gdt, path, tile)
         Y = torch.empty((p, n1, s), dtype=op.vt, device="cuda:0")
         dk.dctk_cprod(ctx, op.h, 1.0, X, 0.0, Y)
-        assert rel(to_np(Y), ref) <= TOL_PROD[gdt], (path, tile)
+        assert rel(to_np(Y), ref) <= tol, (path, tile)
         Z = torch.empty((p, n2, s), dtype=op.vt, device="cuda:0")
         dk.dctk_cprod_T(ctx, op.h, 1.0, Yin, 0.0, Z)
-        assert rel(to_np(Z), ref_t) <= TOL_PROD[gdt], (path, tile)
+        assert rel(to_np(Z), ref_t) <= tol, (path, tile)
         ran += 1
     fusable = not two_sided and p <= 8
     assert ran >= (5 if fusable else 3) - (1 if fusable and gdt == dk.DCTK_F64 else 0)
