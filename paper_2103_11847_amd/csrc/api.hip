@@ -456,8 +456,8 @@ int dctk_krylov_create(dctk_ctx ctx, dctk_op op, int kind, int k_max, int ortho,
   if (e == hipSuccess) e = hipMalloc(&ws->W, ws->vbytes);
   if (e == hipSuccess) e = hipMalloc(&ws->T, 2 * ws->vbytes);
   if (e == hipSuccess) e = hipMalloc(&ws->R, ws->vbytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&ws->partA, sizeof(double) * kRedBlocks);
-  if (e == hipSuccess) e = hipMalloc((void**)&ws->partB, sizeof(double) * kRedBlocks);
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->partA, sizeof(double) * kNormParts);
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->partB, sizeof(double) * kNormParts);
   if (e == hipSuccess) e = hipMalloc((void**)&ws->partM, sizeof(double) * kRedBlocks * kRedVals);
   if (e == hipSuccess) e = hipMalloc((void**)&ws->st, sizeof(KState));
   if (e == hipSuccess) e = hipMemset(ws->st, 0, sizeof(KState));

@@ -9,7 +9,7 @@
 // one schedule point are merged into a single launch: its 1-D grid is the
 // concatenation of the instances' grids, and a per-workgroup map gives each
 // workgroup its instance and its (x, y, z) inside that instance's grid (see
-// pick_args).  The merged schedule is replayed in order on one stream, which
+// group_args).  The merged schedule is replayed in order on one stream, which
 // keeps every instance's own launch order; it is captured into a HIP graph
 // once.
 #include <algorithm>
@@ -135,7 +135,7 @@ int dctk_batch_create(dctk_ctx ctx, int count, const dctk_krylov* ws, const void
       const std::vector<Member>& mem = kv.second;
       const LaunchRec& r0 = *mem[0].r;
       dctk_batch_s::Launch L;
-      L.fn = kv.first;
+      L.fn = mem.size() == 1 ? kv.first : r0.fn_group;
       L.threads = r0.threads;
       L.shmem = 0;
       L.arg0 = r0.args;

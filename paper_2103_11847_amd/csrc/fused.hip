@@ -51,7 +51,7 @@ __device__ inline void xcd_tile(const VBlock& vb, bool grouped, int gx, int gy, 
 
 // EXACT: p == PMAX (no slice guards); otherwise p <= PMAX at run time.
 template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA>
-__global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const FusedArgs* grp, const int4* bmap) {
+__device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, const VBlock vb, const bool grouped) {
   typedef Mfma<TI> MF;
   typedef typename MF::acc_t acc_t;
   typedef typename MF::frag_t frag_t;
@@ -70,21 +70,19 @@ __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const F
   __shared__ __attribute__((aligned(16))) TI As[PMAX * BM * LD];
   __shared__ __attribute__((aligned(16))) TI Bs[PMAX * BN * LD];
   __shared__ TV sGin[PMAX * PMAX], sGout[PMAX * PMAX];
-  __shared__ double sh[8];
+  __shared__ double sh[kShCtl];
 
-  VBlock vb;
-  const FusedArgs fa = pick_args(fa_, grp, bmap, vb);
-  double a_d, b_d, s_d;
-  if (!ctl_begin(fa.ctl, a_d, b_d, s_d, sh, vb)) return;
-  const TV sc = (TV)s_d;
-
+  static_assert(PMAX * PMAX <= 256, "one transform entry per thread");
   const int p = EXACT ? PMAX : fa.p;
-  const int M = fa.M, N = fa.N, K = fa.K;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < p * p; i += 256) {
-    sGin[i] = ((const TV*)fa.Gin)[i];
-    sGout[i] = ((const TV*)fa.Gout)[i];
-  }
+  // The transform matrices (to registers, stored to LDS after the control
+  // block), the first chunk and the control block's values are loaded in one
+  // go, so the kernel waits for memory once before the first store.
+  const bool gown = tid < p * p;
+  const TV gin_r = ((const TV*)fa.Gin)[gown ? tid : 0];
+  const TV gout_r = ((const TV*)fa.Gout)[gown ? tid : 0];
+
+  const int M = fa.M, N = fa.N, K = fa.K;
   const int m0 = vb.y * BM, n0 = vb.x * BN;
   const TI* A = (const TI*)fa.A;
   const TV* X = (const TV*)fa.X;
@@ -113,6 +111,7 @@ __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const F
   constexpr int A_PER = (A_TOT + 255) / 256, X_PER = (X_TOT + 255) / 256;
   TI ra[A_PER];
   TV rx[X_PER][PMAX];
+  TV sc = (TV)1;  // input scale, set by the control block before the first store
   auto load_chunk = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < A_PER; ++u) {
@@ -185,6 +184,14 @@ __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const F
   };
 
   load_chunk(0);
+  const CtlLoad cl = ctl_load(fa.ctl);
+  double a_d, b_d, s_d;
+  if (!ctl_eval(fa.ctl, cl, a_d, b_d, s_d, sh, vb)) return;
+  sc = (TV)s_d;
+  if (gown) {
+    sGin[tid] = gin_r;
+    sGout[tid] = gout_r;
+  }
   for (int k0 = 0; k0 < K; k0 += BKT) {
     __syncthreads();
     store_chunk(k0);
@@ -275,8 +282,20 @@ __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const F
       }
   }
   if (fa.ctl.part_out != nullptr) {
-    const double tot = block_sum_all(sq, sh);
-    if (tid == 0) fa.ctl.part_out[vb.y * fa.gx + vb.x] = tot;
+    // one partial per wave (no block-wide exchange), in tile order
+    const double tot = wave_sum(sq);
+    if (lane == 0) fa.ctl.part_out[(vb.y * fa.gx + vb.x) * 4 + wave] = tot;
+  }
+}
+
+template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA, bool GROUPED>
+__global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const FusedArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, TA>(fa_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const FusedArgs g = group_args(grp, bmap, vb);
+    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, TA>(g, vb, true);
   }
 }
 
@@ -288,7 +307,7 @@ __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const F
 // base pointers (the host checks that every tensor has < 2^31 elements).
 
 template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA, int VW>
-__global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa_, const FusedArgs* grp, const int4* bmap) {
+__device__ __forceinline__ void cprod_fused_mn_kernel_body(const FusedArgs& fa, const VBlock vb, const bool grouped) {
   typedef Mfma<T> MF;
   typedef typename MF::acc_t acc_t;
   typedef typename MF::frag_t frag_t;
@@ -318,20 +337,21 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa_, cons
   T* const As = smem;
   T* const Bs = smem + A_LDS;
   __shared__ T sGin[PMAX * PMAX], sGout[PMAX * PMAX];
-  __shared__ double sh[8];
+  __shared__ double sh[kShCtl];
 
-  VBlock vb;
-  const FusedArgs fa = pick_args(fa_, grp, bmap, vb);
   const int p = EXACT ? PMAX : fa.p;
   const int M = fa.M, N = fa.N, K = fa.K;
   const int lda = (int)fa.lda, sA = (int)fa.sA;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < p * p; i += 256) {
-    sGin[i] = ((const T*)fa.Gin)[i];
-    sGout[i] = ((const T*)fa.Gout)[i];
-  }
+  // The transform matrices (to registers, stored to LDS after the control
+  // block), the first chunk and the control block's values are loaded in one
+  // go, so the kernel waits for memory once before the first store.
+  static_assert(PMAX * PMAX <= 256, "one transform entry per thread");
+  const bool gown = tid < p * p;
+  const T gin_r = ((const T*)fa.Gin)[gown ? tid : 0];
+  const T gout_r = ((const T*)fa.Gout)[gown ? tid : 0];
   int tx, ty;
-  xcd_tile(vb, grp != nullptr, fa.gx, fa.gy, tx, ty);
+  xcd_tile(vb, grouped, fa.gx, fa.gy, tx, ty);
   const int m0 = ty * BM, n0 = tx * BN;
   const T* A = (const T*)fa.A;
   const T* X = (const T*)fa.X;
@@ -448,12 +468,15 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa_, cons
     }
   };
 
-  // the first chunk's loads do not depend on the control block: issue them
-  // before its (memory-latency bound) evaluation
   load_chunk(0);
+  const CtlLoad cl = ctl_load(fa.ctl);
   double a_d, b_d, s_d;
-  if (!ctl_begin(fa.ctl, a_d, b_d, s_d, sh, vb)) return;
+  if (!ctl_eval(fa.ctl, cl, a_d, b_d, s_d, sh, vb)) return;
   sc = (T)s_d;
+  if (gown) {
+    sGin[tid] = gin_r;
+    sGout[tid] = gout_r;
+  }
   for (int k0 = 0; k0 < K; k0 += BKT) {
     __syncthreads();
     store_chunk(k0);
@@ -574,8 +597,21 @@ __global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa_, cons
       }
     }
   if (fa.ctl.part_out != nullptr) {
-    const double tot = block_sum_all(sq, sh);
-    if (tid == 0) fa.ctl.part_out[ty * fa.gx + tx] = tot;  // by tile: the same order under any tile mapping
+    // one partial per wave (no block-wide exchange), by tile: the same order
+    // under any tile mapping
+    const double tot = wave_sum(sq);
+    if (lane == 0) fa.ctl.part_out[(ty * fa.gx + tx) * 4 + wave] = tot;
+  }
+}
+
+template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA, int VW, bool GROUPED>
+__global__ __launch_bounds__(256) void cprod_fused_mn_kernel(FusedArgs fa_, const FusedArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    cprod_fused_mn_kernel_body<T, PMAX, EXACT, BM, BN, WK, BK, TA, VW>(fa_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const FusedArgs g = group_args(grp, bmap, vb);
+    cprod_fused_mn_kernel_body<T, PMAX, EXACT, BM, BN, WK, BK, TA, VW>(g, vb, true);
   }
 }
 
@@ -592,11 +628,12 @@ struct FusedLaunch {
 template <typename T, int PMAX, bool EXACT, int BM, int BN, int WK, int BK>
 static hipError_t launch_fused_mn_cfg(const FusedLaunch& L, const FusedArgs& fa, int ta, bool vec, int* nblocks_out) {
   dim3 grid((unsigned)((fa.N + BN - 1) / BN), (unsigned)((fa.M + BM - 1) / BM));
-  if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
-  if ((int64_t)grid.x * grid.y > kRedBlocks && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
+  // one norm partial per wave (256 threads: 4 waves)
+  if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y * 4);
+  if ((int64_t)grid.x * grid.y * 4 > kNormParts && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
   constexpr int VW = 16 / (int)sizeof(T);
 #define DCTK_MN_LAUNCH(TA_, VW_) \
-  launch_kernel(L.ctx, L.s, cprod_fused_mn_kernel<T, PMAX, EXACT, BM, BN, WK, BK, TA_, VW_>, grid, 256, 0, fa, L.e0, L.e1)
+  launch_kernel(L.ctx, L.s, cprod_fused_mn_kernel<T, PMAX, EXACT, BM, BN, WK, BK, TA_, VW_, false>, cprod_fused_mn_kernel<T, PMAX, EXACT, BM, BN, WK, BK, TA_, VW_, true>, grid, 256, 0, fa, L.e0, L.e1)
   if (ta) return vec ? DCTK_MN_LAUNCH(true, VW) : DCTK_MN_LAUNCH(true, 1);
   return vec ? DCTK_MN_LAUNCH(false, VW) : DCTK_MN_LAUNCH(false, 1);
 #undef DCTK_MN_LAUNCH
@@ -632,10 +669,11 @@ static hipError_t launch_fused_mn(const FusedLaunch& L, const FusedArgs& fa, int
 template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK>
 static hipError_t launch_fused_cfg(const FusedLaunch& L, const FusedArgs& fa, int ta, int* nblocks_out) {
   dim3 grid((unsigned)((fa.N + BN - 1) / BN), (unsigned)((fa.M + BM - 1) / BM));
-  if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
-  if ((int64_t)grid.x * grid.y > kRedBlocks && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
-  if (ta) return launch_kernel(L.ctx, L.s, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true>, grid, 256, 0, fa, L.e0, L.e1);
-  return launch_kernel(L.ctx, L.s, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false>, grid, 256, 0, fa, L.e0, L.e1);
+  // one norm partial per wave (256 threads: 4 waves)
+  if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y * 4);
+  if ((int64_t)grid.x * grid.y * 4 > kNormParts && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
+  if (ta) return launch_kernel(L.ctx, L.s, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true, false>, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true, true>, grid, 256, 0, fa, L.e0, L.e1);
+  return launch_kernel(L.ctx, L.s, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false, false>, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false, true>, grid, 256, 0, fa, L.e0, L.e1);
 }
 
 // Tile choice: 16x16 with a split contraction while 32x32 tiles would not

@@ -28,9 +28,7 @@ struct GemmArgs {
 };
 
 template <typename TI, typename TO, int BM, int BN, bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const GemmArgs ga = pick_args(ga_, grp, bmap, vb);
+__device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBlock vb, const bool grouped) {
   const int M = ga.M, N = ga.N, K = ga.K;
   const TI* __restrict__ A = (const TI*)ga.A;
   const TI* __restrict__ B = (const TI*)ga.B;
@@ -163,6 +161,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs ga_, const GemmArgs*
     }
 }
 
+template <typename TI, typename TO, int BM, int BN, bool TA, bool TB, bool GROUPED>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    gemm_kernel_body<TI, TO, BM, BN, TA, TB>(ga_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const GemmArgs g = group_args(grp, bmap, vb);
+    gemm_kernel_body<TI, TO, BM, BN, TA, TB>(g, vb, true);
+  }
+}
+
 // FP32 / FP64 slice GEMM with 16-byte global loads (VW elements) along each
 // operand's contiguous dimension and LDS tiles kept in that same orientation:
 // A~ as [m][k] (or [k][m] when transposed), the right operand as [k][n] (or
@@ -173,7 +182,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs ga_, const GemmArgs*
 // registers while the current one is multiplied.  Out-of-range elements are
 // loaded from a clamped address and replaced by zero (no branches per load).
 template <typename T, int BM, int BN, int BK, bool TA, bool TB, int VW>
-__global__ __launch_bounds__(256) void gemm_mn_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
+__device__ __forceinline__ void gemm_mn_kernel_body(const GemmArgs& ga, const VBlock vb, const bool grouped) {
   typedef Mfma<T> MF;
   typedef typename MF::frag_t frag_t;
   constexpr int KSTEP = MF::KSTEP;
@@ -190,8 +199,6 @@ __global__ __launch_bounds__(256) void gemm_mn_kernel(GemmArgs ga_, const GemmAr
   static_assert(FM >= 1 && FN >= 1, "tile");
   static_assert(BK % KSTEP == 0 && BK % VW == 0 && BM % VW == 0 && BN % VW == 0, "chunk");
 
-  VBlock vb;
-  const GemmArgs ga = pick_args(ga_, grp, bmap, vb);
   if (!gate_open(ga.g)) return;
   __shared__ __attribute__((aligned(16))) T As[A_LDS];
   __shared__ __attribute__((aligned(16))) T Bs[B_LDS];
@@ -307,12 +314,23 @@ __global__ __launch_bounds__(256) void gemm_mn_kernel(GemmArgs ga_, const GemmAr
     }
 }
 
+template <typename T, int BM, int BN, int BK, bool TA, bool TB, int VW, bool GROUPED>
+__global__ __launch_bounds__(256) void gemm_mn_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    gemm_mn_kernel_body<T, BM, BN, BK, TA, TB, VW>(ga_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const GemmArgs g = group_args(grp, bmap, vb);
+    gemm_mn_kernel_body<T, BM, BN, BK, TA, TB, VW>(g, vb, true);
+  }
+}
+
 template <typename T, int BM, int BN, int BK>
 static hipError_t launch_gemm_mn(dctk_ctx ctx, hipStream_t s, const GemmArgs& ga, int ta, int tb, bool vec,
                                  int batch) {
   const dim3 grid((unsigned)((ga.N + BN - 1) / BN), (unsigned)((ga.M + BM - 1) / BM), (unsigned)batch);
   constexpr int VW = 16 / (int)sizeof(T);
-#define DCTK_GMN(TA_, TB_, VW_) return launch_kernel(ctx, s, gemm_mn_kernel<T, BM, BN, BK, TA_, TB_, VW_>, grid, 256, 0, ga)
+#define DCTK_GMN(TA_, TB_, VW_) return launch_kernel(ctx, s, gemm_mn_kernel<T, BM, BN, BK, TA_, TB_, VW_, false>, gemm_mn_kernel<T, BM, BN, BK, TA_, TB_, VW_, true>, grid, 256, 0, ga)
 #define DCTK_GMN_V(TA_, TB_)    \
   do {                          \
     if (vec) DCTK_GMN(TA_, TB_, VW); \
@@ -378,7 +396,7 @@ static hipError_t launch_gemm_tile(dctk_ctx ctx, hipStream_t s, int M, int N, in
   ga.ldc = ldc;
   ga.sC = sC;
   ga.g = g;
-#define DCTK_GEMM_LAUNCH(TA_, TB_) return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_>, grid, 256, 0, ga)
+#define DCTK_GEMM_LAUNCH(TA_, TB_) return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_, false>, gemm_kernel<TI, TO, BM, BN, TA_, TB_, true>, grid, 256, 0, ga)
   if (!ta && !tb) DCTK_GEMM_LAUNCH(false, false);
   if (ta && !tb) DCTK_GEMM_LAUNCH(true, false);
   if (!ta && tb) DCTK_GEMM_LAUNCH(false, true);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
+#include <cstddef>
 #include <stdint.h>
 #include <string.h>
 
@@ -14,8 +15,10 @@ namespace dctk {
 
 constexpr int kMaxK = 64;              // largest Krylov dimension (projected problem <= 65 x 64)
 constexpr int kRedBlocks = 4096;       // max blocks of a reducing kernel (partials per reduction)
+constexpr int kNormParts = 4 * kRedBlocks;  // capacity of the norm partial buffers (fused products write one per wave)
 constexpr int kRedVals = kMaxK + 2;    // max values reduced by one multi-dot kernel
 constexpr int kThreads = 256;          // threads per block of streaming kernels
+constexpr int kShCtl = 2 * (kThreads / 64 + 1);  // LDS doubles of the prologue reductions (blocks <= kThreads)
 constexpr int kMaxTube = 64;           // largest n3 (the p x p transform matrix sits in LDS)
 constexpr int kFusedMaxP = 8;          // n3 up to which a c-product is one fused kernel
 constexpr double kBreakFactor = 64.0;  // breakdown: new norm <= 64 eps * running max
@@ -58,10 +61,14 @@ struct KState {
   double pred_lambda;               // learned stop: predicted lambda (0: none)
 };
 
-// GKB step j runs only up to a learned step limit (0: no limit)
-__device__ inline bool beyond_limit(const KState* st, int j) {
-  const int kl = ((const volatile KState*)st)->k_limit;
-  return kl > 0 && j > kl;
+
+// Loads of state fields that a workgroup of the same kernel may be writing:
+// relaxed device-scope atomic loads.  (A volatile access would do, but on this
+// target each one waits for every outstanding load of the thread, so a
+// prologue of several of them pays the memory latency several times.)
+__device__ inline int ld_state(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline double ld_state(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- control of a product kernel inside a Krylov step -----------------------
@@ -110,9 +117,38 @@ template <> __device__ inline bf16_t cvt<bf16_t, double>(double v) { return floa
 template <> __device__ inline f16_t cvt<f16_t, double>(double v) { return (f16_t)(float)v; }
 
 // ---- wave / block reductions (64-wide waves) -----------------------------
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+// DPP moves of a 64-bit value (two 32-bit halves) within 16-lane rows
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  const long long r = ((long long)(unsigned)lo) | ((long long)hi << 32);
+  return __builtin_bit_cast(double, r);
+}
+
+// Sum over the 16 lanes of a row, returned to every lane of the row (identical
+// bits: each step adds a commuted copy of the same partial sums).  All lanes
+// of the wave must be active.
+__device__ inline double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
   return v;
+}
+
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// Sum over the wave in a fixed order, the same in every lane (all lanes active).
+__device__ inline double wave_sum(double v) {
+  v = row16_sum(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // Sum over the block; the result is returned to every thread.  `sh` holds
@@ -154,12 +190,73 @@ __device__ inline double block_sum_partials(const double* part, int n, double* s
   return block_sum_all(v, sh);
 }
 
-// Running max of |alpha_1..alpha_na|, |beta_1..beta_nb| (breakdown scale).
+// This thread's share of sum(part[0..n)): block_sum_all of it is
+// block_sum_partials.  The values are added in the order of the plain strided
+// loop.  part_first takes the first 4 * blockDim entries with four loads that
+// need neither a loop nor a branch (clamped addresses, then selects; part[0]
+// must exist), so they stay in flight with the caller's other loads -- on this
+// target a load inside a conditional block or a loop is waited for before the
+// block ends.  part_rest adds the entries beyond (a loop, rarely entered).
+__device__ inline double part_first(const double* part, int n) {
+  const int bd = (int)blockDim.x, i = (int)threadIdx.x;
+  const int i1 = i + bd, i2 = i + 2 * bd, i3 = i + 3 * bd;
+  const double a0 = part[i < n ? i : 0], a1 = part[i1 < n ? i1 : 0];
+  const double a2 = part[i2 < n ? i2 : 0], a3 = part[i3 < n ? i3 : 0];
+  double v = 0.0;
+  v = i < n ? v + a0 : v;
+  v = i1 < n ? v + a1 : v;
+  v = i2 < n ? v + a2 : v;
+  v = i3 < n ? v + a3 : v;
+  return v;
+}
+__device__ inline double part_rest(double v, const double* part, int n) {
+  for (int i = (int)threadIdx.x + 4 * (int)blockDim.x; i < n; i += (int)blockDim.x) v += part[i];
+  return v;
+}
+__device__ inline double part_local(const double* part, int n) {
+  if (n <= 0) return 0.0;
+  return part_rest(part_first(part, n), part, n);
+}
+
+// (1 <= na, nb <= kMaxK + 2 < kThreads: one value of each per thread, from an
+// index clamped into the range -- a repeated value does not change the max --
+// so the loads need no branch)
+__device__ inline double gkb_scale_local(const KState* st, int na, int nb) {
+  static_assert(kMaxK + 2 <= kThreads, "one history value per thread");
+  const int i = (int)threadIdx.x;
+  const double av = st->alpha[i < na ? i : na - 1], bv = st->beta[i < nb ? i : nb - 1];
+  return fmax(fabs(av), fabs(bv));
+}
+
+// Running max of |alpha_1..alpha_na|, |beta_1..beta_nb| over the block.
 __device__ inline double gkb_scale(const KState* st, int na, int nb, double* sh) {
-  double m = 0.0;
-  for (int i = threadIdx.x; i < na; i += blockDim.x) m = fmax(m, fabs(st->alpha[i]));
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) m = fmax(m, fabs(st->beta[i]));
-  return block_max_all(m, sh);
+  return block_max_all(gkb_scale_local(st, na, nb), sh);
+}
+
+// Sum of s (in block_sum_all's order, so the same bits) and max of m over the
+// block in one exchange; both returned to every thread.  `sh` holds kShCtl doubles.
+__device__ inline void block_sum_max_all(double& s, double& m, double* sh) {
+  s = wave_sum(s);
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  __syncthreads();
+  if (lane == 0) {
+    sh[2 * wid] = s;
+    sh[2 * wid + 1] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0, x = sh[1];
+    for (int w = 0; w < nw; ++w) {
+      r += sh[2 * w];
+      x = fmax(x, sh[2 * w + 1]);
+    }
+    sh[2 * nw] = r;
+    sh[2 * nw + 1] = x;
+  }
+  __syncthreads();
+  s = sh[2 * nw];
+  m = sh[2 * nw + 1];
 }
 
 // ---- plain and grouped launches -------------------------------------------------
@@ -175,41 +272,115 @@ struct VBlock {
 
 __device__ inline VBlock hw_block() { return VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z}; }
 
+// Grouped launches: the instance's argument struct and its workgroup index,
+// copied word by word through readfirstlane so they stay in scalar registers.
+// (Each batchable kernel has a body taking the struct by reference and two
+// call sites -- the kernel argument itself, or this copy -- so the plain path
+// reads its pointers straight from the kernel arguments, where the compiler
+// knows them to be global.)
 template <typename A>
-__device__ inline A pick_args(const A& a, const A* grp, const int4* bmap, VBlock& vb) {
-  if (grp == nullptr) {
-    vb = hw_block();
-    return a;
-  }
+__device__ inline A group_args(const A* grp, const int4* bmap, VBlock& vb) {
+  static_assert(sizeof(A) % 4 == 0, "argument struct of whole words");
   const int4 m = bmap[blockIdx.x];
-  vb = VBlock{m.y, m.z, m.w};
-  return grp[m.x];
+  vb = VBlock{__builtin_amdgcn_readfirstlane(m.y), __builtin_amdgcn_readfirstlane(m.z),
+              __builtin_amdgcn_readfirstlane(m.w)};
+  const int* src = reinterpret_cast<const int*>(grp + __builtin_amdgcn_readfirstlane(m.x));
+  A r;
+  int* dst = reinterpret_cast<int*>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(A) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return r;
 }
 
-// Evaluates the control block at kernel start (all threads of every block
-// call it).  Returns false when the kernel must do nothing.  Block (0, 0, 0)
-// of the instance records the scalar it produced in the state.  `sh` holds
-// >= 20 doubles.
-__device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin, double* sh, const VBlock& vb) {
+// What a control block reads from memory.  ctl_load issues every load (the
+// recorded scalar, this thread's share of the history that scales the
+// breakdown test and of the partials, then the stop flags), none of them
+// inside a branch -- on this target a load in a conditional block is waited
+// for before the block ends; ctl_eval uses them.  A kernel that issues its own
+// first loads, then calls ctl_load, waits for memory once.
+struct CtlLoad {
+  double ps, pm, rec;
+  int ss, kl, halt;
+};
+
+__device__ inline CtlLoad ctl_load(const Ctl& c) {
+  CtlLoad L{0.0, 0.0, 0.0, -1, 0, 0};
+  if (c.kind == CTL_PLAIN) {
+    if (c.st != nullptr) L.halt = ld_state(&c.st->halt);
+    return L;
+  }
+  // Every load is unconditional, from an index computed (or clamped) into the
+  // state or the partials; the kind only selects indices and, afterwards,
+  // values.
+  const KState* st = c.st;
+  const double* sd = reinterpret_cast<const double*>(st);
+  constexpr int oA = (int)(offsetof(KState, alpha) / sizeof(double));
+  constexpr int oB = (int)(offsetof(KState, beta) / sizeof(double));
+  constexpr int oH = (int)(offsetof(KState, H) / sizeof(double));
+  const int j = c.j, i = (int)threadIdx.x;
+  const bool fs = c.from_state != 0;
+  const bool fwd = c.kind == CTL_GKB_FWD, ini = c.kind == CTL_GKB_INIT, adj = c.kind == CTL_GKB_ADJ,
+             arn = c.kind == CTL_ARN_FWD;
+  // the recorded scalar this kernel needs (beta_1 when none)
+  int ri = oB;
+  ri = (fs && arn && j > 1) ? oH + (j - 1) * kMaxK + j - 2 : ri;
+  ri = (fs && adj) ? oB + j : ri;
+  ri = fwd ? oA + j - 1 : ri;
+  L.rec = sd[ri];
+  // breakdown scale: max |alpha_1..alpha_j|, |beta_1..beta_j| (GKB adjoint) or
+  // max_i |h_{i, j-1}| (Arnoldi), one value of each per thread from a clamped
+  // index (j <= kMaxK + 1 < kThreads; a repeated value does not change the max)
+  static_assert(kMaxK + 2 <= kThreads, "one history value per thread");
+  const int ia = j > 1 ? (i < j ? i : j - 1) : 0;
+  const int ih = j > 2 ? (i < j - 1 ? i : j - 2) : 0, ch = j > 2 ? j - 2 : 0;
+  const double av = sd[oA + ia], bv = sd[oB + ia], hv = sd[oH + ih * kMaxK + ch];
+  const double wab = adj ? 1.0 : 0.0, wh = arn ? 1.0 : 0.0;
+  L.pm = fmax(wab * fmax(fabs(av), fabs(bv)), wh * fabs(hv));
+  // the partials of the norm (from beta_1, with no entries, when none)
+  const bool sums = !fs && (ini || adj || (arn && j > 1));
+  L.ps = part_first(sums ? c.part_in : sd + oB, sums ? c.npart_in : 0);
+  // the stop flags last: the compiler moves these uniform values to scalar
+  // registers, which waits for them, and with them for every earlier load
+  L.ss = ld_state(&st->stop_step);
+  L.kl = ld_state(&st->k_limit);
+  L.halt = ld_state(&st->halt);
+  return L;
+}
+
+// Evaluates the control block (all threads of every block call it).  Returns
+// false when the kernel must do nothing.  Block (0, 0, 0) of the instance
+// records the scalar it produced in the state.  `sh` holds kShCtl doubles
+// (blocks of at most kThreads threads).
+__device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, double& b, double& sin, double* sh,
+                                const VBlock& vb) {
   a = 1.0; b = 0.0; sin = 1.0;
   if (c.kind == CTL_PLAIN) {
     // a plain product inside a GMRES solve is skipped once the solve halted
-    if (c.st != nullptr && ((volatile KState*)c.st)->halt) return false;
+    if (L.halt) return false;
     a = c.a; b = c.b; sin = c.s;
     return true;
   }
+  // The loaded values are taken into registers here, in one wait: without
+  // this use the compiler may sink each load into the branch that needs it,
+  // where it would be waited for on its own.
+  asm volatile("" ::"v"(L.ps), "v"(L.pm), "v"(L.rec), "v"(L.ss), "v"(L.kl), "v"(L.halt));
   KState* st = c.st;
-  const int ss = ((volatile KState*)st)->stop_step;
+  const int j = c.j;
+  const bool sums = !c.from_state && (c.kind == CTL_GKB_INIT || c.kind == CTL_GKB_ADJ || (c.kind == CTL_ARN_FWD && j > 1));
+  double ps = sums ? part_rest(L.ps, c.part_in, c.npart_in) : 0.0, pm = L.pm;
+  const double rec = L.rec;
+  const int ss = L.ss, kl = L.kl, halt = L.halt;
+  const bool beyond = kl > 0 && j > kl;  // beyond a learned step limit
   const bool first = vb.x == 0 && vb.y == 0 && vb.z == 0 && threadIdx.x == 0;
   const double eps = 2.220446049250313e-16;
   switch (c.kind) {
     case CTL_GKB_INIT: {
       if (c.from_state) {
         if (ss == 0) return false;
-        sin = 1.0 / st->beta[0];
+        sin = 1.0 / rec;
         return true;
       }
-      const double bt = sqrt(block_sum_partials(c.part_in, c.npart_in, sh));
+      const double bt = sqrt(block_sum_all(ps, sh));
       const bool bad = !(bt > 0.0) || !isfinite(bt);
       if (first) {
         st->beta[0] = bt;
@@ -225,28 +396,28 @@ __device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin
       return true;
     }
     case CTL_GKB_FWD: {
-      if (ss >= 0 || beyond_limit(st, c.j)) return false;  // stopped at an earlier step
-      b = -st->alpha[c.j - 1];
+      if (ss >= 0 || beyond) return false;  // stopped at an earlier step
+      b = -rec;
       return true;
     }
     case CTL_GKB_ADJ: {
-      if ((ss >= 0 && ss < c.j) || beyond_limit(st, c.j)) return false;
+      if ((ss >= 0 && ss < j) || beyond) return false;
       if (c.from_state) {
-        if (ss == c.j) return false;
-        const double bt = st->beta[c.j];
-        sin = 1.0 / bt;
-        b = -bt;
+        if (ss == j) return false;
+        sin = 1.0 / rec;
+        b = -rec;
         return true;
       }
-      const double bt = sqrt(block_sum_partials(c.part_in, c.npart_in, sh));
-      const double scale = fmax(gkb_scale(st, c.j, c.j, sh), bt);
+      block_sum_max_all(ps, pm, sh);
+      const double bt = sqrt(ps);
+      const double scale = fmax(pm, bt);
       const bool fin = isfinite(bt);
       const bool brk = !fin || bt <= kBreakFactor * eps * scale;
       if (first) {
-        st->beta[c.j] = bt;
-        st->steps = c.j;
+        st->beta[j] = bt;
+        st->steps = j;
         if (brk) {
-          st->stop_step = c.j;
+          st->stop_step = j;
           st->stop_kind = STOP_BETA;
           st->status = fin ? DCTK_BREAKDOWN : DCTK_ENONFINITE;
         }
@@ -257,26 +428,25 @@ __device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin
       return true;
     }
     case CTL_ARN_FWD: {
-      if (((volatile KState*)st)->halt) return false;
-      if (ss >= 0 && ss < c.j) return false;
-      if (c.j == 1) return true;  // V_1 was normalised by the cycle start
-      const int r = c.j - 1, col = c.j - 2;   // h_{j, j-1} (1-based) at H[j-1][j-2]
+      if (halt) return false;
+      if (ss >= 0 && ss < j) return false;
+      if (j == 1) return true;  // V_1 was normalised by the cycle start
+      const int r = j - 1, col = j - 2;   // h_{j, j-1} (1-based) at H[j-1][j-2]
       if (c.from_state) {
-        if (ss == c.j - 1) return false;
-        sin = 1.0 / st->H[r * kMaxK + col];
+        if (ss == j - 1) return false;
+        sin = 1.0 / rec;
         return true;
       }
-      const double h = sqrt(block_sum_partials(c.part_in, c.npart_in, sh));
-      double m = 0.0;
-      for (int i = threadIdx.x; i < r; i += blockDim.x) m = fmax(m, fabs(st->H[i * kMaxK + col]));
-      const double scale = fmax(block_max_all(m, sh), h);
+      block_sum_max_all(ps, pm, sh);
+      const double h = sqrt(ps);
+      const double scale = fmax(pm, h);
       const bool fin = isfinite(h);
       const bool brk = !fin || h <= kBreakFactor * eps * scale;
       if (first) {
         st->H[r * kMaxK + col] = h;
-        st->steps = c.j - 1;
+        st->steps = j - 1;
         if (brk) {
-          st->stop_step = c.j - 1;
+          st->stop_step = j - 1;
           st->stop_kind = STOP_BETA;
           st->status = fin ? DCTK_BREAKDOWN : DCTK_ENONFINITE;
         }
@@ -290,6 +460,11 @@ __device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin
   }
 }
 
+__device__ inline bool ctl_begin(const Ctl& c, double& a, double& b, double& sin, double* sh, const VBlock& vb) {
+  const CtlLoad L = ctl_load(c);
+  return ctl_eval(c, L, a, b, sin, sh, vb);
+}
+
 // Gate of the plain kernels (GEMMs, reorthogonalisation passes) of a step:
 // mode 0 runs while the process has not stopped before step j; mode 1 also
 // requires that it did not stop at step j (its input exists).
@@ -301,10 +476,9 @@ struct Gate {
 
 __device__ inline bool gate_open(const Gate& g) {
   if (g.st == nullptr) return true;
-  const volatile KState* st = g.st;
-  if (st->halt) return false;
-  if (st->k_limit > 0 && g.j > st->k_limit) return false;
-  const int ss = st->stop_step;
+  const int halt = ld_state(&g.st->halt), kl = ld_state(&g.st->k_limit), ss = ld_state(&g.st->stop_step);
+  if (halt) return false;
+  if (kl > 0 && g.j > kl) return false;
   if (ss < 0) return true;
   return g.mode == 0 ? ss >= g.j : ss > g.j;
 }
@@ -355,8 +529,8 @@ struct dctk_krylov_s {
   void* W;                 // LSQR search direction
   void* T;                 // scratch vectors (2 slots)
   void* R;                 // GMRES residual
-  double* partA;           // kRedBlocks partials (norms feeding the next product)
-  double* partB;           // kRedBlocks partials
+  double* partA;           // kNormParts partials (norms feeding the next product)
+  double* partB;           // kNormParts partials
   double* partM;           // kRedBlocks * kRedVals partials of multi-dots
   dctk::KState* st;        // device state
 };
@@ -393,7 +567,8 @@ int hip_fail(dctk_ctx ctx, hipError_t e);
 // bytes of its argument struct.  `phase` is advanced by the planner between the
 // steps of the schedule; `sub` numbers the records within a phase.
 struct LaunchRec {
-  const void* fn;
+  const void* fn;        // the kernel's plain variant
+  const void* fn_group;  // its grouped variant
   dim3 grid;
   unsigned threads;
   unsigned shmem;
@@ -413,12 +588,15 @@ inline void rec_phase(dctk_ctx ctx) {
   }
 }
 
-// Launch (or record) kernel fn(A a, const A* grp, const int4* bmap) as a plain
-// launch with grid `grid`.  The grid is stored in a.gx/gy/gz first.  Start and
-// stop events (may be null) are recorded by the dispatch itself.
+// Launch (or record) a kernel fn(A a, const A* grp, const int4* bmap) as a plain
+// launch with grid `grid`; fn_group is the same kernel's grouped variant, which a
+// batch plan uses when it merges this launch with other instances'.  The grid
+// is stored in a.gx/gy/gz first.  Start and stop events (may be null) are
+// recorded by the dispatch itself.
 template <typename A>
-hipError_t launch_kernel(dctk_ctx ctx, hipStream_t s, void (*fn)(A, const A*, const int4*), dim3 grid,
-                         unsigned threads, unsigned shmem, A a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+hipError_t launch_kernel(dctk_ctx ctx, hipStream_t s, void (*fn)(A, const A*, const int4*),
+                         void (*fn_group)(A, const A*, const int4*), dim3 grid, unsigned threads, unsigned shmem, A a,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   a.gx = (int)grid.x;
   a.gy = (int)grid.y;
   a.gz = (int)grid.z;
@@ -426,6 +604,7 @@ hipError_t launch_kernel(dctk_ctx ctx, hipStream_t s, void (*fn)(A, const A*, co
     Recorder* r = (Recorder*)ctx->rec;
     LaunchRec lr;
     lr.fn = (const void*)fn;
+    lr.fn_group = (const void*)fn_group;
     lr.grid = grid;
     lr.threads = threads;
     lr.shmem = shmem;

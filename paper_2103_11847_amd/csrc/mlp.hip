@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(int B, const float* X, cons
 // dout = w (out - T) / B and per-block partials of (1/2B) sum w (out - T)^2
 __global__ __launch_bounds__(256) void k_mlp_loss(int B, const float* out, const float* T, float w0, float w1,
                                                   float* dout, double* loss_part) {
-  __shared__ double sh[256 / 64 + 2];
+  __shared__ double sh[kShCtl];
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   double l = 0.0;
   if (b < B) {
@@ -199,8 +199,7 @@ __global__ void k_mlp_round(const float* P, bf16_t* Pb) {
 
 // the 16 features of a GKB workspace state (after >= 8 steps)
 __device__ inline bool state_features(const KState* st, float* f) {
-  const volatile KState* vst = st;
-  if (vst->steps < kFeatSteps) return false;
+  if (ld_state(&st->steps) < kFeatSteps) return false;
   const double b1 = st->beta[0];
   for (int j = 0; j < kFeatSteps; ++j) {
     f[j] = (float)log(st->alpha[j] / st->beta[j]);
@@ -251,15 +250,13 @@ struct StopArgs {
   float mu, sigma, kscale, koffset;
 };
 
-__global__ __launch_bounds__(64) void k_mlp_stop(StopArgs a_, const StopArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const StopArgs a = pick_args(a_, grp, bmap, vb);
+__device__ __forceinline__ void k_mlp_stop_body(const StopArgs& a, const VBlock vb, const bool grouped) {
   __shared__ float sW[kNParams];
   __shared__ float f[kNIn];
   __shared__ int ok;
   stage_params(a.Pb, sW);
   KState* st = a.st;
-  if (threadIdx.x == 0) ok = (((volatile KState*)st)->stop_step < 0 && state_features(st, f)) ? 1 : 0;
+  if (threadIdx.x == 0) ok = (ld_state(&st->stop_step) < 0 && state_features(st, f)) ? 1 : 0;
   __syncthreads();
   if (threadIdx.x != 0) return;
   if (!ok) {
@@ -275,6 +272,17 @@ __global__ __launch_bounds__(64) void k_mlp_stop(StopArgs a_, const StopArgs* gr
   const bool valid = isfinite(lam) && lam > 0.0f && isfinite(kf);
   st->k_limit = valid ? (int)kf : 0;
   st->pred_lambda = valid ? (double)lam : 0.0;
+}
+
+template <bool GROUPED>
+__global__ __launch_bounds__(64) void k_mlp_stop(StopArgs a_, const StopArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_mlp_stop_body(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const StopArgs g = group_args(grp, bmap, vb);
+    k_mlp_stop_body(g, vb, true);
+  }
 }
 
 }  // namespace dctk
@@ -361,7 +369,7 @@ hipError_t launch_mlp_stop(dctk_ctx ctx, dctk_mlp m, KState* st, int kmin, int k
   a.sigma = (float)m->sigma;
   a.kscale = (float)m->kscale;
   a.koffset = (float)m->koffset;
-  return launch_kernel(ctx, ctx->stream, k_mlp_stop, dim3(1), 64, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_mlp_stop<false>, k_mlp_stop<true>, dim3(1), 64, 0, a);
 }
 
 hipError_t mlp_predict(dctk_ctx ctx, dctk_mlp m, const KState* st, int kmin, int kmax, float* host_pred) {

@@ -3,16 +3,17 @@
 //   * SVD of the (k+1) x k projected matrix (Hessenberg H~_k or lower
 //     bidiagonal C~_k) by one-sided (Hestenes) Jacobi: columns are rotated
 //     pairwise until orthogonal, in a round-robin order; each pair of a round
-//     belongs to a 16-lane row of a wave (rows of the matrix spread over the
-//     lanes, dot products reduced with DPP row permutes), so a round of up to
-//     64 pairs is one pass;
+//     belongs to an 8-lane group of a wave (rows of the matrix spread over the
+//     lanes, dot products reduced with DPP permutes), so a round of up to 32
+//     pairs is one pass of at most four waves, one per SIMD;
 //   * the component of beta e_1 outside range(H), from the null vector z of
 //     H^T (H^T z = 0 is a forward recurrence for a Hessenberg matrix), so it
 //     does not suffer the cancellation of beta^2 - sum g_i^2;
 //   * lambda by GCV: 400-point log grid on [1e-8 sigma_1, sigma_1] (one
-//     point per thread), first minimum, golden-section refinement on
-//     log10(lambda) in the neighbouring cells (bracket < 1e-10 or 200 steps),
-//     keeping the better of the refined midpoint and the grid point;
+//     point per thread), first minimum, then the neighbouring cells are
+//     subdivided in passes of 64 points (one 16-lane row each) around the
+//     first smallest value until the bracket on log10(lambda) is below 1e-10,
+//     keeping the better of the refined point and the grid point;
 //   * y_lambda = V diag(sigma / (sigma^2 + lambda^2)) g  (eq. leastsq / normeq2).
 // The GCV function is that of the rectangular projected problem (mode 0) or
 // the printed eq. (gcv2) (mode 1).
@@ -26,40 +27,38 @@ namespace dctk {
 constexpr int kPT = 1024;            // threads
 constexpr int kPW = kPT / 64;        // waves
 constexpr int kGrid = 400;
-constexpr int kLdG = kMaxK + 2;      // rows <= 65
-static_assert(kPW * 4 >= (kMaxK + 1) / 2, "one Jacobi round must fit in one pass (4 pairs per wave)");
+// Column strides of G (rows <= 65) and V: 72 doubles = 144 dwords, 16 more than a
+// multiple of 64 banks, so that the 8-lane groups of a wave, which read
+// 8 consecutive rows of mostly consecutive columns, fall in distinct bank windows.
+constexpr int kLdG = 72;
+constexpr int kLdV = 72;
+constexpr int kJR = (kMaxK + 1 + 7) / 8;   // rows of G per lane of an 8-lane group
+constexpr int kJV = (kMaxK + 7) / 8;       // rows of V per lane
+constexpr int kRef = kPW * 4;              // GCV refinement points per pass (16-lane rows)
+static_assert(kPW * 8 >= (kMaxK + 1) / 2, "one Jacobi round must fit in one pass (8 pairs per wave)");
+static_assert(kRef == 64, "the refinement pass reduces one value per lane of a wave");
+static_assert(kMaxK % 8 == 0 && kJV * 8 == kMaxK && kLdV >= kMaxK, "a lane reads rows l, l + 8, ... < kMaxK of V");
+static_assert(kJR * 8 <= kLdG && kLdG >= kMaxK + 1, "a lane reads rows l, l + 8, ... < kLdG of G");
 
-// ---- DPP helpers (64-bit values moved as two 32-bit halves) -------------------
-template <int CTRL>
-__device__ inline double dpp(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-  const long long r = ((long long)(unsigned)lo) | ((long long)hi << 32);
-  return __builtin_bit_cast(double, r);
-}
-
-// Sum over the 16 lanes of a row, returned to every lane of the row (identical
-// bits: each step adds a commuted copy of the same partial sums).
-__device__ inline double row16_sum(double v) {
-  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);  // row_half_mirror
-  v += dpp<0x140>(v);  // row_mirror
+// Sum over the 8 lanes of a half row, returned to every lane of it (identical bits).
+__device__ inline double row8_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
   return v;
 }
 
-__device__ inline double readlane_d(double v, int l) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
-}
-
-// Sum over the wave, uniform result.
-__device__ inline double wave_sum_uniform(double v) {
-  v = row16_sum(v);
-  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+// (value, index) of the first smallest value over the wave, in every lane
+__device__ inline void first_min64(double& v, int& i) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double ov = __shfl_xor(v, m);
+    const int oi = __shfl_xor(i, m);
+    if (ov < v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
 }
 
 // GCV at lambda, serial over the k singular values (one thread)
@@ -100,8 +99,34 @@ __device__ inline double gcv_wave(int mode, double lam, int k, const double* sig
       t2 = 1.0 / d;
     }
   }
-  t1 = wave_sum_uniform(t1);
-  t2 = wave_sum_uniform(t2);
+  t1 = wave_sum(t1);
+  t2 = wave_sum(t2);
+  if (mode == 0) {
+    const double tr = 1.0 + t2;
+    return (gperp2 + t1) / (tr * tr);
+  }
+  return t1 / (t2 * t2);
+}
+
+// GCV at lambda, the 16 lanes of a row over the singular values (result in every lane of the row)
+__device__ inline double gcv_row16(int mode, double lam, int k, const double* sig, const double* g, double gperp2,
+                                   int l16) {
+  const double l2 = lam * lam;
+  double t1 = 0.0, t2 = 0.0;
+  for (int i = l16; i < k; i += 16) {
+    const double s2 = sig[i] * sig[i];
+    if (mode == 0) {
+      const double f = l2 / (s2 + l2);
+      t1 += (f * g[i]) * (f * g[i]);
+      t2 += f;
+    } else {
+      const double d = s2 + l2;
+      t1 += (g[i] / d) * (g[i] / d);
+      t2 += 1.0 / d;
+    }
+  }
+  t1 = row16_sum(t1);
+  t2 = row16_sum(t2);
   if (mode == 0) {
     const double tr = 1.0 + t2;
     return (gperp2 + t1) / (tr * tr);
@@ -121,23 +146,24 @@ struct ProjArgs {
   int cand_from_state;  // 1: the proposed lambda is st->pred_lambda (learned stop)
 };
 
-__global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* group, const int4* bmap) {
-  VBlock vb;
-  const ProjArgs a = pick_args(a_, group, bmap, vb);
+__device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock vb, const bool grouped) {
   KState* st = a.st;
   const int bidiag = a.bidiag, gcv_mode = a.gcv_mode;
   const double lam_fixed = a.lam_fixed, gate = a.gate;
-  const double lam_cand = a.cand_from_state ? ((volatile KState*)st)->pred_lambda : a.lam_cand;
+  const double lam_cand = a.cand_from_state ? ld_state(&st->pred_lambda) : a.lam_cand;
   const int k_use = a.k_use;
-  if (((volatile KState*)st)->halt) return;
+  if (ld_state(&st->halt)) return;
   __shared__ double G[kMaxK * kLdG];      // G[c * kLdG + r]: column c of the matrix
-  __shared__ double Vm[kMaxK * kMaxK];    // Vm[c * kMaxK + r]: right singular vectors
+  __shared__ double Vm[kMaxK * kLdV];     // Vm[c * kLdV + r]: right singular vectors
   __shared__ double sig[kMaxK], ssort[kMaxK], gs[kMaxK], g0s[kMaxK];
   __shared__ int order[kMaxK];
   __shared__ double z[kMaxK + 1];
   __shared__ double gridv[kGrid];
+  __shared__ double refv[kRef];
+  __shared__ double wcoef[kMaxK];
   __shared__ int rot_flag[2];
   __shared__ double s_gperp2, s_lam, s_gcv;
+  __shared__ double s_ra, s_rb, s_rt, s_rf;
   __shared__ int s_ib;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -162,45 +188,67 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
     }
     G[i] = v;
   }
-  for (int i = tid; i < k * kMaxK; i += kPT) Vm[i] = ((i / kMaxK) == (i % kMaxK)) ? 1.0 : 0.0;
+  for (int i = tid; i < k * kLdV; i += kPT) Vm[i] = ((i / kLdV) == (i % kLdV)) ? 1.0 : 0.0;
   if (tid == 0) { rot_flag[0] = 0; rot_flag[1] = 0; }
   __syncthreads();
 
   // component of beta e_1 outside range(H): z with H^T z = 0, z_0 = 1 (wave 0)
   if (wave == 0) {
-    bool zero = false;
-    double zl = (lane == 0) ? 1.0 : 0.0;   // lane l holds z_l (k <= 64: z_64 in z[64])
-    if (lane == 0) z[0] = 1.0;
-    for (int j = 0; j < k; ++j) {
-      const double part = (lane <= j) ? G[j * kLdG + lane] * zl : 0.0;
-      const double sum = wave_sum_uniform(part);
-      const double h = G[j * kLdG + j + 1];
-      if (h == 0.0) { zero = true; break; }
-      double zn = -sum / h;
-      if (fabs(zn) > 1e150) {
-        zl *= 1e-150;
-        zn *= 1e-150;
-        if (lane == 0) {
-          for (int i = 0; i <= j; ++i) z[i] *= 1e-150;
+    if (bidiag) {
+      // lower bidiagonal: alpha_j z_j + beta_{j+1} z_{j+1} = 0, one lane
+      if (lane == 0) {
+        bool zero = false;
+        double z0 = 1.0, zj = 1.0, zz = 1.0;
+        for (int j = 0; j < k; ++j) {
+          const double h = G[j * kLdG + j + 1];
+          if (h == 0.0) { zero = true; break; }
+          double zn = -(G[j * kLdG + j] * zj) / h;
+          if (fabs(zn) > 1e150) {
+            z0 *= 1e-150;
+            zz *= 1e-300;
+            zn *= 1e-150;
+          }
+          zz += zn * zn;
+          zj = zn;
         }
+        s_gperp2 = zero ? 0.0 : (beta * z0) * (beta * z0) / zz;
       }
-      if (lane == j + 1) zl = zn;
-      if (lane == 0) z[j + 1] = zn;
+    } else {
+      bool zero = false;
+      double zl = (lane == 0) ? 1.0 : 0.0;   // lane l holds z_l (k <= 64: z_64 in z[64])
+      if (lane == 0) z[0] = 1.0;
+      for (int j = 0; j < k; ++j) {
+        const double part = (lane <= j) ? G[j * kLdG + lane] * zl : 0.0;
+        const double sum = wave_sum(part);
+        const double h = G[j * kLdG + j + 1];
+        if (h == 0.0) { zero = true; break; }
+        double zn = -sum / h;
+        if (fabs(zn) > 1e150) {
+          zl *= 1e-150;
+          zn *= 1e-150;
+          if (lane == 0) {
+            for (int i = 0; i <= j; ++i) z[i] *= 1e-150;
+          }
+        }
+        if (lane == j + 1) zl = zn;
+        if (lane == 0) z[j + 1] = zn;
+      }
+      double zz = 0.0;
+      if (!zero) {
+        for (int i = lane; i <= k; i += 64) zz += z[i] * z[i];
+      }
+      zz = wave_sum(zz);
+      if (lane == 0) s_gperp2 = zero ? 0.0 : (beta * z[0]) * (beta * z[0]) / zz;
     }
-    double zz = 0.0;
-    if (!zero) {
-      for (int i = lane; i <= k; i += 64) zz += z[i] * z[i];
-    }
-    zz = wave_sum_uniform(zz);
-    if (lane == 0) s_gperp2 = zero ? 0.0 : (beta * z[0]) * (beta * z[0]) / zz;
   }
   __syncthreads();
 
-  // one-sided Jacobi: pair pi of a round belongs to row (lane / 16) of wave pi / 4
+  // One-sided Jacobi.  Pair pi of a round belongs to an 8-lane group (lane / 8)
+  // of wave pi / 8, so at most four waves (one per SIMD) do the work of a round.
   const int cEven = k + (k & 1);
   const int npairs = cEven / 2;
-  const int grp = lane >> 4, l16 = lane & 15;
-  const int pi = wave * 4 + grp;
+  const int grp = lane >> 3, l8 = lane & 7;
+  const int pi = wave * 8 + grp;
   // rotate while |g_p . g_q| > tol |g_p| |g_q|; below a few ulps per row the
   // columns are orthogonal to working precision
   const double tolJ = DBL_EPSILON * (double)rows;
@@ -209,6 +257,11 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
     const int flag = sweep & 1;
     sweeps = sweep + 1;
     for (int rr = 0; rr < cEven - 1; ++rr) {
+      // waves without a pair this round go straight to the barrier
+      if (wave * 8 >= npairs) {
+        __syncthreads();
+        continue;
+      }
       int p = 0, q = 0;
       bool valid = pi < npairs;
       if (valid) {
@@ -219,47 +272,64 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
         q = ia < ib ? ib : ia;
         valid = q < k;  // the dummy column of an odd k
       }
-      // every lane takes part in the row reductions (zeros when idle)
-      double xp[5], xq[5];
+      // Every lane takes part in the group reductions (zeros when idle).  All
+      // loads are issued before the first use, from addresses inside the
+      // arrays: rows past the matrix read the zero rows below it, and the
+      // columns of an idle pair are replaced by zeros after the load.
+      double xp[kJR], xq[kJR], vp[kJV], vq[kJV];
+#pragma unroll
+      for (int u = 0; u < kJR; ++u) {
+        const int r = l8 + 8 * u;
+        xp[u] = G[p * kLdG + r];
+        xq[u] = G[q * kLdG + r];
+      }
+#pragma unroll
+      for (int u = 0; u < kJV; ++u) {
+        vp[u] = Vm[p * kLdV + l8 + 8 * u];
+        vq[u] = Vm[q * kLdV + l8 + 8 * u];
+      }
       double a = 0.0, b = 0.0, c = 0.0;
 #pragma unroll
-      for (int u = 0; u < 5; ++u) {
-        const int r = l16 + 16 * u;
-        const bool in = valid && r < rows;
-        xp[u] = in ? G[p * kLdG + r] : 0.0;
-        xq[u] = in ? G[q * kLdG + r] : 0.0;
-        a += xp[u] * xp[u];
-        b += xq[u] * xq[u];
-        c += xp[u] * xq[u];
+      for (int u = 0; u < kJR; ++u) {
+        const double x = valid ? xp[u] : 0.0, y = valid ? xq[u] : 0.0;
+        a += x * x;
+        b += y * y;
+        c += x * y;
       }
-      a = row16_sum(a);
-      b = row16_sum(b);
-      c = row16_sum(c);
+      a = row8_sum(a);
+      b = row8_sum(b);
+      c = row8_sum(c);
       if (valid && c != 0.0 && c * c > (tolJ * tolJ) * (a * b)) {
-        // tan of the rotation angle, the smaller root of t^2 + 2 zeta t - 1 = 0
-        // with zeta = (b - a) / (2c), written with one square root and one division
+        // The smaller of the two rotations that make g_p . g_q zero, through the
+        // double angle: with h = sqrt((b - a)^2 + 4c^2), cos 2th = |b - a| / h and
+        // sin 2th = sign(b - a) 2c / h; then cos th = sqrt((1 + cos 2th) / 2) and
+        // sin th = sin 2th / (2 cos th), with 1 + cos 2th >= 1 (no cancellation):
+        // two reciprocal square roots, no division.
         const double dba = b - a;
-        const double t = (dba >= 0.0 ? 2.0 * c : -2.0 * c) / (fabs(dba) + sqrt(dba * dba + 4.0 * c * c));
-        const double cs = rsqrt(1.0 + t * t);
-        const double sn = cs * t;
+        const double ih = rsqrt(dba * dba + 4.0 * c * c);
+        const double c2 = fabs(dba) * ih;
+        const double s2 = (dba >= 0.0 ? 2.0 * c : -2.0 * c) * ih;
+        const double w = 0.5 + 0.5 * c2;
+        const double iw = rsqrt(w);
+        const double cs = w * iw;
+        const double sn = 0.5 * s2 * iw;
 #pragma unroll
-        for (int u = 0; u < 5; ++u) {
-          const int r = l16 + 16 * u;
+        for (int u = 0; u < kJR; ++u) {
+          const int r = l8 + 8 * u;
           if (r < rows) {
             G[p * kLdG + r] = cs * xp[u] - sn * xq[u];
             G[q * kLdG + r] = sn * xp[u] + cs * xq[u];
           }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int r = l16 + 16 * u;
+        for (int u = 0; u < kJV; ++u) {
+          const int r = l8 + 8 * u;
           if (r < k) {
-            const double vp = Vm[p * kMaxK + r], vq = Vm[q * kMaxK + r];
-            Vm[p * kMaxK + r] = cs * vp - sn * vq;
-            Vm[q * kMaxK + r] = sn * vp + cs * vq;
+            Vm[p * kLdV + r] = cs * vp[u] - sn * vq[u];
+            Vm[q * kLdV + r] = sn * vp[u] + cs * vq[u];
           }
         }
-        if (l16 == 0) rot_flag[flag] = 1;
+        if (l8 == 0) rot_flag[flag] = 1;
       }
       __syncthreads();
     }
@@ -304,58 +374,67 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
   } else {
     const double t0 = log10(ssort[0]) - 8.0;
     const double dt = 8.0 / (double)(kGrid - 1);
-    if (tid < kGrid) gridv[tid] = gcv_serial(gcv_mode, pow(10.0, t0 + (double)tid * dt), k, ssort, gs, s_gperp2);
+    if (tid < kGrid) gridv[tid] = gcv_serial(gcv_mode, exp10(t0 + (double)tid * dt), k, ssort, gs, s_gperp2);
     __syncthreads();
     if (wave == 0) {
-      // first index of the minimum: per-lane scan, then lanes in order
-      int bi = -1;
-      double bv = 0.0;
-      for (int i = lane; i < kGrid; i += 64)
-        if (bi < 0 || gridv[i] < bv) { bi = i; bv = gridv[i]; }
-      if (lane == 0) s_ib = 0;
-      for (int l = 0; l < 64; ++l) {
-        const int li = __builtin_amdgcn_readlane(bi, l);
-        const double lv = readlane_d(bv, l);
-        if (lane == 0 && li >= 0) {
-          const int cur = s_ib;
-          if (lv < gridv[cur] || (lv == gridv[cur] && li < cur)) s_ib = li;
-        }
+      // first index of the minimum (NaN counts as +inf)
+      int bi = kGrid;
+      double bv = __builtin_inf();
+      for (int i = lane; i < kGrid; i += 64) {
+        const double v = gridv[i] == gridv[i] ? gridv[i] : __builtin_inf();
+        if (bi == kGrid || v < bv) { bi = i; bv = v; }
       }
-      const int ib = __builtin_amdgcn_readfirstlane(s_ib);
-      double a = t0 + (double)(ib > 0 ? ib - 1 : 0) * dt;
-      double b = t0 + (double)(ib < kGrid - 1 ? ib + 1 : kGrid - 1) * dt;
-      const double invphi = (sqrt(5.0) - 1.0) / 2.0;
-      double c = b - invphi * (b - a);
-      double d = a + invphi * (b - a);
-      double fc = gcv_wave(gcv_mode, pow(10.0, c), k, ssort, gs, s_gperp2, lane);
-      double fd = gcv_wave(gcv_mode, pow(10.0, d), k, ssort, gs, s_gperp2, lane);
-      int steps = 0;
-      while ((b - a) > 1e-10 && steps < 200) {
-        if (fc <= fd) {
-          b = d; d = c; fd = fc;
-          c = b - invphi * (b - a);
-          fc = gcv_wave(gcv_mode, pow(10.0, c), k, ssort, gs, s_gperp2, lane);
-        } else {
-          a = c; c = d; fc = fd;
-          d = a + invphi * (b - a);
-          fd = gcv_wave(gcv_mode, pow(10.0, d), k, ssort, gs, s_gperp2, lane);
-        }
-        ++steps;
-      }
-      const double tm = 0.5 * (a + b);
-      const double fm = gcv_wave(gcv_mode, pow(10.0, tm), k, ssort, gs, s_gperp2, lane);
+      first_min64(bv, bi);
+      const int ib = bi < kGrid ? bi : 0;
       if (lane == 0) {
-        if (fm <= gridv[ib]) { s_lam = pow(10.0, tm); s_gcv = fm; }
-        else { s_lam = pow(10.0, t0 + (double)ib * dt); s_gcv = gridv[ib]; }
+        s_ib = ib;
+        s_ra = t0 + (double)(ib > 0 ? ib - 1 : 0) * dt;
+        s_rb = t0 + (double)(ib < kGrid - 1 ? ib + 1 : kGrid - 1) * dt;
+        s_rt = __builtin_nan("");
+        s_rf = __builtin_inf();
       }
-      // a proposed lambda is kept when its GCV value is within the gate of the minimum
-      if (lam_cand > 0.0) {
-        const double fcand = gcv_wave(gcv_mode, lam_cand, k, ssort, gs, s_gperp2, lane);
+    }
+    __syncthreads();
+    // Refine on t = log10(lambda) inside the grid cells next to the minimum:
+    // each pass evaluates kRef points evenly inside [a, b] (one 16-lane row
+    // of the workgroup per point) and keeps the two cells next to the first
+    // smallest value, until the bracket is narrower than 1e-10.
+    const int row = wave * 4 + (lane >> 4), l16 = lane & 15;
+    for (int pass = 0; pass < 40; ++pass) {
+      const double ra = s_ra, rb = s_rb;
+      if (!((rb - ra) > 1e-10)) break;
+      const double h = (rb - ra) / (double)(kRef + 1);
+      const double tq = ra + (double)(row + 1) * h;
+      const double f = gcv_row16(gcv_mode, exp10(tq), k, ssort, gs, s_gperp2, l16);
+      if (l16 == 0) refv[row] = f;
+      __syncthreads();
+      if (wave == 0) {
+        const double v = refv[lane] == refv[lane] ? refv[lane] : __builtin_inf();
+        int mi = lane;
+        double mv = v;
+        first_min64(mv, mi);
         if (lane == 0) {
-          const bool keep = fcand <= gate * s_gcv;
-          st->gate_ok = keep ? 1.0 : 0.0;
-          if (keep) { s_lam = lam_cand; s_gcv = fcand; }
+          s_ra = ra + (double)mi * h;          // point mi - 1 (or a)
+          s_rb = ra + (double)(mi + 2) * h;    // point mi + 1 (or b)
+          s_rt = ra + (double)(mi + 1) * h;
+          s_rf = mv;
         }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const int ib = s_ib;
+      if (s_rf <= gridv[ib]) { s_lam = exp10(s_rt); s_gcv = s_rf; }
+      else { s_lam = exp10(t0 + (double)ib * dt); s_gcv = gridv[ib]; }
+    }
+    __syncthreads();
+    // a proposed lambda is kept when its GCV value is within the gate of the minimum
+    if (lam_cand > 0.0 && wave == 0) {
+      const double fcand = gcv_wave(gcv_mode, lam_cand, k, ssort, gs, s_gperp2, lane);
+      if (lane == 0) {
+        const bool keep = fcand <= gate * s_gcv;
+        st->gate_ok = keep ? 1.0 : 0.0;
+        if (keep) { s_lam = lam_cand; s_gcv = fcand; }
       }
     }
   }
@@ -364,17 +443,30 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
   // y = sum_i v_i sigma_i g_i / (sigma_i^2 + lambda^2)
   const double lam = s_lam;
   if (tid < k) {
+    const double dd = ssort[tid] * ssort[tid] + lam * lam;
+    wcoef[tid] = dd > 0.0 ? g0s[tid] / dd : 0.0;
+  }
+  __syncthreads();
+  if (tid < k) {
     double acc = 0.0;
-    for (int i = 0; i < k; ++i) {
-      const double dd = ssort[i] * ssort[i] + lam * lam;
-      if (dd > 0.0) acc += Vm[order[i] * kMaxK + tid] * (g0s[i] / dd);
-    }
+    for (int i = 0; i < k; ++i) acc += Vm[order[i] * kLdV + tid] * wcoef[i];
     st->y[tid] = acc;
   }
   if (tid == 0) {
     st->lambda = lam;
     st->gcv = s_gcv;
     st->sweeps = (double)sweeps;
+  }
+}
+
+template <bool GROUPED>
+__global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_projected_body(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const ProjArgs g = group_args(grp, bmap, vb);
+    k_projected_body(g, vb, true);
   }
 }
 
@@ -389,7 +481,7 @@ hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, 
   a.lam_fixed = lambda;
   a.lam_cand = lam_cand;
   a.gate = gate;
-  return launch_kernel(ctx, ctx->stream, k_projected, dim3(1), kPT, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_projected<false>, k_projected<true>, dim3(1), kPT, 0, a);
 }
 
 }  // namespace dctk

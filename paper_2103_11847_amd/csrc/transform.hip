@@ -119,10 +119,8 @@ struct TubeArgs {
 };
 
 template <typename TIN, typename TOUT, typename TC, int KB, bool VEC, bool SCALE, bool EPI>
-__global__ __launch_bounds__(kThreads) void tube_kernel(TubeArgs ta_, const TubeArgs* grp, const int4* bmap) {
-  __shared__ double sh[kThreads / 64 + 2];
-  VBlock vb;
-  const TubeArgs ta = pick_args(ta_, grp, bmap, vb);
+__device__ __forceinline__ void tube_kernel_body(const TubeArgs& ta, const VBlock vb, const bool grouped) {
+  __shared__ double sh[kShCtl];
   const int p = ta.p;
   const int64_t count = ta.count;
   const TIN* __restrict__ in = (const TIN*)ta.in;
@@ -205,6 +203,17 @@ __global__ __launch_bounds__(kThreads) void tube_kernel(TubeArgs ta_, const Tube
   }
 }
 
+template <typename TIN, typename TOUT, typename TC, int KB, bool VEC, bool SCALE, bool EPI, bool GROUPED>
+__global__ __launch_bounds__(kThreads) void tube_kernel(TubeArgs ta_, const TubeArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    tube_kernel_body<TIN, TOUT, TC, KB, VEC, SCALE, EPI>(ta_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const TubeArgs g = group_args(grp, bmap, vb);
+    tube_kernel_body<TIN, TOUT, TC, KB, VEC, SCALE, EPI>(g, vb, true);
+  }
+}
+
 // Long tubes (p >= 16): the transform out = G x in is a (p x p)(p x count)
 // contraction, so it runs on the matrix cores.  A workgroup takes 64 positions
 // and all p outputs: G (p x p, FP32, rows padded to 16) and the 64-position
@@ -214,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void tube_kernel(TubeArgs ta_, const Tube
 // 16x16x4 FP32 MFMAs; the epilogue applies a, b, src and writes per-block
 // partial sums of out^2.
 template <typename TOUT, int PM, bool SCALE, bool EPI>
-__global__ __launch_bounds__(256) void tube_mfma_kernel(TubeArgs ta_, const TubeArgs* grp, const int4* bmap) {
+__device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const VBlock vb, const bool grouped) {
   typedef Mfma<float> MF;
   constexpr int NB = 64;            // positions per workgroup
   constexpr int LDG = PM + 4;       // G as [k][t], t contiguous (+16 bytes)
@@ -222,9 +231,7 @@ __global__ __launch_bounds__(256) void tube_mfma_kernel(TubeArgs ta_, const Tube
   constexpr int FR = PM / 16;       // row bands
   __shared__ __attribute__((aligned(16))) float sG[PM * LDG];
   __shared__ __attribute__((aligned(16))) float sX[PM * LDX];
-  __shared__ double sh[256 / 64 + 2];
-  VBlock vb;
-  const TubeArgs ta = pick_args(ta_, grp, bmap, vb);
+  __shared__ double sh[kShCtl];
   double a_d, b_d, s_d;
   if (!ctl_begin(ta.ctl, a_d, b_d, s_d, sh, vb)) return;
   if (!SCALE) s_d = 1.0;
@@ -304,6 +311,17 @@ __global__ __launch_bounds__(256) void tube_mfma_kernel(TubeArgs ta_, const Tube
   }
 }
 
+template <typename TOUT, int PM, bool SCALE, bool EPI, bool GROUPED>
+__global__ __launch_bounds__(256) void tube_mfma_kernel(TubeArgs ta_, const TubeArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    tube_mfma_kernel_body<TOUT, PM, SCALE, EPI>(ta_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const TubeArgs g = group_args(grp, bmap, vb);
+    tube_mfma_kernel_body<TOUT, PM, SCALE, EPI>(g, vb, true);
+  }
+}
+
 template <typename TOUT>
 static hipError_t launch_tube_mfma(dctk_ctx ctx, hipStream_t s, int64_t p, int64_t count, const void* in, void* out,
                                    const float* G, const void* src, void* xnorm, const Ctl& ctl, bool scale,
@@ -323,10 +341,10 @@ static hipError_t launch_tube_mfma(dctk_ctx ctx, hipStream_t s, int64_t p, int64
   const dim3 grid((unsigned)blocks);
 #define DCTK_TM(PM_) \
   do { \
-    if (scale && epi) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, true, true>, grid, 256, 0, ta); \
-    if (scale) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, true, false>, grid, 256, 0, ta); \
-    if (epi) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, false, true>, grid, 256, 0, ta); \
-    return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, false, false>, grid, 256, 0, ta); \
+    if (scale && epi) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, true, true, false>, tube_mfma_kernel<TOUT, PM_, true, true, true>, grid, 256, 0, ta); \
+    if (scale) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, true, false, false>, tube_mfma_kernel<TOUT, PM_, true, false, true>, grid, 256, 0, ta); \
+    if (epi) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, false, true, false>, tube_mfma_kernel<TOUT, PM_, false, true, true>, grid, 256, 0, ta); \
+    return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, false, false, false>, tube_mfma_kernel<TOUT, PM_, false, false, true>, grid, 256, 0, ta); \
   } while (0)
   if (p <= 16) DCTK_TM(16);
   if (p <= 32) DCTK_TM(32);
@@ -358,7 +376,7 @@ static hipError_t launch_tube_t(dctk_ctx ctx, hipStream_t s, int64_t p, int64_t 
   ta.ctl = ctl;
   const dim3 grid((unsigned)blocks);
 #define DCTK_TUBE_LAUNCH(KB, V, S, E) \
-  return launch_kernel(ctx, s, tube_kernel<TIN, TOUT, TC, KB, V, S, E>, grid, kThreads, (unsigned)shmem, ta)
+  return launch_kernel(ctx, s, tube_kernel<TIN, TOUT, TC, KB, V, S, E, false>, tube_kernel<TIN, TOUT, TC, KB, V, S, E, true>, grid, kThreads, (unsigned)shmem, ta)
 #define DCTK_TUBE_SE(KB, V)                                  \
   do {                                                       \
     if (scale && epi) DCTK_TUBE_LAUNCH(KB, V, true, true);    \

@@ -123,15 +123,13 @@ struct ResetArgs {
 
 // ---- reductions ----------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sumsq(SumsqArgs a_, const SumsqArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const SumsqArgs a = pick_args(a_, grp, bmap, vb);
+__device__ __forceinline__ void k_sumsq_body(const SumsqArgs& a, const VBlock vb, const bool grouped) {
   if (!gate_open(a.g)) return;
   const int64_t n = a.n;
   const T* x = (const T*)a.x;
   const T* z = (const T*)a.z;
   const bool vec = a.vec;
-  __shared__ double sh[kThreads / 64 + 2];
+  __shared__ double sh[kShCtl];
   double acc = 0.0;
   DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double xv[4];
@@ -148,12 +146,23 @@ __global__ __launch_bounds__(kThreads) void k_sumsq(SumsqArgs a_, const SumsqArg
   if (threadIdx.x == 0) a.part[vb.x] = t;
 }
 
+template <typename T, bool GROUPED>
+__global__ __launch_bounds__(kThreads) void k_sumsq(SumsqArgs a_, const SumsqArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_sumsq_body<T>(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const SumsqArgs g = group_args(grp, bmap, vb);
+    k_sumsq_body<T>(g, vb, true);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_axpy_sumsq(int64_t n, T* out, const T* x, const T* y,
                                                          const double* cptr, double csign, double* part, bool vec,
                                                          Gate g) {
   if (!gate_open(g)) return;
-  __shared__ double sh[kThreads / 64 + 2];
+  __shared__ double sh[kShCtl];
   const double c = csign * cptr[0];
   double acc = 0.0;
   DCTK_GRID_LOOP(e, n) {
@@ -172,16 +181,14 @@ __global__ __launch_bounds__(kThreads) void k_axpy_sumsq(int64_t n, T* out, cons
 
 // partials of <basis_i, w> for i < nb: part[i * gridDim.x + block]
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_multidot(GramArgs a_, const GramArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const GramArgs a = pick_args(a_, grp, bmap, vb);
+__device__ __forceinline__ void k_multidot_body(const GramArgs& a, const VBlock vb, const bool grouped) {
   if (!gate_open(a.g)) return;
   const int64_t n = a.n, bstride = a.bstride;
   const T* basis = (const T*)a.basis;
   const T* w = (const T*)a.w;
   const int nb = a.nb;
   const bool vec = a.vec;
-  __shared__ double sh[kThreads / 64 + 2];
+  __shared__ double sh[kShCtl];
   for (int i0 = 0; i0 < nb; i0 += 8) {
     double acc[8];
     for (int u = 0; u < 8; ++u) acc[u] = 0.0;
@@ -201,10 +208,19 @@ __global__ __launch_bounds__(kThreads) void k_multidot(GramArgs a_, const GramAr
   }
 }
 
+template <typename T, bool GROUPED>
+__global__ __launch_bounds__(kThreads) void k_multidot(GramArgs a_, const GramArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_multidot_body<T>(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const GramArgs g = group_args(grp, bmap, vb);
+    k_multidot_body<T>(g, vb, true);
+  }
+}
+
 // one block: coef[i] = sum_b part[i * nblocks + b]; dst[i * dst_stride] += coef[i]
-__global__ __launch_bounds__(kThreads) void k_coef_finalize(GramArgs a_, const GramArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const GramArgs a = pick_args(a_, grp, bmap, vb);
+__device__ __forceinline__ void k_coef_finalize_body(const GramArgs& a, const VBlock vb, const bool grouped) {
   if (!gate_open(a.g)) return;
   const double* part = a.part;
   const int nblocks = a.nblocks, nb = a.nb, dst_stride = a.dst_stride;
@@ -222,11 +238,20 @@ __global__ __launch_bounds__(kThreads) void k_coef_finalize(GramArgs a_, const G
   }
 }
 
+template <bool GROUPED>
+__global__ __launch_bounds__(kThreads) void k_coef_finalize(GramArgs a_, const GramArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_coef_finalize_body(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const GramArgs g = group_args(grp, bmap, vb);
+    k_coef_finalize_body(g, vb, true);
+  }
+}
+
 // w -= sum_i coef[i] basis_i
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_subtract(GramArgs a_, const GramArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const GramArgs a = pick_args(a_, grp, bmap, vb);
+__device__ __forceinline__ void k_subtract_body(const GramArgs& a, const VBlock vb, const bool grouped) {
   if (!gate_open(a.g)) return;
   const int64_t n = a.n, bstride = a.bstride;
   T* w = (T*)a.w;
@@ -248,11 +273,20 @@ __global__ __launch_bounds__(kThreads) void k_subtract(GramArgs a_, const GramAr
   }
 }
 
+template <typename T, bool GROUPED>
+__global__ __launch_bounds__(kThreads) void k_subtract(GramArgs a_, const GramArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_subtract_body<T>(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const GramArgs g = group_args(grp, bmap, vb);
+    k_subtract_body<T>(g, vb, true);
+  }
+}
+
 // out = x0 + sum_{i < cnt} y[i] basis_i
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a_, const CombineArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const CombineArgs a = pick_args(a_, grp, bmap, vb);
+__device__ __forceinline__ void k_combine_body(const CombineArgs& a, const VBlock vb, const bool grouped) {
   if (!gate_open(a.g)) return;
   const int64_t n = a.n, bstride = a.bstride;
   T* out = (T*)a.out;
@@ -279,13 +313,22 @@ __global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a_, const Comb
   }
 }
 
+template <typename T, bool GROUPED>
+__global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a_, const CombineArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_combine_body<T>(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const CombineArgs g = group_args(grp, bmap, vb);
+    k_combine_body<T>(g, vb, true);
+  }
+}
+
 // ---- Golub-Kahan / LSQR ----------------------------------------------------------
 // Algorithm 6 step 2 after M*(U_1): alpha_1 from the partials; V_1 = V~/alpha_1
 // in place; W_1 = V_1; X_0 = 0.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gkb_start(GkbArgs a_, const GkbArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const GkbArgs a = pick_args(a_, grp, bmap, vb);
+__device__ __forceinline__ void k_gkb_start_body(const GkbArgs& a, const VBlock vb, const bool grouped) {
   const int64_t n = a.n;
   T* X = (T*)a.X;
   T* W = (T*)a.W;
@@ -294,19 +337,22 @@ __global__ __launch_bounds__(kThreads) void k_gkb_start(GkbArgs a_, const GkbArg
   const int npart = a.npart;
   KState* st = a.st;
   const bool vec = a.vec;
-  __shared__ double sh[kThreads / 64 + 2];
-  const bool ok = ((volatile KState*)st)->stop_step < 0;
+  __shared__ double sh[kShCtl];
+  // the partials and beta_1 are loaded before the stop flag: one memory latency
+  const double ps = part_local(part, npart);
+  const double b1 = st->beta[0];
+  const bool ok = ld_state(&st->stop_step) < 0;
   bool brk = true;
   double alpha = 0.0;
   if (ok) {
-    alpha = sqrt(block_sum_partials(part, npart, sh));
-    const double scale = fmax(st->beta[0], alpha);
+    alpha = sqrt(block_sum_all(ps, sh));
+    const double scale = fmax(b1, alpha);
     const bool fin = isfinite(alpha);
     brk = !fin || alpha <= kBreakFactor * DBL_EPSILON * scale;
     if (first_thread(vb)) {
       st->alpha[0] = alpha;
       st->rhobar[0] = alpha;
-      st->phibar[0] = st->beta[0];
+      st->phibar[0] = b1;
       if (brk) {
         st->stop_step = 0;
         st->stop_kind = STOP_ALPHA;
@@ -330,14 +376,23 @@ __global__ __launch_bounds__(kThreads) void k_gkb_start(GkbArgs a_, const GkbArg
   }
 }
 
+template <typename T, bool GROUPED>
+__global__ __launch_bounds__(kThreads) void k_gkb_start(GkbArgs a_, const GkbArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_gkb_start_body<T>(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const GkbArgs g = group_args(grp, bmap, vb);
+    k_gkb_start_body<T>(g, vb, true);
+  }
+}
+
 // Algorithm 4 (e)-(f) and Algorithm 6 (c)-(g) for step j: alpha_{j+1} from the
 // partials of V~ (unless beta_{j+1} broke down), the plane rotation, then
 // V_{j+1} = V~/alpha_{j+1} in place, X_j = X_{j-1} + (phi_j/rho_j) W_j,
 // W_{j+1} = V_{j+1} - (theta_{j+1}/rho_j) W_j.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gkb_update(GkbArgs a_, const GkbArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const GkbArgs a = pick_args(a_, grp, bmap, vb);
+__device__ __forceinline__ void k_gkb_update_body(const GkbArgs& a, const VBlock vb, const bool grouped) {
   const int64_t n = a.n;
   T* X = (T*)a.X;
   T* W = (T*)a.W;
@@ -346,36 +401,39 @@ __global__ __launch_bounds__(kThreads) void k_gkb_update(GkbArgs a_, const GkbAr
   const int npart = a.npart, j = a.j;
   KState* st = a.st;
   const bool vec = a.vec;
-  __shared__ double sh[kThreads / 64 + 2];
-  // the first elements' loads do not depend on the scalars: issue them before
-  // the (memory-latency bound) prologue
-  const int64_t e_first = ((int64_t)vb.x * blockDim.x + threadIdx.x) * 4;
-  double xv0[4], wv0[4], vv0[4];
-  ld4(X, e_first, n, vec, xv0);
-  ld4(W, e_first, n, vec, wv0);
-  ld4(Vn, e_first, n, vec, vv0);
-  const volatile KState* vst = st;
-  const int ss = vst->stop_step;
-  if ((ss >= 0 && ss < j) || beyond_limit(st, j)) return;
-  const bool bbreak = (ss == j && vst->stop_kind == STOP_BETA);
+  __shared__ double sh[kShCtl];
+  // Every load of the prologue (stop flags, recorded scalars, breakdown scale,
+  // partials) is issued before the first use, none inside a branch: one
+  // memory latency.
+  const double bnext = st->beta[j];
+  const double rhob = st->rhobar[j - 1], phib = st->phibar[j - 1];
+  const double tol = st->tol;
+  double pm = gkb_scale_local(st, j, j + 1);
+  double ps = part_first(part, npart);
+  // (the stop flags last: moved to scalar registers, they are waited for at once)
+  const int ss = ld_state(&st->stop_step);
+  const int skind = ld_state(&st->stop_kind);
+  const int kl = ld_state(&st->k_limit);
+  if ((ss >= 0 && ss < j) || (kl > 0 && j > kl)) return;
+  const bool bbreak = (ss == j && skind == STOP_BETA);
   double alpha = 0.0;
   bool abreak = false, fin = true;
   if (!bbreak) {
-    alpha = sqrt(block_sum_partials(part, npart, sh));
-    const double scale = fmax(gkb_scale(st, j, j + 1, sh), alpha);
+    ps = part_rest(ps, part, npart);
+    block_sum_max_all(ps, pm, sh);
+    alpha = sqrt(ps);
+    const double scale = fmax(pm, alpha);
     fin = isfinite(alpha);
     abreak = !fin || alpha <= kBreakFactor * DBL_EPSILON * scale;
   }
-  const double bnext = st->beta[j];
   const double anext = bbreak ? 0.0 : alpha;
-  const double rhob = st->rhobar[j - 1], phib = st->phibar[j - 1];
   const double rho = sqrt(rhob * rhob + bnext * bnext);
   const double c = rhob / rho, s = bnext / rho;
   const double theta = s * anext;
   const double phi = c * phib;
   const double phibar_new = -s * phib;
   const double cx = phi / rho, cw = theta / rho;
-  const bool conv = !bbreak && !abreak && fabs(phibar_new) < st->tol;
+  const bool conv = !bbreak && !abreak && fabs(phibar_new) < tol;
   if (first_thread(vb)) {
     if (!bbreak) {
       st->alpha[j] = alpha;
@@ -397,13 +455,9 @@ __global__ __launch_bounds__(kThreads) void k_gkb_update(GkbArgs a_, const GkbAr
   const double ia = have_v ? 1.0 / alpha : 0.0;
   DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double xv[4], wv[4], vv[4];
-    if (e == e_first) {
-      for (int u = 0; u < 4; ++u) { xv[u] = xv0[u]; wv[u] = wv0[u]; vv[u] = vv0[u]; }
-    } else {
-      ld4(X, e, n, vec, xv);
-      ld4(W, e, n, vec, wv);
-      ld4(Vn, e, n, vec, vv);
-    }
+    ld4(X, e, n, vec, xv);
+    ld4(W, e, n, vec, wv);
+    ld4(Vn, e, n, vec, vv);
     for (int u = 0; u < 4; ++u) xv[u] += cx * wv[u];
     st4(X, e, n, vec, xv);
     if (have_v) {
@@ -417,13 +471,24 @@ __global__ __launch_bounds__(kThreads) void k_gkb_update(GkbArgs a_, const GkbAr
   }
 }
 
+template <typename T, bool GROUPED>
+__global__ __launch_bounds__(kThreads) void k_gkb_update(GkbArgs a_, const GkbArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_gkb_update_body<T>(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const GkbArgs g = group_args(grp, bmap, vb);
+    k_gkb_update_body<T>(g, vb, true);
+  }
+}
+
 // ---- Arnoldi / GMRES -----------------------------------------------------------
 // cycle start: beta = ||R|| from the partials; V_1 = R / beta
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_arn_start(int64_t n, T* out, const T* in, const double* part, int npart,
                                                         KState* st, bool vec) {
-  if (((volatile KState*)st)->halt) return;
-  __shared__ double sh[kThreads / 64 + 2];
+  if (ld_state(&st->halt)) return;
+  __shared__ double sh[kShCtl];
   const double beta = sqrt(block_sum_partials(part, npart, sh));
   const bool fin = isfinite(beta);
   const bool ok = fin && beta > 0.0;
@@ -452,7 +517,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_mgs(int64_t n, T* w, const T* vprev, const T* vi, const double* part_in,
                                                   int npart_in, double* hdst, double* part_out, bool vec, Gate g) {
   if (!gate_open(g)) return;
-  __shared__ double sh[kThreads / 64 + 2];
+  __shared__ double sh[kShCtl];
   double h = 0.0;
   if (part_in) {
     h = block_sum_partials(part_in, npart_in, sh);
@@ -483,15 +548,15 @@ __global__ __launch_bounds__(kThreads) void k_mgs(int64_t n, T* w, const T* vpre
 // one block: h_{j,j-1} from the partials (breakdown test) -- the prologue of the
 // next Arnoldi product, for the last step of a cycle
 __global__ __launch_bounds__(kThreads) void k_arn_finish(Ctl c) {
-  __shared__ double sh[kThreads / 64 + 2];
+  __shared__ double sh[kShCtl];
   double a, b, s;
   (void)ctl_begin(c, a, b, s, sh, hw_block());
 }
 
 // one block: ||C - M(X)|| from the partials; cycle bookkeeping; convergence
 __global__ __launch_bounds__(kThreads) void k_gmres_res(const double* part, int npart, KState* st) {
-  if (((volatile KState*)st)->halt) return;
-  __shared__ double sh[kThreads / 64 + 2];
+  if (ld_state(&st->halt)) return;
+  __shared__ double sh[kShCtl];
   const double r = sqrt(block_sum_partials(part, npart, sh));
   if (threadIdx.x == 0) {
     st->resnorm = r;
@@ -514,13 +579,11 @@ __global__ __launch_bounds__(kThreads) void k_cast(int64_t n, const double* in, 
 }
 
 // full = 1: clear everything (new solve); full = 0: start a new GMRES cycle (unless halted)
-__global__ void k_state_reset(ResetArgs a_, const ResetArgs* grp, const int4* bmap) {
-  VBlock vb;
-  const ResetArgs a = pick_args(a_, grp, bmap, vb);
+__device__ __forceinline__ void k_state_reset_body(const ResetArgs& a, const VBlock vb, const bool grouped) {
   KState* st = a.st;
   const int full = a.full;
   const double tol = a.tol;
-  if (full == 0 && ((volatile KState*)st)->halt) return;
+  if (full == 0 && ld_state(&st->halt)) return;
   if (full) {
     double* d = reinterpret_cast<double*>(st);
     const int nd = (int)(sizeof(KState) / sizeof(double));
@@ -540,6 +603,17 @@ __global__ void k_state_reset(ResetArgs a_, const ResetArgs* grp, const int4* bm
       st->stop_step = -1;
       st->stop_kind = STOP_NONE;
     }
+  }
+}
+
+template <bool GROUPED>
+__global__ void k_state_reset(ResetArgs a_, const ResetArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_state_reset_body(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const ResetArgs g = group_args(grp, bmap, vb);
+    k_state_reset_body(g, vb, true);
   }
 }
 
@@ -563,8 +637,8 @@ hipError_t launch_sumsq(dctk_ctx ctx, int dtype, int64_t n, const void* x, const
   a.z = z;
   a.part = part;
   a.g = g;
-  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_sumsq<double>, dim3(grid), kThreads, 0, a);
-  return launch_kernel(ctx, ctx->stream, k_sumsq<float>, dim3(grid), kThreads, 0, a);
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_sumsq<double, false>, k_sumsq<double, true>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_sumsq<float, false>, k_sumsq<float, true>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_axpy_sumsq(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x, const void* y,
@@ -596,8 +670,8 @@ hipError_t launch_multidot(dctk_ctx ctx, int dtype, int64_t n, const void* basis
   a.w = const_cast<void*>(w);
   a.part = part;
   a.g = g;
-  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_multidot<double>, dim3(grid), kThreads, 0, a);
-  return launch_kernel(ctx, ctx->stream, k_multidot<float>, dim3(grid), kThreads, 0, a);
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_multidot<double, false>, k_multidot<double, true>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_multidot<float, false>, k_multidot<float, true>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_coef_finalize(dctk_ctx ctx, const double* part, int nblocks, int nb, double* coef, double* dst,
@@ -611,7 +685,7 @@ hipError_t launch_coef_finalize(dctk_ctx ctx, const double* part, int nblocks, i
   a.dst = dst;
   a.dst_stride = dst_stride;
   a.g = g;
-  return launch_kernel(ctx, ctx->stream, k_coef_finalize, dim3(1), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_coef_finalize<false>, k_coef_finalize<true>, dim3(1), kThreads, 0, a);
 }
 
 hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* basis, int64_t stride, int nb,
@@ -627,8 +701,8 @@ hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const vo
   a.nb = nb;
   a.coef = const_cast<double*>(coef);
   a.g = g;
-  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_subtract<double>, dim3(grid), kThreads, 0, a);
-  return launch_kernel(ctx, ctx->stream, k_subtract<float>, dim3(grid), kThreads, 0, a);
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_subtract<double, false>, k_subtract<double, true>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_subtract<float, false>, k_subtract<float, true>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x0, const void* basis,
@@ -645,8 +719,8 @@ hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const v
   a.nptr = nptr;
   a.y = y;
   a.g = g;
-  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_combine<double>, dim3(grid), kThreads, 0, a);
-  return launch_kernel(ctx, ctx->stream, k_combine<float>, dim3(grid), kThreads, 0, a);
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_combine<double, false>, k_combine<double, true>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_combine<float, false>, k_combine<float, true>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_arn_start(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* in, const double* part,
@@ -711,8 +785,8 @@ hipError_t launch_gkb_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W
   a.npart = npart;
   a.j = 0;
   a.st = st;
-  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_gkb_start<double>, dim3(grid), kThreads, 0, a);
-  return launch_kernel(ctx, ctx->stream, k_gkb_start<float>, dim3(grid), kThreads, 0, a);
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_gkb_start<double, false>, k_gkb_start<double, true>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_gkb_start<float, false>, k_gkb_start<float, true>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* Vn, const double* part,
@@ -728,8 +802,8 @@ hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* 
   a.npart = npart;
   a.j = j;
   a.st = st;
-  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_gkb_update<double>, dim3(grid), kThreads, 0, a);
-  return launch_kernel(ctx, ctx->stream, k_gkb_update<float>, dim3(grid), kThreads, 0, a);
+  if (dtype == DCTK_F64) return launch_kernel(ctx, ctx->stream, k_gkb_update<double, false>, k_gkb_update<double, true>, dim3(grid), kThreads, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_gkb_update<float, false>, k_gkb_update<float, true>, dim3(grid), kThreads, 0, a);
 }
 
 hipError_t launch_cast(dctk_ctx ctx, int64_t n, const double* in, int out_dtype, void* out) {
@@ -750,7 +824,7 @@ hipError_t launch_state_reset(dctk_ctx ctx, KState* st, int full, double tol) {
   a.full = full;
   a.st = st;
   a.tol = tol;
-  return launch_kernel(ctx, ctx->stream, k_state_reset, dim3(1), 256, 0, a);
+  return launch_kernel(ctx, ctx->stream, k_state_reset<false>, k_state_reset<true>, dim3(1), 256, 0, a);
 }
 
 }  // namespace dctk
