@@ -540,7 +540,7 @@ static hipError_t gkb_init_impl(dctk_ctx ctx, dctk_krylov ws, const void* C, voi
   if ((e = apply_op(op, ctx->stream, 1, C, slot(ws->V, ws, 0), nullptr, slot(ws->U, ws, 0), c, &npB)) != hipSuccess)
     return e;
   rec_phase(ctx);
-  return launch_gkb_start(ctx, vdt, nV, X, ws->W, slot(ws->V, ws, 0), ws->partB, npB, st);
+  return launch_gkb_start(ctx, vdt, nV, X, X ? ws->W : nullptr, slot(ws->V, ws, 0), ws->partB, npB, st);
 }
 
 // Algorithm 4 step 3 (a)-(f) with the LSQR update of Algorithm 6 (c)-(g), step j:
@@ -580,7 +580,65 @@ static hipError_t gkb_step_impl(dctk_ctx ctx, dctk_krylov ws, int j, void* X) {
     if ((e = launch_sumsq(ctx, vdt, nV, Vn, nullptr, ws->partB, &npB, g)) != hipSuccess) return e;
   }
   rec_phase(ctx);
-  return launch_gkb_update(ctx, vdt, nV, X, ws->W, Vn, ws->partB, npB, st, j);
+  return launch_gkb_update(ctx, vdt, nV, X, X ? ws->W : nullptr, nullptr, Vn, ws->partB, npB, st, j);
+}
+
+// Whether a solve without the LSQR iterate can fold each LSQR update into the
+// next forward product: both products fused, no reorthogonalisation.
+static bool merged_steps(dctk_krylov ws) {
+  dctk_op op = ws->op;
+  return ws->reorth == DCTK_REORTH_NONE && fused_eligible(op) && use_fused(op, 0) && use_fused(op, 1);
+}
+
+// Step j of a Tikhonov solve (no LSQR iterate) with the update folded in:
+//   K1: unless j is the first step after an update that was flushed (pending =
+//       false), alpha_j and the rotation of step j-1 from the partials of V~,
+//       V_j = V~/alpha_j written while staged; T = M(V_j) - alpha_j U_j
+//   K2: beta_{j+1}; U_{j+1} = T/beta_{j+1}; V~ = M*(U_{j+1}) - beta_{j+1} V_j
+//       into the second T slot, with its partials.
+// The update of the last step is flushed by gkb_flush_update.
+static hipError_t gkb_step_merged(dctk_ctx ctx, dctk_krylov ws, int j, bool pending) {
+  dctk_op op = ws->op;
+  KState* st = ws->st;
+  void* Uj = slot(ws->U, ws, j - 1);
+  void* Un = slot(ws->U, ws, j);
+  void* Vj = slot(ws->V, ws, j - 1);
+  void* T0 = slot(ws->T, ws, 0);
+  void* T1 = slot(ws->T, ws, 1);
+  hipError_t e;
+  int npA = 0, npB = 0;
+  const Ctl c1 = pending ? make_ctl(CTL_GKB_FWDU, j, st, ws->partB, ws->last_npart, ws->partA)
+                         : make_ctl(CTL_GKB_FWD, j, st, nullptr, 0, ws->partA);
+  rec_phase(ctx);
+  if ((e = apply_op(op, ctx->stream, 0, pending ? T1 : Vj, T0, Uj, pending ? Vj : nullptr, c1, &npA)) != hipSuccess)
+    return e;
+  const Ctl c2 = make_ctl(CTL_GKB_ADJ, j, st, ws->partA, npA, ws->partB);
+  rec_phase(ctx);
+  if ((e = apply_op(op, ctx->stream, 1, T0, T1, Vj, Un, c2, &npB)) != hipSuccess) return e;
+  ws->last_npart = npB;
+  return hipSuccess;
+}
+
+// The LSQR update of step j left pending by gkb_step_merged: alpha_{j+1}, the
+// rotation, V_{j+1} = V~/alpha_{j+1}.
+static hipError_t gkb_flush_update(dctk_ctx ctx, dctk_krylov ws, int j) {
+  dctk_op op = ws->op;
+  rec_phase(ctx);
+  return launch_gkb_update(ctx, op->vec_dtype, op->p * op->n2 * op->s, nullptr, nullptr, slot(ws->T, ws, 1),
+                           slot(ws->V, ws, j), ws->partB, ws->last_npart, ws->st, j);
+}
+
+// Steps from..to of a Tikhonov solve, with the update of step to flushed.
+static hipError_t gkb_steps_tik(dctk_ctx ctx, dctk_krylov ws, int from, int to) {
+  hipError_t e;
+  if (merged_steps(ws)) {
+    for (int j = from; j <= to; ++j)
+      if ((e = gkb_step_merged(ctx, ws, j, j > from)) != hipSuccess) return e;
+    return to >= from ? gkb_flush_update(ctx, ws, to) : hipSuccess;
+  }
+  for (int j = from; j <= to; ++j)
+    if ((e = gkb_step_impl(ctx, ws, j, nullptr)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 // Everything dctk_lsqr_tik_solve enqueues (Algorithms 4-6, then Algorithm 5's
@@ -591,10 +649,14 @@ hipError_t lsqr_enqueue(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, co
   hipError_t e;
   ws->reorth = opts->reorth;
   const bool tik = opts->lambda != 0.0;
-  void* Xl = tik ? ws->X : X;  // LSQR iterate (Algorithm 6)
-  if ((e = gkb_init_impl(ctx, ws, C, Xl, opts->tol)) != hipSuccess) return e;
-  for (int j = 1; j <= opts->k_max; ++j)
-    if ((e = gkb_step_impl(ctx, ws, j, Xl)) != hipSuccess) return e;
+  // the LSQR iterate (Algorithm 6) is formed only when it is the answer
+  if ((e = gkb_init_impl(ctx, ws, C, tik ? nullptr : X, opts->tol)) != hipSuccess) return e;
+  if (tik) {
+    if ((e = gkb_steps_tik(ctx, ws, 1, opts->k_max)) != hipSuccess) return e;
+  } else {
+    for (int j = 1; j <= opts->k_max; ++j)
+      if ((e = gkb_step_impl(ctx, ws, j, X)) != hipSuccess) return e;
+  }
   ws->host_steps = opts->k_max;
   ws->initialised = 1;
   if (tik) {
@@ -682,14 +744,12 @@ hipError_t learned_enqueue(dctk_ctx ctx, dctk_krylov ws, dctk_mlp m, const void*
   dctk_op op = ws->op;
   hipError_t e;
   ws->reorth = opts->reorth;
-  if ((e = gkb_init_impl(ctx, ws, C, ws->X, opts->tol)) != hipSuccess) return e;
-  for (int j = 1; j <= kf; ++j)
-    if ((e = gkb_step_impl(ctx, ws, j, ws->X)) != hipSuccess) return e;
+  if ((e = gkb_init_impl(ctx, ws, C, nullptr, opts->tol)) != hipSuccess) return e;
+  if ((e = gkb_steps_tik(ctx, ws, 1, kf)) != hipSuccess) return e;
   rec_phase(ctx);
   if ((e = launch_mlp_stop(ctx, m, ws->st, kf, opts->k_max)) != hipSuccess) return e;
   // steps beyond the predicted stop exit at once (their gate reads st->k_limit)
-  for (int j = kf + 1; j <= opts->k_max; ++j)
-    if ((e = gkb_step_impl(ctx, ws, j, ws->X)) != hipSuccess) return e;
+  if ((e = gkb_steps_tik(ctx, ws, kf + 1, opts->k_max)) != hipSuccess) return e;
   ws->host_steps = opts->k_max;
   ws->initialised = 1;
   rec_phase(ctx);
@@ -910,13 +970,13 @@ int dctk_lsqr_learned_solve(dctk_ctx ctx, dctk_krylov ws, dctk_mlp mlp, const vo
     return DCTK_EINVAL;
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
   ws->reorth = opts->reorth;
-  DCTK_HIP(ctx, gkb_init_impl(ctx, ws, C, ws->X, opts->tol));
-  for (int j = 1; j <= kf; ++j) DCTK_HIP(ctx, gkb_step_impl(ctx, ws, j, ws->X));
+  DCTK_HIP(ctx, gkb_init_impl(ctx, ws, C, nullptr, opts->tol));
+  DCTK_HIP(ctx, gkb_steps_tik(ctx, ws, 1, kf));
   float pred[5];
   DCTK_HIP(ctx, mlp_predict(ctx, mlp, ws->st, kf, opts->k_max, pred));
   const bool valid = pred[4] > 0.5f;
   const int kstop = valid ? (int)pred[3] : opts->k_max;
-  for (int j = kf + 1; j <= kstop; ++j) DCTK_HIP(ctx, gkb_step_impl(ctx, ws, j, ws->X));
+  DCTK_HIP(ctx, gkb_steps_tik(ctx, ws, kf + 1, kstop));
   ws->host_steps = kstop;
   ws->initialised = 1;
   DCTK_HIP(ctx, launch_projected(ctx, ws->st, 1, opts->gcv_mode, -1.0, 0, valid ? (double)pred[2] : -1.0, gate));

@@ -82,6 +82,9 @@ enum CtlKind : int {
   CTL_GKB_ADJ = 3,   // Alg. 4 (b)-(d): beta_{j+1} = sqrt(sum part_in); input x 1/beta (-> U_{j+1});
                      //   out = M*(U_{j+1}) - beta_{j+1} V_j
   CTL_ARN_FWD = 4,   // Alg. 2 (a): h_{j,j-1} = sqrt(sum part_in) (j > 1); input x 1/h (-> V_j); out = M(V_j)
+  CTL_GKB_FWDU = 5,  // the LSQR update of step j-1 (Alg. 4 (e)-(f), Alg. 6 (c)-(e) without X, W):
+                     //   alpha_j = sqrt(sum part_in), the rotation; input V~ x 1/alpha_j (-> V_j);
+                     //   then Alg. 4 (a) of step j: out = M(V_j) - alpha_j U_j
 };
 
 struct Ctl {
@@ -292,6 +295,56 @@ __device__ inline A group_args(const A* grp, const int4* bmap, VBlock& vb) {
   return r;
 }
 
+// Algorithm 4 (e)-(f) with Algorithm 6 (c)-(e) for step j, after the adjoint
+// product: unless beta_{j+1} broke down, alpha_{j+1} from this thread's share
+// of the partials of ||V~||^2 (ps, already including every entry) and of the
+// breakdown scale (pm), with its breakdown test; then the plane rotation from
+// beta_{j+1} (bnext), rhobar_j, phibar_j.  `first` records alpha_{j+1},
+// rhobar_{j+1}, phibar_{j+1} and the stop flags.  Every thread of the block
+// calls it (block reduction); (cx, cw) are the X and W update coefficients.
+struct GkbUpd {
+  double alpha, cx, cw;
+  bool have_v;
+};
+__device__ inline GkbUpd gkb_update_scalars(KState* st, int j, double ps, double pm, double bnext, double rhob,
+                                            double phib, double tol, int ss, int skind, double* sh, bool first) {
+  const bool bbreak = (ss == j && skind == STOP_BETA);
+  double alpha = 0.0;
+  bool abreak = false, fin = true;
+  if (!bbreak) {
+    block_sum_max_all(ps, pm, sh);
+    alpha = sqrt(ps);
+    const double scale = fmax(pm, alpha);
+    fin = isfinite(alpha);
+    abreak = !fin || alpha <= kBreakFactor * 2.220446049250313e-16 * scale;
+  }
+  const double anext = bbreak ? 0.0 : alpha;
+  const double rho = sqrt(rhob * rhob + bnext * bnext);
+  const double c = rhob / rho, s = bnext / rho;
+  const double theta = s * anext;
+  const double phi = c * phib;
+  const double phibar_new = -s * phib;
+  const bool conv = !bbreak && !abreak && fabs(phibar_new) < tol;
+  if (first) {
+    if (!bbreak) {
+      st->alpha[j] = alpha;
+      st->steps = j;
+    }
+    st->rhobar[j] = c * anext;
+    st->phibar[j] = phibar_new;
+    if (abreak) {
+      st->stop_step = j;
+      st->stop_kind = STOP_ALPHA;
+      st->status = fin ? DCTK_BREAKDOWN : DCTK_ENONFINITE;
+    } else if (conv) {
+      st->stop_step = j;
+      st->stop_kind = STOP_CONV;
+      st->converged = 1;
+    }
+  }
+  return GkbUpd{alpha, phi / rho, theta / rho, !bbreak && !abreak};
+}
+
 // What a control block reads from memory.  ctl_load issues every load (the
 // recorded scalar, this thread's share of the history that scales the
 // breakdown test and of the partials, then the stop flags), none of them
@@ -300,11 +353,12 @@ __device__ inline A group_args(const A* grp, const int4* bmap, VBlock& vb) {
 // first loads, then calls ctl_load, waits for memory once.
 struct CtlLoad {
   double ps, pm, rec;
-  int ss, kl, halt;
+  double bn, rb, pb, tol;  // the LSQR update (CTL_GKB_FWDU): beta_j, rhobar_{j-1}, phibar_{j-1}, tol
+  int ss, kl, halt, sk;
 };
 
 __device__ inline CtlLoad ctl_load(const Ctl& c) {
-  CtlLoad L{0.0, 0.0, 0.0, -1, 0, 0};
+  CtlLoad L{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1, 0, 0, 0};
   if (c.kind == CTL_PLAIN) {
     if (c.st != nullptr) L.halt = ld_state(&c.st->halt);
     return L;
@@ -317,33 +371,45 @@ __device__ inline CtlLoad ctl_load(const Ctl& c) {
   constexpr int oA = (int)(offsetof(KState, alpha) / sizeof(double));
   constexpr int oB = (int)(offsetof(KState, beta) / sizeof(double));
   constexpr int oH = (int)(offsetof(KState, H) / sizeof(double));
+  constexpr int oRB = (int)(offsetof(KState, rhobar) / sizeof(double));
+  constexpr int oPB = (int)(offsetof(KState, phibar) / sizeof(double));
+  constexpr int oTol = (int)(offsetof(KState, tol) / sizeof(double));
   const int j = c.j, i = (int)threadIdx.x;
   const bool fs = c.from_state != 0;
   const bool fwd = c.kind == CTL_GKB_FWD, ini = c.kind == CTL_GKB_INIT, adj = c.kind == CTL_GKB_ADJ,
-             arn = c.kind == CTL_ARN_FWD;
+             arn = c.kind == CTL_ARN_FWD, fwdu = c.kind == CTL_GKB_FWDU;
   // the recorded scalar this kernel needs (beta_1 when none)
   int ri = oB;
   ri = (fs && arn && j > 1) ? oH + (j - 1) * kMaxK + j - 2 : ri;
   ri = (fs && adj) ? oB + j : ri;
   ri = fwd ? oA + j - 1 : ri;
   L.rec = sd[ri];
-  // breakdown scale: max |alpha_1..alpha_j|, |beta_1..beta_j| (GKB adjoint) or
-  // max_i |h_{i, j-1}| (Arnoldi), one value of each per thread from a clamped
-  // index (j <= kMaxK + 1 < kThreads; a repeated value does not change the max)
+  // breakdown scale: max |alpha_1..alpha_na|, |beta_1..beta_j| (GKB adjoint:
+  // na = j; LSQR update of step j-1: na = j - 1) or max_i |h_{i, j-1}|
+  // (Arnoldi), one value of each per thread from a clamped index
+  // (j <= kMaxK + 1 < kThreads; a repeated value does not change the max)
   static_assert(kMaxK + 2 <= kThreads, "one history value per thread");
-  const int ia = j > 1 ? (i < j ? i : j - 1) : 0;
+  const int na = fwdu ? j - 1 : j;
+  const int iaa = na > 1 ? (i < na ? i : na - 1) : 0, iab = j > 1 ? (i < j ? i : j - 1) : 0;
   const int ih = j > 2 ? (i < j - 1 ? i : j - 2) : 0, ch = j > 2 ? j - 2 : 0;
-  const double av = sd[oA + ia], bv = sd[oB + ia], hv = sd[oH + ih * kMaxK + ch];
-  const double wab = adj ? 1.0 : 0.0, wh = arn ? 1.0 : 0.0;
+  const double av = sd[oA + iaa], bv = sd[oB + iab], hv = sd[oH + ih * kMaxK + ch];
+  const double wab = (adj || fwdu) ? 1.0 : 0.0, wh = arn ? 1.0 : 0.0;
   L.pm = fmax(wab * fmax(fabs(av), fabs(bv)), wh * fabs(hv));
+  // the recorded scalars of the LSQR update of step j - 1
+  const int jp = j > 0 ? j - 1 : 0, jq = j > 1 ? j - 2 : 0;
+  L.bn = sd[oB + jp];
+  L.rb = sd[oRB + jq];
+  L.pb = sd[oPB + jq];
+  L.tol = sd[oTol];
   // the partials of the norm (from beta_1, with no entries, when none)
-  const bool sums = !fs && (ini || adj || (arn && j > 1));
+  const bool sums = !fs && (ini || adj || fwdu || (arn && j > 1));
   L.ps = part_first(sums ? c.part_in : sd + oB, sums ? c.npart_in : 0);
   // the stop flags last: the compiler moves these uniform values to scalar
   // registers, which waits for them, and with them for every earlier load
   L.ss = ld_state(&st->stop_step);
   L.kl = ld_state(&st->k_limit);
   L.halt = ld_state(&st->halt);
+  L.sk = ld_state(&st->stop_kind);
   return L;
 }
 
@@ -366,7 +432,8 @@ __device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, doubl
   asm volatile("" ::"v"(L.ps), "v"(L.pm), "v"(L.rec), "v"(L.ss), "v"(L.kl), "v"(L.halt));
   KState* st = c.st;
   const int j = c.j;
-  const bool sums = !c.from_state && (c.kind == CTL_GKB_INIT || c.kind == CTL_GKB_ADJ || (c.kind == CTL_ARN_FWD && j > 1));
+  const bool sums = !c.from_state && (c.kind == CTL_GKB_INIT || c.kind == CTL_GKB_ADJ || c.kind == CTL_GKB_FWDU ||
+                                      (c.kind == CTL_ARN_FWD && j > 1));
   double ps = sums ? part_rest(L.ps, c.part_in, c.npart_in) : 0.0, pm = L.pm;
   const double rec = L.rec;
   const int ss = L.ss, kl = L.kl, halt = L.halt;
@@ -425,6 +492,15 @@ __device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, doubl
       if (brk) return false;
       sin = 1.0 / bt;
       b = -bt;
+      return true;
+    }
+    case CTL_GKB_FWDU: {
+      const int jp = j - 1;  // the pending update
+      if ((ss >= 0 && ss < jp) || (kl > 0 && jp > kl)) return false;
+      const GkbUpd u = gkb_update_scalars(st, jp, ps, pm, L.bn, L.rb, L.pb, L.tol, ss, L.sk, sh, first);
+      if (!u.have_v) return false;
+      sin = 1.0 / u.alpha;
+      b = -u.alpha;
       return true;
     }
     case CTL_ARN_FWD: {
@@ -691,8 +767,8 @@ hipError_t launch_gmres_res(dctk_ctx ctx, const double* part, int npart, KState*
 // GKB start (Algorithm 6 step 2) and the per-step update (Algorithm 6 (c)-(g))
 hipError_t launch_gkb_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* V1, const double* part,
                             int npart, KState* st);
-hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* Vn, const double* part,
-                             int npart, KState* st, int j);
+hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, const void* Vin, void* Vn,
+                             const double* part, int npart, KState* st, int j);
 hipError_t launch_state_reset(dctk_ctx ctx, KState* st, int full, double tol);
 hipError_t launch_cast(dctk_ctx ctx, int64_t n, const double* in, int out_dtype, void* out);
 

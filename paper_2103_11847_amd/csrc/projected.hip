@@ -14,7 +14,9 @@
 //     subdivided in passes of 64 points (one 16-lane row each) around the
 //     first smallest value until the bracket on log10(lambda) is below 1e-10,
 //     keeping the better of the refined point and the grid point;
-//   * y_lambda = V diag(sigma / (sigma^2 + lambda^2)) g  (eq. leastsq / normeq2).
+//   * y_lambda (eq. leastsq / normeq2): for the bidiagonal matrix by plane
+//     rotations of [C~_k; lambda I] (so the Jacobi sweeps need not accumulate
+//     V), for the Hessenberg matrix as V diag(sigma / (sigma^2 + lambda^2)) g.
 // The GCV function is that of the rectangular projected problem (mode 0) or
 // the printed eq. (gcv2) (mode 1).
 #include <cfloat>
@@ -32,12 +34,11 @@ constexpr int kGrid = 400;
 // 8 consecutive rows of mostly consecutive columns, fall in distinct bank windows.
 constexpr int kLdG = 72;
 constexpr int kLdV = 72;
-constexpr int kJR = (kMaxK + 1 + 7) / 8;   // rows of G per lane of an 8-lane group
-constexpr int kJV = (kMaxK + 7) / 8;       // rows of V per lane
+constexpr int kJR = (kMaxK + 1 + 7) / 8;   // rows of G (and V) per lane of an 8-lane group
 constexpr int kRef = kPW * 4;              // GCV refinement points per pass (16-lane rows)
 static_assert(kPW * 8 >= (kMaxK + 1) / 2, "one Jacobi round must fit in one pass (8 pairs per wave)");
 static_assert(kRef == 64, "the refinement pass reduces one value per lane of a wave");
-static_assert(kMaxK % 8 == 0 && kJV * 8 == kMaxK && kLdV >= kMaxK, "a lane reads rows l, l + 8, ... < kMaxK of V");
+static_assert(kLdV >= kMaxK, "V columns hold kMaxK rows");
 static_assert(kJR * 8 <= kLdG && kLdG >= kMaxK + 1, "a lane reads rows l, l + 8, ... < kLdG of G");
 
 // Sum over the 8 lanes of a half row, returned to every lane of it (identical bits).
@@ -134,6 +135,77 @@ __device__ inline double gcv_row16(int mode, double lam, int k, const double* si
   return t1 / (t2 * t2);
 }
 
+// One round of the one-sided Jacobi method for the pair (p, q) of this 8-lane
+// group: each lane holds rows l8, l8 + 8, ... (NR of them) of the two columns
+// of G and, when V is accumulated, of V.  Every load is issued before the
+// first use, from addresses inside the arrays: rows past the matrix read the
+// zero rows below it, and the columns of an idle pair are replaced by zeros
+// after the load.
+template <int NR, bool WITHV>
+__device__ inline void jacobi_round(double* G, double* Vm, int p, int q, bool valid, int l8, int rows, int k,
+                                    double tolJ, int* rot_flag) {
+  static_assert(8 * NR <= kLdG && 8 * NR <= kLdV, "rows of a lane inside the column strides");
+  double xp[NR], xq[NR], vp[NR], vq[NR];
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int r = l8 + 8 * u;
+    xp[u] = G[p * kLdG + r];
+    xq[u] = G[q * kLdG + r];
+  }
+  if constexpr (WITHV) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      vp[u] = Vm[p * kLdV + l8 + 8 * u];
+      vq[u] = Vm[q * kLdV + l8 + 8 * u];
+    }
+  }
+  double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const double x = valid ? xp[u] : 0.0, y = valid ? xq[u] : 0.0;
+    a += x * x;
+    b += y * y;
+    c += x * y;
+  }
+  a = row8_sum(a);
+  b = row8_sum(b);
+  c = row8_sum(c);
+  if (valid && c != 0.0 && c * c > (tolJ * tolJ) * (a * b)) {
+    // The smaller of the two rotations that make g_p . g_q zero, through the
+    // double angle: with h = sqrt((b - a)^2 + 4c^2), cos 2th = |b - a| / h and
+    // sin 2th = sign(b - a) 2c / h; then cos th = sqrt((1 + cos 2th) / 2) and
+    // sin th = sin 2th / (2 cos th), with 1 + cos 2th >= 1 (no cancellation):
+    // two reciprocal square roots, no division.
+    const double dba = b - a;
+    const double ih = rsqrt(dba * dba + 4.0 * c * c);
+    const double c2 = fabs(dba) * ih;
+    const double s2 = (dba >= 0.0 ? 2.0 * c : -2.0 * c) * ih;
+    const double w = 0.5 + 0.5 * c2;
+    const double iw = rsqrt(w);
+    const double cs = w * iw;
+    const double sn = 0.5 * s2 * iw;
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int r = l8 + 8 * u;
+      if (r < rows) {
+        G[p * kLdG + r] = cs * xp[u] - sn * xq[u];
+        G[q * kLdG + r] = sn * xp[u] + cs * xq[u];
+      }
+    }
+    if constexpr (WITHV) {
+#pragma unroll
+      for (int u = 0; u < NR; ++u) {
+        const int r = l8 + 8 * u;
+        if (r < k) {
+          Vm[p * kLdV + r] = cs * vp[u] - sn * vq[u];
+          Vm[q * kLdV + r] = sn * vp[u] + cs * vq[u];
+        }
+      }
+    }
+    if (l8 == 0) *rot_flag = 1;
+  }
+}
+
 struct ProjArgs {
   int gx, gy, gz;
   int bidiag;
@@ -161,6 +233,7 @@ __device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock
   __shared__ double gridv[kGrid];
   __shared__ double refv[kRef];
   __shared__ double wcoef[kMaxK];
+  __shared__ double ab_a[kMaxK], ab_b[kMaxK];   // bidiagonal: alpha_1..alpha_k, beta_2..beta_{k+1}
   __shared__ int rot_flag[2];
   __shared__ double s_gperp2, s_lam, s_gcv;
   __shared__ double s_ra, s_rb, s_rt, s_rf;
@@ -188,7 +261,14 @@ __device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock
     }
     G[i] = v;
   }
-  for (int i = tid; i < k * kLdV; i += kPT) Vm[i] = ((i / kLdV) == (i % kLdV)) ? 1.0 : 0.0;
+  if (bidiag) {
+    if (tid < k) {
+      ab_a[tid] = st->alpha[tid];
+      ab_b[tid] = st->beta[tid + 1];
+    }
+  } else {
+    for (int i = tid; i < k * kLdV; i += kPT) Vm[i] = ((i / kLdV) == (i % kLdV)) ? 1.0 : 0.0;
+  }
   if (tid == 0) { rot_flag[0] = 0; rot_flag[1] = 0; }
   __syncthreads();
 
@@ -245,6 +325,7 @@ __device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock
 
   // One-sided Jacobi.  Pair pi of a round belongs to an 8-lane group (lane / 8)
   // of wave pi / 8, so at most four waves (one per SIMD) do the work of a round.
+  // V is accumulated only for the Hessenberg matrix.
   const int cEven = k + (k & 1);
   const int npairs = cEven / 2;
   const int grp = lane >> 3, l8 = lane & 7;
@@ -252,6 +333,7 @@ __device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock
   // rotate while |g_p . g_q| > tol |g_p| |g_q|; below a few ulps per row the
   // columns are orthogonal to working precision
   const double tolJ = DBL_EPSILON * (double)rows;
+  const bool small = rows <= 48;  // six rows per lane suffice
   int sweeps = 0;
   for (int sweep = 0; sweep < 60 && cEven > 1; ++sweep) {
     const int flag = sweep & 1;
@@ -272,64 +354,14 @@ __device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock
         q = ia < ib ? ib : ia;
         valid = q < k;  // the dummy column of an odd k
       }
-      // Every lane takes part in the group reductions (zeros when idle).  All
-      // loads are issued before the first use, from addresses inside the
-      // arrays: rows past the matrix read the zero rows below it, and the
-      // columns of an idle pair are replaced by zeros after the load.
-      double xp[kJR], xq[kJR], vp[kJV], vq[kJV];
-#pragma unroll
-      for (int u = 0; u < kJR; ++u) {
-        const int r = l8 + 8 * u;
-        xp[u] = G[p * kLdG + r];
-        xq[u] = G[q * kLdG + r];
-      }
-#pragma unroll
-      for (int u = 0; u < kJV; ++u) {
-        vp[u] = Vm[p * kLdV + l8 + 8 * u];
-        vq[u] = Vm[q * kLdV + l8 + 8 * u];
-      }
-      double a = 0.0, b = 0.0, c = 0.0;
-#pragma unroll
-      for (int u = 0; u < kJR; ++u) {
-        const double x = valid ? xp[u] : 0.0, y = valid ? xq[u] : 0.0;
-        a += x * x;
-        b += y * y;
-        c += x * y;
-      }
-      a = row8_sum(a);
-      b = row8_sum(b);
-      c = row8_sum(c);
-      if (valid && c != 0.0 && c * c > (tolJ * tolJ) * (a * b)) {
-        // The smaller of the two rotations that make g_p . g_q zero, through the
-        // double angle: with h = sqrt((b - a)^2 + 4c^2), cos 2th = |b - a| / h and
-        // sin 2th = sign(b - a) 2c / h; then cos th = sqrt((1 + cos 2th) / 2) and
-        // sin th = sin 2th / (2 cos th), with 1 + cos 2th >= 1 (no cancellation):
-        // two reciprocal square roots, no division.
-        const double dba = b - a;
-        const double ih = rsqrt(dba * dba + 4.0 * c * c);
-        const double c2 = fabs(dba) * ih;
-        const double s2 = (dba >= 0.0 ? 2.0 * c : -2.0 * c) * ih;
-        const double w = 0.5 + 0.5 * c2;
-        const double iw = rsqrt(w);
-        const double cs = w * iw;
-        const double sn = 0.5 * s2 * iw;
-#pragma unroll
-        for (int u = 0; u < kJR; ++u) {
-          const int r = l8 + 8 * u;
-          if (r < rows) {
-            G[p * kLdG + r] = cs * xp[u] - sn * xq[u];
-            G[q * kLdG + r] = sn * xp[u] + cs * xq[u];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kJV; ++u) {
-          const int r = l8 + 8 * u;
-          if (r < k) {
-            Vm[p * kLdV + r] = cs * vp[u] - sn * vq[u];
-            Vm[q * kLdV + r] = sn * vp[u] + cs * vq[u];
-          }
-        }
-        if (l8 == 0) rot_flag[flag] = 1;
+      // every lane takes part in the group reductions (zeros when idle); the
+      // bidiagonal case needs no V (y comes from the damped recurrence below)
+      if (bidiag) {
+        if (small) jacobi_round<6, false>(G, Vm, p, q, valid, l8, rows, k, tolJ, &rot_flag[flag]);
+        else jacobi_round<kJR, false>(G, Vm, p, q, valid, l8, rows, k, tolJ, &rot_flag[flag]);
+      } else {
+        if (small) jacobi_round<6, true>(G, Vm, p, q, valid, l8, rows, k, tolJ, &rot_flag[flag]);
+        else jacobi_round<kJR, true>(G, Vm, p, q, valid, l8, rows, k, tolJ, &rot_flag[flag]);
       }
       __syncthreads();
     }
@@ -440,17 +472,52 @@ __device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock
   }
   __syncthreads();
 
-  // y = sum_i v_i sigma_i g_i / (sigma_i^2 + lambda^2)
   const double lam = s_lam;
-  if (tid < k) {
-    const double dd = ssort[tid] * ssort[tid] + lam * lam;
-    wcoef[tid] = dd > 0.0 ? g0s[tid] / dd : 0.0;
-  }
-  __syncthreads();
-  if (tid < k) {
-    double acc = 0.0;
-    for (int i = 0; i < k; ++i) acc += Vm[order[i] * kLdV + tid] * wcoef[i];
-    st->y[tid] = acc;
+  if (bidiag) {
+    // y_lambda = argmin ||C~ y - beta_1 e_1||^2 + lambda^2 ||y||^2 by plane
+    // rotations of [C~; lambda I] (the damped bidiagonal recurrence of LSQR):
+    // at step i the damping row is rotated into rhobar_i, then beta_{i+1}
+    // below it, which leaves R upper bidiagonal (rho_i, theta_{i+1}) and its
+    // right-hand side phi_i; then R y = phi by back substitution.  One lane.
+    if (tid == 0) {
+      double* rho = wcoef;
+      double* phi = gs;
+      double* th = ssort;
+      double rbar = ab_a[0], fbar = beta;
+      for (int i = 0; i < k; ++i) {
+        const double rhat = sqrt(rbar * rbar + lam * lam);
+        const double c1 = rhat > 0.0 ? rbar / rhat : 1.0;
+        const double fhat = c1 * fbar;
+        const double bn = ab_b[i];
+        const double r = sqrt(rhat * rhat + bn * bn);
+        const double c = r > 0.0 ? rhat / r : 1.0, sn = r > 0.0 ? bn / r : 0.0;
+        rho[i] = r;
+        phi[i] = c * fhat;
+        if (i + 1 < k) {
+          th[i] = sn * ab_a[i + 1];
+          rbar = -c * ab_a[i + 1];
+        }
+        fbar = sn * fhat;
+      }
+      double yn = 0.0;
+      for (int i = k - 1; i >= 0; --i) {
+        const double rhs = phi[i] - (i + 1 < k ? th[i] * yn : 0.0);
+        yn = rho[i] > 0.0 ? rhs / rho[i] : 0.0;
+        st->y[i] = yn;
+      }
+    }
+  } else {
+    // y = sum_i v_i sigma_i g_i / (sigma_i^2 + lambda^2)
+    if (tid < k) {
+      const double dd = ssort[tid] * ssort[tid] + lam * lam;
+      wcoef[tid] = dd > 0.0 ? g0s[tid] / dd : 0.0;
+    }
+    __syncthreads();
+    if (tid < k) {
+      double acc = 0.0;
+      for (int i = 0; i < k; ++i) acc += Vm[order[i] * kLdV + tid] * wcoef[i];
+      st->y[tid] = acc;
+    }
   }
   if (tid == 0) {
     st->lambda = lam;

@@ -78,9 +78,10 @@ struct GkbArgs {  // start and per-step update of Algorithm 6
   int gx, gy, gz;
   int vec;
   int64_t n;
-  void* X;
-  void* W;
-  void* V;
+  void* X;          // LSQR iterate (null: not formed)
+  void* W;          // LSQR search direction (null with X)
+  void* V;          // the new basis vector (written)
+  const void* Vin;  // its unnormalised input (update; null: V itself)
   const double* part;
   int npart;
   int j;
@@ -363,14 +364,14 @@ __device__ __forceinline__ void k_gkb_start_body(const GkbArgs& a, const VBlock 
   const double ia = brk ? 0.0 : 1.0 / alpha;
   DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double z[4] = {0.0, 0.0, 0.0, 0.0};
-    st4(X, e, n, vec, z);
+    if (X) st4(X, e, n, vec, z);
     if (!brk) {
       double v[4];
       ld4(V1, e, n, vec, v);
       for (int u = 0; u < 4; ++u) v[u] = (double)(T)(v[u] * ia);
       st4(V1, e, n, vec, v);
-      st4(W, e, n, vec, v);
-    } else {
+      if (W) st4(W, e, n, vec, v);
+    } else if (W) {
       st4(W, e, n, vec, z);
     }
   }
@@ -397,76 +398,46 @@ __device__ __forceinline__ void k_gkb_update_body(const GkbArgs& a, const VBlock
   T* X = (T*)a.X;
   T* W = (T*)a.W;
   T* Vn = (T*)a.V;
+  const T* Vi = a.Vin ? (const T*)a.Vin : Vn;
   const double* part = a.part;
   const int npart = a.npart, j = a.j;
   KState* st = a.st;
   const bool vec = a.vec;
   __shared__ double sh[kShCtl];
-  // Every load of the prologue (stop flags, recorded scalars, breakdown scale,
-  // partials) is issued before the first use, none inside a branch: one
+  // Every load of the prologue (recorded scalars, breakdown scale, partials,
+  // stop flags) is issued before the first use, none inside a branch: one
   // memory latency.
   const double bnext = st->beta[j];
   const double rhob = st->rhobar[j - 1], phib = st->phibar[j - 1];
   const double tol = st->tol;
-  double pm = gkb_scale_local(st, j, j + 1);
+  const double pm = gkb_scale_local(st, j, j + 1);
   double ps = part_first(part, npart);
   // (the stop flags last: moved to scalar registers, they are waited for at once)
   const int ss = ld_state(&st->stop_step);
   const int skind = ld_state(&st->stop_kind);
   const int kl = ld_state(&st->k_limit);
   if ((ss >= 0 && ss < j) || (kl > 0 && j > kl)) return;
-  const bool bbreak = (ss == j && skind == STOP_BETA);
-  double alpha = 0.0;
-  bool abreak = false, fin = true;
-  if (!bbreak) {
-    ps = part_rest(ps, part, npart);
-    block_sum_max_all(ps, pm, sh);
-    alpha = sqrt(ps);
-    const double scale = fmax(pm, alpha);
-    fin = isfinite(alpha);
-    abreak = !fin || alpha <= kBreakFactor * DBL_EPSILON * scale;
-  }
-  const double anext = bbreak ? 0.0 : alpha;
-  const double rho = sqrt(rhob * rhob + bnext * bnext);
-  const double c = rhob / rho, s = bnext / rho;
-  const double theta = s * anext;
-  const double phi = c * phib;
-  const double phibar_new = -s * phib;
-  const double cx = phi / rho, cw = theta / rho;
-  const bool conv = !bbreak && !abreak && fabs(phibar_new) < tol;
-  if (first_thread(vb)) {
-    if (!bbreak) {
-      st->alpha[j] = alpha;
-      st->steps = j;
-    }
-    st->rhobar[j] = c * anext;
-    st->phibar[j] = phibar_new;
-    if (abreak) {
-      st->stop_step = j;
-      st->stop_kind = STOP_ALPHA;
-      st->status = fin ? DCTK_BREAKDOWN : DCTK_ENONFINITE;
-    } else if (conv) {
-      st->stop_step = j;
-      st->stop_kind = STOP_CONV;
-      st->converged = 1;
-    }
-  }
-  const bool have_v = !bbreak && !abreak;
-  const double ia = have_v ? 1.0 / alpha : 0.0;
+  ps = part_rest(ps, part, npart);
+  const GkbUpd u = gkb_update_scalars(st, j, ps, pm, bnext, rhob, phib, tol, ss, skind, sh, first_thread(vb));
+  const double cx = u.cx, cw = u.cw;
+  const bool have_v = u.have_v;
+  const double ia = have_v ? 1.0 / u.alpha : 0.0;
   DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double xv[4], wv[4], vv[4];
-    ld4(X, e, n, vec, xv);
-    ld4(W, e, n, vec, wv);
-    ld4(Vn, e, n, vec, vv);
-    for (int u = 0; u < 4; ++u) xv[u] += cx * wv[u];
-    st4(X, e, n, vec, xv);
+    if (X) {
+      ld4(X, e, n, vec, xv);
+      ld4(W, e, n, vec, wv);
+      for (int q = 0; q < 4; ++q) xv[q] += cx * wv[q];
+      st4(X, e, n, vec, xv);
+    }
     if (have_v) {
-      for (int u = 0; u < 4; ++u) {
-        vv[u] = (double)(T)(vv[u] * ia);
-        wv[u] = vv[u] - cw * wv[u];
-      }
+      ld4(Vi, e, n, vec, vv);
+      for (int q = 0; q < 4; ++q) vv[q] = (double)(T)(vv[q] * ia);
       st4(Vn, e, n, vec, vv);
-      st4(W, e, n, vec, wv);
+      if (X) {
+        for (int q = 0; q < 4; ++q) wv[q] = vv[q] - cw * wv[q];
+        st4(W, e, n, vec, wv);
+      }
     }
   }
 }
@@ -789,15 +760,16 @@ hipError_t launch_gkb_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W
   return launch_kernel(ctx, ctx->stream, k_gkb_start<float, false>, k_gkb_start<float, true>, dim3(grid), kThreads, 0, a);
 }
 
-hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* Vn, const double* part,
-                             int npart, KState* st, int j) {
+hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, const void* Vin, void* Vn,
+                             const double* part, int npart, KState* st, int j) {
   const unsigned grid = grid_for(n);
   GkbArgs a{};
-  a.vec = (n % 4 == 0) && al(X) && al(W) && al(Vn);
+  a.vec = (n % 4 == 0) && al(X) && al(W) && al(Vn) && al(Vin);
   a.n = n;
   a.X = X;
   a.W = W;
   a.V = Vn;
+  a.Vin = Vin;
   a.part = part;
   a.npart = npart;
   a.j = j;
