@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # in the same runs.  They describe the kernel sources with this digest only.
 TRAFFIC_SOURCES = ("paper_2103_11847_amd/csrc/fused.hip", "paper_2103_11847_amd/csrc/mfma.h",
                    "paper_2103_11847_amd/csrc/internal.h")
-TRAFFIC = {"digest": "55480a57c0a79568", "gemm": "f32",
-           "bytes": {"fused_fwd": 6526694, "fused_adj": 7333451}}
+TRAFFIC = {"digest": "2a6c72341e359596", "gemm": "f32",
+           "bytes": {"fused_fwd": 7428502, "fused_adj": 7398060}}
 
 
 def measured_traffic(kind, gemm):
@@ -177,8 +177,10 @@ def main():
     bg = 4 if args.gemm == "f32" else 2
     N = p * n * s
     # algorithmic bytes of one launch inside a GKB step: A~ once, the input, the epilogue's
-    # src (alpha U_j or beta V_j) and the output; the adjoint also writes U_{j+1} = U~/beta
-    nvec_io = {"fused_fwd": 3, "fused_adj": 4, "gemm": 2}[kind]
+    # src (alpha U_j or beta V_j), the output, and the normalised input written while it
+    # is staged (the adjoint: U_{j+1} = U~/beta; the forward, which carries the previous
+    # step's LSQR update: V_j = V~/alpha, in all but the first step)
+    nvec_io = {"fused_fwd": 4, "fused_adj": 4, "gemm": 2}[kind]
     kbytes = p * n * n * bg + nvec_io * N * 4
     peak_f = MFMA_PEAK_TFLOPS[args.gemm]
     ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
