@@ -213,7 +213,8 @@ int dctk_arnoldi_step(dctk_ctx ctx, dctk_krylov ws);
 int dctk_krylov_read(dctk_ctx ctx, dctk_krylov ws, double* alpha, double* beta_or_H, int* info);
 /* Device pointer to basis vector j (0-based) of basis `which`
  * (0 = U for GKB / V for Arnoldi, 1 = V for GKB), or to the LSQR iterate X
- * (which = 2) and search direction W (which = 3).  Owned by the workspace. */
+ * (which = 2) and search direction W (which = 3) -- formed by dctk_gkb_step
+ * and by solves with lambda == 0 only.  Owned by the workspace. */
 int dctk_krylov_basis(dctk_krylov ws, int which, int j, void** ptr);
 
 /* Enqueues a copy of the vector named by (which, j) as in dctk_krylov_basis
@@ -245,9 +246,13 @@ typedef struct {
  * Golub-Kahan steps with the LSQR recurrence (X_0 = 0).  lambda == 0 returns
  * the LSQR iterate of Algorithm 6; otherwise X = V_k (*) y_lambda with y the
  * projected Tikhonov solution of eq. (normeq2) (lambda > 0 fixed, < 0 chosen
- * by GCV), computed in FP64 on the device.  ws must be a DCTK_KRYLOV_GKB
- * workspace of op.  C: p x n1 x s, X (output): p x n2 x s.  Synchronises
- * once to fill info (may be NULL). */
+ * by GCV), computed in FP64 on the device.  With lambda != 0 the LSQR iterate
+ * and search direction (dctk_krylov_basis which = 2, 3) are not formed, and
+ * with no reorthogonalisation and both products fused each step's LSQR
+ * update runs inside the next forward product (same recurrence, two
+ * launches per step).  ws must be a DCTK_KRYLOV_GKB workspace of op.
+ * C: p x n1 x s, X (output): p x n2 x s.  Synchronises once to fill info
+ * (may be NULL). */
 int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X,
                         const dctk_solve_opts* opts, dctk_solve_info* info);
 /* DC-GMRES(m) with Tikhonov on every cycle (Algorithm 3), m = opts->k_max,
