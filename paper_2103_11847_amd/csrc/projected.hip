@@ -330,6 +330,10 @@ __device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock
   const int npairs = cEven / 2;
   const int grp = lane >> 3, l8 = lane & 7;
   const int pi = wave * 8 + grp;
+  // positions of this group's pair and their (pos - 1 + rr) mod (cEven - 1),
+  // advanced by one per round (a sweep of cEven - 1 rounds returns them)
+  const int pa = pi, pb = cEven - 1 - pi;
+  int ma = pa > 0 ? pa - 1 : 0, mb = pb > 0 ? pb - 1 : 0;
   // rotate while |g_p . g_q| > tol |g_p| |g_q|; below a few ulps per row the
   // columns are orthogonal to working precision
   const double tolJ = DBL_EPSILON * (double)rows;
@@ -344,16 +348,12 @@ __device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock
         __syncthreads();
         continue;
       }
-      int p = 0, q = 0;
-      bool valid = pi < npairs;
-      if (valid) {
-        const int pa = pi, pb = cEven - 1 - pi;
-        const int ia = (pa == 0) ? 0 : 1 + ((pa - 1 + rr) % (cEven - 1));
-        const int ib = (pb == 0) ? 0 : 1 + ((pb - 1 + rr) % (cEven - 1));
-        p = ia < ib ? ia : ib;
-        q = ia < ib ? ib : ia;
-        valid = q < k;  // the dummy column of an odd k
-      }
+      const int ia = pa == 0 ? 0 : 1 + ma, ib = pb == 0 ? 0 : 1 + mb;
+      ma = ma + 1 == cEven - 1 ? 0 : ma + 1;
+      mb = mb + 1 == cEven - 1 ? 0 : mb + 1;
+      const bool live = pi < npairs;
+      const int p = live ? min(ia, ib) : 0, q = live ? max(ia, ib) : 0;
+      const bool valid = live && q < k;  // the dummy column of an odd k
       // every lane takes part in the group reductions (zeros when idle); the
       // bidiagonal case needs no V (y comes from the damped recurrence below)
       if (bidiag) {
