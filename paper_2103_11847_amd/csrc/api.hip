@@ -230,7 +230,7 @@ int dctk_tube_inv(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p
 // ---- operators -------------------------------------------------------------------
 static void op_free(dctk_op op) {
   if (!op) return;
-  void* ptrs[] = {op->Ah, op->Bh, op->Gd, op->Gf, op->xh, op->th, op->ch};
+  void* ptrs[] = {op->Ah, op->AhT, op->Bh, op->Gd, op->Gf, op->xh, op->th, op->ch};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete op;
@@ -272,6 +272,10 @@ int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1
   DCTK_TRY(hipMemcpy(op->Gd, Gd.data(), sizeof(double) * 4 * pp, hipMemcpyHostToDevice));
   DCTK_TRY(hipMemcpy(op->Gf, Gf.data(), sizeof(float) * 4 * pp, hipMemcpyHostToDevice));
   DCTK_TRY(hipMalloc(&op->Ah, ge * (size_t)(p * n1 * n2)));
+  // 16-bit fused products read A~ with the contraction index contiguous in
+  // both directions: keep the transposed slices for the adjoint
+  if ((gemm_dtype == DCTK_BF16 || gemm_dtype == DCTK_F16) && fused_eligible(op))
+    DCTK_TRY(hipMalloc(&op->AhT, ge * (size_t)(p * n1 * n2)));
   if (op->two_sided) DCTK_TRY(hipMalloc(&op->Bh, ge * (size_t)(p * s * s)));
   DCTK_TRY(hipMalloc(&op->xh, ge * (size_t)(p * nmax * s)));
   if (op->two_sided) DCTK_TRY(hipMalloc(&op->th, ge * (size_t)(p * nmax * s)));
@@ -291,6 +295,7 @@ int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1
   } else {
     DCTK_TRY(DCTK_TUBE_F64(A, tmp, n1 * n2));
     DCTK_TRY(launch_cast(ctx, p * n1 * n2, tmp, gemm_dtype, op->Ah));
+    if (op->AhT) DCTK_TRY(launch_cast_t(ctx, p, n1, n2, tmp, gemm_dtype, op->AhT));
     if (op->two_sided) {
       DCTK_TRY(DCTK_TUBE_F64(B, tmp, s * s));
       DCTK_TRY(launch_cast(ctx, p * s * s, tmp, gemm_dtype, op->Bh));

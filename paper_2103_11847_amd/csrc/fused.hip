@@ -50,15 +50,21 @@ __device__ inline void xcd_tile(const VBlock& vb, bool grouped, int gx, int gy, 
 }
 
 // EXACT: p == PMAX (no slice guards); otherwise p <= PMAX at run time.
-template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA>
+// The A~ operand always has its contraction index contiguous in memory: the
+// forward product reads the slices of A~, the adjoint the transposed copy the
+// operator keeps for 16-bit GEMM types, so both stage 16-byte rows of 8
+// consecutive k.  VA: those rows are loaded as one 16-byte vector (K and the
+// strides multiples of 8, 16-byte aligned base); else element by element.
+template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool VA>
 __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, const VBlock vb, const bool grouped) {
   typedef Mfma<TI> MF;
   typedef typename MF::acc_t acc_t;
   typedef typename MF::frag_t frag_t;
   constexpr int KSTEP = MF::KSTEP;
+  static_assert(sizeof(TI) == 2 && MF::EPL == 8, "16-bit MFMA operands");
   static_assert(BK % KSTEP == 0, "BK");
   constexpr int BKT = BK * WK;                // contraction chunk staged per iteration
-  constexpr int PAD = 16 / (int)sizeof(TI);   // 16-byte row padding
+  constexpr int PAD = 8;                      // 16-byte row padding
   constexpr int LD = BKT + PAD;
   constexpr int WGM = (WK == 1) ? 2 : 1;      // waves along M / N
   constexpr int WGN = (WK == 1) ? 2 : 1;
@@ -66,9 +72,14 @@ __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, con
   constexpr int FM = WM / 16, FN = WN / 16;
   static_assert(WK == 1 || WK == 4, "WK");
   static_assert(FM >= 1 && FN >= 1, "tile");
+  static_assert(BKT % 8 == 0, "chunk");
 
-  __shared__ __attribute__((aligned(16))) TI As[PMAX * BM * LD];
-  __shared__ __attribute__((aligned(16))) TI Bs[PMAX * BN * LD];
+  // both operands as [slice][row][k] with k contiguous: each lane's MFMA
+  // operand (8 consecutive k of one row) is one 16-byte LDS read
+  // (one buffer, reused by the cross-wave reduction)
+  __shared__ __attribute__((aligned(16))) TI smem[PMAX * (BM + BN) * LD];
+  TI* const As = smem;
+  TI* const Bs = smem + PMAX * BM * LD;
   __shared__ TV sGin[PMAX * PMAX], sGout[PMAX * PMAX];
   __shared__ double sh[kShCtl];
 
@@ -82,11 +93,16 @@ __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, con
   const TV gin_r = ((const TV*)fa.Gin)[gown ? tid : 0];
   const TV gout_r = ((const TV*)fa.Gout)[gown ? tid : 0];
 
+  // offsets are 32-bit from the base pointers (the host checks that every
+  // tensor has < 2^31 elements)
   const int M = fa.M, N = fa.N, K = fa.K;
-  const int m0 = vb.y * BM, n0 = vb.x * BN;
+  const int sA = (int)fa.sA, lda = (int)fa.lda;
+  int tx, ty;
+  xcd_tile(vb, grouped, fa.gx, fa.gy, tx, ty);
+  const int m0 = ty * BM, n0 = tx * BN;
   const TI* A = (const TI*)fa.A;
   const TV* X = (const TV*)fa.X;
-  TV* xnorm = (vb.y == 0) ? (TV*)fa.xnorm : nullptr;
+  TV* xnorm = (ty == 0) ? (TV*)fa.xnorm : nullptr;
 
   const int wk = (WK == 1) ? 0 : wave;
   const int wmn = (WK == 1) ? wave : 0;
@@ -104,79 +120,103 @@ __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, con
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[k][i][j][r] = (acc_t)0;
 
-  // Staging: every thread owns A_PER elements of the A~ tiles and X_PER tube
-  // positions of the X tile per chunk; all global loads of the next chunk are
-  // issued into registers before the current chunk is multiplied.
-  constexpr int A_TOT = PMAX * BM * BKT, X_TOT = BKT * BN;
-  constexpr int A_PER = (A_TOT + 255) / 256, X_PER = (X_TOT + 255) / 256;
-  TI ra[A_PER];
-  TV rx[X_PER][PMAX];
+  // Staging units of 8 consecutive k: a row of one A~ slice, or one column n
+  // of X across all p tubes (8 x p loads, coalesced along n across lanes, then
+  // transformed, rounded and written to LDS as p 16-byte rows).  All global
+  // loads of the next chunk are issued into registers before the current
+  // chunk is multiplied.
+  struct H8 { TI v[8]; };
+  constexpr int KG = BKT / 8;
+  constexpr int A_UN = PMAX * BM * KG, X_UN = KG * BN;
+  constexpr int A_PER = (A_UN + 255) / 256, X_PER = (X_UN + 255) / 256;
+  uint4 ra[A_PER];
+  TV rx[X_PER][8][PMAX];
   TV sc = (TV)1;  // input scale, set by the control block before the first store
   auto load_chunk = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < A_PER; ++u) {
       const int idx = tid + u * 256;
-      const int k = idx / (BM * BKT);
-      const int rem = idx - k * (BM * BKT);
-      int r, kk;
-      if (!TA) { r = rem / BKT; kk = rem - r * BKT; }
-      else { kk = rem / BM; r = rem - kk * BM; }
-      const int gm = m0 + r, gk = k0 + kk;
+      const int k = idx / (BM * KG);
+      const int rem = idx - k * (BM * KG);
+      const int r = rem / KG, kg = rem - r * KG;
+      const int gm = m0 + r, gk = k0 + kg * 8;
       // clamped address + select: every load is issued, none is out of bounds
-      const bool ok = (A_TOT % 256 == 0 || idx < A_TOT) && k < p && gm < M && gk < K;
-      const int64_t off = ok ? (int64_t)k * fa.sA + (TA ? (int64_t)gk * fa.lda + gm : (int64_t)gm * fa.lda + gk) : 0;
-      const TI v = A[off];
-      ra[u] = ok ? v : (TI)0;
+      const bool ok = (A_UN % 256 == 0 || idx < A_UN) && k < p && gm < M && gk < K;
+      const int off = ok ? k * sA + gm * lda + gk : 0;
+      if constexpr (VA) {
+        const uint4 v = *reinterpret_cast<const uint4*>(A + off);
+        ra[u] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+      } else {
+        H8 h;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const bool oki = ok && gk + i < K;
+          const TI v = A[oki ? off + i : 0];
+          h.v[i] = oki ? v : (TI)0;
+        }
+        ra[u] = __builtin_bit_cast(uint4, h);
+      }
     }
 #pragma unroll
     for (int u = 0; u < X_PER; ++u) {
       const int idx = tid + u * 256;
-      const int kk = idx / BN, n = idx - kk * BN;
-      const int gk = k0 + kk, gn = n0 + n;
-      const bool in = (X_TOT % 256 == 0 || idx < X_TOT) && gk < K && gn < N;
+      const int kg = idx / BN, n = idx - kg * BN;
+      const int gk = k0 + kg * 8, gn = n0 + n;
+      const bool in = (X_UN % 256 == 0 || idx < X_UN) && gn < N;
 #pragma unroll
-      for (int t = 0; t < PMAX; ++t) {
-        const bool ok = in && t < p;
-        const TV v = X[ok ? ((int64_t)t * K + gk) * N + gn : 0];
-        rx[u][t] = ok ? v : (TV)0;
-      }
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int t = 0; t < PMAX; ++t) {
+          const bool ok = in && t < p && gk + i < K;
+          const TV v = X[ok ? (t * K + gk + i) * N + gn : 0];
+          rx[u][i][t] = ok ? v : (TV)0;
+        }
     }
   };
   auto store_chunk = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < A_PER; ++u) {
       const int idx = tid + u * 256;
-      if (A_TOT % 256 == 0 || idx < A_TOT) {
-        const int k = idx / (BM * BKT);
-        const int rem = idx - k * (BM * BKT);
-        int r, kk;
-        if (!TA) { r = rem / BKT; kk = rem - r * BKT; }
-        else { kk = rem / BM; r = rem - kk * BM; }
-        As[(k * BM + r) * LD + kk] = ra[u];
+      if (A_UN % 256 == 0 || idx < A_UN) {
+        const int k = idx / (BM * KG);
+        const int rem = idx - k * (BM * KG);
+        const int r = rem / KG, kg = rem - r * KG;
+        *reinterpret_cast<uint4*>(&As[(k * BM + r) * LD + kg * 8]) = ra[u];
       }
     }
 #pragma unroll
     for (int u = 0; u < X_PER; ++u) {
       const int idx = tid + u * 256;
-      if (X_TOT % 256 == 0 || idx < X_TOT) {
-        const int kk = idx / BN, n = idx - kk * BN;
-        const int gk = k0 + kk, gn = n0 + n;
-        TV xv[PMAX];
+      if (X_UN % 256 == 0 || idx < X_UN) {
+        const int kg = idx / BN, n = idx - kg * BN;
+        const int gk = k0 + kg * 8, gn = n0 + n;
+        TV xv[8][PMAX];
 #pragma unroll
-        for (int t = 0; t < PMAX; ++t) xv[t] = sc * rx[u][t];
-        if (xnorm != nullptr && gk < K && gn < N) {
+        for (int i = 0; i < 8; ++i)
 #pragma unroll
-          for (int t = 0; t < PMAX; ++t)
-            if (t < p) xnorm[((int64_t)t * K + gk) * N + gn] = xv[t];
+          for (int t = 0; t < PMAX; ++t) xv[i][t] = sc * rx[u][i][t];
+        if (xnorm != nullptr && gn < N) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (gk + i < K) {
+#pragma unroll
+              for (int t = 0; t < PMAX; ++t)
+                if (t < p) xnorm[(t * K + gk + i) * N + gn] = xv[i][t];
+            }
         }
 #pragma unroll
         for (int k = 0; k < PMAX; ++k) {
           if (k < p) {
-            TV h = (TV)0;
+            H8 h;
 #pragma unroll
-            for (int t = 0; t < PMAX; ++t)
-              if (t < p) h += sGin[k * p + t] * xv[t];
-            Bs[(k * BN + n) * LD + kk] = cvt<TI, TV>(h);
+            for (int i = 0; i < 8; ++i) {
+              TV s = (TV)0;
+#pragma unroll
+              for (int t = 0; t < PMAX; ++t)
+                if (t < p) s += sGin[k * p + t] * xv[i][t];
+              h.v[i] = cvt<TI, TV>(s);
+            }
+            *reinterpret_cast<uint4*>(&Bs[(k * BN + n) * LD + kg * 8]) = __builtin_bit_cast(uint4, h);
           }
         }
       }
@@ -215,87 +255,118 @@ __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, con
     }
   }
 
-  // split contraction: sum the four waves' accumulators (wave 0 keeps the result)
-  if constexpr (WK == 4) {
-    constexpr int SLOT = 64 * 4;  // accumulators of one slice of one wave
-    acc_t* red = reinterpret_cast<acc_t*>(As);
-    constexpr int CAP = (int)((sizeof(TI) * PMAX * BM * LD) / (sizeof(acc_t) * 3 * SLOT));
-    constexpr int PER = CAP < 1 ? 1 : (CAP > PMAX ? PMAX : CAP);
-    static_assert(CAP >= 1, "LDS too small for the cross-wave reduction");
-#pragma unroll
-    for (int k0 = 0; k0 < PMAX; k0 += PER) {
-      __syncthreads();
-      if (wave > 0) {
-#pragma unroll
-        for (int kk = 0; kk < PER; ++kk) {
-          if (k0 + kk < PMAX) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) red[((wave - 1) * PER + kk) * SLOT + lane * 4 + r] = acc[k0 + kk][0][0][r];
-          }
-        }
-      }
-      __syncthreads();
-      if (wave == 0) {
-#pragma unroll
-        for (int kk = 0; kk < PER; ++kk) {
-          if (k0 + kk < PMAX) {
-#pragma unroll
-            for (int w = 0; w < 3; ++w)
-#pragma unroll
-              for (int r = 0; r < 4; ++r) acc[k0 + kk][0][0][r] += red[(w * PER + kk) * SLOT + lane * 4 + r];
-          }
-        }
-      }
-    }
-  }
-
-  // epilogue: inverse transform across slices, a/b/src, partial sums of squares
+  // Epilogue.  Output element (i, j, r) of this lane: row m0 + wm WM + 16 i +
+  // 4 (lane / 16) + r, column n0 + wn WN + 16 j + lane % 16.  With a split
+  // contraction (WK = 4) the four waves' partial accumulators are summed
+  // through LDS and wave w finishes register r = w, so all four waves share
+  // the epilogue.
+  constexpr int RN = (WK == 4) ? 1 : 4;  // accumulator registers finished by this wave
+  auto out_row = [&](int i, int r) { return m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r; };
+  const int rbase = (WK == 4) ? wave : 0;
   const TV a = (TV)a_d, b = (TV)b_d;
   const TV* src = (const TV*)fa.src;
   TV* Y = (TV*)fa.Y;
-  double sq = 0.0;
-  if (WK == 1 || wave == 0) {
+  // prefetch the epilogue's src values (independent of the accumulators).  src
+  // is null whenever b = 0, so the loads are issued only when both are set;
+  // inside, out-of-range positions load element 0 of the (non-null) src.
+  TV sv[FM][FN][RN][PMAX];
+  const bool use_src = src != nullptr && b != (TV)0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int rr = 0; rr < RN; ++rr)
+#pragma unroll
+        for (int t = 0; t < PMAX; ++t) sv[i][j][rr][t] = (TV)0;
+  if (use_src) {
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int col = n0 + wn * WN + j * 16 + (lane & 15);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = m0 + wm * WM + i * 16 + (MF::ROWS_STRIDED ? (lane >> 4) + 4 * r : (lane >> 4) * 4 + r);
-          if (row < M && col < N) {
+        for (int rr = 0; rr < RN; ++rr) {
+          const int row = out_row(i, rbase + rr);
 #pragma unroll
-            for (int t = 0; t < PMAX; ++t) {
-              if (t >= p) break;
-              TV y = (TV)0;
-#pragma unroll
-              for (int k = 0; k < PMAX; ++k)
-                if (k < p) y += sGout[t * p + k] * (TV)acc[k][i][j][r];
-              const int64_t o = ((int64_t)t * M + row) * N + col;
-              TV v = a * y;
-              if (b != (TV)0) v += b * src[o];
-              Y[o] = v;
-              sq += (double)v * (double)v;
-            }
+          for (int t = 0; t < PMAX; ++t) {
+            const bool ok = t < p && row < M && col < N;
+            const TV v = src[ok ? (t * M + row) * N + col : 0];
+            sv[i][j][rr][t] = ok ? v : (TV)0;
           }
         }
       }
   }
+
+  TV accf[PMAX][FM][FN][RN];
+  if constexpr (WK == 4) {
+    constexpr int SLOT = 64 * 4;  // one slice of one wave: 64 lanes x 4 registers
+    static_assert(sizeof(smem) >= sizeof(acc_t) * 4 * PMAX * SLOT, "LDS too small for the cross-wave reduction");
+    acc_t* red = reinterpret_cast<acc_t*>(smem);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(wave * PMAX + k) * SLOT + r * 64 + lane] = acc[k][0][0][r];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      acc_t v = (acc_t)0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) v += red[(w * PMAX + k) * SLOT + wave * 64 + lane];
+      accf[k][0][0][0] = (TV)v;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accf[k][i][j][r] = (TV)acc[k][i][j][r];
+  }
+
+  double sq = 0.0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * WN + j * 16 + (lane & 15);
+#pragma unroll
+      for (int rr = 0; rr < RN; ++rr) {
+        const int row = out_row(i, rbase + rr);
+        if (row < M && col < N) {
+#pragma unroll
+          for (int t = 0; t < PMAX; ++t) {
+            if (t >= p) break;
+            TV y = (TV)0;
+#pragma unroll
+            for (int k = 0; k < PMAX; ++k)
+              if (k < p) y += sGout[t * p + k] * accf[k][i][j][rr];
+            const TV v = a * y + b * sv[i][j][rr][t];
+            Y[(t * M + row) * N + col] = v;
+            sq += (double)v * (double)v;
+          }
+        }
+      }
+    }
   if (fa.ctl.part_out != nullptr) {
-    // one partial per wave (no block-wide exchange), in tile order
+    // one partial per wave (no block-wide exchange), by tile: the same order
+    // under any tile mapping
     const double tot = wave_sum(sq);
-    if (lane == 0) fa.ctl.part_out[(vb.y * fa.gx + vb.x) * 4 + wave] = tot;
+    if (lane == 0) fa.ctl.part_out[(ty * fa.gx + tx) * 4 + wave] = tot;
   }
 }
 
-template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool TA, bool GROUPED>
+template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool VA, bool GROUPED>
 __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const FusedArgs* grp, const int4* bmap) {
   if constexpr (!GROUPED) {
-    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, TA>(fa_, hw_block(), false);
+    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, VA>(fa_, hw_block(), false);
   } else {
     VBlock vb;
     const FusedArgs g = group_args(grp, bmap, vb);
-    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, TA>(g, vb, true);
+    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, VA>(g, vb, true);
   }
 }
 
@@ -667,40 +738,43 @@ static hipError_t launch_fused_mn(const FusedLaunch& L, const FusedArgs& fa, int
 }
 
 template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK>
-static hipError_t launch_fused_cfg(const FusedLaunch& L, const FusedArgs& fa, int ta, int* nblocks_out) {
+static hipError_t launch_fused_cfg(const FusedLaunch& L, const FusedArgs& fa, bool va, int* nblocks_out) {
   dim3 grid((unsigned)((fa.N + BN - 1) / BN), (unsigned)((fa.M + BM - 1) / BM));
   // one norm partial per wave (256 threads: 4 waves)
   if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y * 4);
   if ((int64_t)grid.x * grid.y * 4 > kNormParts && fa.ctl.part_out != nullptr) return hipErrorInvalidConfiguration;
-  if (ta) return launch_kernel(L.ctx, L.s, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true, false>, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true, true>, grid, 256, 0, fa, L.e0, L.e1);
+  if (va) return launch_kernel(L.ctx, L.s, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true, false>, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, true, true>, grid, 256, 0, fa, L.e0, L.e1);
   return launch_kernel(L.ctx, L.s, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false, false>, cprod_fused_kernel<TI, TV, PMAX, EXACT, BM, BN, WK, BK, false, true>, grid, 256, 0, fa, L.e0, L.e1);
 }
 
 // Tile choice: 16x16 with a split contraction while 32x32 tiles would not
-// cover the CUs, then 32x32, then 64x64 (FP64 and p > 4 stay at 32x32 to
-// bound the accumulator registers).
+// cover the CUs, then 32x32, then 64x64 (p > 4 stays at 32x32, also under a
+// tuned 64, to bound the registers).  Chunks: the whole 256-long contraction of the
+// colour and batch shapes in one staged chunk of 16x16 tiles (p <= 4), LDS
+// under ~85 KB everywhere.
 template <typename TI, typename TV, int PMAX, bool EXACT>
-static hipError_t launch_fused_p(const FusedLaunch& L, const FusedArgs& fa, int ta, int* nblocks_out) {
-  constexpr int KS = Mfma<TI>::KSTEP;
-  // contraction chunk per wave: keep each LDS operand buffer near 16-20 KB
-  constexpr int BK16 = (KS == 32) ? 32 : (sizeof(TI) == 8 ? (PMAX > 4 ? 4 : 8) : (PMAX > 4 ? 8 : 16));
-  constexpr int BK32 = (KS == 32) ? 32 : (sizeof(TI) == 8 ? (PMAX > 4 ? 4 : 8) : 16);
-  constexpr int BK64 = (KS == 32) ? 32 : (PMAX > 4 ? 8 : 16);
+static hipError_t launch_fused_p(const FusedLaunch& L, const FusedArgs& fa, bool va, int* nblocks_out) {
+  static_assert(Mfma<TI>::KSTEP == 32, "16-bit MFMA");
+  constexpr int BK16 = PMAX > 4 ? 32 : 64;
+  constexpr int BK32 = 64;
+  constexpr int BK64 = 64;
   const int64_t t32 = (int64_t)((fa.M + 31) / 32) * ((fa.N + 31) / 32);
   const int64_t t64 = (int64_t)((fa.M + 63) / 64) * ((fa.N + 63) / 64);
   const int ncu = num_cus();
   if (L.tile == 16 || (L.tile == 0 && t32 < ncu))
-    return launch_fused_cfg<TI, TV, PMAX, EXACT, 16, 16, 4, BK16>(L, fa, ta, nblocks_out);
-  if (L.tile == 32 || (L.tile == 0 && (t64 < ncu || sizeof(TI) == 8 || PMAX > 4)) || t64 > kRedBlocks)
-    return launch_fused_cfg<TI, TV, PMAX, EXACT, 32, 32, 1, BK32>(L, fa, ta, nblocks_out);
-  return launch_fused_cfg<TI, TV, PMAX, EXACT, 64, 64, 1, BK64>(L, fa, ta, nblocks_out);
+    return launch_fused_cfg<TI, TV, PMAX, EXACT, 16, 16, 4, BK16>(L, fa, va, nblocks_out);
+  if (PMAX > 4 || L.tile == 32 || (L.tile == 0 && t64 < ncu) || t64 > kRedBlocks)
+    return launch_fused_cfg<TI, TV, PMAX, EXACT, 32, 32, 1, BK32>(L, fa, va, nblocks_out);
+  if constexpr (PMAX <= 4) return launch_fused_cfg<TI, TV, PMAX, EXACT, 64, 64, 1, BK64>(L, fa, va, nblocks_out);
+  return hipErrorInvalidValue;
 }
 
 template <typename TI, typename TV>
-static hipError_t launch_fused_t(const FusedLaunch& L, const FusedArgs& fa, int ta, int* nblocks_out) {
-  if (fa.p == 3) return launch_fused_p<TI, TV, 3, true>(L, fa, ta, nblocks_out);  // colour images
-  if (fa.p <= 4) return launch_fused_p<TI, TV, 4, false>(L, fa, ta, nblocks_out);
-  return launch_fused_p<TI, TV, 8, false>(L, fa, ta, nblocks_out);
+static hipError_t launch_fused_t(const FusedLaunch& L, const FusedArgs& fa, int* nblocks_out) {
+  const bool va = fa.K % 8 == 0 && fa.lda % 8 == 0 && fa.sA % 8 == 0 && ((uintptr_t)fa.A % 16) == 0;
+  if (fa.p == 3) return launch_fused_p<TI, TV, 3, true>(L, fa, va, nblocks_out);  // colour images
+  if (fa.p <= 4) return launch_fused_p<TI, TV, 4, false>(L, fa, va, nblocks_out);
+  return launch_fused_p<TI, TV, 8, false>(L, fa, va, nblocks_out);
 }
 
 hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,
@@ -713,6 +787,13 @@ hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, v
   fa.lda = op->n2;
   fa.sA = op->n1 * op->n2;
   fa.A = op->Ah;
+  const bool half = op->gemm_dtype == DCTK_BF16 || op->gemm_dtype == DCTK_F16;
+  if (half && adjoint) {
+    // 16-bit operands: the adjoint reads the transposed slices (n2 x n1)
+    if (op->AhT == nullptr) return hipErrorInvalidValue;
+    fa.A = op->AhT;
+    fa.lda = op->n1;
+  }
   fa.X = X;
   fa.Y = Y;
   fa.src = src;
@@ -732,8 +813,8 @@ hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, v
   switch (op->gemm_dtype) {
     case DCTK_F64: return launch_fused_mn<double>(L, fa, adjoint, nblocks_out);
     case DCTK_F32: return launch_fused_mn<float>(L, fa, adjoint, nblocks_out);
-    case DCTK_BF16: return launch_fused_t<bf16_t, float>(L, fa, adjoint, nblocks_out);
-    case DCTK_F16: return launch_fused_t<f16_t, float>(L, fa, adjoint, nblocks_out);
+    case DCTK_BF16: return launch_fused_t<bf16_t, float>(L, fa, nblocks_out);
+    case DCTK_F16: return launch_fused_t<f16_t, float>(L, fa, nblocks_out);
     default: return hipErrorInvalidValue;
   }
 }

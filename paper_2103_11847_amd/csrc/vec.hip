@@ -549,6 +549,18 @@ __global__ __launch_bounds__(kThreads) void k_cast(int64_t n, const double* in, 
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) out[e] = cvt<TO, double>(in[e]);
 }
 
+// out[k][c][r] = in[k][r][c] for p slices of rows x cols (operator setup only)
+template <typename TO>
+__global__ __launch_bounds__(kThreads) void k_cast_t(int64_t p, int64_t rows, int64_t cols, const double* in, TO* out) {
+  const int64_t n = p * rows * cols, rc = rows * cols;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const int64_t k = e / rc, rem = e - k * rc;
+    const int64_t c = rem / rows, r = rem - c * rows;
+    out[e] = cvt<TO, double>(in[k * rc + r * cols + c]);
+  }
+}
+
 // full = 1: clear everything (new solve); full = 0: start a new GMRES cycle (unless halted)
 __device__ __forceinline__ void k_state_reset_body(const ResetArgs& a, const VBlock vb, const bool grouped) {
   KState* st = a.st;
@@ -786,6 +798,18 @@ hipError_t launch_cast(dctk_ctx ctx, int64_t n, const double* in, int out_dtype,
     case DCTK_F32: hipLaunchKernelGGL(k_cast<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, in, (float*)out); break;
     case DCTK_BF16: hipLaunchKernelGGL(k_cast<bf16_t>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, in, (bf16_t*)out); break;
     case DCTK_F16: hipLaunchKernelGGL(k_cast<f16_t>, dim3(grid), dim3(kThreads), 0, ctx->stream, n, in, (f16_t*)out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_t(dctk_ctx ctx, int64_t p, int64_t rows, int64_t cols, const double* in, int out_dtype,
+                         void* out) {
+  if (recording(ctx)) return hipErrorNotSupported;
+  unsigned grid = grid_for(p * rows * cols * 4);
+  switch (out_dtype) {
+    case DCTK_BF16: hipLaunchKernelGGL(k_cast_t<bf16_t>, dim3(grid), dim3(kThreads), 0, ctx->stream, p, rows, cols, in, (bf16_t*)out); break;
+    case DCTK_F16: hipLaunchKernelGGL(k_cast_t<f16_t>, dim3(grid), dim3(kThreads), 0, ctx->stream, p, rows, cols, in, (f16_t*)out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
