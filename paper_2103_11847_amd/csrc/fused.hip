@@ -53,9 +53,10 @@ __device__ inline void xcd_tile(const VBlock& vb, bool grouped, int gx, int gy, 
 // The A~ operand always has its contraction index contiguous in memory: the
 // forward product reads the slices of A~, the adjoint the transposed copy the
 // operator keeps for 16-bit GEMM types, so both stage 16-byte rows of 8
-// consecutive k.  VA: those rows are loaded as one 16-byte vector (K and the
-// strides multiples of 8, 16-byte aligned base); else element by element.
-template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool VA>
+// consecutive k.  VEC: those rows, and X along n, move as 16-byte vectors (K
+// and the A~ strides multiples of 8, N a multiple of 4, 16-byte aligned
+// bases); else element by element.
+template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool VEC>
 __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, const VBlock vb, const bool grouped) {
   typedef Mfma<TI> MF;
   typedef typename MF::acc_t acc_t;
@@ -120,17 +121,18 @@ __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, con
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[k][i][j][r] = (acc_t)0;
 
-  // Staging units of 8 consecutive k: a row of one A~ slice, or one column n
-  // of X across all p tubes (8 x p loads, coalesced along n across lanes, then
-  // transformed, rounded and written to LDS as p 16-byte rows).  All global
-  // loads of the next chunk are issued into registers before the current
-  // chunk is multiplied.
-  struct H8 { TI v[8]; };
+  // Staging.  A~: units of 8 consecutive k of one row of one slice (one
+  // 16-byte row segment).  X: units of 4 consecutive n x 4 consecutive k of
+  // all p tubes (16-byte loads along n, coalesced across lanes), transformed,
+  // rounded and written to LDS as 8-byte row segments of the p slices.  All
+  // global loads of the next chunk are issued into registers before the
+  // current chunk is multiplied.
+  struct H4 { TI v[4]; };
   constexpr int KG = BKT / 8;
-  constexpr int A_UN = PMAX * BM * KG, X_UN = KG * BN;
+  constexpr int A_UN = PMAX * BM * KG, X_UN = (BKT / 4) * (BN / 4);
   constexpr int A_PER = (A_UN + 255) / 256, X_PER = (X_UN + 255) / 256;
   uint4 ra[A_PER];
-  TV rx[X_PER][8][PMAX];
+  TV rx[X_PER][4][PMAX][4];
   TV sc = (TV)1;  // input scale, set by the control block before the first store
   auto load_chunk = [&](int k0) {
 #pragma unroll
@@ -143,11 +145,11 @@ __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, con
       // clamped address + select: every load is issued, none is out of bounds
       const bool ok = (A_UN % 256 == 0 || idx < A_UN) && k < p && gm < M && gk < K;
       const int off = ok ? k * sA + gm * lda + gk : 0;
-      if constexpr (VA) {
+      if constexpr (VEC) {
         const uint4 v = *reinterpret_cast<const uint4*>(A + off);
         ra[u] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
       } else {
-        H8 h;
+        struct { TI v[8]; } h;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const bool oki = ok && gk + i < K;
@@ -160,16 +162,29 @@ __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, con
 #pragma unroll
     for (int u = 0; u < X_PER; ++u) {
       const int idx = tid + u * 256;
-      const int kg = idx / BN, n = idx - kg * BN;
-      const int gk = k0 + kg * 8, gn = n0 + n;
+      const int kq = idx / (BN / 4), nq = idx - kq * (BN / 4);
+      const int gk = k0 + kq * 4, gn = n0 + nq * 4;
       const bool in = (X_UN % 256 == 0 || idx < X_UN) && gn < N;
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
         for (int t = 0; t < PMAX; ++t) {
-          const bool ok = in && t < p && gk + i < K;
-          const TV v = X[ok ? (t * K + gk + i) * N + gn : 0];
-          rx[u][i][t] = ok ? v : (TV)0;
+          const bool ok = in && t < p && gk + kk < K;
+          const int off = ok ? (t * K + gk + kk) * N + gn : 0;
+          if constexpr (VEC) {
+            VecIO<TV, 4>::ld(X + off, rx[u][kk][t]);
+            if (!ok) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) rx[u][kk][t][v] = (TV)0;
+            }
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const bool okv = ok && gn + v < N;
+              const TV x = X[okv ? off + v : 0];
+              rx[u][kk][t][v] = okv ? x : (TV)0;
+            }
+          }
         }
     }
   };
@@ -188,35 +203,50 @@ __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, con
     for (int u = 0; u < X_PER; ++u) {
       const int idx = tid + u * 256;
       if (X_UN % 256 == 0 || idx < X_UN) {
-        const int kg = idx / BN, n = idx - kg * BN;
-        const int gk = k0 + kg * 8, gn = n0 + n;
-        TV xv[8][PMAX];
+        const int kq = idx / (BN / 4), nq = idx - kq * (BN / 4);
+        const int gk = k0 + kq * 4, gn = n0 + nq * 4;
+        TV xv[4][PMAX][4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-          for (int t = 0; t < PMAX; ++t) xv[i][t] = sc * rx[u][i][t];
+          for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xv[kk][t][v] = sc * rx[u][kk][t][v];
         if (xnorm != nullptr && gn < N) {
 #pragma unroll
-          for (int i = 0; i < 8; ++i)
-            if (gk + i < K) {
+          for (int kk = 0; kk < 4; ++kk)
+            if (gk + kk < K) {
 #pragma unroll
-              for (int t = 0; t < PMAX; ++t)
-                if (t < p) xnorm[(t * K + gk + i) * N + gn] = xv[i][t];
+              for (int t = 0; t < PMAX; ++t) {
+                if (t < p) {
+                  TV* q = xnorm + (t * K + gk + kk) * N + gn;
+                  if constexpr (VEC) {
+                    VecIO<TV, 4>::st(q, xv[kk][t]);
+                  } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                      if (gn + v < N) q[v] = xv[kk][t][v];
+                  }
+                }
+              }
             }
         }
 #pragma unroll
         for (int k = 0; k < PMAX; ++k) {
           if (k < p) {
-            H8 h;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              TV s = (TV)0;
+            for (int v = 0; v < 4; ++v) {
+              H4 h;
 #pragma unroll
-              for (int t = 0; t < PMAX; ++t)
-                if (t < p) s += sGin[k * p + t] * xv[i][t];
-              h.v[i] = cvt<TI, TV>(s);
+              for (int kk = 0; kk < 4; ++kk) {
+                TV s = (TV)0;
+#pragma unroll
+                for (int t = 0; t < PMAX; ++t)
+                  if (t < p) s += sGin[k * p + t] * xv[kk][t][v];
+                h.v[kk] = cvt<TI, TV>(s);
+              }
+              *reinterpret_cast<uint2*>(&Bs[(k * BN + nq * 4 + v) * LD + kq * 4]) = __builtin_bit_cast(uint2, h);
             }
-            *reinterpret_cast<uint4*>(&Bs[(k * BN + n) * LD + kg * 8]) = __builtin_bit_cast(uint4, h);
           }
         }
       }
@@ -359,14 +389,14 @@ __device__ __forceinline__ void cprod_fused_kernel_body(const FusedArgs& fa, con
   }
 }
 
-template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool VA, bool GROUPED>
+template <typename TI, typename TV, int PMAX, bool EXACT, int BM, int BN, int WK, int BK, bool VEC, bool GROUPED>
 __global__ __launch_bounds__(256) void cprod_fused_kernel(FusedArgs fa_, const FusedArgs* grp, const int4* bmap) {
   if constexpr (!GROUPED) {
-    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, VA>(fa_, hw_block(), false);
+    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, VEC>(fa_, hw_block(), false);
   } else {
     VBlock vb;
     const FusedArgs g = group_args(grp, bmap, vb);
-    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, VA>(g, vb, true);
+    cprod_fused_kernel_body<TI, TV, PMAX, EXACT, BM, BN, WK, BK, VEC>(g, vb, true);
   }
 }
 
@@ -771,7 +801,9 @@ static hipError_t launch_fused_p(const FusedLaunch& L, const FusedArgs& fa, bool
 
 template <typename TI, typename TV>
 static hipError_t launch_fused_t(const FusedLaunch& L, const FusedArgs& fa, int* nblocks_out) {
-  const bool va = fa.K % 8 == 0 && fa.lda % 8 == 0 && fa.sA % 8 == 0 && ((uintptr_t)fa.A % 16) == 0;
+  const bool va = fa.K % 8 == 0 && fa.lda % 8 == 0 && fa.sA % 8 == 0 && ((uintptr_t)fa.A % 16) == 0 &&
+                  fa.N % 4 == 0 && ((uintptr_t)fa.X % 16) == 0 &&
+                  (fa.xnorm == nullptr || ((uintptr_t)fa.xnorm % 16) == 0);
   if (fa.p == 3) return launch_fused_p<TI, TV, 3, true>(L, fa, va, nblocks_out);  // colour images
   if (fa.p <= 4) return launch_fused_p<TI, TV, 4, false>(L, fa, va, nblocks_out);
   return launch_fused_p<TI, TV, 8, false>(L, fa, va, nblocks_out);
