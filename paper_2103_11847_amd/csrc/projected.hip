@@ -537,6 +537,280 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
   }
 }
 
+// ---- DC-GK projected problem without an SVD ---------------------------------
+// For the lower bidiagonal C~_k with the GCV function of the rectangular
+// projected problem (or a fixed lambda) no singular vectors are needed:
+//   * sigma_1 (which fixes the GCV grid) by multisection with Sturm counts on
+//     the Golub-Kahan form of C~_k;
+//   * GCV(lambda) = ||beta e_1 - C~ y_lambda||^2 / (1 + lambda^2 ||R^-1||_F^2)^2,
+//     where [C~; lambda I] = Q [R; 0] by the damped bidiagonal recurrence: the
+//     sum over the singular values of lambda^2 / (sigma_i^2 + lambda^2) is
+//     lambda^2 trace((C~^T C~ + lambda^2 I)^-1) = lambda^2 ||R^-1||_F^2, whose
+//     column norms follow a forward recurrence, and the residual is formed
+//     from y_lambda = R^-1 f directly (no cancellation against beta^2);
+//   * the same grid, refinement and gate as the SVD path.
+constexpr int kRecD = 12288;  // doubles of per-lambda recurrence rows (96 KB)
+constexpr int kMS = 256;      // multisection points per round
+static_assert(kRecD / (2 * kMaxK) >= 64, "a refinement pass keeps 64 lambdas' rows");
+
+// Eigenvalues below x > 0 of the Golub-Kahan tridiagonal of C~_k (order
+// 2k + 1, zero diagonal, off-diagonals alpha_1, beta_2, ..., alpha_k,
+// beta_{k+1}; eigenvalues +-sigma_i and 0): by Sylvester's law of inertia the
+// number of negative pivots of T - x I, i.e. of sign changes between
+// consecutive leading principal minors d_i = -x d_{i-1} - e_{i-1}^2 d_{i-2}.
+// No division: with x and the off-diagonals divided by a bound g of the
+// spectrum a minor grows at most twofold per step, so rescaling by powers of
+// two (exact) every eight minors keeps them in range; a zero minor counts as
+// a negative pivot (its successor then has the sign of a positive one).  e2
+// holds the squared off-diagonals in order, ig = 1 / g.
+__device__ inline int gk_count_below(double x, int k, const double* e2, double ig) {
+  const double ig2 = ig * ig;
+  x *= ig;
+  double d0 = 1.0, d1 = -x;
+  int cnt = 1;  // d1 < 0 for x > 0
+  for (int j = 0; j < k; j += 4) {
+    double ev[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ev[u] = e2[min(2 * j + u, 2 * k - 1)] * ig2;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (2 * j + u < 2 * k) {
+        const double d2 = fma(-x, d1, -ev[u] * d0);
+        cnt += ((d2 < 0.0) != (d1 < 0.0)) ? 1 : 0;
+        d0 = d1;
+        d1 = d2;
+      }
+    }
+    const double m = fmax(fabs(d0), fabs(d1));
+    const double s = m > 0x1p256 ? 0x1p-256 : (m < 0x1p-256 ? 0x1p256 : 1.0);
+    d0 *= s;
+    d1 *= s;
+  }
+  return cnt;
+}
+
+// GCV of the rectangular projected problem at lambda > 0, one thread.  Plane
+// rotations of [C~; lambda I] (the damping row into rhobar_i, then beta_{i+1}
+// below it) give R = bidiag(rho_i, theta_{i+1}) and f; with reciprocal square
+// roots, no division.  Column j of R^-1 has squared norm
+// T_j = (1 + theta_j^2 T_{j-1}) / rho_j^2.  The rows f_i / rho_i and
+// theta_{i+1} / rho_i go to q[i * ld] and w[i * ld] for the back substitution
+// y = R^-1 f, which also forms the residual rows of beta e_1 - C~ y (and
+// writes y to yout when it is not null).  Each step's operands are loaded one
+// step ahead, off the recurrence's dependency chain.
+__device__ inline double gk_gcv(double lam, int k, const double* a, const double* b, double beta, double* q,
+                                double* w, int ld, double* yout) {
+  const double l2 = lam * lam;
+  double rbar = a[0], fbar = beta, th = 0.0, tcol = 0.0, tr = 0.0;
+  double bn = b[0], an = a[min(1, k - 1)];
+  for (int i = 0; i < k; ++i) {
+    const double bc = bn, ac = an;
+    bn = b[min(i + 1, k - 1)];
+    an = a[min(i + 2, k - 1)];
+    const double x1 = fma(rbar, rbar, l2);
+    const double i1 = rsqrt(x1);
+    const double i2 = rsqrt(fma(bc, bc, x1));  // 1 / rho_i
+    const double rhat = x1 * i1;
+    const double fhat = (rbar * i1) * fbar;
+    const double c = rhat * i2, sn = bc * i2;
+    tcol = fma(th * th, tcol, 1.0) * (i2 * i2);
+    tr += tcol;
+    q[i * ld] = (c * fhat) * i2;
+    th = sn * ac;       // theta_{i+1} (unused after the last step)
+    w[i * ld] = th * i2;
+    rbar = -c * ac;
+    fbar = sn * fhat;
+  }
+  double yn = 0.0, rr = 0.0;
+  double qn = q[(k - 1) * ld], wn = 0.0, bb = b[k - 1], aa = 0.0;  // operands of step k - 1
+  for (int i = k - 1; i >= 0; --i) {
+    const double qc = qn, wc = wn, bc = bb, ac = aa;  // q_i, w_i, b_i, a_{i+1} (w, a: 0 at i = k - 1)
+    const int ip = max(i - 1, 0);
+    qn = q[ip * ld];
+    wn = w[ip * ld];
+    bb = b[ip];
+    aa = a[i];
+    const double y = fma(-wc, yn, qc);
+    const double row = fma(bc, y, ac * yn);  // row i + 1 of C~ y
+    rr = fma(row, row, rr);
+    yn = y;
+    if (yout != nullptr) yout[i] = y;
+  }
+  const double r0 = fma(-a[0], yn, beta);
+  rr = fma(r0, r0, rr);
+  const double den = fma(l2, tr, 1.0);
+  return rr / (den * den);
+}
+
+__device__ __forceinline__ void k_projected_gk_body(const ProjArgs& a, const VBlock vb, const bool grouped) {
+  KState* st = a.st;
+  const double lam_fixed = a.lam_fixed, gate = a.gate;
+  const double lam_cand = a.cand_from_state ? ld_state(&st->pred_lambda) : a.lam_cand;
+  const int k_use = a.k_use;
+  if (ld_state(&st->halt)) return;
+  __shared__ double rec[kRecD];
+  __shared__ double ab_a[kMaxK], ab_b[kMaxK], e2[2 * kMaxK];
+  __shared__ double gridv[kGrid];
+  __shared__ int wfirst[kPW];
+  __shared__ double s_lo, s_hi;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int k = st->steps;
+  if (k_use > 0 && k_use < k) k = k_use;
+  if (k > kMaxK) k = kMaxK;
+  if (tid == 0) st->gate_ok = 0.0;
+  const double beta = st->beta[0];
+  if (k <= 0) {
+    if (tid == 0) { st->lambda = 0.0; st->gcv = __builtin_nan(""); }
+    return;
+  }
+  if (tid < k) {
+    const double al = st->alpha[tid], be = st->beta[tid + 1];
+    ab_a[tid] = al;
+    ab_b[tid] = be;
+    e2[2 * tid] = al * al;
+    e2[2 * tid + 1] = be * be;
+  }
+  __syncthreads();
+
+  double lam = lam_fixed, gcv = __builtin_nan("");
+  if (lam_fixed < 0.0) {
+    // sigma_1: Gershgorin bound, then rounds of kMS evenly spaced Sturm counts
+    // (one wave per SIMD); the first point above sigma_1 (count 2k + 1) and the
+    // one before it bound the next round (eight rounds reach a few ulps)
+    if (wave == 0) {
+      double gb = 0.0;
+      for (int r = lane; r <= 2 * k; r += 64) {
+        const double el = r > 0 ? (((r - 1) & 1) ? fabs(ab_b[(r - 1) >> 1]) : fabs(ab_a[(r - 1) >> 1])) : 0.0;
+        const double er = r < 2 * k ? ((r & 1) ? fabs(ab_b[r >> 1]) : fabs(ab_a[r >> 1])) : 0.0;
+        gb = fmax(gb, el + er);
+      }
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) gb = fmax(gb, __shfl_xor(gb, m));
+      if (lane == 0) { s_lo = 0.0; s_hi = gb * (1.0 + 8.0 * DBL_EPSILON); }
+    }
+    __syncthreads();
+    for (int round = 0; round < 12; ++round) {
+      const double lo = s_lo, hi = s_hi;
+      if (!(hi - lo > 4.0 * DBL_EPSILON * hi)) break;
+      const double h = (hi - lo) / (double)(kMS + 1);
+      if (tid < kMS) {
+        const bool above = gk_count_below(lo + h * (double)(tid + 1), k, e2, 1.0 / hi) >= 2 * k + 1;
+        const unsigned long long m = __ballot(above);
+        if (lane == 0) wfirst[wave] = m ? wave * 64 + __builtin_ctzll(m) : kMS;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int j = kMS;
+        for (int w = 0; w < kMS / 64; ++w) j = min(j, wfirst[w]);
+        s_lo = j == 0 ? lo : lo + h * (double)j;
+        s_hi = j == kMS ? hi : lo + h * (double)(j + 1);
+      }
+      __syncthreads();
+    }
+    const double sig1 = 0.5 * (s_lo + s_hi);
+    if (!(sig1 > 0.0)) {
+      lam = 0.0;
+    } else {
+      // the 400-point grid, as many lambdas per pass as the row storage holds
+      // (each thread reuses its own slot: no barrier between passes)
+      const double t0 = log10(sig1) - 8.0;
+      const double dt = 8.0 / (double)(kGrid - 1);
+      const int nb = min(kGrid, kRecD / (2 * k));
+      for (int base = 0; base < kGrid; base += nb) {
+        const int i = base + tid;
+        if (tid < nb && i < kGrid)
+          gridv[i] = gk_gcv(exp10(t0 + (double)i * dt), k, ab_a, ab_b, beta, rec + tid, rec + k * nb + tid, nb, nullptr);
+      }
+      __syncthreads();
+      if (wave != 0) return;
+      // wave 0 from here: first index of the minimum (NaN counts as +inf)
+      int bi = kGrid;
+      double bv = __builtin_inf();
+      for (int i = lane; i < kGrid; i += 64) {
+        const double v = gridv[i] == gridv[i] ? gridv[i] : __builtin_inf();
+        if (bi == kGrid || v < bv) { bi = i; bv = v; }
+      }
+      first_min64(bv, bi);
+      const int ib = bi < kGrid ? bi : 0;
+      // refinement on t = log10(lambda): 64 points evenly inside [a, b] per
+      // pass (one per lane), keeping the two cells next to the first smallest
+      // value, until the bracket is narrower than 1e-10
+      double ra = t0 + (double)(ib > 0 ? ib - 1 : 0) * dt;
+      double rb = t0 + (double)(ib < kGrid - 1 ? ib + 1 : kGrid - 1) * dt;
+      double rt = __builtin_nan(""), rf = __builtin_inf();
+      for (int pass = 0; pass < 40 && (rb - ra) > 1e-10; ++pass) {
+        const double h = (rb - ra) / (double)(kRef + 1);
+        const double f = gk_gcv(exp10(ra + (double)(lane + 1) * h), k, ab_a, ab_b, beta, rec + lane,
+                                rec + k * kRef + lane, kRef, nullptr);
+        double mv = f == f ? f : __builtin_inf();
+        int mi = lane;
+        first_min64(mv, mi);
+        const double na = ra + (double)mi * h, nbr = ra + (double)(mi + 2) * h;
+        rt = ra + (double)(mi + 1) * h;
+        rf = mv;
+        ra = na;
+        rb = nbr;
+      }
+      const double gv = gridv[ib];
+      if (rf <= gv) { lam = exp10(rt); gcv = rf; }
+      else { lam = exp10(t0 + (double)ib * dt); gcv = gv; }
+      // a proposed lambda is kept when its GCV value is within the gate of the minimum
+      if (lam_cand > 0.0) {
+        const double fcand = gk_gcv(lam_cand, k, ab_a, ab_b, beta, rec + lane, rec + k * kRef + lane, kRef, nullptr);
+        const bool keep = fcand <= gate * gcv;
+        if (lane == 0) st->gate_ok = keep ? 1.0 : 0.0;
+        if (keep) { lam = lam_cand; gcv = fcand; }
+      }
+    }
+  }
+  if (tid != 0) return;
+  if (lam > 0.0) {
+    // y_lambda from the same rotations as the GCV values (one lane)
+    (void)gk_gcv(lam, k, ab_a, ab_b, beta, rec, rec + kMaxK, 1, st->y);
+  } else {
+    // lambda = 0 (fixed): the recurrence with square roots and guarded divisions
+    double* rho = rec;
+    double* phi = rec + kMaxK;
+    double* th = rec + 2 * kMaxK;
+    double rbar = ab_a[0], fbar = beta;
+    for (int i = 0; i < k; ++i) {
+      const double rhat = fabs(rbar);
+      const double fhat = rbar < 0.0 ? -fbar : fbar;
+      const double bn = ab_b[i];
+      const double r = sqrt(rhat * rhat + bn * bn);
+      const double c = r > 0.0 ? rhat / r : 1.0, sn = r > 0.0 ? bn / r : 0.0;
+      rho[i] = r;
+      phi[i] = c * fhat;
+      if (i + 1 < k) {
+        th[i] = sn * ab_a[i + 1];
+        rbar = -c * ab_a[i + 1];
+      }
+      fbar = sn * fhat;
+    }
+    double yn = 0.0;
+    for (int i = k - 1; i >= 0; --i) {
+      const double rhs = phi[i] - (i + 1 < k ? th[i] * yn : 0.0);
+      yn = rho[i] > 0.0 ? rhs / rho[i] : 0.0;
+      st->y[i] = yn;
+    }
+  }
+  st->lambda = lam;
+  st->gcv = gcv;
+  st->sweeps = 0.0;
+}
+
+template <bool GROUPED>
+__global__ __launch_bounds__(kPT) void k_projected_gk(ProjArgs a_, const ProjArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_projected_gk_body(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const ProjArgs g = group_args(grp, bmap, vb);
+    k_projected_gk_body(g, vb, true);
+  }
+}
+
 hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, double lambda, int k_use,
                             double lam_cand, double gate, int cand_from_state) {
   ProjArgs a{};
@@ -548,6 +822,8 @@ hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, 
   a.lam_fixed = lambda;
   a.lam_cand = lam_cand;
   a.gate = gate;
+  if (bidiag && (gcv_mode == 0 || lambda >= 0.0))
+    return launch_kernel(ctx, ctx->stream, k_projected_gk<false>, k_projected_gk<true>, dim3(1), kPT, 0, a);
   return launch_kernel(ctx, ctx->stream, k_projected<false>, k_projected<true>, dim3(1), kPT, 0, a);
 }
 
