@@ -549,44 +549,48 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
 //     column norms follow a forward recurrence, and the residual is formed
 //     from y_lambda = R^-1 f directly (no cancellation against beta^2);
 //   * the same grid, refinement and gate as the SVD path.
-constexpr int kRecD = 12288;  // doubles of per-lambda recurrence rows (96 KB)
+constexpr int kRecD = 18432;  // doubles of per-lambda recurrence rows (144 KB)
 constexpr int kMS = 256;      // multisection points per round
-static_assert(kRecD / (2 * kMaxK) >= 64, "a refinement pass keeps 64 lambdas' rows");
+constexpr int kRP = 256;      // most refinement points per pass
+static_assert(kRecD / (2 * kMaxK) >= 64, "a pass keeps at least 64 lambdas' rows");
 
 // Eigenvalues below x > 0 of the Golub-Kahan tridiagonal of C~_k (order
 // 2k + 1, zero diagonal, off-diagonals alpha_1, beta_2, ..., alpha_k,
 // beta_{k+1}; eigenvalues +-sigma_i and 0): by Sylvester's law of inertia the
 // number of negative pivots of T - x I, i.e. of sign changes between
 // consecutive leading principal minors d_i = -x d_{i-1} - e_{i-1}^2 d_{i-2}.
-// No division: with x and the off-diagonals divided by a bound g of the
-// spectrum a minor grows at most twofold per step, so rescaling by powers of
-// two (exact) every eight minors keeps them in range; a zero minor counts as
-// a negative pivot (its successor then has the sign of a positive one).  e2
-// holds the squared off-diagonals in order, ig = 1 / g.
-__device__ inline int gk_count_below(double x, int k, const double* e2, double ig) {
+// e2 holds the squared off-diagonals in order, padded with zeros to n2 (a
+// multiple of 8) entries: each zero decouples one more row, an eigenvalue 0,
+// which adds one to the count.  No division: with x and the off-diagonals
+// divided by a bound g of the spectrum (ig = 1 / g) a minor grows at most
+// twofold per step, so rescaling by powers of two (exact) every eight minors
+// keeps them in range.  Sign changes are counted from the sign bits (a zero
+// minor of either sign is followed by one that restores the count).
+__device__ inline int gk_count_below(double x, int n2, const double* e2, double ig) {
   const double ig2 = ig * ig;
   x *= ig;
   double d0 = 1.0, d1 = -x;
-  int cnt = 1;  // d1 < 0 for x > 0
-  for (int j = 0; j < k; j += 4) {
+  unsigned cnt = 1;  // d1 < 0 for x > 0
+  unsigned sg = 1;
+  for (int j = 0; j < n2; j += 8) {
     double ev[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) ev[u] = e2[min(2 * j + u, 2 * k - 1)] * ig2;
+    for (int u = 0; u < 8; ++u) ev[u] = e2[j + u] * ig2;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (2 * j + u < 2 * k) {
-        const double d2 = fma(-x, d1, -ev[u] * d0);
-        cnt += ((d2 < 0.0) != (d1 < 0.0)) ? 1 : 0;
-        d0 = d1;
-        d1 = d2;
-      }
+      const double d2 = fma(-x, d1, -ev[u] * d0);
+      const unsigned s2 = (unsigned)((unsigned long long)__double_as_longlong(d2) >> 63);
+      cnt += s2 ^ sg;
+      sg = s2;
+      d0 = d1;
+      d1 = d2;
     }
     const double m = fmax(fabs(d0), fabs(d1));
-    const double s = m > 0x1p256 ? 0x1p-256 : (m < 0x1p-256 ? 0x1p256 : 1.0);
-    d0 *= s;
-    d1 *= s;
+    const double sc = m > 0x1p256 ? 0x1p-256 : (m < 0x1p-256 ? 0x1p256 : 1.0);
+    d0 *= sc;
+    d1 *= sc;
   }
-  return cnt;
+  return (int)cnt;
 }
 
 // GCV of the rectangular projected problem at lambda > 0, one thread.  Plane
@@ -649,10 +653,11 @@ __device__ __forceinline__ void k_projected_gk_body(const ProjArgs& a, const VBl
   const int k_use = a.k_use;
   if (ld_state(&st->halt)) return;
   __shared__ double rec[kRecD];
-  __shared__ double ab_a[kMaxK], ab_b[kMaxK], e2[2 * kMaxK];
+  __shared__ double ab_a[kMaxK], ab_b[kMaxK], e2[2 * kMaxK + 8];
   __shared__ double gridv[kGrid];
+  __shared__ double refv[kRP];
   __shared__ int wfirst[kPW];
-  __shared__ double s_lo, s_hi;
+  __shared__ double s_lo, s_hi, s_ra, s_rb, s_rt, s_rf, s_fl, s_fr;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int k = st->steps;
@@ -664,20 +669,25 @@ __device__ __forceinline__ void k_projected_gk_body(const ProjArgs& a, const VBl
     if (tid == 0) { st->lambda = 0.0; st->gcv = __builtin_nan(""); }
     return;
   }
+  const int n2 = (2 * k + 7) & ~7;  // padded length of e2
   if (tid < k) {
     const double al = st->alpha[tid], be = st->beta[tid + 1];
     ab_a[tid] = al;
     ab_b[tid] = be;
     e2[2 * tid] = al * al;
     e2[2 * tid + 1] = be * be;
+  } else if (tid >= 2 * k && tid < n2) {
+    e2[tid] = 0.0;
   }
   __syncthreads();
 
   double lam = lam_fixed, gcv = __builtin_nan("");
+  bool y_done = false;
   if (lam_fixed < 0.0) {
     // sigma_1: Gershgorin bound, then rounds of kMS evenly spaced Sturm counts
-    // (one wave per SIMD); the first point above sigma_1 (count 2k + 1) and the
-    // one before it bound the next round (eight rounds reach a few ulps)
+    // (one wave per SIMD); the first point above sigma_1 (count 2k + 1, plus
+    // the padding) and the one before it bound the next round (seven rounds
+    // reach a few ulps)
     if (wave == 0) {
       double gb = 0.0;
       for (int r = lane; r <= 2 * k; r += 64) {
@@ -695,7 +705,7 @@ __device__ __forceinline__ void k_projected_gk_body(const ProjArgs& a, const VBl
       if (!(hi - lo > 4.0 * DBL_EPSILON * hi)) break;
       const double h = (hi - lo) / (double)(kMS + 1);
       if (tid < kMS) {
-        const bool above = gk_count_below(lo + h * (double)(tid + 1), k, e2, 1.0 / hi) >= 2 * k + 1;
+        const bool above = gk_count_below(lo + h * (double)(tid + 1), n2, e2, 1.0 / hi) >= n2 + 1;
         const unsigned long long m = __ballot(above);
         if (lane == 0) wfirst[wave] = m ? wave * 64 + __builtin_ctzll(m) : kMS;
       }
@@ -720,56 +730,99 @@ __device__ __forceinline__ void k_projected_gk_body(const ProjArgs& a, const VBl
       for (int base = 0; base < kGrid; base += nb) {
         const int i = base + tid;
         if (tid < nb && i < kGrid)
-          gridv[i] = gk_gcv(exp10(t0 + (double)i * dt), k, ab_a, ab_b, beta, rec + tid, rec + k * nb + tid, nb, nullptr);
+          gridv[i] = gk_gcv(exp10(t0 + (double)i * dt), k, ab_a, ab_b, beta, rec + tid, rec + k * nb + tid, nb,
+                            nullptr);
       }
       __syncthreads();
-      if (wave != 0) return;
-      // wave 0 from here: first index of the minimum (NaN counts as +inf)
-      int bi = kGrid;
-      double bv = __builtin_inf();
-      for (int i = lane; i < kGrid; i += 64) {
-        const double v = gridv[i] == gridv[i] ? gridv[i] : __builtin_inf();
-        if (bi == kGrid || v < bv) { bi = i; bv = v; }
+      // first index of the grid minimum (NaN counts as +inf)
+      if (wave == 0) {
+        int bi = kGrid;
+        double bv = __builtin_inf();
+        for (int i = lane; i < kGrid; i += 64) {
+          const double v = gridv[i] == gridv[i] ? gridv[i] : __builtin_inf();
+          if (bi == kGrid || v < bv) { bi = i; bv = v; }
+        }
+        first_min64(bv, bi);
+        const int ib = bi < kGrid ? bi : 0;
+        if (lane == 0) {
+          wfirst[0] = ib;
+          s_ra = t0 + (double)(ib > 0 ? ib - 1 : 0) * dt;
+          s_rb = t0 + (double)(ib < kGrid - 1 ? ib + 1 : kGrid - 1) * dt;
+          s_rt = __builtin_nan("");
+          s_rf = __builtin_inf();
+        }
       }
-      first_min64(bv, bi);
-      const int ib = bi < kGrid ? bi : 0;
-      // refinement on t = log10(lambda): 64 points evenly inside [a, b] per
-      // pass (one per lane), keeping the two cells next to the first smallest
-      // value, until the bracket is narrower than 1e-10
-      double ra = t0 + (double)(ib > 0 ? ib - 1 : 0) * dt;
-      double rb = t0 + (double)(ib < kGrid - 1 ? ib + 1 : kGrid - 1) * dt;
-      double rt = __builtin_nan(""), rf = __builtin_inf();
-      for (int pass = 0; pass < 40 && (rb - ra) > 1e-10; ++pass) {
-        const double h = (rb - ra) / (double)(kRef + 1);
-        const double f = gk_gcv(exp10(ra + (double)(lane + 1) * h), k, ab_a, ab_b, beta, rec + lane,
-                                rec + k * kRef + lane, kRef, nullptr);
-        double mv = f == f ? f : __builtin_inf();
-        int mi = lane;
-        first_min64(mv, mi);
-        const double na = ra + (double)mi * h, nbr = ra + (double)(mi + 2) * h;
-        rt = ra + (double)(mi + 1) * h;
-        rf = mv;
-        ra = na;
-        rb = nbr;
+      __syncthreads();
+      const int ib = wfirst[0];
+      // Refinement on t = log10(lambda) inside the grid cells next to the
+      // minimum: two passes of np points evenly inside [a, b] (one per
+      // thread), each keeping the two cells next to the first smallest value
+      // (the bracket shrinks below 1e-5 of a grid cell), then the vertex of
+      // the parabola through the smallest value and its two neighbours.
+      const int np = min(nb, kRP);
+      for (int pass = 0; pass < 2; ++pass) {
+        const double ra = s_ra, rb = s_rb;
+        const double h = (rb - ra) / (double)(np + 1);
+        if (tid < np) {
+          const double f = gk_gcv(exp10(ra + (double)(tid + 1) * h), k, ab_a, ab_b, beta, rec + tid,
+                                  rec + k * np + tid, np, nullptr);
+          refv[tid] = f == f ? f : __builtin_inf();
+        }
+        __syncthreads();
+        if (tid < 64) {
+          int mi = np;
+          double mv = __builtin_inf();
+          for (int i = lane; i < np; i += 64) {
+            if (mi == np || refv[i] < mv) { mi = i; mv = refv[i]; }
+          }
+          first_min64(mv, mi);
+          if (lane == 0) {
+            mi = mi < np ? mi : 0;
+            s_ra = ra + (double)mi * h;          // point mi - 1 (or a)
+            s_rb = ra + (double)(mi + 2) * h;    // point mi + 1 (or b)
+            s_rt = ra + (double)(mi + 1) * h;
+            s_rf = refv[mi];
+            s_fl = mi > 0 ? refv[mi - 1] : __builtin_nan("");
+            s_fr = mi + 1 < np ? refv[mi + 1] : __builtin_nan("");
+          }
+        }
+        __syncthreads();
+      }
+      if (tid != 0) return;
+      double rt = s_rt, rf = s_rf;
+      {
+        // parabola through (rt - h, fl), (rt, rf), (rt + h, fr): vertex offset
+        // h (fl - fr) / (2 (fl - 2 rf + fr)) when the curvature is positive and
+        // the vertex lies inside the bracket; kept if its value is smaller
+        const double h = 0.5 * (s_rb - s_ra), fl = s_fl, fr = s_fr;
+        const double cu = fl - 2.0 * rf + fr;
+        if (cu > 0.0) {
+          const double dv = 0.5 * h * (fl - fr) / cu;
+          if (fabs(dv) < h) {
+            const double fv = gk_gcv(exp10(rt + dv), k, ab_a, ab_b, beta, rec, rec + kMaxK, 1, nullptr);
+            if (fv <= rf) { rt = rt + dv; rf = fv; }
+          }
+        }
       }
       const double gv = gridv[ib];
       if (rf <= gv) { lam = exp10(rt); gcv = rf; }
       else { lam = exp10(t0 + (double)ib * dt); gcv = gv; }
       // a proposed lambda is kept when its GCV value is within the gate of the minimum
       if (lam_cand > 0.0) {
-        const double fcand = gk_gcv(lam_cand, k, ab_a, ab_b, beta, rec + lane, rec + k * kRef + lane, kRef, nullptr);
+        const double fcand = gk_gcv(lam_cand, k, ab_a, ab_b, beta, rec, rec + kMaxK, 1, st->y);
         const bool keep = fcand <= gate * gcv;
-        if (lane == 0) st->gate_ok = keep ? 1.0 : 0.0;
-        if (keep) { lam = lam_cand; gcv = fcand; }
+        st->gate_ok = keep ? 1.0 : 0.0;
+        if (keep) { lam = lam_cand; gcv = fcand; y_done = true; }
       }
     }
   }
   if (tid != 0) return;
-  if (lam > 0.0) {
+  if (y_done) {
+  } else if (lam > 0.0) {
     // y_lambda from the same rotations as the GCV values (one lane)
     (void)gk_gcv(lam, k, ab_a, ab_b, beta, rec, rec + kMaxK, 1, st->y);
   } else {
-    // lambda = 0 (fixed): the recurrence with square roots and guarded divisions
+    // lambda = 0: the recurrence with square roots and guarded divisions
     double* rho = rec;
     double* phi = rec + kMaxK;
     double* th = rec + 2 * kMaxK;
