@@ -151,12 +151,20 @@ def main():
     for _ in range(args.warmup):
         info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
     torch.cuda.synchronize()
+    # timed: the solves are enqueued back to back (no per-solve read-back of the
+    # solve info, so the device never waits for the host)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+        dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # the same with the info read back after every solve (one host round trip each)
+    t0s = time.perf_counter()
+    for _ in range(args.steps):
+        info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+    torch.cuda.synchronize()
+    ms_sync = (time.perf_counter() - t0s) * 1e3 / args.steps
 
     # restoration error of the benchmarked solve
     kr = dk.dctk_krylov_read(ctx, ws, k, dk.DCTK_KRYLOV_GKB)
@@ -261,6 +269,8 @@ def main():
                         "lambda_gpu": info.lam, "lambda_oracle": lam_oracle, "iters": info.iters,
                         "jacobi_sweeps": kr["sweeps"]},
         "cprod": cprod,
+        "per_solve_sync": {"solves_per_s": 1e3 / ms_sync, "ms_per_solve": ms_sync,
+                           "note": "info read back (host synchronisation) after every solve"},
     }
     dk.dctk_krylov_destroy(ws)
     dk.dctk_op_destroy(op)
@@ -498,17 +508,17 @@ def bench_large(args):
     X = torch.zeros_like(C)
     opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0, 0.0)
 
-    def solve():
+    def solve(read_info=True):
         if video:
             X.zero_()
             return dk.dctk_gmres_tik_solve(ctx, ws, C, X, 1, opts)
-        return dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+        return dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=read_info)
     for _ in range(args.warmup):
         info = solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        info = solve()
+        solve(read_info=False)  # DC-GK: enqueued back to back; DC-GMRES reads its info
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     err = float(torch.linalg.norm(X.double() - Xt) / torch.linalg.norm(Xt))

@@ -252,7 +252,9 @@ typedef struct {
  * update runs inside the next forward product (same recurrence, two
  * launches per step).  ws must be a DCTK_KRYLOV_GKB workspace of op.
  * C: p x n1 x s, X (output): p x n2 x s.  Synchronises once to fill info
- * (may be NULL). */
+ * and returns the solve's status; with info NULL the solve is only enqueued
+ * on ctx's stream (no read-back, no synchronisation, DCTK_OK once enqueued),
+ * so solves can follow each other on the device without host round trips. */
 int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X,
                         const dctk_solve_opts* opts, dctk_solve_info* info);
 /* DC-GMRES(m) with Tikhonov on every cycle (Algorithm 3), m = opts->k_max,

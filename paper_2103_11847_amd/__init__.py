@@ -340,11 +340,16 @@ def make_opts(k_max, reorth=DCTK_REORTH_NONE, gcv_mode=0, lam=-1.0, tol=0.0):
     return dctk_solve_opts(int(k_max), int(reorth), int(gcv_mode), 0, float(lam), float(tol))
 
 
-def dctk_lsqr_tik_solve(ctx, ws, C, X, opts):
-    info = dctk_solve_info()
-    _check(lib().dctk_lsqr_tik_solve(ctx, ws, _ptr(C), _ptr(X), ctypes.byref(opts), ctypes.byref(info)),
+def dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=True):
+    """info=False: enqueue only (the library gets a NULL info; nothing is read back)."""
+    if not info:
+        _check(lib().dctk_lsqr_tik_solve(ctx, ws, _ptr(C), _ptr(X), ctypes.byref(opts), None),
+               "dctk_lsqr_tik_solve")
+        return None
+    out = dctk_solve_info()
+    _check(lib().dctk_lsqr_tik_solve(ctx, ws, _ptr(C), _ptr(X), ctypes.byref(opts), ctypes.byref(out)),
            "dctk_lsqr_tik_solve")
-    return info
+    return out
 
 
 def dctk_gmres_tik_solve(ctx, ws, C, X, cycles, opts):

@@ -5,6 +5,7 @@
 // Krylov scalars (alpha, beta, h, the LSQR rotations, lambda, y) live in a
 // device-resident state so a solve synchronises once, at the end.
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -735,12 +736,12 @@ static int read_state(dctk_ctx ctx, dctk_krylov ws, HostState* hs) {
   return DCTK_OK;
 }
 
-static double lsqr_resnorm(dctk_ctx ctx, dctk_krylov ws, int steps) {
-  double v = 0.0;
-  if (hipMemcpyAsync(&v, &ws->st->phibar[steps], sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
-    return NAN;
-  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return NAN;
-  return std::fabs(v);
+// The state up to and including the LSQR scalars (phibar), in one copy and one
+// synchronisation.
+static int read_state_lsqr(dctk_ctx ctx, dctk_krylov ws, KState* hk) {
+  DCTK_HIP(ctx, hipMemcpyAsync(hk, ws->st, offsetof(KState, H), hipMemcpyDeviceToHost, ctx->stream));
+  DCTK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DCTK_OK;
 }
 
 hipError_t learned_enqueue(dctk_ctx ctx, dctk_krylov ws, dctk_mlp m, const void* C, void* X,
@@ -765,20 +766,21 @@ hipError_t learned_enqueue(dctk_ctx ctx, dctk_krylov ws, dctk_mlp m, const void*
 }
 
 int lsqr_info(dctk_ctx ctx, dctk_krylov ws, const dctk_solve_opts* opts, dctk_solve_info* info) {
-  HostState hs;
+  static thread_local KState hk;
   int r;
-  if ((r = read_state(ctx, ws, &hs))) return r;
+  if ((r = read_state_lsqr(ctx, ws, &hk))) return r;
   const bool tik = opts->lambda != 0.0;
+  const int steps = hk.steps < 0 ? 0 : (hk.steps > kMaxK ? kMaxK : hk.steps);
   if (info) {
-    info->iters = hs.steps;
-    info->status = hs.status;
-    info->converged = hs.converged;
+    info->iters = hk.steps;
+    info->status = hk.status;
+    info->converged = hk.converged;
     info->cycles = 0;
-    info->lambda = tik ? hs.lambda : 0.0;
-    info->resnorm = lsqr_resnorm(ctx, ws, hs.steps);
-    info->gcv = (tik && opts->lambda < 0.0) ? hs.gcv : NAN;
+    info->lambda = tik ? hk.lambda : 0.0;
+    info->resnorm = std::fabs(hk.phibar[steps]);
+    info->gcv = (tik && opts->lambda < 0.0) ? hk.gcv : NAN;
   }
-  return hs.status;
+  return hk.status;
 }
 
 }  // namespace dctk
@@ -928,6 +930,7 @@ int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, co
     return DCTK_EINVAL;
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
   DCTK_HIP(ctx, lsqr_enqueue(ctx, ws, C, X, opts));
+  if (info == nullptr) return DCTK_OK;  // enqueued only: no read-back, no synchronisation
   return lsqr_info(ctx, ws, opts, info);
 }
 
@@ -945,18 +948,18 @@ int dctk_krylov_project(dctk_ctx ctx, dctk_krylov ws, int k, const dctk_solve_op
   // the basis vectors beyond a breakdown are never formed: combine min(k, steps) of them
   DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, k,
                                &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
-  HostState hs;
-  if ((r = read_state(ctx, ws, &hs))) return r;
+  static thread_local KState hk;
+  if ((r = read_state_lsqr(ctx, ws, &hk))) return r;
   if (info) {
-    info->iters = hs.steps < k ? hs.steps : k;
-    info->status = hs.status;
-    info->converged = hs.converged;
+    info->iters = hk.steps < k ? hk.steps : k;
+    info->status = hk.status;
+    info->converged = hk.converged;
     info->cycles = 0;
-    info->lambda = hs.lambda;
-    info->resnorm = lsqr_resnorm(ctx, ws, info->iters);
-    info->gcv = opts->lambda < 0.0 ? hs.gcv : NAN;
+    info->lambda = hk.lambda;
+    info->resnorm = std::fabs(hk.phibar[info->iters < 0 ? 0 : info->iters]);
+    info->gcv = opts->lambda < 0.0 ? hk.gcv : NAN;
   }
-  return hs.status;
+  return hk.status;
 }
 
 int dctk_lsqr_learned_solve(dctk_ctx ctx, dctk_krylov ws, dctk_mlp mlp, const void* C, void* X,

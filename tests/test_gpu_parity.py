@@ -439,6 +439,34 @@ def test_folded_and_three_kernel_solves_agree(ctx):
     assert rel(xs[0], xs[1]) <= 2e-3
 
 
+def test_enqueued_solves_match_synchronous_solve(ctx):
+    """dctk_lsqr_tik_solve with info NULL only enqueues: three solves back to
+    back (different right-hand sides into different outputs, no read-back in
+    between) give bit for bit the X, lambda and steps of the same solves run
+    one at a time with their info read back."""
+    w, _, C = _colour_small_problem()
+    k = 12
+    op = Op(ctx, w["A"], None, 32, dk.DCTK_F32)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0)
+    Cs = [to_gpu(C * (1.0 + 0.1 * i), F32) for i in range(3)]
+    ref = []
+    for Ci in Cs:
+        X = torch.empty(C.shape, dtype=F32, device="cuda:0")
+        info = dk.dctk_lsqr_tik_solve(ctx, ws, Ci, X, opts)
+        ref.append((to_np(X), info.lam, info.iters))
+    outs = [torch.empty(C.shape, dtype=F32, device="cuda:0") for _ in Cs]
+    for Ci, Xi in zip(Cs, outs):
+        assert dk.dctk_lsqr_tik_solve(ctx, ws, Ci, Xi, opts, info=False) is None
+    dk.dctk_synchronize(ctx)
+    for (xr, lam, it), Xi in zip(ref, outs):
+        assert np.array_equal(to_np(Xi), xr)
+    # the workspace holds the last solve's state: its info matches the last reference
+    info = dk.dctk_lsqr_tik_solve(ctx, ws, Cs[-1], outs[-1], opts)
+    assert info.lam == ref[-1][1] and info.iters == ref[-1][2]
+    dk.dctk_krylov_destroy(ws)
+
+
 def test_gk_gcv_20_steps_restoration_level(ctx):
     """k = 20 on the same problem: past step ~15 rounding is amplified by the
     process itself (oracle vs oracle with C perturbed by 1e-16: alpha moves 3%,
