@@ -208,8 +208,9 @@ int dctk_arnoldi_step(dctk_ctx ctx, dctk_krylov ws);
  * NULL):  GKB: alpha[0..k_max] = alpha_1.., beta[0..k_max] = beta_1..;
  * Arnoldi: H[(k_max+1) * k_max] row-major h_{i+1,j+1}, beta[0] = ||V||.
  * info[0..5] = steps taken, status (DCTK_OK / DCTK_BREAKDOWN), converged
- * flag, the capacity k_max, the Jacobi sweeps of the last projected solve,
- * and the GMRES cycles run. */
+ * flag, the capacity k_max, the Jacobi sweeps of the last projected solve
+ * (0 when it needed no SVD: DC-GK with the rectangular GCV or a fixed
+ * lambda), and the GMRES cycles run. */
 int dctk_krylov_read(dctk_ctx ctx, dctk_krylov ws, double* alpha, double* beta_or_H, int* info);
 /* Device pointer to basis vector j (0-based) of basis `which`
  * (0 = U for GKB / V for Arnoldi, 1 = V for GKB), or to the LSQR iterate X

@@ -1,11 +1,14 @@
 // The small projected problem of DC-GMRES and DC-GK (Sec. 3.1, 3.2), in FP64
-// on the device, one workgroup of 16 waves:
-//   * SVD of the (k+1) x k projected matrix (Hessenberg H~_k or lower
-//     bidiagonal C~_k) by one-sided (Hestenes) Jacobi: columns are rotated
-//     pairwise until orthogonal, in a round-robin order; each pair of a round
-//     belongs to an 8-lane group of a wave (rows of the matrix spread over the
-//     lanes, dot products reduced with DPP permutes), so a round of up to 32
-//     pairs is one pass of at most four waves, one per SIMD;
+// on the device, one workgroup of 16 waves.  Two kernels:
+//
+// k_projected (the Hessenberg matrix of DC-GMRES, and the printed GCV form
+// eq. (gcv2) of either method):
+//   * SVD of the (k+1) x k projected matrix by one-sided (Hestenes) Jacobi:
+//     columns are rotated pairwise until orthogonal, in a round-robin order;
+//     each pair of a round belongs to an 8-lane group of a wave (rows of the
+//     matrix spread over the lanes, dot products reduced with DPP permutes),
+//     so a round of up to 32 pairs is one pass of at most four waves, one per
+//     SIMD;
 //   * the component of beta e_1 outside range(H), from the null vector z of
 //     H^T (H^T z = 0 is a forward recurrence for a Hessenberg matrix), so it
 //     does not suffer the cancellation of beta^2 - sum g_i^2;
@@ -15,10 +18,11 @@
 //     first smallest value until the bracket on log10(lambda) is below 1e-10,
 //     keeping the better of the refined point and the grid point;
 //   * y_lambda (eq. leastsq / normeq2): for the bidiagonal matrix by plane
-//     rotations of [C~_k; lambda I] (so the Jacobi sweeps need not accumulate
-//     V), for the Hessenberg matrix as V diag(sigma / (sigma^2 + lambda^2)) g.
-// The GCV function is that of the rectangular projected problem (mode 0) or
-// the printed eq. (gcv2) (mode 1).
+//     rotations of [C~_k; lambda I], for the Hessenberg matrix as
+//     V diag(sigma / (sigma^2 + lambda^2)) g.
+//
+// k_projected_gk (the lower bidiagonal C~_k of DC-GK with the GCV function of
+// the rectangular projected problem, or a fixed lambda): no SVD, see below.
 #include <cfloat>
 #include <cmath>
 
