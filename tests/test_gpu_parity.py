@@ -371,6 +371,36 @@ def test_gk_gcv_matches_oracle(ctx, mode):
     dk.dctk_krylov_destroy(ws)
 
 
+def test_gk_projected_gcv_every_k(ctx):
+    """The DC-GK projected solve (sigma_1 by Sturm counts, GCV from the damped
+    rotations, no SVD) at every k from 1 to 12 of one FP64 GKB run on the
+    32 x 32 x 3 colour problem, against the oracle's SVD definitions at the
+    same k: the GCV value at the library's lambda is the oracle's minimum (to
+    1e-9) and equals the oracle's GCV there (to 1e-9); X is the oracle's X at
+    the library's lambda; a fixed lambda gives the oracle's X (1e-9)."""
+    w, _, C = _colour_small_problem()
+    op = Op(ctx, w["A"], None, 32, dk.DCTK_F64)
+    kmax = 12
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, kmax)
+    X = torch.empty(C.shape, dtype=F64, device="cuda:0")
+    dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(kmax, dk.DCTK_REORTH_FULL, 0, -1.0))
+    g = krylov.gkb(op.oracle, C, kmax, reorth="full")
+    for k in range(1, kmax + 1):
+        info = dk.dctk_krylov_project(ctx, ws, k, dk.make_opts(kmax, dk.DCTK_REORTH_FULL, 0, -1.0), X)
+        sig, Vt, gg = tikhonov.projected_svd(g.bidiagonal(k), g.beta[0])
+        lam_ref, gmin = tikhonov.gcv_minimize(sig, gg, "rect")
+        got = tikhonov.gcv_rect(sig, gg, info.lam)
+        say("k", k, "lambda", info.lam, lam_ref, "gcv", info.gcv, gmin)
+        assert got <= gmin * (1.0 + 1e-9)
+        assert abs(info.gcv - got) <= 1e-9 * abs(got)
+        ref = krylov.dc_gk(op.oracle, C, k, lam=info.lam, reorth="full")
+        assert rel(to_np(X), ref["X"]) <= 1e-9
+        dk.dctk_krylov_project(ctx, ws, k, dk.make_opts(kmax, dk.DCTK_REORTH_FULL, 0, 0.03), X)
+        ref = krylov.dc_gk(op.oracle, C, k, lam=0.03, reorth="full")
+        assert rel(to_np(X), ref["X"]) <= 1e-9
+    dk.dctk_krylov_destroy(ws)
+
+
 @pytest.mark.parametrize("lam", [0.05, -1.0])
 def test_gk_folded_updates_match_oracle(ctx, lam):
     """Tikhonov solve (no reorthogonalisation, both products fused), where each
