@@ -552,7 +552,9 @@ __global__ __launch_bounds__(kPT) void k_projected(ProjArgs a_, const ProjArgs* 
 //     lambda^2 trace((C~^T C~ + lambda^2 I)^-1) = lambda^2 ||R^-1||_F^2, whose
 //     column norms follow a forward recurrence, and the residual is formed
 //     from y_lambda = R^-1 f directly (no cancellation against beta^2);
-//   * the same grid, refinement and gate as the SVD path.
+//   * the same grid and gate as the SVD path; the refinement is one pass of
+//     up to 256 points and a step to the vertex of the parabola through the
+//     smallest value and its neighbours.
 constexpr int kRecD = 18432;  // doubles of per-lambda recurrence rows (144 KB)
 constexpr int kMS = 256;      // multisection points per round
 constexpr int kRP = 256;      // most refinement points per pass
@@ -759,12 +761,13 @@ __device__ __forceinline__ void k_projected_gk_body(const ProjArgs& a, const VBl
       __syncthreads();
       const int ib = wfirst[0];
       // Refinement on t = log10(lambda) inside the grid cells next to the
-      // minimum: two passes of np points evenly inside [a, b] (one per
-      // thread), each keeping the two cells next to the first smallest value
-      // (the bracket shrinks below 1e-5 of a grid cell), then the vertex of
-      // the parabola through the smallest value and its two neighbours.
+      // minimum: one pass of np points evenly inside [a, b] (one per thread),
+      // keeping the two cells next to the first smallest value (a bracket of
+      // ~1/100 of a grid cell), then the vertex of the parabola through the
+      // smallest value and its two neighbours (its error, third order in the
+      // spacing, leaves the GCV value at the minimum's to ~1e-15).
       const int np = min(nb, kRP);
-      for (int pass = 0; pass < 2; ++pass) {
+      for (int pass = 0; pass < 1; ++pass) {
         const double ra = s_ra, rb = s_rb;
         const double h = (rb - ra) / (double)(np + 1);
         if (tid < np) {
@@ -794,29 +797,34 @@ __device__ __forceinline__ void k_projected_gk_body(const ProjArgs& a, const VBl
       }
       if (tid != 0) return;
       double rt = s_rt, rf = s_rf;
+      double y_t = __builtin_nan("");  // t whose y st->y holds
       {
         // parabola through (rt - h, fl), (rt, rf), (rt + h, fr): vertex offset
         // h (fl - fr) / (2 (fl - 2 rf + fr)) when the curvature is positive and
-        // the vertex lies inside the bracket; kept if its value is smaller
+        // the vertex lies inside the bracket; kept if its value is smaller.
+        // Its evaluation also writes y, kept when the vertex is the result.
         const double h = 0.5 * (s_rb - s_ra), fl = s_fl, fr = s_fr;
         const double cu = fl - 2.0 * rf + fr;
         if (cu > 0.0) {
           const double dv = 0.5 * h * (fl - fr) / cu;
           if (fabs(dv) < h) {
-            const double fv = gk_gcv(exp10(rt + dv), k, ab_a, ab_b, beta, rec, rec + kMaxK, 1, nullptr);
-            if (fv <= rf) { rt = rt + dv; rf = fv; }
+            const double tv = rt + dv;
+            const double fv = gk_gcv(exp10(tv), k, ab_a, ab_b, beta, rec, rec + kMaxK, 1, st->y);
+            y_t = tv;
+            if (fv <= rf) { rt = tv; rf = fv; }
           }
         }
       }
       const double gv = gridv[ib];
-      if (rf <= gv) { lam = exp10(rt); gcv = rf; }
+      if (rf <= gv) { lam = exp10(rt); gcv = rf; y_done = (rt == y_t); }
       else { lam = exp10(t0 + (double)ib * dt); gcv = gv; }
       // a proposed lambda is kept when its GCV value is within the gate of the minimum
       if (lam_cand > 0.0) {
         const double fcand = gk_gcv(lam_cand, k, ab_a, ab_b, beta, rec, rec + kMaxK, 1, st->y);
         const bool keep = fcand <= gate * gcv;
         st->gate_ok = keep ? 1.0 : 0.0;
-        if (keep) { lam = lam_cand; gcv = fcand; y_done = true; }
+        if (keep) { lam = lam_cand; gcv = fcand; }
+        y_done = keep;
       }
     }
   }

@@ -302,6 +302,29 @@ __device__ __forceinline__ void k_combine_body(const CombineArgs& a, const VBloc
   if (cnt < 0) cnt = 0;
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) sy[i] = y[i];
   __syncthreads();
+  if (vec) {
+    // 16-byte rows (n a multiple of 4): eight basis rows in flight per thread,
+    // loaded unconditionally from clamped indices, summed in basis order
+    constexpr int U = 8;
+    DCTK_VGRID_LOOP(e, n, vb, a.gx) {
+      double o[4] = {0.0, 0.0, 0.0, 0.0};
+      if (x0) V4<T>::ld(x0 + e, o);
+      for (int i0 = 0; i0 < cnt; i0 += U) {
+        double bv[U][4];
+#pragma unroll
+        for (int j = 0; j < U; ++j) V4<T>::ld(basis + (int64_t)min(i0 + j, cnt - 1) * bstride + e, bv[j]);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          if (i0 + j < cnt) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) o[u] += sy[i0 + j] * bv[j][u];
+          }
+        }
+      }
+      V4<T>::st(out + e, o);
+    }
+    return;
+  }
   DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double o[4] = {0.0, 0.0, 0.0, 0.0};
     if (x0) ld4(x0, e, n, vec, o);
