@@ -214,21 +214,29 @@ __global__ __launch_bounds__(kThreads) void tube_kernel(TubeArgs ta_, const Tube
   }
 }
 
+// the epilogue's src in FP32 (bf16_t is the bit pattern of a bfloat16)
+template <typename T> __device__ inline float to_f32(T v) { return (float)v; }
+template <> __device__ inline float to_f32<bf16_t>(bf16_t v) { return bf16_to_float(v); }
+
 // Long tubes (p >= 16): the transform out = G x in is a (p x p)(p x count)
-// contraction, so it runs on the matrix cores.  A workgroup takes 64 positions
-// and all p outputs: G (p x p, FP32, rows padded to 16) and the 64-position
-// input tile (p x 64, 16-byte loads, scaled by the control block's s and
-// written to xnorm on the way) are staged in LDS; wave w computes the 16
-// positions of column block w for every 16-row band of outputs with
-// 16x16x4 FP32 MFMAs; the epilogue applies a, b, src and writes per-block
-// partial sums of out^2.
-template <typename TOUT, int PM, bool SCALE, bool EPI>
+// contraction, so it runs on the matrix cores.  A workgroup stages G (p x p,
+// FP32, rows padded to 16) in LDS once and then walks its 64-position tiles
+// (grid stride): the tile's input (p x 64, 16-byte loads from clamped
+// addresses, issued together, scaled by the control block's s and written to
+// xnorm on the way) and the epilogue's src values are loaded before the tile
+// is multiplied; wave w computes the 16 positions of column block w for
+// every 16-row band of outputs with 16x16x4 FP32 MFMAs; the epilogue applies
+// a, b, src and accumulates the workgroup's partial sum of out^2.
+// VEC: count a multiple of 4 and 16-byte aligned in / xnorm.
+template <typename TOUT, int PM, bool SCALE, bool EPI, bool VEC>
 __device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const VBlock vb, const bool grouped) {
   typedef Mfma<float> MF;
-  constexpr int NB = 64;            // positions per workgroup
+  constexpr int NB = 64;            // positions per tile
   constexpr int LDG = PM + 4;       // G as [k][t], t contiguous (+16 bytes)
   constexpr int LDX = NB + 16;      // input as [t][e], e contiguous (+64 bytes)
   constexpr int FR = PM / 16;       // row bands
+  constexpr int XU = PM * (NB / 4) / 256;  // input float4 units per thread
+  static_assert(XU * 256 == PM * (NB / 4), "tile");
   __shared__ __attribute__((aligned(16))) float sG[PM * LDG];
   __shared__ __attribute__((aligned(16))) float sX[PM * LDX];
   __shared__ double sh[kShCtl];
@@ -244,66 +252,119 @@ __device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const 
   const float* G = (const float*)ta.G;
   const TOUT* src = (const TOUT*)ta.src;
   float* xnorm = (float*)ta.xnorm;
+  const bool use_src = EPI && src != nullptr && b != 0.0f;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t e0 = (int64_t)vb.x * NB;
-  for (int i = tid; i < PM * PM; i += 256) {
-    const int k = i / PM, t = i % PM;
-    sG[k * LDG + t] = (k < p && t < p) ? G[k * p + t] : 0.0f;
+  {
+    constexpr int GU = PM * PM / 256;  // G entries per thread, all loaded first
+    static_assert(GU * 256 == PM * PM, "G");
+    float gv[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int i = tid + u * 256, k = i / PM, t = i % PM;
+      const bool ok = k < p && t < p;
+      const float v = G[ok ? k * p + t : 0];
+      gv[u] = ok ? v : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int i = tid + u * 256, k = i / PM, t = i % PM;
+      sG[k * LDG + t] = gv[u];
+    }
   }
-  // input tile: p rows of 64 positions, 16 float4 per row
-  const bool vec = (count % 4 == 0) && (((uintptr_t)in) % 16 == 0) &&
-                   (xnorm == nullptr || ((uintptr_t)xnorm) % 16 == 0);
-  for (int i = tid; i < PM * (NB / 4); i += 256) {
-    const int t = i / (NB / 4), c = (i % (NB / 4)) * 4;
-    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    const int64_t e = e0 + c;
-    if (t < p) {
-      const float* ip = in + (int64_t)t * count + e;
-      if (vec && e + 4 <= count) {
-        const float4 q = *reinterpret_cast<const float4*>(ip);
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t ntiles = (count + NB - 1) / NB;
+  double sq = 0.0;
+  for (int64_t tile = vb.x; tile < ntiles; tile += ta.gx) {
+    const int64_t e0 = tile * NB;
+    // this tile's input, all loads issued before the first use
+    float rv[XU][4];
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int i = tid + u * 256;
+      const int t = i / (NB / 4), c = (i % (NB / 4)) * 4;
+      const int64_t e = e0 + c;
+      if constexpr (VEC) {
+        const bool ok = t < p && e < count;
+        const float4 q = *reinterpret_cast<const float4*>(in + (ok ? (int64_t)t * count + e : 0));
+        rv[u][0] = ok ? q.x : 0.0f;
+        rv[u][1] = ok ? q.y : 0.0f;
+        rv[u][2] = ok ? q.z : 0.0f;
+        rv[u][3] = ok ? q.w : 0.0f;
       } else {
-        for (int u = 0; u < 4; ++u) v[u] = (e + u < count) ? ip[u] : 0.0f;
-      }
-      if (SCALE) {
-        for (int u = 0; u < 4; ++u) v[u] *= sc;
-        if (xnorm != nullptr) {
-          float* xp = xnorm + (int64_t)t * count + e;
-          if (vec && e + 4 <= count) *reinterpret_cast<float4*>(xp) = make_float4(v[0], v[1], v[2], v[3]);
-          else for (int u = 0; u < 4; ++u) if (e + u < count) xp[u] = v[u];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool ok = t < p && e + v < count;
+          const float x = in[ok ? (int64_t)t * count + e + v : 0];
+          rv[u][v] = ok ? x : 0.0f;
         }
       }
     }
-    *reinterpret_cast<float4*>(&sX[t * LDX + c]) = make_float4(v[0], v[1], v[2], v[3]);
-  }
-  __syncthreads();
-  const int lr = lane & 15, lk = lane >> 4;
-  typename MF::frag_t acc[FR];
-#pragma unroll
-  for (int f = 0; f < FR; ++f)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[f][r] = 0.0f;
-#pragma unroll 4
-  for (int t0 = 0; t0 < PM; t0 += 4) {
-    const float* bp = &sX[(t0 + lk) * LDX + wave * 16 + lr];
-#pragma unroll
-    for (int f = 0; f < FR; ++f) acc[f] = MF::mac(&sG[(f * 16 + lr) * LDG + t0 + lk], bp, acc[f]);
-  }
-  double sq = 0.0;
-  const int64_t e = e0 + wave * 16 + lr;
-  if (e < count) {
+    // the epilogue's src values (independent of the product)
+    const int64_t eo = e0 + wave * 16 + lr;
+    float sv[FR][4];
 #pragma unroll
     for (int f = 0; f < FR; ++f)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = f * 16 + lk * 4 + r;
-        if (k < p) {
-          float y = a * acc[f][r];
-          if (EPI && b != 0.0f) y += b * (float)src[(int64_t)k * count + e];
-          out[(int64_t)k * count + e] = cvt<TOUT, float>(y);
-          if (EPI) sq += (double)y * (double)y;
+      for (int r = 0; r < 4; ++r) sv[f][r] = 0.0f;
+    if (use_src) {
+#pragma unroll
+      for (int f = 0; f < FR; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = f * 16 + lk * 4 + r;
+          const bool ok = k < p && eo < count;
+          const TOUT x = src[ok ? (int64_t)k * count + eo : 0];
+          sv[f][r] = ok ? to_f32(x) : 0.0f;
+        }
+    }
+    __syncthreads();  // the previous tile's operands have been read
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int i = tid + u * 256;
+      const int t = i / (NB / 4), c = (i % (NB / 4)) * 4;
+      const int64_t e = e0 + c;
+      if (SCALE) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rv[u][v] *= sc;
+        if (xnorm != nullptr && t < p) {
+          float* xp = xnorm + (int64_t)t * count + e;
+          if (VEC) {
+            if (e < count) *reinterpret_cast<float4*>(xp) = make_float4(rv[u][0], rv[u][1], rv[u][2], rv[u][3]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (e + v < count) xp[v] = rv[u][v];
+          }
         }
       }
+      *reinterpret_cast<float4*>(&sX[t * LDX + c]) = make_float4(rv[u][0], rv[u][1], rv[u][2], rv[u][3]);
+    }
+    __syncthreads();
+    typename MF::frag_t acc[FR];
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[f][r] = 0.0f;
+#pragma unroll 4
+    for (int t0 = 0; t0 < PM; t0 += 4) {
+      const float* bp = &sX[(t0 + lk) * LDX + wave * 16 + lr];
+#pragma unroll
+      for (int f = 0; f < FR; ++f) acc[f] = MF::mac(&sG[(f * 16 + lr) * LDG + t0 + lk], bp, acc[f]);
+    }
+    if (eo < count) {
+#pragma unroll
+      for (int f = 0; f < FR; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = f * 16 + lk * 4 + r;
+          if (k < p) {
+            float y = a * acc[f][r];
+            if (EPI) y += b * sv[f][r];
+            out[(int64_t)k * count + eo] = cvt<TOUT, float>(y);
+            if (EPI) sq += (double)y * (double)y;
+          }
+        }
+    }
   }
   if (EPI && ta.ctl.part_out != nullptr) {
     const double tot = block_sum_all(sq, sh);
@@ -311,14 +372,14 @@ __device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const 
   }
 }
 
-template <typename TOUT, int PM, bool SCALE, bool EPI, bool GROUPED>
+template <typename TOUT, int PM, bool SCALE, bool EPI, bool VEC, bool GROUPED>
 __global__ __launch_bounds__(256) void tube_mfma_kernel(TubeArgs ta_, const TubeArgs* grp, const int4* bmap) {
   if constexpr (!GROUPED) {
-    tube_mfma_kernel_body<TOUT, PM, SCALE, EPI>(ta_, hw_block(), false);
+    tube_mfma_kernel_body<TOUT, PM, SCALE, EPI, VEC>(ta_, hw_block(), false);
   } else {
     VBlock vb;
     const TubeArgs g = group_args(grp, bmap, vb);
-    tube_mfma_kernel_body<TOUT, PM, SCALE, EPI>(g, vb, true);
+    tube_mfma_kernel_body<TOUT, PM, SCALE, EPI, VEC>(g, vb, true);
   }
 }
 
@@ -326,9 +387,14 @@ template <typename TOUT>
 static hipError_t launch_tube_mfma(dctk_ctx ctx, hipStream_t s, int64_t p, int64_t count, const void* in, void* out,
                                    const float* G, const void* src, void* xnorm, const Ctl& ctl, bool scale,
                                    bool epi, int* nblocks_out) {
-  const int64_t blocks = (count + 63) / 64;
+  // a few workgroups per CU, each walking several 64-position tiles, so G
+  // is staged once per workgroup rather than once per tile
+  int64_t blocks = (count + 63) / 64;
+  const int64_t cap = 4 * (int64_t)num_cus();
+  if (blocks > cap) blocks = cap;
   if (nblocks_out) *nblocks_out = (int)blocks;
   if (epi && ctl.part_out != nullptr && blocks > kRedBlocks) return hipErrorInvalidConfiguration;
+  const bool vec = (count % 4 == 0) && (((uintptr_t)in) % 16 == 0) && (((uintptr_t)xnorm) % 16 == 0);
   TubeArgs ta{};
   ta.p = (int)p;
   ta.count = count;
@@ -339,18 +405,24 @@ static hipError_t launch_tube_mfma(dctk_ctx ctx, hipStream_t s, int64_t p, int64
   ta.xnorm = xnorm;
   ta.ctl = ctl;
   const dim3 grid((unsigned)blocks);
+#define DCTK_TMV(PM_, SC_, EP_) \
+  do { \
+    if (vec) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, SC_, EP_, true, false>, tube_mfma_kernel<TOUT, PM_, SC_, EP_, true, true>, grid, 256, 0, ta); \
+    return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, SC_, EP_, false, false>, tube_mfma_kernel<TOUT, PM_, SC_, EP_, false, true>, grid, 256, 0, ta); \
+  } while (0)
 #define DCTK_TM(PM_) \
   do { \
-    if (scale && epi) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, true, true, false>, tube_mfma_kernel<TOUT, PM_, true, true, true>, grid, 256, 0, ta); \
-    if (scale) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, true, false, false>, tube_mfma_kernel<TOUT, PM_, true, false, true>, grid, 256, 0, ta); \
-    if (epi) return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, false, true, false>, tube_mfma_kernel<TOUT, PM_, false, true, true>, grid, 256, 0, ta); \
-    return launch_kernel(ctx, s, tube_mfma_kernel<TOUT, PM_, false, false, false>, tube_mfma_kernel<TOUT, PM_, false, false, true>, grid, 256, 0, ta); \
+    if (scale && epi) DCTK_TMV(PM_, true, true); \
+    if (scale) DCTK_TMV(PM_, true, false); \
+    if (epi) DCTK_TMV(PM_, false, true); \
+    DCTK_TMV(PM_, false, false); \
   } while (0)
   if (p <= 16) DCTK_TM(16);
   if (p <= 32) DCTK_TM(32);
   if (p <= 48) DCTK_TM(48);
   DCTK_TM(64);
 #undef DCTK_TM
+#undef DCTK_TMV
 }
 
 template <typename TIN, typename TOUT, typename TC>
