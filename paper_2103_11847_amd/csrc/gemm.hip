@@ -27,7 +27,12 @@ struct GemmArgs {
   Gate g;
 };
 
-template <typename TI, typename TO, int BM, int BN, bool TA, bool TB>
+// VEC (16-bit types): operands move as 16-byte vectors of 8 elements along
+// their contiguous dimension (multiples of 8, 16-byte aligned): an operand
+// contiguous in k goes to its LDS rows as one 16-byte store, one contiguous
+// in m (or n) is transposed on the way, as eight 2-byte stores into eight
+// rows at one k.  All loads are issued from clamped addresses and selected.
+template <typename TI, typename TO, int BM, int BN, bool TA, bool TB, bool VEC>
 __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBlock vb, const bool grouped) {
   const int M = ga.M, N = ga.N, K = ga.K;
   const TI* __restrict__ A = (const TI*)ga.A;
@@ -113,6 +118,70 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
     }
   };
 
+  // vector staging (VEC): units of 8 elements along the contiguous dimension
+  constexpr int A_UV = (BM * BK / 8 + 255) / 256, B_UV = (BN * BK / 8 + 255) / 256;
+  struct H8 { TI v[8]; };
+  uint4 va[A_UV], vbv[B_UV];
+  // unit u of an operand tile of R rows: (row, k) of its first element and
+  // whether the 8 elements run along k (true) or along the rows
+  auto unit = [&](int u, int R, bool kcontig, int& r, int& kk) {
+    const int idx = tid + u * 256;
+    if (kcontig) { r = idx / (BK / 8); kk = (idx % (BK / 8)) * 8; }
+    else         { kk = idx / (R / 8); r = (idx % (R / 8)) * 8; }
+  };
+  auto load_vec = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < A_UV; ++u) {
+      int r, kk;
+      unit(u, BM, !TA, r, kk);
+      const int gm = m0 + r, gk = k0 + kk;
+      const bool ok = (BM * BK / 8) % 256 == 0 || tid + u * 256 < BM * BK / 8;
+      const bool in = ok && gm < M && gk < K;
+      const int64_t off = in ? (TA ? (int64_t)gk * lda + gm : (int64_t)gm * lda + gk) : 0;
+      const uint4 v = *reinterpret_cast<const uint4*>(A + off);
+      va[u] = in ? v : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < B_UV; ++u) {
+      int c, kk;
+      unit(u, BN, TB, c, kk);
+      const int gn = n0 + c, gk = k0 + kk;
+      const bool ok = (BN * BK / 8) % 256 == 0 || tid + u * 256 < BN * BK / 8;
+      const bool in = ok && gn < N && gk < K;
+      const int64_t off = in ? (TB ? (int64_t)gn * ldb + gk : (int64_t)gk * ldb + gn) : 0;
+      const uint4 v = *reinterpret_cast<const uint4*>(B + off);
+      vbv[u] = in ? v : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store_vec = [&]() {
+#pragma unroll
+    for (int u = 0; u < A_UV; ++u) {
+      if ((BM * BK / 8) % 256 != 0 && tid + u * 256 >= BM * BK / 8) continue;
+      int r, kk;
+      unit(u, BM, !TA, r, kk);
+      if (!TA) {
+        *reinterpret_cast<uint4*>(&As[r * LDS_LD + kk]) = va[u];
+      } else {
+        const H8 h = __builtin_bit_cast(H8, va[u]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) As[(r + j) * LDS_LD + kk] = h.v[j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < B_UV; ++u) {
+      if ((BN * BK / 8) % 256 != 0 && tid + u * 256 >= BN * BK / 8) continue;
+      int c, kk;
+      unit(u, BN, TB, c, kk);
+      if (TB) {
+        *reinterpret_cast<uint4*>(&Bs[c * LDS_LD + kk]) = vbv[u];
+      } else {
+        const H8 h = __builtin_bit_cast(H8, vbv[u]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bs[(c + j) * LDS_LD + kk] = h.v[j];
+      }
+    }
+  };
+
   frag_t acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -124,12 +193,19 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
   const int lr = lane & 15;          // row (A) / column (B) within a 16-block
   const int lk = (lane >> 4) * MF::EPL;  // first contraction index of this lane
 
-  load_tiles(0);
+  if constexpr (VEC) load_vec(0);
+  else load_tiles(0);
   for (int k0 = 0; k0 < K; k0 += BK) {
     __syncthreads();
-    store_tiles();
+    if constexpr (VEC) store_vec();
+    else store_tiles();
     __syncthreads();
-    if (k0 + BK < K) load_tiles(k0 + BK);  // prefetch the next chunk into registers
+    // prefetch the next chunk into registers
+    if constexpr (VEC) {
+      if (k0 + BK < K) load_vec(k0 + BK);
+    } else {
+      if (k0 + BK < K) load_tiles(k0 + BK);
+    }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += KSTEP) {
       const TI* ap[FM];
@@ -161,14 +237,14 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
     }
 }
 
-template <typename TI, typename TO, int BM, int BN, bool TA, bool TB, bool GROUPED>
+template <typename TI, typename TO, int BM, int BN, bool TA, bool TB, bool VEC, bool GROUPED>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
   if constexpr (!GROUPED) {
-    gemm_kernel_body<TI, TO, BM, BN, TA, TB>(ga_, hw_block(), false);
+    gemm_kernel_body<TI, TO, BM, BN, TA, TB, VEC>(ga_, hw_block(), false);
   } else {
     VBlock vb;
     const GemmArgs g = group_args(grp, bmap, vb);
-    gemm_kernel_body<TI, TO, BM, BN, TA, TB>(g, vb, true);
+    gemm_kernel_body<TI, TO, BM, BN, TA, TB, VEC>(g, vb, true);
   }
 }
 
@@ -396,7 +472,15 @@ static hipError_t launch_gemm_tile(dctk_ctx ctx, hipStream_t s, int M, int N, in
   ga.ldc = ldc;
   ga.sC = sC;
   ga.g = g;
-#define DCTK_GEMM_LAUNCH(TA_, TB_) return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_, false>, gemm_kernel<TI, TO, BM, BN, TA_, TB_, true>, grid, 256, 0, ga)
+  // 16-byte vectors: 8 elements along each operand's contiguous dimension
+  const bool va = (ta ? M % 8 == 0 : K % 8 == 0) && lda % 8 == 0 && sA % 8 == 0 && ((uintptr_t)A % 16) == 0;
+  const bool vb = (tb ? K % 8 == 0 : N % 8 == 0) && ldb % 8 == 0 && sB % 8 == 0 && ((uintptr_t)B % 16) == 0;
+  const bool vec = sizeof(TI) == 2 && va && vb;
+#define DCTK_GEMM_LAUNCH(TA_, TB_) \
+  do { \
+    if (vec) return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_, true, false>, gemm_kernel<TI, TO, BM, BN, TA_, TB_, true, true>, grid, 256, 0, ga); \
+    return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_, false, false>, gemm_kernel<TI, TO, BM, BN, TA_, TB_, false, true>, grid, 256, 0, ga); \
+  } while (0)
   if (!ta && !tb) DCTK_GEMM_LAUNCH(false, false);
   if (ta && !tb) DCTK_GEMM_LAUNCH(true, false);
   if (!ta && tb) DCTK_GEMM_LAUNCH(false, true);
@@ -408,9 +492,13 @@ template <typename TI, typename TO>
 static hipError_t launch_gemm_t(dctk_ctx ctx, hipStream_t s, int M, int N, int K, const void* A, int64_t lda, int64_t sA,
                                 int ta, const void* B, int64_t ldb, int64_t sB, int tb, void* C, int64_t ldc,
                                 int64_t sC, int batch, Gate g, int num_cus, int tile) {
-  // 64 x 64 tiles when they fill the chip, 32 x 32 otherwise.
+  // 128 x 128 tiles while they give every CU two, then 64 x 64 when they
+  // fill the chip, 32 x 32 otherwise.
+  const int64_t tiles128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128) * batch;
   int64_t tiles64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64) * batch;
-  if (tile == 64 || tile == 128 || (tile == 0 && tiles64 >= 2 * (int64_t)num_cus))
+  if (tile == 128 || (tile == 0 && tiles128 >= 2 * (int64_t)num_cus))
+    return launch_gemm_tile<TI, TO, 128, 128>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
+  if (tile == 64 || (tile == 0 && tiles64 >= 2 * (int64_t)num_cus))
     return launch_gemm_tile<TI, TO, 64, 64>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
   return launch_gemm_tile<TI, TO, 32, 32>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
 }
