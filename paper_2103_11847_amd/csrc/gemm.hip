@@ -118,67 +118,82 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
     }
   };
 
-  // vector staging (VEC): units of 8 elements along the contiguous dimension
-  constexpr int A_UV = (BM * BK / 8 + 255) / 256, B_UV = (BN * BK / 8 + 255) / 256;
+  // vector staging (VEC).  An operand contiguous in k moves in units of 8 k
+  // of one row (one 16-byte load and LDS store); an operand contiguous in its
+  // rows moves in units of 8 rows x 4 k (four 16-byte loads), transposed in
+  // registers into 8 rows of 4 consecutive k (eight 8-byte LDS stores).
   struct H8 { TI v[8]; };
-  uint4 va[A_UV], vbv[B_UV];
-  // unit u of an operand tile of R rows: (row, k) of its first element and
-  // whether the 8 elements run along k (true) or along the rows
+  struct H4 { TI v[4]; };
+  constexpr int A_NK = TA ? BM * BK / 32 : BM * BK / 8;   // units of the A tile
+  constexpr int B_NK = TB ? BN * BK / 8 : BN * BK / 32;
+  constexpr int A_UV = (A_NK + 255) / 256, B_UV = (B_NK + 255) / 256;
+  constexpr int A_L = TA ? 4 : 1, B_L = TB ? 1 : 4;        // 16-byte loads per unit
+  uint4 va[A_UV][A_L], vbv[B_UV][B_L];
+  // unit u of an operand tile of R rows: its first (row, k)
   auto unit = [&](int u, int R, bool kcontig, int& r, int& kk) {
     const int idx = tid + u * 256;
     if (kcontig) { r = idx / (BK / 8); kk = (idx % (BK / 8)) * 8; }
-    else         { kk = idx / (R / 8); r = (idx % (R / 8)) * 8; }
+    else         { kk = (idx / (R / 8)) * 4; r = (idx % (R / 8)) * 8; }
   };
   auto load_vec = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < A_UV; ++u) {
       int r, kk;
       unit(u, BM, !TA, r, kk);
-      const int gm = m0 + r, gk = k0 + kk;
-      const bool ok = (BM * BK / 8) % 256 == 0 || tid + u * 256 < BM * BK / 8;
-      const bool in = ok && gm < M && gk < K;
-      const int64_t off = in ? (TA ? (int64_t)gk * lda + gm : (int64_t)gm * lda + gk) : 0;
-      const uint4 v = *reinterpret_cast<const uint4*>(A + off);
-      va[u] = in ? v : make_uint4(0u, 0u, 0u, 0u);
+      const bool ok = A_NK % 256 == 0 || tid + u * 256 < A_NK;
+#pragma unroll
+      for (int l = 0; l < A_L; ++l) {
+        const int gm = m0 + r, gk = k0 + kk + l;
+        const bool in = ok && gm < M && gk < K;
+        const int64_t off = in ? (TA ? (int64_t)gk * lda + gm : (int64_t)gm * lda + gk) : 0;
+        const uint4 v = *reinterpret_cast<const uint4*>(A + off);
+        va[u][l] = in ? v : make_uint4(0u, 0u, 0u, 0u);
+      }
     }
 #pragma unroll
     for (int u = 0; u < B_UV; ++u) {
       int c, kk;
       unit(u, BN, TB, c, kk);
-      const int gn = n0 + c, gk = k0 + kk;
-      const bool ok = (BN * BK / 8) % 256 == 0 || tid + u * 256 < BN * BK / 8;
-      const bool in = ok && gn < N && gk < K;
-      const int64_t off = in ? (TB ? (int64_t)gn * ldb + gk : (int64_t)gk * ldb + gn) : 0;
-      const uint4 v = *reinterpret_cast<const uint4*>(B + off);
-      vbv[u] = in ? v : make_uint4(0u, 0u, 0u, 0u);
+      const bool ok = B_NK % 256 == 0 || tid + u * 256 < B_NK;
+#pragma unroll
+      for (int l = 0; l < B_L; ++l) {
+        const int gn = n0 + c, gk = k0 + kk + l;
+        const bool in = ok && gn < N && gk < K;
+        const int64_t off = in ? (TB ? (int64_t)gn * ldb + gk : (int64_t)gk * ldb + gn) : 0;
+        const uint4 v = *reinterpret_cast<const uint4*>(B + off);
+        vbv[u][l] = in ? v : make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+  };
+  // 8 rows x 4 k held as four 16-byte rows along the operand's rows -> LDS
+  auto put_t = [&](TI* S, int r, int kk, const uint4 (&q)[4]) {
+    H8 h[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) h[l] = __builtin_bit_cast(H8, q[l]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      H4 w;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) w.v[l] = h[l].v[j];
+      *reinterpret_cast<uint2*>(&S[(r + j) * LDS_LD + kk]) = __builtin_bit_cast(uint2, w);
     }
   };
   auto store_vec = [&]() {
 #pragma unroll
     for (int u = 0; u < A_UV; ++u) {
-      if ((BM * BK / 8) % 256 != 0 && tid + u * 256 >= BM * BK / 8) continue;
+      if (A_NK % 256 != 0 && tid + u * 256 >= A_NK) continue;
       int r, kk;
       unit(u, BM, !TA, r, kk);
-      if (!TA) {
-        *reinterpret_cast<uint4*>(&As[r * LDS_LD + kk]) = va[u];
-      } else {
-        const H8 h = __builtin_bit_cast(H8, va[u]);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) As[(r + j) * LDS_LD + kk] = h.v[j];
-      }
+      if constexpr (!TA) *reinterpret_cast<uint4*>(&As[r * LDS_LD + kk]) = va[u][0];
+      else put_t(As, r, kk, va[u]);
     }
 #pragma unroll
     for (int u = 0; u < B_UV; ++u) {
-      if ((BN * BK / 8) % 256 != 0 && tid + u * 256 >= BN * BK / 8) continue;
+      if (B_NK % 256 != 0 && tid + u * 256 >= B_NK) continue;
       int c, kk;
       unit(u, BN, TB, c, kk);
-      if (TB) {
-        *reinterpret_cast<uint4*>(&Bs[c * LDS_LD + kk]) = vbv[u];
-      } else {
-        const H8 h = __builtin_bit_cast(H8, vbv[u]);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) Bs[(c + j) * LDS_LD + kk] = h.v[j];
-      }
+      if constexpr (TB) *reinterpret_cast<uint4*>(&Bs[c * LDS_LD + kk]) = vbv[u][0];
+      else put_t(Bs, c, kk, vbv[u]);
     }
   };
 
