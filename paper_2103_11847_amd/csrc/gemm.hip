@@ -10,6 +10,8 @@
 // Global loads are ordered along each operand's contiguous dimension; the
 // next K-chunk is prefetched into registers while the current one is
 // multiplied.  Ragged edges are zero-filled on load and masked on store.
+#include <type_traits>
+
 #include "mfma.h"
 
 namespace dctk {
@@ -120,20 +122,23 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
 
   // vector staging (VEC).  An operand contiguous in k moves in units of 8 k
   // of one row (one 16-byte load and LDS store); an operand contiguous in its
-  // rows moves in units of 8 rows x 4 k (four 16-byte loads), transposed in
-  // registers into 8 rows of 4 consecutive k (eight 8-byte LDS stores).
+  // rows moves in units of 8 rows x KU k (KU 16-byte loads), transposed in
+  // registers into 8 rows of KU consecutive k (eight LDS stores of KU
+  // elements).
+  constexpr int KU = 8;
   struct H8 { TI v[8]; };
-  struct H4 { TI v[4]; };
-  constexpr int A_NK = TA ? BM * BK / 32 : BM * BK / 8;   // units of the A tile
-  constexpr int B_NK = TB ? BN * BK / 8 : BN * BK / 32;
+  struct HK { TI v[KU]; };
+  typedef typename std::conditional<KU == 8, uint4, uint2>::type kvec_t;
+  constexpr int A_NK = TA ? BM * BK / (8 * KU) : BM * BK / 8;   // units of the A tile
+  constexpr int B_NK = TB ? BN * BK / 8 : BN * BK / (8 * KU);
   constexpr int A_UV = (A_NK + 255) / 256, B_UV = (B_NK + 255) / 256;
-  constexpr int A_L = TA ? 4 : 1, B_L = TB ? 1 : 4;        // 16-byte loads per unit
+  constexpr int A_L = TA ? KU : 1, B_L = TB ? 1 : KU;       // 16-byte loads per unit
   uint4 va[A_UV][A_L], vbv[B_UV][B_L];
   // unit u of an operand tile of R rows: its first (row, k)
   auto unit = [&](int u, int R, bool kcontig, int& r, int& kk) {
     const int idx = tid + u * 256;
     if (kcontig) { r = idx / (BK / 8); kk = (idx % (BK / 8)) * 8; }
-    else         { kk = (idx / (R / 8)) * 4; r = (idx % (R / 8)) * 8; }
+    else         { kk = (idx / (R / 8)) * KU; r = (idx % (R / 8)) * 8; }
   };
   auto load_vec = [&](int k0) {
 #pragma unroll
@@ -165,17 +170,17 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
       }
     }
   };
-  // 8 rows x 4 k held as four 16-byte rows along the operand's rows -> LDS
-  auto put_t = [&](TI* S, int r, int kk, const uint4 (&q)[4]) {
-    H8 h[4];
+  // 8 rows x KU k held as KU 16-byte rows along the operand's rows -> LDS
+  auto put_t = [&](TI* S, int r, int kk, const uint4 (&q)[KU]) {
+    H8 h[KU];
 #pragma unroll
-    for (int l = 0; l < 4; ++l) h[l] = __builtin_bit_cast(H8, q[l]);
+    for (int l = 0; l < KU; ++l) h[l] = __builtin_bit_cast(H8, q[l]);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      H4 w;
+      HK w;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) w.v[l] = h[l].v[j];
-      *reinterpret_cast<uint2*>(&S[(r + j) * LDS_LD + kk]) = __builtin_bit_cast(uint2, w);
+      for (int l = 0; l < KU; ++l) w.v[l] = h[l].v[j];
+      *reinterpret_cast<kvec_t*>(&S[(r + j) * LDS_LD + kk]) = __builtin_bit_cast(kvec_t, w);
     }
   };
   auto store_vec = [&]() {
