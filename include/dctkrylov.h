@@ -249,9 +249,9 @@ typedef struct {
  * projected Tikhonov solution of eq. (normeq2) (lambda > 0 fixed, < 0 chosen
  * by GCV), computed in FP64 on the device.  With lambda != 0 the LSQR iterate
  * and search direction (dctk_krylov_basis which = 2, 3) are not formed, and
- * with no reorthogonalisation and both products fused each step's LSQR
- * update runs inside the next forward product (same recurrence, two
- * launches per step).  ws must be a DCTK_KRYLOV_GKB workspace of op.
+ * with no reorthogonalisation each step's LSQR update runs inside the next
+ * forward product (same recurrence; two launches per step when both products
+ * are fused, in the forward transform of the three-kernel product otherwise).  ws must be a DCTK_KRYLOV_GKB workspace of op.
  * C: p x n1 x s, X (output): p x n2 x s.  Synchronises once to fill info
  * and returns the solve's status; with info NULL the solve is only enqueued
  * on ctx's stream (no read-back, no synchronisation, DCTK_OK once enqueued),

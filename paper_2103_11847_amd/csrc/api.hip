@@ -590,11 +590,9 @@ static hipError_t gkb_step_impl(dctk_ctx ctx, dctk_krylov ws, int j, void* X) {
 }
 
 // Whether a solve without the LSQR iterate can fold each LSQR update into the
-// next forward product: both products fused, no reorthogonalisation.
-static bool merged_steps(dctk_krylov ws) {
-  dctk_op op = ws->op;
-  return ws->reorth == DCTK_REORTH_NONE && fused_eligible(op) && use_fused(op, 0) && use_fused(op, 1);
-}
+// next forward product (its first kernel, fused or the forward transform):
+// no reorthogonalisation.
+static bool merged_steps(dctk_krylov ws) { return ws->reorth == DCTK_REORTH_NONE; }
 
 // Step j of a Tikhonov solve (no LSQR iterate) with the update folded in:
 //   K1: unless j is the first step after an update that was flushed (pending =

@@ -598,8 +598,9 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   if (ctl.kind != CTL_PLAIN) {
     g.st = ctl.st;
     g.j = ctl.kind == CTL_ARN_FWD ? ctl.j - 1 : ctl.j;
-    g.mode = (ctl.kind == CTL_GKB_FWD) ? 0 : 1;
-    if (ctl.kind == CTL_GKB_FWD) g.j = ctl.j;
+    const bool fwd = ctl.kind == CTL_GKB_FWD || ctl.kind == CTL_GKB_FWDU;
+    g.mode = fwd ? 0 : 1;
+    if (fwd) g.j = ctl.j;
   }
   // step 2: slice products
   const int64_t sAh = n1 * n2;

@@ -382,7 +382,7 @@ __device__ inline CtlLoad ctl_load(const Ctl& c) {
   int ri = oB;
   ri = (fs && arn && j > 1) ? oH + (j - 1) * kMaxK + j - 2 : ri;
   ri = (fs && adj) ? oB + j : ri;
-  ri = fwd ? oA + j - 1 : ri;
+  ri = (fwd || (fs && fwdu)) ? oA + j - 1 : ri;
   L.rec = sd[ri];
   // breakdown scale: max |alpha_1..alpha_na|, |beta_1..beta_j| (GKB adjoint:
   // na = j; LSQR update of step j-1: na = j - 1) or max_i |h_{i, j-1}|
@@ -495,6 +495,11 @@ __device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, doubl
       return true;
     }
     case CTL_GKB_FWDU: {
+      if (c.from_state) {  // later kernels of an unfused product: as CTL_GKB_FWD
+        if (ss >= 0 || beyond) return false;
+        b = -rec;
+        return true;
+      }
       const int jp = j - 1;  // the pending update
       if ((ss >= 0 && ss < jp) || (kl > 0 && jp > kl)) return false;
       const GkbUpd u = gkb_update_scalars(st, jp, ps, pm, L.bn, L.rb, L.pb, L.tol, ss, L.sk, sh, first);
