@@ -140,6 +140,96 @@ __device__ __forceinline__ void tube_kernel_body(const TubeArgs& ta, const VBloc
   __syncthreads();
   double sq = 0.0;
   const int64_t stride = (int64_t)ta.gx * blockDim.x * 4;
+  if (p <= KB) {
+    // all p tubes of a 4-position group at once: every input (and src) load
+    // of the group is issued before the first use, from clamped addresses
+    const bool use_src = EPI && src != nullptr && b != (TC)0;
+    const TOUT* srcl = use_src ? src : out;
+    for (int64_t e0 = ((int64_t)vb.x * blockDim.x + threadIdx.x) * 4; e0 < count; e0 += stride) {
+      const int nv = (count - e0) < 4 ? (int)(count - e0) : 4;
+      TIN xv[KB][4];
+      if (VEC && nv == 4) {
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+          Vec4Load<TIN>::load(in + (int64_t)(t < p ? t : 0) * count + e0, xv[t]);
+          if (t >= p) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xv[t][v] = (TIN)0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < KB; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bool ok = t < p && v < nv;
+            const TIN x = in[ok ? (int64_t)t * count + e0 + v : 0];
+            xv[t][v] = ok ? x : (TIN)0;
+          }
+      }
+      TC sv[KB][4];
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sv[k][v] = (TC)0;
+      if (use_src) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bool ok = k < p && v < nv;
+            const TOUT x = srcl[ok ? (int64_t)k * count + e0 + v : 0];
+            sv[k][v] = ok ? (TC)x : (TC)0;
+          }
+      }
+      if (SCALE) {
+#pragma unroll
+        for (int t = 0; t < KB; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xv[t][v] = (TIN)(sc * (TC)xv[t][v]);
+        if (xnorm != nullptr) {
+#pragma unroll
+          for (int t = 0; t < KB; ++t) {
+            if (t < p) {
+              TIN* xp = xnorm + (int64_t)t * count + e0;
+              if (VEC && nv == 4) Vec4Store<TIN>::store(xp, xv[t]);
+              else for (int v = 0; v < nv; ++v) xp[v] = xv[t][v];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        if (k >= p) break;
+        TC acc[4] = {(TC)0, (TC)0, (TC)0, (TC)0};
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+          const TC gk = t < p ? sG[k * p + t] : (TC)0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[v] += gk * (TC)xv[t][v];
+        }
+        TOUT ov[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          TC r = a * acc[v];
+          if (EPI) r += b * sv[k][v];
+          ov[v] = cvt<TOUT, TC>(r);
+          if (EPI && v < nv) {
+            const double rv = (double)r;
+            sq += rv * rv;
+          }
+        }
+        TOUT* op = out + (int64_t)k * count + e0;
+        if (VEC && nv == 4) Vec4Store<TOUT>::store(op, ov);
+        else for (int v = 0; v < nv; ++v) op[v] = ov[v];
+      }
+    }
+    if (EPI && ctl.part_out != nullptr) {
+      const double tot = block_sum_all(sq, sh);
+      if (threadIdx.x == 0) ctl.part_out[vb.x] = tot;
+    }
+    return;
+  }
   for (int64_t e0 = ((int64_t)vb.x * blockDim.x + threadIdx.x) * 4; e0 < count; e0 += stride) {
     const int nv = (count - e0) < 4 ? (int)(count - e0) : 4;
     for (int k0 = 0; k0 < p; k0 += KB) {
