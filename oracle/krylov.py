@@ -152,13 +152,14 @@ def dc_lsqr(op, C, k, tol=0.0, reorth="none", history=False):
             "beta": list(g.beta), "status": status, "history": hist, "gkb": g}
 
 
-def dc_gk(op, C, k, lam=None, gcv_mode="rect", reorth="none"):
-    """Algorithm 5 (DC-GK): k Golub-Kahan steps, lambda by GCV (lam=None)
-    or fixed, projected Tikhonov solve, X = V_k (*) y (eq. xmlsqr)."""
+def dc_gk(op, C, k, lam=None, gcv_mode="rect", reorth="none", target=None):
+    """Algorithm 5 (DC-GK): k Golub-Kahan steps, lambda by GCV (lam=None) or
+    by the discrepancy principle (gcv_mode 'discrepancy', residual target) or
+    fixed, projected Tikhonov solve, X = V_k (*) y (eq. xmlsqr)."""
     g = gkb(op, C, k, reorth)
     kk = g.steps
     B = g.bidiagonal(kk)
-    y, lam_used = solve_projected(B, g.beta[0], lam, gcv_mode)
+    y, lam_used = solve_projected(B, g.beta[0], lam, gcv_mode, target)
     X = combine(g.V[:kk], y)
     return {"X": X, "lambda": lam_used, "iters": kk, "y": y, "alpha": list(g.alpha),
             "beta": list(g.beta), "status": "breakdown" if g.breakdown else "ok", "gkb": g}

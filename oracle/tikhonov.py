@@ -128,14 +128,62 @@ def gcv_minimize(sig, g, mode="rect"):
     return 10.0 ** ts[ib], vals[ib]
 
 
-def solve_projected(H, beta, lam=None, mode="rect"):
-    """Projected Tikhonov solve: lam=None selects lambda by GCV.
+def projected_residual(sig, g, lam):
+    """||beta e_1 - H y_lambda|| of the (m+1) x m projected problem:
+    sqrt(g_{m+1}^2 + sum_i (lambda^2 g_i / (sigma_i^2 + lambda^2))^2),
+    which for Golub-Kahan (orthonormal U) is ||C - M(X_lambda)||."""
+    m = sig.shape[0]
+    l2 = lam * lam
+    r2 = g[m] ** 2
+    for i in range(m):
+        r2 += (l2 * g[i] / (sig[i] ** 2 + l2)) ** 2
+    return float(np.sqrt(r2))
+
+
+DISC_TOL_LOG10 = 1e-12  # bisection stop: bracket width in log10(lambda)
+
+
+def discrepancy_lambda(sig, g, target):
+    """The discrepancy principle (Sec. 2, named with GCV as the paper's two
+    parameter rules): lambda with ||beta e_1 - H y_lambda|| = target, where the
+    caller passes target = eta * delta for a noise norm delta and a safety
+    factor eta >= 1.  The residual increases with lambda, so log10(lambda) is
+    bisected over the GCV range [sigma_1 1e-8, sigma_1]; when the target lies
+    below the residual at the smallest lambda (or above the one at sigma_1)
+    that end of the range is returned.  Returns (lambda, residual)."""
+    s1 = float(sig[0]) if sig.shape[0] > 0 else 0.0
+    if not s1 > 0.0:
+        return 0.0, float("nan")
+    a = np.log10(s1) - GCV_LO_DECADES
+    b = np.log10(s1)
+    ra = projected_residual(sig, g, 10.0 ** a)
+    rb = projected_residual(sig, g, 10.0 ** b)
+    if not ra < target:
+        return 10.0 ** a, ra
+    if not rb > target:
+        return 10.0 ** b, rb
+    while b - a > DISC_TOL_LOG10:
+        c = 0.5 * (a + b)
+        if projected_residual(sig, g, 10.0 ** c) < target:
+            a = c
+        else:
+            b = c
+    lam = 10.0 ** (0.5 * (a + b))
+    return lam, projected_residual(sig, g, lam)
+
+
+def solve_projected(H, beta, lam=None, mode="rect", target=None):
+    """Projected Tikhonov solve: lam=None selects lambda by GCV, or by the
+    discrepancy principle when mode is 'discrepancy' (target = eta delta).
 
     Returns (y, lambda).
     """
     sig, Vt, g = projected_svd(H, beta)
     if lam is None:
-        lam, _ = gcv_minimize(sig, g, mode)
+        if mode == "discrepancy":
+            lam, _ = discrepancy_lambda(sig, g, target)
+        else:
+            lam, _ = gcv_minimize(sig, g, mode)
     return tikhonov_y(sig, Vt, g, lam), lam
 
 

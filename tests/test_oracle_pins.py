@@ -438,6 +438,55 @@ def test_gcv_minimiser_against_brute_force(mode, seed):
     assert abs(val - f(sig, g, lam)) <= 1e-12 * val
 
 
+def _dense_residual(H, beta, lam):
+    """||beta e_1 - H y_lambda|| with y_lambda from the stacked least-squares
+    problem [H; lambda I] y = [beta e_1; 0] (no SVD)."""
+    r, m = H.shape
+    b = np.zeros(r)
+    b[0] = beta
+    y, *_ = np.linalg.lstsq(np.vstack([H, lam * np.eye(m)]), np.concatenate([b, np.zeros(m)]), rcond=None)
+    return float(np.linalg.norm(b - H @ y))
+
+
+@pytest.mark.parametrize("seed", [97, 101, 103])
+def test_discrepancy_lambda_meets_target(seed):
+    """The discrepancy principle's lambda: the residual of the dense stacked
+    least-squares solve at that lambda equals the target (to 1e-9), for
+    targets inside the attainable range; targets outside return the ends."""
+    H, beta = _rand_projected(seed, 10, True)
+    sig, Vt, g = tikhonov.projected_svd(H, beta)
+    lo = _dense_residual(H, beta, sig[0] * 1e-8)
+    hi = _dense_residual(H, beta, sig[0])
+    for f in (0.1, 0.5, 0.9):
+        target = lo + f * (hi - lo)
+        lam, res = tikhonov.discrepancy_lambda(sig, g, target)
+        assert sig[0] * 1e-8 < lam < sig[0]
+        assert abs(_dense_residual(H, beta, lam) - target) <= 1e-9 * target
+        assert abs(res - target) <= 1e-9 * target
+    lam, _ = tikhonov.discrepancy_lambda(sig, g, 0.5 * lo)
+    assert lam == pytest.approx(sig[0] * 1e-8, rel=1e-12)
+    lam, _ = tikhonov.discrepancy_lambda(sig, g, 2.0 * hi)
+    assert lam == pytest.approx(sig[0], rel=1e-12)
+
+
+def test_discrepancy_lambda_one_step_closed_form():
+    """k = 1: H = [alpha; beta_2] has sigma^2 = alpha^2 + beta_2^2,
+    g_1 = beta alpha / sigma, g_2 = beta beta_2 / sigma and the residual
+    r(lambda)^2 = g_2^2 + (q g_1)^2 with q = lambda^2 / (sigma^2 + lambda^2), so
+    the target T is met at lambda^2 = q sigma^2 / (1 - q),
+    q = sqrt(T^2 - g_2^2) / g_1 (q < 1/2 keeps lambda below sigma_1)."""
+    alpha, beta2, beta = 0.8, 0.3, 1.7
+    H = np.array([[alpha], [beta2]])
+    sig, Vt, g = tikhonov.projected_svd(H, beta)
+    s2 = alpha ** 2 + beta2 ** 2
+    g1, g2 = beta * alpha / np.sqrt(s2), beta * beta2 / np.sqrt(s2)
+    for q in (0.01, 0.2, 0.45):
+        target = np.sqrt(g2 ** 2 + (q * g1) ** 2)
+        lam_ref = np.sqrt(q * s2 / (1.0 - q))
+        lam, _ = tikhonov.discrepancy_lambda(sig, g, target)
+        assert lam == pytest.approx(lam_ref, rel=1e-10)
+
+
 # ------------------------------------------------------------------ metrics
 
 def test_snr_relerr_consistency():
