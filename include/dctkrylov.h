@@ -227,10 +227,13 @@ int dctk_krylov_copy(dctk_ctx ctx, dctk_krylov ws, int which, int j, void* dst);
 typedef struct {
   int k_max;        /* GKB steps (LSQR) or Arnoldi steps per cycle (GMRES), <= workspace k_max */
   int reorth;       /* DCTK_REORTH_* (GKB only) */
-  int gcv_mode;     /* 0: GCV of the rectangular projected problem; 1: eq. (gcv2) as printed */
+  int gcv_mode;     /* how lambda < 0 is chosen: 0: GCV of the rectangular projected problem;
+                       1: GCV as printed in eq. (gcv2); 2 (DC-GK only): the discrepancy principle
+                       (Sec. 2), lambda with ||C - M(X_lambda)|| = target */
   int reserved;
-  double lambda;    /* < 0: lambda by GCV; 0: no Tikhonov (LSQR iterate / GMRES LS); > 0: fixed */
+  double lambda;    /* < 0: lambda chosen by gcv_mode; 0: no Tikhonov (LSQR iterate / GMRES LS); > 0: fixed */
   double tol;       /* stop when the residual norm < tol; 0 runs k_max steps / all cycles */
+  double target;    /* gcv_mode 2: the residual norm eta * delta (noise norm delta, eta >= 1), > 0 */
 } dctk_solve_opts;
 
 typedef struct {

@@ -40,7 +40,8 @@ class DctkError(RuntimeError):
 
 class dctk_solve_opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int), ("reorth", ctypes.c_int), ("gcv_mode", ctypes.c_int),
-                ("reserved", ctypes.c_int), ("lam", ctypes.c_double), ("tol", ctypes.c_double)]
+                ("reserved", ctypes.c_int), ("lam", ctypes.c_double), ("tol", ctypes.c_double),
+                ("target", ctypes.c_double)]
 
 
 class dctk_solve_info(ctypes.Structure):
@@ -336,8 +337,8 @@ def dctk_krylov_basis(ws, which, j):
 
 
 # ---- solvers ----------------------------------------------------------------------------
-def make_opts(k_max, reorth=DCTK_REORTH_NONE, gcv_mode=0, lam=-1.0, tol=0.0):
-    return dctk_solve_opts(int(k_max), int(reorth), int(gcv_mode), 0, float(lam), float(tol))
+def make_opts(k_max, reorth=DCTK_REORTH_NONE, gcv_mode=0, lam=-1.0, tol=0.0, target=0.0):
+    return dctk_solve_opts(int(k_max), int(reorth), int(gcv_mode), 0, float(lam), float(tol), float(target))
 
 
 def dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=True):

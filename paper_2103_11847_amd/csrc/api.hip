@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "projected.h"
 
 static_assert(dctk::PROF_KINDS == DCTK_PROF_KINDS, "profiler kinds");
 
@@ -664,10 +665,12 @@ hipError_t lsqr_enqueue(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, co
   ws->host_steps = opts->k_max;
   ws->initialised = 1;
   if (tik) {
-    // Algorithm 5: lambda (GCV or fixed), y, X = V_k (*) y
+    // Algorithm 5: lambda (GCV, the discrepancy principle or fixed), y, X = V_k (*) y
     rec_phase(ctx);
-    if ((e = launch_projected(ctx, ws->st, 1, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda)) != hipSuccess)
-      return e;
+    e = (opts->gcv_mode == 2 && opts->lambda < 0.0)
+            ? launch_projected_disc(ctx, ws->st, opts->target)
+            : launch_projected(ctx, ws->st, 1, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda);
+    if (e != hipSuccess) return e;
     rec_phase(ctx);
     if ((e = launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, opts->k_max,
                             &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0})) != hipSuccess)
@@ -908,7 +911,8 @@ int dctk::check_solve_opts(const dctk_solve_opts* o, const dctk_krylov ws) {
   if (!o) return DCTK_EINVAL;
   if (o->k_max < 1 || o->k_max > ws->k_max) return DCTK_EINVAL;
   if (o->reorth < DCTK_REORTH_NONE || o->reorth > DCTK_REORTH_FULL) return DCTK_EINVAL;
-  if (o->gcv_mode != 0 && o->gcv_mode != 1) return DCTK_EINVAL;
+  if (o->gcv_mode < 0 || o->gcv_mode > 2) return DCTK_EINVAL;
+  if (o->gcv_mode == 2 && o->lambda < 0.0 && !(o->target > 0.0 && std::isfinite(o->target))) return DCTK_EINVAL;
   if (std::isnan(o->lambda) || std::isinf(o->lambda)) return DCTK_EINVAL;
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return DCTK_EINVAL;
   return DCTK_OK;
@@ -938,11 +942,16 @@ int dctk_krylov_project(dctk_ctx ctx, dctk_krylov ws, int k, const dctk_solve_op
   if (r) return r;
   if (!X || !opts) return DCTK_EINVAL;
   if (!ws->initialised || k < 1 || k > ws->host_steps) return DCTK_EINVAL;
-  if (opts->gcv_mode != 0 && opts->gcv_mode != 1) return DCTK_EINVAL;
+  if (opts->gcv_mode < 0 || opts->gcv_mode > 2) return DCTK_EINVAL;
+  if (opts->gcv_mode == 2 && opts->lambda < 0.0 && !(opts->target > 0.0 && std::isfinite(opts->target)))
+    return DCTK_EINVAL;
   if (std::isnan(opts->lambda) || std::isinf(opts->lambda) || opts->lambda == 0.0) return DCTK_EINVAL;
   dctk_op op = ws->op;
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
-  DCTK_HIP(ctx, launch_projected(ctx, ws->st, 1, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda, k));
+  if (opts->gcv_mode == 2 && opts->lambda < 0.0)
+    DCTK_HIP(ctx, launch_projected_disc(ctx, ws->st, opts->target, k));
+  else
+    DCTK_HIP(ctx, launch_projected(ctx, ws->st, 1, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda, k));
   // the basis vectors beyond a breakdown are never formed: combine min(k, steps) of them
   DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, k,
                                &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
@@ -967,7 +976,7 @@ int dctk_lsqr_learned_solve(dctk_ctx ctx, dctk_krylov ws, dctk_mlp mlp, const vo
   if (r) return r;
   if (!C || !X || !mlp) return DCTK_EINVAL;
   if ((r = check_solve_opts(opts, ws))) return r;
-  if (opts->lambda >= 0.0 || !(gate >= 1.0) || !std::isfinite(gate)) return DCTK_EINVAL;
+  if (opts->lambda >= 0.0 || opts->gcv_mode == 2 || !(gate >= 1.0) || !std::isfinite(gate)) return DCTK_EINVAL;
   const int kf = 8;  // steps whose scalars feed the network
   if (opts->k_max < kf) return DCTK_EINVAL;
   dctk_op op = ws->op;
@@ -1002,6 +1011,7 @@ int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, i
   if (!C || !X) return DCTK_EINVAL;
   if (cycles < 1) return DCTK_EINVAL;
   if ((r = check_solve_opts(opts, ws))) return r;
+  if (opts->gcv_mode == 2) return DCTK_EINVAL;  // the discrepancy principle: DC-GK only
   dctk_op op = ws->op;
   const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
   const int64_t n = op->p * op->n1 * op->s;

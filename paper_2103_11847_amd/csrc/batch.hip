@@ -77,7 +77,8 @@ int dctk_batch_create(dctk_ctx ctx, int count, const dctk_krylov* ws, const void
   if (!ctx || !ws || !C || !X || !opts) return DCTK_EINVAL;
   if (count < 1 || count > DCTK_BATCH_MAX) return DCTK_EINVAL;
   if (ctx->rec) return DCTK_ESTATE;
-  if (mlp && (opts->lambda >= 0.0 || opts->k_max < 8 || !(gate >= 1.0) || !std::isfinite(gate))) return DCTK_EINVAL;
+  if (mlp && (opts->lambda >= 0.0 || opts->gcv_mode == 2 || opts->k_max < 8 || !(gate >= 1.0) || !std::isfinite(gate)))
+    return DCTK_EINVAL;
   for (int i = 0; i < count; ++i) {
     if (!ws[i] || !C[i] || !X[i]) return DCTK_EINVAL;
     if (ws[i]->kind != DCTK_KRYLOV_GKB || ws[i]->op->ctx->device != ctx->device) return DCTK_EINVAL;

@@ -27,6 +27,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "projected.h"
 
 namespace dctk {
 
@@ -220,6 +221,7 @@ struct ProjArgs {
   double lam_cand;   // > 0 (with GCV): a proposed lambda, kept when GCV(lam_cand) <= gate * min GCV
   double gate;
   int cand_from_state;  // 1: the proposed lambda is st->pred_lambda (learned stop)
+  double target;        // gcv_mode 2 (discrepancy principle): the residual norm lambda is chosen for
 };
 
 __device__ __forceinline__ void k_projected_body(const ProjArgs& a, const VBlock vb, const bool grouped) {
@@ -609,7 +611,7 @@ __device__ inline int gk_count_below(double x, int n2, const double* e2, double 
 // writes y to yout when it is not null).  Each step's operands are loaded one
 // step ahead, off the recurrence's dependency chain.
 __device__ inline double gk_gcv(double lam, int k, const double* a, const double* b, double beta, double* q,
-                                double* w, int ld, double* yout) {
+                                double* w, int ld, double* yout, double* res2 = nullptr) {
   const double l2 = lam * lam;
   double rbar = a[0], fbar = beta, th = 0.0, tcol = 0.0, tr = 0.0;
   double bn = b[0], an = a[min(1, k - 1)];
@@ -648,6 +650,7 @@ __device__ inline double gk_gcv(double lam, int k, const double* a, const double
   }
   const double r0 = fma(-a[0], yn, beta);
   rr = fma(r0, r0, rr);
+  if (res2 != nullptr) *res2 = rr;
   const double den = fma(l2, tr, 1.0);
   return rr / (den * den);
 }
@@ -727,6 +730,58 @@ __device__ __forceinline__ void k_projected_gk_body(const ProjArgs& a, const VBl
     const double sig1 = 0.5 * (s_lo + s_hi);
     if (!(sig1 > 0.0)) {
       lam = 0.0;
+    } else if (a.gcv_mode == 2) {
+      // The discrepancy principle: lambda with ||beta e_1 - C~ y_lambda|| equal
+      // to the target.  The residual increases with lambda: the range
+      // [1e-8 sigma_1, sigma_1] of t = log10(lambda) is cut in passes of np
+      // points (one per thread), keeping the cell where the residual first
+      // reaches the target, until it is narrower than 1e-12; the ends of the
+      // range are returned for targets outside it.
+      const double tt2 = a.target * a.target;
+      const int nb = min(kRP, kRecD / (2 * k));
+      const double t1 = log10(sig1), t0 = t1 - 8.0;
+      if (tid < 2) {
+        double r2;
+        (void)gk_gcv(exp10(tid == 0 ? t0 : t1), k, ab_a, ab_b, beta, rec + tid, rec + k * 2 + tid, 2, nullptr, &r2);
+        refv[tid] = r2;
+      }
+      __syncthreads();
+      const double r2a = refv[0], r2b = refv[1];
+      if (!(r2a < tt2)) {
+        lam = exp10(t0);
+      } else if (!(r2b > tt2)) {
+        lam = exp10(t1);
+      } else {
+        if (tid == 0) { s_ra = t0; s_rb = t1; }
+        __syncthreads();
+        for (int pass = 0; pass < 12; ++pass) {
+          const double ra = s_ra, rb = s_rb;
+          if (!(rb - ra > 1e-12)) break;
+          const double h = (rb - ra) / (double)(nb + 1);
+          __syncthreads();  // every thread has read the bracket
+          if (tid < nb) {
+            double r2;
+            (void)gk_gcv(exp10(ra + (double)(tid + 1) * h), k, ab_a, ab_b, beta, rec + tid, rec + k * nb + tid, nb,
+                         nullptr, &r2);
+            refv[tid] = r2;
+          }
+          __syncthreads();
+          if (tid < 64) {
+            // first point whose residual reaches the target (nb: none)
+            int fi = nb;
+            for (int i = lane; i < nb; i += 64)
+              if (!(refv[i] < tt2)) { fi = i; break; }
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) fi = min(fi, __shfl_xor(fi, m));
+            if (lane == 0) {
+              s_ra = fi == 0 ? ra : ra + (double)fi * h;
+              s_rb = fi == nb ? rb : ra + (double)(fi + 1) * h;
+            }
+          }
+          __syncthreads();
+        }
+        lam = exp10(0.5 * (s_ra + s_rb));
+      }
     } else {
       // the 400-point grid, as many lambdas per pass as the row storage holds
       // (each thread reuses its own slot: no barrier between passes)
@@ -874,6 +929,19 @@ __global__ __launch_bounds__(kPT) void k_projected_gk(ProjArgs a_, const ProjArg
     const ProjArgs g = group_args(grp, bmap, vb);
     k_projected_gk_body(g, vb, true);
   }
+}
+
+hipError_t launch_projected_disc(dctk_ctx ctx, KState* st, double target, int k_use) {
+  ProjArgs a{};
+  a.bidiag = 1;
+  a.gcv_mode = 2;
+  a.k_use = k_use;
+  a.st = st;
+  a.lam_fixed = -1.0;
+  a.lam_cand = -1.0;
+  a.gate = 1.0;
+  a.target = target;
+  return launch_kernel(ctx, ctx->stream, k_projected_gk<false>, k_projected_gk<true>, dim3(1), kPT, 0, a);
 }
 
 hipError_t launch_projected(dctk_ctx ctx, KState* st, int bidiag, int gcv_mode, double lambda, int k_use,

@@ -401,6 +401,54 @@ def test_gk_projected_gcv_every_k(ctx):
     dk.dctk_krylov_destroy(ws)
 
 
+@pytest.mark.parametrize("where", ["noise", "middle"])
+def test_gk_discrepancy_matches_oracle(ctx, where):
+    """lambda by the discrepancy principle (gcv_mode 2) at k = 12 on the
+    32 x 32 x 3 colour problem, FP64: the target is 1.05 times the norm of the
+    added noise, or the middle of the residuals reachable on the lambda range.
+    The library's lambda is the oracle's (1e-8), its projected residual meets
+    the target (1e-8, when inside the range), X is the oracle's X at it, and
+    dctk_krylov_project gives the same lambda from the stepped workspace."""
+    w, N0, C = _colour_small_problem()
+    op = Op(ctx, w["A"], None, 32, dk.DCTK_F64)
+    k = 12
+    g = krylov.gkb(op.oracle, C, k, reorth="full")
+    sig, Vt, gg = tikhonov.projected_svd(g.bidiagonal(k), g.beta[0])
+    if where == "noise":
+        Ch = op.oracle.apply(w["X_true"])
+        target = 1.05 * w["nu"] * fro(Ch)
+    else:
+        r_lo = tikhonov.projected_residual(sig, gg, sig[0] * 1e-8)
+        r_hi = tikhonov.projected_residual(sig, gg, sig[0])
+        target = np.sqrt(r_lo * r_hi)
+    lam_ref, res_ref = tikhonov.discrepancy_lambda(sig, gg, target)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    X = torch.empty(C.shape, dtype=F64, device="cuda:0")
+    opts = dk.make_opts(k, dk.DCTK_REORTH_FULL, 2, -1.0, 0.0, target)
+    info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, opts)
+    say("discrepancy", where, "target", target, "lambda", info.lam, lam_ref, "res", res_ref)
+    assert abs(info.lam - lam_ref) <= 1e-8 * lam_ref
+    inside = sig[0] * 1e-8 * (1 + 1e-9) < lam_ref < sig[0] * (1 - 1e-9)
+    if inside:
+        assert abs(tikhonov.projected_residual(sig, gg, info.lam) - target) <= 1e-8 * target
+    ref = krylov.dc_gk(op.oracle, C, k, lam=info.lam, reorth="full")
+    assert rel(to_np(X), ref["X"]) <= 1e-9
+    Xp = torch.empty_like(X)
+    ip = dk.dctk_krylov_project(ctx, ws, k, opts, Xp)
+    assert ip.lam == info.lam
+    assert np.array_equal(to_np(Xp), to_np(X))
+    # a non-positive target and DC-GMRES are rejected
+    with pytest.raises(dk.DctkError) as e:
+        dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(k, dk.DCTK_REORTH_FULL, 2, -1.0, 0.0, 0.0))
+    assert e.value.status == dk.DCTK_EINVAL
+    wa = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_ARNOLDI, 4)
+    with pytest.raises(dk.DctkError) as e:
+        dk.dctk_gmres_tik_solve(ctx, wa, to_gpu(C, F64), X, 1, dk.make_opts(4, 0, 2, -1.0, 0.0, target))
+    assert e.value.status == dk.DCTK_EINVAL
+    dk.dctk_krylov_destroy(wa)
+    dk.dctk_krylov_destroy(ws)
+
+
 @pytest.mark.parametrize("lam", [0.05, -1.0])
 def test_gk_folded_updates_match_oracle(ctx, lam):
     """Tikhonov solve (no reorthogonalisation, both products fused), where each
