@@ -72,6 +72,9 @@ def parse():
                     help="batch64: train the stopping network on the library's own solves of 256 smaller "
                          "problems of the same family, run the batch with the learned stop, and compare "
                          "with plain FP32 single solves")
+    ap.add_argument("--lambda-rule", default="gcv", choices=["gcv", "discrepancy"],
+                    help="colour256: lambda by GCV (default) or by the discrepancy principle at 1.05 x the "
+                         "norm of the added noise")
     ap.add_argument("--workload", default="colour256", choices=["colour256", "batch64", "video256", "hyper512"],
                     help="colour256: one 256x256x3 solve per step (default); batch64: the uneven "
                          "64-instance batch per step (merged launches, HIP graph)")
@@ -89,19 +92,21 @@ def blas_threads():
     return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
 
 
-def oracle_leg(w, C_ref_builder, budget_s):
-    """FP64 oracle: restoration error on the same input, and timed solves (bounded sample)."""
+def oracle_leg(w, C_ref_builder, budget_s, target=None):
+    """FP64 oracle: restoration error on the same input, and timed solves (bounded sample).
+    target: lambda by the discrepancy principle at this residual norm (else GCV)."""
     from oracle import krylov, metrics
     from oracle.cprod import Operator, fro
     op = Operator(w["A"])
     Ch = op.apply(w["X_true"])
     C = Ch + w["nu"] * fro(Ch) / fro(w["N0"]) * w["N0"]
-    ref = krylov.dc_gk(op, C, w["iters"], lam=None, gcv_mode="rect", reorth="none")
+    mode = "rect" if target is None else "discrepancy"
+    ref = krylov.dc_gk(op, C, w["iters"], lam=None, gcv_mode=mode, reorth="none", target=target)
     err = metrics.relative_error(w["X_true"], ref["X"])
     n = 0
     t0 = time.perf_counter()
     while True:
-        krylov.dc_gk(op, C, w["iters"], lam=None, gcv_mode="rect", reorth="none")
+        krylov.dc_gk(op, C, w["iters"], lam=None, gcv_mode=mode, reorth="none", target=target)
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
@@ -146,7 +151,13 @@ def main():
     C = C64.to(torch.float32).contiguous()
     X = torch.empty_like(C)
     ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k)
-    opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0, 0.0)
+    # lambda by GCV, or by the discrepancy principle at 1.05 x the added noise's norm
+    target = None
+    if args.lambda_rule == "discrepancy":
+        target = 1.05 * float(w["nu"]) * float(torch.linalg.norm(Ch))
+        opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 2, -1.0, 0.0, target)
+    else:
+        opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0, 0.0)
 
     for _ in range(args.warmup):
         info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
@@ -237,11 +248,12 @@ def main():
     err_oracle = None
     lam_oracle = None
     if not args.no_cpu_baseline:
-        err_oracle, lam_oracle, cps, nsolve, dt = oracle_leg(w, None, args.cpu_seconds)
+        err_oracle, lam_oracle, cps, nsolve, dt = oracle_leg(w, None, args.cpu_seconds, target)
         threads = blas_threads()
         cpu = {"value": cps, "unit": "solves/s", "cores": threads, "kind": "oracle",
-               "sample": "%d full FP64 DC-GK solves (40 GKB steps + GCV) of the same 256x256x3 workload "
-                         "in %.1f s (numpy, BLAS matmul)" % (nsolve, dt)}
+               "sample": "%d full FP64 DC-GK solves (40 GKB steps + %s) of the same 256x256x3 workload "
+                         "in %.1f s (numpy, BLAS matmul)"
+                         % (nsolve, "GCV" if target is None else "discrepancy principle", dt)}
     gate_ok = (err_oracle is None) or (err_gpu <= 1.05 * err_oracle)
     solves_per_s = 1e3 / ms_per_step
     value = solves_per_s if gate_ok else 0.0
@@ -259,7 +271,9 @@ def main():
         "vs_baseline": None,
         "dtype": args.gemm if args.gemm != "f32" else "f32",
         "data": "synthetic",
-        "config": {"workload": "colour deblur 256x256x3, DC-LSQR/DC-GK 40 GKB steps + FP64 GCV, one solve per step",
+        "config": {"workload": "colour deblur 256x256x3, DC-LSQR/DC-GK 40 GKB steps + FP64 %s, one solve per step"
+                               % ("GCV" if target is None else "discrepancy principle"),
+                   "lambda_rule": args.lambda_rule,
                    "n1": n, "n2": n, "s": s, "n3": p, "gkb_steps": k, "gemm_dtype": args.gemm,
                    "vector_dtype": "f32", "reorth": "none", "tube": "th"},
         "roofline": roof,
