@@ -172,6 +172,53 @@ def discrepancy_lambda(sig, g, target):
     return lam, projected_residual(sig, g, lam)
 
 
+def lcurve_points(H, beta, kmax):
+    """The L-curve of the stopping index (Sec. 3.2, after Algorithm 6): for
+    k = 1..kmax the LSQR iterate's residual ||beta e_1 - H_k y_k|| and norm
+    ||y_k|| (= ||C - M(X_k)|| and ||X_k|| for Golub-Kahan), where H_k is the
+    leading (k+1) x k block and y_k its least-squares solution (lstsq)."""
+    res, nrm = [], []
+    for k in range(1, kmax + 1):
+        Hk = np.asarray(H, dtype=np.float64)[: k + 1, :k]
+        b = np.zeros(k + 1)
+        b[0] = beta
+        y, *_ = np.linalg.lstsq(Hk, b, rcond=None)
+        res.append(float(np.linalg.norm(b - Hk @ y)))
+        nrm.append(float(np.linalg.norm(y)))
+    return np.array(res), np.array(nrm)
+
+
+def menger_curvature(p0, p1, p2):
+    """Signed curvature of the circle through three points of the plane:
+    2 cross(p1 - p0, p2 - p1) / (|p1 - p0| |p2 - p1| |p2 - p0|), positive
+    for a left turn."""
+    a = (p1[0] - p0[0], p1[1] - p0[1])
+    b = (p2[0] - p1[0], p2[1] - p1[1])
+    c = (p2[0] - p0[0], p2[1] - p0[1])
+    den = np.hypot(*a) * np.hypot(*b) * np.hypot(*c)
+    if not den > 0.0:
+        return 0.0
+    return 2.0 * (a[0] * b[1] - a[1] * b[0]) / den
+
+
+def lcurve_corner(res, nrm):
+    """The corner of the L-curve (log ||R_k||, log ||X_k||), k = 1..K: the
+    interior point of largest signed curvature (first one on ties), traced
+    with the residual decreasing, so the corner is a right turn and its
+    curvature is taken with the sign flipped.  Returns k (1-based); K when
+    there are fewer than three points or no point bends that way."""
+    K = len(res)
+    if K < 3:
+        return K
+    pts = [(np.log10(res[i]), np.log10(nrm[i])) for i in range(K)]
+    best, kbest = 0.0, K
+    for i in range(1, K - 1):
+        kap = -menger_curvature(pts[i - 1], pts[i], pts[i + 1])
+        if kap > best:
+            best, kbest = kap, i + 1
+    return kbest
+
+
 def solve_projected(H, beta, lam=None, mode="rect", target=None):
     """Projected Tikhonov solve: lam=None selects lambda by GCV, or by the
     discrepancy principle when mode is 'discrepancy' (target = eta delta).

@@ -487,6 +487,41 @@ def test_discrepancy_lambda_one_step_closed_form():
         assert lam == pytest.approx(lam_ref, rel=1e-10)
 
 
+def test_lcurve_points_are_lsqr_residuals_and_norms():
+    """The L-curve points from least squares on the leading blocks of C~_k
+    equal Algorithm 6's |phibar_{k+1}| and ||X_k||_F of the LSQR iterates."""
+    op, C = _problem(seed=107, p=3, n=6, s=4)
+    K = 6
+    ref = krylov.dc_lsqr(op, C, K, reorth="full", history=True)
+    g = ref["gkb"]
+    res, nrm = tikhonov.lcurve_points(g.bidiagonal(K), g.beta[0], K)
+    for k in range(1, K + 1):
+        rk = krylov.dc_lsqr(op, C, k, reorth="full")["resnorm"]
+        assert abs(res[k - 1] - rk) <= 1e-10 * max(rk, 1e-300) + 1e-14
+        assert abs(nrm[k - 1] - np.linalg.norm(ref["history"][k - 1])) <= 1e-10 * nrm[k - 1]
+
+
+def test_menger_curvature_circle_and_sign():
+    """Three points on a circle of radius 2 have curvature 1/2, positive for a
+    counter-clockwise (left) turn and negative for the reverse order;
+    collinear points have curvature 0."""
+    pts = [(2.0 * np.cos(t), 2.0 * np.sin(t)) for t in (0.1, 0.7, 1.6)]
+    assert tikhonov.menger_curvature(*pts) == pytest.approx(0.5, rel=1e-12)
+    assert tikhonov.menger_curvature(*pts[::-1]) == pytest.approx(-0.5, rel=1e-12)
+    assert tikhonov.menger_curvature((0, 0), (1, 1), (3, 3)) == 0.0
+
+
+def test_lcurve_corner_of_a_right_angle():
+    """A polyline going left along a horizontal line and then up a vertical
+    one (in log-log coordinates) has its corner at the vertex."""
+    xs = [4.0, 3.0, 2.0, 1.0, 1.0, 1.0, 1.0]
+    ys = [0.0, 0.0, 0.0, 0.0, 1.0, 2.0, 3.0]
+    res = 10.0 ** np.array(xs)
+    nrm = 10.0 ** np.array(ys)
+    assert tikhonov.lcurve_corner(res, nrm) == 4
+    assert tikhonov.lcurve_corner(res[:2], nrm[:2]) == 2
+
+
 # ------------------------------------------------------------------ metrics
 
 def test_snr_relerr_consistency():
