@@ -268,6 +268,20 @@ int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X,
 int dctk_gmres_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, int cycles,
                          const dctk_solve_opts* opts, dctk_solve_info* info);
 
+/* LSQR with the stopping index from the L-curve (Sec. 3.2, after Algorithm
+ * 6): runs k_max Golub-Kahan steps (opts->lambda and gcv_mode are ignored;
+ * reorth and tol as for dctk_lsqr_tik_solve), evaluates for every k the
+ * LSQR iterate's residual ||C - M(X_k)|| = |phibar_{k+1}| and norm ||X_k||
+ * from the projected bidiagonal in FP64 on the device, takes as k_opt the
+ * corner of the curve (log ||R_k||, log ||X_k||): the interior point of
+ * largest curvature of the circle through it and its neighbours, turning the
+ * way an L-curve's corner turns (k_opt = steps taken when no point does), and
+ * returns X = X_{k_opt}.  info->resnorm is its residual norm, *k_opt (may be
+ * NULL) the index.  Synchronises once.  ws must be a DCTK_KRYLOV_GKB
+ * workspace of op; C: p x n1 x s, X (output): p x n2 x s. */
+int dctk_lsqr_lcurve_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X,
+                           const dctk_solve_opts* opts, dctk_solve_info* info, int* k_opt);
+
 /* Algorithm 5 at step count k from the bases a finished (or stepped) GKB
  * workspace holds: the projected Tikhonov solution of the first k steps (k in
  * [1, steps enqueued]; lambda fixed (> 0) or by GCV (< 0); opts->k_max, reorth

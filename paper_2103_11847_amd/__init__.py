@@ -90,6 +90,8 @@ _SIGS = {
     "dctk_krylov_basis": (_I, [_P, _I, _I, ctypes.POINTER(_P)]),
     "dctk_krylov_copy": (_I, [_P, _P, _I, _I, _P]),
     "dctk_lsqr_tik_solve": (_I, [_P, _P, _P, _P, ctypes.POINTER(dctk_solve_opts), ctypes.POINTER(dctk_solve_info)]),
+    "dctk_lsqr_lcurve_solve": (_I, [_P, _P, _P, _P, ctypes.POINTER(dctk_solve_opts), ctypes.POINTER(dctk_solve_info),
+                                    ctypes.POINTER(_I)]),
     "dctk_gmres_tik_solve": (_I, [_P, _P, _P, _P, _I, ctypes.POINTER(dctk_solve_opts),
                                   ctypes.POINTER(dctk_solve_info)]),
     "dctk_krylov_project": (_I, [_P, _P, _I, ctypes.POINTER(dctk_solve_opts), _P, ctypes.POINTER(dctk_solve_info)]),
@@ -351,6 +353,15 @@ def dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=True):
     _check(lib().dctk_lsqr_tik_solve(ctx, ws, _ptr(C), _ptr(X), ctypes.byref(opts), ctypes.byref(out)),
            "dctk_lsqr_tik_solve")
     return out
+
+
+def dctk_lsqr_lcurve_solve(ctx, ws, C, X, opts):
+    """LSQR stopped at the L-curve corner; returns (info, k_opt)."""
+    out = dctk_solve_info()
+    k = _I()
+    _check(lib().dctk_lsqr_lcurve_solve(ctx, ws, _ptr(C), _ptr(X), ctypes.byref(opts), ctypes.byref(out),
+                                        ctypes.byref(k)), "dctk_lsqr_lcurve_solve")
+    return out, k.value
 
 
 def dctk_gmres_tik_solve(ctx, ws, C, X, cycles, opts):

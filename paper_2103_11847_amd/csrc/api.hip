@@ -936,6 +936,40 @@ int dctk_lsqr_tik_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, co
   return lsqr_info(ctx, ws, opts, info);
 }
 
+int dctk_lsqr_lcurve_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, const dctk_solve_opts* opts,
+                           dctk_solve_info* info, int* k_opt) {
+  int r = ws_check(ctx, ws, DCTK_KRYLOV_GKB);
+  if (r) return r;
+  if (!C || !X) return DCTK_EINVAL;
+  if ((r = check_solve_opts(opts, ws))) return r;
+  dctk_op op = ws->op;
+  const size_t ve = op->vec_dtype == DCTK_F64 ? 8 : 4;
+  if (ranges_overlap(C, (size_t)(op->p * op->n1 * op->s) * ve, X, (size_t)(op->p * op->n2 * op->s) * ve))
+    return DCTK_EINVAL;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  ws->reorth = opts->reorth;
+  DCTK_HIP(ctx, gkb_init_impl(ctx, ws, C, nullptr, opts->tol));
+  DCTK_HIP(ctx, gkb_steps_tik(ctx, ws, 1, opts->k_max));
+  ws->host_steps = opts->k_max;
+  ws->initialised = 1;
+  DCTK_HIP(ctx, launch_lcurve(ctx, ws->st));
+  DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, opts->k_max,
+                               &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
+  static thread_local KState hk;
+  if ((r = read_state_lsqr(ctx, ws, &hk))) return r;
+  if (info) {
+    info->iters = hk.steps;
+    info->status = hk.status;
+    info->converged = hk.converged;
+    info->cycles = 0;
+    info->lambda = 0.0;
+    info->resnorm = hk.resnorm;
+    info->gcv = NAN;
+  }
+  if (k_opt) *k_opt = hk.steps > 0 ? (int)hk.sweeps : 0;
+  return hk.status;
+}
+
 int dctk_krylov_project(dctk_ctx ctx, dctk_krylov ws, int k, const dctk_solve_opts* opts, void* X,
                         dctk_solve_info* info) {
   int r = ws_check(ctx, ws, DCTK_KRYLOV_GKB);

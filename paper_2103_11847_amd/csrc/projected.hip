@@ -931,6 +931,115 @@ __global__ __launch_bounds__(kPT) void k_projected_gk(ProjArgs a_, const ProjArg
   }
 }
 
+// ---- the L-curve of the stopping index -------------------------------------
+// For k = 1..K (K = steps taken) the least-squares solution y_k of the leading
+// (k+1) x k block of C~ (the LSQR iterate X_k = V_k y_k) by plane rotations,
+// its residual |phibar_{k+1}| and norm ||y_k|| (one lane per k, the rows of
+// the back substitution in LDS); the corner of (log ||R_k||, log ||X_k||) is
+// the interior point of largest curvature of the circle through it and its
+// neighbours (taken with the sign of a right turn, the curve being traced
+// with the residual decreasing); y of the corner goes to st->y, zero beyond it.
+__device__ inline void gk_ls(int k, const double* a, const double* b, double beta, double* q, double* w, int ld,
+                             double& res, double& ynorm, double* yout) {
+  double rbar = a[0], fbar = beta;
+  for (int i = 0; i < k; ++i) {
+    const double bn = b[i];
+    const double r = sqrt(rbar * rbar + bn * bn);
+    const double c = r > 0.0 ? rbar / r : 1.0, sn = r > 0.0 ? bn / r : 0.0;
+    const double ir = r > 0.0 ? 1.0 / r : 0.0;
+    q[i * ld] = (c * fbar) * ir;
+    if (i + 1 < k) {
+      w[i * ld] = (sn * a[i + 1]) * ir;
+      rbar = -c * a[i + 1];
+    }
+    fbar = sn * fbar;
+  }
+  res = fabs(fbar);
+  double yn = 0.0, nn = 0.0;
+  for (int i = k - 1; i >= 0; --i) {
+    const double y = (i + 1 < k) ? q[i * ld] - w[i * ld] * yn : q[i * ld];
+    nn = fma(y, y, nn);
+    if (yout != nullptr) yout[i] = y;
+    yn = y;
+  }
+  ynorm = sqrt(nn);
+}
+
+struct LcurveArgs {
+  int gx, gy, gz;
+  KState* st;
+};
+
+__device__ __forceinline__ void k_lcurve_body(const LcurveArgs& a, const VBlock vb, const bool grouped) {
+  KState* st = a.st;
+  if (ld_state(&st->halt)) return;
+  __shared__ double rows[2 * kMaxK * 64];
+  __shared__ double ab_a[kMaxK], ab_b[kMaxK], px[kMaxK], py[kMaxK];
+  const int tid = threadIdx.x, lane = tid & 63;
+  int K = st->steps;
+  if (K > kMaxK) K = kMaxK;
+  if (K <= 0) return;
+  const double beta = st->beta[0];
+  if (tid < K) {
+    ab_a[tid] = st->alpha[tid];
+    ab_b[tid] = st->beta[tid + 1];
+  }
+  __syncthreads();
+  if (tid >= 64) return;
+  if (lane < K) {
+    double res, yn;
+    gk_ls(lane + 1, ab_a, ab_b, beta, rows + lane, rows + kMaxK * 64 + lane, 64, res, yn, nullptr);
+    px[lane] = log10(res);
+    py[lane] = log10(yn);
+  }
+  // wave 0 only from here: its lanes' writes complete before any lane reads
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  double kap = 0.0;
+  if (lane >= 1 && lane + 1 < K) {
+    const double ax = px[lane] - px[lane - 1], ay = py[lane] - py[lane - 1];
+    const double bx = px[lane + 1] - px[lane], by = py[lane + 1] - py[lane];
+    const double cx = px[lane + 1] - px[lane - 1], cy = py[lane + 1] - py[lane - 1];
+    const double den = sqrt(ax * ax + ay * ay) * sqrt(bx * bx + by * by) * sqrt(cx * cx + cy * cy);
+    const double m = den > 0.0 ? 2.0 * (ax * by - ay * bx) / den : 0.0;
+    kap = -m;
+  }
+  double bv = (kap > 0.0) ? kap : 0.0;  // NaN and non-positive: no corner
+  int bi = (kap > 0.0) ? lane : 64;
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double ov = __shfl_xor(bv, m);
+    const int oi = __shfl_xor(bi, m);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  const int kopt = bi < 64 ? bi + 1 : K;  // 1-based
+  if (lane == 0) {
+    double res, yn;
+    gk_ls(kopt, ab_a, ab_b, beta, rows, rows + kMaxK * 64, 1, res, yn, st->y);
+    for (int i = kopt; i < K; ++i) st->y[i] = 0.0;
+    st->lambda = 0.0;
+    st->gcv = __builtin_nan("");
+    st->sweeps = (double)kopt;
+    st->resnorm = res;
+  }
+}
+
+template <bool GROUPED>
+__global__ __launch_bounds__(kPT) void k_lcurve(LcurveArgs a_, const LcurveArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    k_lcurve_body(a_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const LcurveArgs g = group_args(grp, bmap, vb);
+    k_lcurve_body(g, vb, true);
+  }
+}
+
+hipError_t launch_lcurve(dctk_ctx ctx, KState* st) {
+  LcurveArgs a{};
+  a.st = st;
+  return launch_kernel(ctx, ctx->stream, k_lcurve<false>, k_lcurve<true>, dim3(1), kPT, 0, a);
+}
+
 hipError_t launch_projected_disc(dctk_ctx ctx, KState* st, double target, int k_use) {
   ProjArgs a{};
   a.bidiag = 1;

@@ -449,6 +449,37 @@ def test_gk_discrepancy_matches_oracle(ctx, where):
     dk.dctk_krylov_destroy(ws)
 
 
+@pytest.mark.parametrize("case", ["colour", "random"])
+def test_lsqr_lcurve_matches_oracle(ctx, case):
+    """LSQR stopped at the L-curve corner (FP64, full reorthogonalisation):
+    the library's corner index is the oracle's (curvature of the points from
+    least squares on the leading blocks of the oracle's bidiagonal), X is the
+    oracle's LSQR iterate at that index (1e-9) and the reported residual norm
+    is its residual (1e-9)."""
+    if case == "colour":
+        w, _, C = _colour_small_problem()
+        A, s_ = w["A"], 32
+        K = 12
+    else:
+        A, _, C = _krylov_problem(9)
+        s_ = C.shape[2]
+        K = 10
+    op = Op(ctx, A, None, s_, dk.DCTK_F64)
+    g = krylov.gkb(op.oracle, C, K, reorth="full")
+    Kt = g.steps
+    res, nrm = tikhonov.lcurve_points(g.bidiagonal(Kt), g.beta[0], Kt)
+    k_ref = tikhonov.lcurve_corner(res, nrm)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, K)
+    X = torch.empty((C.shape[0], A.shape[2], C.shape[2]), dtype=F64, device="cuda:0")
+    info, k_opt = dk.dctk_lsqr_lcurve_solve(ctx, ws, to_gpu(C, F64), X, dk.make_opts(K, dk.DCTK_REORTH_FULL, 0, 0.0))
+    say("lcurve", case, "k_opt", k_opt, k_ref, "res", info.resnorm, res[k_ref - 1])
+    assert k_opt == k_ref
+    ref = krylov.dc_lsqr(op.oracle, C, k_ref, reorth="full")
+    assert rel(to_np(X), ref["X"]) <= 1e-9
+    assert abs(info.resnorm - res[k_ref - 1]) <= 1e-9 * res[k_ref - 1]
+    dk.dctk_krylov_destroy(ws)
+
+
 @pytest.mark.parametrize("lam", [0.05, -1.0])
 def test_gk_folded_updates_match_oracle(ctx, lam):
     """Tikhonov solve (no reorthogonalisation, both products fused), where each
