@@ -72,9 +72,9 @@ def parse():
                     help="batch64: train the stopping network on the library's own solves of 256 smaller "
                          "problems of the same family, run the batch with the learned stop, and compare "
                          "with plain FP32 single solves")
-    ap.add_argument("--lambda-rule", default="gcv", choices=["gcv", "discrepancy"],
-                    help="colour256: lambda by GCV (default) or by the discrepancy principle at 1.05 x the "
-                         "norm of the added noise")
+    ap.add_argument("--lambda-rule", default="gcv", choices=["gcv", "discrepancy", "lcurve"],
+                    help="colour256: lambda by GCV (default), by the discrepancy principle at 1.05 x the "
+                         "norm of the added noise, or LSQR stopped at the L-curve corner")
     ap.add_argument("--workload", default="colour256", choices=["colour256", "batch64", "video256", "hyper512"],
                     help="colour256: one 256x256x3 solve per step (default); batch64: the uneven "
                          "64-instance batch per step (merged launches, HIP graph)")
@@ -92,21 +92,32 @@ def blas_threads():
     return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
 
 
-def oracle_leg(w, C_ref_builder, budget_s, target=None):
+def oracle_leg(w, C_ref_builder, budget_s, target=None, lcurve=False):
     """FP64 oracle: restoration error on the same input, and timed solves (bounded sample).
-    target: lambda by the discrepancy principle at this residual norm (else GCV)."""
-    from oracle import krylov, metrics
+    target: lambda by the discrepancy principle at this residual norm (else GCV);
+    lcurve: LSQR stopped at the L-curve corner instead."""
+    from oracle import krylov, metrics, tikhonov
     from oracle.cprod import Operator, fro
     op = Operator(w["A"])
     Ch = op.apply(w["X_true"])
     C = Ch + w["nu"] * fro(Ch) / fro(w["N0"]) * w["N0"]
     mode = "rect" if target is None else "discrepancy"
-    ref = krylov.dc_gk(op, C, w["iters"], lam=None, gcv_mode=mode, reorth="none", target=target)
+
+    def solve():
+        if lcurve:
+            g = krylov.gkb(op, C, w["iters"])
+            res, nrm = tikhonov.lcurve_points(g.bidiagonal(g.steps), g.beta[0], g.steps)
+            k = tikhonov.lcurve_corner(res, nrm)
+            out = krylov.dc_lsqr(op, C, k)
+            out["lambda"] = float(k)
+            return out
+        return krylov.dc_gk(op, C, w["iters"], lam=None, gcv_mode=mode, reorth="none", target=target)
+    ref = solve()
     err = metrics.relative_error(w["X_true"], ref["X"])
     n = 0
     t0 = time.perf_counter()
     while True:
-        krylov.dc_gk(op, C, w["iters"], lam=None, gcv_mode=mode, reorth="none", target=target)
+        solve()
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
@@ -159,21 +170,30 @@ def main():
     else:
         opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0, 0.0)
 
+    lcurve = args.lambda_rule == "lcurve"
+    k_opt = [None]
+
+    def solve(read=True):
+        if lcurve:  # LSQR at the L-curve corner (reads its index back)
+            out, k_opt[0] = dk.dctk_lsqr_lcurve_solve(ctx, ws, C, X, opts)
+            return out
+        return dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=read)
+
     for _ in range(args.warmup):
-        info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+        info = solve()
     torch.cuda.synchronize()
     # timed: the solves are enqueued back to back (no per-solve read-back of the
     # solve info, so the device never waits for the host)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=False)
+        solve(read=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     # the same with the info read back after every solve (one host round trip each)
     t0s = time.perf_counter()
     for _ in range(args.steps):
-        info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+        info = solve()
     torch.cuda.synchronize()
     ms_sync = (time.perf_counter() - t0s) * 1e3 / args.steps
 
@@ -187,7 +207,7 @@ def main():
     prof_steps = max(3, min(10, args.steps))
     dk.dctk_profile_begin(ctx)
     for _ in range(prof_steps):
-        dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+        solve()
     prof = dk.dctk_profile_end(ctx)
     kind = max(("fused_fwd", "fused_adj", "gemm"), key=lambda k_: prof[k_][0])
     k_ms, k_n = prof[kind]
@@ -248,12 +268,14 @@ def main():
     err_oracle = None
     lam_oracle = None
     if not args.no_cpu_baseline:
-        err_oracle, lam_oracle, cps, nsolve, dt = oracle_leg(w, None, args.cpu_seconds, target)
+        err_oracle, lam_oracle, cps, nsolve, dt = oracle_leg(w, None, args.cpu_seconds, target,
+                                                             args.lambda_rule == "lcurve")
         threads = blas_threads()
         cpu = {"value": cps, "unit": "solves/s", "cores": threads, "kind": "oracle",
                "sample": "%d full FP64 DC-GK solves (40 GKB steps + %s) of the same 256x256x3 workload "
                          "in %.1f s (numpy, BLAS matmul)"
-                         % (nsolve, "GCV" if target is None else "discrepancy principle", dt)}
+                         % (nsolve, {"gcv": "GCV", "discrepancy": "discrepancy principle",
+                                     "lcurve": "L-curve stopping index"}[args.lambda_rule], dt)}
     gate_ok = (err_oracle is None) or (err_gpu <= 1.05 * err_oracle)
     solves_per_s = 1e3 / ms_per_step
     value = solves_per_s if gate_ok else 0.0
@@ -272,7 +294,8 @@ def main():
         "dtype": args.gemm if args.gemm != "f32" else "f32",
         "data": "synthetic",
         "config": {"workload": "colour deblur 256x256x3, DC-LSQR/DC-GK 40 GKB steps + FP64 %s, one solve per step"
-                               % ("GCV" if target is None else "discrepancy principle"),
+                               % {"gcv": "GCV", "discrepancy": "discrepancy principle",
+                                  "lcurve": "L-curve stopping index"}[args.lambda_rule],
                    "lambda_rule": args.lambda_rule,
                    "n1": n, "n2": n, "s": s, "n3": p, "gkb_steps": k, "gemm_dtype": args.gemm,
                    "vector_dtype": "f32", "reorth": "none", "tube": "th"},
@@ -280,8 +303,9 @@ def main():
         "cpu_baseline": cpu,
         "restoration": {"relerr_gpu": err_gpu, "relerr_oracle_fp64": err_oracle,
                         "ratio": (err_gpu / err_oracle) if err_oracle else None, "gate_1_05": gate_ok,
-                        "lambda_gpu": info.lam, "lambda_oracle": lam_oracle, "iters": info.iters,
-                        "jacobi_sweeps": kr["sweeps"]},
+                        "lambda_gpu": info.lam, "lambda_oracle": None if lcurve else lam_oracle, "iters": info.iters,
+                        "jacobi_sweeps": kr["sweeps"] if not lcurve else None,
+                        "k_opt_gpu": k_opt[0], "k_opt_oracle": int(lam_oracle) if (lcurve and lam_oracle) else None},
         "cprod": cprod,
         "per_solve_sync": {"solves_per_s": 1e3 / ms_sync, "ms_per_solve": ms_sync,
                            "note": "info read back (host synchronisation) after every solve"},
