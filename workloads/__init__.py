@@ -147,6 +147,23 @@ def video_256(instance=0, frames=32):
             "nu": 5e-3, "iters": 40}
 
 
+def paper_shaped(n, nu, instance=0):
+    """Stand-in for the paper's colour experiments (Sec. 4: two-sided
+    A *c X *c B, n3 = 3, Gaussian Toeplitz blur sigma = 4, r = 6, noise level
+    nu): A(:,:,k) = t_k T with the printed A_color tube t = (0.8, 0, 0.1), B =
+    e_1 (x) T^T (the same blur along the other image direction, no channel
+    mixing), a smooth-plus-edges field in place of the images (papav256,
+    cat1024), which are not available."""
+    rng = np.random.default_rng(1000 * 7 + 10 * instance + (n // 256))
+    p = 3
+    T = gaussian_toeplitz(n, 4.0, 6)
+    A = mixed_blur(PAPER_COLOUR_TUBE, T)
+    B = mixed_blur((1.0, 0.0, 0.0), np.ascontiguousarray(T.T))
+    X = edges_field(rng, p, n, n)
+    N0 = rng.standard_normal((p, n, n))
+    return {"name": "paper_%dx%dx3" % (n, n), "A": A, "B": B, "X_true": X, "N0": N0, "nu": nu}
+
+
 def batch_instance(i):
     """Instance i (0..63) of the uneven batched set: n = s in {64, ..., 512},
     n3 in {3, 8, 31}, sigma ~ U[1, 4], r = ceil(2.5 sigma), nu ~ logU[1e-3, 1e-2]."""
