@@ -31,3 +31,19 @@ def test_batch_instances_span_sizes():
     sizes = {W.batch_instance(i)["A"].shape for i in range(6)}
     for p, n, n2 in sizes:
         assert n == n2 and p in (3, 8, 31) and n in (64, 128, 192, 256, 384, 512)
+
+
+def test_paper_shaped_structure():
+    """The paper-shaped workload: A(:,:,k) = t_k T with t = (0.8, 0, 0.1), B =
+    e_1 (x) T^T, T the sigma = 4, r = 6 Gaussian Toeplitz blur; the field in
+    [0, 1]; seeded (two calls agree)."""
+    w = W.paper_shaped(64, 1e-3)
+    T = W.gaussian_toeplitz(64, 4.0, 6)
+    for k, t in enumerate((0.8, 0.0, 0.1)):
+        assert np.array_equal(w["A"][k], t * T)
+    assert np.array_equal(w["B"][0], T.T)
+    assert not w["B"][1].any() and not w["B"][2].any()
+    assert w["X_true"].min() >= 0.0 and w["X_true"].max() <= 1.0
+    w2 = W.paper_shaped(64, 1e-3)
+    assert np.array_equal(w["X_true"], w2["X_true"]) and np.array_equal(w["N0"], w2["N0"])
+
