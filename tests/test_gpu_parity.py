@@ -576,6 +576,38 @@ def test_enqueued_solves_match_synchronous_solve(ctx):
     dk.dctk_krylov_destroy(ws)
 
 
+def test_solves_on_two_streams_match_one_stream(ctx):
+    """Independent enqueue-only solves alternating over two contexts on two
+    streams (each with its own operator and workspace) give bit for bit the X
+    of the same solve on the default context."""
+    w, _, C = _colour_small_problem()
+    k = 12
+    opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0)
+    Cg = to_gpu(C, F32)
+    op = Op(ctx, w["A"], None, 32, dk.DCTK_F32)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    Xr = torch.empty(C.shape, dtype=F32, device="cuda:0")
+    dk.dctk_lsqr_tik_solve(ctx, ws, Cg, Xr, opts)
+    dk.dctk_krylov_destroy(ws)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ctxs = [dk.dctk_create(0, st) for st in streams]
+    A = torch.from_numpy(w["A"]).to("cuda:0")
+    ops = [dk.dctk_op_create(c, dk.DCTK_TUBE_TH, dk.DCTK_F32, A, 32) for c in ctxs]
+    wss = [dk.dctk_krylov_create(c, o, dk.DCTK_KRYLOV_GKB, k) for c, o in zip(ctxs, ops)]
+    Xs = [torch.empty(C.shape, dtype=F32, device="cuda:0") for _ in range(4)]
+    torch.cuda.synchronize()
+    for i in range(4):
+        j = i % 2
+        dk.dctk_lsqr_tik_solve(ctxs[j], wss[j], Cg, Xs[i], opts, info=False)
+    torch.cuda.synchronize()
+    for Xi in Xs:
+        assert torch.equal(Xi, Xr)
+    for j in range(2):
+        dk.dctk_krylov_destroy(wss[j])
+        dk.dctk_op_destroy(ops[j])
+        dk.dctk_destroy(ctxs[j])
+
+
 def test_gk_gcv_20_steps_restoration_level(ctx):
     """k = 20 on the same problem: past step ~15 rounding is amplified by the
     process itself (oracle vs oracle with C perturbed by 1e-16: alpha moves 3%,
