@@ -124,6 +124,32 @@ int dctk_tube_fwd(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p
 /* Same with G = L^{-1} (adjoint_pair = 0) or L^{T} (adjoint_pair = 1). */
 int dctk_tube_inv(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p, int64_t count,
                   const void* in, void* out);
+/* Tubes longer than 64: dctk_tube_fwd and dctk_tube_inv accept a power-of-two
+ * p up to 4096 (DCTK_F32) or 2048 (DCTK_F64) and hand it to the O(p log p)
+ * transform below, enqueued without synchronising.  Other p > 64 give
+ * DCTK_ESHAPE. */
+
+/* Fast tube transform (the fast DCT credited to the method in Sec. 1 and
+ * Sec. 2.1): out = in x_3 G with G = matrix `which` (DCTK_MAT_*) of `tube`,
+ * as the DCT-II of one complex FFT of length p per tube (Makhoul's
+ * reordering) wrapped in the O(p) factors of Remark 2.1:
+ * M = W^{-1} C_n (I + Z) = D^{-1} F (I + Z) with F the unnormalised DCT-II
+ * and D = diag(cos(pi k / (2p))); the inverses of (I + Z) and (I + Z^T) are
+ * alternating suffix and prefix sums.  Layout as dctk_tube_fwd: in/out hold p
+ * slices of `count` elements, slice-major, DCTK_F64 or DCTK_F32 (both).
+ * p: a power of two, 16 <= p <= 4096 (DCTK_F32) or 2048 (DCTK_F64).
+ * Enqueued on the context's stream; returns without synchronising and
+ * allocates nothing; the caller keeps both buffers alive until the stream
+ * has run the work.  Rounding: FP32 results agree with the dense transform
+ * to a relative 1e-6 (p = 256) to 4e-6 (p = 1024) in the 2-norm; the row
+ * scaling D^{-1} (up to 2p / pi) amplifies the FFT's rounding by up to that
+ * factor for the last rows of M and M^{-T}.
+ * Errors: DCTK_EINVAL (NULL, bad tube/which, in and out overlap),
+ * DCTK_EDTYPE, DCTK_ESHAPE (p not allowed, count <= 0), DCTK_ESTATE (while a
+ * batch plan is being recorded), DCTK_EHIP. */
+int dctk_tube_fast(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, int64_t count, const void* in,
+                   void* out);
+
 
 /* ---- operators M(X) = A *c X  or  A *c X *c B  (eq. 2) ------------------ */
 /* Creates the operator of eq. (2) from A in R^{n1 x n2 x p} (device, FP64,

@@ -12,6 +12,7 @@
 
 #include "internal.h"
 #include "projected.h"
+#include "fastdct.h"
 
 static_assert(dctk::PROF_KINDS == DCTK_PROF_KINDS, "profiler kinds");
 
@@ -185,11 +186,34 @@ int dctk_profile_end(dctk_ctx ctx, double* ms, int* count) {
 }
 
 // ---- tube transforms -----------------------------------------------------------
+static int tube_fast_impl(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, int64_t count, const void* in,
+                          void* out) {
+  if (!ctx || !in || !out) return DCTK_EINVAL;
+  if (tube != DCTK_TUBE_TH && tube != DCTK_TUBE_DCT2) return DCTK_EINVAL;
+  if (which < DCTK_MAT_L || which > DCTK_MAT_LT) return DCTK_EINVAL;
+  if (dtype != DCTK_F64 && dtype != DCTK_F32) return DCTK_EDTYPE;
+  if (count <= 0 || !tube_fast_shape_ok(dtype, p) || (count + (tube_fast_max(dtype) / p) - 1) / (tube_fast_max(dtype) / p) > 0x7fffffff)
+    return DCTK_ESHAPE;
+  const size_t bytes = (size_t)(p * count) * (dtype == DCTK_F64 ? 8 : 4);
+  if (ranges_overlap(in, bytes, out, bytes)) return DCTK_EINVAL;
+  if (ctx->rec) return DCTK_ESTATE;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  DCTK_HIP(ctx, launch_tube_fast(ctx, ctx->stream, tube, which, dtype, p, count, in, out));
+  return DCTK_OK;
+}
+
+int dctk_tube_fast(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, int64_t count, const void* in,
+                   void* out) {
+  return tube_fast_impl(ctx, tube, which, dtype, p, count, in, out);
+}
+
 static int tube_common(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, int64_t count, const void* in,
                        void* out) {
   if (!ctx || !in || !out) return DCTK_EINVAL;
   if (tube != DCTK_TUBE_TH && tube != DCTK_TUBE_DCT2) return DCTK_EINVAL;
   if (dtype != DCTK_F64 && dtype != DCTK_F32) return DCTK_EDTYPE;
+  // tubes beyond the dense transform's LDS matrix take the O(p log p) transform
+  if (p > kMaxTube && tube_fast_shape_ok(dtype, p)) return tube_fast_impl(ctx, tube, which, dtype, p, count, in, out);
   if (p <= 0 || count <= 0 || p > kMaxTube) return DCTK_ESHAPE;
   const size_t bytes = (size_t)(p * count) * (dtype == DCTK_F64 ? 8 : 4);
   if (ranges_overlap(in, bytes, out, bytes)) return DCTK_EINVAL;

@@ -1,0 +1,18 @@
+// Tube transforms in O(p log p) per tube for power-of-two tube lengths.
+#pragma once
+#include "internal.h"
+
+namespace dctk {
+
+constexpr int kFastMinTube = 16;  // shortest tube of the fast transform (a workgroup holds at most 256 tubes)
+
+// Longest tube of the fast transform for DCTK_F32 / DCTK_F64 (one workgroup holds a whole tube in LDS).
+int tube_fast_max(int dtype);
+// p is a power of two within [kFastMinTube, tube_fast_max(dtype)].
+bool tube_fast_shape_ok(int dtype, int64_t p);
+// out = in x_3 G, G = matrix `which` (DCTK_MAT_*) of transform `tube`, in O(p log p) per tube; dtype
+// DCTK_F32 or DCTK_F64 for both buffers; enqueued on s, allocates nothing.
+hipError_t launch_tube_fast(dctk_ctx ctx, hipStream_t s, int tube, int which, int dtype, int64_t p, int64_t count,
+                            const void* in, void* out);
+
+}  // namespace dctk
