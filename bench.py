@@ -42,6 +42,20 @@ TRAFFIC = {"digest": "2745717c67c60cfc", "gemm": "f32",
            "bytes": {"fused_fwd": 7444194, "fused_adj": 7373410}}
 
 
+# The same for the O(p log p) tube transform at 512 x 512 positions, p = 256, FP32 (bytes per launch).
+LONGTUBE_SOURCES = ("paper_2103_11847_amd/csrc/fastdct.hip", "paper_2103_11847_amd/csrc/fastdct.h")
+LONGTUBE_TRAFFIC = {"digest": None, "bytes": None}
+
+
+def source_digest(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kind, gemm):
     import hashlib
     h = hashlib.sha256()
@@ -75,7 +89,8 @@ def parse():
     ap.add_argument("--lambda-rule", default="gcv", choices=["gcv", "discrepancy", "lcurve"],
                     help="colour256: lambda by GCV (default), by the discrepancy principle at 1.05 x the "
                          "norm of the added noise, or LSQR stopped at the L-curve corner")
-    ap.add_argument("--workload", default="colour256", choices=["colour256", "batch64", "video256", "hyper512", "paper"],
+    ap.add_argument("--workload", default="colour256",
+                    choices=["colour256", "batch64", "video256", "hyper512", "paper", "longtube"],
                     help="colour256: one 256x256x3 solve per step (default); batch64: the uneven "
                          "64-instance batch per step (merged launches, HIP graph)")
     return ap.parse_args()
@@ -144,6 +159,8 @@ def main():
         return bench_large(args)
     if args.workload == "paper":
         return bench_paper(args)
+    if args.workload == "longtube":
+        return bench_longtube(args)
     dev = torch.device("cuda:0")
     w = W.colour_256()
     p, n, s, k = 3, 256, 256, w["iters"]
@@ -433,6 +450,122 @@ def bench_paper(args):
         "paper_tables": table,
         "note": "paper_cpu_s: the paper's Matlab seconds on an i7-8550U with its images (Tables 1, 3); "
                 "context only, different machine and inputs",
+    }
+    dk.dctk_destroy(ctx)
+    print(json.dumps(line))
+
+
+def bench_longtube(args):
+    """The O(p log p) tube transform on a hyperspectral-shaped cube: 512 x 512
+    positions, p = 256 bands, FP32, one step = M (Remark 2.1) applied to every
+    tube.  Each element is read and written once (8 bytes per element per
+    launch in FP32), so the roofline is HBM.  Also: the four matrices of the
+    family, other tube lengths at the same positions, sampled outputs against
+    the oracle's dense matrix, and the oracle's dense mode-3 product timed on a
+    sample of positions."""
+    import torch
+    import paper_2103_11847_amd as dk
+    from oracle import tube as otube
+    dev = torch.device("cuda:0")
+    ctx = dk.dctk_create(0)
+    p, n = 256, 512
+    count = n * n
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(256)
+    x = torch.randn((p, count), device=dev, generator=gen)
+    out = torch.empty_like(x)
+    TH = dk.DCTK_TUBE_TH
+
+    def avg_seconds(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) * 1e-3 / reps
+
+    def fwd():
+        dk.dctk_tube_fast(ctx, TH, dk.DCTK_MAT_L, x, out)
+
+    for _ in range(args.warmup):
+        fwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    avg = avg_seconds(fwd, 50)
+    bytes_launch = 2 * p * count * 4
+    # sampled positions against the oracle's dense M
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(count, 256, replace=False))
+    it = torch.from_numpy(idx).to(dev)
+    xs = x[:, it].double().cpu().numpy()
+    G = otube.transform_matrix(p, "th")
+    ref = G @ xs
+    got = out[:, it].double().cpu().numpy()
+    relerr = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    names = {"M": dk.DCTK_MAT_L, "M_inv": dk.DCTK_MAT_LINV, "M_invT": dk.DCTK_MAT_LINVT, "M_T": dk.DCTK_MAT_LT}
+    per_matrix = {}
+    for name, which in names.items():
+        us = avg_seconds(lambda: dk.dctk_tube_fast(ctx, TH, which, x, out), 30) * 1e6
+        per_matrix[name] = {"us": us, "GB_per_s": bytes_launch / (us * 1e-6) / 1e9}
+    by_p = {}
+    for pl in (16, 64, 1024, 4096):
+        xl = torch.randn((pl, count), device=dev, generator=gen)
+        ol = torch.empty_like(xl)
+        us = avg_seconds(lambda: dk.dctk_tube_fast(ctx, TH, dk.DCTK_MAT_L, xl, ol), 20) * 1e6
+        by_p[str(pl)] = {"us": us, "GB_per_s": 2 * pl * count * 4 / (us * 1e-6) / 1e9}
+        del xl, ol
+    if args.copy_calib_mib > 0:
+        # a plain copy of known size, for scaling the HBM counters of a profiled run
+        cal = torch.ones(args.copy_calib_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        cal_out = torch.empty_like(cal)
+        for _ in range(3):
+            cal_out.copy_(cal)
+        torch.cuda.synchronize()
+        del cal, cal_out
+    achieved = bytes_launch / avg / 1e9
+    traffic = LONGTUBE_TRAFFIC["bytes"] if source_digest(LONGTUBE_SOURCES) == LONGTUBE_TRAFFIC["digest"] else None
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's dense transform (G @ tubes, numpy/BLAS) over blocks of positions
+        xs_all = x[:, :65536].double().cpu().numpy()
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 15.0):
+            otube.mode3(xs_all.reshape(p, 256, 256), G)
+            done += 65536
+        el = time.perf_counter() - t0
+        cpu = {"value": done / count / el, "unit": "transforms/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": "%d positions (blocks of 65536 of the 262144) through the oracle's dense FP64 mode-3 "
+                         "product in %.1f s, scaled to whole 512x512x256 transforms" % (done, el)}
+    line = {
+        "metric": "tube transforms/s (M of Remark 2.1 on every tube)",
+        "value": 1.0 / sec,
+        "unit": "transforms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "long-tube transform, hyperspectral-shaped 512x512 positions x 256 bands, FP32, "
+                               "O(p log p) (FFT-based DCT-II)", "p": p, "positions": count},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "tube_fast_kernel<float>",
+                     "avg_us": avg * 1e6, "bytes_per_launch": bytes_launch},
+        "cpu_baseline": cpu,
+        "sampled_relerr_vs_oracle": relerr,
+        "per_matrix": per_matrix,
+        "by_p": by_p,
     }
     dk.dctk_destroy(ctx)
     print(json.dumps(line))

@@ -21,8 +21,12 @@
 // A workgroup owns NB = E / p neighbouring tubes (E = 4096 FP32 or 2048 FP64
 // elements): it loads the p x NB block row by row (NB consecutive positions
 // of each slice), runs every step in LDS and writes the block back, so each
-// element crosses HBM once each way.  The work is HBM-bound: about
+// element crosses HBM once each way.  Workgroups stay resident and loop over
+// blocks of tubes, loading the next block into registers while the current
+// one is transformed; the row constants (rotations, diagonals) and the FFT
+// twiddles are computed once per workgroup.  The work is HBM-bound: about
 // 5 p log2 p flops per tube against 2 p elements moved.
+#include <algorithm>
 #include <cmath>
 
 #include "fastdct.h"
@@ -31,7 +35,7 @@ namespace dctk {
 
 namespace {
 
-constexpr int kFastThreads = 256;
+constexpr int kFastThreads = 512;
 constexpr int kFastLds = 16384;  // bytes of each of the three E-element buffers
 
 template <typename T>
@@ -44,7 +48,7 @@ struct FastArgs {
   void* out;
   int64_t count;  // positions per slice
   int p, logp, nb, lognb;
-  int inv;    // 0: F core, 1: F^{-1} core
+  int inv;    // 0: F core, 1: F^{-1} core (the kernel's INV)
   int pre;    // before F: 0 none, 1 (I + Z), 2 (I + Z^T)^{-1}
   int post;   // after F^{-1}: 0 none, 1 (I + Z^T), 2 (I + Z)^{-1}
   int scale;  // diagonal: 0 D^{-1}, 1 D N^{-1}, 2 S (after F); 3 D, 4 N D^{-1}, 5 S^{-1} (before F^{-1})
@@ -67,6 +71,11 @@ __device__ inline T fast_scale(int code, int k, int p, T d) {
     default: return (T)1 / sq;
   }
 }
+
+// Index of element i of the FFT buffers: bits 4-5 are XORed with bits 6-7,
+// a bijection on every 256 elements, so that the four operands of a
+// radix-4 group (16 tubes apart in a block of 16) fall in different banks.
+__device__ inline int sw(int i) { return i ^ (((i >> 6) & 3) << 4); }
 
 __device__ inline int bit_reverse(int n, int bits) { return (int)(__brev((unsigned)n) >> (32 - bits)); }
 
@@ -108,9 +117,10 @@ __device__ void alt_scan(T* buf, T* part, int p, int nb, int lognb) {
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kFastThreads) void tube_fast_kernel(FastArgs a) {
+template <typename T, bool INV>
+__global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) {
   constexpr int E = FastCfg<T>::E;
+  constexpr int U = E / kFastThreads;  // elements per thread and block of tubes
   __shared__ T rb[E];              // the tubes as real values
   __shared__ T re[E], im[E];       // complex FFT buffer, position-major
   __shared__ T twr[E / 2], twi[E / 2];  // exp(-2 pi i m / p), m < p/2
@@ -120,103 +130,171 @@ __global__ __launch_bounds__(kFastThreads) void tube_fast_kernel(FastArgs a) {
   const int tid = threadIdx.x;
   const int p = a.p, nb = a.nb, lognb = a.lognb, logp = a.logp;
   const int64_t count = a.count;
-  const int64_t e0 = (int64_t)blockIdx.x * nb;
+  const int64_t ntiles = (count + nb - 1) / nb;
+  const T two_p = (T)(2 * p);
 
+  // Once per workgroup (it stays resident over many blocks of tubes): the FFT
+  // twiddles, and for the rows k this thread touches the rotation
+  // exp(-i pi k / (2p)) and the diagonal entries at k (and at p - k).
   for (int m = tid; m < p / 2; m += kFastThreads) {
     T s, c;
     sc_pi((T)(2 * m) / (T)p, &s, &c);
     twr[m] = c;
     twi[m] = -s;
   }
-  // load the block: row t holds positions e0 .. e0 + nb - 1 of slice t
-  for (int i = tid; i < E; i += kFastThreads) {
-    const int t = i >> lognb, j = i & (nb - 1);
-    const int64_t e = e0 + j;
-    const int64_t ec = e < count ? e : count - 1;
-    const T v = in[(int64_t)t * count + ec];
-    rb[i] = e < count ? v : (T)0;
+  // A thread keeps one position j of the block (nb divides the thread count)
+  // and rows t0, t0 + RU, t0 + 2 RU, ...
+  const int jt = tid & (nb - 1), t0 = tid >> lognb, ru = kFastThreads >> lognb;
+  const int64_t rstride = (int64_t)ru * count;
+  T rc[U], rs[U], rq[U], rq2[INV ? U : 1];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = t0 + u * ru;
+    sc_pi((T)k / two_p, &rs[u], &rc[u]);
+    rq[u] = fast_scale<T>(a.scale, k, p, rc[u]);
+    if (INV) {
+      T s2, c2;
+      sc_pi((T)(p - k) / two_p, &s2, &c2);
+      rq2[INV ? u : 0] = k ? fast_scale<T>(a.scale, p - k, p, c2) : (T)0;
+    }
   }
-  __syncthreads();
-  if (a.pre == 2) {
-    alt_scan<T, false>(rb, part, p, nb, lognb);
+  // row t of a block holds positions e0 .. e0 + nb - 1 of slice t; clamped
+  // addresses keep every load in bounds, the tail is zeroed when staged
+  T pf[U];
+  auto fetch = [&](int64_t tile) {
+    const int64_t e = tile * nb + jt;
+    const T* src = in + (int64_t)t0 * count + (e < count ? e : count - 1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) pf[u] = src[u * rstride];
+  };
+  int64_t tile = blockIdx.x;  // the grid never exceeds the number of blocks of tubes
+  fetch(tile);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int64_t e0 = tile * nb;
+    const bool live = e0 + jt < count;
+#pragma unroll
+    for (int u = 0; u < U; ++u) rb[tid + u * kFastThreads] = live ? pf[u] : (T)0;
     __syncthreads();
-  }
-  const T two_p = (T)(2 * p);
-  // FFT input at bit-reversed positions
-  for (int i = tid; i < E; i += kFastThreads) {
-    const int t = i >> lognb, j = i & (nb - 1);
-    if (!a.inv) {
-      T y = rb[i];
-      if (a.pre == 1 && t + 1 < p) y += rb[i + nb];
-      const int n = (t & 1) ? p - 1 - (t >> 1) : (t >> 1);  // even entries, then odd ones reversed
-      const int d = bit_reverse(n, logp) * nb + j;
-      re[d] = y;
-      im[d] = 0;
-    } else {
-      // V_k = exp(i pi k / (2p)) (X_k - i X_{p-k}), X_p = 0, with X = R x
-      const int k = t;
-      T s, c;
-      sc_pi((T)k / two_p, &s, &c);
-      const T xk = rb[i] * fast_scale<T>(a.scale, k, p, c);
-      T xpk = 0;
-      if (k) {
-        T s2, c2;
-        sc_pi((T)(p - k) / two_p, &s2, &c2);
-        xpk = rb[(p - k) * nb + j] * fast_scale<T>(a.scale, p - k, p, c2);
+    // the next block of tubes is in flight while this one is transformed
+    fetch(tile + gridDim.x < ntiles ? tile + gridDim.x : tile);
+    if (a.pre == 2) {
+      alt_scan<T, false>(rb, part, p, nb, lognb);
+      __syncthreads();
+    }
+    // FFT input at bit-reversed positions
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = tid + u * kFastThreads;
+      const int t = i >> lognb, j = i & (nb - 1);
+      if (!INV) {
+        T y = rb[i];
+        if (a.pre == 1 && t + 1 < p) y += rb[i + nb];
+        const int n = (t & 1) ? p - 1 - (t >> 1) : (t >> 1);  // even entries, then odd ones reversed
+        const int d = bit_reverse(n, logp) * nb + j;
+        re[sw(d)] = y;
+        im[sw(d)] = 0;
+      } else {
+        // V_k = exp(i pi k / (2p)) (X_k - i X_{p-k}), X_p = 0, with X = R x
+        const int k = t;
+        const T xk = rb[i] * rq[u];
+        const T xpk = k ? rb[(p - k) * nb + j] * rq2[INV ? u : 0] : (T)0;
+        const int d = bit_reverse(k, logp) * nb + j;
+        re[sw(d)] = rc[u] * xk + rs[u] * xpk;
+        im[sw(d)] = rs[u] * xk - rc[u] * xpk;
       }
-      const int d = bit_reverse(k, logp) * nb + j;
-      re[d] = c * xk + s * xpk;
-      im[d] = s * xk - c * xpk;
-    }
-  }
-  __syncthreads();
-  // radix-2 decimation in time, in place; twiddle exp(-+2 pi i pos / (2h)) = tw[pos * p / (2h)]
-  for (int h = 1, sh = logp - 1; h < p; h <<= 1, --sh) {
-    for (int q = tid; q < E / 2; q += kFastThreads) {
-      const int b = q >> lognb, j = q & (nb - 1);
-      const int pos = b & (h - 1);
-      const int i0 = (((b - pos) << 1) + pos) * nb + j, i1 = i0 + h * nb;
-      const T wr = twr[pos << sh], wi = a.inv ? -twi[pos << sh] : twi[pos << sh];
-      const T br = re[i1], bi = im[i1];
-      const T tr = wr * br - wi * bi, ti = wr * bi + wi * br;
-      const T ar = re[i0], ai = im[i0];
-      re[i0] = ar + tr;
-      im[i0] = ai + ti;
-      re[i1] = ar - tr;
-      im[i1] = ai - ti;
     }
     __syncthreads();
-  }
-  if (!a.inv) {
-    // F_k = Re(exp(-i pi k / (2p)) V_k), then the diagonal
-    for (int i = tid; i < E; i += kFastThreads) {
-      const int k = i >> lognb, j = i & (nb - 1);
-      T s, c;
-      sc_pi((T)k / two_p, &s, &c);
-      const T f = re[i] * c + im[i] * s;
-      const int64_t e = e0 + j;
-      if (e < count) out[(int64_t)k * count + e] = f * fast_scale<T>(a.scale, k, p, c);
+    // Decimation in time, in place, two radix-2 stages (half sizes h and 2h)
+    // per pass in registers; a last radix-2 stage when log2 p is odd.  The
+    // twiddle exp(-+2 pi i m / (2H)) of a stage with half size H is
+    // tw[m * p / (2H)].
+    int h = 1, sh = logp - 1;
+    for (; 2 * h < p; h <<= 2, sh -= 2) {
+#pragma unroll 2
+      for (int v = 0; v < U / 4; ++v) {
+        const int q = tid + v * kFastThreads;
+        const int b = q >> lognb, j = q & (nb - 1);
+        const int pos = b & (h - 1);
+        const int i0 = (((b - pos) << 2) + pos) * nb + j, hs = h * nb;
+        const int k1 = pos << sh, k2 = pos << (sh - 1), k3 = (pos + h) << (sh - 1);
+        const T w1r = twr[k1], w1i = INV ? -twi[k1] : twi[k1];
+        const T w2r = twr[k2], w2i = INV ? -twi[k2] : twi[k2];
+        const T w3r = twr[k3], w3i = INV ? -twi[k3] : twi[k3];
+        const int x0 = sw(i0), x1 = sw(i0 + hs), x2 = sw(i0 + 2 * hs), x3 = sw(i0 + 3 * hs);
+        const T a0r = re[x0], a0i = im[x0], a1r = re[x1], a1i = im[x1];
+        const T a2r = re[x2], a2i = im[x2], a3r = re[x3], a3i = im[x3];
+        // stage h: (a0, a1) and (a2, a3) with w1
+        T tr = w1r * a1r - w1i * a1i, ti = w1r * a1i + w1i * a1r;
+        const T b0r = a0r + tr, b0i = a0i + ti, b1r = a0r - tr, b1i = a0i - ti;
+        tr = w1r * a3r - w1i * a3i;
+        ti = w1r * a3i + w1i * a3r;
+        const T b2r = a2r + tr, b2i = a2i + ti, b3r = a2r - tr, b3i = a2i - ti;
+        // stage 2h: (b0, b2) with w2, (b1, b3) with w3
+        tr = w2r * b2r - w2i * b2i;
+        ti = w2r * b2i + w2i * b2r;
+        re[x0] = b0r + tr;
+        im[x0] = b0i + ti;
+        re[x2] = b0r - tr;
+        im[x2] = b0i - ti;
+        tr = w3r * b3r - w3i * b3i;
+        ti = w3r * b3i + w3i * b3r;
+        re[x1] = b1r + tr;
+        im[x1] = b1i + ti;
+        re[x3] = b1r - tr;
+        im[x3] = b1i - ti;
+      }
+      __syncthreads();
     }
-    return;
-  }
-  // y_t = v_n / p with n the reordered index of t
-  const T inv_p = (T)1 / (T)p;
-  for (int i = tid; i < E; i += kFastThreads) {
-    const int t = i >> lognb, j = i & (nb - 1);
-    const int n = (t & 1) ? p - 1 - (t >> 1) : (t >> 1);
-    rb[i] = re[n * nb + j] * inv_p;
-  }
-  __syncthreads();
-  if (a.post == 2) {
-    alt_scan<T, true>(rb, part, p, nb, lognb);
-    __syncthreads();
-  }
-  for (int i = tid; i < E; i += kFastThreads) {
-    const int t = i >> lognb, j = i & (nb - 1);
-    T y = rb[i];
-    if (a.post == 1 && t > 0) y += rb[i - nb];
-    const int64_t e = e0 + j;
-    if (e < count) out[(int64_t)t * count + e] = y;
+    if (h < p) {  // h == p / 2: the last radix-2 stage, twiddle index pos (sh == 0)
+#pragma unroll 2
+      for (int v = 0; v < U / 2; ++v) {
+        const int q = tid + v * kFastThreads;
+        const int pos = q >> lognb, j = q & (nb - 1);
+        const int i0 = sw(pos * nb + j), i1 = sw(pos * nb + j + h * nb);
+        const T wr = twr[pos], wi = INV ? -twi[pos] : twi[pos];
+        const T br = re[i1], bi = im[i1];
+        const T tr = wr * br - wi * bi, ti = wr * bi + wi * br;
+        const T ar = re[i0], ai = im[i0];
+        re[i0] = ar + tr;
+        im[i0] = ai + ti;
+        re[i1] = ar - tr;
+        im[i1] = ai - ti;
+      }
+      __syncthreads();
+    }
+    T* dst = out + (int64_t)t0 * count + e0 + jt;
+    if (!INV) {
+      // F_k = Re(exp(-i pi k / (2p)) V_k), then the diagonal
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = tid + u * kFastThreads;
+        const T f = re[sw(i)] * rc[u] + im[sw(i)] * rs[u];
+        if (live) dst[u * rstride] = f * rq[u];
+      }
+    } else {
+      // y_t = v_n / p with n the reordered index of t
+      const T inv_p = (T)1 / (T)p;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = tid + u * kFastThreads;
+        const int t = i >> lognb, j = i & (nb - 1);
+        const int n = (t & 1) ? p - 1 - (t >> 1) : (t >> 1);
+        rb[i] = re[sw(n * nb + j)] * inv_p;
+      }
+      __syncthreads();
+      if (a.post == 2) {
+        alt_scan<T, true>(rb, part, p, nb, lognb);
+        __syncthreads();
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = tid + u * kFastThreads;
+        T y = rb[i];
+        if (a.post == 1 && t0 + u * ru > 0) y += rb[i - nb];
+        if (live) dst[u * rstride] = y;
+      }
+    }
+    __syncthreads();  // the buffers are rewritten by the next block of tubes
   }
 }
 
@@ -256,12 +334,17 @@ hipError_t launch_tube_fast(dctk_ctx ctx, hipStream_t s, int tube, int which, in
     case DCTK_MAT_LT: a.inv = 1; a.post = th ? 1 : 0; a.scale = th ? 4 : 5; break;
     default: return hipErrorInvalidValue;
   }
-  const int64_t blocks = (count + a.nb - 1) / a.nb;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  if (dtype == DCTK_F64)
-    tube_fast_kernel<double><<<dim3((unsigned)blocks), dim3(kFastThreads), 0, s>>>(a);
-  else
-    tube_fast_kernel<float><<<dim3((unsigned)blocks), dim3(kFastThreads), 0, s>>>(a);
+  const int64_t tiles = (count + a.nb - 1) / a.nb;
+  // resident workgroups (two fit a CU's LDS, 16 waves), each looping over blocks of tubes
+  const int64_t blocks = std::min<int64_t>(tiles, 2 * (int64_t)num_cus());
+  const dim3 g((unsigned)blocks), b(kFastThreads);
+  if (dtype == DCTK_F64) {
+    if (a.inv) tube_fast_kernel<double, true><<<g, b, 0, s>>>(a);
+    else tube_fast_kernel<double, false><<<g, b, 0, s>>>(a);
+  } else {
+    if (a.inv) tube_fast_kernel<float, true><<<g, b, 0, s>>>(a);
+    else tube_fast_kernel<float, false><<<g, b, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 
