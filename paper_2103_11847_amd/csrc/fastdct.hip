@@ -48,6 +48,7 @@ struct FastArgs {
   void* out;
   int64_t count;  // positions per slice
   int p, logp, nb, lognb;
+  int group;  // blocks of tubes sharing 128-byte lines, taken by one workgroup back to back
   int inv;    // 0: F core, 1: F^{-1} core (the kernel's INV)
   int pre;    // before F: 0 none, 1 (I + Z), 2 (I + Z^T)^{-1}
   int post;   // after F^{-1}: 0 none, 1 (I + Z^T), 2 (I + Z)^{-1}
@@ -167,16 +168,23 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
 #pragma unroll
     for (int u = 0; u < U; ++u) pf[u] = src[u * rstride];
   };
-  int64_t tile = blockIdx.x;  // the grid never exceeds the number of blocks of tubes
+  // Workgroup w takes groups w, w + G, w + 2G, ... (G = gridDim.x) of `group`
+  // consecutive blocks of tubes; a group spans whole 128-byte lines of every
+  // slice, so a line's second part is read from the CU's own L2.  The grid
+  // never exceeds the number of groups, so the first block exists.
+  const int grp = a.group;
+  auto tile_of = [&](int64_t n) { return ((int64_t)blockIdx.x + n / grp * gridDim.x) * grp + n % grp; };
+  int64_t n = 0, tile = tile_of(0);
   fetch(tile);
-  for (; tile < ntiles; tile += gridDim.x) {
+  for (; tile < ntiles; tile = tile_of(++n)) {
     const int64_t e0 = tile * nb;
     const bool live = e0 + jt < count;
 #pragma unroll
     for (int u = 0; u < U; ++u) rb[tid + u * kFastThreads] = live ? pf[u] : (T)0;
     __syncthreads();
     // the next block of tubes is in flight while this one is transformed
-    fetch(tile + gridDim.x < ntiles ? tile + gridDim.x : tile);
+    const int64_t next = tile_of(n + 1);
+    fetch(next < ntiles ? next : tile);
     if (a.pre == 2) {
       alt_scan<T, false>(rb, part, p, nb, lognb);
       __syncthreads();
@@ -335,8 +343,14 @@ hipError_t launch_tube_fast(dctk_ctx ctx, hipStream_t s, int tube, int which, in
     default: return hipErrorInvalidValue;
   }
   const int64_t tiles = (count + a.nb - 1) / a.nb;
-  // resident workgroups (two fit a CU's LDS, 16 waves), each looping over blocks of tubes
-  const int64_t blocks = std::min<int64_t>(tiles, 2 * (int64_t)num_cus());
+  // Blocks of tubes narrower than a 128-byte line go to one workgroup in
+  // groups, while a group's lines (p of them) still fit the L2 share of the
+  // workgroups resident on an XCD (p <= 512).
+  const int seg = a.nb * (dtype == DCTK_F64 ? 8 : 4);
+  a.group = (p <= 512 && seg < 128) ? 128 / seg : 1;
+  const int64_t groups = (tiles + a.group - 1) / a.group;
+  // resident workgroups (two fit a CU's LDS, 16 waves), each looping over groups
+  const int64_t blocks = std::min<int64_t>(groups, 2 * (int64_t)num_cus());
   const dim3 g((unsigned)blocks), b(kFastThreads);
   if (dtype == DCTK_F64) {
     if (a.inv) tube_fast_kernel<double, true><<<g, b, 0, s>>>(a);
