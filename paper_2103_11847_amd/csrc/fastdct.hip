@@ -118,9 +118,14 @@ __device__ void alt_scan(T* buf, T* part, int p, int nb, int lognb) {
   }
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, bool PAIR>
 __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) {
   constexpr int E = FastCfg<T>::E;
+  // With two or more tubes per block (PAIR), tubes j and j + nb/2 share one
+  // complex FFT as its real and imaginary parts: the forward input and the
+  // inverse output are real, so each FFT serves two tubes.
+  constexpr int NQ4 = PAIR ? E / 8 : E / 4;  // radix-4 groups per pass
+  constexpr int NQ2 = PAIR ? E / 4 : E / 2;  // radix-2 butterflies of a last stage
   constexpr int U = E / kFastThreads;  // elements per thread and block of tubes
   __shared__ T rb[E];              // the tubes as real values
   __shared__ T re[E], im[E];       // complex FFT buffer, position-major
@@ -147,6 +152,9 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
   // and rows t0, t0 + RU, t0 + 2 RU, ...
   const int jt = tid & (nb - 1), t0 = tid >> lognb, ru = kFastThreads >> lognb;
   const int64_t rstride = (int64_t)ru * count;
+  const int nbc = PAIR ? nb >> 1 : nb, lognbc = PAIR ? lognb - 1 : lognb;  // complex columns
+  const int jc = jt & (nbc - 1);                  // this thread's complex column
+  const bool hi = PAIR && jt >= nbc;              // imaginary part of it
   T rc[U], rs[U], rq[U], rq2[INV ? U : 1];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -198,9 +206,29 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
         T y = rb[i];
         if (a.pre == 1 && t + 1 < p) y += rb[i + nb];
         const int n = (t & 1) ? p - 1 - (t >> 1) : (t >> 1);  // even entries, then odd ones reversed
-        const int d = bit_reverse(n, logp) * nb + j;
-        re[sw(d)] = y;
-        im[sw(d)] = 0;
+        if (!PAIR) {
+          const int d = bit_reverse(n, logp) * nb + j;
+          re[sw(d)] = y;
+          im[sw(d)] = 0;
+        } else {
+          const int d = sw(bit_reverse(n, logp) * nbc + jc);
+          if (hi) im[d] = y;
+          else re[d] = y;
+        }
+      } else if (PAIR) {
+        // Z_k = V_k(tube jc) + i V_k(tube jc + nbc), formed by the low half of the threads
+        if (!hi) {
+          const int k = t;
+          const T xk = rb[i] * rq[u], yk = rb[i + nbc] * rq[u];
+          const int ip = (p - k) * nb + j;
+          const T xpk = k ? rb[ip] * rq2[INV ? u : 0] : (T)0;
+          const T ypk = k ? rb[ip + nbc] * rq2[INV ? u : 0] : (T)0;
+          const T var = rc[u] * xk + rs[u] * xpk, vai = rs[u] * xk - rc[u] * xpk;
+          const T vbr = rc[u] * yk + rs[u] * ypk, vbi = rs[u] * yk - rc[u] * ypk;
+          const int d = sw(bit_reverse(k, logp) * nbc + jc);
+          re[d] = var - vbi;
+          im[d] = vai + vbr;
+        }
       } else {
         // V_k = exp(i pi k / (2p)) (X_k - i X_{p-k}), X_p = 0, with X = R x
         const int k = t;
@@ -219,11 +247,10 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
     int h = 1, sh = logp - 1;
     for (; 2 * h < p; h <<= 2, sh -= 2) {
 #pragma unroll 2
-      for (int v = 0; v < U / 4; ++v) {
-        const int q = tid + v * kFastThreads;
-        const int b = q >> lognb, j = q & (nb - 1);
+      for (int q = tid; q < NQ4; q += kFastThreads) {
+        const int b = q >> lognbc, j = q & (nbc - 1);
         const int pos = b & (h - 1);
-        const int i0 = (((b - pos) << 2) + pos) * nb + j, hs = h * nb;
+        const int i0 = (((b - pos) << 2) + pos) * nbc + j, hs = h * nbc;
         const int k1 = pos << sh, k2 = pos << (sh - 1), k3 = (pos + h) << (sh - 1);
         const T w1r = twr[k1], w1i = INV ? -twi[k1] : twi[k1];
         const T w2r = twr[k2], w2i = INV ? -twi[k2] : twi[k2];
@@ -255,10 +282,9 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
     }
     if (h < p) {  // h == p / 2: the last radix-2 stage, twiddle index pos (sh == 0)
 #pragma unroll 2
-      for (int v = 0; v < U / 2; ++v) {
-        const int q = tid + v * kFastThreads;
-        const int pos = q >> lognb, j = q & (nb - 1);
-        const int i0 = sw(pos * nb + j), i1 = sw(pos * nb + j + h * nb);
+      for (int q = tid; q < NQ2; q += kFastThreads) {
+        const int pos = q >> lognbc, j = q & (nbc - 1);
+        const int i0 = sw(pos * nbc + j), i1 = sw(pos * nbc + j + h * nbc);
         const T wr = twr[pos], wi = INV ? -twi[pos] : twi[pos];
         const T br = re[i1], bi = im[i1];
         const T tr = wr * br - wi * bi, ti = wr * bi + wi * br;
@@ -276,7 +302,17 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = tid + u * kFastThreads;
-        const T f = re[sw(i)] * rc[u] + im[sw(i)] * rs[u];
+        T f;
+        if (!PAIR) {
+          f = re[sw(i)] * rc[u] + im[sw(i)] * rs[u];
+        } else {
+          // this tube's spectrum from Z_k and Z_{p-k} of the shared FFT
+          const int k = t0 + u * ru;
+          const int zk = sw(k * nbc + jc), zp = sw(((p - k) & (p - 1)) * nbc + jc);
+          const T zr = re[zk], zi = im[zk], wr = re[zp], wi = im[zp];
+          const T vr = hi ? zi + wi : zr + wr, vi = hi ? wr - zr : zi - wi;
+          f = (T)0.5 * (vr * rc[u] + vi * rs[u]);
+        }
         if (live) dst[u * rstride] = f * rq[u];
       }
     } else {
@@ -287,7 +323,8 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
         const int i = tid + u * kFastThreads;
         const int t = i >> lognb, j = i & (nb - 1);
         const int n = (t & 1) ? p - 1 - (t >> 1) : (t >> 1);
-        rb[i] = re[sw(n * nb + j)] * inv_p;
+        if (!PAIR) rb[i] = re[sw(n * nb + j)] * inv_p;
+        else rb[i] = (hi ? im : re)[sw(n * nbc + jc)] * inv_p;
       }
       __syncthreads();
       if (a.post == 2) {
@@ -352,13 +389,20 @@ hipError_t launch_tube_fast(dctk_ctx ctx, hipStream_t s, int tube, int which, in
   // resident workgroups (two fit a CU's LDS, 16 waves), each looping over groups
   const int64_t blocks = std::min<int64_t>(groups, 2 * (int64_t)num_cus());
   const dim3 g((unsigned)blocks), b(kFastThreads);
-  if (dtype == DCTK_F64) {
-    if (a.inv) tube_fast_kernel<double, true><<<g, b, 0, s>>>(a);
-    else tube_fast_kernel<double, false><<<g, b, 0, s>>>(a);
-  } else {
-    if (a.inv) tube_fast_kernel<float, true><<<g, b, 0, s>>>(a);
-    else tube_fast_kernel<float, false><<<g, b, 0, s>>>(a);
-  }
+  const bool pair = a.nb >= 2;
+#define DCTK_FAST_LAUNCH(T)                                                          \
+  do {                                                                               \
+    if (a.inv) {                                                                     \
+      if (pair) tube_fast_kernel<T, true, true><<<g, b, 0, s>>>(a);                  \
+      else tube_fast_kernel<T, true, false><<<g, b, 0, s>>>(a);                      \
+    } else {                                                                         \
+      if (pair) tube_fast_kernel<T, false, true><<<g, b, 0, s>>>(a);                 \
+      else tube_fast_kernel<T, false, false><<<g, b, 0, s>>>(a);                     \
+    }                                                                                \
+  } while (0)
+  if (dtype == DCTK_F64) DCTK_FAST_LAUNCH(double);
+  else DCTK_FAST_LAUNCH(float);
+#undef DCTK_FAST_LAUNCH
   return hipGetLastError();
 }
 
