@@ -193,6 +193,55 @@ def test_adjoint_is_dense_transpose(tb, two_sided):
             assert np.allclose(Dm[:, e], cprod_definition(A, x.reshape(p, n2, s)).ravel(), atol=1e-12)
 
 
+@pytest.mark.parametrize("p,n1,n2,s", [(1, 2, 3, 2), (2, 3, 2, 3), (3, 2, 4, 2), (4, 3, 3, 2), (5, 2, 2, 3)])
+def test_two_sided_operator_is_definition_applied_twice(p, n1, n2, s):
+    """eq. (2): A *c X *c B with L = M is (A *c X) *c B, each product the
+    block Toeplitz-plus-Hankel Definition of Sec. 2.2 (brute force).  A right
+    factor used transposed, or multiplied on the wrong side, fails this."""
+    rng = np.random.default_rng(61 + 7 * p + n1 + 3 * s)
+    A = rng.standard_normal((p, n1, n2))
+    B = rng.standard_normal((p, s, s))
+    X = rng.standard_normal((p, n2, s))
+    ref = cprod_definition(cprod_definition(A, X), B)
+    out = Operator(A, B, "th").apply(X)
+    assert np.abs(out - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max())
+    # the dense adjoint of the two-sided operator is the transpose of the
+    # literal block matrix mat(B)^T (x) mat(A) acting on the unfolded X
+    Dref = []
+    for e in range(p * n2 * s):
+        x = np.zeros(p * n2 * s)
+        x[e] = 1.0
+        Dref.append(cprod_definition(cprod_definition(A, x.reshape(p, n2, s)), B).ravel())
+    Dref = np.stack(Dref, axis=1)
+    op = Operator(A, B, "th")
+    Y = rng.standard_normal((p, n1, s))
+    assert np.allclose(op.adjoint(Y).ravel(), Dref.T @ Y.ravel(), atol=1e-11)
+
+
+@pytest.mark.parametrize("p,n1,n2,s", [(2, 3, 2, 3), (3, 4, 3, 2), (8, 2, 3, 2)])
+def test_two_sided_dct2_operator_matches_scipy_dct(p, n1, n2, s):
+    """With L = C_n (Algorithm 1's orthonormal DCT along tubes), A *c X *c B is
+    idct(dct(A)_k dct(X)_k dct(B)_k) per frontal slice, the DCT taken by
+    scipy's FFT-based routine and the slices multiplied in explicit loops."""
+    rng = np.random.default_rng(67 + p)
+    A = rng.standard_normal((p, n1, n2))
+    B = rng.standard_normal((p, s, s))
+    X = rng.standard_normal((p, n2, s))
+    Ah, Xh, Bh = (scipy.fft.dct(T, type=2, norm="ortho", axis=0) for T in (A, X, B))
+    Yh = np.zeros((p, n1, s))
+    for k in range(p):
+        for i in range(n1):
+            for j in range(s):
+                acc = 0.0
+                for t in range(n2):
+                    for u in range(s):
+                        acc += Ah[k, i, t] * Xh[k, t, u] * Bh[k, u, j]
+                Yh[k, i, j] = acc
+    ref = scipy.fft.idct(Yh, type=2, norm="ortho", axis=0)
+    out = Operator(A, B, "dct2").apply(X)
+    assert np.abs(out - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
 def test_adjoint_for_orthogonal_dct_is_slice_transpose():
     """For L = C_n (orthogonal), M* transposes every transform-domain slice."""
     rng = np.random.default_rng(19)
@@ -319,6 +368,51 @@ def test_gmres_lambda0_is_krylov_least_squares():
         ref = X0 + combine(K, coef)
         out = krylov.dc_gmres(op, C, X0, m, 1, lam=0.0)["X"]
         assert fro(out - ref) <= 1e-9 * fro(ref)
+
+
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_restarted_gmres_lambda0_is_restarted_krylov_least_squares(two_sided):
+    """Algorithm 3 with restarts at lambda = 0: every cycle c restarts from the
+    true residual R = C - M(X_{c-1}) and adds the minimiser of
+    ||R - M(Z)|| over Z in TK_m(A, R) (eq. tr3).  Reference: that recursion
+    written out on the dense matrix of M with the power basis of each cycle's
+    Krylov space and a least-squares solve; a cycle that reuses R_0 or skips
+    X's update fails it."""
+    op, C = _problem(seed=71, p=2, n=3, s=2, two_sided=two_sided)
+    D = op.dense(2)
+    b = C.ravel()
+    rng = np.random.default_rng(3)
+    X0 = rng.standard_normal(C.shape)
+    for m, cycles in [(1, 4), (2, 3), (3, 2)]:
+        x = X0.ravel().copy()
+        for _ in range(cycles):
+            r = b - D @ x
+            K = [r]
+            for _ in range(m - 1):
+                K.append(D @ K[-1])
+            K = np.stack(K, axis=1)
+            coef, *_ = np.linalg.lstsq(D @ K, r, rcond=None)
+            x = x + K @ coef
+        out = krylov.dc_gmres(op, C, X0, m, cycles, lam=0.0)
+        assert np.linalg.norm(out["X"].ravel() - x) <= 1e-9 * np.linalg.norm(x)
+        assert abs(out["resnorm"] - np.linalg.norm(b - D @ x)) <= 1e-9 * np.linalg.norm(b)
+        # restarts do make progress here: more cycles, smaller residual
+        one = krylov.dc_gmres(op, C, X0, m, 1, lam=0.0)
+        assert out["resnorm"] < one["resnorm"]
+
+
+def test_restarted_gmres_matches_scipy_gmres():
+    """DC-GMRES(m) at lambda = 0 with c cycles equals scipy's restarted GMRES
+    on the dense matrix of M (restart = m, c outer iterations, no tolerance
+    stop), a library implementation of the same restarted minimisation."""
+    op, C = _problem(seed=73, p=2, n=3, s=2)
+    D = op.dense(2)
+    b = C.ravel()
+    for m, cycles in [(2, 3), (4, 2)]:
+        ref, info = scipy.sparse.linalg.gmres(D, b, x0=np.zeros_like(b), restart=m, maxiter=cycles,
+                                              rtol=1e-300, atol=0.0)
+        out = krylov.dc_gmres(op, C, np.zeros_like(C), m, cycles, lam=0.0)["X"].ravel()
+        assert np.linalg.norm(out - ref) <= 1e-8 * np.linalg.norm(ref)
 
 
 def test_gk_tikhonov_full_dimension_is_dense_tikhonov():
