@@ -1,22 +1,29 @@
-"""Benchmark: DC-LSQR/DC-GK solves per second on one MI355X.
+"""Benchmark: DC-GK / DC-LSQR solves per second on one MI355X.
 
-Workload: colour-image deblurring, n1 = n2 = s = 256, n3 = 3 (mixing tube
-(0.7, 0.15, 0.15) times a Gaussian Toeplitz blur sigma = 3, band 8), smooth
-plus edges synthetic image, noise 1e-2.  One step = one solve: 40
-Golub-Kahan steps with the LSQR recurrence, FP64 projected SVD + GCV, and
-X = V_k (*) y -- every stage of the hot path, inputs resident in HBM.
+Default workload (the largest single-GPU configuration): hyperspectral-like
+deblurring, n1 = n2 = s = 512, n3 = 64, band-dependent Gaussian blur (sigma
+from 1.5 to 4 over the bands), spectral Gaussian field, noise level drawn in
+[1e-3, 2e-2].  One step = one solve: 40 Golub-Kahan steps (Algorithm 4) with
+FP32 vectors and FP32 slice GEMMs on MFMA, the FP64 projected Tikhonov problem
+with GCV (Algorithm 5), X = V_k (*) y -- every stage of the hot path, inputs
+resident in HBM.
 
 Printed JSON line (rank 0):
-  value        solves/s, counted only if the restoration error of the solve
-               is within 1.05x of the FP64 oracle's on the same input
-  roofline     the dominant kernel (the fused c-product with the largest total
-               time) timed live with HIP events around each launch; bound by
-               MFMA or HBM according to its arithmetic intensity
-  cpu_baseline the FP64 oracle timed on the host cores on a bounded sample
-  cprod        one c-product: time, algorithmic GB/s and MFMA fraction
+  value        solves/s, counted only if the solve's restoration error is
+               within 1.05x of a full FP64 oracle solve of the same input,
+               run in the same process
+  roofline     the kernel kind with the largest total time inside the timed
+               solves, timed by start/stop events that each launch records on
+               the library's stream; bound by MFMA or HBM by its arithmetic
+               intensity
+  cpu_baseline the same full oracle solve, timed on the host cores
+  mixed_bf16   the same solve with BF16 slice GEMMs (FP32 accumulation), gated
+               the same way
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--gemm f32|bf16|f16]
-                       [--no-cpu-baseline] [--cprod-reps R] [--copy-calib-mib M]
+Other workloads: --workload colour256 | video256 | batch64 | paper | longtube.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hyper512]
+                       [--gemm f32|bf16|f16] [--no-cpu-baseline] [--copy-calib-mib M]
 """
 import argparse
 import json
@@ -46,6 +53,12 @@ TRAFFIC = {"digest": "2745717c67c60cfc", "gemm": "f32",
 LONGTUBE_SOURCES = ("paper_2103_11847_amd/csrc/fastdct.hip", "paper_2103_11847_amd/csrc/fastdct.h")
 LONGTUBE_TRAFFIC = {"digest": "8316061216a2f747", "bytes": 657846060}
 
+# The same for the three kernels of the 512 x 512 x 64 products (bytes per launch,
+# keyed "gemm type/kernel"), filled in from the counter passes of the hyper512 bench.
+HYPER_TRAFFIC_SOURCES = ("paper_2103_11847_amd/csrc/gemm.hip", "paper_2103_11847_amd/csrc/transform.hip",
+                         "paper_2103_11847_amd/csrc/mfma.h", "paper_2103_11847_amd/csrc/internal.h")
+HYPER_TRAFFIC = {"digest": None, "bytes": {}}
+
 
 def source_digest(files):
     import hashlib
@@ -71,8 +84,9 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "f64": 78.6}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 for hyper512, 50 for the other workloads)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 3 for hyper512, else 5)")
     ap.add_argument("--gemm", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -89,11 +103,18 @@ def parse():
     ap.add_argument("--lambda-rule", default="gcv", choices=["gcv", "discrepancy", "lcurve"],
                     help="colour256: lambda by GCV (default), by the discrepancy principle at 1.05 x the "
                          "norm of the added noise, or LSQR stopped at the L-curve corner")
-    ap.add_argument("--workload", default="colour256",
-                    choices=["colour256", "batch64", "video256", "hyper512", "paper", "longtube"],
-                    help="colour256: one 256x256x3 solve per step (default); batch64: the uneven "
-                         "64-instance batch per step (merged launches, HIP graph)")
-    return ap.parse_args()
+    ap.add_argument("--workload", default="hyper512",
+                    choices=["hyper512", "colour256", "batch64", "video256", "paper", "longtube"],
+                    help="hyper512: one 512x512x64 solve per step (default); colour256: one 256x256x3 "
+                         "solve per step; batch64: the uneven 64-instance batch per step (merged launches, "
+                         "HIP graph)")
+    ap.add_argument("--no-mixed", action="store_true", help="hyper512: skip the BF16-GEMM leg")
+    a = ap.parse_args()
+    if a.steps is None:
+        a.steps = 20 if a.workload == "hyper512" else 50
+    if a.warmup is None:
+        a.warmup = 3 if a.workload == "hyper512" else 5
+    return a
 
 
 def blas_threads():
@@ -155,7 +176,9 @@ def main():
         sys.exit(1)
     if args.workload == "batch64":
         return bench_batch(args)
-    if args.workload in ("video256", "hyper512"):
+    if args.workload == "hyper512":
+        return bench_hyper(args)
+    if args.workload == "video256":
         return bench_large(args)
     if args.workload == "paper":
         return bench_paper(args)
@@ -772,16 +795,184 @@ def plain_fp32_loop(ctx, insts, k, opts, args):
     return {"loop_s": loop_s, "errs": errs}
 
 
+# Algorithmic work per launch of the three kernels of a one-sided product inside a
+# GKB step (N = p n s elements per Krylov tensor, b_g bytes per GEMM element):
+#   tube_fwd  reads the unnormalised vector, writes its normalised copy (V_j or
+#             U_{j+1}) and the transformed tubes in the GEMM type: N (8 + b_g) bytes,
+#             2 p N flops
+#   gemm      reads A~ (p n1 n2 b_g) and the transformed tubes (N b_g), writes the
+#             FP32 slice products (4 N): 2 n1 n2 s p flops
+#   tube_inv  reads the slice products and the epilogue's src, writes the output:
+#             12 N bytes, 2 p N flops
+def kernel_work(kind, p, n1, n2, s, bg):
+    N = p * n2 * s
+    if kind == "gemm":
+        return 2.0 * n1 * n2 * s * p, p * n1 * n2 * bg + N * (bg + 4)
+    if kind == "tube_fwd":
+        return 2.0 * p * N, N * (8 + bg)
+    if kind == "tube_inv":
+        return 2.0 * p * N, 12.0 * N
+    raise ValueError(kind)
+
+
+def roofline_entry(kind, avg_us, flops, byts, gemm, traffic=None):
+    """Bound by arithmetic intensity against the ridge of the kernel's arithmetic:
+    the slice GEMM against its MFMA type, the transforms against FP32."""
+    peak_f = MFMA_PEAK_TFLOPS[gemm if kind == "gemm" else "f32"]
+    ai = flops / byts
+    if ai >= peak_f * 1e12 / (HBM_PEAK_GBS * 1e9):
+        r = {"bound": "mfma", "achieved": flops / (avg_us * 1e-6) / 1e12, "peak": peak_f, "unit": "TFLOP/s"}
+    else:
+        r = {"bound": "hbm", "achieved": byts / (avg_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = traffic
+    r.update({"kernel": kind, "avg_us": avg_us, "flops_per_launch": flops, "bytes_per_launch": byts,
+              "arith_intensity": ai})
+    return r
+
+
+def hyper_traffic(kind, gemm):
+    """HBM bytes per launch from the rocprofv3 counter passes, while the sources match."""
+    if source_digest(HYPER_TRAFFIC_SOURCES) != HYPER_TRAFFIC["digest"]:
+        return None
+    return HYPER_TRAFFIC["bytes"].get("%s/%s" % (gemm, kind))
+
+
+def bench_hyper(args):
+    """hyper512: one DC-GK solve (40 GKB steps, FP64 GCV) of the 512 x 512 x 64
+    hyperspectral-like problem per step, gated on a full FP64 oracle solve."""
+    import torch
+    import paper_2103_11847_amd as dk
+    import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.hyperspectral(0)
+    p, n, s = w["X_true"].shape
+    k = w["iters"]
+    ctx = dk.dctk_create(0)
+    A64 = torch.from_numpy(w["A"]).to(dev)
+    # C = M(X_true) + noise at relative level nu, formed with the library's FP64 product
+    op64 = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F64, A64, s)
+    Xt = torch.from_numpy(w["X_true"]).to(dev)
+    Ch = torch.empty_like(Xt)
+    dk.dctk_cprod(ctx, op64, 1.0, Xt, 0.0, Ch)
+    dk.dctk_op_destroy(op64)
+    N0 = torch.from_numpy(w["N0"]).to(dev)
+    C = (Ch + w["nu"] * torch.linalg.norm(Ch) / torch.linalg.norm(N0) * N0).to(torch.float32).contiguous()
+    del Ch, N0
+    opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0, 0.0)
+    nrm_t = float(torch.linalg.norm(Xt))
+
+    def run(gemm, steps, warmup):
+        """Timed region: `steps` solves enqueued back to back (no read-back between
+        them).  Then the same number of solves with every transform / GEMM launch
+        recording start and stop events on the library's stream (kernel times)."""
+        op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DTYPES[gemm], A64, s)
+        ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k)
+        X = torch.empty_like(C)
+        for _ in range(warmup):
+            dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        dk.dctk_profile_begin(ctx)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=False)
+        torch.cuda.synchronize()
+        ms_prof = (time.perf_counter() - t0) * 1e3 / steps
+        prof = dk.dctk_profile_end(ctx)
+        info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, opts)
+        err = float(torch.linalg.norm(X.double() - Xt)) / nrm_t
+        dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
+        return ms, ms_prof, prof, err, info
+
+    gemm = args.gemm
+    ms, ms_prof, prof, err_gpu, info = run(gemm, args.steps, args.warmup)
+    bg = {"f32": 4, "bf16": 2, "f16": 2}[gemm]
+    kinds = {}
+    for kind in ("tube_fwd", "gemm", "tube_inv"):
+        tot, cnt = prof[kind]
+        if cnt:
+            f, b = kernel_work(kind, p, n, n, s, bg)
+            kinds[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, gemm, hyper_traffic(kind, gemm))
+            kinds[kind].update({"launches": cnt, "ms_total": tot})
+    dom = max(kinds, key=lambda k_: kinds[k_]["ms_total"])
+    roof = dict(kinds[dom])
+    roof["kernel"] = {"gemm": "slice GEMM batch (p MFMA GEMMs of n1 x n2 by n2 x s)",
+                      "tube_fwd": "forward tube transform (MFMA, with the normalised copy)",
+                      "tube_inv": "inverse tube transform (MFMA, with the epilogue)"}[dom]
+    roof["per_kind"] = kinds
+
+    mixed = None
+    if not args.no_mixed and gemm == "f32":
+        ms_b, _, prof_b, err_b, info_b = run("bf16", args.steps, 2)
+        kb = {}
+        for kind in ("tube_fwd", "gemm", "tube_inv"):
+            tot, cnt = prof_b[kind]
+            if cnt:
+                f, b = kernel_work(kind, p, n, n, s, 2)
+                kb[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, "bf16", hyper_traffic(kind, "bf16"))
+                kb[kind].update({"launches": cnt, "ms_total": tot})
+        mixed = {"solves_per_s": 1e3 / ms_b, "ms_per_step": ms_b, "relerr_gpu": err_b, "lambda": info_b.lam,
+                 "per_kind": kb}
+
+    # the FP64 oracle: one full solve of the same problem (its own C), timed
+    from oracle import krylov, metrics
+    from oracle.cprod import Operator, fro
+    t0 = time.perf_counter()
+    orc = Operator(w["A"])
+    Cn = orc.apply(w["X_true"])
+    Cn = Cn + w["nu"] * fro(Cn) / fro(w["N0"]) * w["N0"]
+    ref = krylov.dc_gk(orc, Cn, k, lam=None, gcv_mode="rect", reorth="none")
+    dt = time.perf_counter() - t0
+    err_oracle = metrics.relative_error(w["X_true"], ref["X"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = {"value": 1.0 / dt, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": "one full FP64 DC-GK solve of the same 512x512x64 problem (operator set-up, C, 40 GKB "
+                         "steps, GCV, combine) in %.1f s (numpy, BLAS matmul)" % dt}
+    gate = err_gpu <= 1.05 * err_oracle
+    if mixed is not None:
+        mixed["ratio_vs_oracle"] = mixed["relerr_gpu"] / err_oracle
+        mixed["gate_1_05"] = mixed["relerr_gpu"] <= 1.05 * err_oracle
+        mixed["value"] = mixed["solves_per_s"] if mixed["gate_1_05"] else 0.0
+        mixed["speedup_vs_f32"] = ms / ms_b
+    dk.dctk_destroy(ctx)
+    line = {
+        "metric": METRIC, "value": (1e3 / ms) if gate else 0.0, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": gemm, "data": "synthetic",
+        "config": {"workload": "hyperspectral-like deblur 512x512x64, band-dependent blur sigma 1.5-4, "
+                               "DC-GK 40 GKB steps + FP64 GCV, one solve per step",
+                   "n1": n, "n2": n, "s": s, "n3": p, "gkb_steps": k, "gemm_dtype": gemm,
+                   "vector_dtype": "f32", "reorth": "none", "tube": "th", "nu": w["nu"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "restoration": {"relerr_gpu": err_gpu, "relerr_oracle_fp64": err_oracle, "ratio": err_gpu / err_oracle,
+                        "gate_1_05": gate, "lambda_gpu": info.lam, "lambda_oracle": ref["lambda"],
+                        "iters": info.iters},
+        "profiled_pass": {"ms_per_step": ms_prof,
+                          "note": "the kernel times come from a second pass of the same number of solves in "
+                                  "which every launch records start/stop events"},
+        "mixed_bf16": mixed,
+    }
+    print(json.dumps(line))
+
+
 def bench_large(args):
-    """video256: two-sided 256x256x32 DC-GMRES (40 Arnoldi steps, GCV); hyper512: 512x512x64
-    DC-GK (40 GKB steps, GCV).  One step = one solve; the dominant kernel is timed live."""
+    """video256: two-sided 256x256x32 DC-GMRES (40 Arnoldi steps, GCV), one solve per
+    step; the dominant kernel is timed live."""
     import torch
     import paper_2103_11847_amd as dk
     import workloads as W
     dev = torch.device("cuda:0")
     gdt = dk.DTYPES[args.gemm]
     video = args.workload == "video256"
-    w = W.video_256() if video else W.hyperspectral(0)
+    w = W.video_256()
     p, n, s = w["X_true"].shape
     k = 40
     ctx = dk.dctk_create(0)

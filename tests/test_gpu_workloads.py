@@ -1,16 +1,24 @@
-"""The larger workloads at their full sizes.
+"""The larger workloads at their full sizes, against the FP64 oracle.
 
-Video: two-sided A *c X *c B, 256 x 256 x 32 frames, DC-GMRES with Tikhonov/GCV
-(40 Arnoldi steps, one cycle) with FP32 and FP16 slice GEMMs: restoration error
-within 1.05x of the FP64 oracle's on the same input.
+Video: two-sided A *c X *c B, 256 x 256 x 32 frames: the whole product and
+its adjoint element-wise (FP32 to 1e-5; FP16 to the rounding model of the
+16-bit GEMM mode), and DC-GMRES with Tikhonov/GCV (40 Arnoldi steps) with
+restoration error within 1.05x of the oracle's on the same input.
 
-Hyperspectral: 512 x 512 x 64 with band-dependent blur, DC-GK (40 GKB steps,
-GCV), FP32 and BF16 slice GEMMs.  At this size the oracle computes sampled
-output tubes of one product (each from its own tube transforms and slice
-rows), and the solve is checked through the LSQR residual identity
-|phibar_{k+1}| = ||C - M(X_k)|| (Algorithm 6 / Proposition 3.2), which holds
-at any size (to the slices' rounding); the restoration error
-is compared with the oracle's on the same problem family at 128 x 128 x 64.
+Hyperspectral-like: 512 x 512 x 64, band-dependent blur: the whole product
+and adjoint element-wise (FP32 to 1e-5; BF16 to the rounding model and to
+the roundoff bound of its operands), DC-GK (40 GKB steps, GCV) in FP32 and
+BF16 with restoration error within 1.05x of a full FP64 oracle solve of the
+same C, and the FP32 LSQR iterate's residual identity |phibar_{k+1}| =
+||C - M(X_k)|| (Algorithm 6), the right side evaluated by the oracle.
+
+Paper-shaped (Sec. 4, Tables 1 and 3): two-sided colour deblurring with the
+A_color tube, sigma = 4, r = 6.  At 256 x 256 x 3 DC-GMRES(10) (10 cycles),
+DC-GK (15 steps) and DC-LSQR (14 steps) in FP64 and FP32 within 1.05x of the
+oracle's restoration error; at 1024 x 1024 x 3 one product and one adjoint
+element-wise.
+
+Every C here is formed by the oracle (FP64) and handed to the GPU.
 """
 import numpy as np
 import pytest
@@ -19,6 +27,7 @@ import workloads as W
 from oracle import krylov, metrics
 from oracle import tube as otube
 from oracle.cprod import Operator, fro
+from tests import rounding_model as RM
 from tests.gpu_util import rel, say, to_gpu, to_np
 
 torch = pytest.importorskip("torch")
@@ -27,6 +36,7 @@ pytestmark = pytest.mark.gpu
 import paper_2103_11847_amd as dk  # noqa: E402
 
 F64, F32 = torch.float64, torch.float32
+KIND = {dk.DCTK_BF16: "bf16", dk.DCTK_F16: "f16"}
 
 
 @pytest.fixture(scope="module")
@@ -43,6 +53,44 @@ def _noisy(orc, w):
     Ch = orc.apply(w["X_true"])
     return Ch + w["nu"] * fro(Ch) / fro(w["N0"]) * w["N0"]
 
+
+def _check_products(ctx, op, gdt, w, orc, X, Yin, label, bound_exact=False):
+    """Product of X and adjoint of Yin on the GPU against the oracle, element-wise."""
+    p = X.shape[0]
+    A, B = w["A"], w.get("B")
+    L = otube.transform_matrix(p, "th")
+    vt = F64 if gdt == dk.DCTK_F64 else F32
+    out = {}
+    for adj, inp in ((False, X), (True, Yin)):
+        rows = A.shape[2] if adj else A.shape[1]
+        Yg = torch.empty((p, rows, inp.shape[2]), dtype=vt, device="cuda:0")
+        fn = dk.dctk_cprod_T if adj else dk.dctk_cprod
+        fn(ctx, op, 1.0, to_gpu(inp, vt), 0.0, Yg)
+        got = to_np(Yg)
+        del Yg
+        exact = orc.adjoint(inp) if adj else orc.apply(inp)
+        if gdt in (dk.DCTK_F64, dk.DCTK_F32):
+            e = rel(got, exact)
+            tol = 1e-10 if gdt == dk.DCTK_F64 else 1e-5
+            say(label, "adjoint" if adj else "product", "rel", e, "tol", tol)
+            assert e <= tol
+            out[adj] = e
+            continue
+        kind = KIND[gdt]
+        gap, e, e_model = RM.check_lowp(got, A, B, L, inp, kind, exact, adj)
+        say(label, "adjoint" if adj else "product", kind, "gap to rounding model", gap,
+            "rel", e, "model rel", e_model)
+        assert gap <= RM.MODEL_TOL[kind]
+        assert e <= 1.25 * e_model
+        if bound_exact:
+            b = RM.roundoff_bound(A, B, L, inp, kind, adj) / np.linalg.norm(exact.ravel())
+            say(label, "  roundoff bound", b)
+            assert e <= b
+        out[adj] = e
+    return out
+
+
+# ------------------------------------------------------------------- video
 
 @pytest.fixture(scope="module")
 def video(ctx):
@@ -62,13 +110,8 @@ def test_video_two_sided_gmres(ctx, video, gdt):
     op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, to_gpu(w["A"], F64), s, to_gpu(w["B"], F64))
     ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_ARNOLDI, 40)
     try:
-        # product parity at full size
-        Y = torch.empty((p, n, s), dtype=F32, device="cuda:0")
-        dk.dctk_cprod(ctx, op, 1.0, to_gpu(w["X_true"], F32), 0.0, Y)
-        Yref = orc.apply(w["X_true"])
-        bound = 1e-5 if gdt == dk.DCTK_F32 else 2 * 8.0 * 2.0 ** -11 * np.sqrt(p)
-        say("video cprod rel", rel(to_np(Y), Yref), "bound", bound)
-        assert rel(to_np(Y), Yref) <= bound
+        rng = np.random.default_rng(31)
+        _check_products(ctx, op, gdt, w, orc, w["X_true"], rng.standard_normal((p, n, s)), "video")
         X = torch.zeros((p, n, s), dtype=F32, device="cuda:0")
         info = dk.dctk_gmres_tik_solve(ctx, ws, to_gpu(C, F32), X, 1, dk.make_opts(40, 0, 0, -1.0))
         e = metrics.relative_error(w["X_true"], to_np(X))
@@ -81,71 +124,79 @@ def test_video_two_sided_gmres(ctx, video, gdt):
         dk.dctk_op_destroy(op)
 
 
-def _sampled_tubes(A, X, L, Linv, pts):
-    """Output tubes Y(i, j, :) of A *c X from the transform formula, one tube at a time."""
-    Ah = (L @ A.reshape(A.shape[0], -1)).reshape(A.shape)   # A~_k, every slice
-    out = {}
-    for (i, j) in pts:
-        Xh_col = L @ X[:, :, j]                   # X~_k(:, j) for every k
-        yh = np.array([Ah[k, i, :] @ Xh_col[k] for k in range(A.shape[0])])
-        out[(i, j)] = Linv @ yh
-    return out
+# ---------------------------------------------------- hyperspectral 512 x 512 x 64
 
-
-@pytest.mark.parametrize("gdt,bound", [(dk.DCTK_F32, 1e-5), (dk.DCTK_BF16, 8.0 * 2.0 ** -8)])
-def test_hyperspectral_512_product_and_residual_identity(ctx, gdt, bound):
+@pytest.fixture(scope="module")
+def hyper(ctx):
+    """The 512 x 512 x 64 problem, its C from the oracle and a full FP64 oracle
+    DC-GK solve (40 GKB steps, GCV) of that C."""
     w = W.hyperspectral(0)
+    orc = Operator(w["A"])
+    C = _noisy(orc, w)
+    ref = krylov.dc_gk(orc, C, 40, lam=None, gcv_mode="rect", reorth="none")
+    e_ref = metrics.relative_error(w["X_true"], ref["X"])
+    say("hyper512 oracle relerr", e_ref, "lambda", ref["lambda"])
+    return w, orc, C, e_ref, ref["lambda"]
+
+
+@pytest.mark.parametrize("gdt", [dk.DCTK_F32, dk.DCTK_BF16])
+def test_hyperspectral_512_product_and_adjoint(ctx, hyper, gdt):
+    """Every output element of one product (of X_true) and one adjoint (of C)."""
+    w, orc, C, _, _ = hyper
+    s = w["X_true"].shape[2]
+    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, to_gpu(w["A"], F64), s)
+    try:
+        _check_products(ctx, op, gdt, w, orc, w["X_true"], C, "hyper512", bound_exact=True)
+    finally:
+        torch.cuda.synchronize()
+        dk.dctk_op_destroy(op)
+
+
+@pytest.mark.parametrize("gdt", [dk.DCTK_F32, dk.DCTK_BF16])
+def test_hyperspectral_512_restoration(ctx, hyper, gdt):
+    """DC-GK, 40 GKB steps, lambda by GCV: restoration error within 1.05x of the
+    FP64 oracle's solve of the same C."""
+    w, orc, C, e_ref, lam_ref = hyper
     p, n, s = w["X_true"].shape
-    A64 = to_gpu(w["A"], F64)
-    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, A64, s)
-    op64 = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F64, A64, s)
+    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, to_gpu(w["A"], F64), s)
     ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, 40)
     try:
-        # sampled output tubes of one product against the oracle's transform formula
-        Xt = to_gpu(w["X_true"], F32)
-        Y = torch.empty((p, n, s), dtype=F32, device="cuda:0")
-        dk.dctk_cprod(ctx, op, 1.0, Xt, 0.0, Y)
-        L = otube.transform_matrix(p, "th")
-        rng = np.random.default_rng(4)
-        pts = [(int(rng.integers(0, n)), int(rng.integers(0, s))) for _ in range(12)] + [(0, 0), (n - 1, s - 1)]
-        ref = _sampled_tubes(w["A"], w["X_true"], L, np.linalg.inv(L), pts)
-        Yn = to_np(Y)
-        got = np.stack([Yn[:, i, j] for (i, j) in pts])
-        want = np.stack([ref[q] for q in pts])
-        say("hyper sampled tubes rel", gdt, rel(got, want), "bound", bound)
-        assert rel(got, want) <= bound
-        # the solve: C from the library's FP64 product (an input, not an expected value)
-        Ch = torch.empty((p, n, s), dtype=F64, device="cuda:0")
-        dk.dctk_cprod(ctx, op64, 1.0, to_gpu(w["X_true"], F64), 0.0, Ch)
-        N0 = to_gpu(w["N0"], F64)
-        C = (Ch + w["nu"] * torch.linalg.norm(Ch) / torch.linalg.norm(N0) * N0).to(F32).contiguous()
         X = torch.empty((p, n, s), dtype=F32, device="cuda:0")
-        info = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, dk.make_opts(40, 0, 0, 0.0))   # LSQR iterate
-        # the identity holds for the operator the solver applied.  With FP32 slices that
-        # is the FP64 operator up to FP32 rounding.  With BF16 slices every product also
-        # rounds its transformed input to bfloat16, so M(X_k) differs from the
-        # combination of the products the recurrence saw by up to ~u ||C||, u = 2^-8.
-        MX = torch.empty((p, n, s), dtype=F64, device="cuda:0")
-        dk.dctk_cprod(ctx, op64, 1.0, X.double().contiguous(), 0.0, MX)
-        res = float(torch.linalg.norm(C.double() - MX))
-        cn = float(torch.linalg.norm(C.double()))
-        tol = 2e-3 * res if gdt == dk.DCTK_F32 else 4.0 * 2.0 ** -8 * cn
-        say("hyper LSQR residual identity", info.resnorm, res, "||C||", cn, "tol", tol)
-        assert abs(info.resnorm - res) <= tol
-        infog = dk.dctk_lsqr_tik_solve(ctx, ws, C, X, dk.make_opts(40, 0, 0, -1.0))
-        e = float(torch.linalg.norm(X.double() - to_gpu(w["X_true"], F64)) / torch.linalg.norm(to_gpu(w["X_true"], F64)))
-        say("hyper 512 GCV relerr", gdt, e, "lambda", infog.lam)
-        assert np.isfinite(e) and e < 1.0
+        info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F32), X, dk.make_opts(40, 0, 0, -1.0))
+        e = metrics.relative_error(w["X_true"], to_np(X))
+        say("hyper512 GCV", gdt, "relerr", e, "oracle", e_ref, "ratio", e / e_ref, "lambda", info.lam, lam_ref)
+        assert info.iters == 40
+        assert e <= 1.05 * e_ref
     finally:
         torch.cuda.synchronize()
         dk.dctk_krylov_destroy(ws)
         dk.dctk_op_destroy(op)
-        dk.dctk_op_destroy(op64)
+
+
+def test_hyperspectral_512_lsqr_residual_identity(ctx, hyper):
+    """FP32 DC-LSQR (lambda = 0, 40 steps): the recurrence's |phibar_{k+1}|
+    equals the true residual ||C - M(X_k)||, M applied by the oracle in FP64,
+    to 2e-3 of the residual (FP32 vectors and products over 40 steps)."""
+    w, orc, C, _, _ = hyper
+    p, n, s = w["X_true"].shape
+    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F32, to_gpu(w["A"], F64), s)
+    ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, 40)
+    try:
+        X = torch.empty((p, n, s), dtype=F32, device="cuda:0")
+        info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F32), X, dk.make_opts(40, 0, 0, 0.0))
+        Xk = to_np(X)
+        res = fro(C - orc.apply(Xk))
+        say("hyper512 LSQR |phibar|", info.resnorm, "true residual", res, "||C||", fro(C))
+        assert abs(info.resnorm - res) <= 2e-3 * res
+    finally:
+        torch.cuda.synchronize()
+        dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
 
 
 @pytest.mark.parametrize("gdt", [dk.DCTK_F32, dk.DCTK_BF16])
 def test_hyperspectral_128_restoration(ctx, gdt):
-    """The same family at 128 x 128 x 64, where the oracle runs the whole solve."""
+    """The same family at 128 x 128 x 64 (another instance)."""
     w = W.hyperspectral(1, n=128, p=64)
     orc = Operator(w["A"])
     C = _noisy(orc, w)
@@ -163,4 +214,74 @@ def test_hyperspectral_128_restoration(ctx, gdt):
     finally:
         torch.cuda.synchronize()
         dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
+
+
+# ----------------------------------------------------------- paper-shaped runs
+
+# Sec. 4, Table 1 (nu = 1e-3): DC-GMRES(10) with 10 restart cycles, DC-GK with
+# mmax = 15, DC-LSQR with k_opt = 14.
+PAPER_256 = {"gmres": 10, "gk": 15, "lsqr": 14}
+
+
+@pytest.fixture(scope="module")
+def paper256(ctx):
+    w = W.paper_shaped(256, 1e-3)
+    orc = Operator(w["A"], w["B"])
+    C = _noisy(orc, w)
+    refs = {
+        "gmres": krylov.dc_gmres(orc, C, np.zeros_like(C), 10, PAPER_256["gmres"], lam=None)["X"],
+        "gk": krylov.dc_gk(orc, C, PAPER_256["gk"], lam=None)["X"],
+        "lsqr": krylov.dc_lsqr(orc, C, PAPER_256["lsqr"])["X"],
+    }
+    errs = {k: metrics.relative_error(w["X_true"], v) for k, v in refs.items()}
+    say("paper 256 oracle relerr", errs)
+    return w, orc, C, refs, errs
+
+
+@pytest.mark.parametrize("gdt", [dk.DCTK_F64, dk.DCTK_F32])
+@pytest.mark.parametrize("meth", ["gmres", "gk", "lsqr"])
+def test_paper_shaped_256_solves(ctx, paper256, gdt, meth):
+    w, orc, C, refs, errs = paper256
+    p, n, s = w["X_true"].shape
+    vt = F64 if gdt == dk.DCTK_F64 else F32
+    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, to_gpu(w["A"], F64), s, to_gpu(w["B"], F64))
+    its = PAPER_256[meth]
+    ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_ARNOLDI if meth == "gmres" else dk.DCTK_KRYLOV_GKB,
+                               10 if meth == "gmres" else its)
+    try:
+        X = torch.zeros((p, n, s), dtype=vt, device="cuda:0")
+        if meth == "gmres":
+            info = dk.dctk_gmres_tik_solve(ctx, ws, to_gpu(C, vt), X, its, dk.make_opts(10, 0, 0, -1.0))
+        else:
+            info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, vt), X,
+                                          dk.make_opts(its, 0, 0, -1.0 if meth == "gk" else 0.0))
+        Xg = to_np(X)
+        e = metrics.relative_error(w["X_true"], Xg)
+        say("paper256", meth, gdt, "relerr", e, "oracle", errs[meth], "X gap", rel(Xg, refs[meth]),
+            "lambda", info.lam)
+        assert e <= 1.05 * errs[meth]
+        if gdt == dk.DCTK_F64:
+            # These short runs are stable: a 1e-15 change of C moves the oracle's X by
+            # <= 3e-10.  With lambda = 0 the FP64 iterate is the oracle's; with GCV the
+            # two minimisers agree to ~1e-5 in lambda (the GCV minimum is flat) and X
+            # moves by 3.9e-3 times the relative change of lambda.
+            assert rel(Xg, refs[meth]) <= (1e-8 if meth == "lsqr" else 1e-6)
+    finally:
+        torch.cuda.synchronize()
+        dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
+
+
+@pytest.mark.parametrize("gdt", [dk.DCTK_F64, dk.DCTK_F32])
+def test_paper_shaped_1024_product_and_adjoint(ctx, gdt):
+    w = W.paper_shaped(1024, 1e-3)
+    orc = Operator(w["A"], w["B"])
+    s = w["X_true"].shape[2]
+    op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, to_gpu(w["A"], F64), s, to_gpu(w["B"], F64))
+    try:
+        Y = np.random.default_rng(37).standard_normal(w["X_true"].shape)
+        _check_products(ctx, op, gdt, w, orc, w["X_true"], Y, "paper1024")
+    finally:
+        torch.cuda.synchronize()
         dk.dctk_op_destroy(op)

@@ -47,3 +47,17 @@ def test_paper_shaped_structure():
     w2 = W.paper_shaped(64, 1e-3)
     assert np.array_equal(w["X_true"], w2["X_true"]) and np.array_equal(w["N0"], w2["N0"])
 
+
+
+def test_hyperspectral_band_weights():
+    """The hyperspectral-like operator: slice k is w_k T_{sigma_k} with sigma_k
+    linear from 1.5 to 4 and w_k decaying geometrically from 1 to 0.005, so the
+    last band still carries 0.5 % of the first band's weight."""
+    p, n = 64, 40
+    A = W.band_blur(p, n, last_weight=W.HYPER_LAST_WEIGHT)
+    for k in (0, 1, 31, 63):
+        sk = 1.5 + 2.5 * k / 63.0
+        T = W.gaussian_toeplitz(n, sk, int(math.ceil(2.5 * sk)))
+        assert np.allclose(A[k], 0.005 ** (k / 63.0) * T, rtol=1e-14, atol=0.0)
+    ratios = [np.abs(A[k + 1]).max() / np.abs(A[k]).max() for k in range(p - 1)]
+    assert 0.85 < min(ratios) and max(ratios) < 0.95

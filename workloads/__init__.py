@@ -190,14 +190,28 @@ def tiny_random(seed, p, n1, n2, s, two_sided=False):
     return {"A": A, "B": B, "X": X, "Y": Y}
 
 
-def band_blur(p, n, sig_lo=1.5, sig_hi=4.0):
-    """Hyperspectral-like operator: frontal slice k is 2^-(k+1) T_{sigma_k, ceil(2.5 sigma_k)}
-    with sigma_k spanning [sig_lo, sig_hi] linearly over the p bands."""
+def band_blur(p, n, sig_lo=1.5, sig_hi=4.0, last_weight=None):
+    """Hyperspectral-like operator: frontal slice k is w_k T_{sigma_k, ceil(2.5 sigma_k)}
+    with sigma_k spanning [sig_lo, sig_hi] linearly over the p bands.
+
+    last_weight=None: w_k = 2^-(k+1) (the first few bands carry the operator).
+    last_weight=c: w_k = c^(k/(p-1)), a geometric decay from 1 at the first band
+    to c at the last (c = 0.005 at p = 64 is a factor 0.919 per band), so every
+    band's sigma enters every transform-domain slice.  With all blurs equal the
+    tube transform of such a decay stays positive while (1-r)/(1+r) > r^p for the
+    ratio r, which holds for c = 0.005 at every p >= 2."""
     A = np.zeros((p, n, n))
     for k in range(p):
         sk = sig_lo + (sig_hi - sig_lo) * (k / max(1, p - 1))
-        A[k] = 2.0 ** -(k + 1) * gaussian_toeplitz(n, sk, int(math.ceil(2.5 * sk)))
+        if last_weight is None:
+            wk = 2.0 ** -(k + 1)
+        else:
+            wk = float(last_weight) ** (k / max(1, p - 1))
+        A[k] = wk * gaussian_toeplitz(n, sk, int(math.ceil(2.5 * sk)))
     return A
+
+
+HYPER_LAST_WEIGHT = 0.005
 
 
 def spectral_field(rng, p, n, s, count=8):
@@ -218,9 +232,10 @@ def spectral_field(rng, p, n, s, count=8):
 
 def hyperspectral(instance=0, n=512, p=64, seed_base=5000):
     """The hyperspectral-like workload: n1 = n2 = s = n, n3 = p, band-dependent blur
-    sigma from 1.5 to 4, spectral Gaussian field, noise nu ~ logU[1e-3, 2e-2]."""
+    sigma from 1.5 to 4 with slice weights decaying geometrically to 0.005 at the
+    last band, spectral Gaussian field, noise nu ~ logU[1e-3, 2e-2]."""
     rng = np.random.default_rng(seed_base + instance)
-    A = band_blur(p, n)
+    A = band_blur(p, n, last_weight=HYPER_LAST_WEIGHT)
     X = spectral_field(rng, p, n, n)
     N0 = rng.standard_normal((p, n, n))
     nu = float(10.0 ** rng.uniform(-3.0, math.log10(2e-2)))
