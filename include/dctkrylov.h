@@ -150,6 +150,26 @@ int dctk_tube_inv(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p
 int dctk_tube_fast(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, int64_t count, const void* in,
                    void* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the transform of
+ * dctk_tube_fwd / dctk_tube_inv without allocating.  out = in x_3 G with
+ * G = matrix `which` (DCTK_MAT_L, _LINV, _LINVT, _LT) of `tube`; layout, dtype
+ * and overlap rules as dctk_tube_fwd.  Where dctk_tube_fwd copies G into a
+ * device buffer allocated and freed per call (and synchronises), this call
+ * builds G on the device into a fixed staging array of the library
+ * (64 x 64 FP64 = 32 KB per GPU, held until the process ends) and only
+ * enqueues: no hipMalloc, hipFree or host synchronisation.  p <= 64 uses the
+ * staging array; a power-of-two p up to 4096 (DCTK_F32) or 2048 (DCTK_F64)
+ * goes to dctk_tube_fast, which stages nothing; any other p gives
+ * DCTK_ESHAPE.  All calls on one GPU share the staging array: calls that
+ * overlap on one GPU (other streams, other contexts or host threads) race and
+ * must be ordered by the caller.  The result equals dctk_tube_fwd /
+ * dctk_tube_inv's to rounding (the device builds G from the same closed
+ * forms).  Errors: DCTK_EINVAL, DCTK_EDTYPE, DCTK_ESHAPE, DCTK_ESTATE (while a
+ * batch plan is being recorded), DCTK_EHIP. */
+int dctk_tube_apply_noalloc(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, int64_t count,
+                            const void* in, void* out);
+
 
 /* ---- operators M(X) = A *c X  or  A *c X *c B  (eq. 2) ------------------ */
 /* Creates the operator of eq. (2) from A in R^{n1 x n2 x p} (device, FP64,

@@ -74,6 +74,7 @@ _SIGS = {
     "dctk_tube_fwd": (_I, [_P, _I, _I, _I, _L, _L, _P, _P]),
     "dctk_tube_inv": (_I, [_P, _I, _I, _I, _L, _L, _P, _P]),
     "dctk_tube_fast": (_I, [_P, _I, _I, _I, _L, _L, _P, _P]),
+    "dctk_tube_apply_noalloc": (_I, [_P, _I, _I, _I, _L, _L, _P, _P]),
     "dctk_op_create": (_I, [_P, _I, _I, _L, _L, _L, _P, _L, _P, ctypes.POINTER(_P)]),
     "dctk_op_destroy": (_I, [_P]),
     "dctk_op_info": (_I, [_P, ctypes.POINTER(_L)]),
@@ -250,6 +251,11 @@ def dctk_tube_inv(ctx, tube, adjoint_pair, x, out):
 def dctk_tube_fast(ctx, tube, which, x, out):
     """O(p log p) transform by matrix `which` (DCTK_MAT_*); enqueued, no synchronisation."""
     return _tube_call(lib().dctk_tube_fast, "dctk_tube_fast", ctx, tube, which, x, out)
+
+
+def dctk_tube_apply_noalloc(ctx, tube, which, x, out):
+    """Transform by matrix `which` (DCTK_MAT_*) without allocating; enqueued only."""
+    return _tube_call(lib().dctk_tube_apply_noalloc, "dctk_tube_apply_noalloc", ctx, tube, which, x, out)
 
 
 # ---- operators ----------------------------------------------------------------------

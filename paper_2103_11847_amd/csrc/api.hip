@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -75,6 +76,69 @@ void prof_end(dctk_ctx ctx, int kind) {
   P->open = nullptr;
 }
 
+// ---- staging without allocation ----------------------------------------------
+// dctk_tube_apply_noalloc builds its p x p transform matrix in this file-scope
+// array instead of a buffer allocated per call.  Every GPU the library runs on
+// holds one copy (32 KB) until the process ends; all calls on that GPU share it.
+// Host code never passes the array's name to a kernel (on the host it only
+// stands in for the symbol): it uses the device address that
+// hipGetSymbolAddress returns, taken once per device with that device current.
+constexpr int kMaxScratchDevices = 256;
+static __device__ __align__(256) double scratch[kMaxTube * kMaxTube];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices];
+
+static hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (ptr == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+// The matrix G (row-major p x p) of one of the four transforms, built on the
+// device from the closed forms the host builder uses: C_n of eq. (dft1), and
+// for the T+H transform M = W^{-1} C_n (I + Z), M^{-1} = (I + Z)^{-1} C_n^T W
+// (Remark 2.1); the plain DCT's inverse is C_n^T.  One workgroup; C_n in LDS.
+__global__ __launch_bounds__(256) void k_tube_matrix(int tube, int which, int p, int out_f64, void* out) {
+  __shared__ double C[kMaxTube * kMaxTube];
+  const int pp = p * p;
+  for (int e = threadIdx.x; e < pp; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    const double sc = sqrt((i == 0 ? 1.0 : 2.0) / (double)p);
+    C[e] = sc * cospi((double)(i * (2 * j + 1)) / (2.0 * (double)p));
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < pp; e += blockDim.x) {
+    const int r = e / p, c = e % p;
+    // G[r][c] is L[i][j] or L^{-1}[i][j] with (i, j) = (r, c) or (c, r)
+    const bool inv = which == DCTK_MAT_LINV || which == DCTK_MAT_LINVT;
+    const bool tr = which == DCTK_MAT_LINVT || which == DCTK_MAT_LT;
+    const int i = tr ? c : r, j = tr ? r : c;
+    double v;
+    if (tube == DCTK_TUBE_DCT2) {
+      v = inv ? C[j * p + i] : C[i * p + j];
+    } else if (!inv) {
+      v = (C[i * p + j] + (j > 0 ? C[i * p + j - 1] : 0.0)) / C[i * p];
+    } else {
+      double acc = 0.0, sg = 1.0;
+      for (int l = i; l < p; ++l, sg = -sg) acc += sg * C[j * p + l];
+      v = acc * C[j * p];
+    }
+    if (out_f64)
+      static_cast<double*>(out)[e] = v;
+    else
+      static_cast<float*>(out)[e] = (float)v;
+  }
+}
+
 }  // namespace dctk
 
 extern "C" {
@@ -111,7 +175,9 @@ int dctk_create(dctk_ctx* out, int device, void* hip_stream) {
   c->last_hip_error = 0;
   c->prof = nullptr;
   c->rec = nullptr;
+  c->scratch = nullptr;
   hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = scratch_address(device, &c->scratch);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->red_partials, sizeof(double) * kRedBlocks * kRedVals);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -251,6 +317,32 @@ int dctk_tube_fwd(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p
 int dctk_tube_inv(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p, int64_t count, const void* in,
                   void* out) {
   return tube_common(ctx, tube, adjoint_pair ? DCTK_MAT_LT : DCTK_MAT_LINV, dtype, p, count, in, out);
+}
+
+int dctk_tube_apply_noalloc(dctk_ctx ctx, int tube, int which, int dtype, int64_t p, int64_t count, const void* in,
+                            void* out) {
+  if (!ctx || !in || !out) return DCTK_EINVAL;
+  if (tube != DCTK_TUBE_TH && tube != DCTK_TUBE_DCT2) return DCTK_EINVAL;
+  if (which < DCTK_MAT_L || which > DCTK_MAT_LT) return DCTK_EINVAL;
+  if (dtype != DCTK_F64 && dtype != DCTK_F32) return DCTK_EDTYPE;
+  // long tubes: the O(p log p) transform, which uses no staging memory
+  if (p > kMaxTube && tube_fast_shape_ok(dtype, p)) return tube_fast_impl(ctx, tube, which, dtype, p, count, in, out);
+  if (p <= 0 || count <= 0 || p > kMaxTube) return DCTK_ESHAPE;
+  const size_t bytes = (size_t)(p * count) * (dtype == DCTK_F64 ? 8 : 4);
+  if (ranges_overlap(in, bytes, out, bytes)) return DCTK_EINVAL;
+  if (ctx->rec) return DCTK_ESTATE;
+  if (!ctx->scratch) return DCTK_ESTATE;
+  DCTK_HIP(ctx, hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_tube_matrix, dim3(1), dim3(256), 0, ctx->stream, tube, which, (int)p,
+                     dtype == DCTK_F64 ? 1 : 0, ctx->scratch);
+  DCTK_HIP(ctx, hipGetLastError());
+  Ctl plain{};
+  plain.kind = CTL_PLAIN;
+  plain.a = 1.0;
+  plain.s = 1.0;
+  DCTK_HIP(ctx, launch_tube(ctx, ctx->stream, dtype, dtype, p, count, in, out, (const double*)ctx->scratch,
+                            (const float*)ctx->scratch, nullptr, nullptr, plain, false, true, nullptr));
+  return DCTK_OK;
 }
 
 // ---- operators -------------------------------------------------------------------

@@ -575,6 +575,7 @@ struct dctk_ctx_s {
   double* red_partials;   // kRedBlocks * kRedVals doubles: partials of standalone reductions
   void* prof;             // dctk::Profiler while profiling, else null
   void* rec;              // dctk::Recorder while a batch schedule is being planned, else null
+  void* scratch;          // this device's copy of the no-allocation staging array (device address)
 };
 
 struct dctk_op_s {
