@@ -920,6 +920,15 @@ def bench_hyper(args):
         mixed = {"solves_per_s": 1e3 / ms_b, "ms_per_step": ms_b, "relerr_gpu": err_b, "lambda": info_b.lam,
                  "per_kind": kb}
 
+    if args.copy_calib_mib > 0:
+        # plain device copies of known size, for scaling the HBM counters of a profiled run
+        cal = torch.ones(args.copy_calib_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        cal_out = torch.empty_like(cal)
+        for _ in range(3):
+            cal_out.copy_(cal)
+        torch.cuda.synchronize()
+        del cal, cal_out
+
     # the FP64 oracle: one full solve of the same problem (its own C), timed
     from oracle import krylov, metrics
     from oracle.cprod import Operator, fro

@@ -311,63 +311,66 @@ template <> __device__ inline float to_f32<bf16_t>(bf16_t v) { return bf16_to_fl
 // Long tubes (p >= 16): the transform out = G x in is a (p x p)(p x count)
 // contraction, so it runs on the matrix cores.  A workgroup stages G (p x p,
 // FP32, rows padded to 16) in LDS once and then walks its 64-position tiles
-// (grid stride): the tile's input (p x 64, 16-byte loads from clamped
-// addresses, issued together, scaled by the control block's s and written to
-// xnorm on the way) and the epilogue's src values are loaded before the tile
-// is multiplied; wave w computes the 16 positions of column block w for
-// every 16-row band of outputs with 16x16x4 FP32 MFMAs; the epilogue applies
-// a, b, src and accumulates the workgroup's partial sum of out^2.
-// VEC: count a multiple of 4 and 16-byte aligned in / xnorm.
+// (grid stride).  Every global access of a tile is a row of 64 consecutive
+// positions of one slice, moved as 16-byte vectors: the input (from clamped
+// addresses, all issued together, scaled by the control block's s and
+// written to xnorm on the way) and the epilogue's src are loaded before the
+// tile is multiplied; wave w computes the 16 positions of column block w for
+// every 16-row band of outputs with 16x16x4 FP32 MFMAs; the products return
+// to LDS, and the epilogue reads them back as rows, applies a, b and src,
+// stores the rows and accumulates the workgroup's partial sum of out^2.
+// Without an epilogue (fewer registers live) the control block's loads, G
+// and the first tile are in flight together, and the next tile's rows load
+// while the current one is multiplied.
+// VEC: count a multiple of 4 and 16-byte aligned in / src / xnorm / out.
+template <typename T> struct RowStore;
+template <> struct RowStore<float> {
+  __device__ static void st(float* p, const float (&v)[4]) {
+    *reinterpret_cast<f32x4*>(p) = f32x4{v[0], v[1], v[2], v[3]};
+  }
+};
+template <> struct RowStore<bf16_t> {
+  __device__ static void st(bf16_t* p, const float (&v)[4]) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const unsigned lo = (unsigned)float_to_bf16(v[0]) | ((unsigned)float_to_bf16(v[1]) << 16);
+    const unsigned hi = (unsigned)float_to_bf16(v[2]) | ((unsigned)float_to_bf16(v[3]) << 16);
+    *reinterpret_cast<u32x2*>(p) = u32x2{lo, hi};
+  }
+};
+template <> struct RowStore<f16_t> {
+  __device__ static void st(f16_t* p, const float (&v)[4]) {
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<h4*>(p) = h4{(f16_t)v[0], (f16_t)v[1], (f16_t)v[2], (f16_t)v[3]};
+  }
+};
+
 template <typename TOUT, int PM, bool SCALE, bool EPI, bool VEC>
 __device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const VBlock vb, const bool grouped) {
   typedef Mfma<float> MF;
   constexpr int NB = 64;            // positions per tile
   constexpr int LDG = PM + 4;       // G as [k][t], t contiguous (+16 bytes)
-  constexpr int LDX = NB + 16;      // input as [t][e], e contiguous (+64 bytes)
+  constexpr int LDX = NB + 4;       // input / products as [row][e], e contiguous (+16 bytes)
   constexpr int FR = PM / 16;       // row bands
-  constexpr int XU = PM * (NB / 4) / 256;  // input float4 units per thread
-  static_assert(XU * 256 == PM * (NB / 4), "tile");
+  constexpr int XU = PM * (NB / 4) / 256;  // 4-position units of a tile per thread
+  constexpr int GU = PM * PM / 256;        // G entries per thread
+  static_assert(XU * 256 == PM * (NB / 4) && GU * 256 == PM * PM, "tile");
   __shared__ __attribute__((aligned(16))) float sG[PM * LDG];
   __shared__ __attribute__((aligned(16))) float sX[PM * LDX];
   __shared__ double sh[kShCtl];
-  double a_d, b_d, s_d;
-  if (!ctl_begin(ta.ctl, a_d, b_d, s_d, sh, vb)) return;
-  if (!SCALE) s_d = 1.0;
-  if (!EPI) { a_d = 1.0; b_d = 0.0; }
-  const float a = (float)a_d, b = (float)b_d, sc = (float)s_d;
   const int p = ta.p;
   const int64_t count = ta.count;
   const float* in = (const float*)ta.in;
   TOUT* out = (TOUT*)ta.out;
   const float* G = (const float*)ta.G;
-  const TOUT* src = (const TOUT*)ta.src;
+  const float* src = (const float*)ta.src;   // FP32 outputs only (launch_tube refuses src otherwise)
   float* xnorm = (float*)ta.xnorm;
-  const bool use_src = EPI && src != nullptr && b != 0.0f;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  {
-    constexpr int GU = PM * PM / 256;  // G entries per thread, all loaded first
-    static_assert(GU * 256 == PM * PM, "G");
-    float gv[GU];
-#pragma unroll
-    for (int u = 0; u < GU; ++u) {
-      const int i = tid + u * 256, k = i / PM, t = i % PM;
-      const bool ok = k < p && t < p;
-      const float v = G[ok ? k * p + t : 0];
-      gv[u] = ok ? v : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < GU; ++u) {
-      const int i = tid + u * 256, k = i / PM, t = i % PM;
-      sG[k * LDG + t] = gv[u];
-    }
-  }
-  const int lr = lane & 15, lk = lane >> 4;
   const int64_t ntiles = (count + NB - 1) / NB;
-  double sq = 0.0;
-  for (int64_t tile = vb.x; tile < ntiles; tile += ta.gx) {
+
+  // a tile's input rows and src rows into registers (clamped addresses, selected)
+  float rv[XU][4], sv[XU][4];
+  auto load_tile = [&](int64_t tile) {
     const int64_t e0 = tile * NB;
-    // this tile's input, all loads issued before the first use
-    float rv[XU][4];
 #pragma unroll
     for (int u = 0; u < XU; ++u) {
       const int i = tid + u * 256;
@@ -380,34 +383,60 @@ __device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const 
         rv[u][1] = ok ? q.y : 0.0f;
         rv[u][2] = ok ? q.z : 0.0f;
         rv[u][3] = ok ? q.w : 0.0f;
+        if (EPI) {
+          const bool oks = ok && src != nullptr;
+          const float4 w = *reinterpret_cast<const float4*>(oks ? src + (int64_t)t * count + e : in);
+          sv[u][0] = oks ? w.x : 0.0f;
+          sv[u][1] = oks ? w.y : 0.0f;
+          sv[u][2] = oks ? w.z : 0.0f;
+          sv[u][3] = oks ? w.w : 0.0f;
+        }
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const bool ok = t < p && e + v < count;
           const float x = in[ok ? (int64_t)t * count + e + v : 0];
           rv[u][v] = ok ? x : 0.0f;
+          if (EPI) {
+            const bool oks = ok && src != nullptr;
+            const float y = (src != nullptr ? src : in)[oks ? (int64_t)t * count + e + v : 0];
+            sv[u][v] = oks ? y : 0.0f;
+          }
         }
       }
     }
-    // the epilogue's src values (independent of the product)
-    const int64_t eo = e0 + wave * 16 + lr;
-    float sv[FR][4];
+  };
+
+  // prologue: the control block's loads, G and the first tile's rows are all in
+  // flight before the first of them is used
+  const CtlLoad cl = ctl_load(ta.ctl);
+  float gv[GU];
 #pragma unroll
-    for (int f = 0; f < FR; ++f)
+  for (int u = 0; u < GU; ++u) {
+    const int i = tid + u * 256, k = i / PM, t = i % PM;
+    const bool ok = k < p && t < p;
+    const float v = G[ok ? k * p + t : 0];
+    gv[u] = ok ? v : 0.0f;
+  }
+  int64_t tile = vb.x;
+  if (!EPI && tile < ntiles) load_tile(tile);
+  double a_d, b_d, s_d;
+  if (!ctl_eval(ta.ctl, cl, a_d, b_d, s_d, sh, vb)) return;
+  if (!SCALE) s_d = 1.0;
+  if (!EPI) { a_d = 1.0; b_d = 0.0; }
+  const float a = (float)a_d, b = (float)b_d, sc = (float)s_d;
+  const bool use_src = EPI && src != nullptr && b != 0.0f;   // b = 0: src never enters
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sv[f][r] = 0.0f;
-    if (use_src) {
-#pragma unroll
-      for (int f = 0; f < FR; ++f)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = f * 16 + lk * 4 + r;
-          const bool ok = k < p && eo < count;
-          const TOUT x = src[ok ? (int64_t)k * count + eo : 0];
-          sv[f][r] = ok ? to_f32(x) : 0.0f;
-        }
-    }
-    __syncthreads();  // the previous tile's operands have been read
+  for (int u = 0; u < GU; ++u) {
+    const int i = tid + u * 256, k = i / PM, t = i % PM;
+    sG[k * LDG + t] = gv[u];
+  }
+  const int lr = lane & 15, lk = lane >> 4;
+  double sq = 0.0;
+  for (; tile < ntiles; tile += ta.gx) {
+    const int64_t e0 = tile * NB;
+    if (EPI) load_tile(tile);
+    __syncthreads();  // the previous tile's products have been read from LDS (and G is staged)
 #pragma unroll
     for (int u = 0; u < XU; ++u) {
       const int i = tid + u * 256;
@@ -419,7 +448,7 @@ __device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const 
         if (xnorm != nullptr && t < p) {
           float* xp = xnorm + (int64_t)t * count + e;
           if (VEC) {
-            if (e < count) *reinterpret_cast<float4*>(xp) = make_float4(rv[u][0], rv[u][1], rv[u][2], rv[u][3]);
+            if (e < count) RowStore<float>::st(xp, rv[u]);
           } else {
 #pragma unroll
             for (int v = 0; v < 4; ++v)
@@ -430,6 +459,9 @@ __device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const 
       *reinterpret_cast<float4*>(&sX[t * LDX + c]) = make_float4(rv[u][0], rv[u][1], rv[u][2], rv[u][3]);
     }
     __syncthreads();
+    // without an epilogue (fewer registers live) the next tile's rows load while
+    // this one is multiplied; with it they load at the top of the next tile
+    if (!EPI && tile + ta.gx < ntiles) load_tile(tile + ta.gx);
     typename MF::frag_t acc[FR];
 #pragma unroll
     for (int f = 0; f < FR; ++f)
@@ -441,19 +473,42 @@ __device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const 
 #pragma unroll
       for (int f = 0; f < FR; ++f) acc[f] = MF::mac(&sG[(f * 16 + lr) * LDG + t0 + lk], bp, acc[f]);
     }
-    if (eo < count) {
+    __syncthreads();  // every wave has read its operands from sX
+    // products back to LDS as [k][e]: lane holds rows 4 (lane / 16) + r of column lane % 16
 #pragma unroll
-      for (int f = 0; f < FR; ++f)
+    for (int f = 0; f < FR; ++f)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = f * 16 + lk * 4 + r;
-          if (k < p) {
-            float y = a * acc[f][r];
-            if (EPI) y += b * sv[f][r];
-            out[(int64_t)k * count + eo] = cvt<TOUT, float>(y);
-            if (EPI) sq += (double)y * (double)y;
+      for (int r = 0; r < 4; ++r) sX[(f * 16 + lk * 4 + r) * LDX + wave * 16 + lr] = acc[f][r];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int i = tid + u * 256;
+      const int k = i / (NB / 4), c = (i % (NB / 4)) * 4;
+      const int64_t e = e0 + c;
+      if (k >= p) continue;
+      const float4 q = *reinterpret_cast<const float4*>(&sX[k * LDX + c]);
+      float y[4] = {a * q.x, a * q.y, a * q.z, a * q.w};
+      if (EPI) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[v] += use_src ? b * sv[u][v] : 0.0f;
+      }
+      TOUT* op = out + (int64_t)k * count + e;
+      if (VEC) {
+        if (e < count) {
+          RowStore<TOUT>::st(op, y);
+          if (EPI) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sq += (double)y[v] * (double)y[v];
           }
         }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (e + v < count) {
+            op[v] = cvt<TOUT, float>(y[v]);
+            if (EPI) sq += (double)y[v] * (double)y[v];
+          }
+      }
     }
   }
   if (EPI && ta.ctl.part_out != nullptr) {
@@ -484,7 +539,8 @@ static hipError_t launch_tube_mfma(dctk_ctx ctx, hipStream_t s, int64_t p, int64
   if (blocks > cap) blocks = cap;
   if (nblocks_out) *nblocks_out = (int)blocks;
   if (epi && ctl.part_out != nullptr && blocks > kRedBlocks) return hipErrorInvalidConfiguration;
-  const bool vec = (count % 4 == 0) && (((uintptr_t)in) % 16 == 0) && (((uintptr_t)xnorm) % 16 == 0);
+  const bool vec = (count % 4 == 0) && (((uintptr_t)in) % 16 == 0) && (((uintptr_t)xnorm) % 16 == 0) &&
+                   (((uintptr_t)out) % 16 == 0) && (((uintptr_t)src) % 16 == 0);
   TubeArgs ta{};
   ta.p = (int)p;
   ta.count = count;
