@@ -16,6 +16,8 @@
 
 namespace dctk {
 
+// batches of at least this many slices are placed per XCD (slice_block)
+constexpr int kSliceXcdMin = 16;
 
 struct GemmArgs {
   int gx, gy, gz;
@@ -27,7 +29,28 @@ struct GemmArgs {
   void* C;
   int64_t ldc, sC;
   Gate g;
+  int nbatch;   // > 0: slices placed per XCD (see slice_block); the grid's z is padded to 8 ceil(nbatch / 8)
 };
+
+// XCD-aware slice placement of a plain batched launch.  Workgroups are dealt to
+// the 8 XCDs round robin in dispatch order, and each XCD has its own L2.  With
+// T = gx gy tiles per slice, dispatch slot `lin` goes to XCD lin % 8 and is
+// given tile (lin / 8) % T of slice 8 ((lin / 8) / T) + lin % 8: every tile of
+// a slice runs on one XCD, in consecutive slots, so the slice's operands are
+// fetched into one L2 instead of eight.  Padding slots (slice >= nbatch) exit.
+__device__ inline bool slice_block(const GemmArgs& ga, VBlock& vb) {
+  if (ga.nbatch <= 0) return true;
+  const int64_t T = (int64_t)ga.gx * ga.gy;
+  const int64_t lin = vb.x + (int64_t)ga.gx * (vb.y + (int64_t)ga.gy * vb.z);
+  const int64_t slot = lin >> 3;
+  const int64_t z = (slot / T) * 8 + (lin & 7);
+  if (z >= ga.nbatch) return false;
+  const int64_t t = slot % T;
+  vb.x = (int)(t % ga.gx);
+  vb.y = (int)(t / ga.gx);
+  vb.z = (int)z;
+  return true;
+}
 
 // VEC (16-bit types): operands move as 16-byte vectors of 8 elements along
 // their contiguous dimension (multiples of 8, 16-byte aligned): an operand
@@ -260,10 +283,13 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
 template <typename TI, typename TO, int BM, int BN, bool TA, bool TB, bool VEC, bool GROUPED>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
   if constexpr (!GROUPED) {
-    gemm_kernel_body<TI, TO, BM, BN, TA, TB, VEC>(ga_, hw_block(), false);
+    VBlock vb = hw_block();
+    if (!slice_block(ga_, vb)) return;
+    gemm_kernel_body<TI, TO, BM, BN, TA, TB, VEC>(ga_, vb, false);
   } else {
     VBlock vb;
     const GemmArgs g = group_args(grp, bmap, vb);
+    if (!slice_block(g, vb)) return;   // the instance's grid may be padded
     gemm_kernel_body<TI, TO, BM, BN, TA, TB, VEC>(g, vb, true);
   }
 }
@@ -413,18 +439,23 @@ __device__ __forceinline__ void gemm_mn_kernel_body(const GemmArgs& ga, const VB
 template <typename T, int BM, int BN, int BK, bool TA, bool TB, int VW, bool GROUPED>
 __global__ __launch_bounds__(256) void gemm_mn_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
   if constexpr (!GROUPED) {
-    gemm_mn_kernel_body<T, BM, BN, BK, TA, TB, VW>(ga_, hw_block(), false);
+    VBlock vb = hw_block();
+    if (!slice_block(ga_, vb)) return;
+    gemm_mn_kernel_body<T, BM, BN, BK, TA, TB, VW>(ga_, vb, false);
   } else {
     VBlock vb;
     const GemmArgs g = group_args(grp, bmap, vb);
+    if (!slice_block(g, vb)) return;   // the instance's grid may be padded
     gemm_mn_kernel_body<T, BM, BN, BK, TA, TB, VW>(g, vb, true);
   }
 }
 
 template <typename T, int BM, int BN, int BK>
-static hipError_t launch_gemm_mn(dctk_ctx ctx, hipStream_t s, const GemmArgs& ga, int ta, int tb, bool vec,
+static hipError_t launch_gemm_mn(dctk_ctx ctx, hipStream_t s, GemmArgs ga, int ta, int tb, bool vec,
                                  int batch) {
-  const dim3 grid((unsigned)((ga.N + BN - 1) / BN), (unsigned)((ga.M + BM - 1) / BM), (unsigned)batch);
+  ga.nbatch = batch >= kSliceXcdMin ? batch : 0;
+  const int gz = ga.nbatch > 0 ? (batch + 7) / 8 * 8 : batch;
+  const dim3 grid((unsigned)((ga.N + BN - 1) / BN), (unsigned)((ga.M + BM - 1) / BM), (unsigned)gz);
   constexpr int VW = 16 / (int)sizeof(T);
 #define DCTK_GMN(TA_, TB_, VW_) return launch_kernel(ctx, s, gemm_mn_kernel<T, BM, BN, BK, TA_, TB_, VW_, false>, gemm_mn_kernel<T, BM, BN, BK, TA_, TB_, VW_, true>, grid, 256, 0, ga)
 #define DCTK_GMN_V(TA_, TB_)    \
@@ -477,8 +508,10 @@ template <typename TI, typename TO, int BM, int BN>
 static hipError_t launch_gemm_tile(dctk_ctx ctx, hipStream_t s, int M, int N, int K, const void* A, int64_t lda,
                                    int64_t sA, int ta, const void* B, int64_t ldb, int64_t sB, int tb,
                                    void* C, int64_t ldc, int64_t sC, int batch, Gate g) {
-  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)batch);
   GemmArgs ga{};
+  ga.nbatch = batch >= kSliceXcdMin ? batch : 0;
+  const int gz = ga.nbatch > 0 ? (batch + 7) / 8 * 8 : batch;
+  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)gz);
   ga.M = M;
   ga.N = N;
   ga.K = K;
