@@ -183,6 +183,21 @@ int dctk_tube_apply_noalloc(dctk_ctx ctx, int tube, int which, int dtype, int64_
  * Errors: DCTK_ESHAPE (a dimension <= 0, or p > 64), DCTK_EDTYPE, DCTK_ENOMEM. */
 int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1, int64_t n2,
                    const void* A, int64_t s, const void* B, dctk_op* out);
+/* Order-N operators (the recursive extension to higher-order tensors that
+ * Sec. 1 states): A in R^{n1 x n2 x n3 x ... x nN}, X in R^{n2 x s x n3 x ...
+ * x nN}, with ntube = N - 2 tube modes of sizes tube_dims[0] = n3, ...,
+ * tube_dims[ntube-1] = nN (host array).  Storage: (nN, ..., n3, rows, cols)
+ * row-major, i.e. the order-3 layout with p = n3 * ... * nN frontal slices
+ * and flattened slice index q = k3 + n3 (k4 + n4 (...)).  The product is the
+ * order-3 Definition applied recursively over the last mode (blocks in the
+ * Toeplitz-plus-Hankel pattern, multiplied by the order-(N-1) product); it
+ * is computed by the transform of every tube mode, which on q is the single
+ * matrix L_{nN} (x) ... (x) L_{n3}, so every product path, Krylov workspace
+ * and solver of an order-3 operator applies unchanged.  1 <= ntube <= 6,
+ * product of tube_dims <= 64; ntube = 1 is dctk_op_create.
+ * Errors as dctk_op_create (DCTK_ESHAPE also for ntube out of range). */
+int dctk_op_create_nd(dctk_ctx ctx, int tube, int gemm_dtype, int ntube, const int64_t* tube_dims,
+                      int64_t n1, int64_t n2, const void* A, int64_t s, const void* B, dctk_op* out);
 int dctk_op_destroy(dctk_op op);
 
 /* Product paths.  A product (and its adjoint) runs either fused -- one

@@ -76,6 +76,7 @@ _SIGS = {
     "dctk_tube_fast": (_I, [_P, _I, _I, _I, _L, _L, _P, _P]),
     "dctk_tube_apply_noalloc": (_I, [_P, _I, _I, _I, _L, _L, _P, _P]),
     "dctk_op_create": (_I, [_P, _I, _I, _L, _L, _L, _P, _L, _P, ctypes.POINTER(_P)]),
+    "dctk_op_create_nd": (_I, [_P, _I, _I, _I, ctypes.POINTER(_L), _L, _L, _P, _L, _P, ctypes.POINTER(_P)]),
     "dctk_op_destroy": (_I, [_P]),
     "dctk_op_info": (_I, [_P, ctypes.POINTER(_L)]),
     "dctk_op_autotune": (_I, [_P, _P, _I, ctypes.POINTER(_I)]),
@@ -266,6 +267,20 @@ def dctk_op_create(ctx, tube, gemm_dtype, A, s, B=None):
     h = ctypes.c_void_p()
     _check(lib().dctk_op_create(ctx, int(tube), int(gemm_dtype), p, n1, n2, _ptr(A, torch.float64), int(s),
                                 _ptr(B, torch.float64), ctypes.byref(h)), "dctk_op_create")
+    return h
+
+
+def dctk_op_create_nd(ctx, tube, gemm_dtype, A, s, B=None):
+    """Order-N operator.  A: float64 GPU tensor shaped (nN, ..., n3, n1, n2);
+    B: optional (nN, ..., n3, s, s).  Vectors are (nN, ..., n3, rows, s), or
+    equivalently the order-3 layout with p = n3 * ... * nN slices."""
+    torch = _torch()
+    n1, n2 = A.shape[-2], A.shape[-1]
+    dims = list(reversed(A.shape[:-2]))
+    arr = (ctypes.c_int64 * len(dims))(*dims)
+    h = ctypes.c_void_p()
+    _check(lib().dctk_op_create_nd(ctx, int(tube), int(gemm_dtype), len(dims), arr, n1, n2, _ptr(A, torch.float64),
+                                   int(s), _ptr(B, torch.float64), ctypes.byref(h)), "dctk_op_create_nd")
     return h
 
 

@@ -354,14 +354,52 @@ static void op_free(dctk_op op) {
   delete op;
 }
 
-int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1, int64_t n2, const void* A,
-                   int64_t s, const void* B, dctk_op* out) {
-  if (!ctx || !A || !out) return DCTK_EINVAL;
+// The transform matrices of an operator on tensors with tube modes
+// dims[0] = n3, ..., dims[nd-1] = nN (flattened tube index q = k3 + n3 (k4 +
+// n4 (...)), mode N most significant): transforming every tube mode is one
+// product with G = G_N (x) ... (x) G_3 on q, and the four matrices of that
+// Kronecker product are the Kronecker products of each mode's four
+// (inverses and transposes factor mode by mode).  One mode: the p x p matrices.
+static void build_op_matrices(int tube, int nd, const int64_t* dims, int64_t P, std::vector<double>& Gd) {
+  const int64_t pp = P * P;
+  Gd.assign((size_t)(4 * pp), 0.0);
+  std::vector<std::vector<double>> mode((size_t)nd);
+  for (int w = 0; w < 4; ++w) {
+    for (int m = 0; m < nd; ++m) {
+      mode[m].assign((size_t)(dims[m] * dims[m]), 0.0);
+      build_tube_matrix(tube, w, dims[m], mode[m].data());
+    }
+    double* G = Gd.data() + w * pp;
+    for (int64_t r = 0; r < P; ++r)
+      for (int64_t c = 0; c < P; ++c) {
+        double v = 1.0;
+        int64_t rr = r, cc = c;
+        for (int m = 0; m < nd; ++m) {
+          const int64_t n = dims[m];
+          v *= mode[m][(size_t)((rr % n) * n + (cc % n))];
+          rr /= n;
+          cc /= n;
+        }
+        G[r * P + c] = v;
+      }
+  }
+}
+
+static int op_create_impl(dctk_ctx ctx, int tube, int gemm_dtype, int nd, const int64_t* dims, int64_t n1,
+                          int64_t n2, const void* A, int64_t s, const void* B, dctk_op* out) {
+  if (!ctx || !A || !out || !dims) return DCTK_EINVAL;
   *out = nullptr;
   if (tube != DCTK_TUBE_TH && tube != DCTK_TUBE_DCT2) return DCTK_EINVAL;
   if (gemm_dtype < DCTK_F64 || gemm_dtype > DCTK_F16) return DCTK_EDTYPE;
-  if (p <= 0 || n1 <= 0 || n2 <= 0 || s <= 0) return DCTK_ESHAPE;
-  if (n1 > (1 << 30) || n2 > (1 << 30) || s > (1 << 30) || p > kMaxTube) return DCTK_ESHAPE;
+  if (nd < 1 || nd > kMaxTubeModes) return DCTK_ESHAPE;
+  int64_t p = 1;
+  for (int m = 0; m < nd; ++m) {
+    if (dims[m] <= 0 || dims[m] > kMaxTube) return DCTK_ESHAPE;
+    p *= dims[m];
+    if (p > kMaxTube) return DCTK_ESHAPE;
+  }
+  if (n1 <= 0 || n2 <= 0 || s <= 0) return DCTK_ESHAPE;
+  if (n1 > (1 << 30) || n2 > (1 << 30) || s > (1 << 30)) return DCTK_ESHAPE;
   dctk_op op = new (std::nothrow) dctk_op_s();
   if (!op) return DCTK_ENOMEM;
   op->ctx = ctx;
@@ -378,8 +416,8 @@ int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1
   const size_t ae = gemm_dtype == DCTK_F64 ? 8 : 4;
   const int64_t nmax = n1 > n2 ? n1 : n2;
   const int64_t pp = p * p;
-  std::vector<double> Gd((size_t)(4 * pp));
-  for (int w = 0; w < 4; ++w) build_tube_matrix(tube, w, p, Gd.data() + w * pp);
+  std::vector<double> Gd;
+  build_op_matrices(tube, nd, dims, p, Gd);
   std::vector<float> Gf(Gd.size());
   for (size_t i = 0; i < Gd.size(); ++i) Gf[i] = (float)Gd[i];
   double* tmp = nullptr;
@@ -430,6 +468,16 @@ int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1
   }
   *out = op;
   return DCTK_OK;
+}
+
+int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1, int64_t n2, const void* A,
+                   int64_t s, const void* B, dctk_op* out) {
+  return op_create_impl(ctx, tube, gemm_dtype, 1, &p, n1, n2, A, s, B, out);
+}
+
+int dctk_op_create_nd(dctk_ctx ctx, int tube, int gemm_dtype, int ntube, const int64_t* tube_dims, int64_t n1,
+                      int64_t n2, const void* A, int64_t s, const void* B, dctk_op* out) {
+  return op_create_impl(ctx, tube, gemm_dtype, ntube, tube_dims, n1, n2, A, s, B, out);
 }
 
 int dctk_op_destroy(dctk_op op) {

@@ -20,6 +20,7 @@ constexpr int kRedVals = kMaxK + 2;    // max values reduced by one multi-dot ke
 constexpr int kThreads = 256;          // threads per block of streaming kernels
 constexpr int kShCtl = 2 * (kThreads / 64 + 1);  // LDS doubles of the prologue reductions (blocks <= kThreads)
 constexpr int kMaxTube = 64;           // largest n3 (the p x p transform matrix sits in LDS)
+constexpr int kMaxTubeModes = 6;       // tube modes of an order-N operator (N <= 8)
 constexpr int kFusedMaxP = 8;          // n3 up to which a c-product is one fused kernel
 constexpr double kBreakFactor = 64.0;  // breakdown: new norm <= 64 eps * running max
 

@@ -61,3 +61,17 @@ def test_hyperspectral_band_weights():
         assert np.allclose(A[k], 0.005 ** (k / 63.0) * T, rtol=1e-14, atol=0.0)
     ratios = [np.abs(A[k + 1]).max() / np.abs(A[k]).max() for k in range(p - 1)]
     assert 0.85 < min(ratios) and max(ratios) < 0.95
+
+
+def test_colour_video_structure():
+    """Order-4 colour video: A[f, c] = t_f a_c T (mode-3 colour tube, mode-4
+    temporal half-kernel), X_true in [0, 1], seeded."""
+    w = W.colour_video(0, n=32, frames=4)
+    assert w["A"].shape == (4, 3, 32, 32) and w["X_true"].shape == (4, 3, 32, 32)
+    T = W.gaussian_toeplitz(32, 2.0, 5)
+    for f, tf in enumerate((0.5, 0.25, 0.0, 0.0)):
+        for c, ac in enumerate((0.7, 0.15, 0.15)):
+            assert np.array_equal(w["A"][f, c], tf * ac * T)
+    assert w["X_true"].min() == 0.0 and w["X_true"].max() == 1.0
+    w2 = W.colour_video(0, n=32, frames=4)
+    assert np.array_equal(w["X_true"], w2["X_true"])
