@@ -305,6 +305,16 @@ typedef struct {
   double lambda;    /* regularisation parameter used (last cycle for GMRES) */
   double resnorm;   /* LSQR: |phibar_{k+1}| = ||C - M(X_LSQR)||;  GMRES: ||C - M(X)|| */
   double gcv;       /* GCV value at lambda (NaN when lambda was not chosen by GCV) */
+  /* Optional caller-owned host arrays (the library never allocates or frees
+   * them; NULL or cap <= 0: not written).  After a DC-LSQR / DC-GK solve
+   * (dctk_lsqr_tik_solve, dctk_lsqr_lcurve_solve, dctk_krylov_project, the
+   * batches) they receive the Golub-Kahan scalars of Algorithm 4,
+   * alpha[j] = alpha_{j+1} and beta[j] = beta_{j+1} for j < min(cap, iters + 1)
+   * (beta_1 = ||C||_F).  DC-GMRES leaves them untouched. */
+  double* alpha;
+  double* beta;
+  int cap;
+  int reserved;
 } dctk_solve_info;
 
 /* DC-LSQR / DC-GK (Algorithms 4, 5, 6) for min ||M(X) - C||: runs k_max
@@ -409,8 +419,10 @@ int dctk_lsqr_learned_solve(dctk_ctx ctx, dctk_krylov ws, dctk_mlp mlp, const vo
  * schedule point) is captured once into a HIP graph.  Every instance computes
  * exactly what its own dctk_lsqr_tik_solve would.
  *
- * dctk_batch_create: count in [1, DCTK_BATCH_MAX]; ws[i] distinct
- *   DCTK_KRYLOV_GKB workspaces on ctx's device; C[i] (p x n1 x s) and X[i]
+ * dctk_batch_create: count in [1, DCTK_BATCH_MAX]; ws[i] DCTK_KRYLOV_GKB
+ *   workspaces of distinct operators on ctx's device (the products of a batch
+ *   run concurrently and an operator's transform scratch is not shared);
+ *   C[i] (p x n1 x s) and X[i]
  *   (p x n2 x s) device buffers of instance i in its vector type, captured by
  *   the plan (every run reads C[i] and writes X[i]; they must outlive the
  *   batch).  opts applies to all (k_max <= each workspace's).  With mlp !=
@@ -441,6 +453,15 @@ int dctk_batch_run(dctk_ctx ctx, dctk_batch b);
 int dctk_batch_info(dctk_ctx ctx, dctk_batch b, dctk_solve_info* infos);
 int dctk_batch_stats(dctk_batch b, int* merged_launches, int* single_launches);
 int dctk_batch_destroy(dctk_batch b);
+/* One call for a batch solved once: for ops[0..count) (distinct operators on
+ * ctx's device) creates a DCTK_KRYLOV_GKB workspace of opts->k_max steps per
+ * operator, plans the batch (graph-captured merged launches, no learned
+ * stop), runs it once, fills infos[0..count) (alpha / beta as described at
+ * dctk_solve_info when the caller set them) and frees the workspaces and the
+ * plan.  C[i] / X[i] as for dctk_batch_create.  Synchronises.  Returns
+ * DCTK_OK or the first non-OK solve status; errors as dctk_batch_create. */
+int dctk_batch_lsqr_tik_solve(dctk_ctx ctx, int count, const dctk_op* ops, const void* const* C, void* const* X,
+                              const dctk_solve_opts* opts, dctk_solve_info* infos);
 
 #ifdef __cplusplus
 }

@@ -47,11 +47,24 @@ class dctk_solve_opts(ctypes.Structure):
 class dctk_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("converged", ctypes.c_int),
                 ("cycles", ctypes.c_int), ("lam", ctypes.c_double), ("resnorm", ctypes.c_double),
-                ("gcv", ctypes.c_double)]
+                ("gcv", ctypes.c_double), ("alpha", ctypes.POINTER(ctypes.c_double)),
+                ("beta", ctypes.POINTER(ctypes.c_double)), ("cap", ctypes.c_int), ("reserved", ctypes.c_int)]
 
     def as_dict(self):
         return {"iters": self.iters, "status": self.status, "converged": self.converged,
                 "cycles": self.cycles, "lambda": self.lam, "resnorm": self.resnorm, "gcv": self.gcv}
+
+
+def solve_info_with_scalars(cap):
+    """A dctk_solve_info whose alpha / beta point at host arrays of `cap` doubles
+    (returned with it: keep them alive while the info is in use)."""
+    a = (ctypes.c_double * cap)()
+    b = (ctypes.c_double * cap)()
+    info = dctk_solve_info()
+    info.alpha = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+    info.beta = ctypes.cast(b, ctypes.POINTER(ctypes.c_double))
+    info.cap = cap
+    return info, a, b
 
 
 _lib = None
@@ -116,6 +129,8 @@ _SIGS = {
     "dctk_batch_info": (_I, [_P, _P, ctypes.POINTER(dctk_solve_info)]),
     "dctk_batch_stats": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "dctk_batch_destroy": (_I, [_P]),
+    "dctk_batch_lsqr_tik_solve": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                       ctypes.POINTER(dctk_solve_opts), ctypes.POINTER(dctk_solve_info)]),
 }
 EXPORTED = tuple(sorted(_SIGS))
 
@@ -371,7 +386,12 @@ def make_opts(k_max, reorth=DCTK_REORTH_NONE, gcv_mode=0, lam=-1.0, tol=0.0, tar
 
 
 def dctk_lsqr_tik_solve(ctx, ws, C, X, opts, info=True):
-    """info=False: enqueue only (the library gets a NULL info; nothing is read back)."""
+    """info=False: enqueue only (the library gets a NULL info; nothing is read back).
+    info may also be a dctk_solve_info to fill (e.g. from solve_info_with_scalars)."""
+    if isinstance(info, dctk_solve_info):
+        _check(lib().dctk_lsqr_tik_solve(ctx, ws, _ptr(C), _ptr(X), ctypes.byref(opts), ctypes.byref(info)),
+               "dctk_lsqr_tik_solve")
+        return info
     if not info:
         _check(lib().dctk_lsqr_tik_solve(ctx, ws, _ptr(C), _ptr(X), ctypes.byref(opts), None),
                "dctk_lsqr_tik_solve")
@@ -504,6 +524,20 @@ def dctk_batch_stats(batch):
     m, s = ctypes.c_int(), ctypes.c_int()
     _check(lib().dctk_batch_stats(batch, ctypes.byref(m), ctypes.byref(s)), "dctk_batch_stats")
     return m.value, s.value
+
+
+def dctk_batch_lsqr_tik_solve(ctx, ops, C_list, X_list, opts, infos=None):
+    """One-shot batch of DC-LSQR / DC-GK solves on distinct operators; returns the infos
+    (a list of dctk_solve_info, optionally the caller's own, e.g. with alpha/beta arrays)."""
+    n = len(ops)
+    if len(C_list) != n or len(X_list) != n:
+        raise ValueError("dctk_batch_lsqr_tik_solve: ops, C and X lists differ in length")
+    arr = ctypes.c_void_p * n
+    infos_a = (dctk_solve_info * n)(*(infos if infos is not None else []))
+    _check(lib().dctk_batch_lsqr_tik_solve(ctx, n, arr(*ops), arr(*[_ptr(c) for c in C_list]),
+                                           arr(*[_ptr(x) for x in X_list]), ctypes.byref(opts), infos_a),
+           "dctk_batch_lsqr_tik_solve")
+    return list(infos_a)
 
 
 def dctk_batch_destroy(batch):

@@ -4,6 +4,7 @@
 // Everything after argument validation is enqueued on the context's stream;
 // Krylov scalars (alpha, beta, h, the LSQR rotations, lambda, y) live in a
 // device-resident state so a solve synchronises once, at the end.
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstring>
@@ -930,6 +931,17 @@ hipError_t learned_enqueue(dctk_ctx ctx, dctk_krylov ws, dctk_mlp m, const void*
                         &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0});
 }
 
+// alpha_1.. and beta_1.. of the recorded process into the caller's host arrays
+// (info->alpha / beta, at most info->cap entries, steps + 1 at most)
+static void copy_gk_scalars(const KState& hk, int steps, dctk_solve_info* info) {
+  if (!info || info->cap <= 0) return;
+  const int n = std::min(info->cap, std::max(0, steps) + 1);
+  for (int j = 0; j < n; ++j) {
+    if (info->alpha) info->alpha[j] = hk.alpha[j];
+    if (info->beta) info->beta[j] = hk.beta[j];
+  }
+}
+
 int lsqr_info(dctk_ctx ctx, dctk_krylov ws, const dctk_solve_opts* opts, dctk_solve_info* info) {
   static thread_local KState hk;
   int r;
@@ -944,6 +956,7 @@ int lsqr_info(dctk_ctx ctx, dctk_krylov ws, const dctk_solve_opts* opts, dctk_so
     info->lambda = tik ? hk.lambda : 0.0;
     info->resnorm = std::fabs(hk.phibar[steps]);
     info->gcv = (tik && opts->lambda < 0.0) ? hk.gcv : NAN;
+    copy_gk_scalars(hk, steps, info);
   }
   return hk.status;
 }
@@ -1129,6 +1142,7 @@ int dctk_lsqr_lcurve_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X,
     info->lambda = 0.0;
     info->resnorm = hk.resnorm;
     info->gcv = NAN;
+    copy_gk_scalars(hk, hk.steps, info);
   }
   if (k_opt) *k_opt = hk.steps > 0 ? (int)hk.sweeps : 0;
   return hk.status;
@@ -1163,6 +1177,7 @@ int dctk_krylov_project(dctk_ctx ctx, dctk_krylov ws, int k, const dctk_solve_op
     info->lambda = hk.lambda;
     info->resnorm = std::fabs(hk.phibar[info->iters < 0 ? 0 : info->iters]);
     info->gcv = opts->lambda < 0.0 ? hk.gcv : NAN;
+    copy_gk_scalars(hk, info->iters, info);
   }
   return hk.status;
 }

@@ -84,8 +84,10 @@ int dctk_batch_create(dctk_ctx ctx, int count, const dctk_krylov* ws, const void
     if (ws[i]->kind != DCTK_KRYLOV_GKB || ws[i]->op->ctx->device != ctx->device) return DCTK_EINVAL;
     int r = check_solve_opts(opts, ws[i]);
     if (r) return r;
+    // instances share no workspace and no operator (an operator's transform
+    // scratch is written by its products, which run concurrently in a batch)
     for (int k = 0; k < i; ++k)
-      if (ws[k] == ws[i]) return DCTK_EINVAL;
+      if (ws[k] == ws[i] || ws[k]->op == ws[i]->op) return DCTK_EINVAL;
   }
   DCTK_HIP(ctx, hipSetDevice(ctx->device));
 
@@ -259,6 +261,29 @@ int dctk_batch_destroy(dctk_batch b) {
   (void)hipStreamSynchronize(b->ctx->stream);
   batch_free(b);
   return DCTK_OK;
+}
+
+int dctk_batch_lsqr_tik_solve(dctk_ctx ctx, int count, const dctk_op* ops, const void* const* C, void* const* X,
+                              const dctk_solve_opts* opts, dctk_solve_info* infos) {
+  if (!ctx || !ops || !C || !X || !opts || !infos) return DCTK_EINVAL;
+  if (count < 1 || count > DCTK_BATCH_MAX) return DCTK_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    if (!ops[i]) return DCTK_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (ops[k] == ops[i]) return DCTK_EINVAL;
+  }
+  std::vector<dctk_krylov> ws((size_t)count, nullptr);
+  int r = DCTK_OK;
+  for (int i = 0; i < count && r == DCTK_OK; ++i)
+    r = dctk_krylov_create(ctx, ops[i], DCTK_KRYLOV_GKB, opts->k_max, DCTK_ORTHO_MGS, &ws[(size_t)i]);
+  dctk_batch b = nullptr;
+  if (r == DCTK_OK) r = dctk_batch_create(ctx, count, ws.data(), C, X, opts, nullptr, 1.0, 1, &b);
+  if (r == DCTK_OK) r = dctk_batch_run(ctx, b);
+  if (r == DCTK_OK) r = dctk_batch_info(ctx, b, infos);
+  if (b) (void)dctk_batch_destroy(b);
+  for (dctk_krylov w : ws)
+    if (w) (void)dctk_krylov_destroy(w);
+  return r;
 }
 
 }  // extern "C"

@@ -227,3 +227,38 @@ def test_uneven_batch_of_64_restoration(ctx):
         for it in insts:
             dk.dctk_krylov_destroy(it["ws"])
             dk.dctk_op_destroy(it["op"])
+
+
+def test_one_shot_batch_and_scalar_arrays(ctx):
+    """dctk_batch_lsqr_tik_solve (workspaces, plan, run, info and clean-up in one
+    call) gives the single solves' iterates bit for bit, and fills the caller's
+    alpha / beta arrays with the Golub-Kahan scalars the workspace recorded."""
+    k = 12
+    shapes = SHAPES[:5]
+    insts = [Inst(ctx, sd, p, n1, n2, s, g, k, ts) for (sd, p, n1, n2, s, g, ts) in shapes]
+    try:
+        opts = dk.make_opts(k, 0, 0, -1.0)
+        refs, ref_scalars = [], []
+        for it in insts:
+            info, a, b = dk.solve_info_with_scalars(k + 1)
+            dk.dctk_lsqr_tik_solve(ctx, it.ws, it.C, it.X, opts, info)
+            kr = dk.dctk_krylov_read(ctx, it.ws, k, dk.DCTK_KRYLOV_GKB)
+            assert list(a) == kr["alpha"][:k + 1] and list(b) == kr["beta"][:k + 1]
+            assert b[0] == pytest.approx(float(torch.linalg.norm(it.C.double())), rel=1e-6)
+            refs.append(it.X.clone())
+            ref_scalars.append((list(a), list(b)))
+        outs = [torch.full_like(it.X, float("nan")) for it in insts]
+        bufs = [dk.solve_info_with_scalars(k + 1) for _ in insts]
+        infos = dk.dctk_batch_lsqr_tik_solve(ctx, [it.op for it in insts], [it.C for it in insts], outs, opts,
+                                             [bf[0] for bf in bufs])
+        for it, out, ref, info, (_, a, b), (ra, rb) in zip(insts, outs, refs, infos, bufs, ref_scalars):
+            assert torch.equal(out, ref)
+            assert info.iters == k
+            assert list(a) == ra and list(b) == rb
+        # distinct operators only
+        with pytest.raises(dk.DctkError):
+            dk.dctk_batch_lsqr_tik_solve(ctx, [insts[0].op, insts[0].op], [insts[0].C] * 2, outs[:2], opts)
+    finally:
+        torch.cuda.synchronize()
+        for it in insts:
+            it.free()
