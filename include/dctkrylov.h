@@ -143,7 +143,12 @@ int dctk_tube_inv(dctk_ctx ctx, int tube, int adjoint_pair, int dtype, int64_t p
  * has run the work.  Rounding: FP32 results agree with the dense transform
  * to a relative 1e-6 (p = 256) to 4e-6 (p = 1024) in the 2-norm; the row
  * scaling D^{-1} (up to 2p / pi) amplifies the FFT's rounding by up to that
- * factor for the last rows of M and M^{-T}.
+ * factor for the last rows of M and M^{-T}.  Blocks of E / p >= 2 tubes
+ * (E = 4096 FP32, 2048 FP64) share complex FFTs in pairs: position e of a
+ * block is the real part, e + E / (2p) the imaginary part, so a tube's error
+ * is bounded relative to the norm of the pair's outputs (within 4x the
+ * whole-array figures above), not its own: a tube next to a partner 1e4
+ * times larger gets ~1e4 times its own relative error.
  * Errors: DCTK_EINVAL (NULL, bad tube/which, in and out overlap),
  * DCTK_EDTYPE, DCTK_ESHAPE (p not allowed, count <= 0), DCTK_ESTATE (while a
  * batch plan is being recorded), DCTK_EHIP. */

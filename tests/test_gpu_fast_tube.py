@@ -141,3 +141,52 @@ def test_fast_tube_longest_properties(ctx, tb):
             row = np.sqrt((1.0 if k == 0 else 2.0) / p) * np.cos(np.pi * k * (2 * tt + 1) / (2.0 * p))
         ref = row @ x
         assert np.linalg.norm(Lx[k] - ref) <= t * np.linalg.norm(Lx), k
+
+
+@pytest.mark.parametrize("p,count", [(256, 512 * 512), (512, 65536)])
+def test_fast_tube_resident_loop_matches_oracle(ctx, p, count):
+    """Many more groups of tube blocks than resident workgroups (2 per CU), so
+    every workgroup walks the grid stride with the next block prefetched:
+    512 x 512 positions at p = 256 (16384 blocks in 8192 groups) and 65536
+    positions at p = 512 (8192 blocks in 2048 groups), element-wise."""
+    say("fast tube resident loop", p, count)
+    x = np.random.default_rng(p + 3).standard_normal((p, count))
+    G = family(p, "th")
+    for which in (dk.DCTK_MAT_L, dk.DCTK_MAT_LINV):
+        got = run(ctx, "th", which, x, dk.DCTK_F32)
+        ref = G[which] @ x
+        err = rel(got, ref)
+        say("  which", which, "rel", err)
+        assert err <= tol(dk.DCTK_F32, p)
+        # no position is skipped or written twice: every column within its own bound
+        col = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        assert np.max(col) <= 50 * tol(dk.DCTK_F32, p)
+
+
+@pytest.mark.parametrize("p", [64, 256])
+def test_fast_tube_paired_tubes_error_bound(ctx, p):
+    """Two tubes share one complex FFT (tube j of a block of nb = E / p tubes is
+    the real part, tube j + nb / 2 the imaginary part), so a tube's rounding
+    error scales with the pair's norm, not its own: the bound the header
+    states is 4x the whole-array tolerance (a maximum over tubes rather than
+    an average) relative to the norm of the pair's outputs.  With every
+    partner 1e4 times larger that bound holds per tube, and the small tubes'
+    own relative error (~1e-2 here) shows the coupling."""
+    nb = E[dk.DCTK_F32] // p
+    count = 8 * nb
+    rng = np.random.default_rng(p)
+    x = rng.standard_normal((p, count))
+    big = (np.arange(count) % nb) >= nb // 2
+    x[:, big] *= 1e4
+    G = family(p, "th")
+    for which in WHICH:
+        got = run(ctx, "th", which, x, dk.DCTK_F32)
+        ref = G[which] @ x
+        err = np.linalg.norm(got - ref, axis=0)
+        nrm = np.linalg.norm(ref, axis=0)
+        partner = np.arange(count) ^ (nb // 2)
+        pair_rel = err / (nrm + nrm[partner])
+        own_rel = err / nrm
+        say("fast tube pairs", p, which, "max pair-relative", pair_rel.max(),
+            "max own relative (small tubes)", own_rel[~big].max())
+        assert pair_rel.max() <= 4 * tol(dk.DCTK_F32, p)
