@@ -104,11 +104,23 @@ def parse():
                     help="colour256: lambda by GCV (default), by the discrepancy principle at 1.05 x the "
                          "norm of the added noise, or LSQR stopped at the L-curve corner")
     ap.add_argument("--workload", default="hyper512",
-                    choices=["hyper512", "colour256", "batch64", "video256", "paper", "longtube"],
+                    choices=["hyper512", "colour256", "batch64", "video256", "paper", "longtube", "learned512"],
                     help="hyper512: one 512x512x64 solve per step (default); colour256: one 256x256x3 "
                          "solve per step; batch64: the uneven 64-instance batch per step (merged launches, "
                          "HIP graph)")
     ap.add_argument("--no-mixed", action="store_true", help="hyper512: skip the BF16-GEMM leg")
+    ap.add_argument("--stop-quantile", type=float, default=0.97,
+                    help="learned stop: margin added to the predicted step, the quantile of (label - prediction) "
+                         "over the training problems")
+    ap.add_argument("--mixed-min-n", type=int, default=128,
+                    help="batch64 with 16-bit GEMMs: instances with n below this keep FP32 slice GEMMs")
+    ap.add_argument("--lambda-gate", type=float, default=1.0,
+                    help="learned stop: the predicted lambda is kept when GCV(prediction) <= this x min GCV at the "
+                         "predicted step (1.0: the GCV minimiser unless the prediction is as good)")
+    ap.add_argument("--train-count", type=int, default=20000,
+                    help="learned512: training problems (128x128x64, same family) for the stopping network")
+    ap.add_argument("--eval-count", type=int, default=8,
+                    help="learned512: 512x512x64 problems solved (each gated on its own FP64 oracle solve)")
     a = ap.parse_args()
     if a.steps is None:
         a.steps = 20 if a.workload == "hyper512" else 50
@@ -178,6 +190,8 @@ def main():
         return bench_batch(args)
     if args.workload == "hyper512":
         return bench_hyper(args)
+    if args.workload == "learned512":
+        return bench_learned512(args)
     if args.workload == "video256":
         return bench_large(args)
     if args.workload == "paper":
@@ -599,7 +613,8 @@ def bench_longtube(args):
 
 
 def oracle_batch_leg(insts, k, budget_s):
-    """FP64 oracle on the smallest instances of the batch: restoration errors and solves/s."""
+    """FP64 oracle on the batch's instances, smallest first, until budget_s is spent
+    (None: every instance): restoration errors and the time taken."""
     from oracle import krylov, metrics
     from oracle.cprod import Operator, fro
     order = sorted(range(len(insts)), key=lambda i: insts[i]["w"]["A"].size * insts[i]["w"]["X_true"].shape[2])
@@ -612,7 +627,9 @@ def oracle_batch_leg(insts, k, budget_s):
         r = krylov.dc_gk(op, C, k, lam=None, gcv_mode="rect", reorth="none")
         errs[i] = metrics.relative_error(w["X_true"], r["X"])
         n += 1
-        if time.perf_counter() - t0 >= budget_s:
+        if n % 8 == 0:
+            print("oracle: %d solves done (%.0f s)" % (n, time.perf_counter() - t0), file=sys.stderr, flush=True)
+        if budget_s is not None and time.perf_counter() - t0 >= budget_s:
             break
     return errs, n, time.perf_counter() - t0
 
@@ -640,9 +657,12 @@ def bench_batch(args):
         dk.dctk_op_destroy(op64)
         N0 = torch.from_numpy(w["N0"]).to(dev)
         C = (Ch + w["nu"] * torch.linalg.norm(Ch) / torch.linalg.norm(N0) * N0).to(torch.float32).contiguous()
-        op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, A64, n)
+        # 16-bit slice GEMMs only where the products are bandwidth-bound (n >= --mixed-min-n);
+        # smaller, latency-bound instances gain nothing from them and keep FP32
+        gdt_i = gdt if (gdt == dk.DCTK_F32 or n >= args.mixed_min_n) else dk.DCTK_F32
+        op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt_i, A64, n)
         if not args.no_autotune:
-            key = (p, n)
+            key = (p, n, gdt_i)
             if key not in tuned:
                 tuned[key] = dk.dctk_op_autotune(ctx, op, 5)
             t = tuned[key]
@@ -661,7 +681,7 @@ def bench_batch(args):
     # a loop of single solves of the same form (learned or not)
     def single(it):
         if mlp is not None:
-            dk.dctk_lsqr_learned_solve(ctx, it["ws"], mlp, it["C"], it["X"], opts, 1.05)
+            dk.dctk_lsqr_learned_solve(ctx, it["ws"], mlp, it["C"], it["X"], opts, args.lambda_gate)
         else:
             dk.dctk_lsqr_tik_solve(ctx, it["ws"], it["C"], it["X"], opts)
     for it in insts:
@@ -677,7 +697,7 @@ def bench_batch(args):
     loop_s = (time.perf_counter() - t0) / loop_steps
     # the batch: merged launches captured in a graph
     b = dk.dctk_batch_create(ctx, [it["ws"] for it in insts], [it["C"] for it in insts],
-                             [it["X"] for it in insts], opts, True, mlp=mlp, gate=1.05)
+                             [it["X"] for it in insts], opts, True, mlp=mlp, gate=args.lambda_gate)
     merged, single = dk.dctk_batch_stats(b)
     for _ in range(args.warmup):
         dk.dctk_batch_run(ctx, b)
@@ -695,17 +715,18 @@ def bench_batch(args):
         Xn = it["X"].double().cpu().numpy()
         Xt = it["w"]["X_true"]
         errs.append(float(np.linalg.norm((Xn - Xt).ravel()) / np.linalg.norm(Xt.ravel())))
-    cpu, gate_ok, worst = None, same, None
+    # every instance is gated on its own full FP64 oracle solve (also without the
+    # baseline report); only the instances that pass count in `value`
+    oerr, nsolve, dt = oracle_batch_leg(insts, k, None)
+    oratios = [errs[i] / oerr[i] for i in range(len(insts))]
+    worst = max(oratios)
+    passed = [r <= 1.05 for r in oratios]
+    cpu = None
     if not args.no_cpu_baseline:
-        oerr, nsolve, dt = oracle_batch_leg(insts, k, args.cpu_seconds)
-        ratios = [errs[i] / e for i, e in oerr.items()]
-        worst = max(ratios)
-        gate_ok = gate_ok and worst <= 1.05
-        elems = sum(insts[i]["w"]["X_true"].size for i in oerr)
+        elems = sum(it["w"]["X_true"].size for it in insts)
         cpu = {"value": nsolve / dt, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
-               "sample": "%d FP64 DC-GK solves (40 GKB steps + GCV) of the smallest batch instances "
-                         "(%d tensor elements in all) in %.1f s; the batch's instances average %.0f elements"
-                         % (nsolve, elems, dt, sum(it["w"]["X_true"].size for it in insts) / len(insts))}
+               "sample": "all %d FP64 DC-GK solves (40 GKB steps + GCV) of the batch's instances (%d tensor "
+                         "elements in all) in %.1f s" % (nsolve, elems, dt)}
     dk.dctk_batch_destroy(b)
     for it in insts:
         dk.dctk_krylov_destroy(it["ws"])
@@ -720,11 +741,11 @@ def bench_batch(args):
                                                  "max": float(ratios.max()),
                                                  "frac_within_1_05": float(np.mean(ratios <= 1.05))},
                   "mean_steps": float(np.mean(k_used)), "network": learned_info}
-        gate_ok = gate_ok and float(np.median(ratios)) <= 1.05
     if mlp is not None:
         dk.dctk_mlp_destroy(mlp)
     dk.dctk_destroy(ctx)
-    value = (64.0 / batch_s) if gate_ok else 0.0
+    # the batch must reproduce its single solves; then the gated instances count
+    value = (sum(passed) / batch_s) if same else 0.0
     peak = MFMA_PEAK_TFLOPS[args.gemm]
     sizes = collections_count([(it["w"]["A"].shape[1], it["w"]["A"].shape[0]) for it in insts])
     line = {
@@ -735,14 +756,16 @@ def bench_batch(args):
                                "+ FP64 GCV each), one batch per step, merged launches in a HIP graph"
                                % ("learned stop after 8 of up to 40 GKB steps" if args.learned else "40 GKB steps"),
                    "instances": 64, "gkb_steps": k, "gemm_dtype": args.gemm, "sizes_n_n3": sizes,
-                   "autotuned_paths": {"%dx%d" % (kk[1], kk[0]): v for kk, v in tuned.items()}},
+                   "mixed_min_n": args.mixed_min_n,
+                   "autotuned_paths": {"%dx%d/%d" % (kk[1], kk[0], kk[2]): v for kk, v in tuned.items()}},
         "roofline": {"bound": "mfma", "achieved": flops / batch_s / 1e12, "peak": peak, "unit": "TFLOP/s",
                      "frac": flops / batch_s / 1e12 / peak, "traffic": None,
                      "kernel": "whole batch step (slice-GEMM flops of all 81 products per instance)"},
         "cpu_baseline": cpu,
         "batch": {"loop_of_single_solves_per_s": 64.0 / loop_s, "speedup_vs_loop": loop_s / batch_s,
                   "launches_merged": merged, "launches_single": single, "bitwise_equal_to_single": same,
-                  "worst_relerr_ratio_vs_oracle": worst, "median_relerr": float(np.median(errs)),
+                  "worst_relerr_ratio_vs_oracle": worst, "instances_passing_1_05": int(sum(passed)),
+                  "relerr_ratio_vs_oracle": oratios, "median_relerr": float(np.median(errs)),
                   "lambda_range": [min(x.lam for x in infos), max(x.lam for x in infos)]},
         "target_form": target,
     }
@@ -750,13 +773,15 @@ def bench_batch(args):
 
 
 def train_stop_network(ctx, args):
-    """The stopping network, trained on the library's own FP32 solves of 256 smaller
+    """The stopping network, trained on the library's own FP32 solves of 1024 smaller
     problems of the batch's family (labels from their restoration errors)."""
     import paper_2103_11847_amd as dk
     from paper_2103_11847_amd import learned_stop as ls
     import workloads as W
     t0 = time.perf_counter()
-    data = ls.make_dataset(ctx, [W.batch_train_instance(i) for i in range(256)])
+    data = ls.make_dataset(ctx, (W.batch_train_instance(i) for i in range(1024)),
+                           progress=lambda i: print("batch64: labelled %d training problems (%.0f s)"
+                                                    % (i, time.perf_counter() - t0), file=sys.stderr, flush=True))
     t_data = time.perf_counter() - t0
     T, scaling = ls.targets(data)
     m = dk.dctk_mlp_create(ctx, 5)
@@ -764,7 +789,7 @@ def train_stop_network(ctx, args):
     t0 = time.perf_counter()
     curve = ls.train(ctx, m, data["F"], T, steps=2000)
     t_train = time.perf_counter() - t0
-    off = ls.calibrate_offset(ctx, m, data["F"], data["k"], scaling)
+    off = ls.calibrate_offset(ctx, m, data["F"], data["k"], scaling, quantile=args.stop_quantile)
     return m, {"train_problems": int(data["F"].shape[0]), "label_seconds": t_data, "train_seconds": t_train,
                "loss_first_last": [curve[0][1], curve[-1][1]], "stop_offset": off,
                "label_k_mean": float(data["k"].mean())}
@@ -972,6 +997,161 @@ def bench_hyper(args):
                           "note": "the kernel times come from a second pass of the same number of solves in "
                                   "which every launch records start/stop events"},
         "mixed_bf16": mixed,
+    }
+    print(json.dumps(line))
+
+
+
+def bench_learned512(args):
+    """The target form on the 512 x 512 x 64 hyperspectral workload: the
+    stopping network trained on the library's own FP32 solves of --train-count
+    problems of the same family at 128 x 128 x 64; then --eval-count 512 x 512
+    x 64 problems (own fields, noise levels) solved (a) as plain FP32 DC-GK
+    single solves (40 GKB steps + GCV) and (b) in the target form: BF16 slice
+    GEMMs, the learned stop after 8 steps with the GCV gate, all instances in
+    one batch (merged launches, HIP graph).  Every instance of both forms is
+    gated on a full FP64 oracle solve of the same problem; `value` counts only
+    the target-form solves that pass (within 1.05x of the oracle's error)."""
+    import torch
+    import paper_2103_11847_amd as dk
+    from paper_2103_11847_amd import learned_stop as ls
+    import workloads as W
+    from oracle import krylov, metrics
+    from oracle.cprod import Operator, fro
+    dev = torch.device("cuda:0")
+    k = 40
+    ctx = dk.dctk_create(0)
+    # 1. training data from the library's own solves, and training
+    t0 = time.perf_counter()
+    ntrain = args.train_count
+    def note(msg):
+        print("learned512: %s (%.0f s)" % (msg, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    data = ls.make_family_dataset(ctx, lambda i: W.hyper_family_instance(i, 128), ntrain,
+                                  W.hyper_family_operator(128), 128, k_max=k,
+                                  progress=lambda i: note("labelled %d problems" % i))
+    t_label = time.perf_counter() - t0
+    T, scaling = ls.targets(data)
+    mlp = dk.dctk_mlp_create(ctx, 21)
+    dk.dctk_mlp_set_scaling(mlp, *scaling)
+    t0 = time.perf_counter()
+    curve = ls.train(ctx, mlp, data["F"], T, steps=3000)
+    t_train = time.perf_counter() - t0
+    off = ls.calibrate_offset(ctx, mlp, data["F"], data["k"], scaling, quantile=args.stop_quantile)
+    # 2. the 512 x 512 x 64 problems
+    insts = []
+    for i in range(args.eval_count):
+        w = W.hyperspectral(i)
+        A64 = torch.from_numpy(w["A"]).to(dev)
+        op64 = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F64, A64, w["X_true"].shape[2])
+        Xt = torch.from_numpy(w["X_true"]).to(dev)
+        Ch = torch.empty_like(Xt)
+        dk.dctk_cprod(ctx, op64, 1.0, Xt, 0.0, Ch)
+        dk.dctk_op_destroy(op64)
+        N0 = torch.from_numpy(w["N0"]).to(dev)
+        C = (Ch + w["nu"] * torch.linalg.norm(Ch) / torch.linalg.norm(N0) * N0).to(torch.float32).contiguous()
+        del Ch, N0
+        insts.append({"w": w, "A64": A64, "C": C, "Xt": Xt.to(torch.float32), "nx": float(torch.linalg.norm(Xt))})
+        del Xt
+    opts = dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, -1.0, 0.0)
+    s = insts[0]["w"]["X_true"].shape[2]
+    # (a) plain FP32 single solves, one after another
+    op32 = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F32, insts[0]["A64"], s)
+    ws32 = dk.dctk_krylov_create(ctx, op32, dk.DCTK_KRYLOV_GKB, k)
+    X = torch.empty_like(insts[0]["C"])
+    dk.dctk_lsqr_tik_solve(ctx, ws32, insts[0]["C"], X, opts)
+    torch.cuda.synchronize()
+    err_plain, t_plain = [], 0.0
+    for it in insts:
+        t0 = time.perf_counter()
+        dk.dctk_lsqr_tik_solve(ctx, ws32, it["C"], X, opts)
+        t_plain += time.perf_counter() - t0
+        err_plain.append(float(torch.linalg.norm(X - it["Xt"])) / it["nx"])
+    dk.dctk_krylov_destroy(ws32)
+    dk.dctk_op_destroy(op32)
+    del X
+    # (b) the target form: BF16 GEMMs + learned stop, all instances in one batch
+    made = []
+    for it in insts:
+        op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_BF16, it["A64"], s)
+        ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k)
+        made.append((op, ws, torch.empty_like(it["C"])))
+    b = dk.dctk_batch_create(ctx, [m[1] for m in made], [it["C"] for it in insts], [m[2] for m in made], opts,
+                             True, mlp=mlp, gate=args.lambda_gate)
+    for _ in range(max(1, args.warmup)):
+        dk.dctk_batch_run(ctx, b)
+    dk.dctk_synchronize(ctx)
+    reps = max(1, min(args.steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dk.dctk_batch_run(ctx, b)
+    dk.dctk_synchronize(ctx)
+    t_batch = (time.perf_counter() - t0) / reps
+    infos = dk.dctk_batch_info(ctx, b, len(made))
+    k_lim, acc = dk.dctk_batch_learned(ctx, b, len(made))
+    err_target = [float(torch.linalg.norm(m[2] - it["Xt"])) / it["nx"] for m, it in zip(made, insts)]
+    # kernel times of the target form: one learned single solve per instance, profiled
+    dk.dctk_profile_begin(ctx)
+    for m, it in zip(made, insts):
+        dk.dctk_lsqr_learned_solve(ctx, m[1], mlp, it["C"], m[2], opts, args.lambda_gate)
+    prof = dk.dctk_profile_end(ctx)
+    dk.dctk_batch_destroy(b)
+    for op, ws, _ in made:
+        dk.dctk_krylov_destroy(ws)
+        dk.dctk_op_destroy(op)
+    dk.dctk_mlp_destroy(mlp)
+    p, n = insts[0]["w"]["X_true"].shape[:2]
+    kinds = {}
+    for kind in ("tube_fwd", "gemm", "tube_inv"):
+        tot, cnt = prof[kind]
+        if cnt:
+            f, byt = kernel_work(kind, p, n, n, s, 2)
+            kinds[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, byt, "bf16", hyper_traffic(kind, "bf16"))
+            kinds[kind].update({"launches": cnt, "ms_total": tot})
+    dom = max(kinds, key=lambda k_: kinds[k_]["ms_total"])
+    roof = dict(kinds[dom])
+    roof["per_kind"] = kinds
+    # 3. the FP64 oracle on every problem (the gate), timed
+    err_oracle, t_oracle = [], 0.0
+    for it in insts:
+        w = it["w"]
+        t0 = time.perf_counter()
+        orc = Operator(w["A"])
+        Cn = orc.apply(w["X_true"])
+        Cn = Cn + w["nu"] * fro(Cn) / fro(w["N0"]) * w["N0"]
+        ref = krylov.dc_gk(orc, Cn, k, lam=None, gcv_mode="rect", reorth="none")
+        t_oracle += time.perf_counter() - t0
+        err_oracle.append(metrics.relative_error(w["X_true"], ref["X"]))
+        del orc, Cn, ref
+        print("learned512: oracle solve %d of %d done" % (len(err_oracle), len(insts)), file=sys.stderr, flush=True)
+    ratio_t = [e / o for e, o in zip(err_target, err_oracle)]
+    ratio_p = [e / o for e, o in zip(err_plain, err_oracle)]
+    passed = [r <= 1.05 for r in ratio_t]
+    E = len(insts)
+    dk.dctk_destroy(ctx)
+    line = {
+        "metric": METRIC, "value": sum(passed) / t_batch, "unit": "solves/s", "n_gpus": 1, "steps": reps,
+        "warmup": max(1, args.warmup), "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "target form on hyperspectral-like 512x512x64 (band-dependent blur sigma 1.5-4): "
+                               "%d problems per step in one batch, BF16 slice GEMMs, learned stop after 8 of up "
+                               "to 40 GKB steps + FP64 GCV gate" % E,
+                   "n1": n, "n2": n, "s": s, "n3": p, "instances": E, "gemm_dtype": "bf16", "vector_dtype": "f32"},
+        "roofline": roof,
+        "cpu_baseline": None if args.no_cpu_baseline else {
+            "value": E / t_oracle, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+            "sample": "%d full FP64 DC-GK solves (40 GKB steps + GCV) of the evaluated 512x512x64 problems in "
+                      "%.1f s (numpy, BLAS matmul)" % (E, t_oracle)},
+        "target_form": {
+            "solves_per_s": E / t_batch, "gated_solves_per_s": sum(passed) / t_batch,
+            "plain_fp32_single_solves_per_s": E / t_plain, "speedup_vs_plain_fp32": t_plain / t_batch,
+            "relerr_ratio_vs_oracle": {"target": ratio_t, "plain_fp32": ratio_p, "max_target": max(ratio_t)},
+            "instances_passing_1_05": int(sum(passed)), "steps_used": [x.iters for x in infos],
+            "learned_step_limit": k_lim, "lambda_accepted": acc},
+        "network": {"train_problems": int(data["F"].shape[0]), "train_size": "128x128x64",
+                    "label_seconds": t_label, "train_seconds": t_train,
+                    "loss_first_last": [curve[0][1], curve[-1][1]], "stop_offset": off,
+                    "label_k_mean": float(data["k"].mean()), "label_k_range": [float(data["k"].min()),
+                                                                                float(data["k"].max())]},
     }
     print(json.dumps(line))
 

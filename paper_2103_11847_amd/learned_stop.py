@@ -70,8 +70,13 @@ def label_instance(ctx, inst, k_max=40, near=1.02, gemm=dk.DCTK_F32, dev="cuda:0
             "lambda": lams[kstar - 1], "err_kmax": float(errs[-1]), "err_best": best}
 
 
-def make_dataset(ctx, instances, k_max=40, near=1.02, gemm=dk.DCTK_F32):
-    rows = [label_instance(ctx, inst, k_max, near, gemm) for inst in instances]
+def make_dataset(ctx, instances, k_max=40, near=1.02, gemm=dk.DCTK_F32, progress=None):
+    """Labels of the given problems; progress(i) is called after every 128th."""
+    rows = []
+    for i, inst in enumerate(instances):
+        rows.append(label_instance(ctx, inst, k_max, near, gemm))
+        if progress is not None and (i + 1) % 128 == 0:
+            progress(i + 1)
     F = np.stack([r["features"] for r in rows]).astype(np.float32)
     K = np.array([r["k"] for r in rows], dtype=np.float64)
     L = np.array([r["lambda"] for r in rows], dtype=np.float64)
@@ -175,3 +180,84 @@ def summary(results):
             "frac_lambda_accepted": float(np.mean([x["accepted"] for x in results])),
             "time_plain_s": float(sum(x["t_plain"] for x in results)),
             "time_learned_s": float(sum(x["t_learned"] for x in results))}
+
+
+class SharedOperatorLabeler:
+    """Labels for a family of problems that share one operator (the
+    hyperspectral family at a fixed size): the FP64 operator (observations),
+    the solve operator and its workspace are created once."""
+
+    def __init__(self, ctx, A, s, k_max=40, gemm=dk.DCTK_F32, dev="cuda:0"):
+        torch = _torch()
+        self.ctx, self.k_max, self.dev = ctx, k_max, dev
+        A64 = torch.from_numpy(A).to(dev)
+        self.shape = A.shape
+        self.s = s
+        self.op64 = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F64, A64, s)
+        self.op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gemm, A64, s)
+        self.ws = dk.dctk_krylov_create(ctx, self.op, dk.DCTK_KRYLOV_GKB, k_max)
+        p, n1, n2 = A.shape
+        self.X = torch.empty((p, n2, s), dtype=torch.float32, device=dev)
+        self.Ch = torch.empty((p, n1, s), dtype=torch.float64, device=dev)
+        self.feat = torch.empty(16, dtype=torch.float32, device=dev)
+
+    def close(self):
+        _torch().cuda.synchronize()
+        dk.dctk_krylov_destroy(self.ws)
+        dk.dctk_op_destroy(self.op)
+        dk.dctk_op_destroy(self.op64)
+
+    def label(self, inst, near=1.02):
+        torch = _torch()
+        ctx, k_max = self.ctx, self.k_max
+        Xt64 = torch.from_numpy(inst["X_true"]).to(self.dev)
+        dk.dctk_cprod(ctx, self.op64, 1.0, Xt64, 0.0, self.Ch)
+        N0 = torch.from_numpy(inst["N0"]).to(self.dev)
+        C = (self.Ch + inst["nu"] * torch.linalg.norm(self.Ch) / torch.linalg.norm(N0) * N0).to(torch.float32)
+        C = C.contiguous()
+        Xt = Xt64.to(torch.float32)
+        opts = dk.make_opts(k_max, dk.DCTK_REORTH_NONE, 0, -1.0)
+        info = dk.dctk_lsqr_tik_solve(ctx, self.ws, C, self.X, opts)
+        dk.dctk_mlp_features(ctx, self.ws, self.feat)
+        nx = torch.linalg.norm(Xt)
+        errs = torch.empty(info.iters, dtype=torch.float64, device=self.dev)
+        lams = []
+        for k in range(1, info.iters + 1):
+            ik = dk.dctk_krylov_project(ctx, self.ws, k, opts, self.X)
+            errs[k - 1] = torch.linalg.norm(self.X - Xt) / nx
+            lams.append(ik.lam)
+        errs = errs.cpu().numpy()
+        best = float(errs.min())
+        ks = [k for k in range(K_FEAT, len(errs) + 1) if errs[k - 1] <= near * best]
+        kstar = ks[0] if ks else int(np.argmin(errs)) + 1
+        return {"features": self.feat.cpu().numpy(), "errors": errs, "lambdas": np.array(lams), "k": kstar,
+                "lambda": lams[kstar - 1], "err_kmax": float(errs[-1]), "err_best": best}
+
+
+def make_family_dataset(ctx, make_instance, count, A, s, k_max=40, near=1.02, workers=8, progress=None):
+    """Labels of `count` problems make_instance(i) sharing the operator A; the
+    host draws the next problems on `workers` threads while the GPU labels.
+    progress(i) is called after every 500th problem."""
+    from concurrent.futures import ThreadPoolExecutor
+    lab = SharedOperatorLabeler(ctx, A, s, k_max)
+    rows = []
+    try:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            futs = [ex.submit(make_instance, i) for i in range(min(count, 2 * workers))]
+            nxt = len(futs)
+            for i in range(count):
+                inst = futs[i].result()
+                futs[i] = None
+                if nxt < count:
+                    futs.append(ex.submit(make_instance, nxt))
+                    nxt += 1
+                rows.append(lab.label(inst, near))
+                if progress is not None and (i + 1) % 500 == 0:
+                    progress(i + 1)
+    finally:
+        lab.close()
+    F = np.stack([r["features"] for r in rows]).astype(np.float32)
+    K = np.array([r["k"] for r in rows], dtype=np.float64)
+    L = np.array([r["lambda"] for r in rows], dtype=np.float64)
+    ok = np.all(np.isfinite(F), axis=1) & np.isfinite(L) & (L > 0)
+    return {"F": F[ok], "k": K[ok], "lambda": L[ok], "rows": [r for r, o in zip(rows, ok) if o]}

@@ -296,3 +296,28 @@ def colour_video(instance=0, n=128, frames=16):
     N0 = rng.standard_normal((frames, 3, n, n))
     return {"name": "colour_video_%dx%dx3x%d" % (n, n, frames), "A": A, "B": None, "X_true": X, "N0": N0,
             "nu": 5e-3, "iters": 40}
+
+
+_HYPER_OPS = {}
+
+
+def hyper_family_operator(n=128, p=64):
+    """The band-dependent blur of the hyperspectral workload at size n (cached:
+    every instance of the family shares it)."""
+    key = (n, p)
+    if key not in _HYPER_OPS:
+        _HYPER_OPS[key] = band_blur(p, n, last_weight=HYPER_LAST_WEIGHT)
+    return _HYPER_OPS[key]
+
+
+def hyper_family_instance(i, n=128, p=64):
+    """Training / evaluation problem of the learned stop for the hyperspectral
+    workload: its operator (sigma 1.5 to 4, slice weights to 0.005) at size n,
+    its own spectral field and noise, nu ~ logU[1e-3, 2e-2] (seed 9000 + i;
+    A is shared by all instances of one n)."""
+    rng = np.random.default_rng(9000 + i)
+    X = spectral_field(rng, p, n, n)
+    N0 = rng.standard_normal((p, n, n))
+    nu = float(10.0 ** rng.uniform(-3.0, math.log10(2e-2)))
+    return {"name": "hyper_family_%d_%d" % (n, i), "A": hyper_family_operator(n, p), "B": None, "X_true": X,
+            "N0": N0, "nu": nu, "iters": 40}
