@@ -197,7 +197,7 @@ def trained(ctx):
     dk.dctk_mlp_set_scaling(m, *scaling)
     curve = ls.train(ctx, m, data["F"], T, steps=2000)
     say("loss curve", curve[0], curve[-1])
-    off = ls.calibrate_offset(ctx, m, data["F"], data["k"], scaling)
+    off = ls.calibrate_offset(ctx, m, data["F"], data["k"], scaling, quantile=0.97)
     say("stop offset", off)
     yield m, curve
     torch.cuda.synchronize()
@@ -205,16 +205,19 @@ def trained(ctx):
 
 
 def test_trained_network_gain(ctx, trained):
-    """Evaluated on 48 problems it was not trained on, the learned-stop solve keeps the
-    restoration error of GCV at 40 steps (within 1.05x on most problems) with fewer
+    """Evaluated on 48 problems it was not trained on, the learned-stop solve (stop
+    margin: the 97th percentile of the training labels' shortfall; lambda: the GCV
+    minimiser at the predicted step) keeps the restoration error of GCV at 40 steps
+    within 1.05x on at least 46 of the 48 problems (a stop predicted from 8 steps
+    can still come early on a few: the worst is reported), with fewer
     Golub-Kahan steps and less time."""
     net, curve = trained
     assert curve[-1][1] < 0.1 * curve[0][1]
-    res = ls.evaluate(ctx, net, [W.learned_stop_instance(1000 + i, n=64) for i in range(48)])
+    res = ls.evaluate(ctx, net, [W.learned_stop_instance(1000 + i, n=64) for i in range(48)], gate=1.0)
     summ = ls.summary(res)
     say("gain", summ)
     assert summ["median_err_ratio"] <= 1.05
-    assert summ["frac_within_1_05"] >= 0.8
+    assert summ["frac_within_1_05"] >= 46 / 48
     assert summ["mean_k_learned"] < 0.9 * summ["mean_k_plain"]
     assert summ["time_learned_s"] < summ["time_plain_s"]
 
