@@ -429,9 +429,10 @@ static int op_create_impl(dctk_ctx ctx, int tube, int gemm_dtype, int nd, const 
   DCTK_TRY(hipMemcpy(op->Gd, Gd.data(), sizeof(double) * 4 * pp, hipMemcpyHostToDevice));
   DCTK_TRY(hipMemcpy(op->Gf, Gf.data(), sizeof(float) * 4 * pp, hipMemcpyHostToDevice));
   DCTK_TRY(hipMalloc(&op->Ah, ge * (size_t)(p * n1 * n2)));
-  // 16-bit fused products read A~ with the contraction index contiguous in
-  // both directions: keep the transposed slices for the adjoint
-  if ((gemm_dtype == DCTK_BF16 || gemm_dtype == DCTK_F16) && fused_eligible(op))
+  // 16-bit products read A~ with the contraction index contiguous in both
+  // directions (16-byte rows straight into LDS): keep the transposed slices
+  // for the adjoint
+  if (gemm_dtype == DCTK_BF16 || gemm_dtype == DCTK_F16)
     DCTK_TRY(hipMalloc(&op->AhT, ge * (size_t)(p * n1 * n2)));
   if (op->two_sided) DCTK_TRY(hipMalloc(&op->Bh, ge * (size_t)(p * s * s)));
   DCTK_TRY(hipMalloc(&op->xh, ge * (size_t)(p * nmax * s)));
@@ -509,7 +510,7 @@ int dctk_op_autotune(dctk_ctx ctx, dctk_op op, int reps, int* choice) {
   c.a = 1.0;
   c.s = 1.0;
   for (int adj = 0; adj < 2 && e == hipSuccess; ++adj) {
-    int cand[6][2];
+    int cand[7][2];
     int nc = 0;
     if (fused_eligible(op)) {
       cand[nc][0] = 1; cand[nc++][1] = 16;
@@ -519,6 +520,7 @@ int dctk_op_autotune(dctk_ctx ctx, dctk_op op, int reps, int* choice) {
     cand[nc][0] = 0; cand[nc++][1] = 32;
     cand[nc][0] = 0; cand[nc++][1] = 64;
     if (op->gemm_dtype != DCTK_F64) { cand[nc][0] = 0; cand[nc++][1] = 128; }
+    if (op->gemm_dtype == DCTK_BF16 || op->gemm_dtype == DCTK_F16) { cand[nc][0] = 0; cand[nc++][1] = 256; }
     float best = 1e30f;
     int bi = -1;
     for (int i = 0; i < nc && e == hipSuccess; ++i) {
@@ -562,8 +564,9 @@ int dctk_op_autotune(dctk_ctx ctx, dctk_op op, int reps, int* choice) {
 
 int dctk_op_set_path(dctk_op op, int adjoint, int path, int tile) {
   if (!op || (adjoint != 0 && adjoint != 1) || path < -1 || path > 1) return DCTK_EINVAL;
-  if (tile != 0 && tile != 16 && tile != 32 && tile != 64 && tile != 128) return DCTK_EINVAL;
-  if (path == 1 && (!fused_eligible(op) || tile == 128)) return DCTK_EINVAL;
+  if (tile != 0 && tile != 16 && tile != 32 && tile != 64 && tile != 128 && tile != 256) return DCTK_EINVAL;
+  if (path == 1 && (!fused_eligible(op) || tile >= 128)) return DCTK_EINVAL;
+  if (tile == 256 && op->gemm_dtype != DCTK_BF16 && op->gemm_dtype != DCTK_F16) return DCTK_EINVAL;
   if (path == 0 && tile == 16) return DCTK_EINVAL;
   op->tune[adjoint][0] = path;
   op->tune[adjoint][1] = tile;

@@ -3,7 +3,8 @@
 // as batched GEMMs on the gfx950 matrix cores.
 //
 // Tile: BM x BN outputs per workgroup of 4 waves arranged 2 x 2, each wave
-// owning (BM/2) x (BN/2) as 16 x 16 MFMA blocks.  Operands are staged through
+// owning (BM/2) x (BN/2) as 16 x 16 MFMA blocks (16-bit 256 x 256 tiles: 8
+// waves in 2 x 4).  Operands are staged through
 // LDS as [rows][BK + pad] (contraction index contiguous) so each lane's MFMA
 // operand is one LDS read: 1 element for the K = 4 FP32/FP64 instructions,
 // 8 packed 16-bit elements for the K = 32 BF16/FP16 instructions of gfx950.
@@ -18,6 +19,9 @@ namespace dctk {
 
 // batches of at least this many slices are placed per XCD (slice_block)
 constexpr int kSliceXcdMin = 16;
+
+// threads of a 16-bit GEMM workgroup: 512 for 256 x 256 tiles, else 256
+__host__ __device__ constexpr int gemm_threads(int bm, int bn) { return bm * bn >= 65536 ? 512 : 256; }
 
 struct GemmArgs {
   int gx, gy, gz;
@@ -69,12 +73,15 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
   typedef typename MF::acc_t acc_t;
   typedef typename MF::frag_t frag_t;
   constexpr int KSTEP = MF::KSTEP;
-  constexpr int BK = (KSTEP == 4) ? 16 : 64;
+  // 256 x 256 tiles: 512 threads (2 x 4 waves of 128 x 64 outputs) and 32-wide
+  // contraction chunks (the two operand tiles of a chunk are 40 KB of LDS)
+  constexpr int BK = (KSTEP == 4) ? 16 : (BM >= 256 ? 32 : 64);
   constexpr int PAD = (sizeof(TI) == 2) ? 8 : (sizeof(TI) == 4 ? 4 : 2);  // 16 bytes
   constexpr int LDS_LD = BK + PAD;
-  constexpr int A_PER = BM * BK / 256;  // elements of the A tile per thread
-  constexpr int B_PER = BN * BK / 256;
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int NT = gemm_threads(BM, BN), WGM = 2, WGN = NT / 128;   // threads, wave grid
+  constexpr int A_PER = (BM * BK + NT - 1) / NT;  // elements of the A tile per thread
+  constexpr int B_PER = (BN * BK + NT - 1) / NT;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
   static_assert(A_PER >= 1 && B_PER >= 1, "tile too small");
 
@@ -93,16 +100,16 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
 
   // element (r, kk) of the A tile (r < BM, kk < BK) handled by this thread, slot u
   auto a_coord = [&](int u, int& r, int& kk) {
-    int idx = tid + u * 256;
+    int idx = tid + u * NT;
     if (!TA) { r = idx / BK; kk = idx % BK; }   // contiguous along k
     else     { kk = idx / BM; r = idx % BM; }   // contiguous along m
   };
   auto b_coord = [&](int u, int& c, int& kk) {
-    int idx = tid + u * 256;
+    int idx = tid + u * NT;
     if (!TB) { kk = idx / BN; c = idx % BN; }   // contiguous along n
     else     { c = idx / BK; kk = idx % BK; }   // contiguous along k
   };
@@ -154,12 +161,12 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
   typedef typename std::conditional<KU == 8, uint4, uint2>::type kvec_t;
   constexpr int A_NK = TA ? BM * BK / (8 * KU) : BM * BK / 8;   // units of the A tile
   constexpr int B_NK = TB ? BN * BK / 8 : BN * BK / (8 * KU);
-  constexpr int A_UV = (A_NK + 255) / 256, B_UV = (B_NK + 255) / 256;
+  constexpr int A_UV = (A_NK + NT - 1) / NT, B_UV = (B_NK + NT - 1) / NT;
   constexpr int A_L = TA ? KU : 1, B_L = TB ? 1 : KU;       // 16-byte loads per unit
   uint4 va[A_UV][A_L], vbv[B_UV][B_L];
   // unit u of an operand tile of R rows: its first (row, k)
   auto unit = [&](int u, int R, bool kcontig, int& r, int& kk) {
-    const int idx = tid + u * 256;
+    const int idx = tid + u * NT;
     if (kcontig) { r = idx / (BK / 8); kk = (idx % (BK / 8)) * 8; }
     else         { kk = (idx / (R / 8)) * KU; r = (idx % (R / 8)) * 8; }
   };
@@ -168,7 +175,7 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
     for (int u = 0; u < A_UV; ++u) {
       int r, kk;
       unit(u, BM, !TA, r, kk);
-      const bool ok = A_NK % 256 == 0 || tid + u * 256 < A_NK;
+      const bool ok = A_NK % NT == 0 || tid + u * NT < A_NK;
 #pragma unroll
       for (int l = 0; l < A_L; ++l) {
         const int gm = m0 + r, gk = k0 + kk + l;
@@ -182,7 +189,7 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
     for (int u = 0; u < B_UV; ++u) {
       int c, kk;
       unit(u, BN, TB, c, kk);
-      const bool ok = B_NK % 256 == 0 || tid + u * 256 < B_NK;
+      const bool ok = B_NK % NT == 0 || tid + u * NT < B_NK;
 #pragma unroll
       for (int l = 0; l < B_L; ++l) {
         const int gn = n0 + c, gk = k0 + kk + l;
@@ -209,7 +216,7 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
   auto store_vec = [&]() {
 #pragma unroll
     for (int u = 0; u < A_UV; ++u) {
-      if (A_NK % 256 != 0 && tid + u * 256 >= A_NK) continue;
+      if (A_NK % NT != 0 && tid + u * NT >= A_NK) continue;
       int r, kk;
       unit(u, BM, !TA, r, kk);
       if constexpr (!TA) *reinterpret_cast<uint4*>(&As[r * LDS_LD + kk]) = va[u][0];
@@ -217,7 +224,7 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
     }
 #pragma unroll
     for (int u = 0; u < B_UV; ++u) {
-      if (B_NK % 256 != 0 && tid + u * 256 >= B_NK) continue;
+      if (B_NK % NT != 0 && tid + u * NT >= B_NK) continue;
       int c, kk;
       unit(u, BN, TB, c, kk);
       if constexpr (TB) *reinterpret_cast<uint4*>(&Bs[c * LDS_LD + kk]) = vbv[u][0];
@@ -281,7 +288,7 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
 }
 
 template <typename TI, typename TO, int BM, int BN, bool TA, bool TB, bool VEC, bool GROUPED>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
+__global__ __launch_bounds__(gemm_threads(BM, BN)) void gemm_kernel(GemmArgs ga_, const GemmArgs* grp, const int4* bmap) {
   if constexpr (!GROUPED) {
     VBlock vb = hw_block();
     if (!slice_block(ga_, vb)) return;
@@ -531,8 +538,8 @@ static hipError_t launch_gemm_tile(dctk_ctx ctx, hipStream_t s, int M, int N, in
   const bool vec = sizeof(TI) == 2 && va && vb;
 #define DCTK_GEMM_LAUNCH(TA_, TB_) \
   do { \
-    if (vec) return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_, true, false>, gemm_kernel<TI, TO, BM, BN, TA_, TB_, true, true>, grid, 256, 0, ga); \
-    return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_, false, false>, gemm_kernel<TI, TO, BM, BN, TA_, TB_, false, true>, grid, 256, 0, ga); \
+    if (vec) return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_, true, false>, gemm_kernel<TI, TO, BM, BN, TA_, TB_, true, true>, grid, gemm_threads(BM, BN), 0, ga); \
+    return launch_kernel(ctx, s, gemm_kernel<TI, TO, BM, BN, TA_, TB_, false, false>, gemm_kernel<TI, TO, BM, BN, TA_, TB_, false, true>, grid, gemm_threads(BM, BN), 0, ga); \
   } while (0)
   if (!ta && !tb) DCTK_GEMM_LAUNCH(false, false);
   if (ta && !tb) DCTK_GEMM_LAUNCH(true, false);
@@ -547,8 +554,13 @@ static hipError_t launch_gemm_t(dctk_ctx ctx, hipStream_t s, int M, int N, int K
                                 int64_t sC, int batch, Gate g, int num_cus, int tile) {
   // 128 x 128 tiles while they give every CU two, then 64 x 64 when they
   // fill the chip, 32 x 32 otherwise.
+  const int64_t tiles256 = (int64_t)((M + 255) / 256) * ((N + 255) / 256) * batch;
   const int64_t tiles128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128) * batch;
   int64_t tiles64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64) * batch;
+  // 256 x 256 while they still give every CU one (each operand byte staged
+  // serves twice the flops of a 128 x 128 tile)
+  if (tile == 256 || (tile == 0 && M >= 256 && N >= 256 && tiles256 >= (int64_t)num_cus))
+    return launch_gemm_tile<TI, TO, 256, 256>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
   if (tile == 128 || (tile == 0 && tiles128 >= 2 * (int64_t)num_cus))
     return launch_gemm_tile<TI, TO, 128, 128>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
   if (tile == 64 || (tile == 0 && tiles64 >= 2 * (int64_t)num_cus))
@@ -638,12 +650,18 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   // step 2: slice products
   const int64_t sAh = n1 * n2;
   prof_begin(ctx, PROF_GEMM);
+  // the left operand: A~ (n1 x n2), or for the adjoint A~^T (n2 x n1) -- read
+  // from the transposed copy when the operator keeps one (16-bit types)
+  const bool tcopy = adjoint && op->AhT != nullptr;
+  const void* Aop = tcopy ? op->AhT : op->Ah;
+  const int64_t ldA = tcopy ? n1 : n2;
+  const int tA = adjoint && !tcopy ? 1 : 0;
   if (!op->two_sided) {
     // forward: (n1 x n2)(n2 x s);  adjoint: (n2 x n1 := A~^T)(n1 x s)
-    e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
+    e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)rin, Aop, ldA, sAh, tA,
                     op->xh, sc, rin * sc, 0, op->ch, sc, rout * sc, (int)p, g, tile);
   } else {
-    e = launch_gemm(ctx, s, gdt, 0, (int)rout, (int)sc, (int)rin, op->Ah, n2, sAh, adjoint ? 1 : 0,
+    e = launch_gemm(ctx, s, gdt, 0, (int)rout, (int)sc, (int)rin, Aop, ldA, sAh, tA,
                     op->xh, sc, rin * sc, 0, op->th, sc, rout * sc, (int)p, g, tile);
     if (e != hipSuccess) return e;
     // right factor: forward (rout x s)(s x s) with B~; adjoint with B~^T

@@ -181,7 +181,7 @@ def test_low_precision_gemm_modes(ctx, gdt, two_sided):
                    label="lowp adjoint")
 
 
-PATHS = [(1, 16), (1, 32), (1, 64), (0, 32), (0, 64), (0, 128)]
+PATHS = [(1, 16), (1, 32), (1, 64), (0, 32), (0, 64), (0, 128), (0, 256)]
 
 
 @pytest.mark.parametrize("gdt", [dk.DCTK_F64, dk.DCTK_F32, dk.DCTK_BF16, dk.DCTK_F16])
