@@ -57,7 +57,8 @@ LONGTUBE_TRAFFIC = {"digest": "8316061216a2f747", "bytes": 657846060}
 # keyed "gemm type/kernel"), filled in from the counter passes of the hyper512 bench.
 HYPER_TRAFFIC_SOURCES = ("paper_2103_11847_amd/csrc/gemm.hip", "paper_2103_11847_amd/csrc/transform.hip",
                          "paper_2103_11847_amd/csrc/mfma.h", "paper_2103_11847_amd/csrc/internal.h")
-HYPER_TRAFFIC = {"digest": None, "bytes": {}}
+HYPER_TRAFFIC = {"digest": "66199a40135f8679",
+                 "bytes": {'f32/gemm': 201930594, 'f32/tube_fwd': 200901075, 'f32/tube_inv': 200840016, 'bf16/gemm': 134498981, 'bf16/tube_fwd': 167378976, 'bf16/tube_inv': 200840526}}
 
 
 def source_digest(files):
@@ -104,7 +105,8 @@ def parse():
                     help="colour256: lambda by GCV (default), by the discrepancy principle at 1.05 x the "
                          "norm of the added noise, or LSQR stopped at the L-curve corner")
     ap.add_argument("--workload", default="hyper512",
-                    choices=["hyper512", "colour256", "batch64", "video256", "paper", "longtube", "learned512"],
+                    choices=["hyper512", "colour256", "batch64", "video256", "paper", "longtube", "learned512",
+                             "video4"],
                     help="hyper512: one 512x512x64 solve per step (default); colour256: one 256x256x3 "
                          "solve per step; batch64: the uneven 64-instance batch per step (merged launches, "
                          "HIP graph)")
@@ -188,7 +190,7 @@ def main():
         sys.exit(1)
     if args.workload == "batch64":
         return bench_batch(args)
-    if args.workload == "hyper512":
+    if args.workload in ("hyper512", "video4"):
         return bench_hyper(args)
     if args.workload == "learned512":
         return bench_learned512(args)
@@ -869,18 +871,27 @@ def hyper_traffic(kind, gemm):
 
 def bench_hyper(args):
     """hyper512: one DC-GK solve (40 GKB steps, FP64 GCV) of the 512 x 512 x 64
-    hyperspectral-like problem per step, gated on a full FP64 oracle solve."""
+    hyperspectral-like problem per step, gated on a full FP64 oracle solve.
+    video4: the same for the order-4 colour video (128 x 128 x 3 colours x 16
+    frames, an order-4 operator: 48 flattened tube slices)."""
     import torch
     import paper_2103_11847_amd as dk
     import workloads as W
     dev = torch.device("cuda:0")
-    w = W.hyperspectral(0)
-    p, n, s = w["X_true"].shape
+    order4 = args.workload == "video4"
+    w = W.colour_video(0) if order4 else W.hyperspectral(0)
+    n, s = w["X_true"].shape[-2:]
+    p = int(np.prod(w["X_true"].shape[:-2]))
     k = w["iters"]
     ctx = dk.dctk_create(0)
     A64 = torch.from_numpy(w["A"]).to(dev)
+
+    def make_op(gdt):
+        if order4:
+            return dk.dctk_op_create_nd(ctx, dk.DCTK_TUBE_TH, gdt, A64, s)
+        return dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, gdt, A64, s)
     # C = M(X_true) + noise at relative level nu, formed with the library's FP64 product
-    op64 = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DCTK_F64, A64, s)
+    op64 = make_op(dk.DCTK_F64)
     Xt = torch.from_numpy(w["X_true"]).to(dev)
     Ch = torch.empty_like(Xt)
     dk.dctk_cprod(ctx, op64, 1.0, Xt, 0.0, Ch)
@@ -895,7 +906,7 @@ def bench_hyper(args):
         """Timed region: `steps` solves enqueued back to back (no read-back between
         them).  Then the same number of solves with every transform / GEMM launch
         recording start and stop events on the library's stream (kernel times)."""
-        op = dk.dctk_op_create(ctx, dk.DCTK_TUBE_TH, dk.DTYPES[gemm], A64, s)
+        op = make_op(dk.DTYPES[gemm])
         ws = dk.dctk_krylov_create(ctx, op, dk.DCTK_KRYLOV_GKB, k)
         X = torch.empty_like(C)
         for _ in range(warmup):
@@ -927,7 +938,8 @@ def bench_hyper(args):
         tot, cnt = prof[kind]
         if cnt:
             f, b = kernel_work(kind, p, n, n, s, bg)
-            kinds[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, gemm, hyper_traffic(kind, gemm))
+            kinds[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, gemm,
+                                         None if order4 else hyper_traffic(kind, gemm))
             kinds[kind].update({"launches": cnt, "ms_total": tot})
     dom = max(kinds, key=lambda k_: kinds[k_]["ms_total"])
     roof = dict(kinds[dom])
@@ -944,7 +956,8 @@ def bench_hyper(args):
             tot, cnt = prof_b[kind]
             if cnt:
                 f, b = kernel_work(kind, p, n, n, s, 2)
-                kb[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, "bf16", hyper_traffic(kind, "bf16"))
+                kb[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, "bf16",
+                                          None if order4 else hyper_traffic(kind, "bf16"))
                 kb[kind].update({"launches": cnt, "ms_total": tot})
         mixed = {"solves_per_s": 1e3 / ms_b, "ms_per_step": ms_b, "relerr_gpu": err_b, "lambda": info_b.lam,
                  "per_kind": kb}
@@ -957,12 +970,28 @@ def bench_hyper(args):
             cal_out.copy_(cal)
         torch.cuda.synchronize()
         del cal, cal_out
+    # what a plain device copy attains on this GPU (1 read + 1 write stream, 256 MiB
+    # buffers taken in turn so the 256 MB last-level cache cannot serve them): context
+    # for the transforms' HBM fraction, whose roofline stays the published peak
+    bufs = [torch.ones(64 << 20, dtype=torch.float32, device=dev) for _ in range(4)]
+    for i in range(4):
+        bufs[(i + 1) % 4].copy_(bufs[i])
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for i in range(20):
+        bufs[(i + 1) % 4].copy_(bufs[i % 4])
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 20 * 2 * (256 << 20) / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del bufs
 
     # the FP64 oracle: one full solve of the same problem (its own C), timed
     from oracle import krylov, metrics
     from oracle.cprod import Operator, fro
+    from oracle.ordern import OperatorND
     t0 = time.perf_counter()
-    orc = Operator(w["A"])
+    orc = OperatorND(w["A"]) if order4 else Operator(w["A"])
     Cn = orc.apply(w["X_true"])
     Cn = Cn + w["nu"] * fro(Cn) / fro(w["N0"]) * w["N0"]
     ref = krylov.dc_gk(orc, Cn, k, lam=None, gcv_mode="rect", reorth="none")
@@ -971,8 +1000,9 @@ def bench_hyper(args):
     cpu = None
     if not args.no_cpu_baseline:
         cpu = {"value": 1.0 / dt, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
-               "sample": "one full FP64 DC-GK solve of the same 512x512x64 problem (operator set-up, C, 40 GKB "
-                         "steps, GCV, combine) in %.1f s (numpy, BLAS matmul)" % dt}
+               "sample": "one full FP64 DC-GK solve of the same %s problem (operator set-up, C, 40 GKB "
+                         "steps, GCV, combine) in %.1f s (numpy, BLAS matmul)"
+                         % ("128x128x3x16" if order4 else "512x512x64", dt)}
     gate = err_gpu <= 1.05 * err_oracle
     if mixed is not None:
         mixed["ratio_vs_oracle"] = mixed["relerr_gpu"] / err_oracle
@@ -984,9 +1014,13 @@ def bench_hyper(args):
         "metric": METRIC, "value": (1e3 / ms) if gate else 0.0, "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": gemm, "data": "synthetic",
-        "config": {"workload": "hyperspectral-like deblur 512x512x64, band-dependent blur sigma 1.5-4, "
-                               "DC-GK 40 GKB steps + FP64 GCV, one solve per step",
-                   "n1": n, "n2": n, "s": s, "n3": p, "gkb_steps": k, "gemm_dtype": gemm,
+        "config": {"workload": ("order-4 colour video deblur 128x128 x 3 colours x 16 frames (colour tube "
+                                "(0.7, 0.15, 0.15) on mode 3, temporal half-kernel on mode 4, Gaussian blur "
+                                "sigma 2), DC-GK 40 GKB steps + FP64 GCV, one solve per step" if order4 else
+                                "hyperspectral-like deblur 512x512x64, band-dependent blur sigma 1.5-4, "
+                                "DC-GK 40 GKB steps + FP64 GCV, one solve per step"),
+                   "n1": n, "n2": n, "s": s, "n3": p, "tube_dims": list(reversed(w["X_true"].shape[:-2])),
+                   "gkb_steps": k, "gemm_dtype": gemm,
                    "vector_dtype": "f32", "reorth": "none", "tube": "th", "nu": w["nu"]},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -997,6 +1031,7 @@ def bench_hyper(args):
                           "note": "the kernel times come from a second pass of the same number of solves in "
                                   "which every launch records start/stop events"},
         "mixed_bf16": mixed,
+        "device_copy_GB_per_s": copy_gbs,
     }
     print(json.dumps(line))
 
