@@ -185,7 +185,13 @@ int dctk_tube_apply_noalloc(dctk_ctx ctx, int tube, int which, int dtype, int64_
  * Vector element type: DCTK_F64 when gemm_dtype is DCTK_F64, else DCTK_F32
  * (BF16/F16 operators cast the transformed vector to the GEMM type and
  * accumulate in FP32).  A and B are only read during this call.
- * Errors: DCTK_ESHAPE (a dimension <= 0, or p > 64), DCTK_EDTYPE, DCTK_ENOMEM. */
+ * Tube length: p <= 64 keeps the four p x p transform matrices and applies
+ * them on the matrix cores; a power-of-two p from 128 to 2048 uses the
+ * O(p log p) transform of dctk_tube_fast for A~, B~ and both transforms of
+ * every product (the fast DCT of Sec. 1 and Sec. 2.1), with the same
+ * products, workspaces, solvers and batches.
+ * Errors: DCTK_ESHAPE (a dimension <= 0, or p > 64 and not a power of two
+ * up to 2048), DCTK_EDTYPE, DCTK_ENOMEM. */
 int dctk_op_create(dctk_ctx ctx, int tube, int gemm_dtype, int64_t p, int64_t n1, int64_t n2,
                    const void* A, int64_t s, const void* B, dctk_op* out);
 /* Order-N operators (the recursive extension to higher-order tensors that

@@ -394,11 +394,16 @@ static int op_create_impl(dctk_ctx ctx, int tube, int gemm_dtype, int nd, const 
   if (gemm_dtype < DCTK_F64 || gemm_dtype > DCTK_F16) return DCTK_EDTYPE;
   if (nd < 1 || nd > kMaxTubeModes) return DCTK_ESHAPE;
   int64_t p = 1;
-  for (int m = 0; m < nd; ++m) {
+  // one tube mode longer than kMaxTube: a power of two up to kFastOpMaxP,
+  // transformed by the O(p log p) kernels instead of a p x p matrix
+  const bool fast = nd == 1 && dims[0] > kMaxTube;
+  if (fast && (dims[0] > kFastOpMaxP || !tube_fast_shape_ok(DCTK_F64, dims[0]))) return DCTK_ESHAPE;
+  for (int m = 0; m < nd && !fast; ++m) {
     if (dims[m] <= 0 || dims[m] > kMaxTube) return DCTK_ESHAPE;
     p *= dims[m];
     if (p > kMaxTube) return DCTK_ESHAPE;
   }
+  if (fast) p = dims[0];
   if (n1 <= 0 || n2 <= 0 || s <= 0) return DCTK_ESHAPE;
   if (n1 > (1 << 30) || n2 > (1 << 30) || s > (1 << 30)) return DCTK_ESHAPE;
   dctk_op op = new (std::nothrow) dctk_op_s();
@@ -409,6 +414,7 @@ static int op_create_impl(dctk_ctx ctx, int tube, int gemm_dtype, int nd, const 
   op->vec_dtype = gemm_dtype == DCTK_F64 ? DCTK_F64 : DCTK_F32;
   op->p = p; op->n1 = n1; op->n2 = n2; op->s = s;
   op->two_sided = B != nullptr;
+  op->fast = fast ? 1 : 0;
   for (int d = 0; d < 2; ++d) {
     op->tune[d][0] = -1;
     op->tune[d][1] = 0;
@@ -418,16 +424,18 @@ static int op_create_impl(dctk_ctx ctx, int tube, int gemm_dtype, int nd, const 
   const int64_t nmax = n1 > n2 ? n1 : n2;
   const int64_t pp = p * p;
   std::vector<double> Gd;
-  build_op_matrices(tube, nd, dims, p, Gd);
+  if (!fast) build_op_matrices(tube, nd, dims, p, Gd);
   std::vector<float> Gf(Gd.size());
   for (size_t i = 0; i < Gd.size(); ++i) Gf[i] = (float)Gd[i];
   double* tmp = nullptr;
   hipError_t e = hipSetDevice(ctx->device);
 #define DCTK_TRY(call) do { if (e == hipSuccess) e = (call); } while (0)
-  DCTK_TRY(hipMalloc((void**)&op->Gd, sizeof(double) * 4 * pp));
-  DCTK_TRY(hipMalloc((void**)&op->Gf, sizeof(float) * 4 * pp));
-  DCTK_TRY(hipMemcpy(op->Gd, Gd.data(), sizeof(double) * 4 * pp, hipMemcpyHostToDevice));
-  DCTK_TRY(hipMemcpy(op->Gf, Gf.data(), sizeof(float) * 4 * pp, hipMemcpyHostToDevice));
+  if (!fast) {
+    DCTK_TRY(hipMalloc((void**)&op->Gd, sizeof(double) * 4 * pp));
+    DCTK_TRY(hipMalloc((void**)&op->Gf, sizeof(float) * 4 * pp));
+    DCTK_TRY(hipMemcpy(op->Gd, Gd.data(), sizeof(double) * 4 * pp, hipMemcpyHostToDevice));
+    DCTK_TRY(hipMemcpy(op->Gf, Gf.data(), sizeof(float) * 4 * pp, hipMemcpyHostToDevice));
+  }
   DCTK_TRY(hipMalloc(&op->Ah, ge * (size_t)(p * n1 * n2)));
   // 16-bit products read A~ with the contraction index contiguous in both
   // directions (16-byte rows straight into LDS): keep the transposed slices
@@ -445,8 +453,10 @@ static int op_create_impl(dctk_ctx ctx, int tube, int gemm_dtype, int nd, const 
   none.kind = CTL_PLAIN;
   none.a = 1.0;
   none.s = 1.0;
-#define DCTK_TUBE_F64(SRC, DST, CNT) \
-  launch_tube(ctx, ctx->stream, DCTK_F64, DCTK_F64, p, (CNT), (SRC), (DST), op->Gd, op->Gf, nullptr, nullptr, none, false, true, nullptr)
+#define DCTK_TUBE_F64(SRC, DST, CNT)                                                                   \
+  (fast ? launch_tube_fast(ctx, ctx->stream, tube, DCTK_MAT_L, DCTK_F64, p, (CNT), (SRC), (DST))         \
+        : launch_tube(ctx, ctx->stream, DCTK_F64, DCTK_F64, p, (CNT), (SRC), (DST), op->Gd, op->Gf, nullptr, \
+                      nullptr, none, false, true, nullptr))
   if (gemm_dtype == DCTK_F64) {
     DCTK_TRY(DCTK_TUBE_F64(A, op->Ah, n1 * n2));
     if (op->two_sided) DCTK_TRY(DCTK_TUBE_F64(B, op->Bh, s * s));

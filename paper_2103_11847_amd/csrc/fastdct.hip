@@ -44,15 +44,24 @@ struct FastCfg {
 };
 
 struct FastArgs {
-  const void* in;
-  void* out;
-  int64_t count;  // positions per slice
+  int gx, gy, gz;  // the instance's grid (recorded by launch_kernel)
   int p, logp, nb, lognb;
   int group;  // blocks of tubes sharing 128-byte lines, taken by one workgroup back to back
   int inv;    // 0: F core, 1: F^{-1} core (the kernel's INV)
   int pre;    // before F: 0 none, 1 (I + Z), 2 (I + Z^T)^{-1}
   int post;   // after F^{-1}: 0 none, 1 (I + Z^T), 2 (I + Z)^{-1}
   int scale;  // diagonal: 0 D^{-1}, 1 D N^{-1}, 2 S (after F); 3 D, 4 N D^{-1}, 5 S^{-1} (before F^{-1})
+  int pad_;
+  int64_t count;  // positions per slice
+  const void* in;
+  void* out;
+  // inside a c-product: the input side of the control block (SCALE: the
+  // input is multiplied by its scale s, and s * in written to xnorm when
+  // given) or its output side (EPI: out = a * (in x_3 G) + b * src, with
+  // per-workgroup partial sums of out^2 in ctl.part_out)
+  const void* src;  // p x count, or null
+  void* xnorm;      // p x count, or null
+  Ctl ctl;
 };
 
 __device__ inline void sc_pi(float x, float* s, float* c) { sincospif(x, s, c); }
@@ -118,8 +127,11 @@ __device__ void alt_scan(T* buf, T* part, int p, int nb, int lognb) {
   }
 }
 
-template <typename T, bool INV, bool PAIR>
-__global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) {
+// T: the arithmetic and input type; TO: the output type (T, or a 16-bit GEMM
+// operand type for a forward transform feeding the slice products).
+template <typename T, typename TO, bool INV, bool PAIR, bool SCALE, bool EPI>
+__device__ __forceinline__ void tube_fast_body(const FastArgs& a, const VBlock vb) {
+  static_assert(!(SCALE && INV) && !(EPI && !INV), "the input side precedes F, the output side follows F^{-1}");
   constexpr int E = FastCfg<T>::E;
   // With two or more tubes per block (PAIR), tubes j and j + nb/2 share one
   // complex FFT as its real and imaginary parts: the forward input and the
@@ -131,9 +143,13 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
   __shared__ T re[E], im[E];       // complex FFT buffer, position-major
   __shared__ T twr[E / 2], twi[E / 2];  // exp(-2 pi i m / p), m < p/2
   __shared__ T part[kFastThreads];
+  __shared__ double shc[2 * (kFastThreads / 64 + 1)];  // the control block's reductions
   const T* in = (const T*)a.in;
-  T* out = (T*)a.out;
+  TO* out = (TO*)a.out;
   const int tid = threadIdx.x;
+  // the control block's loads first, so they are in flight with the first block's
+  CtlLoad cl{};
+  if constexpr (SCALE || EPI) cl = ctl_load(a.ctl);
   const int p = a.p, nb = a.nb, lognb = a.lognb, logp = a.logp;
   const int64_t count = a.count;
   const int64_t ntiles = (count + nb - 1) / nb;
@@ -181,14 +197,41 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
   // slice, so a line's second part is read from the CU's own L2.  The grid
   // never exceeds the number of groups, so the first block exists.
   const int grp = a.group;
-  auto tile_of = [&](int64_t n) { return ((int64_t)blockIdx.x + n / grp * gridDim.x) * grp + n % grp; };
+  auto tile_of = [&](int64_t n) { return ((int64_t)vb.x + n / grp * a.gx) * grp + n % grp; };
   int64_t n = 0, tile = tile_of(0);
   fetch(tile);
+  T sc = (T)1, ea = (T)1, eb = (T)0;
+  bool use_src = false;
+  if constexpr (SCALE || EPI) {
+    double ad, bd, sd;
+    if (!ctl_eval(a.ctl, cl, ad, bd, sd, shc, vb)) return;
+    if (SCALE) sc = (T)sd;
+    if (EPI) {
+      ea = (T)ad;
+      eb = (T)bd;
+      use_src = a.src != nullptr && bd != 0.0;  // b = 0: src never enters
+    }
+  }
+  T* xn = (T*)a.xnorm;
+  // without src the epilogue reads this block's own input rows again (from
+  // the cache) instead of a branch around its loads
+  const T* sp = use_src ? (const T*)a.src : in;
+  double sq = 0.0;
+  T sv[EPI ? U : 1];
   for (; tile < ntiles; tile = tile_of(++n)) {
     const int64_t e0 = tile * nb;
     const bool live = e0 + jt < count;
+    if constexpr (EPI) {
+      const T* s0 = sp + (int64_t)t0 * count + (live ? e0 + jt : count - 1);
 #pragma unroll
-    for (int u = 0; u < U; ++u) rb[tid + u * kFastThreads] = live ? pf[u] : (T)0;
+      for (int u = 0; u < U; ++u) sv[u] = s0[u * rstride];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T v = live ? (SCALE ? sc * pf[u] : pf[u]) : (T)0;
+      rb[tid + u * kFastThreads] = v;
+      if (SCALE && xn != nullptr && live) xn[(int64_t)t0 * count + e0 + jt + u * rstride] = v;
+    }
     __syncthreads();
     // the next block of tubes is in flight while this one is transformed
     const int64_t next = tile_of(n + 1);
@@ -296,7 +339,7 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
       }
       __syncthreads();
     }
-    T* dst = out + (int64_t)t0 * count + e0 + jt;
+    TO* dst = out + (int64_t)t0 * count + e0 + jt;
     if (!INV) {
       // F_k = Re(exp(-i pi k / (2p)) V_k), then the diagonal
 #pragma unroll
@@ -313,7 +356,7 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
           const T vr = hi ? zi + wi : zr + wr, vi = hi ? wr - zr : zi - wi;
           f = (T)0.5 * (vr * rc[u] + vi * rs[u]);
         }
-        if (live) dst[u * rstride] = f * rq[u];
+        if (live) dst[u * rstride] = cvt<TO, T>(f * rq[u]);
       }
     } else {
       // y_t = v_n / p with n the reordered index of t
@@ -336,10 +379,32 @@ __global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a) 
         const int i = tid + u * kFastThreads;
         T y = rb[i];
         if (a.post == 1 && t0 + u * ru > 0) y += rb[i - nb];
-        if (live) dst[u * rstride] = y;
+        if constexpr (EPI) {
+          y = ea * y + (use_src ? eb * sv[u] : (T)0);
+          if (live) sq += (double)y * (double)y;
+        }
+        if (live) dst[u * rstride] = cvt<TO, T>(y);
       }
     }
     __syncthreads();  // the buffers are rewritten by the next block of tubes
+  }
+  if constexpr (EPI) {
+    if (a.ctl.part_out != nullptr) {
+      const double tot = block_sum_all(sq, shc);
+      if (tid == 0) a.ctl.part_out[vb.x] = tot;
+    }
+  }
+}
+
+template <typename T, typename TO, bool INV, bool PAIR, bool SCALE, bool EPI, bool GROUPED>
+__global__ __launch_bounds__(kFastThreads, 4) void tube_fast_kernel(FastArgs a_, const FastArgs* grp,
+                                                                    const int4* bmap) {
+  if constexpr (!GROUPED) {
+    tube_fast_body<T, TO, INV, PAIR, SCALE, EPI>(a_, hw_block());
+  } else {
+    VBlock vb;
+    const FastArgs g = group_args(grp, bmap, vb);
+    tube_fast_body<T, TO, INV, PAIR, SCALE, EPI>(g, vb);
   }
 }
 
@@ -357,14 +422,12 @@ bool tube_fast_shape_ok(int dtype, int64_t p) {
   return p >= kFastMinTube && p <= tube_fast_max(dtype) && (p & (p - 1)) == 0;
 }
 
-hipError_t launch_tube_fast(dctk_ctx ctx, hipStream_t s, int tube, int which, int dtype, int64_t p, int64_t count,
-                            const void* in, void* out) {
-  if (recording(ctx)) return hipErrorNotSupported;
+// The arguments of transform `which` of family `tube` on p x count elements
+// of type `dtype`, and the number of resident workgroups.
+static hipError_t fast_setup(int tube, int which, int dtype, int64_t p, int64_t count, FastArgs& a, int64_t& blocks) {
   if ((dtype != DCTK_F64 && dtype != DCTK_F32) || !tube_fast_shape_ok(dtype, p) || count <= 0)
     return hipErrorInvalidValue;
-  FastArgs a{};
-  a.in = in;
-  a.out = out;
+  a = FastArgs{};
   a.count = count;
   a.p = (int)p;
   a.logp = ilog2(p);
@@ -387,23 +450,87 @@ hipError_t launch_tube_fast(dctk_ctx ctx, hipStream_t s, int tube, int which, in
   a.group = (p <= 512 && seg < 128) ? 128 / seg : 1;
   const int64_t groups = (tiles + a.group - 1) / a.group;
   // resident workgroups (two fit a CU's LDS, 16 waves), each looping over groups
-  const int64_t blocks = std::min<int64_t>(groups, 2 * (int64_t)num_cus());
-  const dim3 g((unsigned)blocks), b(kFastThreads);
+  blocks = std::min<int64_t>(groups, 2 * (int64_t)num_cus());
+  return hipSuccess;
+}
+
+hipError_t launch_tube_fast(dctk_ctx ctx, hipStream_t s, int tube, int which, int dtype, int64_t p, int64_t count,
+                            const void* in, void* out) {
+  if (recording(ctx)) return hipErrorNotSupported;
+  FastArgs a;
+  int64_t blocks = 0;
+  hipError_t e = fast_setup(tube, which, dtype, p, count, a, blocks);
+  if (e != hipSuccess) return e;
+  a.in = in;
+  a.out = out;
+  a.ctl.kind = CTL_PLAIN;
+  const dim3 g((unsigned)blocks);
   const bool pair = a.nb >= 2;
-#define DCTK_FAST_LAUNCH(T)                                                          \
-  do {                                                                               \
-    if (a.inv) {                                                                     \
-      if (pair) tube_fast_kernel<T, true, true><<<g, b, 0, s>>>(a);                  \
-      else tube_fast_kernel<T, true, false><<<g, b, 0, s>>>(a);                      \
-    } else {                                                                         \
-      if (pair) tube_fast_kernel<T, false, true><<<g, b, 0, s>>>(a);                 \
-      else tube_fast_kernel<T, false, false><<<g, b, 0, s>>>(a);                     \
-    }                                                                                \
+#define DCTK_FAST_PLAIN(T, I, P) \
+  return launch_kernel(ctx, s, tube_fast_kernel<T, T, I, P, false, false, false>, \
+                       tube_fast_kernel<T, T, I, P, false, false, false>, g, kFastThreads, 0, a)
+#define DCTK_FAST_T(T)                                              \
+  do {                                                              \
+    if (a.inv) {                                                    \
+      if (pair) DCTK_FAST_PLAIN(T, true, true);                     \
+      DCTK_FAST_PLAIN(T, true, false);                              \
+    }                                                               \
+    if (pair) DCTK_FAST_PLAIN(T, false, true);                      \
+    DCTK_FAST_PLAIN(T, false, false);                               \
   } while (0)
-  if (dtype == DCTK_F64) DCTK_FAST_LAUNCH(double);
-  else DCTK_FAST_LAUNCH(float);
-#undef DCTK_FAST_LAUNCH
-  return hipGetLastError();
+  if (dtype == DCTK_F64) DCTK_FAST_T(double);
+  DCTK_FAST_T(float);
+#undef DCTK_FAST_T
+#undef DCTK_FAST_PLAIN
+}
+
+hipError_t launch_tube_fast_ctl(dctk_ctx ctx, hipStream_t s, int tube, int which, int in_dtype, int out_dtype,
+                                int64_t p, int64_t count, const void* in, void* out, const void* src, void* xnorm,
+                                const Ctl& ctl, bool scale, bool epi, int* nblocks_out) {
+  FastArgs a;
+  int64_t blocks = 0;
+  hipError_t e = fast_setup(tube, which, in_dtype, p, count, a, blocks);
+  if (e != hipSuccess) return e;
+  // the input side belongs to F (the transforms L, L^{-T}), the output side to F^{-1} (L^{-1}, L^T)
+  if (scale == epi || (scale && a.inv) || (epi && !a.inv)) return hipErrorInvalidValue;
+  if (epi && out_dtype != in_dtype) return hipErrorInvalidValue;
+  if (in_dtype == DCTK_F64 && out_dtype != DCTK_F64) return hipErrorInvalidValue;
+  if (epi && ctl.part_out != nullptr && blocks > kRedBlocks) return hipErrorInvalidConfiguration;
+  if (nblocks_out) *nblocks_out = (int)blocks;
+  a.in = in;
+  a.out = out;
+  a.src = epi ? src : nullptr;
+  a.xnorm = scale ? xnorm : nullptr;
+  a.ctl = ctl;
+  const dim3 g((unsigned)blocks);
+  const bool pair = a.nb >= 2;
+#define DCTK_FAST_CTL(T, TO, I, P, S, E_)                                                         \
+  return launch_kernel(ctx, s, tube_fast_kernel<T, TO, I, P, S, E_, false>,                       \
+                       tube_fast_kernel<T, TO, I, P, S, E_, true>, g, kFastThreads, 0, a)
+#define DCTK_FAST_FWD(T, TO)                                  \
+  do {                                                        \
+    if (pair) DCTK_FAST_CTL(T, TO, false, true, true, false); \
+    DCTK_FAST_CTL(T, TO, false, false, true, false);          \
+  } while (0)
+#define DCTK_FAST_INV(T)                                      \
+  do {                                                        \
+    if (pair) DCTK_FAST_CTL(T, T, true, true, false, true);   \
+    DCTK_FAST_CTL(T, T, true, false, false, true);            \
+  } while (0)
+  if (in_dtype == DCTK_F64) {
+    if (scale) DCTK_FAST_FWD(double, double);
+    DCTK_FAST_INV(double);
+  }
+  if (epi) DCTK_FAST_INV(float);
+  switch (out_dtype) {
+    case DCTK_F32: DCTK_FAST_FWD(float, float);
+    case DCTK_BF16: DCTK_FAST_FWD(float, bf16_t);
+    case DCTK_F16: DCTK_FAST_FWD(float, f16_t);
+    default: return hipErrorInvalidValue;
+  }
+#undef DCTK_FAST_INV
+#undef DCTK_FAST_FWD
+#undef DCTK_FAST_CTL
 }
 
 }  // namespace dctk

@@ -13,6 +13,7 @@
 // multiplied.  Ragged edges are zero-filled on load and masked on store.
 #include <type_traits>
 
+#include "fastdct.h"
 #include "mfma.h"
 
 namespace dctk {
@@ -632,8 +633,12 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   // this kernel evaluates the control block (input scale, recorded scalars)
   const int gi = adjoint ? 2 : 0;
   prof_begin(ctx, PROF_TUBE_FWD);
-  e = launch_tube(ctx, s, vdt, gdt, p, rin * sc, X, op->xh, Gd + gi * pp, Gf + gi * pp, nullptr, xnorm, ctl, true,
-                  false, nullptr);
+  if (op->fast)  // tubes longer than kMaxTube: the O(p log p) transform
+    e = launch_tube_fast_ctl(ctx, s, op->tube, adjoint ? DCTK_MAT_LINVT : DCTK_MAT_L, vdt, gdt, p, rin * sc, X,
+                             op->xh, nullptr, xnorm, ctl, true, false, nullptr);
+  else
+    e = launch_tube(ctx, s, vdt, gdt, p, rin * sc, X, op->xh, Gd + gi * pp, Gf + gi * pp, nullptr, xnorm, ctl, true,
+                    false, nullptr);
   prof_end(ctx, PROF_TUBE_FWD);
   if (e != hipSuccess) return e;
   // later kernels read the recorded scalars from the state
@@ -673,8 +678,12 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   // step 3: inverse transform (L^{-1}, or L^T for the adjoint) with the epilogue
   const int go = adjoint ? 3 : 1;
   prof_begin(ctx, PROF_TUBE_INV);
-  e = launch_tube(ctx, s, vdt, vdt, p, rout * sc, op->ch, Y, Gd + go * pp, Gf + go * pp, src, nullptr, later, false,
-                  true, nblocks_out);
+  if (op->fast)
+    e = launch_tube_fast_ctl(ctx, s, op->tube, adjoint ? DCTK_MAT_LT : DCTK_MAT_LINV, vdt, vdt, p, rout * sc, op->ch,
+                             Y, src, nullptr, later, false, true, nblocks_out);
+  else
+    e = launch_tube(ctx, s, vdt, vdt, p, rout * sc, op->ch, Y, Gd + go * pp, Gf + go * pp, src, nullptr, later, false,
+                    true, nblocks_out);
   prof_end(ctx, PROF_TUBE_INV);
   return e;
 }

@@ -22,6 +22,7 @@ constexpr int kShCtl = 2 * (kThreads / 64 + 1);  // LDS doubles of the prologue 
 constexpr int kMaxTube = 64;           // largest n3 (the p x p transform matrix sits in LDS)
 constexpr int kMaxTubeModes = 6;       // tube modes of an order-N operator (N <= 8)
 constexpr int kFusedMaxP = 8;          // n3 up to which a c-product is one fused kernel
+constexpr int kFastOpMaxP = 2048;      // longest tube of an operator (the fast transform's FP64 limit)
 constexpr double kBreakFactor = 64.0;  // breakdown: new norm <= 64 eps * running max
 
 typedef unsigned short bf16_t;         // storage of bfloat16 (bit pattern)
@@ -591,8 +592,9 @@ struct dctk_op_s {
   void* Ah;       // p*n1*n2, gemm dtype
   void* AhT;      // p*n2*n1: slices of Ah transposed (16-bit gemm dtype, fused products), else null
   void* Bh;       // p*s*s, gemm dtype (two-sided)
-  double* Gd;     // 4 matrices p*p (L, L^-1, L^-T, L^T), FP64
+  double* Gd;     // 4 matrices p*p (L, L^-1, L^-T, L^T), FP64 (null for a fast operator)
   float* Gf;      // same in FP32
+  int fast;       // 1: tubes longer than kMaxTube, transformed in O(p log p) (power-of-two p)
   void* xh;       // transformed operand, gemm dtype, p*max(n1,n2)*s
   void* th;       // two-sided intermediate, gemm dtype, p*max(n1,n2)*s
   void* ch;       // slice products, accumulator dtype, p*max(n1,n2)*s
