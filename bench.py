@@ -20,13 +20,15 @@ Printed JSON line (rank 0):
   mixed_bf16   the same solve with BF16 slice GEMMs (FP32 accumulation), gated
                the same way
 
-Other workloads: --workload colour256 | video256 | batch64 | paper | longtube.
+Other workloads: --workload colour256 | video256 | video4 | batch64 | paper | longtube |
+longsolve | learned512.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hyper512]
                        [--gemm f32|bf16|f16] [--no-cpu-baseline] [--copy-calib-mib M]
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -106,7 +108,7 @@ def parse():
                          "norm of the added noise, or LSQR stopped at the L-curve corner")
     ap.add_argument("--workload", default="hyper512",
                     choices=["hyper512", "colour256", "batch64", "video256", "paper", "longtube", "learned512",
-                             "video4"],
+                             "video4", "longsolve"],
                     help="hyper512: one 512x512x64 solve per step (default); colour256: one 256x256x3 "
                          "solve per step; batch64: the uneven 64-instance batch per step (merged launches, "
                          "HIP graph)")
@@ -125,9 +127,9 @@ def parse():
                     help="learned512: 512x512x64 problems solved (each gated on its own FP64 oracle solve)")
     a = ap.parse_args()
     if a.steps is None:
-        a.steps = 20 if a.workload == "hyper512" else 50
+        a.steps = 20 if a.workload in ("hyper512", "longsolve") else 50
     if a.warmup is None:
-        a.warmup = 3 if a.workload == "hyper512" else 5
+        a.warmup = 3 if a.workload in ("hyper512", "longsolve") else 5
     return a
 
 
@@ -192,7 +194,7 @@ def main():
         sys.exit(1)
     if args.workload == "batch64":
         return bench_batch(args)
-    if args.workload in ("hyper512", "video4"):
+    if args.workload in ("hyper512", "video4", "longsolve"):
         return bench_hyper(args)
     if args.workload == "learned512":
         return bench_learned512(args)
@@ -887,14 +889,18 @@ def plain_fp32_loop(ctx, insts, k, opts, args):
 #             FP32 slice products (4 N): 2 n1 n2 s p flops
 #   tube_inv  reads the slice products and the epilogue's src, writes the output:
 #             12 N bytes, 2 p N flops
-def kernel_work(kind, p, n1, n2, s, bg):
+def kernel_work(kind, p, n1, n2, s, bg, fast=False):
+    """(flops, algorithmic bytes) of one launch.  Transforms: 2p flops per
+    element as a dense p x p product, about 5 log2(p) with the O(p log p)
+    transform of long tubes (one complex FFT of length p per tube pair)."""
     N = p * n2 * s
+    tf = 5.0 * math.log2(p) * N if fast else 2.0 * p * N
     if kind == "gemm":
         return 2.0 * n1 * n2 * s * p, p * n1 * n2 * bg + N * (bg + 4)
     if kind == "tube_fwd":
-        return 2.0 * p * N, N * (8 + bg)
+        return tf, N * (8 + bg)
     if kind == "tube_inv":
-        return 2.0 * p * N, 12.0 * N
+        return tf, 12.0 * N
     raise ValueError(kind)
 
 
@@ -931,7 +937,14 @@ def bench_hyper(args):
     import workloads as W
     dev = torch.device("cuda:0")
     order4 = args.workload == "video4"
-    w = W.colour_video(0) if order4 else W.hyperspectral(0)
+    longsolve = args.workload == "longsolve"
+    if order4:
+        w = W.colour_video(0)
+    elif longsolve:
+        w = W.hyperspectral(0, n=256, p=256)
+    else:
+        w = W.hyperspectral(0)
+    shape_name = "128x128x3x16" if order4 else ("256x256x256" if longsolve else "512x512x64")
     n, s = w["X_true"].shape[-2:]
     p = int(np.prod(w["X_true"].shape[:-2]))
     k = w["iters"]
@@ -989,15 +1002,16 @@ def bench_hyper(args):
     for kind in ("tube_fwd", "gemm", "tube_inv"):
         tot, cnt = prof[kind]
         if cnt:
-            f, b = kernel_work(kind, p, n, n, s, bg)
+            f, b = kernel_work(kind, p, n, n, s, bg, fast=longsolve)
             kinds[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, gemm,
-                                         None if order4 else hyper_traffic(kind, gemm))
+                                         None if (order4 or longsolve) else hyper_traffic(kind, gemm))
             kinds[kind].update({"launches": cnt, "ms_total": tot})
     dom = max(kinds, key=lambda k_: kinds[k_]["ms_total"])
     roof = dict(kinds[dom])
+    how = "O(p log p)" if longsolve else "MFMA"
     roof["kernel"] = {"gemm": "slice GEMM batch (p MFMA GEMMs of n1 x n2 by n2 x s)",
-                      "tube_fwd": "forward tube transform (MFMA, with the normalised copy)",
-                      "tube_inv": "inverse tube transform (MFMA, with the epilogue)"}[dom]
+                      "tube_fwd": "forward tube transform (%s, with the normalised copy)" % how,
+                      "tube_inv": "inverse tube transform (%s, with the epilogue)" % how}[dom]
     roof["per_kind"] = kinds
 
     mixed = None
@@ -1007,9 +1021,9 @@ def bench_hyper(args):
         for kind in ("tube_fwd", "gemm", "tube_inv"):
             tot, cnt = prof_b[kind]
             if cnt:
-                f, b = kernel_work(kind, p, n, n, s, 2)
+                f, b = kernel_work(kind, p, n, n, s, 2, fast=longsolve)
                 kb[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, "bf16",
-                                          None if order4 else hyper_traffic(kind, "bf16"))
+                                          None if (order4 or longsolve) else hyper_traffic(kind, "bf16"))
                 kb[kind].update({"launches": cnt, "ms_total": tot})
         mixed = {"solves_per_s": 1e3 / ms_b, "ms_per_step": ms_b, "relerr_gpu": err_b, "lambda": info_b.lam,
                  "per_kind": kb}
@@ -1053,8 +1067,7 @@ def bench_hyper(args):
     if not args.no_cpu_baseline:
         cpu = {"value": 1.0 / dt, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
                "sample": "one full FP64 DC-GK solve of the same %s problem (operator set-up, C, 40 GKB "
-                         "steps, GCV, combine) in %.1f s (numpy, BLAS matmul)"
-                         % ("128x128x3x16" if order4 else "512x512x64", dt)}
+                         "steps, GCV, combine) in %.1f s (numpy, BLAS matmul)" % (shape_name, dt)}
     gate = err_gpu <= 1.05 * err_oracle
     if mixed is not None:
         mixed["ratio_vs_oracle"] = mixed["relerr_gpu"] / err_oracle
@@ -1069,8 +1082,9 @@ def bench_hyper(args):
         "config": {"workload": ("order-4 colour video deblur 128x128 x 3 colours x 16 frames (colour tube "
                                 "(0.7, 0.15, 0.15) on mode 3, temporal half-kernel on mode 4, Gaussian blur "
                                 "sigma 2), DC-GK 40 GKB steps + FP64 GCV, one solve per step" if order4 else
-                                "hyperspectral-like deblur 512x512x64, band-dependent blur sigma 1.5-4, "
-                                "DC-GK 40 GKB steps + FP64 GCV, one solve per step"),
+                                "hyperspectral-like deblur %s, band-dependent blur sigma 1.5-4, "
+                                "DC-GK 40 GKB steps + FP64 GCV, one solve per step%s"
+                                % (shape_name, ", O(p log p) tube transforms" if longsolve else "")),
                    "n1": n, "n2": n, "s": s, "n3": p, "tube_dims": list(reversed(w["X_true"].shape[:-2])),
                    "gkb_steps": k, "gemm_dtype": gemm,
                    "vector_dtype": "f32", "reorth": "none", "tube": "th", "nu": w["nu"]},
