@@ -287,7 +287,11 @@ int dctk_krylov_read(dctk_ctx ctx, dctk_krylov ws, double* alpha, double* beta_o
 /* Device pointer to basis vector j (0-based) of basis `which`
  * (0 = U for GKB / V for Arnoldi, 1 = V for GKB), or to the LSQR iterate X
  * (which = 2) and search direction W (which = 3) -- formed by dctk_gkb_step
- * and by solves with lambda == 0 only.  Owned by the workspace. */
+ * and by solves with lambda == 0 only.  Owned by the workspace.  A Tikhonov
+ * solve without reorthogonalisation (lambda != 0) writes no normalised copy
+ * of its intermediate basis vectors: after k steps, GKB slots 1..k-1 hold
+ * beta_{j+1} U_{j+1} and alpha_{j+1} V_{j+1} (the recorded alpha, beta of
+ * dctk_krylov_read); slots 0 and k hold the normalised vectors. */
 int dctk_krylov_basis(dctk_krylov ws, int which, int j, void** ptr);
 
 /* Enqueues a copy of the vector named by (which, j) as in dctk_krylov_basis

@@ -689,6 +689,13 @@ static Ctl make_ctl(int kind, int j, KState* st, const double* part_in, int npar
   return c;
 }
 
+// Slots [lo, hi) of the basis bit mask.
+static unsigned long long slot_bits(int lo, int hi) {
+  unsigned long long m = 0;
+  for (int i = lo; i < hi && i < 64; ++i) m |= 1ull << i;
+  return m;
+}
+
 // Classical Gram-Schmidt applied twice: w -= B (B^T w), with B the first nb slots of `basis`.
 // When hcol is given the coefficients are also added to it (Arnoldi column).
 static hipError_t cgs2(dctk_ctx ctx, dctk_krylov ws, void* basis, int nb, void* w, int64_t n, Gate g,
@@ -715,6 +722,7 @@ static hipError_t gkb_init_impl(dctk_ctx ctx, dctk_krylov ws, const void* C, voi
   const int vdt = op->vec_dtype;
   const int64_t nU = op->p * op->n1 * op->s, nV = op->p * op->n2 * op->s;
   hipError_t e;
+  ws->vmask = 0;
   rec_phase(ctx);
   if ((e = launch_state_reset(ctx, st, 1, tol)) != hipSuccess) return e;
   int npA = 0, npB = 0;
@@ -746,6 +754,7 @@ static hipError_t gkb_step_impl(dctk_ctx ctx, dctk_krylov ws, int j, void* X) {
   void* T = ws->T;
   hipError_t e;
   int npA = 0, npB = 0;
+  ws->vmask &= ~slot_bits(j, j + 1);  // this step writes U_{j+1} and V_{j+1} normalised
   const bool ru = ws->reorth == DCTK_REORTH_FULL;
   const bool rv = ws->reorth != DCTK_REORTH_NONE;
   const Ctl c1 = make_ctl(CTL_GKB_FWD, j, st, nullptr, 0, ru ? nullptr : ws->partA);
@@ -773,12 +782,19 @@ static hipError_t gkb_step_impl(dctk_ctx ctx, dctk_krylov ws, int j, void* X) {
 // no reorthogonalisation.
 static bool merged_steps(dctk_krylov ws) { return ws->reorth == DCTK_REORTH_NONE; }
 
-// Step j of a Tikhonov solve (no LSQR iterate) with the update folded in:
-//   K1: unless j is the first step after an update that was flushed (pending =
-//       false), alpha_j and the rotation of step j-1 from the partials of V~,
-//       V_j = V~/alpha_j written while staged; T = M(V_j) - alpha_j U_j
-//   K2: beta_{j+1}; U_{j+1} = T/beta_{j+1}; V~ = M*(U_{j+1}) - beta_{j+1} V_j
-//       into the second T slot, with its partials.
+// Step j of a Tikhonov solve (no LSQR iterate) with the update folded in.  The
+// new basis vectors stay in their slots unnormalised, as the products leave
+// them (U slot j: beta_{j+1} U_{j+1}, V slot j: alpha_{j+1} V_{j+1}): the
+// product that reads one scales it as it is staged, the epilogue that uses one
+// as src divides its coefficient by the normaliser, and the combine divides
+// y_j -- so no normalised copy is written.  The first step of a run (pending =
+// false) reads the slots the initialisation or the previous run's flush
+// normalised.
+//   K1: unless pending = false, alpha_j and the rotation of step j-1 from the
+//       partials of alpha_j V_j; T = M(V_j) - alpha_j U_j into U slot j, with
+//       its partials
+//   K2: beta_{j+1}; V~ = M*(U_{j+1}) - beta_{j+1} V_j into V slot j, with its
+//       partials.
 // The update of the last step is flushed by gkb_flush_update.
 static hipError_t gkb_step_merged(dctk_ctx ctx, dctk_krylov ws, int j, bool pending) {
   dctk_op op = ws->op;
@@ -786,29 +802,29 @@ static hipError_t gkb_step_merged(dctk_ctx ctx, dctk_krylov ws, int j, bool pend
   void* Uj = slot(ws->U, ws, j - 1);
   void* Un = slot(ws->U, ws, j);
   void* Vj = slot(ws->V, ws, j - 1);
-  void* T0 = slot(ws->T, ws, 0);
-  void* T1 = slot(ws->T, ws, 1);
+  void* Vn = slot(ws->V, ws, j);
   hipError_t e;
   int npA = 0, npB = 0;
-  const Ctl c1 = pending ? make_ctl(CTL_GKB_FWDU, j, st, ws->partB, ws->last_npart, ws->partA)
-                         : make_ctl(CTL_GKB_FWD, j, st, nullptr, 0, ws->partA);
+  Ctl c1 = pending ? make_ctl(CTL_GKB_FWDU, j, st, ws->partB, ws->last_npart, ws->partA)
+                   : make_ctl(CTL_GKB_FWD, j, st, nullptr, 0, ws->partA);
+  c1.src_div = pending ? 1 : 0;
   rec_phase(ctx);
-  if ((e = apply_op(op, ctx->stream, 0, pending ? T1 : Vj, T0, Uj, pending ? Vj : nullptr, c1, &npA)) != hipSuccess)
-    return e;
-  const Ctl c2 = make_ctl(CTL_GKB_ADJ, j, st, ws->partA, npA, ws->partB);
+  if ((e = apply_op(op, ctx->stream, 0, Vj, Un, Uj, nullptr, c1, &npA)) != hipSuccess) return e;
+  Ctl c2 = make_ctl(CTL_GKB_ADJ, j, st, ws->partA, npA, ws->partB);
+  c2.src_div = pending ? 1 : 0;
   rec_phase(ctx);
-  if ((e = apply_op(op, ctx->stream, 1, T0, T1, Vj, Un, c2, &npB)) != hipSuccess) return e;
+  if ((e = apply_op(op, ctx->stream, 1, Un, Vn, Vj, nullptr, c2, &npB)) != hipSuccess) return e;
   ws->last_npart = npB;
   return hipSuccess;
 }
 
 // The LSQR update of step j left pending by gkb_step_merged: alpha_{j+1}, the
-// rotation, V_{j+1} = V~/alpha_{j+1}.
+// rotation, V_{j+1} and U_{j+1} normalised in their slots.
 static hipError_t gkb_flush_update(dctk_ctx ctx, dctk_krylov ws, int j) {
   dctk_op op = ws->op;
   rec_phase(ctx);
-  return launch_gkb_update(ctx, op->vec_dtype, op->p * op->n2 * op->s, nullptr, nullptr, slot(ws->T, ws, 1),
-                           slot(ws->V, ws, j), ws->partB, ws->last_npart, ws->st, j);
+  return launch_gkb_update(ctx, op->vec_dtype, op->p * op->n2 * op->s, nullptr, nullptr, nullptr,
+                           slot(ws->V, ws, j), ws->partB, ws->last_npart, ws->st, j, slot(ws->U, ws, j));
 }
 
 // Steps from..to of a Tikhonov solve, with the update of step to flushed.
@@ -817,7 +833,10 @@ static hipError_t gkb_steps_tik(dctk_ctx ctx, dctk_krylov ws, int from, int to) 
   if (merged_steps(ws)) {
     for (int j = from; j <= to; ++j)
       if ((e = gkb_step_merged(ctx, ws, j, j > from)) != hipSuccess) return e;
-    return to >= from ? gkb_flush_update(ctx, ws, to) : hipSuccess;
+    if (to < from) return hipSuccess;
+    // slots from..to-1 keep their vectors unnormalised; the flush normalises slot to
+    ws->vmask = (ws->vmask | slot_bits(from, to)) & ~slot_bits(to, to + 1);
+    return gkb_flush_update(ctx, ws, to);
   }
   for (int j = from; j <= to; ++j)
     if ((e = gkb_step_impl(ctx, ws, j, nullptr)) != hipSuccess) return e;
@@ -851,7 +870,7 @@ hipError_t lsqr_enqueue(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X, co
     if (e != hipSuccess) return e;
     rec_phase(ctx);
     if ((e = launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, opts->k_max,
-                            &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0})) != hipSuccess)
+                            &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}, ws->vmask, ws->st->alpha)) != hipSuccess)
       return e;
   }
   return hipSuccess;
@@ -941,7 +960,7 @@ hipError_t learned_enqueue(dctk_ctx ctx, dctk_krylov ws, dctk_mlp m, const void*
   if ((e = launch_projected(ctx, ws->st, 1, opts->gcv_mode, -1.0, 0, -1.0, gate, 1)) != hipSuccess) return e;
   rec_phase(ctx);
   return launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, opts->k_max,
-                        &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0});
+                        &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}, ws->vmask, ws->st->alpha);
 }
 
 // alpha_1.. and beta_1.. of the recorded process into the caller's host arrays
@@ -1144,7 +1163,7 @@ int dctk_lsqr_lcurve_solve(dctk_ctx ctx, dctk_krylov ws, const void* C, void* X,
   ws->initialised = 1;
   DCTK_HIP(ctx, launch_lcurve(ctx, ws->st));
   DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, opts->k_max,
-                               &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
+                               &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}, ws->vmask, ws->st->alpha));
   static thread_local KState hk;
   if ((r = read_state_lsqr(ctx, ws, &hk))) return r;
   if (info) {
@@ -1179,7 +1198,7 @@ int dctk_krylov_project(dctk_ctx ctx, dctk_krylov ws, int k, const dctk_solve_op
     DCTK_HIP(ctx, launch_projected(ctx, ws->st, 1, opts->gcv_mode, opts->lambda < 0.0 ? -1.0 : opts->lambda, k));
   // the basis vectors beyond a breakdown are never formed: combine min(k, steps) of them
   DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, k,
-                               &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
+                               &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}, ws->vmask, ws->st->alpha));
   static thread_local KState hk;
   if ((r = read_state_lsqr(ctx, ws, &hk))) return r;
   if (info) {
@@ -1222,7 +1241,7 @@ int dctk_lsqr_learned_solve(dctk_ctx ctx, dctk_krylov ws, dctk_mlp mlp, const vo
   ws->initialised = 1;
   DCTK_HIP(ctx, launch_projected(ctx, ws->st, 1, opts->gcv_mode, -1.0, 0, valid ? (double)pred[2] : -1.0, gate));
   DCTK_HIP(ctx, launch_combine(ctx, op->vec_dtype, op->p * op->n2 * op->s, X, nullptr, ws->V, ws->nvec, kstop,
-                               &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}));
+                               &ws->st->steps, ws->st->y, Gate{nullptr, 0, 0}, ws->vmask, ws->st->alpha));
   double gate_ok = 0.0;
   DCTK_HIP(ctx, hipMemcpyAsync(&gate_ok, &ws->st->gate_ok, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   if (pred_k) *pred_k = valid ? kstop : -1;

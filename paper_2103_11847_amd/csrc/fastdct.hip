@@ -221,11 +221,6 @@ __device__ __forceinline__ void tube_fast_body(const FastArgs& a, const VBlock v
   for (; tile < ntiles; tile = tile_of(++n)) {
     const int64_t e0 = tile * nb;
     const bool live = e0 + jt < count;
-    if constexpr (EPI) {
-      const T* s0 = sp + (int64_t)t0 * count + (live ? e0 + jt : count - 1);
-#pragma unroll
-      for (int u = 0; u < U; ++u) sv[u] = s0[u * rstride];
-    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const T v = live ? (SCALE ? sc * pf[u] : pf[u]) : (T)0;
@@ -359,6 +354,14 @@ __device__ __forceinline__ void tube_fast_body(const FastArgs& a, const VBlock v
         if (live) dst[u * rstride] = cvt<TO, T>(f * rq[u]);
       }
     } else {
+      // the epilogue's src rows, in flight while the output is reordered (and
+      // scanned): loaded here rather than with the input, where they would
+      // hold registers through the FFT
+      if constexpr (EPI) {
+        const T* s0 = sp + (int64_t)t0 * count + (live ? e0 + jt : count - 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) sv[u] = s0[u * rstride];
+      }
       // y_t = v_n / p with n the reordered index of t
       const T inv_p = (T)1 / (T)p;
 #pragma unroll

@@ -94,6 +94,11 @@ struct Ctl {
   int j;                  // 1-based step (0: initialisation)
   int from_state;         // 1: scalars already recorded in st (later kernels of an unfused product)
   int npart_in;
+  // GKB products: src holds its basis vector unnormalised (beta_j U_j for the
+  // forward product, alpha_j V_j for the adjoint), so the epilogue's b is
+  // divided by that recorded normaliser
+  int src_div;
+  int pad_;
   KState* st;
   const double* part_in;  // partials consumed (sums of squares)
   double* part_out;       // per-block sum of squares of the output (nullptr: none)
@@ -356,11 +361,12 @@ __device__ inline GkbUpd gkb_update_scalars(KState* st, int j, double ps, double
 struct CtlLoad {
   double ps, pm, rec;
   double bn, rb, pb, tol;  // the LSQR update (CTL_GKB_FWDU): beta_j, rhobar_{j-1}, phibar_{j-1}, tol
+  double an;               // alpha_j (the normaliser of an unnormalised V_j source)
   int ss, kl, halt, sk;
 };
 
 __device__ inline CtlLoad ctl_load(const Ctl& c) {
-  CtlLoad L{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1, 0, 0, 0};
+  CtlLoad L{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1, 0, 0, 0};
   if (c.kind == CTL_PLAIN) {
     if (c.st != nullptr) L.halt = ld_state(&c.st->halt);
     return L;
@@ -400,6 +406,7 @@ __device__ inline CtlLoad ctl_load(const Ctl& c) {
   // the recorded scalars of the LSQR update of step j - 1
   const int jp = j > 0 ? j - 1 : 0, jq = j > 1 ? j - 2 : 0;
   L.bn = sd[oB + jp];
+  L.an = sd[oA + jp];
   L.rb = sd[oRB + jq];
   L.pb = sd[oPB + jq];
   L.tol = sd[oTol];
@@ -431,7 +438,7 @@ __device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, doubl
   // The loaded values are taken into registers here, in one wait: without
   // this use the compiler may sink each load into the branch that needs it,
   // where it would be waited for on its own.
-  asm volatile("" ::"v"(L.ps), "v"(L.pm), "v"(L.rec), "v"(L.ss), "v"(L.kl), "v"(L.halt));
+  asm volatile("" ::"v"(L.ps), "v"(L.pm), "v"(L.rec), "v"(L.bn), "v"(L.an), "v"(L.ss), "v"(L.kl), "v"(L.halt));
   KState* st = c.st;
   const int j = c.j;
   const bool sums = !c.from_state && (c.kind == CTL_GKB_INIT || c.kind == CTL_GKB_ADJ || c.kind == CTL_GKB_FWDU ||
@@ -441,6 +448,8 @@ __device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, doubl
   const int ss = L.ss, kl = L.kl, halt = L.halt;
   const bool beyond = kl > 0 && j > kl;  // beyond a learned step limit
   const bool first = vb.x == 0 && vb.y == 0 && vb.z == 0 && threadIdx.x == 0;
+  // an unnormalised source: beta_j U_j (forward kinds) or alpha_j V_j (adjoint)
+  const double fdiv = c.src_div ? L.bn : 1.0, adiv = c.src_div ? L.an : 1.0;
   const double eps = 2.220446049250313e-16;
   switch (c.kind) {
     case CTL_GKB_INIT: {
@@ -466,7 +475,7 @@ __device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, doubl
     }
     case CTL_GKB_FWD: {
       if (ss >= 0 || beyond) return false;  // stopped at an earlier step
-      b = -rec;
+      b = -rec / fdiv;
       return true;
     }
     case CTL_GKB_ADJ: {
@@ -474,7 +483,7 @@ __device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, doubl
       if (c.from_state) {
         if (ss == j) return false;
         sin = 1.0 / rec;
-        b = -rec;
+        b = -rec / adiv;
         return true;
       }
       block_sum_max_all(ps, pm, sh);
@@ -493,13 +502,13 @@ __device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, doubl
       }
       if (brk) return false;
       sin = 1.0 / bt;
-      b = -bt;
+      b = -bt / adiv;
       return true;
     }
     case CTL_GKB_FWDU: {
       if (c.from_state) {  // later kernels of an unfused product: as CTL_GKB_FWD
         if (ss >= 0 || beyond) return false;
-        b = -rec;
+        b = -rec / fdiv;
         return true;
       }
       const int jp = j - 1;  // the pending update
@@ -507,7 +516,7 @@ __device__ inline bool ctl_eval(const Ctl& c, const CtlLoad& L, double& a, doubl
       const GkbUpd u = gkb_update_scalars(st, jp, ps, pm, L.bn, L.rb, L.pb, L.tol, ss, L.sk, sh, first);
       if (!u.have_v) return false;
       sin = 1.0 / u.alpha;
-      b = -u.alpha;
+      b = -u.alpha / fdiv;
       return true;
     }
     case CTL_ARN_FWD: {
@@ -607,6 +616,9 @@ struct dctk_krylov_s {
   int initialised;
   int host_steps;          // steps enqueued since init
   int last_npart;          // partials produced by the last enqueued norm (feeds the next step)
+  // bit i set: V slot i holds alpha_{i+1} V_{i+1} (and U slot i beta_{i+1} U_{i+1}) unnormalised, as the
+  // Tikhonov steps leave them; the combine divides y_i by alpha_{i+1}
+  unsigned long long vmask;
   int64_t nvec;            // slot stride in elements (>= p*max(n1,n2)*s, 64-aligned)
   size_t vbytes;           // bytes of one slot
   void* U;                 // (k_max+1) slots (GKB U / Arnoldi V)
@@ -759,9 +771,11 @@ hipError_t launch_coef_finalize(dctk_ctx ctx, const double* part, int nblocks, i
 // w -= sum_i coef[i] basis_i
 hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const void* basis, int64_t stride,
                            int nb, const double* coef, Gate g);
-// out = (x0 ? x0 : 0) + sum_{i < min(nb, *nptr)} y[i] basis_i
+// out = (x0 ? x0 : 0) + sum_{i < min(nb, *nptr)} c_i basis_i with c_i = y[i], or y[i] / div[i] where bit i
+// of `mask` is set (a basis vector stored unnormalised)
 hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x0, const void* basis,
-                          int64_t stride, int nb, const int* nptr, const double* y, Gate g);
+                          int64_t stride, int nb, const int* nptr, const double* y, Gate g,
+                          unsigned long long mask = 0, const double* div = nullptr);
 // GMRES cycle start: beta = sqrt(sum part) -> st->beta0 (halt on 0); out = in / beta
 hipError_t launch_arn_start(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* in, const double* part,
                             int npart, KState* st);
@@ -777,8 +791,9 @@ hipError_t launch_gmres_res(dctk_ctx ctx, const double* part, int npart, KState*
 // GKB start (Algorithm 6 step 2) and the per-step update (Algorithm 6 (c)-(g))
 hipError_t launch_gkb_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, void* V1, const double* part,
                             int npart, KState* st);
+// (U, if given: beta_{j+1} U_{j+1} normalised in place by the recorded beta_{j+1})
 hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, const void* Vin, void* Vn,
-                             const double* part, int npart, KState* st, int j);
+                             const double* part, int npart, KState* st, int j, void* U = nullptr);
 hipError_t launch_state_reset(dctk_ctx ctx, KState* st, int full, double tol);
 hipError_t launch_cast(dctk_ctx ctx, int64_t n, const double* in, int out_dtype, void* out);
 // Transposing cast of p slices rows x cols (FP64) to cols x rows (16-bit types).

@@ -82,6 +82,7 @@ struct GkbArgs {  // start and per-step update of Algorithm 6
   void* W;          // LSQR search direction (null with X)
   void* V;          // the new basis vector (written)
   const void* Vin;  // its unnormalised input (update; null: V itself)
+  void* U;          // update: beta_{j+1} U_{j+1}, normalised in place (null: none)
   const double* part;
   int npart;
   int j;
@@ -99,6 +100,8 @@ struct CombineArgs {
   const int* nptr;
   const double* y;
   Gate g;
+  unsigned long long mask;  // bit i: basis_i stored unnormalised, coefficient y[i] / div[i]
+  const double* div;
 };
 struct GramArgs {  // reorthogonalisation passes: multi-dot, coefficient sums, subtraction
   int gx, gy, gz;
@@ -300,7 +303,8 @@ __device__ __forceinline__ void k_combine_body(const CombineArgs& a, const VBloc
   int cnt = a.nptr ? a.nptr[0] : nb;
   if (cnt > nb) cnt = nb;
   if (cnt < 0) cnt = 0;
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) sy[i] = y[i];
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+    sy[i] = (i < 64 && ((a.mask >> i) & 1ull)) ? y[i] / a.div[i] : y[i];
   __syncthreads();
   if (vec) {
     // 16-byte rows (n a multiple of 4): eight basis rows in flight per thread,
@@ -445,8 +449,18 @@ __device__ __forceinline__ void k_gkb_update_body(const GkbArgs& a, const VBlock
   const double cx = u.cx, cw = u.cw;
   const bool have_v = u.have_v;
   const double ia = have_v ? 1.0 / u.alpha : 0.0;
+  T* Un = (T*)a.U;
+  // U_{j+1} exists unless beta_{j+1} broke down (then it is never used)
+  const bool have_u = Un != nullptr && !(ss == j && skind == STOP_BETA) && bnext > 0.0;
+  const double ib = have_u ? 1.0 / bnext : 0.0;
   DCTK_VGRID_LOOP(e, n, vb, a.gx) {
     double xv[4], wv[4], vv[4];
+    if (have_u) {
+      double uv[4];
+      ld4(Un, e, n, vec, uv);
+      for (int q = 0; q < 4; ++q) uv[q] = (double)(T)(uv[q] * ib);
+      st4(Un, e, n, vec, uv);
+    }
     if (X) {
       ld4(X, e, n, vec, xv);
       ld4(W, e, n, vec, wv);
@@ -712,9 +726,12 @@ hipError_t launch_subtract(dctk_ctx ctx, int dtype, int64_t n, void* w, const vo
 }
 
 hipError_t launch_combine(dctk_ctx ctx, int dtype, int64_t n, void* out, const void* x0, const void* basis,
-                          int64_t stride, int nb, const int* nptr, const double* y, Gate g) {
+                          int64_t stride, int nb, const int* nptr, const double* y, Gate g,
+                          unsigned long long mask, const double* div) {
   const unsigned grid = grid_for(n);
   CombineArgs a{};
+  a.mask = div != nullptr ? mask : 0ull;
+  a.div = div;
   a.vec = (n % 4 == 0) && (stride % 4 == 0) && al(out) && al(x0) && al(basis);
   a.n = n;
   a.out = out;
@@ -796,10 +813,11 @@ hipError_t launch_gkb_start(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W
 }
 
 hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* W, const void* Vin, void* Vn,
-                             const double* part, int npart, KState* st, int j) {
+                             const double* part, int npart, KState* st, int j, void* U) {
   const unsigned grid = grid_for(n);
   GkbArgs a{};
-  a.vec = (n % 4 == 0) && al(X) && al(W) && al(Vn) && al(Vin);
+  a.vec = (n % 4 == 0) && al(X) && al(W) && al(Vn) && al(Vin) && al(U);
+  a.U = U;
   a.n = n;
   a.X = X;
   a.W = W;
