@@ -306,10 +306,9 @@ def main():
     bg = 4 if args.gemm == "f32" else 2
     N = p * n * s
     # algorithmic bytes of one launch inside a GKB step: A~ once, the input, the epilogue's
-    # src (alpha U_j or beta V_j), the output, and the normalised input written while it
-    # is staged (the adjoint: U_{j+1} = U~/beta; the forward, which carries the previous
-    # step's LSQR update: V_j = V~/alpha, in all but the first step)
-    nvec_io = {"fused_fwd": 4, "fused_adj": 4, "gemm": 2}[kind]
+    # src (the previous basis vector) and the output -- the Tikhonov steps keep their basis
+    # vectors unnormalised, so no normalised copy of the input is written
+    nvec_io = {"fused_fwd": 3, "fused_adj": 3, "gemm": 2}[kind]
     kbytes = p * n * n * bg + nvec_io * N * 4
     peak_f = MFMA_PEAK_TFLOPS[args.gemm]
     ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
@@ -481,7 +480,7 @@ def bench_paper(args):
     bg = {"f32": 4, "bf16": 2, "f16": 2}[args.gemm]
     n, p = 1024, 3
     kinds = {}
-    for kind in ("tube_fwd", "gemm", "tube_inv"):
+    for kind in ("tube_fwd", "gemm", "tube_inv", "tube_pair"):
         tot, cnt = prof_gk[kind]
         if cnt:
             f, b = kernel_work(kind, p, n, n, n, bg)
@@ -898,9 +897,14 @@ def kernel_work(kind, p, n1, n2, s, bg, fast=False):
     if kind == "gemm":
         return 2.0 * n1 * n2 * s * p, p * n1 * n2 * bg + N * (bg + 4)
     if kind == "tube_fwd":
-        return tf, N * (8 + bg)
+        # input read, X~ written in the GEMM type (the Tikhonov steps write no normalised copy)
+        return tf, N * (4 + bg)
     if kind == "tube_inv":
         return tf, 12.0 * N
+    if kind == "tube_pair":
+        # the slice products and src read, the new basis vector written, and the
+        # next product's transformed input written in the GEMM type; two transforms
+        return 2.0 * tf, N * (12 + bg)
     raise ValueError(kind)
 
 
@@ -999,7 +1003,7 @@ def bench_hyper(args):
     ms, ms_prof, prof, err_gpu, info = run(gemm, args.steps, args.warmup)
     bg = {"f32": 4, "bf16": 2, "f16": 2}[gemm]
     kinds = {}
-    for kind in ("tube_fwd", "gemm", "tube_inv"):
+    for kind in ("tube_fwd", "gemm", "tube_inv", "tube_pair"):
         tot, cnt = prof[kind]
         if cnt:
             f, b = kernel_work(kind, p, n, n, s, bg, fast=longsolve)
@@ -1010,15 +1014,17 @@ def bench_hyper(args):
     roof = dict(kinds[dom])
     how = "O(p log p)" if longsolve else "MFMA"
     roof["kernel"] = {"gemm": "slice GEMM batch (p MFMA GEMMs of n1 x n2 by n2 x s)",
-                      "tube_fwd": "forward tube transform (%s, with the normalised copy)" % how,
-                      "tube_inv": "inverse tube transform (%s, with the epilogue)" % how}[dom]
+                      "tube_fwd": "forward tube transform (%s, with the input scale)" % how,
+                      "tube_inv": "inverse tube transform (%s, with the epilogue)" % how,
+                      "tube_pair": "inverse tube transform with the epilogue paired with the next product's "
+                                   "forward transform (MFMA)"}[dom]
     roof["per_kind"] = kinds
 
     mixed = None
     if not args.no_mixed and gemm == "f32":
         ms_b, _, prof_b, err_b, info_b = run("bf16", args.steps, 2)
         kb = {}
-        for kind in ("tube_fwd", "gemm", "tube_inv"):
+        for kind in ("tube_fwd", "gemm", "tube_inv", "tube_pair"):
             tot, cnt = prof_b[kind]
             if cnt:
                 f, b = kernel_work(kind, p, n, n, s, 2, fast=longsolve)
@@ -1202,7 +1208,7 @@ def bench_learned512(args):
     dk.dctk_mlp_destroy(mlp)
     p, n = insts[0]["w"]["X_true"].shape[:2]
     kinds = {}
-    for kind in ("tube_fwd", "gemm", "tube_inv"):
+    for kind in ("tube_fwd", "gemm", "tube_inv", "tube_pair"):
         tot, cnt = prof[kind]
         if cnt:
             f, byt = kernel_work(kind, p, n, n, s, 2)

@@ -103,9 +103,12 @@ int dctk_version(void);
  * the launch count to count[DCTK_PROF_KINDS] (either may be NULL).  Kinds:
  * 0 forward tube transform, 1 slice GEMMs of one product, 2 inverse tube
  * transform with epilogue (these three make up an unfused product), 3 one
- * fused forward product M(X), 4 one fused adjoint product M*(Y).
+ * fused forward product M(X), 4 one fused adjoint product M*(Y), 5 an
+ * inverse transform with its epilogue paired with the next product's forward
+ * transform (the Golub-Kahan steps of a Tikhonov solve with three-kernel
+ * products, FP32 vectors, 16 <= p <= 64).
  * Error: DCTK_ESTATE if not profiling. */
-#define DCTK_PROF_KINDS 5
+#define DCTK_PROF_KINDS 6
 int dctk_profile_begin(dctk_ctx ctx);
 int dctk_profile_end(dctk_ctx ctx, double* ms, int* count);
 

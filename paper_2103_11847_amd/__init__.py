@@ -223,7 +223,7 @@ def dctk_last_hip_error(ctx):
     return lib().dctk_last_hip_error(ctx)
 
 
-PROF_KINDS = ("tube_fwd", "gemm", "tube_inv", "fused_fwd", "fused_adj")
+PROF_KINDS = ("tube_fwd", "gemm", "tube_inv", "fused_fwd", "fused_adj", "tube_pair")
 
 
 def dctk_profile_begin(ctx):

@@ -808,10 +808,31 @@ static hipError_t gkb_step_merged(dctk_ctx ctx, dctk_krylov ws, int j, bool pend
   Ctl c1 = pending ? make_ctl(CTL_GKB_FWDU, j, st, ws->partB, ws->last_npart, ws->partA)
                    : make_ctl(CTL_GKB_FWD, j, st, nullptr, 0, ws->partA);
   c1.src_div = pending ? 1 : 0;
+  Ctl c2 = make_ctl(CTL_GKB_ADJ, j, st, ws->partA, 0, ws->partB);
+  c2.src_div = pending ? 1 : 0;
+  if (pair_eligible(op)) {
+    // Three-kernel products with paired transforms: each product's inverse
+    // transform also forms the next product's transformed input (from the
+    // unnormalised vector it has just written), so only the first step of a
+    // run has a forward transform of its own.  A pending update is evaluated
+    // by the first paired kernel of the step, after the forward GEMM (the
+    // GEMM's input is alpha_j V_j transformed; 1/alpha_j joins the epilogue).
+    // (one schedule point per product, as on the other paths, so batches of
+    // mixed paths stay aligned step by step)
+    rec_phase(ctx);
+    if ((e = pending ? pair_gemm(op, ctx->stream, 0, c1) : pair_first(op, ctx->stream, 0, Vj, c1)) != hipSuccess)
+      return e;
+    if ((e = pair_transforms(op, ctx->stream, 0, Uj, Un, c1, &npA)) != hipSuccess) return e;
+    c2.npart_in = npA;
+    rec_phase(ctx);
+    if ((e = pair_gemm(op, ctx->stream, 1, c2)) != hipSuccess) return e;
+    if ((e = pair_transforms(op, ctx->stream, 1, Vj, Vn, c2, &npB)) != hipSuccess) return e;
+    ws->last_npart = npB;
+    return hipSuccess;
+  }
   rec_phase(ctx);
   if ((e = apply_op(op, ctx->stream, 0, Vj, Un, Uj, nullptr, c1, &npA)) != hipSuccess) return e;
-  Ctl c2 = make_ctl(CTL_GKB_ADJ, j, st, ws->partA, npA, ws->partB);
-  c2.src_div = pending ? 1 : 0;
+  c2.npart_in = npA;
   rec_phase(ctx);
   if ((e = apply_op(op, ctx->stream, 1, Un, Vn, Vj, nullptr, c2, &npB)) != hipSuccess) return e;
   ws->last_npart = npB;

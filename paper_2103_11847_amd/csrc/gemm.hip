@@ -615,11 +615,95 @@ bool use_fused(dctk_op op, int adjoint) {
   return t32 < g_num_cus && (op->p <= 4 || M * N * K <= (int64_t)192 * 192 * 192);
 }
 
+// The GEMM's gate under a product's control block: it runs unless the process
+// stopped at an earlier step.
+static Gate gemm_gate(const Ctl& ctl) {
+  Gate g{nullptr, 0, 0};
+  if (ctl.kind != CTL_PLAIN) {
+    g.st = ctl.st;
+    g.j = ctl.kind == CTL_ARN_FWD ? ctl.j - 1 : ctl.j;
+    const bool fwd = ctl.kind == CTL_GKB_FWD || ctl.kind == CTL_GKB_FWDU;
+    g.mode = fwd ? 0 : 1;
+    if (fwd) g.j = ctl.j;
+  }
+  return g;
+}
+
+// Step 2 of a three-kernel product: the slice products of X~ (op->xh) into op->ch.
+static hipError_t slice_gemms(dctk_op op, hipStream_t s, int adjoint, const Gate& g) {
+  dctk_ctx ctx = op->ctx;
+  const int tile = op->tune[adjoint ? 1 : 0][1];
+  const int64_t p = op->p, n1 = op->n1, n2 = op->n2, sc = op->s;
+  const int gdt = op->gemm_dtype;
+  const int64_t rin = adjoint ? n1 : n2;
+  const int64_t rout = adjoint ? n2 : n1;
+  const int64_t sAh = n1 * n2;
+  hipError_t e;
+  prof_begin(ctx, PROF_GEMM);
+  // the left operand: A~ (n1 x n2), or for the adjoint A~^T (n2 x n1) -- read
+  // from the transposed copy when the operator keeps one (16-bit types)
+  const bool tcopy = adjoint && op->AhT != nullptr;
+  const void* Aop = tcopy ? op->AhT : op->Ah;
+  const int64_t ldA = tcopy ? n1 : n2;
+  const int tA = adjoint && !tcopy ? 1 : 0;
+  if (!op->two_sided) {
+    // forward: (n1 x n2)(n2 x s);  adjoint: (n2 x n1 := A~^T)(n1 x s)
+    e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)rin, Aop, ldA, sAh, tA,
+                    op->xh, sc, rin * sc, 0, op->ch, sc, rout * sc, (int)p, g, tile);
+  } else {
+    e = launch_gemm(ctx, s, gdt, 0, (int)rout, (int)sc, (int)rin, Aop, ldA, sAh, tA,
+                    op->xh, sc, rin * sc, 0, op->th, sc, rout * sc, (int)p, g, tile);
+    // right factor: forward (rout x s)(s x s) with B~; adjoint with B~^T
+    if (e == hipSuccess)
+      e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)sc, op->th, sc, rout * sc, 0,
+                      op->Bh, sc, sc * sc, adjoint ? 1 : 0, op->ch, sc, rout * sc, (int)p, g, tile);
+  }
+  prof_end(ctx, PROF_GEMM);
+  return e;
+}
+
+bool pair_eligible(dctk_op op) {
+  return !op->fast && tube_pair_ok(op->p, op->vec_dtype) &&
+         !(fused_eligible(op) && (use_fused(op, 0) || use_fused(op, 1)));
+}
+
+hipError_t pair_first(dctk_op op, hipStream_t s, int adjoint, const void* X, const Ctl& ctl) {
+  dctk_ctx ctx = op->ctx;
+  const int64_t pp = op->p * op->p;
+  const int64_t rin = adjoint ? op->n1 : op->n2;
+  const int gi = adjoint ? 2 : 0;
+  prof_begin(ctx, PROF_TUBE_FWD);
+  hipError_t e = launch_tube(ctx, s, op->vec_dtype, op->gemm_dtype, op->p, rin * op->s, X, op->xh, op->Gd + gi * pp,
+                             op->Gf + gi * pp, nullptr, nullptr, ctl, true, false, nullptr);
+  prof_end(ctx, PROF_TUBE_FWD);
+  if (e != hipSuccess) return e;
+  return slice_gemms(op, s, adjoint, gemm_gate(ctl));
+}
+
+hipError_t pair_gemm(dctk_op op, hipStream_t s, int adjoint, const Ctl& ctl) {
+  return slice_gemms(op, s, adjoint, gemm_gate(ctl));
+}
+
+hipError_t pair_transforms(dctk_op op, hipStream_t s, int adjoint, const void* src, void* Y, const Ctl& ctl,
+                           int* nblocks_out) {
+  dctk_ctx ctx = op->ctx;
+  const int64_t pp = op->p * op->p;
+  const int64_t rout = adjoint ? op->n2 : op->n1;
+  // this product's inverse (L^{-1}, or L^T for the adjoint); the next product's
+  // forward transform (L^{-T} for the adjoint after a forward product, L after an adjoint)
+  const int g1 = adjoint ? 3 : 1, g2 = adjoint ? 0 : 2;
+  prof_begin(ctx, PROF_TUBE_PAIR);
+  hipError_t e = launch_tube_pair(ctx, s, op->gemm_dtype, op->p, rout * op->s, (const float*)op->ch,
+                                  (const float*)src, (float*)Y, op->xh, op->Gf + g1 * pp, op->Gf + g2 * pp, ctl,
+                                  nblocks_out);
+  prof_end(ctx, PROF_TUBE_PAIR);
+  return e;
+}
+
 hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,
                     void* xnorm, const Ctl& ctl, int* nblocks_out) {
   dctk_ctx ctx = op->ctx;
   if (fused_eligible(op) && use_fused(op, adjoint)) return launch_fused(op, s, adjoint, X, Y, src, xnorm, ctl, nblocks_out);
-  const int tile = op->tune[adjoint ? 1 : 0][1];
   const int64_t p = op->p, n1 = op->n1, n2 = op->n2, sc = op->s;
   const int gdt = op->gemm_dtype, vdt = op->vec_dtype;
   const double* Gd = op->Gd;
@@ -644,36 +728,8 @@ hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void*
   // later kernels read the recorded scalars from the state
   Ctl later = ctl;
   later.from_state = 1;
-  Gate g{nullptr, 0, 0};
-  if (ctl.kind != CTL_PLAIN) {
-    g.st = ctl.st;
-    g.j = ctl.kind == CTL_ARN_FWD ? ctl.j - 1 : ctl.j;
-    const bool fwd = ctl.kind == CTL_GKB_FWD || ctl.kind == CTL_GKB_FWDU;
-    g.mode = fwd ? 0 : 1;
-    if (fwd) g.j = ctl.j;
-  }
   // step 2: slice products
-  const int64_t sAh = n1 * n2;
-  prof_begin(ctx, PROF_GEMM);
-  // the left operand: A~ (n1 x n2), or for the adjoint A~^T (n2 x n1) -- read
-  // from the transposed copy when the operator keeps one (16-bit types)
-  const bool tcopy = adjoint && op->AhT != nullptr;
-  const void* Aop = tcopy ? op->AhT : op->Ah;
-  const int64_t ldA = tcopy ? n1 : n2;
-  const int tA = adjoint && !tcopy ? 1 : 0;
-  if (!op->two_sided) {
-    // forward: (n1 x n2)(n2 x s);  adjoint: (n2 x n1 := A~^T)(n1 x s)
-    e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)rin, Aop, ldA, sAh, tA,
-                    op->xh, sc, rin * sc, 0, op->ch, sc, rout * sc, (int)p, g, tile);
-  } else {
-    e = launch_gemm(ctx, s, gdt, 0, (int)rout, (int)sc, (int)rin, Aop, ldA, sAh, tA,
-                    op->xh, sc, rin * sc, 0, op->th, sc, rout * sc, (int)p, g, tile);
-    if (e != hipSuccess) return e;
-    // right factor: forward (rout x s)(s x s) with B~; adjoint with B~^T
-    e = launch_gemm(ctx, s, gdt, 1, (int)rout, (int)sc, (int)sc, op->th, sc, rout * sc, 0,
-                    op->Bh, sc, sc * sc, adjoint ? 1 : 0, op->ch, sc, rout * sc, (int)p, g, tile);
-  }
-  prof_end(ctx, PROF_GEMM);
+  e = slice_gemms(op, s, adjoint, gemm_gate(ctl));
   if (e != hipSuccess) return e;
   // step 3: inverse transform (L^{-1}, or L^T for the adjoint) with the epilogue
   const int go = adjoint ? 3 : 1;

@@ -642,7 +642,8 @@ enum ProfKind : int {
   PROF_TUBE_INV = 2,
   PROF_FUSED_FWD = 3,
   PROF_FUSED_ADJ = 4,
-  PROF_KINDS = 5
+  PROF_TUBE_PAIR = 5,
+  PROF_KINDS = 6
 };
 void prof_begin(dctk_ctx ctx, int kind);  // no-ops unless profiling
 void prof_end(dctk_ctx ctx, int kind);
@@ -736,6 +737,14 @@ hipError_t launch_tube(dctk_ctx ctx, hipStream_t st, int in_dtype, int out_dtype
                        const void* in, void* out, const double* Gd, const float* Gf,
                        const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi, int* nblocks_out);
 
+// Inverse transform of one product with its epilogue, y = a (G1 c) + b src (a scaled
+// by the control block's input scale; partials of y^2 in ctl.part_out), paired with
+// the next product's forward transform x = G2 y in x_dtype (FP32 vectors, 16 <= p <= 64).
+bool tube_pair_ok(int64_t p, int vec_dtype);
+hipError_t launch_tube_pair(dctk_ctx ctx, hipStream_t s, int x_dtype, int64_t p, int64_t count, const float* c,
+                            const float* src, float* y, void* x, const float* G1, const float* G2, const Ctl& ctl,
+                            int* nblocks_out);
+
 // C_k = op(A_k) op(B_k), batched over `batch`; tile 0: by problem size, else 32/64/128
 hipError_t launch_gemm(dctk_ctx ctx, hipStream_t s, int in_dtype, int out_acc, int M, int N, int K,
                        const void* A, int64_t lda, int64_t sA, int ta,
@@ -754,6 +763,19 @@ hipError_t launch_fused(dctk_op op, hipStream_t s, int adjoint, const void* X, v
 // Writes the number of partials produced to *nblocks_out (when ctl.part_out).
 hipError_t apply_op(dctk_op op, hipStream_t s, int adjoint, const void* X, void* Y, const void* src,
                     void* xnorm, const Ctl& ctl, int* nblocks_out);
+
+// Golub-Kahan steps with paired transforms (three-kernel products, FP32 vectors,
+// 16 <= p <= 64): pair_eligible says whether op takes them; pair_first enqueues
+// a product's forward transform (input X, scale from ctl) and its slice GEMMs;
+// pair_gemm the slice GEMMs of a product whose transformed input is already in
+// place; pair_transforms the product's inverse transform with its epilogue
+// (Y = a M(.) + b src under ctl, partials of Y^2) paired with the forward
+// transform of the next product (the other direction), whose input is Y.
+bool pair_eligible(dctk_op op);
+hipError_t pair_first(dctk_op op, hipStream_t s, int adjoint, const void* X, const Ctl& ctl);
+hipError_t pair_gemm(dctk_op op, hipStream_t s, int adjoint, const Ctl& ctl);
+hipError_t pair_transforms(dctk_op op, hipStream_t s, int adjoint, const void* src, void* Y, const Ctl& ctl,
+                           int* nblocks_out);
 
 // ---- streaming vector kernels (vec.hip) ------------------------------------
 // partials of sum(x . z) (z null: x . x)

@@ -571,6 +571,265 @@ static hipError_t launch_tube_mfma(dctk_ctx ctx, hipStream_t s, int64_t p, int64
 #undef DCTK_TMV
 }
 
+// ---- the two transforms between consecutive slice products ---------------------
+// Inside a Golub-Kahan step the inverse transform of one product and the
+// forward transform of the next act on the same tubes: y = a (G1 c) + b src is
+// the new basis vector (Algorithm 4's U~ or V~, kept unnormalised in its slot)
+// and x = G2 y is the next product's transformed input (its normalisation is
+// applied by the next product's epilogue, as `a`).  One pass over a 64-position
+// tile does both: the slice products' rows and the src rows come in, y goes
+// out (with the workgroup's partial sum of y^2), y returns to LDS, the second
+// MFMA pass forms x, and x goes out in the GEMM type -- y is never read back
+// from memory.  The control block is the one of the first transform's
+// product; the scale it returns for that product's input (1/alpha or 1/beta,
+// as the input x of that product was stored unnormalised) joins `a`.
+struct PairArgs {
+  int gx, gy, gz;
+  int p;
+  int64_t count;
+  const float* c;    // p x count slice products (FP32)
+  const float* src;  // p x count, or null
+  float* y;          // p x count, the new basis vector
+  void* x;           // p x count, TX: the next product's transformed input
+  const float* G1;   // p x p
+  const float* G2;   // p x p
+  Ctl ctl;
+};
+
+template <typename TX, int PM, bool VEC>
+__device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const VBlock vb, const bool grouped) {
+  typedef Mfma<float> MF;
+  constexpr int NB = 64;
+  constexpr int LDG = PM + 4;
+  constexpr int LDX = NB + 4;
+  constexpr int FR = PM / 16;
+  constexpr int XU = PM * (NB / 4) / 256;
+  constexpr int GU = PM * PM / 256;
+  static_assert(XU * 256 == PM * (NB / 4) && GU * 256 == PM * PM, "tile");
+  __shared__ __attribute__((aligned(16))) float sG1[PM * LDG];
+  __shared__ __attribute__((aligned(16))) float sG2[PM * LDG];
+  __shared__ __attribute__((aligned(16))) float sX[PM * LDX];
+  __shared__ double sh[kShCtl];
+  const int p = pa.p;
+  const int64_t count = pa.count;
+  const float* in = pa.c;
+  const float* src = pa.src;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ntiles = (count + NB - 1) / NB;
+
+  // a tile's product rows (rv) and src rows (sv) into registers (clamped
+  // addresses, selected); loading the next tile's rows during the two passes
+  // measured slower (more registers live, three workgroups per CU)
+  float rv[XU][4], sv[XU][4];
+  auto load_tile = [&](int64_t tile) {
+    const int64_t e0 = tile * NB;
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int i = tid + u * 256;
+      const int t = i / (NB / 4), c = (i % (NB / 4)) * 4;
+      const int64_t e = e0 + c;
+      if constexpr (VEC) {
+        const bool ok = t < p && e < count;
+        const float4 q = *reinterpret_cast<const float4*>(in + (ok ? (int64_t)t * count + e : 0));
+        rv[u][0] = ok ? q.x : 0.0f;
+        rv[u][1] = ok ? q.y : 0.0f;
+        rv[u][2] = ok ? q.z : 0.0f;
+        rv[u][3] = ok ? q.w : 0.0f;
+        const bool oks = ok && src != nullptr;
+        const float4 w = *reinterpret_cast<const float4*>(oks ? src + (int64_t)t * count + e : in);
+        sv[u][0] = oks ? w.x : 0.0f;
+        sv[u][1] = oks ? w.y : 0.0f;
+        sv[u][2] = oks ? w.z : 0.0f;
+        sv[u][3] = oks ? w.w : 0.0f;
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool ok = t < p && e + v < count;
+          const float x = in[ok ? (int64_t)t * count + e + v : 0];
+          rv[u][v] = ok ? x : 0.0f;
+          const bool oks = ok && src != nullptr;
+          const float y = (src != nullptr ? src : in)[oks ? (int64_t)t * count + e + v : 0];
+          sv[u][v] = oks ? y : 0.0f;
+        }
+      }
+    }
+  };
+  // one MFMA pass: the products G x (tile in sX) back into sX as [k][e]
+  auto mfma_pass = [&](const float* sG) {
+    typename MF::frag_t acc[FR];
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[f][r] = 0.0f;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+    for (int t0 = 0; t0 < PM; t0 += 4) {
+      const float* bp = &sX[(t0 + lk) * LDX + wave * 16 + lr];
+#pragma unroll
+      for (int f = 0; f < FR; ++f) acc[f] = MF::mac(&sG[(f * 16 + lr) * LDG + t0 + lk], bp, acc[f]);
+    }
+    __syncthreads();  // every wave has read its operands from sX
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sX[(f * 16 + lk * 4 + r) * LDX + wave * 16 + lr] = acc[f][r];
+    __syncthreads();
+  };
+
+  // prologue: the control block's loads and both matrices in flight together
+  const CtlLoad cl = ctl_load(pa.ctl);
+  float g1[GU], g2[GU];
+#pragma unroll
+  for (int u = 0; u < GU; ++u) {
+    const int i = tid + u * 256, k = i / PM, t = i % PM;
+    const bool ok = k < p && t < p;
+    const float v1 = pa.G1[ok ? k * p + t : 0], v2 = pa.G2[ok ? k * p + t : 0];
+    g1[u] = ok ? v1 : 0.0f;
+    g2[u] = ok ? v2 : 0.0f;
+  }
+  double a_d, b_d, s_d;
+  if (!ctl_eval(pa.ctl, cl, a_d, b_d, s_d, sh, vb)) return;
+  const float a = (float)(a_d * s_d), b = (float)b_d;
+  const bool use_src = src != nullptr && b != 0.0f;   // b = 0: src never enters
+#pragma unroll
+  for (int u = 0; u < GU; ++u) {
+    const int i = tid + u * 256, k = i / PM, t = i % PM;
+    sG1[k * LDG + t] = g1[u];
+    sG2[k * LDG + t] = g2[u];
+  }
+  double sq = 0.0;
+  for (int64_t tile = vb.x; tile < ntiles; tile += pa.gx) {
+    const int64_t e0 = tile * NB;
+    load_tile(tile);
+    __syncthreads();  // the previous tile's x rows have been read from sX (and G1, G2 are staged)
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int i = tid + u * 256;
+      const int t = i / (NB / 4), c = (i % (NB / 4)) * 4;
+      *reinterpret_cast<float4*>(&sX[t * LDX + c]) = make_float4(rv[u][0], rv[u][1], rv[u][2], rv[u][3]);
+    }
+    __syncthreads();
+    mfma_pass(sG1);
+    // y = a (G1 c) + b src: written out, summed, and staged for the second pass
+    // (rows k >= p are zero in both passes)
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int i = tid + u * 256;
+      const int k = i / (NB / 4), c = (i % (NB / 4)) * 4;
+      const int64_t e = e0 + c;
+      float4* rowp = reinterpret_cast<float4*>(&sX[k * LDX + c]);
+      const float4 q = *rowp;
+      float y[4] = {a * q.x, a * q.y, a * q.z, a * q.w};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) y[v] += use_src ? b * sv[u][v] : 0.0f;
+      if (k < p) {
+        float* op = pa.y + (int64_t)k * count + e;
+        if (VEC) {
+          if (e < count) {
+            RowStore<float>::st(op, y);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sq += (double)y[v] * (double)y[v];
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (e + v < count) {
+              op[v] = y[v];
+              sq += (double)y[v] * (double)y[v];
+            }
+        }
+      }
+      // positions beyond the slice enter the second pass as zeros
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (e + v >= count) y[v] = 0.0f;
+      *rowp = make_float4(y[0], y[1], y[2], y[3]);
+    }
+    __syncthreads();
+    mfma_pass(sG2);
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int i = tid + u * 256;
+      const int k = i / (NB / 4), c = (i % (NB / 4)) * 4;
+      const int64_t e = e0 + c;
+      if (k >= p) continue;
+      const float4 q = *reinterpret_cast<const float4*>(&sX[k * LDX + c]);
+      const float xv[4] = {q.x, q.y, q.z, q.w};
+      TX* xp = (TX*)pa.x + (int64_t)k * count + e;
+      if (VEC) {
+        if (e < count) RowStore<TX>::st(xp, xv);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (e + v < count) xp[v] = cvt<TX, float>(xv[v]);
+      }
+    }
+  }
+  if (pa.ctl.part_out != nullptr) {
+    const double tot = block_sum_all(sq, sh);
+    if (tid == 0) pa.ctl.part_out[vb.x] = tot;
+  }
+}
+
+template <typename TX, int PM, bool VEC, bool GROUPED>
+__global__ __launch_bounds__(256) void tube_pair_kernel(PairArgs pa_, const PairArgs* grp, const int4* bmap) {
+  if constexpr (!GROUPED) {
+    tube_pair_kernel_body<TX, PM, VEC>(pa_, hw_block(), false);
+  } else {
+    VBlock vb;
+    const PairArgs g = group_args(grp, bmap, vb);
+    tube_pair_kernel_body<TX, PM, VEC>(g, vb, true);
+  }
+}
+
+bool tube_pair_ok(int64_t p, int vec_dtype) { return vec_dtype == DCTK_F32 && p >= 16 && p <= kMaxTube; }
+
+hipError_t launch_tube_pair(dctk_ctx ctx, hipStream_t s, int x_dtype, int64_t p, int64_t count, const float* c,
+                            const float* src, float* y, void* x, const float* G1, const float* G2, const Ctl& ctl,
+                            int* nblocks_out) {
+  if (!tube_pair_ok(p, DCTK_F32)) return hipErrorInvalidValue;
+  // three workgroups per CU (52 KB of LDS each), each walking several tiles
+  int64_t blocks = (count + 63) / 64;
+  const int64_t cap = 3 * (int64_t)num_cus();
+  if (blocks > cap) blocks = cap;
+  if (nblocks_out) *nblocks_out = (int)blocks;
+  if (ctl.part_out != nullptr && blocks > kRedBlocks) return hipErrorInvalidConfiguration;
+  const size_t xe = x_dtype == DCTK_F32 ? 4 : 2;
+  const bool vec = (count % 4 == 0) && ((uintptr_t)c % 16 == 0) && ((uintptr_t)src % 16 == 0) &&
+                   ((uintptr_t)y % 16 == 0) && ((uintptr_t)x % (4 * xe) == 0);
+  PairArgs pa{};
+  pa.p = (int)p;
+  pa.count = count;
+  pa.c = c;
+  pa.src = src;
+  pa.y = y;
+  pa.x = x;
+  pa.G1 = G1;
+  pa.G2 = G2;
+  pa.ctl = ctl;
+  const dim3 grid((unsigned)blocks);
+#define DCTK_PAIR_V(TX, PM_)                                                                                     \
+  do {                                                                                                         \
+    if (vec) return launch_kernel(ctx, s, tube_pair_kernel<TX, PM_, true, false>, tube_pair_kernel<TX, PM_, true, true>, grid, 256, 0, pa); \
+    return launch_kernel(ctx, s, tube_pair_kernel<TX, PM_, false, false>, tube_pair_kernel<TX, PM_, false, true>, grid, 256, 0, pa); \
+  } while (0)
+#define DCTK_PAIR_P(TX)            \
+  do {                             \
+    if (p <= 16) DCTK_PAIR_V(TX, 16); \
+    if (p <= 32) DCTK_PAIR_V(TX, 32); \
+    if (p <= 48) DCTK_PAIR_V(TX, 48); \
+    DCTK_PAIR_V(TX, 64);           \
+  } while (0)
+  switch (x_dtype) {
+    case DCTK_F32: DCTK_PAIR_P(float);
+    case DCTK_BF16: DCTK_PAIR_P(bf16_t);
+    case DCTK_F16: DCTK_PAIR_P(f16_t);
+    default: return hipErrorInvalidValue;
+  }
+#undef DCTK_PAIR_P
+#undef DCTK_PAIR_V
+}
+
 template <typename TIN, typename TOUT, typename TC>
 static hipError_t launch_tube_t(dctk_ctx ctx, hipStream_t s, int64_t p, int64_t count, const void* in, void* out,
                                 const TC* G, const void* src, void* xnorm, const Ctl& ctl, bool scale, bool epi,

@@ -359,6 +359,49 @@ def test_gk_fixed_lambda_matches_oracle(ctx, lam):
     dk.dctk_krylov_destroy(ws)
 
 
+@pytest.mark.parametrize("p,n,s,two_sided,pm", [(16, 40, 24, False, 16), (33, 32, 20, False, 48),
+                                                (64, 24, 16, True, 64), (24, 36, 28, False, 32)])
+def test_gk_paired_transforms_match_oracle(ctx, p, n, s, two_sided, pm):
+    """Tikhonov solve with three-kernel products and FP32 vectors (every tile
+    width of the paired transform kernel): each product's inverse transform
+    also forms the next product's transformed input, and the basis vectors
+    stay unnormalised in their slots.  The Golub-Kahan scalars match the
+    oracle's FP64 process (no reorthogonalisation; 10 steps of a
+    well-conditioned operator, where FP32 rounding moves them by ~1e-6), the
+    last basis vectors (normalised by the flush) and X at a fixed lambda match
+    the oracle's to FP32 accuracy."""
+    say("paired", p, n, s, two_sided)
+    A, B, C = _krylov_problem(50 + p, p=p, n=n, s=s, two_sided=two_sided)
+    k = 10
+    op = Op(ctx, A, B, s, dk.DCTK_F32)
+    for adj in (0, 1):
+        dk.dctk_op_set_path(op.h, adj, 0, 0)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k)
+    X = torch.empty(C.shape, dtype=F32, device="cuda:0")
+    dk.dctk_profile_begin(ctx)
+    info = dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, F32), X, dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, 0.3))
+    prof = dk.dctk_profile_end(ctx)
+    # the paired path ran: two paired kernels per step; forward transforms only
+    # for the initial adjoint product M*(C) and the first step, one inverse (M*(C)'s)
+    assert prof["tube_pair"][1] == 2 * k and prof["tube_fwd"][1] == 2 and prof["tube_inv"][1] == 1
+    g = krylov.gkb(op.oracle, C, k, "none")
+    r = dk.dctk_krylov_read(ctx, ws, k, dk.DCTK_KRYLOV_GKB)
+    assert r["steps"] == k and info.iters == k
+    ea, eb = rel(r["alpha"][: k + 1], g.alpha[: k + 1]), rel(r["beta"][: k + 1], g.beta[: k + 1])
+    v = torch.empty(C.shape, dtype=F32, device="cuda:0")
+    dk.dctk_krylov_copy(ctx, ws, 1, k, v)
+    ev = rel(to_np(v), g.V[k])
+    dk.dctk_krylov_copy(ctx, ws, 0, k, v)
+    eu = rel(to_np(v), g.U[k])
+    ref = krylov.dc_gk(op.oracle, C, k, lam=0.3, reorth="none")
+    ex = rel(to_np(X), ref["X"])
+    say("  alpha", ea, "beta", eb, "V", ev, "U", eu, "X", ex)
+    assert ea <= 1e-5 and eb <= 1e-5
+    assert ev <= 1e-4 and eu <= 1e-4
+    assert ex <= 1e-4
+    dk.dctk_krylov_destroy(ws)
+
+
 def _colour_small_problem():
     w = W.colour_small()
     orc = Operator(w["A"])
