@@ -47,20 +47,20 @@ HBM_PEAK_GBS = 8000.0
 # in the same runs.  They describe the kernel sources with this digest only.
 TRAFFIC_SOURCES = ("paper_2103_11847_amd/csrc/fused.hip", "paper_2103_11847_amd/csrc/mfma.h",
                    "paper_2103_11847_amd/csrc/internal.h")
-TRAFFIC = {"digest": "2745717c67c60cfc", "gemm": "f32",
-           "bytes": {"fused_fwd": 7444194, "fused_adj": 7373410}}
+TRAFFIC = {"digest": "75922566f72158e4", "gemm": "f32",
+           "bytes": {"fused_fwd": 6677661, "fused_adj": 6637658}}
 
 
 # The same for the O(p log p) tube transform at 512 x 512 positions, p = 256, FP32 (bytes per launch).
 LONGTUBE_SOURCES = ("paper_2103_11847_amd/csrc/fastdct.hip", "paper_2103_11847_amd/csrc/fastdct.h")
-LONGTUBE_TRAFFIC = {"digest": "8316061216a2f747", "bytes": 657846060}
+LONGTUBE_TRAFFIC = {"digest": "2b4748b4b2668618", "bytes": 656636507}
 
-# The same for the three kernels of the 512 x 512 x 64 products (bytes per launch,
-# keyed "gemm type/kernel"), filled in from the counter passes of the hyper512 bench.
+# The same for the slice GEMMs and the paired transforms of the 512 x 512 x 64 solve
+# (bytes per launch, keyed "gemm type/kernel"), from the counter passes of the hyper512 bench.
 HYPER_TRAFFIC_SOURCES = ("paper_2103_11847_amd/csrc/gemm.hip", "paper_2103_11847_amd/csrc/transform.hip",
                          "paper_2103_11847_amd/csrc/mfma.h", "paper_2103_11847_amd/csrc/internal.h")
-HYPER_TRAFFIC = {"digest": "66199a40135f8679",
-                 "bytes": {'f32/gemm': 201930594, 'f32/tube_fwd': 200901075, 'f32/tube_inv': 200840016, 'bf16/gemm': 134498981, 'bf16/tube_fwd': 167378976, 'bf16/tube_inv': 200840526}}
+HYPER_TRAFFIC = {"digest": "400ab246520c1303",
+                 "bytes": {"f32/gemm": 201938117, "f32/tube_pair": 269026324, "bf16/gemm": 134495473, "bf16/tube_pair": 235499104}}
 
 
 def source_digest(files):

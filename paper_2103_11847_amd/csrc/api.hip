@@ -439,8 +439,10 @@ static int op_create_impl(dctk_ctx ctx, int tube, int gemm_dtype, int nd, const 
   DCTK_TRY(hipMalloc(&op->Ah, ge * (size_t)(p * n1 * n2)));
   // 16-bit products read A~ with the contraction index contiguous in both
   // directions (16-byte rows straight into LDS): keep the transposed slices
-  // for the adjoint
-  if (gemm_dtype == DCTK_BF16 || gemm_dtype == DCTK_F16)
+  // for the adjoint; the FP32 slice GEMMs of the three-kernel path also read
+  // them (the untransposed operand order of the forward product is the faster
+  // one), while the fused FP32 products stage A~ itself
+  if (gemm_dtype == DCTK_BF16 || gemm_dtype == DCTK_F16 || gemm_dtype == DCTK_F32)
     DCTK_TRY(hipMalloc(&op->AhT, ge * (size_t)(p * n1 * n2)));
   if (op->two_sided) DCTK_TRY(hipMalloc(&op->Bh, ge * (size_t)(p * s * s)));
   DCTK_TRY(hipMalloc(&op->xh, ge * (size_t)(p * nmax * s)));

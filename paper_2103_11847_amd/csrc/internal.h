@@ -599,7 +599,7 @@ struct dctk_op_s {
   // 0 by problem size, else the output tile edge (set by dctk_op_autotune)
   int tune[2][2];
   void* Ah;       // p*n1*n2, gemm dtype
-  void* AhT;      // p*n2*n1: slices of Ah transposed (16-bit gemm dtype, fused products), else null
+  void* AhT;      // p*n2*n1: slices of Ah transposed (FP32 and 16-bit gemm types), else null
   void* Bh;       // p*s*s, gemm dtype (two-sided)
   double* Gd;     // 4 matrices p*p (L, L^-1, L^-T, L^T), FP64 (null for a fast operator)
   float* Gf;      // same in FP32
@@ -818,7 +818,7 @@ hipError_t launch_gkb_update(dctk_ctx ctx, int dtype, int64_t n, void* X, void* 
                              const double* part, int npart, KState* st, int j, void* U = nullptr);
 hipError_t launch_state_reset(dctk_ctx ctx, KState* st, int full, double tol);
 hipError_t launch_cast(dctk_ctx ctx, int64_t n, const double* in, int out_dtype, void* out);
-// Transposing cast of p slices rows x cols (FP64) to cols x rows (16-bit types).
+// Transposing cast of p slices rows x cols (FP64) to cols x rows (FP32 and 16-bit types).
 hipError_t launch_cast_t(dctk_ctx ctx, int64_t p, int64_t rows, int64_t cols, const double* in, int out_dtype,
                          void* out);
 

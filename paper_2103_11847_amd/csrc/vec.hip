@@ -849,6 +849,7 @@ hipError_t launch_cast_t(dctk_ctx ctx, int64_t p, int64_t rows, int64_t cols, co
   if (recording(ctx)) return hipErrorNotSupported;
   unsigned grid = grid_for(p * rows * cols * 4);
   switch (out_dtype) {
+    case DCTK_F32: hipLaunchKernelGGL(k_cast_t<float>, dim3(grid), dim3(kThreads), 0, ctx->stream, p, rows, cols, in, (float*)out); break;
     case DCTK_BF16: hipLaunchKernelGGL(k_cast_t<bf16_t>, dim3(grid), dim3(kThreads), 0, ctx->stream, p, rows, cols, in, (bf16_t*)out); break;
     case DCTK_F16: hipLaunchKernelGGL(k_cast_t<f16_t>, dim3(grid), dim3(kThreads), 0, ctx->stream, p, rows, cols, in, (f16_t*)out); break;
     default: return hipErrorInvalidValue;
