@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0
 # in the same runs.  They describe the kernel sources with this digest only.
 TRAFFIC_SOURCES = ("paper_2103_11847_amd/csrc/fused.hip", "paper_2103_11847_amd/csrc/mfma.h",
                    "paper_2103_11847_amd/csrc/internal.h")
-TRAFFIC = {"digest": "75922566f72158e4", "gemm": "f32",
+TRAFFIC = {"digest": "cf0bb7cb00fb9bc0", "gemm": "f32",
            "bytes": {"fused_fwd": 6677661, "fused_adj": 6637658}}
 
 
@@ -59,8 +59,8 @@ LONGTUBE_TRAFFIC = {"digest": "2b4748b4b2668618", "bytes": 656636507}
 # (bytes per launch, keyed "gemm type/kernel"), from the counter passes of the hyper512 bench.
 HYPER_TRAFFIC_SOURCES = ("paper_2103_11847_amd/csrc/gemm.hip", "paper_2103_11847_amd/csrc/transform.hip",
                          "paper_2103_11847_amd/csrc/mfma.h", "paper_2103_11847_amd/csrc/internal.h")
-HYPER_TRAFFIC = {"digest": "400ab246520c1303",
-                 "bytes": {"f32/gemm": 201938117, "f32/tube_pair": 269026324, "bf16/gemm": 134495473, "bf16/tube_pair": 235499104}}
+HYPER_TRAFFIC = {"digest": "7bdb9a021457ffc0",
+                 "bytes": {"f32/gemm": 202065172, "f32/tube_pair": 269026324, "bf16/gemm": 134494268, "bf16/tube_pair": 235498742}}
 
 
 def source_digest(files):
