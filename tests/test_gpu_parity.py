@@ -402,6 +402,39 @@ def test_gk_paired_transforms_match_oracle(ctx, p, n, s, two_sided, pm):
     dk.dctk_krylov_destroy(ws)
 
 
+@pytest.mark.parametrize("gdt,p,tol", [(dk.DCTK_F64, 3, 1e-9), (dk.DCTK_F32, 16, 1e-5)])
+def test_gkb_steps_continue_after_tikhonov_solve(ctx, gdt, p, tol):
+    """A Tikhonov solve leaves its intermediate basis vectors unnormalised and
+    normalises the last U and V in place; single GKB steps taken after it
+    continue the same process: alpha, beta of the continued steps and the last
+    basis vectors match the oracle's longer process (FP64 fused products; FP32
+    three-kernel products with paired transforms)."""
+    say("continue", gdt, p)
+    A, _, C = _krylov_problem(70 + p, p=p, n=24, s=12)
+    k, extra = 8, 3
+    op = Op(ctx, A, None, C.shape[2], gdt)
+    if gdt == dk.DCTK_F32:
+        for adj in (0, 1):
+            dk.dctk_op_set_path(op.h, adj, 0, 0)
+    ws = dk.dctk_krylov_create(ctx, op.h, dk.DCTK_KRYLOV_GKB, k + extra)
+    vt = VT[gdt]
+    X = torch.empty(C.shape, dtype=vt, device="cuda:0")
+    dk.dctk_lsqr_tik_solve(ctx, ws, to_gpu(C, vt), X, dk.make_opts(k, dk.DCTK_REORTH_NONE, 0, 0.1))
+    for _ in range(extra):
+        dk.dctk_gkb_step(ctx, ws)
+    g = krylov.gkb(op.oracle, C, k + extra, "none")
+    r = dk.dctk_krylov_read(ctx, ws, k + extra, dk.DCTK_KRYLOV_GKB)
+    ea = rel(r["alpha"][: k + extra + 1], g.alpha[: k + extra + 1])
+    eb = rel(r["beta"][: k + extra + 1], g.beta[: k + extra + 1])
+    v = torch.empty(C.shape, dtype=vt, device="cuda:0")
+    dk.dctk_krylov_copy(ctx, ws, 1, k + extra, v)
+    ev = rel(to_np(v), g.V[k + extra])
+    say("  alpha", ea, "beta", eb, "V", ev)
+    assert r["steps"] == k + extra
+    assert ea <= tol and eb <= tol and ev <= 10 * tol
+    dk.dctk_krylov_destroy(ws)
+
+
 def _colour_small_problem():
     w = W.colour_small()
     orc = Operator(w["A"])
