@@ -473,7 +473,9 @@ __device__ __forceinline__ void tube_mfma_kernel_body(const TubeArgs& ta, const 
 #pragma unroll
       for (int f = 0; f < FR; ++f) acc[f] = MF::mac(&sG[(f * 16 + lr) * LDG + t0 + lk], bp, acc[f]);
     }
-    __syncthreads();  // every wave has read its operands from sX
+    // a wave reads and writes only its own 16 columns of sX, and a wave's LDS
+    // accesses complete in order: no block barrier before its products go back
+    __builtin_amdgcn_wave_barrier();
     // products back to LDS as [k][e]: lane holds rows 4 (lane / 16) + r of column lane % 16
 #pragma unroll
     for (int f = 0; f < FR; ++f)
@@ -668,7 +670,10 @@ __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const 
 #pragma unroll
       for (int f = 0; f < FR; ++f) acc[f] = MF::mac(&sG[(f * 16 + lr) * LDG + t0 + lk], bp, acc[f]);
     }
-    __syncthreads();  // every wave has read its operands from sX
+    // a wave reads and writes only its own 16 columns of sX, and a wave's LDS
+    // accesses complete in order: no block barrier between its operand reads
+    // and its product writes
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int f = 0; f < FR; ++f)
 #pragma unroll
