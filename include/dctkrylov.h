@@ -219,8 +219,9 @@ int dctk_op_destroy(dctk_op op);
  * the matrix cores and the inverse transform in the epilogue (one-sided
  * operators with p <= 8) -- or as three kernels: tube transform, batched slice
  * GEMMs, inverse transform with epilogue (Algorithm 1 steps 1-3).  The
- * output tile edge of the GEMM part is 16, 32 or 64 (fused) or 32, 64 or 128
- * (three kernels; 128 not for FP64).  All paths compute the same product;
+ * output tile edge of the GEMM part is 16, 32 or 64 (fused) or 32, 64, 128
+ * or 256 (three kernels; 128 not for FP64; 256, tiles of 256 x 128, only for
+ * BF16 and FP16 GEMMs).  All paths compute the same product;
  * results differ only by the rounding of the contraction order.
  * dctk_op_autotune: times every path and tile the operator can take, `reps`
  * launches each (1..1000) of the forward and of the adjoint product on ctx's

@@ -3,8 +3,7 @@
 // as batched GEMMs on the gfx950 matrix cores.
 //
 // Tile: BM x BN outputs per workgroup of 4 waves arranged 2 x 2, each wave
-// owning (BM/2) x (BN/2) as 16 x 16 MFMA blocks (16-bit 256 x 256 tiles: 8
-// waves in 2 x 4).  Operands are staged through
+// owning (BM/2) x (BN/2) as 16 x 16 MFMA blocks.  Operands are staged through
 // LDS as [rows][BK + pad] (contraction index contiguous) so each lane's MFMA
 // operand is one LDS read: 1 element for the K = 4 FP32/FP64 instructions,
 // 8 packed 16-bit elements for the K = 32 BF16/FP16 instructions of gfx950.
@@ -74,8 +73,8 @@ __device__ __forceinline__ void gemm_kernel_body(const GemmArgs& ga, const VBloc
   typedef typename MF::acc_t acc_t;
   typedef typename MF::frag_t frag_t;
   constexpr int KSTEP = MF::KSTEP;
-  // 256 x 256 tiles: 512 threads (2 x 4 waves of 128 x 64 outputs) and 32-wide
-  // contraction chunks (the two operand tiles of a chunk are 40 KB of LDS)
+  // 256-row tiles: 32-wide contraction chunks (the two operand tiles of a
+  // 256 x 128 chunk are 30 KB of LDS, so two workgroups share a CU)
   constexpr int BK = (KSTEP == 4) ? 16 : (BM >= 256 ? 32 : 64);
   constexpr int PAD = (sizeof(TI) == 2) ? 8 : (sizeof(TI) == 4 ? 4 : 2);  // 16 bytes
   constexpr int LDS_LD = BK + PAD;
@@ -558,10 +557,11 @@ static hipError_t launch_gemm_t(dctk_ctx ctx, hipStream_t s, int M, int N, int K
   const int64_t tiles256 = (int64_t)((M + 255) / 256) * ((N + 255) / 256) * batch;
   const int64_t tiles128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128) * batch;
   int64_t tiles64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64) * batch;
-  // 256 x 256 while they still give every CU one (each operand byte staged
-  // serves twice the flops of a 128 x 128 tile)
+  // 256 x 128 while 256 x 256 blocks still give every CU one (each operand
+  // byte staged serves 4/3 the flops of a 128 x 128 tile, and two workgroups
+  // of 4 waves per CU hide more latency than one of 8 with 256 x 256 tiles)
   if (tile == 256 || (tile == 0 && M >= 256 && N >= 256 && tiles256 >= (int64_t)num_cus))
-    return launch_gemm_tile<TI, TO, 256, 256>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
+    return launch_gemm_tile<TI, TO, 256, 128>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
   if (tile == 128 || (tile == 0 && tiles128 >= 2 * (int64_t)num_cus))
     return launch_gemm_tile<TI, TO, 128, 128>(ctx, s, M, N, K, A, lda, sA, ta, B, ldb, sB, tb, C, ldc, sC, batch, g);
   if (tile == 64 || (tile == 0 && tiles64 >= 2 * (int64_t)num_cus))
