@@ -689,13 +689,13 @@ hipError_t pair_transforms(dctk_op op, hipStream_t s, int adjoint, const void* s
   dctk_ctx ctx = op->ctx;
   const int64_t pp = op->p * op->p;
   const int64_t rout = adjoint ? op->n2 : op->n1;
-  // this product's inverse (L^{-1}, or L^T for the adjoint); the next product's
-  // forward transform (L^{-T} for the adjoint after a forward product, L after an adjoint)
-  const int g1 = adjoint ? 3 : 1, g2 = adjoint ? 0 : 2;
+  // this product's inverse (L^{-1}, or L^T for the adjoint); its transpose is the
+  // next product's forward transform (L^{-T} for the adjoint after a forward
+  // product, L after an adjoint)
+  const int g1 = adjoint ? 3 : 1;
   prof_begin(ctx, PROF_TUBE_PAIR);
   hipError_t e = launch_tube_pair(ctx, s, op->gemm_dtype, op->p, rout * op->s, (const float*)op->ch,
-                                  (const float*)src, (float*)Y, op->xh, op->Gf + g1 * pp, op->Gf + g2 * pp, ctl,
-                                  nblocks_out);
+                                  (const float*)src, (float*)Y, op->xh, op->Gf + g1 * pp, ctl, nblocks_out);
   prof_end(ctx, PROF_TUBE_PAIR);
   return e;
 }

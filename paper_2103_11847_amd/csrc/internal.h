@@ -739,10 +739,11 @@ hipError_t launch_tube(dctk_ctx ctx, hipStream_t st, int in_dtype, int out_dtype
 
 // Inverse transform of one product with its epilogue, y = a (G1 c) + b src (a scaled
 // by the control block's input scale; partials of y^2 in ctl.part_out), paired with
-// the next product's forward transform x = G2 y in x_dtype (FP32 vectors, 16 <= p <= 64).
+// the next product's forward transform x = G1^T y in x_dtype (FP32 vectors, 16 <= p <= 64).
+// G1 is L^{-1} after a forward product (then G1^T = L^{-T}), L^T after an adjoint (G1^T = L).
 bool tube_pair_ok(int64_t p, int vec_dtype);
 hipError_t launch_tube_pair(dctk_ctx ctx, hipStream_t s, int x_dtype, int64_t p, int64_t count, const float* c,
-                            const float* src, float* y, void* x, const float* G1, const float* G2, const Ctl& ctl,
+                            const float* src, float* y, void* x, const float* G1, const Ctl& ctl,
                             int* nblocks_out);
 
 // C_k = op(A_k) op(B_k), batched over `batch`; tile 0: by problem size, else 32/64/128

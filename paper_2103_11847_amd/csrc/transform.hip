@@ -577,14 +577,18 @@ static hipError_t launch_tube_mfma(dctk_ctx ctx, hipStream_t s, int64_t p, int64
 // Inside a Golub-Kahan step the inverse transform of one product and the
 // forward transform of the next act on the same tubes: y = a (G1 c) + b src is
 // the new basis vector (Algorithm 4's U~ or V~, kept unnormalised in its slot)
-// and x = G2 y is the next product's transformed input (its normalisation is
-// applied by the next product's epilogue, as `a`).  One pass over a 64-position
-// tile does both: the slice products' rows and the src rows come in, y goes
-// out (with the workgroup's partial sum of y^2), y returns to LDS, the second
-// MFMA pass forms x, and x goes out in the GEMM type -- y is never read back
-// from memory.  The control block is the one of the first transform's
-// product; the scale it returns for that product's input (1/alpha or 1/beta,
-// as the input x of that product was stored unnormalised) joins `a`.
+// and x = G1^T y is the next product's transformed input (its normalisation is
+// applied by the next product's epilogue, as `a`).  The second matrix is always
+// the transpose of the first: after a forward product G1 = L^{-1} and the
+// adjoint's forward transform is L^{-T}; after an adjoint product G1 = L^T and
+// the forward product's transform is L.  One pass over a 64-position tile does
+// both: the slice products' rows and the src rows come in, y goes out (with
+// the workgroup's partial sum of y^2), y returns to LDS, the second MFMA pass
+// forms x reading the one staged copy of G1 transposed, and x goes out in the
+// GEMM type -- y is never read back from memory.  The control block is the one
+// of the first transform's product; the scale it returns for that product's
+// input (1/alpha or 1/beta, as the input x of that product was stored
+// unnormalised) joins `a`.
 struct PairArgs {
   int gx, gy, gz;
   int p;
@@ -594,7 +598,6 @@ struct PairArgs {
   float* y;          // p x count, the new basis vector
   void* x;           // p x count, TX: the next product's transformed input
   const float* G1;   // p x p
-  const float* G2;   // p x p
   Ctl ctl;
 };
 
@@ -602,14 +605,15 @@ template <typename TX, int PM, bool VEC>
 __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const VBlock vb, const bool grouped) {
   typedef Mfma<float> MF;
   constexpr int NB = 64;
-  constexpr int LDG = PM + 4;
+  // rows of G1 padded by 8: both the row reads of the first pass and the
+  // column reads of the second spread over the banks
+  constexpr int LDG = PM + 8;
   constexpr int LDX = NB + 4;
   constexpr int FR = PM / 16;
   constexpr int XU = PM * (NB / 4) / 256;
   constexpr int GU = PM * PM / 256;
   static_assert(XU * 256 == PM * (NB / 4) && GU * 256 == PM * PM, "tile");
   __shared__ __attribute__((aligned(16))) float sG1[PM * LDG];
-  __shared__ __attribute__((aligned(16))) float sG2[PM * LDG];
   __shared__ __attribute__((aligned(16))) float sX[PM * LDX];
   __shared__ double sh[kShCtl];
   const int p = pa.p;
@@ -620,8 +624,8 @@ __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const 
   const int64_t ntiles = (count + NB - 1) / NB;
 
   // a tile's product rows (rv) and src rows (sv) into registers (clamped
-  // addresses, selected); loading the next tile's rows during the two passes
-  // measured slower (more registers live, three workgroups per CU)
+  // addresses, selected); loading the next tile's rows during the passes
+  // measured slower
   float rv[XU][4], sv[XU][4];
   auto load_tile = [&](int64_t tile) {
     const int64_t e0 = tile * NB;
@@ -656,8 +660,10 @@ __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const 
       }
     }
   };
-  // one MFMA pass: the products G x (tile in sX) back into sX as [k][e]
-  auto mfma_pass = [&](const float* sG) {
+  // one MFMA pass: the products G x (tile in sX) back into sX as [k][e], with
+  // G = G1, or (TR) its transpose read from the same LDS copy
+  auto mfma_pass = [&](const float* sG, auto tr) {
+    constexpr bool TR = decltype(tr)::value;
     typename MF::frag_t acc[FR];
 #pragma unroll
     for (int f = 0; f < FR; ++f)
@@ -668,7 +674,8 @@ __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const 
     for (int t0 = 0; t0 < PM; t0 += 4) {
       const float* bp = &sX[(t0 + lk) * LDX + wave * 16 + lr];
 #pragma unroll
-      for (int f = 0; f < FR; ++f) acc[f] = MF::mac(&sG[(f * 16 + lr) * LDG + t0 + lk], bp, acc[f]);
+      for (int f = 0; f < FR; ++f)
+        acc[f] = MF::mac(TR ? &sG[(t0 + lk) * LDG + f * 16 + lr] : &sG[(f * 16 + lr) * LDG + t0 + lk], bp, acc[f]);
     }
     // a wave reads and writes only its own 16 columns of sX, and a wave's LDS
     // accesses complete in order: no block barrier between its operand reads
@@ -683,14 +690,13 @@ __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const 
 
   // prologue: the control block's loads and both matrices in flight together
   const CtlLoad cl = ctl_load(pa.ctl);
-  float g1[GU], g2[GU];
+  float g1[GU];
 #pragma unroll
   for (int u = 0; u < GU; ++u) {
     const int i = tid + u * 256, k = i / PM, t = i % PM;
     const bool ok = k < p && t < p;
-    const float v1 = pa.G1[ok ? k * p + t : 0], v2 = pa.G2[ok ? k * p + t : 0];
+    const float v1 = pa.G1[ok ? k * p + t : 0];
     g1[u] = ok ? v1 : 0.0f;
-    g2[u] = ok ? v2 : 0.0f;
   }
   double a_d, b_d, s_d;
   if (!ctl_eval(pa.ctl, cl, a_d, b_d, s_d, sh, vb)) return;
@@ -700,13 +706,12 @@ __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const 
   for (int u = 0; u < GU; ++u) {
     const int i = tid + u * 256, k = i / PM, t = i % PM;
     sG1[k * LDG + t] = g1[u];
-    sG2[k * LDG + t] = g2[u];
   }
   double sq = 0.0;
   for (int64_t tile = vb.x; tile < ntiles; tile += pa.gx) {
     const int64_t e0 = tile * NB;
     load_tile(tile);
-    __syncthreads();  // the previous tile's x rows have been read from sX (and G1, G2 are staged)
+    __syncthreads();  // the previous tile's x rows have been read from sX (and G1 is staged)
 #pragma unroll
     for (int u = 0; u < XU; ++u) {
       const int i = tid + u * 256;
@@ -714,7 +719,7 @@ __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const 
       *reinterpret_cast<float4*>(&sX[t * LDX + c]) = make_float4(rv[u][0], rv[u][1], rv[u][2], rv[u][3]);
     }
     __syncthreads();
-    mfma_pass(sG1);
+    mfma_pass(sG1, std::false_type{});
     // y = a (G1 c) + b src: written out, summed, and staged for the second pass
     // (rows k >= p are zero in both passes)
 #pragma unroll
@@ -751,7 +756,7 @@ __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const 
       *rowp = make_float4(y[0], y[1], y[2], y[3]);
     }
     __syncthreads();
-    mfma_pass(sG2);
+    mfma_pass(sG1, std::true_type{});
 #pragma unroll
     for (int u = 0; u < XU; ++u) {
       const int i = tid + u * 256;
@@ -790,12 +795,12 @@ __global__ __launch_bounds__(256) void tube_pair_kernel(PairArgs pa_, const Pair
 bool tube_pair_ok(int64_t p, int vec_dtype) { return vec_dtype == DCTK_F32 && p >= 16 && p <= kMaxTube; }
 
 hipError_t launch_tube_pair(dctk_ctx ctx, hipStream_t s, int x_dtype, int64_t p, int64_t count, const float* c,
-                            const float* src, float* y, void* x, const float* G1, const float* G2, const Ctl& ctl,
+                            const float* src, float* y, void* x, const float* G1, const Ctl& ctl,
                             int* nblocks_out) {
   if (!tube_pair_ok(p, DCTK_F32)) return hipErrorInvalidValue;
-  // three workgroups per CU (52 KB of LDS each), each walking several tiles
+  // four workgroups per CU (36 KB of LDS each), each walking several tiles
   int64_t blocks = (count + 63) / 64;
-  const int64_t cap = 3 * (int64_t)num_cus();
+  const int64_t cap = 4 * (int64_t)num_cus();
   if (blocks > cap) blocks = cap;
   if (nblocks_out) *nblocks_out = (int)blocks;
   if (ctl.part_out != nullptr && blocks > kRedBlocks) return hipErrorInvalidConfiguration;
@@ -810,7 +815,6 @@ hipError_t launch_tube_pair(dctk_ctx ctx, hipStream_t s, int x_dtype, int64_t p,
   pa.y = y;
   pa.x = x;
   pa.G1 = G1;
-  pa.G2 = G2;
   pa.ctl = ctl;
   const dim3 grid((unsigned)blocks);
 #define DCTK_PAIR_V(TX, PM_)                                                                                     \
