@@ -483,7 +483,7 @@ def bench_paper(args):
     for kind in ("tube_fwd", "gemm", "tube_inv", "tube_pair"):
         tot, cnt = prof_gk[kind]
         if cnt:
-            f, b = kernel_work(kind, p, n, n, n, bg)
+            f, b = kernel_work(kind, p, n, n, n, bg, per_solve=cnt)
             kinds[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, args.gemm, None)
             kinds[kind].update({"launches": cnt, "ms_total": tot})
     dom = max(kinds, key=lambda k_: kinds[k_]["ms_total"])
@@ -888,8 +888,9 @@ def plain_fp32_loop(ctx, insts, k, opts, args):
 #             FP32 slice products (4 N): 2 n1 n2 s p flops
 #   tube_inv  reads the slice products and the epilogue's src, writes the output:
 #             12 N bytes, 2 p N flops
-def kernel_work(kind, p, n1, n2, s, bg, fast=False):
-    """(flops, algorithmic bytes) of one launch.  Transforms: 2p flops per
+def kernel_work(kind, p, n1, n2, s, bg, fast=False, per_solve=None):
+    """(flops, algorithmic bytes) of one launch, averaged over a DC-GK solve's
+    launches of that kind (`per_solve` of them).  Transforms: 2p flops per
     element as a dense p x p product, about 5 log2(p) with the O(p log p)
     transform of long tubes (one complex FFT of length p per tube pair)."""
     N = p * n2 * s
@@ -897,10 +898,14 @@ def kernel_work(kind, p, n1, n2, s, bg, fast=False):
     if kind == "gemm":
         return 2.0 * n1 * n2 * s * p, p * n1 * n2 * bg + N * (bg + 4)
     if kind == "tube_fwd":
-        # input read, X~ written in the GEMM type (the Tikhonov steps write no normalised copy)
-        return tf, N * (4 + bg)
+        # input read, X~ written in the GEMM type (the Tikhonov steps write no
+        # normalised copy); the forward transform of the initial product M*(C)
+        # also writes U_1 (FP32), once per solve
+        return tf, N * (4 + bg) + (4.0 * N / per_solve if per_solve else 0.0)
     if kind == "tube_inv":
-        return tf, 12.0 * N
+        # product rows read, output written; every inverse but that of M*(C)
+        # (one per solve) also reads its src
+        return tf, 8.0 * N + (4.0 * N * (per_solve - 1) / per_solve if per_solve else 4.0 * N)
     if kind == "tube_pair":
         # the slice products and src read, the new basis vector written, and the
         # next product's transformed input written in the GEMM type; two transforms
@@ -1006,7 +1011,7 @@ def bench_hyper(args):
     for kind in ("tube_fwd", "gemm", "tube_inv", "tube_pair"):
         tot, cnt = prof[kind]
         if cnt:
-            f, b = kernel_work(kind, p, n, n, s, bg, fast=longsolve)
+            f, b = kernel_work(kind, p, n, n, s, bg, fast=longsolve, per_solve=cnt / args.steps)
             kinds[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, gemm,
                                          None if (order4 or longsolve) else hyper_traffic(kind, gemm))
             kinds[kind].update({"launches": cnt, "ms_total": tot})
@@ -1027,7 +1032,7 @@ def bench_hyper(args):
         for kind in ("tube_fwd", "gemm", "tube_inv", "tube_pair"):
             tot, cnt = prof_b[kind]
             if cnt:
-                f, b = kernel_work(kind, p, n, n, s, 2, fast=longsolve)
+                f, b = kernel_work(kind, p, n, n, s, 2, fast=longsolve, per_solve=cnt / args.steps)
                 kb[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, b, "bf16",
                                           None if (order4 or longsolve) else hyper_traffic(kind, "bf16"))
                 kb[kind].update({"launches": cnt, "ms_total": tot})
@@ -1211,7 +1216,7 @@ def bench_learned512(args):
     for kind in ("tube_fwd", "gemm", "tube_inv", "tube_pair"):
         tot, cnt = prof[kind]
         if cnt:
-            f, byt = kernel_work(kind, p, n, n, s, 2)
+            f, byt = kernel_work(kind, p, n, n, s, 2, per_solve=cnt / len(made))
             kinds[kind] = roofline_entry(kind, tot * 1e3 / cnt, f, byt, "bf16", hyper_traffic(kind, "bf16"))
             kinds[kind].update({"launches": cnt, "ms_total": tot})
     dom = max(kinds, key=lambda k_: kinds[k_]["ms_total"])
