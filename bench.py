@@ -59,7 +59,7 @@ LONGTUBE_TRAFFIC = {"digest": "2b4748b4b2668618", "bytes": 656636507}
 # (bytes per launch, keyed "gemm type/kernel"), from the counter passes of the hyper512 bench.
 HYPER_TRAFFIC_SOURCES = ("paper_2103_11847_amd/csrc/gemm.hip", "paper_2103_11847_amd/csrc/transform.hip",
                          "paper_2103_11847_amd/csrc/mfma.h", "paper_2103_11847_amd/csrc/internal.h")
-HYPER_TRAFFIC = {"digest": "b73efbae43052313",
+HYPER_TRAFFIC = {"digest": "50678c7cb80bf0dd",
                  "bytes": {"f32/gemm": 202097938, "f32/tube_pair": 268908161, "bf16/gemm": 134564564, "bf16/tube_pair": 235377510}}
 
 

@@ -688,7 +688,7 @@ __device__ __forceinline__ void tube_pair_kernel_body(const PairArgs& pa, const 
     __syncthreads();
   };
 
-  // prologue: the control block's loads and both matrices in flight together
+  // prologue: the control block's loads and the matrix in flight together
   const CtlLoad cl = ctl_load(pa.ctl);
   float g1[GU];
 #pragma unroll
