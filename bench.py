@@ -182,8 +182,8 @@ def oracle_leg(w, C_ref_builder, budget_s, target=None, lcurve=False):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU "
-              "sharding is a design note, not an implementation" % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on one GPU (--gpus %d requested); how the path would "
+              "shard over several GPUs is described, not implemented" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2103_11847_amd as dk
