@@ -66,8 +66,10 @@ class Inst:
 
 
 # (seed, p, n1, n2, s, gemm dtype, two-sided): fused FP32 (square, ragged, p = 8),
-# unfused (p > 8, two-sided), BF16 and FP64 fused kernels, and a 512 x 512 slice
-# size that takes the 32 x 32 fused tiles
+# unfused (p > 8, two-sided), BF16 and FP64 fused kernels, a 512 x 512 slice
+# size that takes the 32 x 32 fused tiles, and three-kernel products whose
+# Golub-Kahan steps pair the transforms (16 <= p <= 64: 24, 33 with BF16
+# operands, 64)
 SHAPES = [
     (1, 3, 40, 40, 40, dk.DCTK_F32, False),
     (2, 3, 64, 48, 56, dk.DCTK_F32, False),
@@ -78,6 +80,9 @@ SHAPES = [
     (7, 3, 20, 20, 20, dk.DCTK_F64, False),
     (8, 3, 512, 512, 512, dk.DCTK_F32, False),
     (9, 3, 40, 40, 40, dk.DCTK_F32, False),
+    (10, 24, 40, 40, 32, dk.DCTK_F32, False),
+    (11, 33, 32, 32, 24, dk.DCTK_BF16, False),
+    (12, 64, 48, 48, 40, dk.DCTK_F32, False),
 ]
 
 
